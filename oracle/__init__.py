@@ -1,0 +1,274 @@
+"""Python access to the plain FP64 CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, the smoke check and the
+benchmark's CPU-baseline leg.  The GPU library never imports it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c: plain FP64, no FMA contraction, no fast-math, OpenMP on column scans."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-fopenmp",
+               "-std=c99", os.path.join(_HERE, "oracle.c"), "-o", _LIB_PATH + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_void_p) for name in
+                ("sweeps", "n_strong", "n_viol", "n_rounds", "n_safe", "n_active", "rss", "obj", "gap")]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        i64, dbl, vp, i32 = ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_int
+        L.or_standardize.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp]
+        L.or_standardize.restype = i64
+        L.or_zscan.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp, vp, vp]
+        L.or_zscan.restype = None
+        L.or_lambda_max.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.or_lambda_max.restype = i32
+        L.or_bedpp_b.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp, i64, vp]
+        L.or_bedpp_b.restype = None
+        L.or_bedpp_discard.argtypes = [i64, vp, vp, vp, dbl, dbl, dbl, dbl, vp]
+        L.or_bedpp_discard.restype = i64
+        L.or_lambda_grid.argtypes = [dbl, dbl, i64, vp]
+        L.or_lambda_grid.restype = None
+        L.or_cd.argtypes = [i64, i64, vp, i64, vp, vp, vp, dbl, vp, i64, vp, vp, dbl, i64, vp]
+        L.or_cd.restype = i32
+        L.or_residual.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp, vp, vp]
+        L.or_residual.restype = None
+        L.or_objective.argtypes = [i64, vp, vp, i64, vp, dbl]
+        L.or_objective.restype = dbl
+        L.or_duality_gap.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp, vp, vp, vp, dbl]
+        L.or_duality_gap.restype = dbl
+        L.or_fit_path.argtypes = [i64, i64, vp, i64, vp, vp, i64, dbl, i32, dbl, i64,
+                                  vp, vp, vp, vp, vp, vp, ctypes.POINTER(_Stats), vp]
+        L.or_fit_path.restype = i32
+        L.or_mlp_forward.argtypes = [i64, i64, vp, vp, vp]
+        L.or_mlp_forward.restype = None
+        L.or_mlp_loss_grad.argtypes = [i64, i64, vp, vp, vp, vp]
+        L.or_mlp_loss_grad.restype = dbl
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _design(Xt):
+    """Accept X as a (p, n) array (row j = column j); returns float64 (p, ld) and ld."""
+    Xt = _f64(Xt)
+    return Xt, Xt.shape[1]
+
+
+def _mask(mask, n_total):
+    if mask is None:
+        return None
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    assert m.shape == (n_total,)
+    return m
+
+
+def standardize(Xt, mask=None):
+    Xt, ld = _design(Xt)
+    p, n_total = Xt.shape
+    m = _mask(mask, n_total)
+    c = np.empty(p)
+    s = np.empty(p)
+    keep = np.empty(p, dtype=np.uint8)
+    n = _load().or_standardize(n_total, p, _ptr(Xt), ld, _ptr(m), _ptr(c), _ptr(s), _ptr(keep))
+    return c, s, keep.astype(bool), n
+
+
+def zscan(Xt, c, s, keep, r, mask=None):
+    Xt, ld = _design(Xt)
+    p, n_total = Xt.shape
+    m = _mask(mask, n_total)
+    c, s, r = _f64(c), _f64(s), _f64(r)
+    k = np.ascontiguousarray(keep, dtype=np.uint8)
+    z = np.empty(p)
+    _load().or_zscan(n_total, p, _ptr(Xt), ld, _ptr(m), _ptr(c), _ptr(s), _ptr(k), _ptr(r), _ptr(z))
+    return z
+
+
+def lambda_max(Xt, c, s, keep, y, mask=None):
+    Xt, ld = _design(Xt)
+    p, n_total = Xt.shape
+    m = _mask(mask, n_total)
+    c, s, y = _f64(c), _f64(s), _f64(y)
+    k = np.ascontiguousarray(keep, dtype=np.uint8)
+    ybar = ctypes.c_double()
+    lmax = ctypes.c_double()
+    jstar = ctypes.c_int64()
+    ytilde = np.empty(n_total)
+    a = np.empty(p)
+    rc = _load().or_lambda_max(n_total, p, _ptr(Xt), ld, _ptr(m), _ptr(c), _ptr(s), _ptr(k), _ptr(y),
+                               ctypes.addressof(ybar), _ptr(ytilde), _ptr(a), ctypes.addressof(lmax),
+                               ctypes.addressof(jstar))
+    if rc:
+        raise ValueError("lambda_max: no usable column or no rows")
+    return ybar.value, ytilde, a, lmax.value, jstar.value
+
+
+def bedpp_b(Xt, c, s, keep, jstar, mask=None):
+    Xt, ld = _design(Xt)
+    p, n_total = Xt.shape
+    m = _mask(mask, n_total)
+    c, s = _f64(c), _f64(s)
+    k = np.ascontiguousarray(keep, dtype=np.uint8)
+    b = np.empty(p)
+    _load().or_bedpp_b(n_total, p, _ptr(Xt), ld, _ptr(m), _ptr(c), _ptr(s), _ptr(k), int(jstar), _ptr(b))
+    return b
+
+
+def bedpp_discard(a, b, keep, lambda_max, sign_star, v, lam):
+    a, b = _f64(a), _f64(b)
+    k = np.ascontiguousarray(keep, dtype=np.uint8)
+    d = np.empty(a.size, dtype=np.uint8)
+    _load().or_bedpp_discard(a.size, _ptr(a), _ptr(b), _ptr(k), lambda_max, sign_star, v, lam, _ptr(d))
+    return d.astype(bool)
+
+
+def lambda_grid(lambda_max, ratio, K):
+    lam = np.empty(K)
+    _load().or_lambda_grid(lambda_max, ratio, K, _ptr(lam))
+    return lam
+
+
+def cd(Xt, c, s, lam, sset, beta, r, tol=1e-13, max_sweeps=100000, mask=None):
+    """Cyclic CD in place on beta and r; returns (converged, sweeps)."""
+    Xt, ld = _design(Xt)
+    p, n_total = Xt.shape
+    m = _mask(mask, n_total)
+    c, s = _f64(c), _f64(s)
+    sset = np.ascontiguousarray(sset, dtype=np.int64)
+    assert beta.dtype == np.float64 and beta.flags.c_contiguous
+    assert r.dtype == np.float64 and r.flags.c_contiguous
+    sw = ctypes.c_int64()
+    rc = _load().or_cd(n_total, p, _ptr(Xt), ld, _ptr(m), _ptr(c), _ptr(s), lam, _ptr(sset), sset.size,
+                       _ptr(beta), _ptr(r), tol, max_sweeps, ctypes.addressof(sw))
+    return rc == 0, sw.value
+
+
+def residual(Xt, c, s, ytilde, beta, mask=None):
+    Xt, ld = _design(Xt)
+    p, n_total = Xt.shape
+    m = _mask(mask, n_total)
+    r = np.empty(n_total)
+    _load().or_residual(n_total, p, _ptr(Xt), ld, _ptr(m), _ptr(_f64(c)), _ptr(_f64(s)), _ptr(_f64(ytilde)),
+                        _ptr(_f64(beta)), _ptr(r))
+    return r
+
+
+def objective(r, beta, lam, mask=None):
+    r = _f64(r)
+    m = _mask(mask, r.size)
+    beta = _f64(beta)
+    return _load().or_objective(r.size, _ptr(m), _ptr(r), beta.size, _ptr(beta), lam)
+
+
+def duality_gap(Xt, c, s, keep, ytilde, r, beta, lam, mask=None):
+    Xt, ld = _design(Xt)
+    p, n_total = Xt.shape
+    m = _mask(mask, n_total)
+    k = np.ascontiguousarray(keep, dtype=np.uint8)
+    return _load().or_duality_gap(n_total, p, _ptr(Xt), ld, _ptr(m), _ptr(_f64(c)), _ptr(_f64(s)), _ptr(k),
+                                  _ptr(_f64(ytilde)), _ptr(_f64(r)), _ptr(_f64(beta)), lam)
+
+
+@dataclass
+class Path:
+    lam: np.ndarray        # (K,)
+    beta: np.ndarray       # (K, p) standardized scale
+    c: np.ndarray
+    s: np.ndarray
+    keep: np.ndarray
+    ybar: float
+    sweeps: np.ndarray
+    n_strong: np.ndarray
+    n_viol: np.ndarray
+    n_rounds: np.ndarray
+    n_safe: np.ndarray
+    n_active: np.ndarray
+    rss: np.ndarray
+    obj: np.ndarray
+    gap: np.ndarray
+    k_done: int
+    status: int
+
+    def original_scale(self):
+        """Coefficients beta_j / s_j and intercept ybar - sum_j c_j beta_j / s_j, per lambda."""
+        s = np.where(self.keep, self.s, 1.0)
+        b = np.where(self.keep[None, :], self.beta / s[None, :], 0.0)
+        icpt = self.ybar - b @ self.c
+        return icpt, b
+
+
+SCREEN_NONE, SCREEN_SSR = 0, 1
+
+
+def fit_path(Xt, y, K=100, ratio=0.1, screen=SCREEN_SSR, tol=1e-13, max_sweeps=100000, mask=None) -> Path:
+    Xt, ld = _design(Xt)
+    p, n_total = Xt.shape
+    m = _mask(mask, n_total)
+    y = _f64(y)
+    c, s = np.empty(p), np.empty(p)
+    keep = np.empty(p, dtype=np.uint8)
+    lam = np.empty(K)
+    beta = np.zeros((K, p))
+    ybar = ctypes.c_double()
+    arr = {k: np.zeros(K, dtype=np.int64) for k in ("sweeps", "n_strong", "n_viol", "n_rounds", "n_safe", "n_active")}
+    arr.update({k: np.zeros(K) for k in ("rss", "obj", "gap")})
+    st = _Stats(**{k: v.ctypes.data for k, v in arr.items()})
+    k_done = ctypes.c_int64()
+    rc = _load().or_fit_path(n_total, p, _ptr(Xt), ld, _ptr(m), _ptr(y), K, ratio, screen, tol, max_sweeps,
+                             _ptr(c), _ptr(s), _ptr(keep), _ptr(lam), _ptr(beta), ctypes.addressof(ybar),
+                             ctypes.byref(st), ctypes.addressof(k_done))
+    if rc == 2:
+        raise ValueError("fit_path: bad input")
+    return Path(lam, beta, c, s, keep.astype(bool), ybar.value, k_done=k_done.value, status=rc, **arr)
+
+
+def n_params(H):
+    return H * H + 7 * H + 1
+
+
+def mlp_forward(feat, params, H):
+    feat = _f64(feat).reshape(-1, 4)
+    params = _f64(params)
+    assert params.size == n_params(H)
+    prob = np.empty(feat.shape[0])
+    _load().or_mlp_forward(feat.shape[0], H, _ptr(feat), _ptr(params), _ptr(prob))
+    return prob
+
+
+def mlp_loss_grad(feat, label, params, H):
+    feat = _f64(feat).reshape(-1, 4)
+    label = _f64(label)
+    params = _f64(params)
+    grad = np.empty_like(params)
+    loss = _load().or_mlp_loss_grad(feat.shape[0], H, _ptr(feat), _ptr(label), _ptr(params), _ptr(grad))
+    return loss, grad

@@ -1,0 +1,500 @@
+/*
+ * Plain FP64 CPU oracle for the pathwise lasso of Zeng & Breheny, "The
+ * biglasso Package" (arXiv:1701.05936).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Loaded by the test suite, the smoke check and
+ * the benchmark's CPU-baseline leg; never by the GPU library, with which it
+ * shares no code.
+ *
+ * Every quantity is computed from its plain definition, in double precision,
+ * one loop per formula, without blocking or fusion.  Column scans run their
+ * columns in parallel with OpenMP (each column's sum is still a plain loop in
+ * row order), as the paper parallelizes matrix-vector products (Section 3.2).
+ *
+ * Readings of the paper taken here (the paper leaves these open):
+ *   - standard deviation uses divisor n, so (1/n) sum_i x~_ij^2 = 1
+ *     (the paper's notation block in Section 2);
+ *   - objective Q(b; l) = ||y~ - X~ b||^2 / (2n) + l ||b||_1, which makes
+ *     l_max = max_j |x~_j' y~| / n;
+ *   - lambda grid geometric from l_max down to ratio * l_max (Section 4 and the
+ *     printed lambda values of the Section 5 example);
+ *   - a column with s_j <= 1e-6 is constant and is left out (beta_j = 0);
+ *   - the intercept is the mean of y over the fitted rows (y is centered);
+ *   - CD stops when the largest |change| of a coefficient over one sweep of the
+ *     set is below tol;
+ *   - the strong rule keeps j when |z_j(prev)| >= 2 l_k - l_{k-1}; the
+ *     post-convergence check flags j when |z_j| > l_k (strict).
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define KEEP_MIN_SD 1e-6
+
+static int64_t count_rows(int64_t n_total, const uint8_t* mask) {
+    if (!mask) return n_total;
+    int64_t n = 0;
+    for (int64_t i = 0; i < n_total; ++i) n += mask[i] ? 1 : 0;
+    return n;
+}
+
+static inline int in_fit(const uint8_t* mask, int64_t i) { return mask == NULL || mask[i] != 0; }
+
+static double soft_threshold(double u, double l) {
+    if (u > l) return u - l;
+    if (u < -l) return u + l;
+    return 0.0;
+}
+
+/*
+ * Column centers c and scales s (Section 3.1: the package keeps only the
+ * column means and standard deviations and standardizes cell by cell).
+ * Two passes per column: mean, then mean squared deviation.
+ */
+int64_t or_standardize(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
+                       double* c, double* s, uint8_t* keep) {
+    int64_t n = count_rows(n_total, mask);
+    if (n <= 0) return 0;
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < p; ++j) {
+        const double* x = X + j * ldx;
+        double sum = 0.0;
+        for (int64_t i = 0; i < n_total; ++i)
+            if (in_fit(mask, i)) sum += x[i];
+        double mean = sum / (double)n;
+        double ss = 0.0;
+        for (int64_t i = 0; i < n_total; ++i)
+            if (in_fit(mask, i)) ss += (x[i] - mean) * (x[i] - mean);
+        double sd = sqrt(ss / (double)n);
+        c[j] = mean;
+        s[j] = sd;
+        keep[j] = sd > KEEP_MIN_SD ? 1 : 0;
+    }
+    return n;
+}
+
+/*
+ * z_j = (1/n) sum_{i in fit} x~_ij r_i  with x~_ij = (x_ij - c_j)/s_j, the
+ * standardized correlation of Section 3.1.1 (type (3) divided by n), written
+ * with the explicit standardized cell rather than the simplified form.
+ * z_j = 0 for columns left out.
+ */
+void or_zscan(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
+              const double* c, const double* s, const uint8_t* keep, const double* r, double* z) {
+    int64_t n = count_rows(n_total, mask);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < p; ++j) {
+        if (!keep[j]) {
+            z[j] = 0.0;
+            continue;
+        }
+        const double* x = X + j * ldx;
+        double acc = 0.0;
+        for (int64_t i = 0; i < n_total; ++i)
+            if (in_fit(mask, i)) acc += ((x[i] - c[j]) / s[j]) * r[i];
+        z[j] = acc / (double)n;
+    }
+}
+
+/*
+ * y-bar, centered y~, the initial correlations a_j = z_j(y~) (Section 3.1.1,
+ * type (2)), lambda_max = max_j |a_j| and the smallest index attaining it.
+ * At any lambda >= lambda_max the zero vector satisfies the optimality
+ * conditions, so the path starts at beta = 0.
+ */
+int or_lambda_max(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
+                  const double* c, const double* s, const uint8_t* keep, const double* y,
+                  double* ybar, double* ytilde, double* a, double* lambda_max, int64_t* jstar) {
+    int64_t n = count_rows(n_total, mask);
+    if (n <= 0) return 1;
+    double sum = 0.0;
+    for (int64_t i = 0; i < n_total; ++i)
+        if (in_fit(mask, i)) sum += y[i];
+    double mean = sum / (double)n;
+    for (int64_t i = 0; i < n_total; ++i) ytilde[i] = in_fit(mask, i) ? y[i] - mean : 0.0;
+    or_zscan(n_total, p, X, ldx, mask, c, s, keep, ytilde, a);
+    double best = -1.0;
+    int64_t arg = -1;
+    for (int64_t j = 0; j < p; ++j) {
+        if (!keep[j]) continue;
+        if (fabs(a[j]) > best) {
+            best = fabs(a[j]);
+            arg = j;
+        }
+    }
+    *ybar = mean;
+    *lambda_max = best < 0 ? 0.0 : best;
+    *jstar = arg;
+    return arg < 0 ? 1 : 0;
+}
+
+/* b_j = x~_j' x~_* / n, the correlation with the column attaining lambda_max (type (1) of Section 3.1.1) */
+void or_bedpp_b(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
+                const double* c, const double* s, const uint8_t* keep, int64_t jstar, double* b) {
+    int64_t n = count_rows(n_total, mask);
+    const double* xs = X + jstar * ldx;
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < p; ++j) {
+        if (!keep[j]) {
+            b[j] = 0.0;
+            continue;
+        }
+        const double* x = X + j * ldx;
+        double acc = 0.0;
+        for (int64_t i = 0; i < n_total; ++i)
+            if (in_fit(mask, i)) acc += ((x[i] - c[j]) / s[j]) * ((xs[i] - c[jstar]) / s[jstar]);
+        b[j] = acc / (double)n;
+    }
+}
+
+/*
+ * Basic EDPP safe rule (Section 2.2): EDPP of Wang, Wonka & Ye (JMLR 2015)
+ * with the reference point at lambda_max, where the dual solution is known
+ * exactly (y~ / (n lambda_max)).  Rewritten for the scaling above
+ * (their penalty n*lambda, ||x~_j||^2 = n), feature j is discarded at
+ * lambda < lambda_max when
+ *   | (lmax + l) a_j - (lmax - l) sgn(a_*) lmax b_j |
+ *        < 2 l lmax - (lmax - l) sqrt(max(0, v - lmax^2)),   v = ||y~||^2 / n.
+ * At l = lmax this is |a_j| < lmax.  Returns the number discarded.
+ */
+int64_t or_bedpp_discard(int64_t p, const double* a, const double* b, const uint8_t* keep,
+                         double lambda_max, double sign_star, double v, double lambda, uint8_t* discard) {
+    double lm = lambda_max, l = lambda;
+    double slack = v - lm * lm;
+    if (slack < 0.0) slack = 0.0;
+    double rhs = 2.0 * l * lm - (lm - l) * sqrt(slack);
+    int64_t cnt = 0;
+    for (int64_t j = 0; j < p; ++j) {
+        if (!keep[j]) {
+            discard[j] = 1;
+            ++cnt;
+            continue;
+        }
+        double lhs = fabs((lm + l) * a[j] - (lm - l) * sign_star * lm * b[j]);
+        discard[j] = lhs < rhs ? 1 : 0;
+        cnt += discard[j];
+    }
+    return cnt;
+}
+
+/* lambda_k = lambda_max * ratio^(k/(K-1)), k = 0..K-1 (geometric grid, Section 4) */
+void or_lambda_grid(double lambda_max, double ratio, int64_t K, double* lam) {
+    if (K == 1) {
+        lam[0] = lambda_max;
+        return;
+    }
+    for (int64_t k = 0; k < K; ++k) lam[k] = lambda_max * pow(ratio, (double)k / (double)(K - 1));
+}
+
+/*
+ * Cyclic coordinate descent at a fixed lambda over the features in `set`,
+ * visited in the order given, warm-started from beta and its residual r
+ * (the pathwise coordinate descent the package builds on, Section 1).
+ * One coordinate step:
+ *   g = (1/n) x~_j' r,  u = g + beta_j,  beta_j' = S(u, lambda),
+ *   r <- r - (beta_j' - beta_j) x~_j
+ * (the curvature (1/n) ||x~_j||^2 is 1).  Returns 0 when the largest |change|
+ * over a sweep fell below tol, 1 when max_sweeps ran out.
+ */
+int or_cd(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
+          const double* c, const double* s, double lambda, const int64_t* set, int64_t set_len,
+          double* beta, double* r, double tol, int64_t max_sweeps, int64_t* sweeps) {
+    (void)p;
+    int64_t n = count_rows(n_total, mask);
+    for (int64_t sweep = 1; sweep <= max_sweeps; ++sweep) {
+        double max_change = 0.0;
+        for (int64_t t = 0; t < set_len; ++t) {
+            int64_t j = set[t];
+            const double* x = X + j * ldx;
+            double g = 0.0;
+            for (int64_t i = 0; i < n_total; ++i)
+                if (in_fit(mask, i)) g += ((x[i] - c[j]) / s[j]) * r[i];
+            g /= (double)n;
+            double bnew = soft_threshold(g + beta[j], lambda);
+            double delta = bnew - beta[j];
+            if (delta != 0.0) {
+                for (int64_t i = 0; i < n_total; ++i)
+                    if (in_fit(mask, i)) r[i] -= delta * ((x[i] - c[j]) / s[j]);
+                beta[j] = bnew;
+            }
+            if (fabs(delta) > max_change) max_change = fabs(delta);
+        }
+        if (max_change < tol) {
+            *sweeps = sweep;
+            return 0;
+        }
+    }
+    *sweeps = max_sweeps;
+    return 1;
+}
+
+/* r = y~ - X~ beta over the fitted rows, recomputed from scratch */
+void or_residual(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
+                 const double* c, const double* s, const double* ytilde, const double* beta, double* r) {
+    for (int64_t i = 0; i < n_total; ++i) r[i] = in_fit(mask, i) ? ytilde[i] : 0.0;
+    for (int64_t j = 0; j < p; ++j) {
+        if (beta[j] == 0.0) continue;
+        const double* x = X + j * ldx;
+        for (int64_t i = 0; i < n_total; ++i)
+            if (in_fit(mask, i)) r[i] -= beta[j] * ((x[i] - c[j]) / s[j]);
+    }
+}
+
+/* Q(beta; lambda) = ||r||^2/(2n) + lambda ||beta||_1 with r = y~ - X~ beta */
+double or_objective(int64_t n_total, const uint8_t* mask, const double* r, int64_t p, const double* beta,
+                    double lambda) {
+    int64_t n = count_rows(n_total, mask);
+    double rss = 0.0, l1 = 0.0;
+    for (int64_t i = 0; i < n_total; ++i)
+        if (in_fit(mask, i)) rss += r[i] * r[i];
+    for (int64_t j = 0; j < p; ++j) l1 += fabs(beta[j]);
+    return rss / (2.0 * (double)n) + lambda * l1;
+}
+
+/*
+ * Relative duality gap of beta at lambda.  Primal P = n Q; dual point
+ * theta = r / max(n lambda, ||X~' r||_inf); D = ||y~||^2/2 - ||y~ - n lambda theta||^2/2.
+ */
+double or_duality_gap(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
+                      const double* c, const double* s, const uint8_t* keep, const double* ytilde,
+                      const double* r, const double* beta, double lambda) {
+    int64_t n = count_rows(n_total, mask);
+    double* z = (double*)malloc(sizeof(double) * (size_t)p);
+    or_zscan(n_total, p, X, ldx, mask, c, s, keep, r, z);
+    double zmax = 0.0;
+    for (int64_t j = 0; j < p; ++j)
+        if (keep[j] && fabs(z[j]) * (double)n > zmax) zmax = fabs(z[j]) * (double)n;
+    free(z);
+    double nl = (double)n * lambda;
+    double scale = zmax > nl ? zmax : nl;
+    double primal = (double)n * or_objective(n_total, mask, r, p, beta, lambda);
+    double yy = 0.0, dd = 0.0;
+    for (int64_t i = 0; i < n_total; ++i) {
+        if (!in_fit(mask, i)) continue;
+        double theta = r[i] / scale;
+        double d = ytilde[i] - nl * theta;
+        yy += ytilde[i] * ytilde[i];
+        dd += d * d;
+    }
+    double dual = 0.5 * yy - 0.5 * dd;
+    return primal > 0.0 ? (primal - dual) / primal : 0.0;
+}
+
+/*
+ * The lasso path over the geometric grid with warm starts, screened by the
+ * sequential strong rule (or not screened) and repaired by a post-convergence
+ * check over every kept feature:
+ *   E_k = {j : beta_j != 0} u {j : |z_j(prev)| >= 2 l_k - l_{k-1}}
+ *   repeat: CD over E_k; z = scan of all kept j;
+ *           V = {j not in E_k : |z_j| > l_k}; stop if V is empty; E_k u= V.
+ * BEDPP is evaluated only to report its survivor count; the solve never uses
+ * it.  beta is p x K on the standardized scale.  Returns 0 on success, 1 if
+ * CD did not converge (k_done then counts the finished lambdas), 2 on bad input.
+ */
+int or_fit_path(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
+                const double* y, int64_t K, double ratio, int screen, double tol, int64_t max_sweeps,
+                double* c, double* s, uint8_t* keep, double* lambda, double* beta, double* ybar,
+                or_path_stats* st, int64_t* k_done) {
+    *k_done = 0;
+    if (p <= 0 || K <= 0) return 2;
+    int64_t n = or_standardize(n_total, p, X, ldx, mask, c, s, keep);
+    if (n <= 0) return 2;
+    double* ytilde = (double*)calloc((size_t)n_total, sizeof(double));
+    double* r = (double*)calloc((size_t)n_total, sizeof(double));
+    double* a = (double*)calloc((size_t)p, sizeof(double));
+    double* b = (double*)calloc((size_t)p, sizeof(double));
+    double* z = (double*)calloc((size_t)p, sizeof(double));
+    double* zprev = (double*)calloc((size_t)p, sizeof(double));
+    double* bcur = (double*)calloc((size_t)p, sizeof(double));
+    uint8_t* inE = (uint8_t*)calloc((size_t)p, 1);
+    uint8_t* disc = (uint8_t*)calloc((size_t)p, 1);
+    int64_t* set = (int64_t*)malloc(sizeof(int64_t) * (size_t)p);
+    int status = 0;
+
+    double lmax;
+    int64_t jstar;
+    if (or_lambda_max(n_total, p, X, ldx, mask, c, s, keep, y, ybar, ytilde, a, &lmax, &jstar)) {
+        status = 2;
+        goto done;
+    }
+    or_bedpp_b(n_total, p, X, ldx, mask, c, s, keep, jstar, b);
+    double v = 0.0;
+    for (int64_t i = 0; i < n_total; ++i) v += ytilde[i] * ytilde[i];
+    v /= (double)n;
+    double sgn = a[jstar] >= 0 ? 1.0 : -1.0;
+    or_lambda_grid(lmax, ratio, K, lambda);
+    memcpy(r, ytilde, sizeof(double) * (size_t)n_total);
+    memcpy(zprev, a, sizeof(double) * (size_t)p);
+
+    for (int64_t k = 0; k < K; ++k) {
+        double lk = lambda[k];
+        int64_t sweeps_k = 0, viol_k = 0, rounds_k = 0, nE = 0;
+        if (k > 0) {
+            double thr = 2.0 * lk - lambda[k - 1];
+            for (int64_t j = 0; j < p; ++j) {
+                if (!keep[j]) {
+                    inE[j] = 0;
+                    continue;
+                }
+                if (screen == OR_SCREEN_NONE)
+                    inE[j] = 1;
+                else
+                    inE[j] = (bcur[j] != 0.0 || fabs(zprev[j]) >= thr) ? 1 : 0;
+            }
+            for (;;) {
+                nE = 0;
+                for (int64_t j = 0; j < p; ++j)
+                    if (inE[j]) set[nE++] = j;
+                int64_t sw = 0;
+                int rc = or_cd(n_total, p, X, ldx, mask, c, s, lk, set, nE, bcur, r, tol, max_sweeps, &sw);
+                sweeps_k += sw;
+                rounds_k += 1;
+                if (rc) {
+                    status = 1;
+                    goto done;
+                }
+                or_zscan(n_total, p, X, ldx, mask, c, s, keep, r, z);
+                int64_t nv = 0;
+                for (int64_t j = 0; j < p; ++j) {
+                    if (keep[j] && !inE[j] && fabs(z[j]) > lk) {
+                        inE[j] = 1;
+                        ++nv;
+                    }
+                }
+                viol_k += nv;
+                if (nv == 0) break;
+            }
+            memcpy(zprev, z, sizeof(double) * (size_t)p);
+        }
+        memcpy(beta + k * p, bcur, sizeof(double) * (size_t)p);
+        int64_t nact = 0;
+        for (int64_t j = 0; j < p; ++j) nact += bcur[j] != 0.0;
+        if (st) {
+            if (st->sweeps) st->sweeps[k] = sweeps_k;
+            if (st->n_strong) st->n_strong[k] = nE;
+            if (st->n_viol) st->n_viol[k] = viol_k;
+            if (st->n_rounds) st->n_rounds[k] = rounds_k;
+            if (st->n_safe) st->n_safe[k] = p - or_bedpp_discard(p, a, b, keep, lmax, sgn, v, lk, disc);
+            if (st->n_active) st->n_active[k] = nact;
+            double rss = 0.0;
+            for (int64_t i = 0; i < n_total; ++i) rss += r[i] * r[i];
+            if (st->rss) st->rss[k] = rss;
+            if (st->obj) st->obj[k] = or_objective(n_total, mask, r, p, bcur, lk);
+            if (st->gap) st->gap[k] = or_duality_gap(n_total, p, X, ldx, mask, c, s, keep, ytilde, r, bcur, lk);
+        }
+        *k_done = k + 1;
+    }
+done:
+    free(ytilde);
+    free(r);
+    free(a);
+    free(b);
+    free(z);
+    free(zprev);
+    free(bcur);
+    free(inE);
+    free(disc);
+    free(set);
+    return status;
+}
+
+/*
+ * Screening network used by the learned form: 4 inputs -> H (ReLU) -> H (ReLU)
+ * -> 1 logit -> logistic.  Parameter vector layout:
+ *   W1[H][4], b1[H], W2[H][H], b2[H], w3[H], b3.
+ * The paper has no such network; this is the plain definition of the model
+ * the GPU form trains, so its outputs and gradients can be checked.
+ */
+static double relu(double x) { return x > 0.0 ? x : 0.0; }
+
+static void mlp_one(int64_t H, const double* f, const double* P, double* h1, double* h2, double* logit) {
+    const double* W1 = P;
+    const double* b1 = W1 + H * 4;
+    const double* W2 = b1 + H;
+    const double* b2 = W2 + H * H;
+    const double* w3 = b2 + H;
+    const double* b3 = w3 + H;
+    for (int64_t u = 0; u < H; ++u) {
+        double acc = b1[u];
+        for (int64_t q = 0; q < 4; ++q) acc += W1[u * 4 + q] * f[q];
+        h1[u] = relu(acc);
+    }
+    for (int64_t u = 0; u < H; ++u) {
+        double acc = b2[u];
+        for (int64_t q = 0; q < H; ++q) acc += W2[u * H + q] * h1[q];
+        h2[u] = relu(acc);
+    }
+    double o = b3[0];
+    for (int64_t u = 0; u < H; ++u) o += w3[u] * h2[u];
+    *logit = o;
+}
+
+void or_mlp_forward(int64_t m, int64_t H, const double* feat, const double* params, double* prob) {
+    double* h1 = (double*)malloc(sizeof(double) * (size_t)H);
+    double* h2 = (double*)malloc(sizeof(double) * (size_t)H);
+    for (int64_t t = 0; t < m; ++t) {
+        double o;
+        mlp_one(H, feat + t * 4, params, h1, h2, &o);
+        prob[t] = 1.0 / (1.0 + exp(-o));
+    }
+    free(h1);
+    free(h2);
+}
+
+/*
+ * Mean binary cross-entropy over m rows, L = (1/m) sum [log(1 + e^o) - y o],
+ * and its gradient with respect to every parameter (back-propagation through
+ * the layers above, written out per layer).
+ */
+double or_mlp_loss_grad(int64_t m, int64_t H, const double* feat, const double* label, const double* params,
+                        double* grad) {
+    int64_t np = H * H + 7 * H + 1;
+    memset(grad, 0, sizeof(double) * (size_t)np);
+    double* g_W1 = grad;
+    double* g_b1 = g_W1 + H * 4;
+    double* g_W2 = g_b1 + H;
+    double* g_b2 = g_W2 + H * H;
+    double* g_w3 = g_b2 + H;
+    double* g_b3 = g_w3 + H;
+    const double* W2 = params + H * 4 + H;
+    const double* w3 = W2 + H * H + H;
+    double* h1 = (double*)malloc(sizeof(double) * (size_t)H);
+    double* h2 = (double*)malloc(sizeof(double) * (size_t)H);
+    double* d2 = (double*)malloc(sizeof(double) * (size_t)H);
+    double* d1 = (double*)malloc(sizeof(double) * (size_t)H);
+    double loss = 0.0;
+    for (int64_t t = 0; t < m; ++t) {
+        const double* f = feat + t * 4;
+        double o;
+        mlp_one(H, f, params, h1, h2, &o);
+        double y = label[t];
+        double sp = o > 0.0 ? o + log1p(exp(-o)) : log1p(exp(o));
+        loss += sp - y * o;
+        double dout = (1.0 / (1.0 + exp(-o)) - y) / (double)m;
+        g_b3[0] += dout;
+        for (int64_t u = 0; u < H; ++u) {
+            g_w3[u] += dout * h2[u];
+            d2[u] = h2[u] > 0.0 ? dout * w3[u] : 0.0;
+        }
+        for (int64_t u = 0; u < H; ++u) {
+            g_b2[u] += d2[u];
+            for (int64_t q = 0; q < H; ++q) g_W2[u * H + q] += d2[u] * h1[q];
+        }
+        for (int64_t q = 0; q < H; ++q) {
+            double acc = 0.0;
+            for (int64_t u = 0; u < H; ++u) acc += W2[u * H + q] * d2[u];
+            d1[q] = h1[q] > 0.0 ? acc : 0.0;
+        }
+        for (int64_t u = 0; u < H; ++u) {
+            g_b1[u] += d1[u];
+            for (int64_t q = 0; q < 4; ++q) g_W1[u * 4 + q] += d1[u] * f[q];
+        }
+    }
+    free(h1);
+    free(h2);
+    free(d2);
+    free(d1);
+    return loss / (double)m;
+}

@@ -1,0 +1,381 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: library
+routines (numpy mean/std/lstsq), closed forms of the lasso (soft-thresholding
+on orthogonal designs, the first segment of the path), brute-force
+enumeration of sign patterns, optimality certificates, and the lambda values
+the paper prints.  None of them retypes the oracle's own formulas.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def std_numpy(Xt, mask=None):
+    """Explicitly standardized copy X~ (n x p) and centered y helper, in numpy."""
+    X = Xt.T.astype(np.float64)
+    if mask is not None:
+        X = X[mask.astype(bool)]
+    c = X.mean(axis=0)
+    s = X.std(axis=0)
+    return (X - c) / s, c, s
+
+
+def soft(u, l):
+    return np.sign(u) * np.maximum(np.abs(u) - l, 0.0)
+
+
+# ---------------------------------------------------------------------------------------------
+# standardization and the scan (Section 3.1, 3.1.1)
+# ---------------------------------------------------------------------------------------------
+
+def test_standardize_matches_numpy_population_sd():
+    rng = np.random.default_rng(0)
+    Xt = rng.normal(3.0, 2.0, size=(37, 53))
+    Xt[5] = 1.25  # constant column
+    mask = (rng.uniform(size=53) < 0.7).astype(np.uint8)
+    c, s, keep, n = oracle.standardize(Xt, mask)
+    X = Xt.T[mask.astype(bool)]
+    assert n == mask.sum()
+    np.testing.assert_allclose(c, X.mean(axis=0), rtol=1e-14, atol=1e-14)
+    np.testing.assert_allclose(s, X.std(axis=0, ddof=0), rtol=1e-13, atol=1e-15)
+    assert not keep[5] and keep.sum() == 36
+
+
+def test_scan_equals_simplified_identity_type3():
+    # Section 3.1.1 type (3): x~_j' r = (sum_i x_ij r_i - c_j sum_i r_i) / s_j, with r not centered
+    rng = np.random.default_rng(1)
+    Xt = datagen.genotype_u8(7, 61, 45).astype(np.float64)
+    mask = np.ones(61, dtype=np.uint8)
+    mask[::7] = 0
+    c, s, keep, n = oracle.standardize(Xt, mask)
+    r = rng.normal(size=61) + 0.3
+    r[mask == 0] = 0.0
+    z = oracle.zscan(Xt, c, s, keep, r, mask)
+    X = Xt.T
+    ident = (X.T @ r - c * r.sum()) / (s * n)
+    np.testing.assert_allclose(z[keep], ident[keep], rtol=1e-12, atol=1e-14)
+
+
+def test_type1_and_type2_identities():
+    # Section 3.1.1 types (1) and (2) through lambda_max and the BEDPP correlations
+    rng = np.random.default_rng(2)
+    Xt = rng.normal(size=(30, 80)) * rng.uniform(0.5, 3, size=(30, 1)) + rng.normal(size=(30, 1))
+    y = rng.normal(size=80) + 4.0
+    c, s, keep, n = oracle.standardize(Xt)
+    ybar, yt, a, lmax, js = oracle.lambda_max(Xt, c, s, keep, y)
+    X = Xt.T
+    np.testing.assert_allclose(a, (X.T @ y - c * y.sum()) / (s * n), rtol=1e-12, atol=1e-14)
+    b = oracle.bedpp_b(Xt, c, s, keep, js)
+    xs = X[:, js]
+    np.testing.assert_allclose(b, (X.T @ xs - n * c * c[js]) / (n * s * s[js]), rtol=1e-11, atol=1e-13)
+    assert lmax == pytest.approx(np.abs(a).max(), rel=0, abs=0)
+    assert js == int(np.argmax(np.abs(a)))
+    assert ybar == pytest.approx(y.mean(), rel=1e-15)
+
+
+# ---------------------------------------------------------------------------------------------
+# the lasso solution: closed forms, brute force, certificates
+# ---------------------------------------------------------------------------------------------
+
+def orthogonal_design(n, p, seed):
+    """Columns centered, mutually orthogonal, (1/n)||x_j||^2 = 1, random means and scales added back."""
+    rng = np.random.default_rng(seed)
+    G = rng.normal(size=(n, p))
+    G -= G.mean(axis=0)
+    Q, _ = np.linalg.qr(G)
+    Xs = Q * np.sqrt(n)
+    scale = rng.uniform(0.5, 2.0, size=p)
+    shift = rng.normal(size=p)
+    return (Xs * scale + shift).T.copy()  # (p, n)
+
+
+def test_orthogonal_design_soft_threshold_closed_form():
+    n, p = 60, 12
+    Xt = orthogonal_design(n, p, 3)
+    rng = np.random.default_rng(4)
+    y = Xt.T @ rng.normal(size=p) + rng.normal(size=n)
+    path = oracle.fit_path(Xt, y, K=25, ratio=0.05)
+    Xtil, c, s = std_numpy(Xt)
+    a = Xtil.T @ (y - y.mean()) / n
+    for k, lam in enumerate(path.lam):
+        np.testing.assert_allclose(path.beta[k], soft(a, lam), atol=1e-11)
+
+
+def test_first_segment_closed_form():
+    # with one active feature the solution is sign(a_*) (lambda_max - lambda) (unit curvature)
+    rng = np.random.default_rng(5)
+    Xt = rng.normal(size=(40, 120))
+    y = 2.0 * Xt[7] + rng.normal(size=120)
+    c, s, keep, n = oracle.standardize(Xt)
+    ybar, yt, a, lmax, js = oracle.lambda_max(Xt, c, s, keep, y)
+    second = np.sort(np.abs(a))[-2]
+    lam = 0.5 * (lmax + second)
+    beta = np.zeros(40)
+    r = yt.copy()
+    ok, sweeps = oracle.cd(Xt, c, s, lam, np.arange(40), beta, r)
+    assert ok
+    expect = np.zeros(40)
+    expect[js] = np.sign(a[js]) * (lmax - lam)
+    np.testing.assert_allclose(beta, expect, atol=1e-13)
+
+
+def test_beta_zero_at_lambda_max():
+    prob = datagen.make("c1", n=150, p=300)
+    path = oracle.fit_path(prob.Xt, prob.y[0], K=10, ratio=0.1)
+    assert path.lam[0] == pytest.approx(path.lam[0])
+    assert np.all(path.beta[0] == 0.0)
+    assert path.sweeps[0] == 0          # no iterations at lambda_max (iter[1] = 0 in the package output)
+    assert path.n_active[1] >= 1
+
+
+def brute_force_lasso(Xtil, yt, lam):
+    """Enumerate sign patterns; return the unique pattern meeting the optimality conditions."""
+    n, p = Xtil.shape
+    G = Xtil.T @ Xtil / n
+    q = Xtil.T @ yt / n
+    found = []
+    for sig in itertools.product((-1, 0, 1), repeat=p):
+        sig = np.array(sig)
+        A = np.flatnonzero(sig)
+        beta = np.zeros(p)
+        if A.size:
+            try:
+                beta[A] = np.linalg.solve(G[np.ix_(A, A)], q[A] - lam * sig[A])
+            except np.linalg.LinAlgError:
+                continue
+            if not np.all(np.sign(beta[A]) == sig[A]):
+                continue
+        grad = q - G @ beta
+        off = np.setdiff1d(np.arange(p), A)
+        if np.all(np.abs(grad[off]) <= lam * (1 + 1e-12)):
+            found.append(beta)
+    return found
+
+
+@pytest.mark.parametrize("seed,design", [(11, "gaussian"), (12, "genotype"), (13, "ar1")])
+def test_brute_force_sign_enumeration(seed, design):
+    n, p = 30, 8
+    rng = np.random.default_rng(seed)
+    if design == "gaussian":
+        Xt = rng.normal(size=(p, n))
+    elif design == "genotype":
+        Xt = datagen.genotype_u8(seed, n, p).astype(np.float64)
+    else:
+        Xt = datagen.ar1_f32(seed, n, p, 0.8).astype(np.float64)
+    y = Xt[:3].T @ np.array([1.5, -1.0, 0.7]) + rng.normal(size=n)
+    path = oracle.fit_path(Xt, y, K=12, ratio=0.02)
+    Xtil, c, s = std_numpy(Xt)
+    yt = y - y.mean()
+    for k in range(1, 12, 2):
+        sols = brute_force_lasso(Xtil, yt, path.lam[k])
+        assert len(sols) == 1
+        np.testing.assert_allclose(path.beta[k], sols[0], atol=1e-10)
+
+
+def test_brute_force_p10_with_row_mask():
+    n, p = 45, 10
+    rng = np.random.default_rng(21)
+    Xt = rng.normal(size=(p, n)) + rng.normal(size=(p, 1))
+    mask = np.ones(n, dtype=np.uint8)
+    mask[rng.choice(n, 9, replace=False)] = 0
+    y = Xt[2] - 2 * Xt[5] + rng.normal(size=n)
+    path = oracle.fit_path(Xt, y, K=8, ratio=0.05, mask=mask)
+    Xtil, c, s = std_numpy(Xt, mask)
+    ym = y[mask.astype(bool)]
+    for k in (3, 7):
+        sols = brute_force_lasso(Xtil, ym - ym.mean(), path.lam[k])
+        assert len(sols) == 1
+        np.testing.assert_allclose(path.beta[k], sols[0], atol=1e-10)
+
+
+def test_ols_limit_matches_lstsq():
+    rng = np.random.default_rng(6)
+    n, p = 200, 15
+    Xt = rng.normal(size=(p, n))
+    y = Xt.T @ rng.normal(size=p) + rng.normal(size=n)
+    c, s, keep, nn = oracle.standardize(Xt)
+    ybar, yt, a, lmax, js = oracle.lambda_max(Xt, c, s, keep, y)
+    lam = lmax * 1e-10
+    beta = np.zeros(p)
+    r = yt.copy()
+    ok, _ = oracle.cd(Xt, c, s, lam, np.arange(p), beta, r, tol=1e-15)
+    assert ok
+    Xtil, _, _ = std_numpy(Xt)
+    ols, *_ = np.linalg.lstsq(Xtil, y - y.mean(), rcond=None)
+    np.testing.assert_allclose(beta, ols, atol=1e-8)
+
+
+def test_single_feature_soft_threshold():
+    rng = np.random.default_rng(7)
+    x = rng.normal(size=(1, 50))
+    y = 0.8 * x[0] + rng.normal(size=50)
+    path = oracle.fit_path(x, y, K=6, ratio=0.1)
+    a = (x[0] - x[0].mean()) / x[0].std() @ (y - y.mean()) / 50
+    for k, lam in enumerate(path.lam):
+        assert path.beta[k, 0] == pytest.approx(soft(a, lam), abs=1e-13)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c4"])
+def test_kkt_certificate_and_duality_gap(name):
+    prob = datagen.make(name, n=300, p=700) if name != "c4" else datagen.make("c4", n=300, p=400, nresp=1, nsub=1)
+    Xt = prob.Xt.astype(np.float64)
+    y = prob.y[0]
+    K = 40
+    path = oracle.fit_path(Xt, y, K=K, ratio=prob.recipe.lambda_min_ratio)
+    Xtil, c, s = std_numpy(Xt)
+    yt = y - y.mean()
+    n = Xtil.shape[0]
+    for k in range(K):
+        b = path.beta[k]
+        r = yt - Xtil @ b
+        z = Xtil.T @ r / n
+        lam = path.lam[k]
+        act = b != 0
+        assert np.all(np.abs(z[~act]) <= lam * (1 + 1e-9))
+        np.testing.assert_allclose(z[act], lam * np.sign(b[act]), atol=1e-9 * max(1.0, lam))
+        assert path.gap[k] <= 1e-10
+        # objective (1/2n)||r||^2 + lam ||b||_1 recomputed in numpy
+        assert path.obj[k] == pytest.approx(r @ r / (2 * n) + lam * np.abs(b).sum(), rel=1e-12)
+
+
+def test_screening_none_and_strong_rule_agree():
+    prob = datagen.make("c2", n=250, p=900)
+    Xt = prob.Xt.astype(np.float64)
+    p1 = oracle.fit_path(Xt, prob.y[0], K=30, ratio=0.05, screen=oracle.SCREEN_SSR)
+    p0 = oracle.fit_path(Xt, prob.y[0], K=30, ratio=0.05, screen=oracle.SCREEN_NONE)
+    np.testing.assert_allclose(p1.beta, p0.beta, atol=1e-11)
+    assert np.all(p1.n_strong <= p0.n_strong)
+
+
+def test_cd_not_converged_reports():
+    prob = datagen.make("c1", n=100, p=200)
+    path = oracle.fit_path(prob.Xt, prob.y[0], K=20, ratio=0.1, max_sweeps=1)
+    assert path.status == 1 and 1 <= path.k_done < 20
+
+
+# ---------------------------------------------------------------------------------------------
+# BEDPP safe rule (Section 2.2): safety, monotonicity, reduction at lambda_max
+# ---------------------------------------------------------------------------------------------
+
+def bedpp_inputs(Xt, y):
+    c, s, keep, n = oracle.standardize(Xt)
+    ybar, yt, a, lmax, js = oracle.lambda_max(Xt, c, s, keep, y)
+    b = oracle.bedpp_b(Xt, c, s, keep, js)
+    v = yt @ yt / n
+    return a, b, keep, lmax, np.sign(a[js]), v
+
+
+@pytest.mark.parametrize("seed,design", [(31, "gaussian"), (32, "genotype"), (33, "ar1"), (34, "ar1_strong")])
+def test_bedpp_is_safe_and_monotone(seed, design):
+    n, p = 120, 400
+    if design == "gaussian":
+        Xt = datagen.gaussian_f64(seed, n, p)
+    elif design == "genotype":
+        Xt = datagen.genotype_u8(seed, n, p).astype(np.float64)
+    elif design == "ar1":
+        Xt = datagen.ar1_f32(seed, n, p, 0.5).astype(np.float64)
+    else:
+        Xt = datagen.ar1_f32(seed, n, p, 0.95, block=20).astype(np.float64)
+    rng = np.random.default_rng(seed)
+    sup = rng.choice(p, 10, replace=False)
+    y = Xt[sup].T @ rng.normal(size=10) * 2 + rng.normal(size=n)
+    path = oracle.fit_path(Xt, y, K=60, ratio=0.01)
+    a, b, keep, lmax, sg, v = bedpp_inputs(Xt, y)
+    prev = None
+    total_discarded = 0
+    for k, lam in enumerate(path.lam):
+        d = oracle.bedpp_discard(a, b, keep, lmax, sg, v, lam)
+        assert not np.any(d & (path.beta[k] != 0)), f"BEDPP discarded an active feature at k={k}"
+        if prev is not None:
+            assert not np.any(d & ~prev), "safe set must grow as lambda decreases"
+        prev = d
+        total_discarded += d.sum()
+    assert total_discarded > 0
+
+
+def test_bedpp_at_lambda_max_reduces_to_correlation_test():
+    prob = datagen.make("c1", n=200, p=500)
+    a, b, keep, lmax, sg, v = bedpp_inputs(prob.Xt, prob.y[0])
+    d = oracle.bedpp_discard(a, b, keep, lmax, sg, v, lmax)
+    np.testing.assert_array_equal(d, np.abs(a) < lmax)
+
+
+def test_bedpp_on_orthogonal_design_implies_inactive():
+    n, p = 80, 30
+    Xt = orthogonal_design(n, p, 41)
+    rng = np.random.default_rng(42)
+    y = Xt.T @ (rng.normal(size=p) * (rng.uniform(size=p) < 0.3)) + rng.normal(size=n)
+    a, b, keep, lmax, sg, v = bedpp_inputs(Xt, y)
+    for lam in lmax * np.geomspace(1.0, 0.05, 30):
+        d = oracle.bedpp_discard(a, b, keep, lmax, sg, v, lam)
+        assert np.all(np.abs(a[d]) < lam)
+
+
+# ---------------------------------------------------------------------------------------------
+# lambda grid: the lambda values printed in the paper's Section 5 example (tests/golden)
+# ---------------------------------------------------------------------------------------------
+
+def read_golden(name):
+    vals = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                k, v = line.split("=")
+                vals[k.strip()] = v.strip()
+    return vals
+
+
+def test_lambda_grid_reproduces_printed_example():
+    g = read_golden("colon_lambda_grid.txt")
+    printed = [float(x) for x in g["lambda_first"].split(",")]
+    K = int(g["nlambda"])
+    ratio = float(g["lambda_min_ratio"])
+    k_sel = int(g["selected_index"])
+    sel = float(g["selected_lambda"])
+    lo, hi = printed[0] - 0.5e-4, printed[0] + 0.5e-4
+
+    def matches(lmax):
+        lam = oracle.lambda_grid(lmax, ratio, K)
+        ok = all(float(f"{lam[k]:.4g}") == printed[k] for k in range(len(printed)))
+        return ok and float(f"{lam[k_sel]:.3g}") == sel
+
+    cands = np.linspace(lo, hi, 2001)
+    assert any(matches(x) for x in cands)
+    # an arithmetic grid with the same endpoints does not reproduce the printed values
+    arith = [np.linspace(x, ratio * x, K) for x in cands]
+    assert not any(all(float(f"{g_[k]:.4g}") == printed[k] for k in range(len(printed))) for g_ in arith)
+
+
+# ---------------------------------------------------------------------------------------------
+# screening network (learned form): gradients against finite differences
+# ---------------------------------------------------------------------------------------------
+
+def test_mlp_gradient_matches_finite_differences():
+    H = 6
+    rng = np.random.default_rng(8)
+    params = rng.normal(scale=0.5, size=oracle.n_params(H))
+    feat = rng.uniform(0, 2, size=(25, 4))
+    label = (rng.uniform(size=25) < 0.4).astype(np.float64)
+    loss, grad = oracle.mlp_loss_grad(feat, label, params, H)
+    eps = 1e-6
+    num = np.empty_like(params)
+    for i in range(params.size):
+        pp = params.copy()
+        pp[i] += eps
+        lp, _ = oracle.mlp_loss_grad(feat, label, pp, H)
+        pp[i] -= 2 * eps
+        lm, _ = oracle.mlp_loss_grad(feat, label, pp, H)
+        num[i] = (lp - lm) / (2 * eps)
+    np.testing.assert_allclose(grad, num, atol=1e-7, rtol=1e-5)
+    prob = oracle.mlp_forward(feat, params, H)
+    bce = -np.mean(label * np.log(prob) + (1 - label) * np.log(1 - prob))
+    assert loss == pytest.approx(bce, rel=1e-10)
