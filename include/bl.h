@@ -1,0 +1,215 @@
+/*
+ * bl.h -- C ABI of the GPU pathwise-lasso library (libbl.so) for AMD CDNA4 (gfx950).
+ *
+ * The library computes the lasso solution path with implicit standardization,
+ * hybrid safe-strong screening (BEDPP + sequential strong rule) and a
+ * post-convergence check, as described by Zeng & Breheny, "The biglasso
+ * Package" (arXiv:1701.05936), Sections 2.2 and 3.1.
+ *
+ * Problem (standardized scale; the paper standardizes X, Section 3.1):
+ *   minimize over beta  Q(beta; lambda) = ||y~ - X~ beta||^2 / (2n) + lambda ||beta||_1
+ *   x~_ij = (x_ij - c_j) / s_j   (c_j column mean, s_j column SD with divisor n, over the fitted rows)
+ *   y~_i  = y_i - mean(y)        (the intercept is unpenalized)
+ * z_j(r) = x~_j' r / n is the standardized correlation of column j with a residual r.
+ *
+ * General conventions
+ *   - Every array argument is a DEVICE pointer unless the comment says "host".
+ *     The caller allocates and owns every array.  Scalar outputs are host pointers.
+ *   - X is column-major: element (i, j) at X[i + j*ldx], ldx >= n_total.
+ *   - Vectors over rows (y, y~, r) have n_total entries.  Rows outside the fit
+ *     (row_mask[i] == 0) must hold 0 in residual vectors; the library writes 0 there.
+ *   - All work is enqueued on the context's HIP stream.  A call returns after
+ *     its host-visible (scalar) outputs are available; device outputs are then
+ *     also complete.
+ *   - Errors are return codes; bl_last_error() gives the message.  Arguments
+ *     are validated on the host before anything is launched.  On error, device
+ *     outputs are unspecified (bl_fit_path: see k_done).
+ *   - Calls on one context must not overlap (one host thread at a time).
+ */
+#ifndef BL_H
+#define BL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bl_ctx_s* bl_ctx;
+
+typedef enum {
+    BL_OK = 0,
+    BL_ERR_INVALID = 1,        /* bad argument (null pointer, size, NaN/Inf scalar, misaligned X ...) */
+    BL_ERR_NOMEM = 2,          /* device scratch allocation failed                                     */
+    BL_ERR_DEVICE = 3,         /* a HIP call failed                                                    */
+    BL_ERR_NOT_CONVERGED = 4,  /* coordinate descent hit max_sweeps                                    */
+    BL_ERR_UNSUPPORTED = 5     /* valid request outside what this build handles (e.g. n_total too big) */
+} bl_status;
+
+typedef enum {
+    BL_X_F64 = 0,   /* double                                      */
+    BL_X_F32 = 1,   /* float                                       */
+    BL_X_I8 = 2     /* int8 codes (e.g. genotypes 0, 1, 2), exact   */
+} bl_xtype;
+
+typedef enum {
+    BL_SCREEN_NONE = 0,       /* working set = every kept feature                                   */
+    BL_SCREEN_SSR = 1,        /* sequential strong rule + check over all kept features              */
+    BL_SCREEN_BEDPP = 2,      /* safe rule only: working set = BEDPP survivors, check over them     */
+    BL_SCREEN_SSR_BEDPP = 3   /* hybrid (default): strong rule and check restricted to BEDPP survivors */
+} bl_screen_rule;
+
+/* Design matrix.  X must be 16-byte aligned when ldx*sizeof(element) is a multiple of 16;
+ * otherwise the library uses element-wise loads (slower, still correct). */
+typedef struct {
+    const void* X;             /* device, column-major, n_total x p, leading dimension ldx        */
+    int32_t xtype;             /* bl_xtype                                                        */
+    int64_t n_total;           /* rows stored                                                     */
+    int64_t p;                 /* columns                                                         */
+    int64_t ldx;               /* leading dimension (elements), >= n_total                        */
+    const uint8_t* row_mask;   /* device [n_total], 1 = row is in the fit; NULL = all rows.
+                                  Cross-validation fits pass a mask instead of copying X (Section 3.1.2). */
+} bl_matrix;
+
+/* Create a context on `device` ordinal using `hip_stream` (hipStream_t; NULL = default stream). */
+bl_status bl_create(bl_ctx* ctx, int device, void* hip_stream);
+void bl_destroy(bl_ctx ctx);
+const char* bl_last_error(bl_ctx ctx);
+/* Number of compute units and the device name the context runs on (host outputs). */
+bl_status bl_device_info(bl_ctx ctx, int* n_cu, char* name, int name_len);
+
+/*
+ * Column centers and scales over the fitted rows (Section 3.1: only c and s are
+ * kept, X~ is never formed).  center[j] = mean, scale[j] = SD with divisor n,
+ * keep[j] = scale[j] > 1e-6 (constant columns are left out of the fit).
+ * Int8 X: sums are exact integers.  n_rows (host, may be NULL) = rows in the fit.
+ * Outputs: center, scale (double [p]), keep (uint8 [p]).
+ */
+bl_status bl_standardize(bl_ctx ctx, const bl_matrix* X, double* center, double* scale, uint8_t* keep,
+                         int64_t* n_rows);
+
+/*
+ * lambda_max (Section 3.1.1, type (2) products): y_mean = mean of y over the fit,
+ * ytilde = y - y_mean on fitted rows and 0 elsewhere, a[j] = z_j(ytilde)
+ * (0 for columns not kept), lambda_max = max_j |a_j|, jstar = smallest j attaining it.
+ * beta = 0 is the solution for every lambda >= lambda_max.
+ * Inputs: y [n_total].  Outputs: ytilde [n_total], a [p]; y_mean, lambda_max, jstar are host.
+ * Returns BL_ERR_INVALID if no column is kept.
+ */
+bl_status bl_lambda_max(bl_ctx ctx, const bl_matrix* X, const double* center, const double* scale,
+                        const uint8_t* keep, const double* y, double* ytilde, double* a, double* y_mean,
+                        double* lambda_max, int64_t* jstar);
+
+/*
+ * One-time inputs of the BEDPP safe rule (Section 2.2; Section 3.1.1 type (1)):
+ * b[j] = x~_j' x~_* / n with x~_* the column jstar, and v = ||ytilde||^2 / n (host).
+ */
+bl_status bl_bedpp_setup(bl_ctx ctx, const bl_matrix* X, const double* center, const double* scale,
+                         const uint8_t* keep, const double* ytilde, int64_t jstar, double* b, double* v);
+
+/* State the screening rules read (all device arrays have p entries). */
+typedef struct {
+    int64_t p;
+    int32_t rule;              /* bl_screen_rule                                            */
+    const double* a;           /* z_j(ytilde)                                               */
+    const double* b;           /* BEDPP b_j                                                 */
+    const uint8_t* keep;       /* kept columns                                              */
+    const uint8_t* active;     /* beta_j != 0 at the previous lambda (uint8), or NULL       */
+    double lambda_max;
+    double sign_star;          /* sign(a[jstar]), +1 or -1                                   */
+    double v;                  /* ||ytilde||^2 / n                                          */
+} bl_screen_state;
+
+/*
+ * Screening at lambda_k (Section 2.2):
+ *   safe[j]   = 1 unless BEDPP discards j at lambda_k (always 1 for kept j when the
+ *               rule has no BEDPP part; 0 for columns not kept).  BEDPP discards j when
+ *               |(lm + l) a_j - (lm - l) sign_star lm b_j| < 2 l lm - (lm - l) sqrt(max(0, v - lm^2)).
+ *   strong[j] = safe[j] and (active[j] or |z_prev[j]| >= 2 lambda_k - lambda_prev)
+ *               (strong rule; for rule NONE or BEDPP: strong = safe).
+ * z_prev [p] holds z at lambda_prev (only read where safe[j] = 1).
+ * n_safe, n_strong: host counts.
+ */
+bl_status bl_screen(bl_ctx ctx, const bl_screen_state* st, double lambda_k, double lambda_prev,
+                    const double* z_prev, uint8_t* safe, uint8_t* strong, int64_t* n_safe, int64_t* n_strong);
+
+/*
+ * Cyclic coordinate descent at fixed lambda over the features set[0..set_len-1]
+ * (visited in that order; int32 indices into 0..p-1, distinct, kept), warm-started
+ * from beta [p] and its residual r [n_total] = ytilde - X~ beta, both updated in place.
+ * Coordinate step: u = z_j(r) + beta_j, beta_j' = S(u, lambda), r -= (beta_j' - beta_j) x~_j.
+ * Stops when the largest |beta_j' - beta_j| of a sweep is < tol.  sweeps (host) = sweeps run.
+ * Returns BL_ERR_NOT_CONVERGED after max_sweeps sweeps (beta, r are then the last iterate).
+ * n_total <= 16384 in this build (BL_ERR_UNSUPPORTED otherwise).
+ */
+bl_status bl_cd_solve(bl_ctx ctx, const bl_matrix* X, const double* center, const double* scale,
+                      double lambda, const int32_t* set, int64_t set_len, double* beta, double* r, double tol,
+                      int32_t max_sweeps, int32_t* sweeps);
+
+/*
+ * Post-convergence check (Sections 2.2 and 3.1.1, type (3)): for every j in
+ * check_set[0..len-1] (int32, ascending) compute
+ *   z[j] = (x_j' r - c_j sum(r)) / (n s_j)
+ * (sum(r) is computed once per call) and collect the violators
+ *   { j in check_set : exclude[j] == 0 and |z[j]| > lambda }
+ * into violators[0..n_viol-1] in ascending order.  exclude [p] may be NULL
+ * (nothing excluded).  z entries outside check_set are left untouched.
+ * violators must have room for len entries; n_viol is host.
+ */
+bl_status bl_kkt_check(bl_ctx ctx, const bl_matrix* X, const double* center, const double* scale,
+                       const double* r, double lambda, const int32_t* check_set, int64_t len,
+                       const uint8_t* exclude, double* z, int32_t* violators, int64_t* n_viol);
+
+/* Options of bl_fit_path. */
+typedef struct {
+    int32_t nlambda;           /* K >= 1                                                      */
+    double lambda_min_ratio;   /* 0 < ratio < 1; grid lambda_k = lambda_max ratio^(k/(K-1))   */
+    const double* lambda;      /* host [K] user grid (decreasing, positive) or NULL           */
+    int32_t rule;              /* bl_screen_rule                                              */
+    double tol;                /* CD stop: largest |coefficient change| in a sweep < tol       */
+    int32_t max_sweeps;        /* per CD solve                                                */
+    int32_t max_rounds;        /* CD + check rounds per lambda before giving up (>= 1)        */
+} bl_path_opts;
+
+/* Results of bl_fit_path.  Host arrays have K entries; any pointer may be NULL (not written). */
+typedef struct {
+    double* beta;              /* DEVICE [K x p] row k = beta(lambda_k), standardized scale   */
+    double* center;            /* DEVICE [p]                                                   */
+    double* scale;             /* DEVICE [p]                                                   */
+    uint8_t* keep;             /* DEVICE [p]                                                   */
+    double* lambda;            /* host: grid used                                             */
+    double* intercept;         /* host: y_mean - sum_j c_j beta_j / s_j (original scale)     */
+    double* rss;               /* host: ||r||^2                                               */
+    double* obj;               /* host: Q(beta; lambda_k)                                      */
+    int32_t* sweeps;           /* host: CD sweeps summed over rounds                          */
+    int32_t* rounds;           /* host: CD solves (0 at k = 0)                                 */
+    int64_t* n_active;         /* host: nonzero coefficients                                  */
+    int64_t* n_strong;         /* host: size of the working set after the last round          */
+    int64_t* n_safe;           /* host: BEDPP survivors (p - safe rejections)                  */
+    int64_t* n_viol;           /* host: features the check added back                          */
+    int64_t* n_scanned;        /* host: columns scanned by checks at this lambda               */
+    double y_mean;             /* out                                                          */
+    double lambda_max;         /* out                                                          */
+    int64_t jstar;             /* out                                                          */
+    int32_t k_done;            /* out: lambdas finished (results valid for k < k_done)         */
+    double time_ms;            /* out: wall time of the call                                   */
+} bl_path_result;
+
+/*
+ * The whole lasso path (Sections 2.2 and 3): standardize, lambda_max, BEDPP set-up,
+ * then for k = 1..K-1 with warm starts:
+ *   S_k   = BEDPP survivors at lambda_k (grows along the path);
+ *   E_k   = active(k-1) u { j in S_k : |z_j(k-1)| >= 2 lambda_k - lambda_{k-1} };
+ *   repeat: CD over E_k; scan z over S_{k+1} (which contains S_k);
+ *           V = { j in S_k \ E_k : |z_j| > lambda_k }; stop if V is empty; E_k u= V.
+ * The scan at lambda_k also supplies the strong-rule input for lambda_{k+1}.
+ * y [n_total] device.  Returns BL_ERR_NOT_CONVERGED if CD or max_rounds gave out
+ * (res->k_done tells how far the path got).
+ */
+bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_path_opts* opts,
+                      bl_path_result* res);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BL_H */

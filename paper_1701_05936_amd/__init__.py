@@ -1,0 +1,309 @@
+"""Python binding of libbl.so, the gfx950 pathwise-lasso library.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in include/bl.h.  PyTorch supplies device
+memory and the stream.  There is no fallback: if libbl.so is missing or the
+device is unavailable, the calls raise.
+
+Matrices are passed as tensors ``Xt`` of shape (p, ld): row j holds column j
+of X, so the bytes are X in column-major order with leading dimension ld.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbl.so")
+
+BL_OK, BL_ERR_INVALID, BL_ERR_NOMEM, BL_ERR_DEVICE, BL_ERR_NOT_CONVERGED, BL_ERR_UNSUPPORTED = range(6)
+X_F64, X_F32, X_I8 = 0, 1, 2
+SCREEN_NONE, SCREEN_SSR, SCREEN_BEDPP, SCREEN_SSR_BEDPP = 0, 1, 2, 3
+
+_STATUS_NAMES = {0: "BL_OK", 1: "BL_ERR_INVALID", 2: "BL_ERR_NOMEM", 3: "BL_ERR_DEVICE",
+                 4: "BL_ERR_NOT_CONVERGED", 5: "BL_ERR_UNSUPPORTED"}
+
+# exported C symbols (kept in step with include/bl.h)
+EXPORTS = ("bl_create", "bl_destroy", "bl_last_error", "bl_device_info", "bl_standardize", "bl_lambda_max",
+           "bl_bedpp_setup", "bl_screen", "bl_cd_solve", "bl_kkt_check", "bl_fit_path")
+
+
+class BLError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Matrix(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("xtype", ctypes.c_int32), ("n_total", ctypes.c_int64),
+                ("p", ctypes.c_int64), ("ldx", ctypes.c_int64), ("row_mask", ctypes.c_void_p)]
+
+
+class _ScreenState(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int64), ("rule", ctypes.c_int32), ("a", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("keep", ctypes.c_void_p), ("active", ctypes.c_void_p), ("lambda_max", ctypes.c_double),
+                ("sign_star", ctypes.c_double), ("v", ctypes.c_double)]
+
+
+class _PathOpts(ctypes.Structure):
+    _fields_ = [("nlambda", ctypes.c_int32), ("lambda_min_ratio", ctypes.c_double), ("lambda_", ctypes.c_void_p),
+                ("rule", ctypes.c_int32), ("tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
+                ("max_rounds", ctypes.c_int32)]
+
+
+class _PathResult(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_void_p), ("center", ctypes.c_void_p), ("scale", ctypes.c_void_p),
+                ("keep", ctypes.c_void_p), ("lambda_", ctypes.c_void_p), ("intercept", ctypes.c_void_p),
+                ("rss", ctypes.c_void_p), ("obj", ctypes.c_void_p), ("sweeps", ctypes.c_void_p),
+                ("rounds", ctypes.c_void_p), ("n_active", ctypes.c_void_p), ("n_strong", ctypes.c_void_p),
+                ("n_safe", ctypes.c_void_p), ("n_viol", ctypes.c_void_p), ("n_scanned", ctypes.c_void_p),
+                ("y_mean", ctypes.c_double), ("lambda_max", ctypes.c_double), ("jstar", ctypes.c_int64),
+                ("k_done", ctypes.c_int32), ("time_ms", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libbl.so and declare the C signatures.  Raises if the library is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libbl.so not built ({path}); run paper_1701_05936_amd/build.py")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    L.bl_create.argtypes = [P(vp), ctypes.c_int, vp]
+    L.bl_destroy.argtypes = [vp]
+    L.bl_destroy.restype = None
+    L.bl_last_error.argtypes = [vp]
+    L.bl_last_error.restype = ctypes.c_char_p
+    L.bl_device_info.argtypes = [vp, P(ctypes.c_int), ctypes.c_char_p, ctypes.c_int]
+    L.bl_standardize.argtypes = [vp, P(_Matrix), vp, vp, vp, P(i64)]
+    L.bl_lambda_max.argtypes = [vp, P(_Matrix), vp, vp, vp, vp, vp, vp, P(dbl), P(dbl), P(i64)]
+    L.bl_bedpp_setup.argtypes = [vp, P(_Matrix), vp, vp, vp, vp, i64, vp, P(dbl)]
+    L.bl_screen.argtypes = [vp, P(_ScreenState), dbl, dbl, vp, vp, vp, P(i64), P(i64)]
+    L.bl_cd_solve.argtypes = [vp, P(_Matrix), vp, vp, dbl, vp, i64, vp, vp, dbl, i32, P(i32)]
+    L.bl_kkt_check.argtypes = [vp, P(_Matrix), vp, vp, vp, dbl, vp, i64, vp, vp, vp, P(i64)]
+    L.bl_fit_path.argtypes = [vp, P(_Matrix), vp, P(_PathOpts), P(_PathResult)]
+    for name in EXPORTS:
+        f = getattr(L, name)
+        if name not in ("bl_destroy", "bl_last_error"):
+            f.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+_XTYPES = {torch.float64: X_F64, torch.float32: X_F32, torch.int8: X_I8}
+
+
+def matrix(Xt: torch.Tensor, n_total: int | None = None, row_mask: torch.Tensor | None = None) -> _Matrix:
+    """Descriptor of X given as a (p, ld) tensor; n_total defaults to ld."""
+    if Xt.dim() != 2:
+        raise ValueError("Xt must be 2-D (p, ld)")
+    if Xt.dtype not in _XTYPES:
+        raise TypeError(f"unsupported X dtype {Xt.dtype}")
+    p, ld = Xt.shape
+    n_total = ld if n_total is None else int(n_total)
+    if row_mask is not None and (row_mask.dtype != torch.uint8 or row_mask.numel() != n_total):
+        raise ValueError("row_mask must be uint8 with n_total entries")
+    return _Matrix(_ptr(Xt), _XTYPES[Xt.dtype], n_total, p, ld, _ptr(row_mask))
+
+
+class Context:
+    """A library context bound to one device and the current torch stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        L = load_library()
+        torch.cuda.set_device(device)
+        stream = stream or torch.cuda.current_stream(device)
+        self.stream = stream
+        self.device = device
+        h = ctypes.c_void_p()
+        st = L.bl_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        if st != BL_OK:
+            raise BLError(st, "bl_create failed")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().bl_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st: int):
+        if st != BL_OK:
+            msg = load_library().bl_last_error(self._h).decode(errors="replace")
+            raise BLError(st, msg)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def device_info(self):
+        n = ctypes.c_int()
+        buf = ctypes.create_string_buffer(256)
+        self._check(load_library().bl_device_info(self._h, ctypes.byref(n), buf, 256))
+        return n.value, buf.value.decode()
+
+
+def _dev(ctx):
+    return torch.device("cuda", ctx.device)
+
+
+def standardize(ctx: Context, Xt, row_mask=None, n_total=None):
+    M = matrix(Xt, n_total, row_mask)
+    p = M.p
+    c = torch.empty(p, dtype=torch.float64, device=_dev(ctx))
+    s = torch.empty_like(c)
+    keep = torch.empty(p, dtype=torch.uint8, device=_dev(ctx))
+    n = ctypes.c_int64()
+    ctx._check(load_library().bl_standardize(ctx.handle, ctypes.byref(M), _ptr(c), _ptr(s), _ptr(keep),
+                                             ctypes.byref(n)))
+    return c, s, keep, n.value
+
+
+def lambda_max(ctx: Context, Xt, c, s, keep, y, row_mask=None, n_total=None):
+    M = matrix(Xt, n_total, row_mask)
+    yt = torch.empty(M.n_total, dtype=torch.float64, device=_dev(ctx))
+    a = torch.empty(M.p, dtype=torch.float64, device=_dev(ctx))
+    ym, lm, js = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    ctx._check(load_library().bl_lambda_max(ctx.handle, ctypes.byref(M), _ptr(c), _ptr(s), _ptr(keep), _ptr(y),
+                                            _ptr(yt), _ptr(a), ctypes.byref(ym), ctypes.byref(lm), ctypes.byref(js)))
+    return ym.value, yt, a, lm.value, js.value
+
+
+def bedpp_setup(ctx: Context, Xt, c, s, keep, ytilde, jstar, row_mask=None, n_total=None):
+    M = matrix(Xt, n_total, row_mask)
+    b = torch.empty(M.p, dtype=torch.float64, device=_dev(ctx))
+    v = ctypes.c_double()
+    ctx._check(load_library().bl_bedpp_setup(ctx.handle, ctypes.byref(M), _ptr(c), _ptr(s), _ptr(keep),
+                                             _ptr(ytilde), int(jstar), _ptr(b), ctypes.byref(v)))
+    return b, v.value
+
+
+def screen(ctx: Context, rule, a, b, keep, lambda_max, sign_star, v, lam, lam_prev, z_prev, active=None):
+    p = keep.numel()
+    st = _ScreenState(p, rule, _ptr(a), _ptr(b), _ptr(keep), _ptr(active), lambda_max, sign_star, v)
+    safe = torch.empty(p, dtype=torch.uint8, device=_dev(ctx))
+    strong = torch.empty_like(safe)
+    ns, ne = ctypes.c_int64(), ctypes.c_int64()
+    ctx._check(load_library().bl_screen(ctx.handle, ctypes.byref(st), lam, lam_prev, _ptr(z_prev), _ptr(safe),
+                                        _ptr(strong), ctypes.byref(ns), ctypes.byref(ne)))
+    return safe, strong, ns.value, ne.value
+
+
+def cd_solve(ctx: Context, Xt, c, s, lam, cset, beta, r, tol=1e-10, max_sweeps=100000, row_mask=None,
+             n_total=None):
+    """In-place cyclic CD on beta and r over the int32 index tensor cset; returns sweeps."""
+    M = matrix(Xt, n_total, row_mask)
+    if cset.dtype != torch.int32:
+        raise TypeError("cset must be int32")
+    sw = ctypes.c_int32()
+    ctx._check(load_library().bl_cd_solve(ctx.handle, ctypes.byref(M), _ptr(c), _ptr(s), lam,
+                                          _ptr(cset) if cset.numel() else None, cset.numel(), _ptr(beta), _ptr(r),
+                                          tol, max_sweeps, ctypes.byref(sw)))
+    return sw.value
+
+
+def kkt_check(ctx: Context, Xt, c, s, r, lam, check_set, exclude=None, z=None, row_mask=None, n_total=None):
+    """z over check_set and the ascending violators {j : !exclude[j], |z_j| > lam}."""
+    M = matrix(Xt, n_total, row_mask)
+    if check_set.dtype != torch.int32:
+        raise TypeError("check_set must be int32")
+    if z is None:
+        z = torch.zeros(M.p, dtype=torch.float64, device=_dev(ctx))
+    viol = torch.empty(max(1, check_set.numel()), dtype=torch.int32, device=_dev(ctx))
+    nv = ctypes.c_int64()
+    ctx._check(load_library().bl_kkt_check(ctx.handle, ctypes.byref(M), _ptr(c), _ptr(s), _ptr(r), lam,
+                                           _ptr(check_set) if check_set.numel() else None, check_set.numel(),
+                                           _ptr(exclude), _ptr(z), _ptr(viol), ctypes.byref(nv)))
+    return z, viol[: nv.value]
+
+
+@dataclass
+class PathResult:
+    lam: np.ndarray
+    beta: torch.Tensor | None    # (K, p) device, standardized scale
+    center: torch.Tensor
+    scale: torch.Tensor
+    keep: torch.Tensor
+    intercept: np.ndarray
+    rss: np.ndarray
+    obj: np.ndarray
+    sweeps: np.ndarray
+    rounds: np.ndarray
+    n_active: np.ndarray
+    n_strong: np.ndarray
+    n_safe: np.ndarray
+    n_viol: np.ndarray
+    n_scanned: np.ndarray
+    y_mean: float
+    lambda_max: float
+    jstar: int
+    k_done: int
+    time_ms: float
+    status: int
+    message: str
+
+
+def fit_path(ctx: Context, Xt, y, nlambda=100, lambda_min_ratio=0.1, lambdas=None, rule=SCREEN_SSR_BEDPP,
+             tol=1e-8, max_sweeps=100000, max_rounds=100, row_mask=None, n_total=None, want_beta=True,
+             raise_on_error=True) -> PathResult:
+    M = matrix(Xt, n_total, row_mask)
+    K = int(nlambda)
+    p = M.p
+    dev = _dev(ctx)
+    beta = torch.empty((K, p), dtype=torch.float64, device=dev) if want_beta else None
+    c = torch.empty(p, dtype=torch.float64, device=dev)
+    s = torch.empty_like(c)
+    keep = torch.empty(p, dtype=torch.uint8, device=dev)
+    host = {k: np.zeros(K) for k in ("lam", "intercept", "rss", "obj")}
+    host.update({k: np.zeros(K, dtype=np.int32) for k in ("sweeps", "rounds")})
+    host.update({k: np.zeros(K, dtype=np.int64) for k in ("n_active", "n_strong", "n_safe", "n_viol", "n_scanned")})
+    lam_in = None
+    if lambdas is not None:
+        lam_in = np.ascontiguousarray(lambdas, dtype=np.float64)
+        assert lam_in.size == K
+    opts = _PathOpts(K, float(lambda_min_ratio), lam_in.ctypes.data if lam_in is not None else None, int(rule),
+                     float(tol), int(max_sweeps), int(max_rounds))
+    res = _PathResult(_ptr(beta), _ptr(c), _ptr(s), _ptr(keep), host["lam"].ctypes.data,
+                      host["intercept"].ctypes.data, host["rss"].ctypes.data, host["obj"].ctypes.data,
+                      host["sweeps"].ctypes.data, host["rounds"].ctypes.data, host["n_active"].ctypes.data,
+                      host["n_strong"].ctypes.data, host["n_safe"].ctypes.data, host["n_viol"].ctypes.data,
+                      host["n_scanned"].ctypes.data, 0.0, 0.0, 0, 0, 0.0)
+    st = load_library().bl_fit_path(ctx.handle, ctypes.byref(M), _ptr(y), ctypes.byref(opts), ctypes.byref(res))
+    msg = load_library().bl_last_error(ctx.handle).decode(errors="replace") if st != BL_OK else ""
+    if st != BL_OK and raise_on_error:
+        raise BLError(st, msg)
+    return PathResult(host["lam"], beta, c, s, keep, host["intercept"], host["rss"], host["obj"], host["sweeps"],
+                      host["rounds"], host["n_active"], host["n_strong"], host["n_safe"], host["n_viol"],
+                      host["n_scanned"], res.y_mean, res.lambda_max, res.jstar, res.k_done, res.time_ms, st, msg)

@@ -1,0 +1,645 @@
+// C ABI of libbl.so: argument validation, device scratch, and the host-side
+// driver of the lasso path (one stream, one host synchronization per
+// CD + check round).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "bl.h"
+#include "internal.h"
+
+using namespace blk;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+}  // namespace
+
+struct bl_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    DevScalars* sc = nullptr;      // device
+    DevScalars* sc_host = nullptr; // pinned host mirror
+    std::vector<DevBuf> bufs;
+};
+
+namespace {
+
+enum BufId {
+    B_CMP = 0, B_ARGV, B_ARGI, B_YT, B_R, B_XS, B_A, B_B, B_Z0, B_Z1, B_S0, B_S1, B_E, B_LT, B_LE, B_LENS,
+    B_BETA, B_STATS, B_C, B_S, B_KEEP, B_MARK, B_COUNT
+};
+
+bl_status fail(bl_ctx c, bl_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(ctx, BL_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// Device scratch owned by the context; grown on demand, freed by bl_destroy.
+bl_status ensure(bl_ctx ctx, int id, size_t bytes, void** out) {
+    if ((int)ctx->bufs.size() <= id) ctx->bufs.resize(B_COUNT);
+    DevBuf& b = ctx->bufs[id];
+    if (bytes == 0) bytes = 8;
+    if (b.cap < bytes) {
+        if (b.p) (void)hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+        if (hipMalloc(&b.p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ctx, BL_ERR_NOMEM, "device scratch allocation of %zu bytes failed", bytes);
+        }
+        b.cap = bytes;
+    }
+    *out = b.p;
+    return BL_OK;
+}
+
+#define ENSURE(id, bytes, ptr)                                          \
+    do {                                                                \
+        void* p_;                                                       \
+        bl_status s_ = ensure(ctx, (id), (size_t)(bytes), &p_);         \
+        if (s_ != BL_OK) return s_;                                     \
+        (ptr) = (decltype(ptr))p_;                                      \
+    } while (0)
+
+int elem_bytes(int xtype) { return xtype == BL_X_F64 ? 8 : (xtype == BL_X_F32 ? 4 : 1); }
+
+bl_status check_ctx(bl_ctx ctx) {
+    if (!ctx) return BL_ERR_INVALID;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, BL_ERR_DEVICE, "hipSetDevice failed");
+    return BL_OK;
+}
+
+bl_status check_matrix(bl_ctx ctx, const bl_matrix* X, Mat* m) {
+    if (!X) return fail(ctx, BL_ERR_INVALID, "X is NULL");
+    if (!X->X) return fail(ctx, BL_ERR_INVALID, "X->X is NULL");
+    if (X->xtype != BL_X_F64 && X->xtype != BL_X_F32 && X->xtype != BL_X_I8)
+        return fail(ctx, BL_ERR_INVALID, "unknown xtype %d", X->xtype);
+    if (X->n_total < 1) return fail(ctx, BL_ERR_INVALID, "n_total must be >= 1 (got %lld)", (long long)X->n_total);
+    if (X->p < 1) return fail(ctx, BL_ERR_INVALID, "p must be >= 1 (got %lld)", (long long)X->p);
+    if (X->p > 2147483647LL) return fail(ctx, BL_ERR_UNSUPPORTED, "p above 2^31-1");
+    if (X->n_total > 2147483647LL) return fail(ctx, BL_ERR_UNSUPPORTED, "n_total above 2^31-1");
+    if (X->ldx < X->n_total) return fail(ctx, BL_ERR_INVALID, "ldx < n_total");
+    m->X = X->X;
+    m->xtype = X->xtype;
+    m->n_total = X->n_total;
+    m->p = X->p;
+    m->ldx = X->ldx;
+    m->mask = X->row_mask;
+    return BL_OK;
+}
+
+// rows in the fit (synchronous)
+bl_status rows_in_fit(bl_ctx ctx, const Mat& m, int64_t* n) {
+    if (!m.mask) {
+        *n = m.n_total;
+        return BL_OK;
+    }
+    HIPCHK(launch_count_rows(m, &ctx->sc->n_rows, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->sc_host, ctx->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    *n = ctx->sc_host->n_rows;
+    if (*n < 1) return fail(ctx, BL_ERR_INVALID, "row_mask selects no rows");
+    return BL_OK;
+}
+
+bl_status set_n_rows(bl_ctx ctx, int64_t n) {
+    HIPCHK(hipMemcpyAsync(&ctx->sc->n_rows, &n, sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return BL_OK;
+}
+
+bl_status read_scalars(bl_ctx ctx) {
+    HIPCHK(hipMemcpyAsync(ctx->sc_host, ctx->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return BL_OK;
+}
+
+double bedpp_rhs(double lmax, double lam, double v) {
+    double slack = v - lmax * lmax;
+    if (slack < 0.0) slack = 0.0;
+    return 2.0 * lam * lmax - (lmax - lam) * std::sqrt(slack);
+}
+
+}  // namespace
+
+extern "C" {
+
+bl_status bl_create(bl_ctx* out, int device, void* hip_stream) {
+    if (!out) return BL_ERR_INVALID;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return BL_ERR_DEVICE;
+    if (device < 0 || device >= ndev) return BL_ERR_INVALID;
+    if (hipSetDevice(device) != hipSuccess) return BL_ERR_DEVICE;
+    bl_ctx c = new bl_ctx_s();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->bufs.resize(B_COUNT);
+    if (hipMalloc(&c->sc, sizeof(DevScalars)) != hipSuccess ||
+        hipHostMalloc((void**)&c->sc_host, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        bl_destroy(c);
+        return BL_ERR_NOMEM;
+    }
+    std::memset(c->sc_host, 0, sizeof(DevScalars));
+    *out = c;
+    return BL_OK;
+}
+
+void bl_destroy(bl_ctx c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    for (auto& b : c->bufs)
+        if (b.p) (void)hipFree(b.p);
+    if (c->sc) (void)hipFree(c->sc);
+    if (c->sc_host) (void)hipHostFree(c->sc_host);
+    delete c;
+}
+
+const char* bl_last_error(bl_ctx c) { return c ? c->err.c_str() : "null context"; }
+
+bl_status bl_device_info(bl_ctx ctx, int* n_cu, char* name, int name_len) {
+    bl_status s = check_ctx(ctx);
+    if (s) return s;
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, ctx->device));
+    if (n_cu) *n_cu = prop.multiProcessorCount;
+    if (name && name_len > 0) {
+        std::snprintf(name, (size_t)name_len, "%s (%s)", prop.name, prop.gcnArchName);
+    }
+    return BL_OK;
+}
+
+bl_status bl_standardize(bl_ctx ctx, const bl_matrix* X, double* center, double* scale, uint8_t* keep,
+                         int64_t* n_rows) {
+    bl_status s = check_ctx(ctx);
+    if (s) return s;
+    Mat m;
+    if ((s = check_matrix(ctx, X, &m))) return s;
+    if (!center || !scale || !keep) return fail(ctx, BL_ERR_INVALID, "center/scale/keep must be non-NULL");
+    int64_t n;
+    if ((s = rows_in_fit(ctx, m, &n))) return s;
+    HIPCHK(launch_colstats(m, center, scale, keep, n, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (n_rows) *n_rows = n;
+    return BL_OK;
+}
+
+bl_status bl_lambda_max(bl_ctx ctx, const bl_matrix* X, const double* center, const double* scale,
+                        const uint8_t* keep, const double* y, double* ytilde, double* a, double* y_mean,
+                        double* lambda_max, int64_t* jstar) {
+    bl_status s = check_ctx(ctx);
+    if (s) return s;
+    Mat m;
+    if ((s = check_matrix(ctx, X, &m))) return s;
+    if (!center || !scale || !keep || !y || !ytilde || !a)
+        return fail(ctx, BL_ERR_INVALID, "array arguments must be non-NULL");
+    int64_t n;
+    if ((s = rows_in_fit(ctx, m, &n))) return s;
+    double* pv;
+    int64_t* pi;
+    ENSURE(B_ARGV, 256 * sizeof(double), pv);
+    ENSURE(B_ARGI, 256 * sizeof(int64_t), pi);
+    HIPCHK(launch_center_y(m, y, ytilde, nullptr, ctx->sc, ctx->stream));
+    HIPCHK(launch_sum_r(m, ytilde, ctx->sc, false, ctx->stream));
+    ScanArgs sa{};
+    sa.cols = nullptr;
+    sa.len_dev = nullptr;
+    sa.len_host = m.p;
+    sa.r = ytilde;
+    sa.sc = ctx->sc;
+    sa.c = center;
+    sa.s = scale;
+    sa.keep = keep;
+    sa.z = a;
+    HIPCHK(launch_scan(m, sa, ctx->stream));
+    HIPCHK(launch_argmax_abs(a, keep, m.p, pv, pi, ctx->sc, ctx->stream));
+    if ((s = read_scalars(ctx))) return s;
+    const DevScalars& h = *ctx->sc_host;
+    if (!std::isfinite(h.y_mean) || !std::isfinite(h.yy)) return fail(ctx, BL_ERR_INVALID, "y has NaN or Inf");
+    if (h.jstar < 0) return fail(ctx, BL_ERR_INVALID, "no column is kept (all constant)");
+    if (!std::isfinite(h.lmax)) return fail(ctx, BL_ERR_INVALID, "X or y has NaN or Inf (lambda_max not finite)");
+    if (y_mean) *y_mean = h.y_mean;
+    if (lambda_max) *lambda_max = h.lmax;
+    if (jstar) *jstar = h.jstar;
+    return BL_OK;
+}
+
+bl_status bl_bedpp_setup(bl_ctx ctx, const bl_matrix* X, const double* center, const double* scale,
+                         const uint8_t* keep, const double* ytilde, int64_t jstar, double* b, double* v) {
+    bl_status s = check_ctx(ctx);
+    if (s) return s;
+    Mat m;
+    if ((s = check_matrix(ctx, X, &m))) return s;
+    if (!center || !scale || !keep || !ytilde || !b) return fail(ctx, BL_ERR_INVALID, "array arguments must be non-NULL");
+    if (jstar < 0 || jstar >= m.p) return fail(ctx, BL_ERR_INVALID, "jstar out of range");
+    int64_t n;
+    if ((s = rows_in_fit(ctx, m, &n))) return s;
+    if ((s = set_n_rows(ctx, n))) return s;
+    double* xs;
+    ENSURE(B_XS, m.n_total * sizeof(double), xs);
+    HIPCHK(launch_sum_r(m, ytilde, ctx->sc, true, ctx->stream));  // rss = ||y~||^2
+    HIPCHK(launch_std_column(m, jstar, center, scale, xs, ctx->stream));
+    HIPCHK(launch_sum_r(m, xs, ctx->sc, false, ctx->stream));
+    ScanArgs sa{};
+    sa.len_host = m.p;
+    sa.r = xs;
+    sa.sc = ctx->sc;
+    sa.c = center;
+    sa.s = scale;
+    sa.keep = keep;
+    sa.z = b;
+    HIPCHK(launch_scan(m, sa, ctx->stream));
+    if ((s = read_scalars(ctx))) return s;
+    if (v) *v = ctx->sc_host->rss / (double)n;
+    return BL_OK;
+}
+
+bl_status bl_screen(bl_ctx ctx, const bl_screen_state* st, double lambda_k, double lambda_prev, const double* z_prev,
+                    uint8_t* safe, uint8_t* strong, int64_t* n_safe, int64_t* n_strong) {
+    bl_status s = check_ctx(ctx);
+    if (s) return s;
+    if (!st || !safe || !strong) return fail(ctx, BL_ERR_INVALID, "state/safe/strong must be non-NULL");
+    if (st->p < 1 || st->p > 2147483647LL) return fail(ctx, BL_ERR_INVALID, "bad p");
+    if (!st->keep) return fail(ctx, BL_ERR_INVALID, "keep must be non-NULL");
+    const int rule = st->rule;
+    if (rule < BL_SCREEN_NONE || rule > BL_SCREEN_SSR_BEDPP) return fail(ctx, BL_ERR_INVALID, "unknown rule");
+    const bool bedpp = rule == BL_SCREEN_BEDPP || rule == BL_SCREEN_SSR_BEDPP;
+    const bool ssr = rule == BL_SCREEN_SSR || rule == BL_SCREEN_SSR_BEDPP;
+    if (bedpp && (!st->a || !st->b)) return fail(ctx, BL_ERR_INVALID, "BEDPP needs a and b");
+    if (ssr && !z_prev) return fail(ctx, BL_ERR_INVALID, "strong rule needs z_prev");
+    if (!(std::isfinite(lambda_k) && lambda_k > 0.0)) return fail(ctx, BL_ERR_INVALID, "lambda_k must be finite and > 0");
+    if (ssr && !(std::isfinite(lambda_prev) && lambda_prev >= lambda_k))
+        return fail(ctx, BL_ERR_INVALID, "lambda_prev must be finite and >= lambda_k");
+    if (bedpp && !(std::isfinite(st->lambda_max) && st->lambda_max > 0.0 && std::isfinite(st->v)))
+        return fail(ctx, BL_ERR_INVALID, "bad lambda_max or v");
+    const int64_t p = st->p;
+    const double rhs = bedpp ? bedpp_rhs(st->lambda_max, lambda_k, st->v) : 0.0;
+    const double sgn = st->sign_star < 0 ? -1.0 : 1.0;
+    HIPCHK(launch_bedpp(p, st->a, st->b, st->keep, bedpp, st->lambda_max, sgn, lambda_k, rhs, safe, ctx->stream));
+    HIPCHK(launch_ssr(p, safe, st->active, nullptr, z_prev, ssr, 2.0 * lambda_k - lambda_prev, strong, ctx->stream));
+    void* scr;
+    int32_t* lst;
+    int64_t* lens;
+    ENSURE(B_CMP, compact_scratch_bytes(p), scr);
+    ENSURE(B_LT, p * sizeof(int32_t), lst);
+    ENSURE(B_LENS, 8 * sizeof(int64_t), lens);
+    HIPCHK(launch_compact(safe, p, lst, lens + 0, scr, ctx->stream));
+    HIPCHK(launch_compact(strong, p, lst, lens + 1, scr, ctx->stream));
+    int64_t h[2];
+    HIPCHK(hipMemcpyAsync(h, lens, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (n_safe) *n_safe = h[0];
+    if (n_strong) *n_strong = h[1];
+    return BL_OK;
+}
+
+bl_status bl_cd_solve(bl_ctx ctx, const bl_matrix* X, const double* center, const double* scale, double lambda,
+                      const int32_t* set, int64_t set_len, double* beta, double* r, double tol, int32_t max_sweeps,
+                      int32_t* sweeps) {
+    bl_status s = check_ctx(ctx);
+    if (s) return s;
+    Mat m;
+    if ((s = check_matrix(ctx, X, &m))) return s;
+    if (!center || !scale || !beta || !r) return fail(ctx, BL_ERR_INVALID, "array arguments must be non-NULL");
+    if (set_len < 0 || set_len > m.p) return fail(ctx, BL_ERR_INVALID, "set_len out of range");
+    if (set_len > 0 && !set) return fail(ctx, BL_ERR_INVALID, "set is NULL");
+    if (!(std::isfinite(lambda) && lambda >= 0.0)) return fail(ctx, BL_ERR_INVALID, "lambda must be finite and >= 0");
+    if (!(tol > 0.0) || max_sweeps < 1) return fail(ctx, BL_ERR_INVALID, "tol must be > 0 and max_sweeps >= 1");
+    if (!cd_supported(m.n_total))
+        return fail(ctx, BL_ERR_UNSUPPORTED, "coordinate descent supports n_total <= 16384 (got %lld)",
+                    (long long)m.n_total);
+    int64_t n;
+    if ((s = rows_in_fit(ctx, m, &n))) return s;
+    if ((s = set_n_rows(ctx, n))) return s;
+    CdArgs ca{};
+    ca.set = set;
+    ca.len_dev = nullptr;
+    ca.len_host = set_len;
+    ca.c = center;
+    ca.s = scale;
+    ca.lam = lambda;
+    ca.beta = beta;
+    ca.r = r;
+    ca.tol = tol;
+    ca.max_sweeps = max_sweeps;
+    ca.sc = ctx->sc;
+    HIPCHK(launch_cd(m, ca, ctx->stream));
+    if ((s = read_scalars(ctx))) return s;
+    if (sweeps) *sweeps = ctx->sc_host->round.sweeps;
+    if (ctx->sc_host->round.status != 0)
+        return fail(ctx, BL_ERR_NOT_CONVERGED, "coordinate descent did not converge in %d sweeps", max_sweeps);
+    return BL_OK;
+}
+
+bl_status bl_kkt_check(bl_ctx ctx, const bl_matrix* X, const double* center, const double* scale, const double* r,
+                       double lambda, const int32_t* check_set, int64_t len, const uint8_t* exclude, double* z,
+                       int32_t* violators, int64_t* n_viol) {
+    bl_status s = check_ctx(ctx);
+    if (s) return s;
+    Mat m;
+    if ((s = check_matrix(ctx, X, &m))) return s;
+    if (!center || !scale || !r || !z || !violators) return fail(ctx, BL_ERR_INVALID, "array arguments must be non-NULL");
+    if (len < 0 || len > m.p) return fail(ctx, BL_ERR_INVALID, "len out of range");
+    if (len > 0 && !check_set) return fail(ctx, BL_ERR_INVALID, "check_set is NULL");
+    if (!(std::isfinite(lambda) && lambda >= 0.0)) return fail(ctx, BL_ERR_INVALID, "lambda must be finite and >= 0");
+    int64_t n;
+    if ((s = rows_in_fit(ctx, m, &n))) return s;
+    if ((s = set_n_rows(ctx, n))) return s;
+    uint8_t* mark;
+    void* scr;
+    int64_t* lens;
+    ENSURE(B_MARK, m.p, mark);
+    ENSURE(B_CMP, compact_scratch_bytes(m.p), scr);
+    ENSURE(B_LENS, 8 * sizeof(int64_t), lens);
+    HIPCHK(launch_fill_u8(mark, 0, m.p, ctx->stream));
+    HIPCHK(hipMemsetAsync(&ctx->sc->round, 0, sizeof(RoundInfo), ctx->stream));
+    HIPCHK(launch_sum_r(m, r, ctx->sc, false, ctx->stream));
+    if (len > 0) {
+        ScanArgs sa{};
+        sa.cols = check_set;
+        sa.len_host = len;
+        sa.r = r;
+        sa.sc = ctx->sc;
+        sa.c = center;
+        sa.s = scale;
+        sa.keep = nullptr;
+        sa.z = z;
+        sa.check = true;
+        sa.lam = lambda;
+        sa.in_s = nullptr;
+        sa.excl = exclude;
+        sa.mark = mark;
+        sa.nviol = &ctx->sc->round.n_viol;
+        HIPCHK(launch_scan(m, sa, ctx->stream));
+    }
+    HIPCHK(launch_compact(mark, m.p, violators, lens, scr, ctx->stream));
+    int64_t nv = 0;
+    HIPCHK(hipMemcpyAsync(&nv, lens, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (n_viol) *n_viol = nv;
+    return BL_OK;
+}
+
+bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_path_opts* opts,
+                      bl_path_result* res) {
+    auto t_start = std::chrono::steady_clock::now();
+    bl_status s = check_ctx(ctx);
+    if (s) return s;
+    Mat m;
+    if ((s = check_matrix(ctx, X, &m))) return s;
+    if (!y || !opts || !res) return fail(ctx, BL_ERR_INVALID, "y/opts/res must be non-NULL");
+    res->k_done = 0;
+    const int K = opts->nlambda;
+    if (K < 1) return fail(ctx, BL_ERR_INVALID, "nlambda must be >= 1");
+    if (!opts->lambda && !(opts->lambda_min_ratio > 0.0 && opts->lambda_min_ratio < 1.0) && K > 1)
+        return fail(ctx, BL_ERR_INVALID, "lambda_min_ratio must be in (0, 1)");
+    if (opts->lambda) {
+        for (int k = 0; k < K; ++k) {
+            if (!(std::isfinite(opts->lambda[k]) && opts->lambda[k] > 0.0))
+                return fail(ctx, BL_ERR_INVALID, "user lambda[%d] must be finite and > 0", k);
+            if (k > 0 && !(opts->lambda[k] <= opts->lambda[k - 1]))
+                return fail(ctx, BL_ERR_INVALID, "user lambda must be non-increasing");
+        }
+    }
+    if (opts->rule < BL_SCREEN_NONE || opts->rule > BL_SCREEN_SSR_BEDPP) return fail(ctx, BL_ERR_INVALID, "unknown rule");
+    if (!(opts->tol > 0.0) || opts->max_sweeps < 1 || opts->max_rounds < 1)
+        return fail(ctx, BL_ERR_INVALID, "tol > 0, max_sweeps >= 1 and max_rounds >= 1 are required");
+    if (!cd_supported(m.n_total))
+        return fail(ctx, BL_ERR_UNSUPPORTED, "coordinate descent supports n_total <= 16384 (got %lld)",
+                    (long long)m.n_total);
+    const bool bedpp = opts->rule == BL_SCREEN_BEDPP || opts->rule == BL_SCREEN_SSR_BEDPP;
+    const bool ssr = opts->rule == BL_SCREEN_SSR || opts->rule == BL_SCREEN_SSR_BEDPP;
+    const int64_t p = m.p, nt = m.n_total;
+    hipStream_t st = ctx->stream;
+
+    double *yt, *r, *xs, *a, *b, *z0, *z1, *beta, *c, *sc_, *pv;
+    uint8_t *s0, *s1, *strong, *keep;
+    int32_t *lT, *lE;
+    int64_t *lens, *pi;
+    LamStats* stats;
+    void* scr;
+    ENSURE(B_YT, nt * 8, yt);
+    ENSURE(B_R, nt * 8, r);
+    ENSURE(B_XS, nt * 8, xs);
+    ENSURE(B_A, p * 8, a);
+    ENSURE(B_B, p * 8, b);
+    ENSURE(B_Z0, p * 8, z0);
+    ENSURE(B_Z1, p * 8, z1);
+    ENSURE(B_BETA, p * 8, beta);
+    ENSURE(B_S0, p, s0);
+    ENSURE(B_S1, p, s1);
+    ENSURE(B_E, p, strong);
+    ENSURE(B_LT, p * 4, lT);
+    ENSURE(B_LE, p * 4, lE);
+    ENSURE(B_LENS, 8 * 8, lens);
+    ENSURE(B_STATS, (size_t)K * sizeof(LamStats), stats);
+    ENSURE(B_CMP, compact_scratch_bytes(p), scr);
+    ENSURE(B_ARGV, 256 * 8, pv);
+    ENSURE(B_ARGI, 256 * 8, pi);
+    if (res->center) c = res->center; else ENSURE(B_C, p * 8, c);
+    if (res->scale) sc_ = res->scale; else ENSURE(B_S, p * 8, sc_);
+    if (res->keep) keep = res->keep; else ENSURE(B_KEEP, p, keep);
+
+    // standardize, lambda_max, BEDPP inputs
+    int64_t n;
+    if ((s = rows_in_fit(ctx, m, &n))) return s;
+    if ((s = set_n_rows(ctx, n))) return s;
+    HIPCHK(launch_colstats(m, c, sc_, keep, n, st));
+    HIPCHK(launch_center_y(m, y, yt, r, ctx->sc, st));
+    HIPCHK(launch_sum_r(m, yt, ctx->sc, true, st));
+    ScanArgs sa{};
+    sa.len_host = p;
+    sa.r = yt;
+    sa.sc = ctx->sc;
+    sa.c = c;
+    sa.s = sc_;
+    sa.keep = keep;
+    sa.z = a;
+    HIPCHK(launch_scan(m, sa, st));
+    HIPCHK(launch_argmax_abs(a, keep, p, pv, pi, ctx->sc, st));
+    if ((s = read_scalars(ctx))) return s;
+    const double ybar = ctx->sc_host->y_mean, yy = ctx->sc_host->yy, lmax = ctx->sc_host->lmax;
+    const int64_t jstar = ctx->sc_host->jstar;
+    if (!std::isfinite(ybar) || !std::isfinite(yy)) return fail(ctx, BL_ERR_INVALID, "y has NaN or Inf");
+    if (jstar < 0) return fail(ctx, BL_ERR_INVALID, "no column is kept (all constant)");
+    if (!std::isfinite(lmax)) return fail(ctx, BL_ERR_INVALID, "X or y has NaN or Inf");
+    if (!(lmax > 0.0)) return fail(ctx, BL_ERR_INVALID, "lambda_max is 0 (y is constant on the fitted rows)");
+    const double v = yy / (double)n;
+    double sgn = 1.0;
+    {
+        HIPCHK(hipMemcpyAsync(&ctx->sc_host->rss, a + jstar, 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        sgn = ctx->sc_host->rss < 0 ? -1.0 : 1.0;
+    }
+    if (bedpp) {
+        HIPCHK(launch_std_column(m, jstar, c, sc_, xs, st));
+        HIPCHK(launch_sum_r(m, xs, ctx->sc, false, st));
+        sa.r = xs;
+        sa.z = b;
+        HIPCHK(launch_scan(m, sa, st));
+    }
+    std::vector<double> lam(K);
+    if (opts->lambda) {
+        for (int k = 0; k < K; ++k) lam[k] = opts->lambda[k];
+    } else {
+        for (int k = 0; k < K; ++k)
+            lam[k] = K == 1 ? lmax : lmax * std::pow(opts->lambda_min_ratio, (double)k / (double)(K - 1));
+    }
+    if (res->lambda)
+        for (int k = 0; k < K; ++k) res->lambda[k] = lam[k];
+    res->y_mean = ybar;
+    res->lambda_max = lmax;
+    res->jstar = jstar;
+
+    // k = 0: beta = 0 when lambda_0 >= lambda_max (the grid's first point); a user grid may start lower
+    HIPCHK(launch_fill_f64(beta, 0.0, p, st));
+    HIPCHK(launch_sum_r(m, r, ctx->sc, true, st));
+    // lens: [0] = |E|, [1],[2] = |S| slots, [3] = zero
+    HIPCHK(hipMemsetAsync(lens, 0, 8 * 8, st));
+    std::vector<int32_t> h_sweeps(K, 0), h_rounds(K, 0);
+    std::vector<int64_t> h_viol(K, 0);
+
+    uint8_t* safe_cur = s0;
+    uint8_t* safe_next = s1;
+    double* zprev = a;       // z at the previous lambda (a at lambda_max)
+    double* zcur = z0;
+    double* zspare = z1;
+    int64_t* len_cur = lens + 1;
+    int64_t* len_next = lens + 2;
+    bl_status final_status = BL_OK;
+
+    // S_0 and its size
+    HIPCHK(launch_bedpp(p, a, b, keep, bedpp, lmax, sgn, lam[0], bedpp_rhs(lmax, lam[0], v), safe_cur, st));
+    HIPCHK(launch_compact(safe_cur, p, lT, len_cur, scr, st));
+    int k_first = 0;
+    if (lam[0] >= lmax) {
+        HIPCHK(launch_record(nullptr, lens + 3, len_cur, lens + 3, beta, c, sc_, ctx->sc, lam[0], stats + 0, st));
+        if (res->beta) HIPCHK(hipMemcpyAsync(res->beta, beta, p * 8, hipMemcpyDeviceToDevice, st));
+        k_first = 1;
+    }
+    for (int k = k_first; k < K; ++k) {
+        const double lk = lam[k];
+        const double lprev = k > 0 ? lam[k - 1] : lmax;
+        // S_k (current) and S_{k+1} (scanned, feeds the strong rule at k+1)
+        HIPCHK(launch_bedpp(p, a, b, keep, bedpp, lmax, sgn, lk, bedpp_rhs(lmax, lk, v), safe_cur, st));
+        HIPCHK(launch_compact(safe_cur, p, lT, len_cur, scr, st));
+        uint8_t* scan_mask = safe_cur;
+        if (k + 1 < K) {
+            const double ln = lam[k + 1];
+            HIPCHK(launch_bedpp(p, a, b, keep, bedpp, lmax, sgn, ln, bedpp_rhs(lmax, ln, v), safe_next, st));
+            scan_mask = safe_next;
+        }
+        HIPCHK(launch_compact(scan_mask, p, lT, len_next, scr, st));
+        // working set E_k
+        HIPCHK(launch_ssr(p, safe_cur, nullptr, beta, zprev, ssr, 2.0 * lk - lprev, strong, st));
+        HIPCHK(launch_compact(strong, p, lE, lens + 0, scr, st));
+        int rounds = 0;
+        int64_t viol_total = 0;
+        int sweeps_total = 0;
+        for (;;) {
+            CdArgs ca{};
+            ca.set = lE;
+            ca.len_dev = lens + 0;
+            ca.c = c;
+            ca.s = sc_;
+            ca.lam = lk;
+            ca.beta = beta;
+            ca.r = r;
+            ca.tol = opts->tol;
+            ca.max_sweeps = opts->max_sweeps;
+            ca.sc = ctx->sc;
+            HIPCHK(launch_cd(m, ca, st));
+            HIPCHK(hipMemsetAsync(&ctx->sc->round.n_viol, 0, sizeof(uint32_t), st));
+            ScanArgs ka{};
+            ka.cols = lT;
+            ka.len_dev = len_next;
+            ka.r = r;
+            ka.sc = ctx->sc;
+            ka.c = c;
+            ka.s = sc_;
+            ka.keep = keep;
+            ka.z = zcur;
+            ka.check = ssr;
+            ka.lam = lk;
+            ka.in_s = safe_cur;
+            ka.excl = strong;
+            ka.mark = strong;
+            ka.nviol = &ctx->sc->round.n_viol;
+            HIPCHK(launch_scan(m, ka, st));
+            HIPCHK(hipMemcpyAsync(&ctx->sc_host->round, &ctx->sc->round, sizeof(RoundInfo), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            const RoundInfo ri = ctx->sc_host->round;
+            ++rounds;
+            sweeps_total += ri.sweeps;
+            viol_total += ri.n_viol;
+            if (ri.status != 0) {
+                final_status = fail(ctx, BL_ERR_NOT_CONVERGED, "CD did not converge at lambda index %d", k);
+                break;
+            }
+            if (ri.n_viol == 0) break;
+            if (rounds >= opts->max_rounds) {
+                final_status = fail(ctx, BL_ERR_NOT_CONVERGED, "check rounds exhausted at lambda index %d", k);
+                break;
+            }
+            HIPCHK(launch_compact(strong, p, lE, lens + 0, scr, st));
+        }
+        if (final_status != BL_OK) break;
+        h_sweeps[k] = sweeps_total;
+        h_rounds[k] = rounds;
+        h_viol[k] = viol_total;
+        HIPCHK(launch_record(lE, lens + 0, len_cur, len_next, beta, c, sc_, ctx->sc, lk, stats + k, st));
+        if (res->beta) HIPCHK(hipMemcpyAsync(res->beta + (size_t)k * p, beta, p * 8, hipMemcpyDeviceToDevice, st));
+        res->k_done = k + 1;
+        // the scan at lambda_k is the strong-rule input at lambda_{k+1}
+        zprev = zcur;
+        zcur = (zcur == z0) ? z1 : z0;
+        (void)zspare;
+    }
+    if (k_first == 1 && res->k_done < 1) res->k_done = 1;
+    // results
+    std::vector<LamStats> hs(K);
+    HIPCHK(hipMemcpyAsync(hs.data(), stats, (size_t)K * sizeof(LamStats), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int k = 0; k < res->k_done; ++k) {
+        if (res->intercept) res->intercept[k] = hs[k].intercept;
+        if (res->rss) res->rss[k] = hs[k].rss;
+        if (res->obj) res->obj[k] = hs[k].obj;
+        if (res->n_active) res->n_active[k] = hs[k].n_active;
+        if (res->sweeps) res->sweeps[k] = h_sweeps[k];
+        if (res->rounds) res->rounds[k] = h_rounds[k];
+        if (res->n_viol) res->n_viol[k] = h_viol[k];
+        if (res->n_scanned) res->n_scanned[k] = hs[k].n_scan * h_rounds[k];
+        if (res->n_safe) res->n_safe[k] = hs[k].n_safe;
+        if (res->n_strong) res->n_strong[k] = hs[k].n_strong;
+    }
+    res->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    return final_status;
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+// Internal interface between the path driver (api.cpp) and the HIP kernels (kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace blk {
+
+// Per-lambda statistics reduced on the device (one record per lambda).
+struct LamStats {
+    double rss;        // ||r||^2
+    double obj;        // Q(beta; lambda)
+    double intercept;  // y_mean - sum_j c_j beta_j / s_j
+    double l1;         // ||beta||_1
+    int64_t n_active;  // nonzero coefficients
+    int64_t n_strong;  // working-set size after the last round
+    int64_t n_safe;    // BEDPP survivors at this lambda
+    int64_t n_scan;    // columns in one check scan
+};
+
+// Outcome of one CD solve plus the following check, read back by the host in one copy.
+struct RoundInfo {
+    uint32_t n_viol;   // violators found by the check
+    int32_t sweeps;    // CD sweeps of the solve
+    int32_t status;    // 0 converged, 1 max_sweeps reached
+    int32_t pad;
+};
+
+// Scalars the kernels share through device memory.
+struct DevScalars {
+    double sum_r;      // sum of the residual over the rows (for the simplified scan)
+    double rss;        // ||r||^2 after the last CD solve
+    double y_mean;
+    double yy;         // ||y~||^2
+    double lmax;       // lambda_max
+    int64_t jstar;
+    int64_t n_rows;
+    RoundInfo round;
+};
+
+struct Mat {
+    const void* X;
+    int xtype;         // bl_xtype
+    int64_t n_total, p, ldx;
+    const uint8_t* mask;
+};
+
+int device_cu_count();
+
+// column statistics: center, scale, keep; n_rows written to *n_rows_dev (device) when not null
+hipError_t launch_colstats(const Mat& m, double* c, double* s, uint8_t* keep, int64_t n_rows, hipStream_t st);
+// rows in the fit
+hipError_t launch_count_rows(const Mat& m, int64_t* out_dev, hipStream_t st);
+// y_mean, y~ (0 outside the fit), ||y~||^2 -> sc->y_mean, sc->yy; also r = y~ when r != nullptr
+hipError_t launch_center_y(const Mat& m, const double* y, double* ytilde, double* r, DevScalars* sc, hipStream_t st);
+// sc->sum_r (and sc->rss when want_rss) of a row vector
+hipError_t launch_sum_r(const Mat& m, const double* r, DevScalars* sc, bool want_rss, hipStream_t st);
+// v_i = (x_{i,j} - c_j)/s_j on fitted rows, 0 elsewhere
+hipError_t launch_std_column(const Mat& m, int64_t j, const double* c, const double* s, double* v, hipStream_t st);
+
+// z_j = (x_j'r - c_j sum_r)/(n s_j) for j = cols[t], t < len (cols == nullptr: j = t).
+// len is read from len_dev when not null (device-side length), else len_host.
+// Epilogue when check is true: j is a violator if (in_s == null || in_s[j]) && excl[j] == 0 && |z_j| > lam;
+// violators get mark[j] = 1 and bump *nviol.  keep[j] == 0 gives z_j = 0 and is never a violator.
+struct ScanArgs {
+    const int32_t* cols;
+    const int64_t* len_dev;
+    int64_t len_host;
+    const double* r;
+    const DevScalars* sc;     // sum_r, n_rows
+    const double* c;
+    const double* s;
+    const uint8_t* keep;
+    double* z;
+    bool check;
+    double lam;
+    const uint8_t* in_s;
+    const uint8_t* excl;
+    uint8_t* mark;
+    uint32_t* nviol;
+};
+hipError_t launch_scan(const Mat& m, const ScanArgs& a, hipStream_t st);
+
+// argmax_j |a_j| over kept columns (ties -> smallest j) -> sc->lmax, sc->jstar
+hipError_t launch_argmax_abs(const double* a, const uint8_t* keep, int64_t p, double* part_v, int64_t* part_i,
+                             DevScalars* sc, hipStream_t st);
+
+// safe[j] = keep[j] && !BEDPP-discard(j)  (bedpp false: safe = keep); counts into *cnt (device, += )
+hipError_t launch_bedpp(int64_t p, const double* a, const double* b, const uint8_t* keep, bool bedpp, double lmax,
+                        double sgn, double lam, double rhs, uint8_t* safe, hipStream_t st);
+// strong[j] = safe[j] && (act(j) || (ssr && |zprev_j| >= thr)); act(j) = active ? active[j] : beta[j] != 0
+hipError_t launch_ssr(int64_t p, const uint8_t* safe, const uint8_t* active, const double* beta, const double* zprev,
+                      bool ssr, double thr, uint8_t* strong, hipStream_t st);
+
+// ordered compaction of a uint8 mask: out[0..len) = ascending j with mask[j] != 0; *len_dev = len
+size_t compact_scratch_bytes(int64_t p);
+hipError_t launch_compact(const uint8_t* mask, int64_t p, int32_t* out, int64_t* len_dev, void* scratch,
+                          hipStream_t st);
+
+// cyclic CD over set[0..len) (len from len_dev if not null); writes sc->round.{sweeps,status}, sc->sum_r, sc->rss
+struct CdArgs {
+    const int32_t* set;
+    const int64_t* len_dev;
+    int64_t len_host;
+    const double* c;
+    const double* s;
+    double lam;
+    double* beta;
+    double* r;
+    double tol;
+    int max_sweeps;
+    DevScalars* sc;
+};
+bool cd_supported(int64_t n_total);
+hipError_t launch_cd(const Mat& m, const CdArgs& a, hipStream_t st);
+
+// per-lambda record: stats over the set (beta nonzero only there) into *out
+hipError_t launch_record(const int32_t* set, const int64_t* len_dev, const int64_t* len_safe, const int64_t* len_scan,
+                         const double* beta, const double* c, const double* s, const DevScalars* sc, double lam,
+                         LamStats* out, hipStream_t st);
+
+hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t st);
+hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t st);
+hipError_t launch_or_u8(uint8_t* dst, const uint8_t* src, int64_t n, hipStream_t st);
+
+}  // namespace blk
