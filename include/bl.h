@@ -209,6 +209,31 @@ typedef struct {
 bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_path_opts* opts,
                       bl_path_result* res);
 
+/*
+ * Kernel timing (diagnostics for measurement).  When enabled, bl_fit_path records HIP
+ * events on the context stream around each launch of the scan, the CD solve and the
+ * column statistics, and accumulates per kernel: launches, summed duration and the
+ * algorithmic bytes those launches had to read:
+ *   scan      columns scanned x n_total x sizeof(element)   (+ the residual once per launch)
+ *   CD        covariance solve: sweeps x m^2 x 8 (the Gram of the working set, m features, per sweep);
+ *             residual solve (working sets above the covariance limit): sweeps x m x n_total x sizeof(element)
+ *   colstats  p x n_total x sizeof(element)
+ *   gram      Gram entries of new pool members and the gather of the working set's Gram
+ *   rupdate   residual update after a solve: m x n_total x sizeof(element)
+ * bl_profile(ctx, 1) enables and resets the counters, bl_profile(ctx, 0) disables.
+ */
+typedef struct {
+    int64_t launches;
+    double total_ms;
+    double bytes;
+} bl_kernel_profile;
+
+enum { BL_PROF_SCAN = 0, BL_PROF_CD = 1, BL_PROF_COLSTATS = 2, BL_PROF_GRAM = 3, BL_PROF_RUPDATE = 4,
+       BL_PROF_COUNT = 5 };
+
+bl_status bl_profile(bl_ctx ctx, int enable);
+bl_status bl_profile_get(bl_ctx ctx, int kernel, bl_kernel_profile* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -39,6 +39,8 @@ def _load():
             build()
         L = ctypes.CDLL(_LIB_PATH)
         i64, dbl, vp, i32 = ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_int
+        L.or_num_threads.argtypes = []
+        L.or_num_threads.restype = i32
         L.or_standardize.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp]
         L.or_standardize.restype = i64
         L.or_zscan.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp, vp, vp]
@@ -90,6 +92,10 @@ def _mask(mask, n_total):
     m = np.ascontiguousarray(mask, dtype=np.uint8)
     assert m.shape == (n_total,)
     return m
+
+
+def num_threads() -> int:
+    return int(_load().or_num_threads())
 
 
 def standardize(Xt, mask=None):

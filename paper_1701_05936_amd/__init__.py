@@ -29,7 +29,9 @@ _STATUS_NAMES = {0: "BL_OK", 1: "BL_ERR_INVALID", 2: "BL_ERR_NOMEM", 3: "BL_ERR_
 
 # exported C symbols (kept in step with include/bl.h)
 EXPORTS = ("bl_create", "bl_destroy", "bl_last_error", "bl_device_info", "bl_standardize", "bl_lambda_max",
-           "bl_bedpp_setup", "bl_screen", "bl_cd_solve", "bl_kkt_check", "bl_fit_path")
+           "bl_bedpp_setup", "bl_screen", "bl_cd_solve", "bl_kkt_check", "bl_fit_path", "bl_profile",
+           "bl_profile_get")
+PROF_SCAN, PROF_CD, PROF_COLSTATS, PROF_GRAM, PROF_RUPDATE = 0, 1, 2, 3, 4
 
 
 class BLError(RuntimeError):
@@ -47,6 +49,10 @@ class _ScreenState(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int64), ("rule", ctypes.c_int32), ("a", ctypes.c_void_p), ("b", ctypes.c_void_p),
                 ("keep", ctypes.c_void_p), ("active", ctypes.c_void_p), ("lambda_max", ctypes.c_double),
                 ("sign_star", ctypes.c_double), ("v", ctypes.c_double)]
+
+
+class _KernelProfile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
 class _PathOpts(ctypes.Structure):
@@ -91,6 +97,8 @@ def load_library(path: str = LIB_PATH):
     L.bl_cd_solve.argtypes = [vp, P(_Matrix), vp, vp, dbl, vp, i64, vp, vp, dbl, i32, P(i32)]
     L.bl_kkt_check.argtypes = [vp, P(_Matrix), vp, vp, vp, dbl, vp, i64, vp, vp, vp, P(i64)]
     L.bl_fit_path.argtypes = [vp, P(_Matrix), vp, P(_PathOpts), P(_PathResult)]
+    L.bl_profile.argtypes = [vp, ctypes.c_int]
+    L.bl_profile_get.argtypes = [vp, ctypes.c_int, P(_KernelProfile)]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("bl_destroy", "bl_last_error"):
@@ -167,6 +175,15 @@ class Context:
     @property
     def handle(self):
         return self._h
+
+    def profile(self, enable: bool = True):
+        """Enable (and reset) or disable per-kernel event timing inside bl_fit_path."""
+        self._check(load_library().bl_profile(self._h, 1 if enable else 0))
+
+    def profile_get(self, kernel: int) -> dict:
+        kp = _KernelProfile()
+        self._check(load_library().bl_profile_get(self._h, kernel, ctypes.byref(kp)))
+        return {"launches": kp.launches, "total_ms": kp.total_ms, "bytes": kp.bytes}
 
     def device_info(self):
         n = ctypes.c_int()

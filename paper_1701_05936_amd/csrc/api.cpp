@@ -32,13 +32,23 @@ struct bl_ctx_s {
     DevScalars* sc = nullptr;      // device
     DevScalars* sc_host = nullptr; // pinned host mirror
     std::vector<DevBuf> bufs;
+    // Gram pool of the covariance solve (features that have been in a working set)
+    int64_t pool_size = 0;
+    int64_t pool_cap = 0;
+    double* gpool = nullptr;
+    // kernel timing
+    bool prof = false;
+    hipEvent_t ev[10] = {};
+    double pend_gram_bytes = 0.0, pend_ru_bytes = 0.0;  // bytes of the last solve, for the timing harvest
+    bl_kernel_profile kp[BL_PROF_COUNT] = {};
 };
 
 namespace {
 
 enum BufId {
     B_CMP = 0, B_ARGV, B_ARGI, B_YT, B_R, B_XS, B_A, B_B, B_Z0, B_Z1, B_S0, B_S1, B_E, B_LT, B_LE, B_LENS,
-    B_BETA, B_STATS, B_C, B_S, B_KEEP, B_MARK, B_COUNT
+    B_BETA, B_STATS, B_C, B_S, B_KEEP, B_MARK, B_POOLPOS, B_POOLLIST, B_GE, B_G0, B_B0, B_B1, B_RUPART, B_ZS,
+    B_DELTA, B_SYNC, B_COUNT
 };
 
 bl_status fail(bl_ctx c, bl_status st, const char* fmt, ...) {
@@ -137,6 +147,157 @@ bl_status read_scalars(bl_ctx ctx) {
     return BL_OK;
 }
 
+// kernel timing: record an event pair around a launch when profiling is on
+void prof_mark(bl_ctx ctx, int slot) {
+    if (ctx->prof) (void)hipEventRecord(ctx->ev[slot], ctx->stream);
+}
+// after the stream has been synchronized: add the pair (slot, slot+1) to kernel `which`
+void prof_add(bl_ctx ctx, int slot, int which, double bytes) {
+    if (!ctx->prof) return;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev[slot], ctx->ev[slot + 1]) == hipSuccess) {
+        ctx->kp[which].launches += 1;
+        ctx->kp[which].total_ms += ms;
+        ctx->kp[which].bytes += bytes;
+    }
+}
+
+// ---- Gram pool -------------------------------------------------------------------------------------
+bl_status pool_reset(bl_ctx ctx, int64_t p) {
+    int32_t *pos, *list;
+    ENSURE(B_POOLPOS, p * 4, pos);
+    ENSURE(B_POOLLIST, p * 4, list);
+    HIPCHK(launch_fill_u8((uint8_t*)pos, 0xff, p * 4, ctx->stream));  // every slot = -1
+    ctx->pool_size = 0;
+    return BL_OK;
+}
+
+bl_status pool_reserve(bl_ctx ctx, int64_t need) {
+    if (need <= ctx->pool_cap) return BL_OK;
+    int64_t cap = ctx->pool_cap * 2;
+    if (cap < need) cap = need;
+    if (cap < 1024) cap = 1024;
+    cap = (cap + 63) / 64 * 64;
+    double* g = nullptr;
+    if (hipMalloc(&g, (size_t)cap * cap * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, BL_ERR_NOMEM, "Gram pool of %lld features does not fit", (long long)cap);
+    }
+    if (ctx->gpool && ctx->pool_size > 0)
+        HIPCHK(hipMemcpy2DAsync(g, cap * sizeof(double), ctx->gpool, ctx->pool_cap * sizeof(double),
+                                ctx->pool_size * sizeof(double), ctx->pool_size, hipMemcpyDeviceToDevice,
+                                ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (ctx->gpool) (void)hipFree(ctx->gpool);
+    ctx->gpool = g;
+    ctx->pool_cap = cap;
+    return BL_OK;
+}
+
+// Cyclic CD at lambda over set[0..m) (length also at *len_dev), warm-started from beta and r.
+// z[j] must hold x~_j' r / n at the current r for every j of the set.  Updates beta, r,
+// sc->sum_r, sc->rss and sc->round.{sweeps, status, cd_len}.
+bl_status solve_set(bl_ctx ctx, const Mat& mt, const int32_t* set, const int64_t* len_dev, int64_t m,
+                    const double* z, double* beta, double* r, const double* c, const double* s, double n_rows,
+                    double lam, double tol, int max_sweeps) {
+    hipStream_t st = ctx->stream;
+    const double es = (double)elem_bytes(mt.xtype);
+    if (m > GCD_MAX) {
+        if (!cd_supported(mt.n_total))
+            return fail(ctx, BL_ERR_UNSUPPORTED, "working set of %lld features with n_total %lld is too large",
+                        (long long)m, (long long)mt.n_total);
+        CdArgs ca{};
+        ca.set = set;
+        ca.len_host = m;
+        ca.c = c;
+        ca.s = s;
+        ca.lam = lam;
+        ca.beta = beta;
+        ca.r = r;
+        ca.tol = tol;
+        ca.max_sweeps = max_sweeps;
+        ca.sc = ctx->sc;
+        prof_mark(ctx, 0);
+        HIPCHK(launch_cd(mt, ca, st));
+        prof_mark(ctx, 1);
+        return BL_OK;
+    }
+    int32_t *pos, *list;
+    double *GE, *g0, *b0, *b1, *part;
+    ENSURE(B_POOLPOS, mt.p * 4, pos);
+    ENSURE(B_POOLLIST, mt.p * 4, list);
+    ENSURE(B_GE, (size_t)(m > 0 ? m : 1) * (m > 0 ? m : 1) * 8, GE);
+    ENSURE(B_G0, (m + 1) * 8, g0);
+    ENSURE(B_B0, (m + 1) * 8, b0);
+    ENSURE(B_B1, (m + 1) * 8, b1);
+    ENSURE(B_RUPART, r_update_scratch_bytes(mt.n_total, m), part);
+    prof_mark(ctx, 4);
+    HIPCHK(launch_pool_add(set, len_dev, m, pos, list, ctx->pool_size, &ctx->sc->n_new, st));
+    HIPCHK(hipMemcpyAsync(&ctx->sc_host->n_new, &ctx->sc->n_new, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const int64_t n_new = ctx->sc_host->n_new;
+    bl_status s_;
+    if ((s_ = pool_reserve(ctx, ctx->pool_size + n_new))) return s_;
+    HIPCHK(launch_gram_update(mt, list, ctx->pool_size + n_new, ctx->pool_size, n_new, c, s, n_rows, ctx->gpool,
+                              ctx->pool_cap, st));
+    const double gram_bytes = (double)(ctx->pool_size + 2 * n_new) * mt.n_total * es + (double)m * m * 8.0;
+    ctx->pool_size += n_new;
+    HIPCHK(launch_gather_gram(set, m, pos, ctx->gpool, ctx->pool_cap, GE, st));
+    HIPCHK(launch_gather_start(set, m, z, beta, g0, b0, st));
+    prof_mark(ctx, 5);
+    const int H = gcd_multi_helpers(m);
+    if (H > 0) {
+        // leader + helper workgroups; g0 holds the working gradient, b1 the working coefficients
+        double* dl;
+        uint32_t* sy;
+        const size_t words = gcd_multi_sync_words(H);
+        ENSURE(B_DELTA, (size_t)2 * (m + 64) * 8, dl);
+        ENSURE(B_SYNC, words * 4, sy);
+        HIPCHK(launch_copy_f64(b0, b1, m, st));
+        HIPCHK(hipMemsetAsync(sy, 0, words * 4, st));
+        GcdMultiArgs ma{};
+        ma.G = GE;
+        ma.m = m;
+        ma.g = g0;
+        ma.b = b1;
+        ma.delta = dl;
+        ma.sync = sy;
+        ma.H = H;
+        ma.spin_limit = 2000000u;  // about two seconds of polling per wait
+        ma.lam = lam;
+        ma.tol = tol;
+        ma.max_sweeps = max_sweeps;
+        ma.sc = ctx->sc;
+        prof_mark(ctx, 0);
+        HIPCHK(launch_gcd_multi(ma, st));
+        prof_mark(ctx, 1);
+        HIPCHK(launch_scatter_beta(set, m, b1, beta, st));
+    } else {
+        GcdArgs ga{};
+        ga.G = GE;
+        ga.m = m;
+        ga.g0 = g0;
+        ga.b0 = b0;
+        ga.b1 = b1;
+        ga.set = set;
+        ga.beta = beta;
+        ga.lam = lam;
+        ga.tol = tol;
+        ga.max_sweeps = max_sweeps;
+        ga.sc = ctx->sc;
+        prof_mark(ctx, 0);
+        HIPCHK(launch_gcd(ga, st));
+        prof_mark(ctx, 1);
+    }
+    prof_mark(ctx, 6);
+    HIPCHK(launch_r_update(mt, set, m, b0, b1, c, s, part, r, st));
+    HIPCHK(launch_sum_r(mt, r, ctx->sc, true, st));
+    prof_mark(ctx, 7);
+    ctx->pend_gram_bytes = gram_bytes;
+    ctx->pend_ru_bytes = (double)m * mt.n_total * es;
+    return BL_OK;
+}
+
 double bedpp_rhs(double lmax, double lam, double v) {
     double slack = v - lmax * lmax;
     if (slack < 0.0) slack = 0.0;
@@ -176,12 +337,34 @@ void bl_destroy(bl_ctx c) {
     else (void)hipDeviceSynchronize();
     for (auto& b : c->bufs)
         if (b.p) (void)hipFree(b.p);
+    for (auto& e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (c->gpool) (void)hipFree(c->gpool);
     if (c->sc) (void)hipFree(c->sc);
     if (c->sc_host) (void)hipHostFree(c->sc_host);
     delete c;
 }
 
 const char* bl_last_error(bl_ctx c) { return c ? c->err.c_str() : "null context"; }
+
+bl_status bl_profile(bl_ctx ctx, int enable) {
+    bl_status s = check_ctx(ctx);
+    if (s) return s;
+    if (enable) {
+        for (auto& e : ctx->ev)
+            if (!e) HIPCHK(hipEventCreate(&e));
+    }
+    ctx->prof = enable != 0;
+    for (auto& k : ctx->kp) k = bl_kernel_profile{0, 0.0, 0.0};
+    return BL_OK;
+}
+
+bl_status bl_profile_get(bl_ctx ctx, int kernel, bl_kernel_profile* out) {
+    if (!ctx) return BL_ERR_INVALID;
+    if (kernel < 0 || kernel >= BL_PROF_COUNT || !out) return fail(ctx, BL_ERR_INVALID, "bad kernel id or NULL out");
+    *out = ctx->kp[kernel];
+    return BL_OK;
+}
 
 bl_status bl_device_info(bl_ctx ctx, int* n_cu, char* name, int name_len) {
     bl_status s = check_ctx(ctx);
@@ -331,27 +514,31 @@ bl_status bl_cd_solve(bl_ctx ctx, const bl_matrix* X, const double* center, cons
     if (set_len > 0 && !set) return fail(ctx, BL_ERR_INVALID, "set is NULL");
     if (!(std::isfinite(lambda) && lambda >= 0.0)) return fail(ctx, BL_ERR_INVALID, "lambda must be finite and >= 0");
     if (!(tol > 0.0) || max_sweeps < 1) return fail(ctx, BL_ERR_INVALID, "tol must be > 0 and max_sweeps >= 1");
-    if (!cd_supported(m.n_total))
-        return fail(ctx, BL_ERR_UNSUPPORTED, "coordinate descent supports n_total <= 16384 (got %lld)",
-                    (long long)m.n_total);
     int64_t n;
     if ((s = rows_in_fit(ctx, m, &n))) return s;
     if ((s = set_n_rows(ctx, n))) return s;
-    CdArgs ca{};
-    ca.set = set;
-    ca.len_dev = nullptr;
-    ca.len_host = set_len;
-    ca.c = center;
-    ca.s = scale;
-    ca.lam = lambda;
-    ca.beta = beta;
-    ca.r = r;
-    ca.tol = tol;
-    ca.max_sweeps = max_sweeps;
-    ca.sc = ctx->sc;
-    HIPCHK(launch_cd(m, ca, ctx->stream));
+    double* zs;
+    ENSURE(B_ZS, m.p * 8, zs);
+    HIPCHK(launch_sum_r(m, r, ctx->sc, false, ctx->stream));
+    if (set_len > 0) {
+        ScanArgs sa{};
+        sa.cols = set;
+        sa.len_host = set_len;
+        sa.r = r;
+        sa.sc = ctx->sc;
+        sa.c = center;
+        sa.s = scale;
+        sa.z = zs;
+        HIPCHK(launch_scan(m, sa, ctx->stream));
+    }
+    if ((s = pool_reset(ctx, m.p))) return s;
+    if ((s = solve_set(ctx, m, set, nullptr, set_len, zs, beta, r, center, scale, (double)n, lambda, tol,
+                       max_sweeps)))
+        return s;
     if ((s = read_scalars(ctx))) return s;
     if (sweeps) *sweeps = ctx->sc_host->round.sweeps;
+    if (ctx->sc_host->round.status == 2)
+        return fail(ctx, BL_ERR_DEVICE, "coordinate descent workgroups timed out waiting for each other");
     if (ctx->sc_host->round.status != 0)
         return fail(ctx, BL_ERR_NOT_CONVERGED, "coordinate descent did not converge in %d sweeps", max_sweeps);
     return BL_OK;
@@ -430,9 +617,6 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
     if (opts->rule < BL_SCREEN_NONE || opts->rule > BL_SCREEN_SSR_BEDPP) return fail(ctx, BL_ERR_INVALID, "unknown rule");
     if (!(opts->tol > 0.0) || opts->max_sweeps < 1 || opts->max_rounds < 1)
         return fail(ctx, BL_ERR_INVALID, "tol > 0, max_sweeps >= 1 and max_rounds >= 1 are required");
-    if (!cd_supported(m.n_total))
-        return fail(ctx, BL_ERR_UNSUPPORTED, "coordinate descent supports n_total <= 16384 (got %lld)",
-                    (long long)m.n_total);
     const bool bedpp = opts->rule == BL_SCREEN_BEDPP || opts->rule == BL_SCREEN_SSR_BEDPP;
     const bool ssr = opts->rule == BL_SCREEN_SSR || opts->rule == BL_SCREEN_SSR_BEDPP;
     const int64_t p = m.p, nt = m.n_total;
@@ -466,11 +650,16 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
     if (res->scale) sc_ = res->scale; else ENSURE(B_S, p * 8, sc_);
     if (res->keep) keep = res->keep; else ENSURE(B_KEEP, p, keep);
 
+    if ((s = pool_reset(ctx, p))) return s;
     // standardize, lambda_max, BEDPP inputs
     int64_t n;
     if ((s = rows_in_fit(ctx, m, &n))) return s;
     if ((s = set_n_rows(ctx, n))) return s;
+    const double es = (double)elem_bytes(m.xtype);
+    const double col_bytes = (double)nt * es;
+    prof_mark(ctx, 0);
     HIPCHK(launch_colstats(m, c, sc_, keep, n, st));
+    prof_mark(ctx, 1);
     HIPCHK(launch_center_y(m, y, yt, r, ctx->sc, st));
     HIPCHK(launch_sum_r(m, yt, ctx->sc, true, st));
     ScanArgs sa{};
@@ -481,9 +670,13 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
     sa.s = sc_;
     sa.keep = keep;
     sa.z = a;
+    prof_mark(ctx, 2);
     HIPCHK(launch_scan(m, sa, st));
+    prof_mark(ctx, 3);
     HIPCHK(launch_argmax_abs(a, keep, p, pv, pi, ctx->sc, st));
     if ((s = read_scalars(ctx))) return s;
+    prof_add(ctx, 0, BL_PROF_COLSTATS, (double)p * col_bytes);
+    prof_add(ctx, 2, BL_PROF_SCAN, (double)p * col_bytes + nt * 8.0);
     const double ybar = ctx->sc_host->y_mean, yy = ctx->sc_host->yy, lmax = ctx->sc_host->lmax;
     const int64_t jstar = ctx->sc_host->jstar;
     if (!std::isfinite(ybar) || !std::isfinite(yy)) return fail(ctx, BL_ERR_INVALID, "y has NaN or Inf");
@@ -502,7 +695,11 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         HIPCHK(launch_sum_r(m, xs, ctx->sc, false, st));
         sa.r = xs;
         sa.z = b;
+        prof_mark(ctx, 2);
         HIPCHK(launch_scan(m, sa, st));
+        prof_mark(ctx, 3);
+        HIPCHK(hipStreamSynchronize(st));
+        prof_add(ctx, 2, BL_PROF_SCAN, (double)p * col_bytes + nt * 8.0);
     }
     std::vector<double> lam(K);
     if (opts->lambda) {
@@ -563,18 +760,12 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         int64_t viol_total = 0;
         int sweeps_total = 0;
         for (;;) {
-            CdArgs ca{};
-            ca.set = lE;
-            ca.len_dev = lens + 0;
-            ca.c = c;
-            ca.s = sc_;
-            ca.lam = lk;
-            ca.beta = beta;
-            ca.r = r;
-            ca.tol = opts->tol;
-            ca.max_sweeps = opts->max_sweeps;
-            ca.sc = ctx->sc;
-            HIPCHK(launch_cd(m, ca, st));
+            HIPCHK(hipMemcpyAsync(&ctx->sc_host->n_new, lens + 0, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            const int64_t m_len = ctx->sc_host->n_new;
+            if ((s = solve_set(ctx, m, lE, lens + 0, m_len, rounds == 0 ? zprev : zcur, beta, r, c, sc_, (double)n,
+                               lk, opts->tol, opts->max_sweeps)))
+                return s;
             HIPCHK(hipMemsetAsync(&ctx->sc->round.n_viol, 0, sizeof(uint32_t), st));
             ScanArgs ka{};
             ka.cols = lT;
@@ -591,13 +782,28 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
             ka.excl = strong;
             ka.mark = strong;
             ka.nviol = &ctx->sc->round.n_viol;
+            ka.len_out = &ctx->sc->round.scan_len;
+            prof_mark(ctx, 2);
             HIPCHK(launch_scan(m, ka, st));
+            prof_mark(ctx, 3);
             HIPCHK(hipMemcpyAsync(&ctx->sc_host->round, &ctx->sc->round, sizeof(RoundInfo), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             const RoundInfo ri = ctx->sc_host->round;
+            if (m_len > GCD_MAX) {
+                prof_add(ctx, 0, BL_PROF_CD, (double)ri.sweeps * ri.cd_len * col_bytes);
+            } else {
+                prof_add(ctx, 0, BL_PROF_CD, (double)ri.sweeps * (double)m_len * (double)m_len * 8.0);
+                prof_add(ctx, 4, BL_PROF_GRAM, ctx->pend_gram_bytes);
+                prof_add(ctx, 6, BL_PROF_RUPDATE, ctx->pend_ru_bytes);
+            }
+            prof_add(ctx, 2, BL_PROF_SCAN, (double)ri.scan_len * col_bytes + nt * 8.0);
             ++rounds;
             sweeps_total += ri.sweeps;
             viol_total += ri.n_viol;
+            if (ri.status == 2) {
+                final_status = fail(ctx, BL_ERR_DEVICE, "CD workgroups timed out waiting for each other at lambda index %d", k);
+                break;
+            }
             if (ri.status != 0) {
                 final_status = fail(ctx, BL_ERR_NOT_CONVERGED, "CD did not converge at lambda index %d", k);
                 break;

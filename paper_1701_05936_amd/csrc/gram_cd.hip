@@ -1,0 +1,789 @@
+// Coordinate descent with covariance updates on the working set.
+//
+// For the working set E (m features, ascending) the solve keeps the gradient
+// g_e = x~_{E[e]}' r / n instead of the residual.  A coordinate step
+//   u = g_e + beta_e,  beta_e' = S(u, lambda),  d = beta_e' - beta_e,
+//   g_k -= d * G[k, e]  for every k in E,   G = X~_E' X~_E / n,
+// is the same cyclic coordinate descent as the residual form (the same
+// iterates up to rounding), but a step touches m numbers instead of n.
+//
+// G comes from a Gram "pool": every feature that has ever been in a working
+// set along the path keeps its row of Gram entries, computed once with the
+// simplified identity  x~_j' x~_k = (sum_i x_ij x_ik - n c_j c_k)/(s_j s_k)
+// (type (1) of the paper's Section 3.1.1).  New members of E get their
+// entries against the whole pool by a tiled FP64 GEMM; G_E is then gathered.
+//
+// The sequential part runs in blocks of GCD_B coordinates: one wavefront
+// carries the chain of a block with the block's own Gram entries in LDS
+// (lane l holds g of coordinate b0+l; each step broadcasts g_t, computes d,
+// updates every lane).  Then the whole workgroup pushes the block's changes
+// into the gradient of every other coordinate.  After the solve the residual
+// is brought up to date in one pass, r -= X~_E (beta_E - beta_E(start)).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace blk {
+
+namespace {
+
+constexpr int WAVE = 64;
+
+__device__ __forceinline__ double soft_threshold(double u, double l) {
+    return u > l ? u - l : (u < -l ? u + l : 0.0);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    uint64_t b = __builtin_bit_cast(uint64_t, v);
+    uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, lane);
+    uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+template <typename XT>
+__device__ __forceinline__ double ld_x(const XT* p) { return (double)*p; }
+
+// ---- pool membership ---------------------------------------------------------------------------------
+// Features of set[0..len) without a pool slot get slots pool_size, pool_size+1, ... in set order.
+__global__ __launch_bounds__(1024) void k_pool_add(const int32_t* __restrict__ set, const int64_t* __restrict__ len_dev,
+                                                   int64_t len_host, int32_t* __restrict__ pool_pos,
+                                                   int32_t* __restrict__ pool_list, int64_t pool_size,
+                                                   int64_t* __restrict__ n_new_out) {
+    __shared__ int32_t sh[1024];
+    __shared__ int64_t carry;
+    const int64_t len = len_dev ? *len_dev : len_host;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < len; b0 += blockDim.x) {
+        const int64_t t = b0 + threadIdx.x;
+        int32_t j = -1;
+        int flag = 0;
+        if (t < len) {
+            j = set[t];
+            flag = pool_pos[j] < 0 ? 1 : 0;
+        }
+        sh[threadIdx.x] = flag;
+        __syncthreads();
+        for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+            int add = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (flag) {
+            const int64_t pos = pool_size + carry + sh[threadIdx.x] - 1;
+            pool_pos[j] = (int32_t)pos;
+            pool_list[pos] = j;
+        }
+        __syncthreads();
+        if (threadIdx.x == blockDim.x - 1) carry += sh[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *n_new_out = carry;
+}
+
+// ---- Gram entries of new pool members ----------------------------------------------------------------
+// C[k, t] = x~_{pool[k]}' x~_{pool[P0 + t]} / n for k < P, t < N, written to G[k, P0+t] and G[P0+t, k].
+constexpr int GT_K = 64;   // pool columns per tile
+constexpr int GT_N = 32;   // new columns per tile
+constexpr int GT_R = 32;   // rows per LDS chunk
+
+template <typename XT, bool MASK>
+__global__ __launch_bounds__(256) void k_gram_update(const XT* __restrict__ X, int64_t ldx, int64_t n_total,
+                                                     const uint8_t* __restrict__ mask,
+                                                     const int32_t* __restrict__ pool_list, int64_t P, int64_t P0,
+                                                     int64_t N, const double* __restrict__ c,
+                                                     const double* __restrict__ s, double n_rows,
+                                                     double* __restrict__ G, int64_t ldg) {
+    __shared__ double As[GT_R][GT_K + 1];
+    __shared__ double Bs[GT_R][GT_N + 1];
+    const int tid = threadIdx.x;
+    const int64_t k0 = (int64_t)blockIdx.x * GT_K, t0 = (int64_t)blockIdx.y * GT_N;
+    const int tx = tid % 16, ty = tid / 16;  // thread computes k = k0 + tx + 16*a (a < 4), t = t0 + ty + 16*b (b < 2)
+    double acc[4][2] = {};
+    // loaders: A chunk GT_R x GT_K -> 8 elements per thread; B chunk GT_R x GT_N -> 4 per thread
+    const int a_col = tid / 4, a_row = (tid % 4) * 8;
+    const int b_col = tid / 8, b_row = (tid % 8) * 4;
+    const XT* acol = (k0 + a_col < P) ? X + (int64_t)pool_list[k0 + a_col] * ldx : nullptr;
+    const XT* bcol = (t0 + b_col < N) ? X + (int64_t)pool_list[P0 + t0 + b_col] * ldx : nullptr;
+    for (int64_t i0 = 0; i0 < n_total; i0 += GT_R) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t i = i0 + a_row + q;
+            As[a_row + q][a_col] = (acol && i < n_total) ? ld_x(acol + i) : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = i0 + b_row + q;
+            double v = (bcol && i < n_total) ? ld_x(bcol + i) : 0.0;
+            if (MASK && i < n_total && !mask[i]) v = 0.0;
+            Bs[b_row + q][b_col] = v;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int rr = 0; rr < GT_R; ++rr) {
+            double av[4], bv[2];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) av[q] = As[rr][tx + 16 * q];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) bv[q] = Bs[rr][ty + 16 * q];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int w = 0; w < 2; ++w) acc[q][w] = fma(av[q], bv[w], acc[q][w]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t k = k0 + tx + 16 * q;
+        if (k >= P) continue;
+        const int jk = pool_list[k];
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            const int64_t t = t0 + ty + 16 * w;
+            if (t >= N) continue;
+            const int jt = pool_list[P0 + t];
+            // symmetric in (jk, jt): two tiles write each new-by-new entry and must agree bitwise
+            const double gv = (acc[q][w] - n_rows * (c[jk] * c[jt])) / (n_rows * (s[jk] * s[jt]));
+            G[k * ldg + (P0 + t)] = gv;
+            G[(P0 + t) * ldg + k] = gv;
+        }
+    }
+}
+
+// G_E[e, f] = G_pool[pos(set[e]), pos(set[f])] (symmetric, m x m)
+__global__ void k_gather_gram(const int32_t* __restrict__ set, int64_t m, const int32_t* __restrict__ pool_pos,
+                              const double* __restrict__ Gp, int64_t ldg, double* __restrict__ GE) {
+    const int64_t total = m * m;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = idx / m, f = idx - e * m;
+        GE[idx] = Gp[(int64_t)pool_pos[set[e]] * ldg + pool_pos[set[f]]];
+    }
+}
+
+// gradient and coefficients of the set at the start of a solve
+__global__ void k_gather_start(const int32_t* __restrict__ set, int64_t m, const double* __restrict__ z,
+                               const double* __restrict__ beta, double* __restrict__ g0,
+                               double* __restrict__ b0) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        const int j = set[e];
+        g0[e] = z[j];
+        b0[e] = beta[j];
+    }
+}
+
+// ---- the solve -----------------------------------------------------------------------------------------
+constexpr int GCD_THREADS = 1024;
+
+__global__ __launch_bounds__(GCD_THREADS) void k_gcd(GcdArgs a) {
+    __shared__ double g[GCD_MAX];
+    __shared__ double bE[GCD_MAX];
+    __shared__ double Gbb[GCD_B * GCD_B];
+    __shared__ double dlt[GCD_B];
+    __shared__ int nz[GCD_B];
+    __shared__ int nnz_sh;
+    __shared__ double maxd_sh;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+    const int64_t m = a.m;
+    const double lam = a.lam;
+    const double* __restrict__ G = a.G;
+    for (int64_t e = tid; e < m; e += GCD_THREADS) {
+        g[e] = a.g0[e];
+        bE[e] = a.b0[e];
+    }
+    int sweeps = 0, status = 0;
+    if (tid == 0) maxd_sh = 0.0;
+    __syncthreads();
+    if (m > 0) {
+        for (;;) {
+            for (int64_t b0 = 0; b0 < m; b0 += GCD_B) {
+                const int bl = (int)((m - b0) < GCD_B ? (m - b0) : GCD_B);
+                for (int idx = tid; idx < GCD_B * GCD_B; idx += GCD_THREADS) {
+                    const int t = idx / GCD_B, l = idx % GCD_B;
+                    Gbb[idx] = (t < bl && l < bl) ? G[(b0 + t) * m + b0 + l] : 0.0;
+                }
+                __syncthreads();
+                if (wv == 0) {
+                    // the sequential chain of this block, one coordinate per step
+                    double gl = lane < bl ? g[b0 + lane] : 0.0;
+                    double bv = lane < bl ? bE[b0 + lane] : 0.0;
+                    double dl = 0.0, wmax = 0.0;
+                    for (int t = 0; t < bl; ++t) {
+                        const double gt = readlane_f64(gl, t);
+                        const double bt = readlane_f64(bv, t);
+                        const double bn = soft_threshold(gt + bt, lam);
+                        const double d = bn - bt;
+                        if (d != 0.0) {
+                            gl = fma(-d, Gbb[t * GCD_B + lane], gl);
+                            if (lane == t) {
+                                bv = bn;
+                                dl = d;
+                            }
+                            wmax = fmax(wmax, fabs(d));
+                        }
+                    }
+                    if (lane < bl) {
+                        g[b0 + lane] = gl;
+                        bE[b0 + lane] = bv;
+                        dlt[lane] = dl;
+                    }
+                    const uint64_t ball = __ballot(lane < bl && dl != 0.0);
+                    const int before = __popcll(ball & ((1ull << lane) - 1ull));
+                    if (lane < bl && dl != 0.0) nz[before] = lane;
+                    if (lane == 0) {
+                        nnz_sh = __popcll(ball);
+                        maxd_sh = fmax(maxd_sh, wmax);
+                    }
+                }
+                __syncthreads();
+                const int nnz = nnz_sh;
+                if (nnz > 0) {
+                    // push the block's changes into every other coordinate's gradient
+                    for (int64_t k = tid; k < m; k += GCD_THREADS) {
+                        if (k >= b0 && k < b0 + bl) continue;
+                        double acc = g[k];
+                        for (int q = 0; q < nnz; ++q) {
+                            const int t = nz[q];
+                            acc = fma(-dlt[t], G[(b0 + t) * m + k], acc);
+                        }
+                        g[k] = acc;
+                    }
+                }
+                __syncthreads();
+            }
+            ++sweeps;
+            const double md = maxd_sh;
+            __syncthreads();
+            if (tid == 0) maxd_sh = 0.0;
+            if (md < a.tol) break;
+            if (sweeps >= a.max_sweeps) {
+                status = 1;
+                break;
+            }
+            __syncthreads();
+        }
+    } else {
+        sweeps = 1;
+    }
+    __syncthreads();
+    for (int64_t e = tid; e < m; e += GCD_THREADS) {
+        a.b1[e] = bE[e];
+        a.beta[a.set[e]] = bE[e];
+    }
+    if (tid == 0) {
+        a.sc->round.sweeps = sweeps;
+        a.sc->round.status = status;
+        a.sc->round.cd_len = (int32_t)m;
+    }
+}
+
+// ---- the solve across workgroups ----------------------------------------------------------------------
+//
+// Workgroup 0 (the leader) runs the sequential chain, block after block, in a
+// global sequence q = sweep * nb + b (block b = q mod nb).  After the chain of
+// q it publishes the block's coefficient changes d_q.  Every other workgroup
+// (a helper) owns some blocks of the gradient g and applies each published d_q
+// to them, in sequence order, except for the blocks b_q, b_q+1, ..., b_q+SLACK
+// (mod nb): block b_q took its own changes inside the chain, and the leader
+// itself applies the SLACK most recent changes to the block it is about to run.
+// So before running block b at sequence q the leader needs the owner of b to
+// have applied every sequence below q - SLACK; that is what it waits for.
+// Every gradient entry receives the changes in sequence order, so the result
+// does not depend on timing.  Changes are kept for two sweeps (slot q mod 2nb):
+// the leader waits for every helper at least once per sweep, so a slot is never
+// rewritten before its last reader has taken it.
+//
+// Shared data (gradient, changes, coefficients) is written and read with
+// device-coherent (relaxed, device-scope) atomic accesses, and a writer waits
+// for its stores to complete before it raises the counter that publishes them.
+// Every wait is bounded: on time-out the waiter raises an error flag that all
+// others see, and the host reports a device error.
+constexpr int MB = 32;      // coordinates per block
+constexpr int SLACK = 3;    // most recent blocks whose changes the leader applies itself
+constexpr int MT = 256;     // threads per workgroup
+constexpr int HBATCH = 4;   // sequences a helper applies per round trip at most
+constexpr int HOWN = 2;     // blocks a helper owns at most
+
+__device__ __forceinline__ double ld_coh(const double* p) {
+    return __builtin_bit_cast(double, __hip_atomic_load((const uint64_t*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void st_coh(double* p, double v) {
+    __hip_atomic_store((uint64_t*)p, __builtin_bit_cast(uint64_t, v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_flag(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_flag(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// wait until every memory access this wave issued has completed
+__device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0); }
+
+// sync word layout (uint32): [0] published sequences, [1] stop, [2] error,
+// [SYNC_APPLIED + 16 h] sequences helper h has applied (one 64-byte line each)
+constexpr int SYNC_PUB = 0, SYNC_STOP = 1, SYNC_ERR = 2, SYNC_APPLIED = 64;
+
+__device__ __forceinline__ int blk_len(int64_t m, int b) {
+    const int64_t r = m - (int64_t)b * MB;
+    return (int)(r < MB ? r : MB);
+}
+
+// load G[rows of block rb, columns of block cb] into dst[t * MB + l] (t column, l row), zero padded;
+// the caller's STEP threads (numbered t0 = 0..STEP-1) each issue all their loads before storing any
+template <int STEP>
+__device__ __forceinline__ void load_gblock(const double* __restrict__ G, int64_t m, int rb, int cb, double* dst,
+                                            int t0) {
+    constexpr int PER = MB * MB / STEP;
+    const int rl = blk_len(m, rb), cl = blk_len(m, cb);
+    const int64_t r0 = (int64_t)rb * MB, c0 = (int64_t)cb * MB;
+    double v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int idx = t0 + k * STEP;
+        const int t = idx / MB, l = idx % MB;
+        v[k] = (t < cl && l < rl) ? G[(c0 + t) * m + r0 + l] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) dst[t0 + k * STEP] = v[k];
+}
+
+__global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+    const int64_t m = a.m;
+    const int nb = (int)((m + MB - 1) / MB);
+    const int H = a.H;
+    uint32_t* sync = a.sync;
+    const uint32_t spin_limit = a.spin_limit;
+
+    if (blockIdx.x == 0) {
+        // ---------------- leader ----------------
+        __shared__ double Gm[2][SLACK + 1][MB * MB];  // [buf][0] = G(b,b), [s] = G(b, block of q-s)
+        __shared__ double gb[2][MB], bb[2][MB];       // gradient and coefficients of the block to run
+        __shared__ double dh[SLACK + 1][MB];          // changes of the last blocks, by sequence mod (SLACK+1)
+        __shared__ double gout[2][MB], bout[2][MB];   // results of a block, staged for publishing
+        __shared__ double part[MT / MB][MB];
+        __shared__ double maxd_sh;
+        __shared__ int err_sh;
+        const double lam = a.lam;
+        if (tid == 0) {
+            maxd_sh = 0.0;
+            err_sh = 0;
+        }
+        // block of sequence 0
+        load_gblock<MT>(a.G, m, 0, 0, Gm[0][0], tid);
+        if (tid < MB) {
+            const bool ok = tid < blk_len(m, 0);
+            gb[0][tid] = ok ? ld_coh(a.g + tid) : 0.0;
+            bb[0][tid] = ok ? ld_coh(a.b + tid) : 0.0;
+        }
+        __syncthreads();
+        int sweeps = 0, status = 0;
+        int64_t q = 0;
+        for (;;) {
+            const int b = (int)(q % nb), cur = (int)(q & 1), nxt = cur ^ 1;
+            const int bl = blk_len(m, b);
+            if (wv == 0) {
+                const int l32 = lane & (MB - 1);
+                // the SLACK most recent changes, oldest first (lane l = row l of the block)
+                double gl = lane < bl ? gb[cur][l32] : 0.0;
+                for (int s = SLACK; s >= 1; --s) {
+                    if (q - s < 0) continue;
+                    const double* Gs = Gm[cur][s];
+                    const double* ds = dh[(q - s) % (SLACK + 1)];
+                    double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
+#pragma unroll
+                    for (int t = 0; t < MB; t += 4) {
+                        u0 = fma(Gs[t * MB + l32], ds[t], u0);
+                        u1 = fma(Gs[(t + 1) * MB + l32], ds[t + 1], u1);
+                        u2 = fma(Gs[(t + 2) * MB + l32], ds[t + 2], u2);
+                        u3 = fma(Gs[(t + 3) * MB + l32], ds[t + 3], u3);
+                    }
+                    gl -= (u0 + u1) + (u2 + u3);
+                }
+                // the chain of block b, with the block's Gram column entries in registers
+                double gc[MB];
+#pragma unroll
+                for (int t = 0; t < MB; ++t) gc[t] = Gm[cur][0][t * MB + l32];
+                double bv = lane < bl ? bb[cur][l32] : 0.0;
+                double dl = 0.0, wmax = 0.0;
+                // rows past the block's length hold zeros, so their steps change nothing
+#pragma unroll
+                for (int t = 0; t < MB; ++t) {
+                    const double gt = readlane_f64(gl, t);
+                    const double bt = readlane_f64(bv, t);
+                    const double u = gt + bt;
+                    const double bn = u - fmin(fmax(u, -lam), lam);  // soft threshold S(u, lam)
+                    const double d = bn - bt;
+                    gl = fma(-d, gc[t], gl);
+                    bv = lane == t ? bn : bv;
+                    dl = lane == t ? d : dl;
+                    wmax = fmax(wmax, fabs(d));
+                }
+                if (lane < MB) {
+                    dh[q % (SLACK + 1)][lane] = lane < bl ? dl : 0.0;
+                    gout[cur][lane] = gl;
+                    bout[cur][lane] = bv;
+                }
+                if (lane == 0) maxd_sh = fmax(maxd_sh, wmax);
+            } else if (wv == 1) {
+                // publish the previous block (sequence q-1)
+                if (q >= 1) {
+                    const int pb = (int)((q - 1) % nb), pl = blk_len(m, pb), pc = cur ^ 1;
+                    const int64_t e0 = (int64_t)pb * MB;
+                    if (lane < pl) {
+                        st_coh(a.delta + ((q - 1) % (2 * nb)) * MB + lane, dh[(q - 1) % (SLACK + 1)][lane]);
+                        st_coh(a.g + e0 + lane, gout[pc][lane]);
+                        st_coh(a.b + e0 + lane, bout[pc][lane]);
+                    }
+                    wait_mem();
+                    if (lane == 0) st_flag(sync + SYNC_PUB, (uint32_t)q);
+                }
+            } else if (wv == 2) {
+                // gradient and coefficients of the next block, once its owner is far enough
+                const int64_t qn = q + 1;
+                const int nbk = (int)(qn % nb), nl = blk_len(m, nbk);
+                const int64_t need = qn - SLACK;
+                if (need > 0 && H > 0) {
+                    const int owner = nbk % H;
+                    uint32_t spins = 0;
+                    bool bad = false;
+                    if (lane == 0) {
+                        while ((int64_t)ld_flag(sync + SYNC_APPLIED + 16 * owner) < need) {
+                            if (ld_flag(sync + SYNC_ERR) || ++spins > spin_limit) {
+                                bad = true;
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                        if (bad) err_sh = 1;
+                    }
+                }
+                const int64_t e0 = (int64_t)nbk * MB;
+                if (lane < MB) {
+                    gb[nxt][lane] = lane < nl ? ld_coh(a.g + e0 + lane) : 0.0;
+                    bb[nxt][lane] = lane < nl ? ld_coh(a.b + e0 + lane) : 0.0;
+                }
+            } else {
+                // Gram blocks of the next block
+                const int64_t qn = q + 1;
+                const int nbk = (int)(qn % nb);
+                load_gblock<WAVE>(a.G, m, nbk, nbk, Gm[nxt][0], lane);
+                for (int s = 1; s <= SLACK; ++s) {
+                    if (qn - s < 0) continue;
+                    load_gblock<WAVE>(a.G, m, nbk, (int)((qn - s) % nb), Gm[nxt][s], lane);
+                }
+            }
+            __syncthreads();
+            const bool sweep_end = (b == nb - 1);
+            bool stop = err_sh != 0;
+            if (err_sh) status = 2;
+            if (sweep_end && !stop) {
+                ++sweeps;
+                const double md = maxd_sh;
+                if (md < a.tol) stop = true;
+                else if (sweeps >= a.max_sweeps) {
+                    status = 1;
+                    stop = true;
+                }
+            }
+            __syncthreads();
+            if (sweep_end && tid == 0) maxd_sh = 0.0;
+            ++q;
+            if (stop) break;
+        }
+        // publish the last block, then stop the helpers
+        if (wv == 0 && status != 2) {
+            const int pb = (int)((q - 1) % nb), pl = blk_len(m, pb), pc = (int)((q - 1) & 1);
+            const int64_t e0 = (int64_t)pb * MB;
+            if (lane < pl) {
+                st_coh(a.g + e0 + lane, gout[pc][lane]);
+                st_coh(a.b + e0 + lane, bout[pc][lane]);
+            }
+            wait_mem();
+        }
+        __syncthreads();
+        if (tid == 0) {
+            st_flag(sync + SYNC_STOP, 1u);
+            if (status == 2) st_flag(sync + SYNC_ERR, 1u);
+            a.sc->round.sweeps = sweeps;
+            a.sc->round.status = status;
+            a.sc->round.cd_len = (int32_t)m;
+        }
+        return;
+    }
+
+    // ---------------- helper ----------------
+    __shared__ double Gh[HBATCH][HOWN][MB * MB];
+    __shared__ double dlt[HBATCH][MB];
+    __shared__ double gh[HOWN][MB];
+    __shared__ double hp[MT / MB][HOWN][MB];
+    __shared__ int64_t pub_sh;
+    __shared__ int quit_sh;
+    const int h = blockIdx.x - 1;
+    int own[HOWN];
+    int nown = 0;
+    for (int c = h; c < nb && nown < HOWN; c += H) own[nown++] = c;
+    int64_t s0 = 0;  // next sequence to apply
+    for (;;) {
+        if (tid == 0) {
+            uint32_t spins = 0;
+            int quit = 0;
+            int64_t pub;
+            for (;;) {
+                pub = (int64_t)ld_flag(sync + SYNC_PUB);
+                if (pub > s0) break;
+                if (ld_flag(sync + SYNC_STOP) || ld_flag(sync + SYNC_ERR)) {
+                    quit = 1;
+                    break;
+                }
+                if (++spins > spin_limit) {
+                    st_flag(sync + SYNC_ERR, 1u);
+                    quit = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            pub_sh = pub;
+            quit_sh = quit;
+        }
+        __syncthreads();
+        if (quit_sh) break;
+        const int nbat = (int)((pub_sh - s0) < HBATCH ? (pub_sh - s0) : HBATCH);
+        // changes and Gram blocks of this batch, and the owned gradient blocks: every load is
+        // issued before the first one is waited for
+        {
+            constexpr int PER = MB * MB / MT;
+            double gv[HBATCH][HOWN][PER];
+            double dv[HBATCH];
+            double hv[HOWN];
+#pragma unroll
+            for (int k = 0; k < HBATCH; ++k) {
+                const int bq = (int)((s0 + k) % nb);
+                const bool kin = k < nbat;
+                dv[k] = (kin && tid < blk_len(m, bq)) ? ld_coh(a.delta + ((s0 + k) % (2 * nb)) * MB + tid) : 0.0;
+#pragma unroll
+                for (int o = 0; o < HOWN; ++o) {
+                    const bool use = kin && o < nown && (((own[o] - bq) % nb + nb) % nb) > SLACK;
+                    const int rl = use ? blk_len(m, own[o]) : 0, cl = use ? blk_len(m, bq) : 0;
+                    const int64_t r0 = use ? (int64_t)own[o] * MB : 0, c0 = (int64_t)bq * MB;
+#pragma unroll
+                    for (int q2 = 0; q2 < PER; ++q2) {
+                        const int idx = tid + q2 * MT, t = idx / MB, l = idx % MB;
+                        gv[k][o][q2] = (t < cl && l < rl) ? a.G[(c0 + t) * m + r0 + l] : 0.0;
+                    }
+                }
+            }
+#pragma unroll
+            for (int o = 0; o < HOWN; ++o)
+                hv[o] = (o < nown && tid < blk_len(m, own[o])) ? ld_coh(a.g + (int64_t)own[o] * MB + tid) : 0.0;
+#pragma unroll
+            for (int k = 0; k < HBATCH; ++k) {
+                if (tid < MB) dlt[k][tid] = dv[k];
+#pragma unroll
+                for (int o = 0; o < HOWN; ++o)
+#pragma unroll
+                    for (int q2 = 0; q2 < PER; ++q2) Gh[k][o][tid + q2 * MT] = gv[k][o][q2];
+            }
+#pragma unroll
+            for (int o = 0; o < HOWN; ++o)
+                if (tid < MB) gh[o][tid] = hv[o];
+        }
+        __syncthreads();
+        bool touched[HOWN] = {};
+        for (int k = 0; k < nbat; ++k) {
+            const int bq = (int)((s0 + k) % nb);
+            for (int o = 0; o < nown; ++o) {
+                const int dist = (int)(((own[o] - bq) % nb + nb) % nb);
+                if (dist <= SLACK) continue;  // uniform
+                touched[o] = true;
+                const int l = tid % MB, pp = tid / MB;
+                double acc = 0.0;
+#pragma unroll
+                for (int t = pp * 4; t < pp * 4 + 4; ++t) acc = fma(Gh[k][o][t * MB + l], dlt[k][t], acc);
+                hp[pp][o][l] = acc;
+                __syncthreads();
+                if (tid < MB) {
+                    double tot = 0.0;
+#pragma unroll
+                    for (int q2 = 0; q2 < MT / MB; ++q2) tot += hp[q2][o][tid];
+                    gh[o][tid] -= tot;
+                }
+                __syncthreads();
+            }
+        }
+        // a block is written back only when this batch changed it: a batch that only skips a block
+        // may overlap the leader's own update of it
+        for (int o = 0; o < nown; ++o)
+            if (touched[o] && tid < blk_len(m, own[o])) st_coh(a.g + (int64_t)own[o] * MB + tid, gh[o][tid]);
+        wait_mem();
+        __syncthreads();
+        s0 += nbat;
+        if (tid == 0) st_flag(sync + SYNC_APPLIED + 16 * h, (uint32_t)s0);
+    }
+}
+
+// ---- residual update after a solve -----------------------------------------------------------------------
+// partial[c][i] = sum over set positions e in chunk c of x~_{i,set[e]} (b1[e] - b0[e]) on fitted rows
+constexpr int RU_CHUNK = 64;
+
+template <typename XT, bool MASK>
+__global__ __launch_bounds__(256) void k_r_update_part(const XT* __restrict__ X, int64_t ldx, int64_t n_total,
+                                                       const uint8_t* __restrict__ mask,
+                                                       const int32_t* __restrict__ set, int64_t m,
+                                                       const double* __restrict__ b0, const double* __restrict__ b1,
+                                                       const double* __restrict__ c, const double* __restrict__ s,
+                                                       double* __restrict__ part) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e0 = (int64_t)blockIdx.y * RU_CHUNK;
+    const int64_t e1 = e0 + RU_CHUNK < m ? e0 + RU_CHUNK : m;
+    double acc = 0.0;
+    if (i < n_total && (!MASK || mask[i])) {
+        for (int64_t e = e0; e < e1; ++e) {
+            const double d = b1[e] - b0[e];
+            if (d == 0.0) continue;
+            const int j = set[e];
+            acc = fma(d / s[j], ld_x(X + (int64_t)j * ldx + i) - c[j], acc);
+        }
+    }
+    if (i < n_total) part[blockIdx.y * n_total + i] = acc;
+}
+
+__global__ void k_r_update_reduce(int64_t n_total, int nchunks, const double* __restrict__ part,
+                                  double* __restrict__ r) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_total; i += (int64_t)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int q = 0; q < nchunks; ++q) acc += part[(int64_t)q * n_total + i];
+        r[i] -= acc;
+    }
+}
+
+int grid_for(int64_t work, int per_block, int max_blocks) {
+    int64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > max_blocks) g = max_blocks;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_pool_add(const int32_t* set, const int64_t* len_dev, int64_t len_host, int32_t* pool_pos,
+                           int32_t* pool_list, int64_t pool_size, int64_t* n_new_out, hipStream_t st) {
+    k_pool_add<<<1, 1024, 0, st>>>(set, len_dev, len_host, pool_pos, pool_list, pool_size, n_new_out);
+    return hipGetLastError();
+}
+
+template <typename XT>
+static hipError_t gram_typed(const Mat& m, const int32_t* pool_list, int64_t P, int64_t P0, int64_t N,
+                             const double* c, const double* s, double n_rows, double* G, int64_t ldg,
+                             hipStream_t st) {
+    dim3 grid((unsigned)((P + GT_K - 1) / GT_K), (unsigned)((N + GT_N - 1) / GT_N));
+    if (m.mask)
+        k_gram_update<XT, true><<<grid, 256, 0, st>>>((const XT*)m.X, m.ldx, m.n_total, m.mask, pool_list, P, P0, N,
+                                                      c, s, n_rows, G, ldg);
+    else
+        k_gram_update<XT, false><<<grid, 256, 0, st>>>((const XT*)m.X, m.ldx, m.n_total, m.mask, pool_list, P, P0, N,
+                                                       c, s, n_rows, G, ldg);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_update(const Mat& m, const int32_t* pool_list, int64_t P, int64_t P0, int64_t N,
+                              const double* c, const double* s, double n_rows, double* G, int64_t ldg,
+                              hipStream_t st) {
+    if (N <= 0) return hipSuccess;
+    switch (m.xtype) {
+        case 0: return gram_typed<double>(m, pool_list, P, P0, N, c, s, n_rows, G, ldg, st);
+        case 1: return gram_typed<float>(m, pool_list, P, P0, N, c, s, n_rows, G, ldg, st);
+        default: return gram_typed<int8_t>(m, pool_list, P, P0, N, c, s, n_rows, G, ldg, st);
+    }
+}
+
+hipError_t launch_gather_gram(const int32_t* set, int64_t m, const int32_t* pool_pos, const double* Gp, int64_t ldg,
+                              double* GE, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    k_gather_gram<<<grid_for(m * m, 256, 8192), 256, 0, st>>>(set, m, pool_pos, Gp, ldg, GE);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_start(const int32_t* set, int64_t m, const double* z, const double* beta, double* g0,
+                               double* b0, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    k_gather_start<<<grid_for(m, 256, 1024), 256, 0, st>>>(set, m, z, beta, g0, b0);
+    return hipGetLastError();
+}
+
+hipError_t launch_gcd(const GcdArgs& a, hipStream_t st) {
+    k_gcd<<<1, GCD_THREADS, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+int gcd_multi_helpers(int64_t m) {
+    const int nb = (int)((m + MB - 1) / MB);
+    if (nb < 2 * (SLACK + 2)) return 0;  // small sets: the single-workgroup solve
+    return (nb + HOWN - 1) / HOWN;
+}
+
+size_t gcd_multi_sync_words(int H) { return (size_t)(SYNC_APPLIED + 16 * (H + 1)); }
+
+hipError_t launch_gcd_multi(const GcdMultiArgs& a, hipStream_t st) {
+    k_gcd_multi<<<1 + a.H, MT, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+__global__ void k_copy_f64(const double* __restrict__ src, double* __restrict__ dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// write the final coefficients back to beta[set[e]]
+__global__ void k_scatter_beta(const int32_t* __restrict__ set, int64_t m, const double* __restrict__ b1,
+                               double* __restrict__ beta) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
+        beta[set[e]] = b1[e];
+}
+
+hipError_t launch_copy_f64(const double* src, double* dst, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_copy_f64<<<grid_for(n, 256, 1024), 256, 0, st>>>(src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_beta(const int32_t* set, int64_t m, const double* b1, double* beta, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    k_scatter_beta<<<grid_for(m, 256, 1024), 256, 0, st>>>(set, m, b1, beta);
+    return hipGetLastError();
+}
+
+size_t r_update_scratch_bytes(int64_t n_total, int64_t m) {
+    const int64_t nch = (m + RU_CHUNK - 1) / RU_CHUNK;
+    return (size_t)(nch < 1 ? 1 : nch) * (size_t)n_total * sizeof(double);
+}
+
+template <typename XT>
+static hipError_t ru_typed(const Mat& mt, const int32_t* set, int64_t m, const double* b0, const double* b1,
+                           const double* c, const double* s, double* part, double* r, hipStream_t st) {
+    const int nch = (int)((m + RU_CHUNK - 1) / RU_CHUNK);
+    dim3 grid((unsigned)((mt.n_total + 255) / 256), (unsigned)nch);
+    if (mt.mask)
+        k_r_update_part<XT, true><<<grid, 256, 0, st>>>((const XT*)mt.X, mt.ldx, mt.n_total, mt.mask, set, m, b0, b1,
+                                                        c, s, part);
+    else
+        k_r_update_part<XT, false><<<grid, 256, 0, st>>>((const XT*)mt.X, mt.ldx, mt.n_total, mt.mask, set, m, b0,
+                                                         b1, c, s, part);
+    k_r_update_reduce<<<grid_for(mt.n_total, 256, 1024), 256, 0, st>>>(mt.n_total, nch, part, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_r_update(const Mat& mt, const int32_t* set, int64_t m, const double* b0, const double* b1,
+                           const double* c, const double* s, double* part, double* r, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    switch (mt.xtype) {
+        case 0: return ru_typed<double>(mt, set, m, b0, b1, c, s, part, r, st);
+        case 1: return ru_typed<float>(mt, set, m, b0, b1, c, s, part, r, st);
+        default: return ru_typed<int8_t>(mt, set, m, b0, b1, c, s, part, r, st);
+    }
+}
+
+}  // namespace blk

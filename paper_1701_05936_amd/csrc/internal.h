@@ -22,7 +22,8 @@ struct RoundInfo {
     uint32_t n_viol;   // violators found by the check
     int32_t sweeps;    // CD sweeps of the solve
     int32_t status;    // 0 converged, 1 max_sweeps reached
-    int32_t pad;
+    int32_t cd_len;    // size of the set the solve cycled over
+    int64_t scan_len;  // columns the check scanned
 };
 
 // Scalars the kernels share through device memory.
@@ -34,6 +35,7 @@ struct DevScalars {
     double lmax;       // lambda_max
     int64_t jstar;
     int64_t n_rows;
+    int64_t n_new;     // features the last pool update added
     RoundInfo round;
 };
 
@@ -77,6 +79,7 @@ struct ScanArgs {
     const uint8_t* excl;
     uint8_t* mark;
     uint32_t* nviol;
+    int64_t* len_out;   // when not null, block 0 stores the scanned length here
 };
 hipError_t launch_scan(const Mat& m, const ScanArgs& a, hipStream_t st);
 
@@ -117,6 +120,57 @@ hipError_t launch_cd(const Mat& m, const CdArgs& a, hipStream_t st);
 hipError_t launch_record(const int32_t* set, const int64_t* len_dev, const int64_t* len_safe, const int64_t* len_scan,
                          const double* beta, const double* c, const double* s, const DevScalars* sc, double lam,
                          LamStats* out, hipStream_t st);
+
+// ---- coordinate descent with covariance updates (gram_cd.hip) ----
+constexpr int GCD_B = 64;       // coordinates per sequential block
+constexpr int GCD_MAX = 7168;   // largest working set the covariance solve holds in LDS
+
+struct GcdArgs {
+    const double* G;      // m x m Gram of the set (column-major, ld m)
+    int64_t m;
+    const double* g0;     // gradient at the start
+    const double* b0;     // coefficients at the start
+    double* b1;           // coefficients at the end (per set position)
+    const int32_t* set;
+    double* beta;         // [p], updated at set positions
+    double lam, tol;
+    int max_sweeps;
+    DevScalars* sc;
+};
+hipError_t launch_pool_add(const int32_t* set, const int64_t* len_dev, int64_t len_host, int32_t* pool_pos,
+                           int32_t* pool_list, int64_t pool_size, int64_t* n_new_out, hipStream_t st);
+hipError_t launch_gram_update(const Mat& m, const int32_t* pool_list, int64_t P, int64_t P0, int64_t N,
+                              const double* c, const double* s, double n_rows, double* G, int64_t ldg,
+                              hipStream_t st);
+hipError_t launch_gather_gram(const int32_t* set, int64_t m, const int32_t* pool_pos, const double* Gp, int64_t ldg,
+                              double* GE, hipStream_t st);
+hipError_t launch_gather_start(const int32_t* set, int64_t m, const double* z, const double* beta, double* g0,
+                               double* b0, hipStream_t st);
+hipError_t launch_gcd(const GcdArgs& a, hipStream_t st);
+
+// multi-workgroup covariance solve (leader + helpers); g, b are device arrays of m entries holding the
+// start values (g0, b0) on entry and the final values on exit; sync must be zeroed before the launch.
+struct GcdMultiArgs {
+    const double* G;
+    int64_t m;
+    double* g;
+    double* b;
+    double* delta;        // m entries (block changes)
+    uint32_t* sync;       // gcd_multi_sync_words(H) words, zeroed
+    int H;                // helper workgroups
+    uint32_t spin_limit;  // bound of every wait (sleep iterations)
+    double lam, tol;
+    int max_sweeps;
+    DevScalars* sc;
+};
+int gcd_multi_helpers(int64_t m);  // 0: use the single-workgroup solve
+size_t gcd_multi_sync_words(int H);
+hipError_t launch_gcd_multi(const GcdMultiArgs& a, hipStream_t st);
+hipError_t launch_copy_f64(const double* src, double* dst, int64_t n, hipStream_t st);
+hipError_t launch_scatter_beta(const int32_t* set, int64_t m, const double* b1, double* beta, hipStream_t st);
+size_t r_update_scratch_bytes(int64_t n_total, int64_t m);
+hipError_t launch_r_update(const Mat& mt, const int32_t* set, int64_t m, const double* b0, const double* b1,
+                           const double* c, const double* s, double* part, double* r, hipStream_t st);
 
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t st);
 hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t st);

@@ -285,6 +285,7 @@ __global__ __launch_bounds__(512) void k_scan(const XT* __restrict__ X, int64_t 
     extern __shared__ double r_lds[];
     const int wpb = blockDim.x / WAVE;
     const int64_t len = a.len_dev ? *a.len_dev : a.len_host;
+    if (a.len_out && blockIdx.x == 0 && threadIdx.x == 0) *a.len_out = len;
     const int64_t wid0 = (int64_t)blockIdx.x * wpb;
     if (wid0 >= len) return;  // whole block idle (uniform)
     const double* r = a.r;
@@ -646,6 +647,7 @@ __global__ __launch_bounds__(CD_THREADS) void k_cd(const XT* __restrict__ X, int
         a.sc->rss = tsq;
         a.sc->round.sweeps = sweeps;
         a.sc->round.status = status;
+        a.sc->round.cd_len = (int32_t)m;
     }
 }
 

@@ -250,3 +250,26 @@ def test_not_converged_reports_progress(gpu_ctx):
     ref = oracle.fit_path(prob.Xt, prob.y[0], K=30, ratio=0.1)
     beta = res.beta.cpu().numpy()[: res.k_done]
     assert np.abs(beta - ref.beta[: res.k_done]).max() <= 1e-6
+
+
+@pytest.mark.parametrize("m_set", [300, 1500, 4000])
+def test_cd_solve_large_working_set(gpu_ctx, m_set):
+    """Working sets large enough for the multi-workgroup covariance solve (and its block tail)."""
+    prob = datagen.make("c1", n=900, p=m_set + 500)
+    Xt = prob.Xt
+    oc, os_, ok, on = oracle.standardize(Xt)
+    oy, oyt, oa, olm, ojs = oracle.lambda_max(Xt, oc, os_, ok, prob.y[0])
+    cset = np.sort(np.argsort(-np.abs(oa))[:m_set]).astype(np.int32)
+    lam = 0.2 * olm
+    ob, orr = np.zeros(Xt.shape[0]), oyt.copy()
+    conv, osw = oracle.cd(Xt, oc, os_, lam, cset.astype(np.int64), ob, orr, tol=1e-11)
+    assert conv
+    bd, rd = to_dev(np.zeros(Xt.shape[0])), to_dev(oyt.copy())
+    sw = bl.cd_solve(gpu_ctx, to_dev(Xt), to_dev(oc), to_dev(os_), lam, to_dev(cset), bd, rd, tol=1e-11)
+    assert abs(sw - osw) <= 1
+    np.testing.assert_allclose(bd.cpu().numpy(), ob, atol=1e-9)
+    np.testing.assert_allclose(rd.cpu().numpy(), orr, atol=1e-8 * np.abs(oyt).max())
+    # the same solve again gives the same bits
+    bd2, rd2 = to_dev(np.zeros(Xt.shape[0])), to_dev(oyt.copy())
+    bl.cd_solve(gpu_ctx, to_dev(Xt), to_dev(oc), to_dev(os_), lam, to_dev(cset), bd2, rd2, tol=1e-11)
+    assert torch.equal(bd, bd2)
