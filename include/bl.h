@@ -160,6 +160,28 @@ bl_status bl_kkt_check(bl_ctx ctx, const bl_matrix* X, const double* center, con
                        const double* r, double lambda, const int32_t* check_set, int64_t len,
                        const uint8_t* exclude, double* z, int32_t* violators, int64_t* n_viol);
 
+/* Arithmetic of the check scans. */
+typedef enum {
+    BL_PREC_FP64 = 0,      /* FP64 vector scan (any X type)                                          */
+    BL_PREC_BF16X3 = 1     /* int8 X only: BF16 matrix cores against three BF16 pieces of the residual,
+                              FP32 chunks promoted to FP64; decisions within the error bound are
+                              re-taken on the FP64 scan, so they equal the FP64 decisions            */
+} bl_precision;
+
+/*
+ * The scan alone (Section 3.1.1, type (3)): z[j] = (x_j' r - c_j sum(r)) / (n s_j) for j in
+ * cols[0..len-1], in the given precision.  For BL_PREC_BF16X3, err[j] (device, may be NULL)
+ * receives the bound on |z[j] - exact| the precision form guarantees:
+ *   err_j = (u_r + (1 + 2^-7) g32 + g64) sqrt(n (s_j^2 + c_j^2)) ||r||_2 / (n s_j),
+ *   u_r = (2^-8 + 2^-24)^3 (residual left after three BF16 pieces, relative to |r_i|),
+ *   g32 = 32 u / (1 - 32 u), u = 2^-24 (FP32 chunks of 32 rows), g64 = 65536 * 2^-53 (FP64 sums of up
+ *   to 2^16 chunk and piece terms; n_total <= 2^21),
+ * plus 1e-14 |z_j|.  BL_ERR_UNSUPPORTED for BF16X3 unless X is int8 with 16-byte aligned
+ * columns (X pointer and ldx a multiple of 16) and n_total <= 2^21.
+ */
+bl_status bl_scan(bl_ctx ctx, const bl_matrix* X, const double* center, const double* scale, const double* r,
+                  const int32_t* cols, int64_t len, int32_t precision, double* z, double* err);
+
 /* Options of bl_fit_path. */
 typedef struct {
     int32_t nlambda;           /* K >= 1                                                      */
@@ -169,6 +191,7 @@ typedef struct {
     double tol;                /* CD stop: largest |coefficient change| in a sweep < tol       */
     int32_t max_sweeps;        /* per CD solve                                                */
     int32_t max_rounds;        /* CD + check rounds per lambda before giving up (>= 1)        */
+    int32_t precision;         /* bl_precision of the check scans                              */
 } bl_path_opts;
 
 /* Results of bl_fit_path.  Host arrays have K entries; any pointer may be NULL (not written). */
@@ -188,6 +211,7 @@ typedef struct {
     int64_t* n_safe;           /* host: BEDPP survivors (p - safe rejections)                  */
     int64_t* n_viol;           /* host: features the check added back                          */
     int64_t* n_scanned;        /* host: columns scanned by checks at this lambda               */
+    int64_t* n_recheck;        /* host: precision form: columns re-scanned in FP64 (band + set) */
     double y_mean;             /* out                                                          */
     double lambda_max;         /* out                                                          */
     int64_t jstar;             /* out                                                          */
@@ -214,12 +238,14 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
  * events on the context stream around each launch of the scan, the CD solve and the
  * column statistics, and accumulates per kernel: launches, summed duration and the
  * algorithmic bytes those launches had to read:
- *   scan      columns scanned x n_total x sizeof(element)   (+ the residual once per launch)
+ *   scan      columns scanned x n_total x sizeof(element)   (+ the residual once per launch);
+ *             in the precision form this is the BF16 matrix-core scan
  *   CD        covariance solve: sweeps x m^2 x 8 (the Gram of the working set, m features, per sweep);
  *             residual solve (working sets above the covariance limit): sweeps x m x n_total x sizeof(element)
  *   colstats  p x n_total x sizeof(element)
  *   gram      Gram entries of new pool members and the gather of the working set's Gram
  *   rupdate   residual update after a solve: m x n_total x sizeof(element)
+ *   recheck   precision form: residual pieces, error band and FP64 re-scans of flagged and set columns
  * bl_profile(ctx, 1) enables and resets the counters, bl_profile(ctx, 0) disables.
  */
 typedef struct {
@@ -229,7 +255,7 @@ typedef struct {
 } bl_kernel_profile;
 
 enum { BL_PROF_SCAN = 0, BL_PROF_CD = 1, BL_PROF_COLSTATS = 2, BL_PROF_GRAM = 3, BL_PROF_RUPDATE = 4,
-       BL_PROF_COUNT = 5 };
+       BL_PROF_RECHECK = 5, BL_PROF_COUNT = 6 };
 
 bl_status bl_profile(bl_ctx ctx, int enable);
 bl_status bl_profile_get(bl_ctx ctx, int kernel, bl_kernel_profile* out);

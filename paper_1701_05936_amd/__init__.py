@@ -23,15 +23,16 @@ LIB_PATH = os.path.join(_HERE, "libbl.so")
 BL_OK, BL_ERR_INVALID, BL_ERR_NOMEM, BL_ERR_DEVICE, BL_ERR_NOT_CONVERGED, BL_ERR_UNSUPPORTED = range(6)
 X_F64, X_F32, X_I8 = 0, 1, 2
 SCREEN_NONE, SCREEN_SSR, SCREEN_BEDPP, SCREEN_SSR_BEDPP = 0, 1, 2, 3
+PREC_FP64, PREC_BF16X3 = 0, 1
 
 _STATUS_NAMES = {0: "BL_OK", 1: "BL_ERR_INVALID", 2: "BL_ERR_NOMEM", 3: "BL_ERR_DEVICE",
                  4: "BL_ERR_NOT_CONVERGED", 5: "BL_ERR_UNSUPPORTED"}
 
 # exported C symbols (kept in step with include/bl.h)
 EXPORTS = ("bl_create", "bl_destroy", "bl_last_error", "bl_device_info", "bl_standardize", "bl_lambda_max",
-           "bl_bedpp_setup", "bl_screen", "bl_cd_solve", "bl_kkt_check", "bl_fit_path", "bl_profile",
+           "bl_bedpp_setup", "bl_screen", "bl_cd_solve", "bl_kkt_check", "bl_scan", "bl_fit_path", "bl_profile",
            "bl_profile_get")
-PROF_SCAN, PROF_CD, PROF_COLSTATS, PROF_GRAM, PROF_RUPDATE = 0, 1, 2, 3, 4
+PROF_SCAN, PROF_CD, PROF_COLSTATS, PROF_GRAM, PROF_RUPDATE, PROF_RECHECK = 0, 1, 2, 3, 4, 5
 
 
 class BLError(RuntimeError):
@@ -58,7 +59,7 @@ class _KernelProfile(ctypes.Structure):
 class _PathOpts(ctypes.Structure):
     _fields_ = [("nlambda", ctypes.c_int32), ("lambda_min_ratio", ctypes.c_double), ("lambda_", ctypes.c_void_p),
                 ("rule", ctypes.c_int32), ("tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
-                ("max_rounds", ctypes.c_int32)]
+                ("max_rounds", ctypes.c_int32), ("precision", ctypes.c_int32)]
 
 
 class _PathResult(ctypes.Structure):
@@ -67,7 +68,7 @@ class _PathResult(ctypes.Structure):
                 ("rss", ctypes.c_void_p), ("obj", ctypes.c_void_p), ("sweeps", ctypes.c_void_p),
                 ("rounds", ctypes.c_void_p), ("n_active", ctypes.c_void_p), ("n_strong", ctypes.c_void_p),
                 ("n_safe", ctypes.c_void_p), ("n_viol", ctypes.c_void_p), ("n_scanned", ctypes.c_void_p),
-                ("y_mean", ctypes.c_double), ("lambda_max", ctypes.c_double), ("jstar", ctypes.c_int64),
+                ("n_recheck", ctypes.c_void_p), ("y_mean", ctypes.c_double), ("lambda_max", ctypes.c_double), ("jstar", ctypes.c_int64),
                 ("k_done", ctypes.c_int32), ("time_ms", ctypes.c_double)]
 
 
@@ -96,6 +97,7 @@ def load_library(path: str = LIB_PATH):
     L.bl_screen.argtypes = [vp, P(_ScreenState), dbl, dbl, vp, vp, vp, P(i64), P(i64)]
     L.bl_cd_solve.argtypes = [vp, P(_Matrix), vp, vp, dbl, vp, i64, vp, vp, dbl, i32, P(i32)]
     L.bl_kkt_check.argtypes = [vp, P(_Matrix), vp, vp, vp, dbl, vp, i64, vp, vp, vp, P(i64)]
+    L.bl_scan.argtypes = [vp, P(_Matrix), vp, vp, vp, vp, i64, i32, vp, vp]
     L.bl_fit_path.argtypes = [vp, P(_Matrix), vp, P(_PathOpts), P(_PathResult)]
     L.bl_profile.argtypes = [vp, ctypes.c_int]
     L.bl_profile_get.argtypes = [vp, ctypes.c_int, P(_KernelProfile)]
@@ -266,6 +268,19 @@ def kkt_check(ctx: Context, Xt, c, s, r, lam, check_set, exclude=None, z=None, r
     return z, viol[: nv.value]
 
 
+def scan(ctx: Context, Xt, c, s, r, cols, precision=PREC_FP64, row_mask=None, n_total=None, want_err=False):
+    """z over cols (and, for the BF16 form, the guaranteed error bound per column)."""
+    M = matrix(Xt, n_total, row_mask)
+    if cols.dtype != torch.int32:
+        raise TypeError("cols must be int32")
+    z = torch.zeros(M.p, dtype=torch.float64, device=_dev(ctx))
+    err = torch.zeros(M.p, dtype=torch.float64, device=_dev(ctx)) if want_err else None
+    ctx._check(load_library().bl_scan(ctx.handle, ctypes.byref(M), _ptr(c), _ptr(s), _ptr(r),
+                                      _ptr(cols) if cols.numel() else None, cols.numel(), int(precision), _ptr(z),
+                                      _ptr(err)))
+    return (z, err) if want_err else z
+
+
 @dataclass
 class PathResult:
     lam: np.ndarray
@@ -283,6 +298,7 @@ class PathResult:
     n_safe: np.ndarray
     n_viol: np.ndarray
     n_scanned: np.ndarray
+    n_recheck: np.ndarray
     y_mean: float
     lambda_max: float
     jstar: int
@@ -294,7 +310,7 @@ class PathResult:
 
 def fit_path(ctx: Context, Xt, y, nlambda=100, lambda_min_ratio=0.1, lambdas=None, rule=SCREEN_SSR_BEDPP,
              tol=1e-8, max_sweeps=100000, max_rounds=100, row_mask=None, n_total=None, want_beta=True,
-             raise_on_error=True) -> PathResult:
+             raise_on_error=True, precision=PREC_FP64) -> PathResult:
     M = matrix(Xt, n_total, row_mask)
     K = int(nlambda)
     p = M.p
@@ -305,22 +321,23 @@ def fit_path(ctx: Context, Xt, y, nlambda=100, lambda_min_ratio=0.1, lambdas=Non
     keep = torch.empty(p, dtype=torch.uint8, device=dev)
     host = {k: np.zeros(K) for k in ("lam", "intercept", "rss", "obj")}
     host.update({k: np.zeros(K, dtype=np.int32) for k in ("sweeps", "rounds")})
-    host.update({k: np.zeros(K, dtype=np.int64) for k in ("n_active", "n_strong", "n_safe", "n_viol", "n_scanned")})
+    host.update({k: np.zeros(K, dtype=np.int64) for k in ("n_active", "n_strong", "n_safe", "n_viol", "n_scanned",
+                                                          "n_recheck")})
     lam_in = None
     if lambdas is not None:
         lam_in = np.ascontiguousarray(lambdas, dtype=np.float64)
         assert lam_in.size == K
     opts = _PathOpts(K, float(lambda_min_ratio), lam_in.ctypes.data if lam_in is not None else None, int(rule),
-                     float(tol), int(max_sweeps), int(max_rounds))
+                     float(tol), int(max_sweeps), int(max_rounds), int(precision))
     res = _PathResult(_ptr(beta), _ptr(c), _ptr(s), _ptr(keep), host["lam"].ctypes.data,
                       host["intercept"].ctypes.data, host["rss"].ctypes.data, host["obj"].ctypes.data,
                       host["sweeps"].ctypes.data, host["rounds"].ctypes.data, host["n_active"].ctypes.data,
                       host["n_strong"].ctypes.data, host["n_safe"].ctypes.data, host["n_viol"].ctypes.data,
-                      host["n_scanned"].ctypes.data, 0.0, 0.0, 0, 0, 0.0)
+                      host["n_scanned"].ctypes.data, host["n_recheck"].ctypes.data, 0.0, 0.0, 0, 0, 0.0)
     st = load_library().bl_fit_path(ctx.handle, ctypes.byref(M), _ptr(y), ctypes.byref(opts), ctypes.byref(res))
     msg = load_library().bl_last_error(ctx.handle).decode(errors="replace") if st != BL_OK else ""
     if st != BL_OK and raise_on_error:
         raise BLError(st, msg)
     return PathResult(host["lam"], beta, c, s, keep, host["intercept"], host["rss"], host["obj"], host["sweeps"],
                       host["rounds"], host["n_active"], host["n_strong"], host["n_safe"], host["n_viol"],
-                      host["n_scanned"], res.y_mean, res.lambda_max, res.jstar, res.k_done, res.time_ms, st, msg)
+                      host["n_scanned"], host["n_recheck"], res.y_mean, res.lambda_max, res.jstar, res.k_done, res.time_ms, st, msg)

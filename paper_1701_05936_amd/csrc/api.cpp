@@ -48,7 +48,7 @@ namespace {
 enum BufId {
     B_CMP = 0, B_ARGV, B_ARGI, B_YT, B_R, B_XS, B_A, B_B, B_Z0, B_Z1, B_S0, B_S1, B_E, B_LT, B_LE, B_LENS,
     B_BETA, B_STATS, B_C, B_S, B_KEEP, B_MARK, B_POOLPOS, B_POOLLIST, B_GE, B_G0, B_B0, B_B1, B_RUPART, B_ZS,
-    B_DELTA, B_SYNC, B_COUNT
+    B_DELTA, B_SYNC, B_PIECES, B_LB, B_COUNT
 };
 
 bl_status fail(bl_ctx c, bl_status st, const char* fmt, ...) {
@@ -202,7 +202,7 @@ bl_status solve_set(bl_ctx ctx, const Mat& mt, const int32_t* set, const int64_t
                     double lam, double tol, int max_sweeps) {
     hipStream_t st = ctx->stream;
     const double es = (double)elem_bytes(mt.xtype);
-    if (m > GCD_MAX) {
+    if (m > gram_cd_max()) {
         if (!cd_supported(mt.n_total))
             return fail(ctx, BL_ERR_UNSUPPORTED, "working set of %lld features with n_total %lld is too large",
                         (long long)m, (long long)mt.n_total);
@@ -593,6 +593,53 @@ bl_status bl_kkt_check(bl_ctx ctx, const bl_matrix* X, const double* center, con
     return BL_OK;
 }
 
+bl_status bl_scan(bl_ctx ctx, const bl_matrix* X, const double* center, const double* scale, const double* r,
+                  const int32_t* cols, int64_t len, int32_t precision, double* z, double* err) {
+    bl_status s = check_ctx(ctx);
+    if (s) return s;
+    Mat m;
+    if ((s = check_matrix(ctx, X, &m))) return s;
+    if (!center || !scale || !r || !z) return fail(ctx, BL_ERR_INVALID, "array arguments must be non-NULL");
+    if (len < 0 || len > m.p) return fail(ctx, BL_ERR_INVALID, "len out of range");
+    if (len > 0 && !cols) return fail(ctx, BL_ERR_INVALID, "cols is NULL");
+    if (precision != BL_PREC_FP64 && precision != BL_PREC_BF16X3) return fail(ctx, BL_ERR_INVALID, "unknown precision");
+    if (precision == BL_PREC_BF16X3 && !lowp_supported(m))
+        return fail(ctx, BL_ERR_UNSUPPORTED, "BF16 scan needs int8 X with 16-byte aligned columns");
+    int64_t n;
+    if ((s = rows_in_fit(ctx, m, &n))) return s;
+    if ((s = set_n_rows(ctx, n))) return s;
+    hipStream_t st = ctx->stream;
+    HIPCHK(launch_sum_r(m, r, ctx->sc, true, st));
+    if (len > 0) {
+        if (precision == BL_PREC_FP64) {
+            ScanArgs sa{};
+            sa.cols = cols;
+            sa.len_host = len;
+            sa.r = r;
+            sa.sc = ctx->sc;
+            sa.c = center;
+            sa.s = scale;
+            sa.z = z;
+            HIPCHK(launch_scan(m, sa, st));
+        } else {
+            __bf16* pieces;
+            int64_t* lens;
+            ENSURE(B_PIECES, (size_t)LOWP_PIECES * lowp_pad(m.n_total) * 2, pieces);
+            ENSURE(B_LENS, 8 * sizeof(int64_t), lens);
+            HIPCHK(launch_r_pieces(r, m.n_total, pieces, st));
+            HIPCHK(launch_scan_bf16(m, pieces, cols, nullptr, len, ctx->sc, center, scale, nullptr, z, st));
+            if (err) {
+                ctx->sc_host->stage = len;
+                HIPCHK(hipMemcpyAsync(lens + 5, &ctx->sc_host->stage, sizeof(int64_t), hipMemcpyHostToDevice, st));
+                HIPCHK(launch_band(cols, lens + 5, z, center, scale, ctx->sc, -1.0, nullptr, nullptr, -1.0, nullptr,
+                                   err, m.p, st));
+            }
+        }
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    return BL_OK;
+}
+
 bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_path_opts* opts,
                       bl_path_result* res) {
     auto t_start = std::chrono::steady_clock::now();
@@ -619,6 +666,11 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         return fail(ctx, BL_ERR_INVALID, "tol > 0, max_sweeps >= 1 and max_rounds >= 1 are required");
     const bool bedpp = opts->rule == BL_SCREEN_BEDPP || opts->rule == BL_SCREEN_SSR_BEDPP;
     const bool ssr = opts->rule == BL_SCREEN_SSR || opts->rule == BL_SCREEN_SSR_BEDPP;
+    if (opts->precision != BL_PREC_FP64 && opts->precision != BL_PREC_BF16X3)
+        return fail(ctx, BL_ERR_INVALID, "unknown precision");
+    const bool lowp = opts->precision == BL_PREC_BF16X3;
+    if (lowp && !lowp_supported(m))
+        return fail(ctx, BL_ERR_UNSUPPORTED, "BF16 scan needs int8 X with 16-byte aligned columns");
     const int64_t p = m.p, nt = m.n_total;
     hipStream_t st = ctx->stream;
 
@@ -649,6 +701,14 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
     if (res->center) c = res->center; else ENSURE(B_C, p * 8, c);
     if (res->scale) sc_ = res->scale; else ENSURE(B_S, p * 8, sc_);
     if (res->keep) keep = res->keep; else ENSURE(B_KEEP, p, keep);
+    __bf16* pieces = nullptr;
+    uint8_t* flag = nullptr;
+    int32_t* lB = nullptr;
+    if (lowp) {
+        ENSURE(B_PIECES, (size_t)LOWP_PIECES * lowp_pad(nt) * 2, pieces);
+        ENSURE(B_MARK, p, flag);
+        ENSURE(B_LB, p * 4, lB);
+    }
 
     if ((s = pool_reset(ctx, p))) return s;
     // standardize, lambda_max, BEDPP inputs
@@ -720,7 +780,7 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
     // lens: [0] = |E|, [1],[2] = |S| slots, [3] = zero
     HIPCHK(hipMemsetAsync(lens, 0, 8 * 8, st));
     std::vector<int32_t> h_sweeps(K, 0), h_rounds(K, 0);
-    std::vector<int64_t> h_viol(K, 0);
+    std::vector<int64_t> h_viol(K, 0), h_recheck(K, 0);
 
     uint8_t* safe_cur = s0;
     uint8_t* safe_next = s1;
@@ -759,37 +819,81 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         int rounds = 0;
         int64_t viol_total = 0;
         int sweeps_total = 0;
+        int64_t recheck_total = 0;
         for (;;) {
             HIPCHK(hipMemcpyAsync(&ctx->sc_host->n_new, lens + 0, sizeof(int64_t), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             const int64_t m_len = ctx->sc_host->n_new;
-            if ((s = solve_set(ctx, m, lE, lens + 0, m_len, rounds == 0 ? zprev : zcur, beta, r, c, sc_, (double)n,
-                               lk, opts->tol, opts->max_sweeps)))
+            double* zsrc = rounds == 0 ? zprev : zcur;
+            if (lowp && m_len > 0) {
+                // the solve starts from the exact gradient of its working set
+                ScanArgs ea{};
+                ea.cols = lE;
+                ea.len_dev = lens + 0;
+                ea.r = r;
+                ea.sc = ctx->sc;
+                ea.c = c;
+                ea.s = sc_;
+                ea.keep = keep;
+                ea.z = zsrc;
+                HIPCHK(launch_scan(m, ea, st));
+                recheck_total += m_len;
+            }
+            if ((s = solve_set(ctx, m, lE, lens + 0, m_len, zsrc, beta, r, c, sc_, (double)n, lk, opts->tol,
+                               opts->max_sweeps)))
                 return s;
             HIPCHK(hipMemsetAsync(&ctx->sc->round.n_viol, 0, sizeof(uint32_t), st));
-            ScanArgs ka{};
-            ka.cols = lT;
-            ka.len_dev = len_next;
-            ka.r = r;
-            ka.sc = ctx->sc;
-            ka.c = c;
-            ka.s = sc_;
-            ka.keep = keep;
-            ka.z = zcur;
-            ka.check = ssr;
-            ka.lam = lk;
-            ka.in_s = safe_cur;
-            ka.excl = strong;
-            ka.mark = strong;
-            ka.nviol = &ctx->sc->round.n_viol;
-            ka.len_out = &ctx->sc->round.scan_len;
-            prof_mark(ctx, 2);
-            HIPCHK(launch_scan(m, ka, st));
-            prof_mark(ctx, 3);
+            if (!lowp) {
+                ScanArgs ka{};
+                ka.cols = lT;
+                ka.len_dev = len_next;
+                ka.r = r;
+                ka.sc = ctx->sc;
+                ka.c = c;
+                ka.s = sc_;
+                ka.keep = keep;
+                ka.z = zcur;
+                ka.check = ssr;
+                ka.lam = lk;
+                ka.in_s = safe_cur;
+                ka.excl = strong;
+                ka.mark = strong;
+                ka.nviol = &ctx->sc->round.n_viol;
+                ka.len_out = &ctx->sc->round.scan_len;
+                prof_mark(ctx, 2);
+                HIPCHK(launch_scan(m, ka, st));
+                prof_mark(ctx, 3);
+            } else {
+                // BF16 matrix-core scan, then exact FP64 re-scans of the values near a threshold
+                HIPCHK(launch_r_pieces(r, nt, pieces, st));
+                prof_mark(ctx, 2);
+                HIPCHK(launch_scan_bf16(m, pieces, lT, len_next, 0, ctx->sc, c, sc_, keep, zcur, st));
+                prof_mark(ctx, 3);
+                prof_mark(ctx, 8);
+                HIPCHK(hipMemcpyAsync(&ctx->sc->round.scan_len, len_next, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+                HIPCHK(launch_fill_u8(flag, 0, p, st));
+                const double thr2 = (ssr && k + 1 < K) ? 2.0 * lam[k + 1] - lk : -1.0;
+                HIPCHK(launch_band(lT, len_next, zcur, c, sc_, ctx->sc, ssr ? lk : -1.0, safe_cur, strong, thr2, flag,
+                                   nullptr, p, st));
+                HIPCHK(launch_compact(flag, p, lB, lens + 4, scr, st));
+                ScanArgs ba{};
+                ba.cols = lB;
+                ba.len_dev = lens + 4;
+                ba.r = r;
+                ba.sc = ctx->sc;
+                ba.c = c;
+                ba.s = sc_;
+                ba.keep = keep;
+                ba.z = zcur;
+                HIPCHK(launch_scan(m, ba, st));
+                if (ssr) HIPCHK(launch_viol(lT, len_next, zcur, safe_cur, strong, lk, &ctx->sc->round.n_viol, p, st));
+                prof_mark(ctx, 9);
+                HIPCHK(hipMemcpyAsync(&ctx->sc_host->stage, lens + 4, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            }
             HIPCHK(hipMemcpyAsync(&ctx->sc_host->round, &ctx->sc->round, sizeof(RoundInfo), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             const RoundInfo ri = ctx->sc_host->round;
-            if (m_len > GCD_MAX) {
+            if (m_len > gram_cd_max()) {
                 prof_add(ctx, 0, BL_PROF_CD, (double)ri.sweeps * ri.cd_len * col_bytes);
             } else {
                 prof_add(ctx, 0, BL_PROF_CD, (double)ri.sweeps * (double)m_len * (double)m_len * 8.0);
@@ -797,6 +901,11 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
                 prof_add(ctx, 6, BL_PROF_RUPDATE, ctx->pend_ru_bytes);
             }
             prof_add(ctx, 2, BL_PROF_SCAN, (double)ri.scan_len * col_bytes + nt * 8.0);
+            if (lowp) {
+                const int64_t nb_ = ctx->sc_host->stage;
+                recheck_total += nb_;
+                prof_add(ctx, 8, BL_PROF_RECHECK, (double)nb_ * col_bytes);
+            }
             ++rounds;
             sweeps_total += ri.sweeps;
             viol_total += ri.n_viol;
@@ -819,6 +928,7 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         h_sweeps[k] = sweeps_total;
         h_rounds[k] = rounds;
         h_viol[k] = viol_total;
+        h_recheck[k] = recheck_total;
         HIPCHK(launch_record(lE, lens + 0, len_cur, len_next, beta, c, sc_, ctx->sc, lk, stats + k, st));
         if (res->beta) HIPCHK(hipMemcpyAsync(res->beta + (size_t)k * p, beta, p * 8, hipMemcpyDeviceToDevice, st));
         res->k_done = k + 1;
@@ -841,6 +951,7 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         if (res->rounds) res->rounds[k] = h_rounds[k];
         if (res->n_viol) res->n_viol[k] = h_viol[k];
         if (res->n_scanned) res->n_scanned[k] = hs[k].n_scan * h_rounds[k];
+        if (res->n_recheck) res->n_recheck[k] = h_recheck[k];
         if (res->n_safe) res->n_safe[k] = hs[k].n_safe;
         if (res->n_strong) res->n_strong[k] = hs[k].n_strong;
     }

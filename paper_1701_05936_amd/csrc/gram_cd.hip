@@ -719,6 +719,8 @@ hipError_t launch_gcd(const GcdArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+int64_t gram_cd_max() { return (int64_t)255 * HOWN * MB; }  // one workgroup per compute unit at most
+
 int gcd_multi_helpers(int64_t m) {
     const int nb = (int)((m + MB - 1) / MB);
     if (nb < 2 * (SLACK + 2)) return 0;  // small sets: the single-workgroup solve

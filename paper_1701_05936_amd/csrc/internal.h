@@ -36,6 +36,7 @@ struct DevScalars {
     int64_t jstar;
     int64_t n_rows;
     int64_t n_new;     // features the last pool update added
+    int64_t stage;     // host staging slot for small device-to-host and host-to-device copies
     RoundInfo round;
 };
 
@@ -164,6 +165,7 @@ struct GcdMultiArgs {
     DevScalars* sc;
 };
 int gcd_multi_helpers(int64_t m);  // 0: use the single-workgroup solve
+int64_t gram_cd_max();              // largest working set of the covariance solve
 size_t gcd_multi_sync_words(int H);
 hipError_t launch_gcd_multi(const GcdMultiArgs& a, hipStream_t st);
 hipError_t launch_copy_f64(const double* src, double* dst, int64_t n, hipStream_t st);
@@ -171,6 +173,23 @@ hipError_t launch_scatter_beta(const int32_t* set, int64_t m, const double* b1, 
 size_t r_update_scratch_bytes(int64_t n_total, int64_t m);
 hipError_t launch_r_update(const Mat& mt, const int32_t* set, int64_t m, const double* b0, const double* b1,
                            const double* c, const double* s, double* part, double* r, hipStream_t st);
+
+// ---- precision form: int8 codes on BF16 matrix cores (lowp.hip) ----
+constexpr int LOWP_PIECES = 3;  // BF16 pieces of the residual
+int64_t lowp_pad(int64_t n_total);          // rows of each residual piece buffer (multiple of 128)
+double lowp_coef();                         // error coefficient of the scan bound
+bool lowp_supported(const Mat& m);          // int8 X, 16-byte aligned columns
+hipError_t launch_r_pieces(const double* r, int64_t n_total, __bf16* pieces, hipStream_t st);
+hipError_t launch_scan_bf16(const Mat& m, const __bf16* pieces, const int32_t* cols, const int64_t* len_dev,
+                            int64_t len_host, const DevScalars* sc, const double* c, const double* s,
+                            const uint8_t* keep, double* z, hipStream_t st);
+// flag[j] = 1 (flag pre-zeroed) when |z_j| is within its bound of lam (j in in_s, not in excl) or of thr2 (>= 0);
+// err_out[j] = the bound (either pointer may be null)
+hipError_t launch_band(const int32_t* cols, const int64_t* len_dev, const double* z, const double* c, const double* s,
+                       const DevScalars* sc, double lam, const uint8_t* in_s, const uint8_t* excl, double thr2,
+                       uint8_t* flag, double* err_out, int64_t p, hipStream_t st);
+hipError_t launch_viol(const int32_t* cols, const int64_t* len_dev, const double* z, const uint8_t* in_s, uint8_t* inE,
+                       double lam, uint32_t* nviol, int64_t p, hipStream_t st);
 
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t st);
 hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t st);

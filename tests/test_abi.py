@@ -34,7 +34,26 @@ def test_binding_declares_signatures_without_touching_the_device():
     assert L.bl_fit_path(None, None, None, None, None) == bl.BL_ERR_INVALID
 
 
-def test_struct_layouts_match_header_sizes():
-    # bl_matrix: ptr, int32 (+pad), 3 x int64, ptr
-    assert ctypes.sizeof(bl._Matrix) == 48
-    assert ctypes.sizeof(bl._PathOpts) == 48
+def test_struct_layouts_match_the_header(tmp_path):
+    """Offsets and sizes of every ctypes mirror equal what a C compiler gives for include/bl.h."""
+    import subprocess
+    mirrors = {"bl_matrix": bl._Matrix, "bl_screen_state": bl._ScreenState, "bl_path_opts": bl._PathOpts,
+               "bl_path_result": bl._PathResult, "bl_kernel_profile": bl._KernelProfile}
+    renames = {"lambda_": "lambda"}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bl.h"', "int main(void) {"]
+    for cname, cls in mirrors.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            c_field = renames.get(fname, fname)
+            lines.append(f'printf("{cname}.{fname} %zu\\n", offsetof({cname}, {c_field}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = dict(line.rsplit(" ", 1) for line in out if line)
+    for cname, cls in mirrors.items():
+        assert int(got[f"{cname} size"]) == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert int(got[f"{cname}.{fname}"]) == getattr(cls, fname).offset, f"{cname}.{fname}"
