@@ -234,6 +234,42 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
                       bl_path_result* res);
 
 /*
+ * Batched form: nprob <= 64 lasso problems over one design matrix (Section 3.1.2:
+ * cross-validation fits and several responses share X; each problem selects its
+ * rows with its own mask instead of copying X).  Problem b has its own response,
+ * rows, standardization, lambda grid (its own lambda_max, the ratio of opts),
+ * screening sets and coefficients.  The problems advance through their grids in
+ * lockstep; every pass over X (column statistics, lambda_max and BEDPP products,
+ * post-convergence scans) serves all problems at once on FP64 matrix cores.
+ * Options as bl_fit_path (opts->lambda must be NULL, precision FP64); X->row_mask
+ * must be NULL; X is f32 or f64.
+ */
+typedef struct {
+    int32_t nprob;             /* 1..64                                                                */
+    const double* Y;           /* DEVICE [nprob x n_total]: response of problem b at Y[b*n_total + i]   */
+    const uint8_t* masks;      /* DEVICE [nprob x n_total]: 1 = row i is in problem b's fit; NULL = all */
+} bl_batch;
+
+typedef struct {
+    double* beta;              /* DEVICE [nprob x K x p] (problem-major, then lambda) or NULL           */
+    double* lambda;            /* host [nprob x K]                                                     */
+    double* intercept;         /* host [nprob x K]                                                     */
+    double* rss;               /* host [nprob x K]                                                     */
+    double* obj;               /* host [nprob x K]                                                     */
+    int32_t* sweeps;           /* host [nprob x K]                                                     */
+    int32_t* rounds;           /* host [nprob x K]                                                     */
+    int64_t* n_active;         /* host [nprob x K]                                                     */
+    int64_t* n_strong;         /* host [nprob x K]                                                     */
+    int64_t* n_safe;           /* host [nprob x K]                                                     */
+    int64_t* n_viol;           /* host [nprob x K]                                                     */
+    int32_t k_done;            /* out: lambda indices finished by every problem                        */
+    double time_ms;            /* out                                                                  */
+} bl_batch_result;
+
+bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_batch* batch, const bl_path_opts* opts,
+                            bl_batch_result* res);
+
+/*
  * Kernel timing (diagnostics for measurement).  When enabled, bl_fit_path records HIP
  * events on the context stream around each launch of the scan, the CD solve and the
  * column statistics, and accumulates per kernel: launches, summed duration and the

@@ -30,8 +30,8 @@ _STATUS_NAMES = {0: "BL_OK", 1: "BL_ERR_INVALID", 2: "BL_ERR_NOMEM", 3: "BL_ERR_
 
 # exported C symbols (kept in step with include/bl.h)
 EXPORTS = ("bl_create", "bl_destroy", "bl_last_error", "bl_device_info", "bl_standardize", "bl_lambda_max",
-           "bl_bedpp_setup", "bl_screen", "bl_cd_solve", "bl_kkt_check", "bl_scan", "bl_fit_path", "bl_profile",
-           "bl_profile_get")
+           "bl_bedpp_setup", "bl_screen", "bl_cd_solve", "bl_kkt_check", "bl_scan", "bl_fit_path",
+           "bl_fit_path_batch", "bl_profile", "bl_profile_get")
 PROF_SCAN, PROF_CD, PROF_COLSTATS, PROF_GRAM, PROF_RUPDATE, PROF_RECHECK = 0, 1, 2, 3, 4, 5
 
 
@@ -72,6 +72,18 @@ class _PathResult(ctypes.Structure):
                 ("k_done", ctypes.c_int32), ("time_ms", ctypes.c_double)]
 
 
+class _Batch(ctypes.Structure):
+    _fields_ = [("nprob", ctypes.c_int32), ("Y", ctypes.c_void_p), ("masks", ctypes.c_void_p)]
+
+
+class _BatchResult(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_void_p), ("lambda_", ctypes.c_void_p), ("intercept", ctypes.c_void_p),
+                ("rss", ctypes.c_void_p), ("obj", ctypes.c_void_p), ("sweeps", ctypes.c_void_p),
+                ("rounds", ctypes.c_void_p), ("n_active", ctypes.c_void_p), ("n_strong", ctypes.c_void_p),
+                ("n_safe", ctypes.c_void_p), ("n_viol", ctypes.c_void_p), ("k_done", ctypes.c_int32),
+                ("time_ms", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -99,6 +111,7 @@ def load_library(path: str = LIB_PATH):
     L.bl_kkt_check.argtypes = [vp, P(_Matrix), vp, vp, vp, dbl, vp, i64, vp, vp, vp, P(i64)]
     L.bl_scan.argtypes = [vp, P(_Matrix), vp, vp, vp, vp, i64, i32, vp, vp]
     L.bl_fit_path.argtypes = [vp, P(_Matrix), vp, P(_PathOpts), P(_PathResult)]
+    L.bl_fit_path_batch.argtypes = [vp, P(_Matrix), P(_Batch), P(_PathOpts), P(_BatchResult)]
     L.bl_profile.argtypes = [vp, ctypes.c_int]
     L.bl_profile_get.argtypes = [vp, ctypes.c_int, P(_KernelProfile)]
     for name in EXPORTS:
@@ -341,3 +354,60 @@ def fit_path(ctx: Context, Xt, y, nlambda=100, lambda_min_ratio=0.1, lambdas=Non
     return PathResult(host["lam"], beta, c, s, keep, host["intercept"], host["rss"], host["obj"], host["sweeps"],
                       host["rounds"], host["n_active"], host["n_strong"], host["n_safe"], host["n_viol"],
                       host["n_scanned"], host["n_recheck"], res.y_mean, res.lambda_max, res.jstar, res.k_done, res.time_ms, st, msg)
+
+
+MAX_BATCH = 64
+
+
+@dataclass
+class BatchResult:
+    lam: np.ndarray              # (B, K)
+    beta: torch.Tensor | None    # (B, K, p) device, standardized scale of each problem
+    intercept: np.ndarray
+    rss: np.ndarray
+    obj: np.ndarray
+    sweeps: np.ndarray
+    rounds: np.ndarray
+    n_active: np.ndarray
+    n_strong: np.ndarray
+    n_safe: np.ndarray
+    n_viol: np.ndarray
+    k_done: int
+    time_ms: float
+    status: int
+    message: str
+
+
+def fit_path_batch(ctx: Context, Xt, Y, masks=None, nlambda=100, lambda_min_ratio=0.1, rule=SCREEN_SSR_BEDPP,
+                   tol=1e-8, max_sweeps=100000, max_rounds=100, n_total=None, want_beta=True,
+                   raise_on_error=True) -> BatchResult:
+    """Batched form: B <= 64 problems over one X.  Y (B, n_total) float64 device; masks (B, n_total) uint8
+    device or None (all rows in every problem)."""
+    M = matrix(Xt, n_total, None)
+    nt = M.n_total
+    if Y.dtype != torch.float64 or Y.dim() != 2 or Y.shape[1] != nt:
+        raise ValueError("Y must be float64 of shape (B, n_total)")
+    B = int(Y.shape[0])
+    if masks is not None and (masks.dtype != torch.uint8 or tuple(masks.shape) != (B, nt)):
+        raise ValueError("masks must be uint8 of shape (B, n_total)")
+    K = int(nlambda)
+    p = M.p
+    dev = _dev(ctx)
+    beta = torch.empty((B, K, p), dtype=torch.float64, device=dev) if want_beta else None
+    host = {k: np.zeros((B, K)) for k in ("lam", "intercept", "rss", "obj")}
+    host.update({k: np.zeros((B, K), dtype=np.int32) for k in ("sweeps", "rounds")})
+    host.update({k: np.zeros((B, K), dtype=np.int64) for k in ("n_active", "n_strong", "n_safe", "n_viol")})
+    bt = _Batch(B, _ptr(Y), _ptr(masks))
+    opts = _PathOpts(K, float(lambda_min_ratio), None, int(rule), float(tol), int(max_sweeps), int(max_rounds),
+                     PREC_FP64)
+    res = _BatchResult(_ptr(beta), *[host[k].ctypes.data for k in ("lam", "intercept", "rss", "obj", "sweeps",
+                                                                  "rounds", "n_active", "n_strong", "n_safe",
+                                                                  "n_viol")], 0, 0.0)
+    L = load_library()
+    st = L.bl_fit_path_batch(ctx.handle, ctypes.byref(M), ctypes.byref(bt), ctypes.byref(opts), ctypes.byref(res))
+    msg = L.bl_last_error(ctx.handle).decode(errors="replace") if st != BL_OK else ""
+    if st != BL_OK and raise_on_error:
+        raise BLError(st, msg)
+    return BatchResult(host["lam"], beta, host["intercept"], host["rss"], host["obj"], host["sweeps"],
+                       host["rounds"], host["n_active"], host["n_strong"], host["n_safe"], host["n_viol"],
+                       res.k_done, res.time_ms, st, msg)

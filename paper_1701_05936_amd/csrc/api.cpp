@@ -5,51 +5,16 @@
 
 #include <chrono>
 #include <cmath>
-#include <cstdarg>
-#include <cstdio>
 #include <cstring>
-#include <string>
-#include <vector>
 
-#include "bl.h"
-#include "internal.h"
+#include "ctx.h"
 
 using namespace blk;
+using namespace blapi;
 
-namespace {
 
-struct DevBuf {
-    void* p = nullptr;
-    size_t cap = 0;
-};
 
-}  // namespace
-
-struct bl_ctx_s {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    std::string err;
-    DevScalars* sc = nullptr;      // device
-    DevScalars* sc_host = nullptr; // pinned host mirror
-    std::vector<DevBuf> bufs;
-    // Gram pool of the covariance solve (features that have been in a working set)
-    int64_t pool_size = 0;
-    int64_t pool_cap = 0;
-    double* gpool = nullptr;
-    // kernel timing
-    bool prof = false;
-    hipEvent_t ev[10] = {};
-    double pend_gram_bytes = 0.0, pend_ru_bytes = 0.0;  // bytes of the last solve, for the timing harvest
-    bl_kernel_profile kp[BL_PROF_COUNT] = {};
-};
-
-namespace {
-
-enum BufId {
-    B_CMP = 0, B_ARGV, B_ARGI, B_YT, B_R, B_XS, B_A, B_B, B_Z0, B_Z1, B_S0, B_S1, B_E, B_LT, B_LE, B_LENS,
-    B_BETA, B_STATS, B_C, B_S, B_KEEP, B_MARK, B_POOLPOS, B_POOLLIST, B_GE, B_G0, B_B0, B_B1, B_RUPART, B_ZS,
-    B_DELTA, B_SYNC, B_PIECES, B_LB, B_COUNT
-};
+namespace blapi {
 
 bl_status fail(bl_ctx c, bl_status st, const char* fmt, ...) {
     char buf[512];
@@ -60,12 +25,6 @@ bl_status fail(bl_ctx c, bl_status st, const char* fmt, ...) {
     if (c) c->err = buf;
     return st;
 }
-
-#define HIPCHK(expr)                                                                              \
-    do {                                                                                          \
-        hipError_t e_ = (expr);                                                                   \
-        if (e_ != hipSuccess) return fail(ctx, BL_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
 
 // Device scratch owned by the context; grown on demand, freed by bl_destroy.
 bl_status ensure(bl_ctx ctx, int id, size_t bytes, void** out) {
@@ -85,14 +44,6 @@ bl_status ensure(bl_ctx ctx, int id, size_t bytes, void** out) {
     *out = b.p;
     return BL_OK;
 }
-
-#define ENSURE(id, bytes, ptr)                                          \
-    do {                                                                \
-        void* p_;                                                       \
-        bl_status s_ = ensure(ctx, (id), (size_t)(bytes), &p_);         \
-        if (s_ != BL_OK) return s_;                                     \
-        (ptr) = (decltype(ptr))p_;                                      \
-    } while (0)
 
 int elem_bytes(int xtype) { return xtype == BL_X_F64 ? 8 : (xtype == BL_X_F32 ? 4 : 1); }
 
@@ -121,6 +72,12 @@ bl_status check_matrix(bl_ctx ctx, const bl_matrix* X, Mat* m) {
     return BL_OK;
 }
 
+}  // namespace blapi
+
+namespace {
+
+using namespace blapi;
+
 // rows in the fit (synchronous)
 bl_status rows_in_fit(bl_ctx ctx, const Mat& m, int64_t* n) {
     if (!m.mask) {
@@ -147,6 +104,10 @@ bl_status read_scalars(bl_ctx ctx) {
     return BL_OK;
 }
 
+}  // namespace
+
+namespace blapi {
+
 // kernel timing: record an event pair around a launch when profiling is on
 void prof_mark(bl_ctx ctx, int slot) {
     if (ctx->prof) (void)hipEventRecord(ctx->ev[slot], ctx->stream);
@@ -161,6 +122,12 @@ void prof_add(bl_ctx ctx, int slot, int which, double bytes) {
         ctx->kp[which].bytes += bytes;
     }
 }
+
+}  // namespace blapi
+
+namespace {
+
+using namespace blapi;
 
 // ---- Gram pool -------------------------------------------------------------------------------------
 bl_status pool_reset(bl_ctx ctx, int64_t p) {
@@ -340,6 +307,8 @@ void bl_destroy(bl_ctx c) {
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->gpool) (void)hipFree(c->gpool);
+    if (c->bgpool) (void)hipFree(c->bgpool);
+    if (c->bpinned) (void)hipHostFree(c->bpinned);
     if (c->sc) (void)hipFree(c->sc);
     if (c->sc_host) (void)hipHostFree(c->sc_host);
     delete c;

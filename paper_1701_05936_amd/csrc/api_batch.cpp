@@ -1,0 +1,335 @@
+// Host driver of the batched form (bl_fit_path_batch): all problems advance through
+// their lambda grids in lockstep; one host synchronization per CD + check round.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ctx.h"
+
+using namespace blk;
+using namespace blapi;
+
+namespace {
+
+bl_status bpool_reserve(bl_ctx ctx, int nprob, int64_t need, const std::vector<int64_t>& sizes) {
+    if (need <= ctx->bpool_cap && nprob <= ctx->bpool_np) return BL_OK;
+    int64_t cap = need <= ctx->bpool_cap ? ctx->bpool_cap : std::max<int64_t>({need, ctx->bpool_cap * 2, 256});
+    cap = (cap + 63) / 64 * 64;
+    double* g = nullptr;
+    if (hipMalloc(&g, (size_t)nprob * cap * cap * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, BL_ERR_NOMEM, "batched Gram pools of %lld features do not fit", (long long)cap);
+    }
+    for (int b = 0; b < nprob && b < ctx->bpool_np && ctx->bgpool; ++b) {
+        if (sizes[b] <= 0) continue;
+        const hipError_t e = hipMemcpy2DAsync(g + (size_t)b * cap * cap, cap * sizeof(double),
+                                              ctx->bgpool + (size_t)b * ctx->bpool_cap * ctx->bpool_cap,
+                                              ctx->bpool_cap * sizeof(double), sizes[b] * sizeof(double), sizes[b],
+                                              hipMemcpyDeviceToDevice, ctx->stream);
+        if (e != hipSuccess) {
+            (void)hipStreamSynchronize(ctx->stream);
+            (void)hipFree(g);
+            return fail(ctx, BL_ERR_DEVICE, "Gram pool copy: %s", hipGetErrorString(e));
+        }
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (ctx->bgpool) (void)hipFree(ctx->bgpool);
+    ctx->bgpool = g;
+    ctx->bpool_cap = cap;
+    ctx->bpool_np = nprob;
+    return BL_OK;
+}
+
+}  // namespace
+
+extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_batch* bt, const bl_path_opts* opts,
+                                       bl_batch_result* res) {
+    const auto t_start = std::chrono::steady_clock::now();
+    bl_status s = check_ctx(ctx);
+    if (s) return s;
+    Mat m;
+    if ((s = check_matrix(ctx, X, &m))) return s;
+    if (!bt || !opts || !res) return fail(ctx, BL_ERR_INVALID, "batch/opts/res must be non-NULL");
+    res->k_done = 0;
+    if (m.mask) return fail(ctx, BL_ERR_INVALID, "batched form: rows are chosen per problem (X->row_mask must be NULL)");
+    if (m.xtype != BL_X_F64 && m.xtype != BL_X_F32) return fail(ctx, BL_ERR_UNSUPPORTED, "batched form: X must be f32 or f64");
+    const int NB = bt->nprob;
+    if (NB < 1 || NB > BNP) return fail(ctx, BL_ERR_INVALID, "nprob must be in 1..%d", BNP);
+    if (!bt->Y) return fail(ctx, BL_ERR_INVALID, "Y is NULL");
+    const int K = opts->nlambda;
+    if (K < 1) return fail(ctx, BL_ERR_INVALID, "nlambda must be >= 1");
+    if (opts->lambda) return fail(ctx, BL_ERR_UNSUPPORTED, "batched form: user lambda grids are not supported");
+    if (K > 1 && !(opts->lambda_min_ratio > 0.0 && opts->lambda_min_ratio < 1.0))
+        return fail(ctx, BL_ERR_INVALID, "lambda_min_ratio must be in (0, 1)");
+    if (opts->rule < BL_SCREEN_NONE || opts->rule > BL_SCREEN_SSR_BEDPP) return fail(ctx, BL_ERR_INVALID, "unknown rule");
+    if (!(opts->tol > 0.0) || opts->max_sweeps < 1 || opts->max_rounds < 1)
+        return fail(ctx, BL_ERR_INVALID, "tol > 0, max_sweeps >= 1 and max_rounds >= 1 are required");
+    if (opts->precision != BL_PREC_FP64) return fail(ctx, BL_ERR_UNSUPPORTED, "batched form: FP64 scans only");
+    const bool bedpp = opts->rule == BL_SCREEN_BEDPP || opts->rule == BL_SCREEN_SSR_BEDPP;
+    const bool ssr = opts->rule == BL_SCREEN_SSR || opts->rule == BL_SCREEN_SSR_BEDPP;
+    const int64_t p = m.p, nt = m.n_total, npad = batch_pad(nt);
+    const double es = (double)elem_bytes(m.xtype);
+    hipStream_t st = ctx->stream;
+
+    uint8_t *masks, *keep, *safe, *safen, *strong, *uni, *want, *want_all;
+    double *Mb, *Yt, *R, *Bm, *S1, *S2, *c, *sd, *a, *bb, *z0, *z1, *lamg, *thrg, *beta, *g0, *b0, *b1, *GE = nullptr;
+    int32_t *lT, *lE, *pos, *list, *lsafe;
+    int64_t *lens, *lenT, *safecnt;
+    BatchScalars* bs;
+    LamStats* stats;
+    void* cmp;
+    const size_t P8 = (size_t)NB * p * 8, P1 = (size_t)NB * p, P4 = (size_t)NB * p * 4, RB = (size_t)npad * BNP * 8;
+    if (bt->masks) masks = const_cast<uint8_t*>(bt->masks);
+    else ENSURE(BB_MASKS, (size_t)NB * nt, masks);
+    ENSURE(BB_MB, RB, Mb);
+    ENSURE(BB_YT, RB, Yt);
+    ENSURE(BB_R, RB, R);
+    ENSURE(BB_B, RB, Bm);
+    ENSURE(BB_S1, P8, S1);
+    ENSURE(BB_S2, P8, S2);
+    ENSURE(BB_C, P8, c);
+    ENSURE(BB_S, P8, sd);
+    ENSURE(BB_KEEP, P1, keep);
+    ENSURE(BB_A, P8, a);
+    ENSURE(BB_BB, P8, bb);
+    ENSURE(BB_Z0, P8, z0);
+    ENSURE(BB_Z1, P8, z1);
+    ENSURE(BB_SAFE, P1, safe);
+    ENSURE(BB_SAFEN, P1, safen);
+    ENSURE(BB_STRONG, P1, strong);
+    ENSURE(BB_UNION, p, uni);
+    ENSURE(BB_LT, p * 4, lT);
+    ENSURE(BB_LE, P4, lE);
+    ENSURE(BB_LENS, (BNP + 8) * 8, lens);
+    lenT = lens + BNP;
+    ENSURE(BB_SAFECNT, BNP * 8, safecnt);
+    ENSURE(BB_LSAFE, P4, lsafe);
+    ENSURE(BB_LAM, (size_t)(K + 1) * BNP * 8, lamg);   // lamg[k*BNP + b] = lambda_k of problem b
+    ENSURE(BB_THR, (size_t)K * BNP * 8, thrg);         // strong-rule thresholds 2 lambda_k - lambda_{k-1}
+    ENSURE(BB_WANT, BNP, want);
+    ENSURE(BB_WANTALL, BNP, want_all);
+    ENSURE(BB_BS, BNP * sizeof(BatchScalars), bs);
+    ENSURE(BB_BETA, P8, beta);
+    ENSURE(BB_POS, P4, pos);
+    ENSURE(BB_LIST, P4, list);
+    ENSURE(BB_G0, P8, g0);
+    ENSURE(BB_B0, P8, b0);
+    ENSURE(BB_B1, P8, b1);
+    ENSURE(BB_STATS, (size_t)NB * K * sizeof(LamStats), stats);
+    ENSURE(BB_CMP, std::max(b_compact_scratch_bytes(p), compact_scratch_bytes(p)), cmp);
+
+    // pinned host staging: every write to it is followed by a stream synchronization before the next one
+    struct Pinned {
+        uint8_t want[BNP];
+        int64_t lens[BNP];
+        int64_t lenT;
+        BatchScalars bs[BNP];
+    };
+    if (!ctx->bpinned && hipHostMalloc(&ctx->bpinned, sizeof(Pinned), hipHostMallocDefault) != hipSuccess) {
+        ctx->bpinned = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, BL_ERR_NOMEM, "pinned staging allocation failed");
+    }
+    Pinned* hp = (Pinned*)ctx->bpinned;
+    auto read_bs = [&]() -> bl_status {
+        HIPCHK(hipMemcpyAsync(hp->bs, bs, NB * sizeof(BatchScalars), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return BL_OK;
+    };
+
+    // ---- set-up: row masks, per-problem standardization, lambda_max, BEDPP inputs ----
+    HIPCHK(hipMemsetAsync(bs, 0, BNP * sizeof(BatchScalars), st));
+    HIPCHK(hipMemsetAsync(Yt, 0, RB, st));
+    HIPCHK(hipMemsetAsync(R, 0, RB, st));
+    HIPCHK(hipMemsetAsync(Bm, 0, RB, st));
+    HIPCHK(hipMemsetAsync(want_all, 0, BNP, st));
+    HIPCHK(launch_fill_u8(want_all, 1, NB, st));
+    if (!bt->masks) HIPCHK(launch_fill_u8(masks, 1, (int64_t)NB * nt, st));
+    HIPCHK(launch_b_masks(masks, nt, NB, Mb, st));
+    HIPCHK(launch_b_center_y(masks, bt->Y, nt, NB, Yt, R, bs, st));
+    prof_mark(ctx, 0);
+    HIPCHK(launch_bscan(m, 0, nullptr, nullptr, p, Mb, NB, bs, nullptr, nullptr, nullptr, S1, st));
+    HIPCHK(launch_bscan(m, 1, nullptr, nullptr, p, Mb, NB, bs, nullptr, nullptr, nullptr, S2, st));
+    prof_mark(ctx, 1);
+    HIPCHK(launch_b_stats(S1, S2, p, NB, bs, c, sd, keep, st));
+    HIPCHK(launch_b_sum_r(R, nt, NB, bs, st));
+    prof_mark(ctx, 2);
+    HIPCHK(launch_bscan(m, 2, nullptr, nullptr, p, Yt, NB, bs, c, sd, keep, a, st));
+    prof_mark(ctx, 3);
+    HIPCHK(launch_b_argmax(a, keep, p, NB, bs, st));
+    if ((s = read_bs())) return s;
+    prof_add(ctx, 0, BL_PROF_COLSTATS, 2.0 * p * nt * es);
+    prof_add(ctx, 2, BL_PROF_SCAN, (double)p * nt * es);
+    std::vector<double> lmax(NB);
+    for (int b = 0; b < NB; ++b) {
+        const BatchScalars& h = hp->bs[b];
+        if (h.n_rows < 1) return fail(ctx, BL_ERR_INVALID, "problem %d: its mask selects no rows", b);
+        if (!std::isfinite(h.y_mean) || !std::isfinite(h.yy)) return fail(ctx, BL_ERR_INVALID, "problem %d: y has NaN or Inf", b);
+        if (h.jstar < 0) return fail(ctx, BL_ERR_INVALID, "problem %d: no column is kept (all constant)", b);
+        if (!std::isfinite(h.lmax)) return fail(ctx, BL_ERR_INVALID, "problem %d: X or y has NaN or Inf", b);
+        if (!(h.lmax > 0.0)) return fail(ctx, BL_ERR_INVALID, "problem %d: lambda_max is 0 (y constant on its rows)", b);
+        lmax[b] = h.lmax;
+    }
+    if (bedpp) {
+        HIPCHK(launch_b_std_column(m, masks, NB, bs, c, sd, Bm, st));
+        HIPCHK(launch_b_sum_r(Bm, nt, NB, bs, st));   // the mode-2 scan subtracts c_j * (sum of the right-hand side)
+        prof_mark(ctx, 2);
+        HIPCHK(launch_bscan(m, 2, nullptr, nullptr, p, Bm, NB, bs, c, sd, keep, bb, st));
+        prof_mark(ctx, 3);
+        HIPCHK(launch_b_sum_r(R, nt, NB, bs, st));    // back to the residual's sum and ||y~||^2
+        HIPCHK(hipStreamSynchronize(st));
+        prof_add(ctx, 2, BL_PROF_SCAN, (double)p * nt * es);
+    }
+    // lambda grids (own lambda_max per problem) and strong-rule thresholds, resident on the device
+    std::vector<double> lam((size_t)NB * K), lg((size_t)(K + 1) * BNP, 0.0), tg((size_t)K * BNP, 0.0);
+    for (int b = 0; b < NB; ++b)
+        for (int k = 0; k < K; ++k)
+            lam[(size_t)b * K + k] = K == 1 ? lmax[b] : lmax[b] * std::pow(opts->lambda_min_ratio, (double)k / (K - 1));
+    for (int k = 0; k < K; ++k)
+        for (int b = 0; b < NB; ++b) {
+            lg[(size_t)k * BNP + b] = lam[(size_t)b * K + k];
+            tg[(size_t)k * BNP + b] = k > 0 ? 2.0 * lam[(size_t)b * K + k] - lam[(size_t)b * K + k - 1] : lam[(size_t)b * K];
+        }
+    HIPCHK(hipMemcpyAsync(lamg, lg.data(), lg.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(thrg, tg.data(), tg.size() * 8, hipMemcpyHostToDevice, st));
+    if (res->lambda) std::memcpy(res->lambda, lam.data(), lam.size() * sizeof(double));
+
+    HIPCHK(launch_fill_f64(beta, 0.0, (int64_t)NB * p, st));
+    HIPCHK(launch_fill_u8((uint8_t*)pos, 0xff, (int64_t)P4, st));
+    HIPCHK(hipMemsetAsync(lens, 0, (BNP + 8) * 8, st));
+    std::vector<int64_t> pool_size(NB, 0);
+    std::vector<int32_t> h_sweeps((size_t)NB * K, 0), h_rounds((size_t)NB * K, 0);
+    std::vector<int64_t> h_viol((size_t)NB * K, 0);
+    int64_t ge_cap = 0;  // per-problem stride of the working-set Gram buffer (elements)
+    double* zprev = a;   // z of every problem at its previous lambda (a at lambda_max)
+    double* zcur = z0;
+    bl_status final_status = BL_OK;
+
+    // lambda index 0 is lambda_max of every problem: beta = 0
+    HIPCHK(launch_b_bedpp(p, NB, a, bb, keep, bedpp, bs, lamg, safe, st));
+    HIPCHK(launch_b_compact(safe, p, NB, want_all, lsafe, safecnt, cmp, st));
+    HIPCHK(launch_b_record(lE, lens, p, NB, beta, c, sd, bs, lamg, stats, 0, K, safecnt, st));
+    if (res->beta)
+        HIPCHK(hipMemcpy2DAsync(res->beta, (size_t)K * p * 8, beta, p * 8, p * 8, NB, hipMemcpyDeviceToDevice, st));
+    res->k_done = 1;
+
+    for (int k = 1; k < K; ++k) {
+        const double* lam_k = lamg + (size_t)k * BNP;
+        // S_k per problem and its size; the scan list is the union over problems of S_{k+1} (of S_k at the end)
+        HIPCHK(launch_b_bedpp(p, NB, a, bb, keep, bedpp, bs, lam_k, safe, st));
+        HIPCHK(launch_b_compact(safe, p, NB, want_all, lsafe, safecnt, cmp, st));
+        if (k + 1 < K) {
+            HIPCHK(launch_b_bedpp(p, NB, a, bb, keep, bedpp, bs, lam_k + BNP, safen, st));
+            HIPCHK(launch_b_union(p, NB, safen, uni, st));
+        } else {
+            HIPCHK(launch_b_union(p, NB, safe, uni, st));
+        }
+        HIPCHK(launch_compact(uni, p, lT, lenT, cmp, st));
+        HIPCHK(launch_b_ssr(p, NB, safe, beta, zprev, ssr, thrg + (size_t)k * BNP, want_all, strong, st));
+        HIPCHK(launch_b_compact(strong, p, NB, want_all, lE, lens, cmp, st));
+        std::vector<uint8_t> act(NB, 1);
+        std::vector<int> rounds(NB, 0);
+        const uint8_t* wv = want_all;
+        for (int it = 0;; ++it) {
+            // working-set sizes and new pool members of the problems still solving
+            HIPCHK(hipMemcpyAsync(hp->lens, lens, NB * 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(launch_b_pool_add(lE, lens, p, NB, wv, pos, list, bs, st));
+            if ((s = read_bs())) return s;
+            int64_t max_m = 0, max_P = 0, max_N = 0;
+            for (int b = 0; b < NB; ++b) {
+                if (!act[b]) continue;
+                if (hp->lens[b] > BCD_MAX)
+                    return fail(ctx, BL_ERR_UNSUPPORTED, "problem %d: working set of %lld features exceeds %d", b,
+                                (long long)hp->lens[b], BCD_MAX);
+                max_m = std::max(max_m, hp->lens[b]);
+                max_P = std::max(max_P, pool_size[b] + hp->bs[b].n_new);
+                max_N = std::max(max_N, hp->bs[b].n_new);
+            }
+            if ((s = bpool_reserve(ctx, NB, max_P, pool_size))) return s;
+            prof_mark(ctx, 4);
+            HIPCHK(launch_b_gram_update(m, masks, NB, list, bs, c, sd, ctx->bgpool, ctx->bpool_cap, max_P, max_N, wv, st));
+            HIPCHK(launch_b_commit(NB, wv, bs, st));
+            for (int b = 0; b < NB; ++b)
+                if (act[b]) pool_size[b] += hp->bs[b].n_new;
+            if (max_m * max_m > ge_cap) ge_cap = std::max<int64_t>(max_m * max_m, 2 * ge_cap);
+            ENSURE(BB_GE, (size_t)NB * std::max<int64_t>(ge_cap, 1) * 8, GE);
+            HIPCHK(launch_b_gather(lE, lens, p, NB, wv, pos, ctx->bgpool, ctx->bpool_cap, it == 0 ? zprev : zcur, beta,
+                                   GE, ge_cap, g0, b0, max_m, st));
+            prof_mark(ctx, 5);
+            prof_mark(ctx, 6);
+            HIPCHK(launch_b_gcd(lE, lens, p, NB, wv, GE, ge_cap, g0, b0, b1, beta, lam_k, opts->tol, opts->max_sweeps, bs,
+                                st));
+            prof_mark(ctx, 7);
+            HIPCHK(launch_b_r_update(m, masks, lE, lens, NB, wv, b0, b1, c, sd, R, st));
+            HIPCHK(launch_b_sum_r(R, nt, NB, bs, st));
+            // post-convergence scan of every problem over the union list, then each problem's check
+            prof_mark(ctx, 2);
+            HIPCHK(launch_bscan(m, 2, lT, lenT, 0, R, NB, bs, c, sd, keep, zcur, st));
+            prof_mark(ctx, 3);
+            if (ssr) HIPCHK(launch_b_viol(lT, lenT, p, NB, zcur, safe, strong, lam_k, wv, bs, st));
+            HIPCHK(hipMemcpyAsync(&hp->lenT, lenT, 8, hipMemcpyDeviceToHost, st));
+            if ((s = read_bs())) return s;
+            prof_add(ctx, 4, BL_PROF_GRAM, (double)max_N * (double)max_P * nt * es);
+            double cd_bytes = 0.0;
+            for (int b = 0; b < NB; ++b)
+                if (act[b]) cd_bytes += (double)hp->bs[b].sweeps * hp->lens[b] * hp->lens[b] * 8.0;
+            prof_add(ctx, 6, BL_PROF_CD, cd_bytes);
+            prof_add(ctx, 2, BL_PROF_SCAN, (double)hp->lenT * nt * es + (double)npad * BNP * 8.0);
+            bool any = false;
+            for (int b = 0; b < NB; ++b) {
+                if (!act[b]) continue;
+                const BatchScalars& h = hp->bs[b];
+                h_sweeps[(size_t)b * K + k] += h.sweeps;
+                h_viol[(size_t)b * K + k] += h.n_viol;
+                rounds[b] += 1;
+                if (h.status != 0 && final_status == BL_OK)
+                    final_status = fail(ctx, BL_ERR_NOT_CONVERGED, "problem %d: CD did not converge at lambda index %d", b, k);
+                act[b] = (h.n_viol > 0 && h.status == 0) ? 1 : 0;
+                if (act[b] && rounds[b] >= opts->max_rounds && final_status == BL_OK) {
+                    final_status = fail(ctx, BL_ERR_NOT_CONVERGED, "problem %d: check rounds exhausted at lambda index %d", b, k);
+                    act[b] = 0;
+                }
+                any = any || act[b];
+            }
+            if (final_status != BL_OK || !any) break;
+            // problems with violators solve again over their grown working sets
+            std::memset(hp->want, 0, BNP);
+            for (int b = 0; b < NB; ++b) hp->want[b] = act[b];
+            HIPCHK(hipMemcpyAsync(want, hp->want, BNP, hipMemcpyHostToDevice, st));
+            wv = want;
+            HIPCHK(launch_b_compact(strong, p, NB, wv, lE, lens, cmp, st));
+        }
+        if (final_status != BL_OK) break;
+        for (int b = 0; b < NB; ++b) h_rounds[(size_t)b * K + k] = rounds[b];
+        HIPCHK(launch_b_record(lE, lens, p, NB, beta, c, sd, bs, lam_k, stats, k, K, safecnt, st));
+        if (res->beta)
+            HIPCHK(hipMemcpy2DAsync(res->beta + (size_t)k * p, (size_t)K * p * 8, beta, p * 8, p * 8, NB,
+                                    hipMemcpyDeviceToDevice, st));
+        res->k_done = k + 1;
+        zprev = zcur;
+        zcur = (zcur == z0) ? z1 : z0;
+    }
+    std::vector<LamStats> hs((size_t)NB * K);
+    HIPCHK(hipMemcpyAsync(hs.data(), stats, hs.size() * sizeof(LamStats), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int b = 0; b < NB; ++b) {
+        for (int k = 0; k < res->k_done; ++k) {
+            const size_t q = (size_t)b * K + k;
+            if (res->intercept) res->intercept[q] = hs[q].intercept;
+            if (res->rss) res->rss[q] = hs[q].rss;
+            if (res->obj) res->obj[q] = hs[q].obj;
+            if (res->n_active) res->n_active[q] = hs[q].n_active;
+            if (res->n_strong) res->n_strong[q] = hs[q].n_strong;
+            if (res->n_safe) res->n_safe[q] = hs[q].n_safe;
+            if (res->sweeps) res->sweeps[q] = h_sweeps[q];
+            if (res->rounds) res->rounds[q] = h_rounds[q];
+            if (res->n_viol) res->n_viol[q] = h_viol[q];
+        }
+    }
+    res->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    return final_status;
+}

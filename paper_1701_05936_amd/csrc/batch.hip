@@ -1,0 +1,952 @@
+// Batched form: many lasso problems (responses and cross-validation row subsets)
+// over one design matrix, advanced through their lambda grids in lockstep.
+//
+// Everything that reads X does so once for all problems: a right-hand side of
+// up to BNP = 64 columns (problem b in column b) is contracted against the
+// columns of X on FP64 matrix cores (v_mfma_f64_16x16x4f64).  The masked
+// column sums for per-problem standardization, the type (2) and type (1)
+// products of lambda_max and BEDPP, and every post-convergence scan use it.
+// The rest (screening, compaction, Gram pools, coordinate descent, residual
+// updates) runs as batched kernels with the problem in the grid.
+//
+// Layouts: right-hand sides and residuals are row-major n_pad x 64
+// (R[i*64 + b]); per-problem vectors over features are problem-major
+// (v[b*p + j]).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace blk {
+
+namespace {
+
+constexpr int WAVE = 64;
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+
+__device__ double block_sum(double v, double* buf) {
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) buf[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < nw; ++k) t += buf[k];
+    return t;
+}
+
+int grid_for(int64_t work, int per_block, int max_blocks) {
+    int64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > max_blocks) g = max_blocks;
+    return (int)g;
+}
+
+// ---- the shared contraction: OUT = X_cols' B on FP64 matrix cores ----------------------------------------
+// Workgroup tile: BS_F = 128 columns x 64 problems; wavefront w covers columns 32w .. 32w+31 (two 16-row MFMA
+// tiles) against four 16-problem tiles.  Rows go in batches of BS_K = 64: lane (m, kq) holds 16 consecutive
+// rows of its column (rows i0 + 16kq .. +15) and feeds row i0 + 16kq + st at MFMA step st; the same rows of B
+// come from LDS (double buffered, padded rows against bank conflicts).
+constexpr int BS_F = 128;
+constexpr int BS_K = 64;
+constexpr int BS_LD = BNP + 2;   // LDS row stride of the staged B rows (doubles)
+
+// mode 0: raw dot products; mode 1: squared X (masked second moments); mode 2: standardized correlations
+template <typename XT, int MODE>
+__global__ __launch_bounds__(256) void k_bscan(const XT* __restrict__ X, int64_t ldx, int64_t n_total, int64_t n_pad,
+                                               const int32_t* __restrict__ cols, const int64_t* __restrict__ len_dev,
+                                               int64_t len_host, const double* __restrict__ B, int nprob,
+                                               int64_t p, BatchScalars* __restrict__ bs, const double* __restrict__ c,
+                                               const double* __restrict__ s, const uint8_t* __restrict__ keep,
+                                               double* __restrict__ out) {
+    __shared__ double Bl[2][BS_K * BS_LD];
+    const int64_t len = len_dev ? *len_dev : len_host;
+    const int64_t f0 = (int64_t)blockIdx.x * BS_F;
+    if (f0 >= len) return;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
+    const int m = lane & 15, kq = lane >> 4;
+    // the two columns this lane feeds (tiles ft = 0, 1)
+    const XT* xc[2];
+    bool ok[2];
+#pragma unroll
+    for (int ft = 0; ft < 2; ++ft) {
+        const int64_t t = f0 + 32 * w + 16 * ft + m;
+        ok[ft] = t < len;
+        const int64_t j = ok[ft] ? (cols ? (int64_t)cols[t] : t) : 0;
+        xc[ft] = X + j * ldx;
+    }
+    f64x4 acc[2][4];
+#pragma unroll
+    for (int ft = 0; ft < 2; ++ft)
+#pragma unroll
+        for (int pt = 0; pt < 4; ++pt) acc[ft][pt] = (f64x4){0.0, 0.0, 0.0, 0.0};
+
+    auto stage = [&](int buf, int64_t i0) {
+        // 64 rows x 64 problems; each thread copies 16 doubles
+        for (int idx = tid; idx < BS_K * BNP / 2; idx += 256) {
+            const int row = idx / (BNP / 2), col2 = (idx % (BNP / 2)) * 2;
+            const double* src = B + (i0 + row) * BNP + col2;
+            Bl[buf][row * BS_LD + col2] = src[0];
+            Bl[buf][row * BS_LD + col2 + 1] = src[1];
+        }
+    };
+    int buf = 0;
+    stage(0, 0);
+    __syncthreads();
+    for (int64_t i0 = 0; i0 < n_pad; i0 += BS_K) {
+        // rows of this batch for the lane's two columns (zero past n_total)
+        double xa[2][16];
+#pragma unroll
+        for (int ft = 0; ft < 2; ++ft) {
+            const int64_t r0 = i0 + 16 * kq;
+            if (ok[ft] && r0 + 16 <= n_total) {
+#pragma unroll
+                for (int q = 0; q < 16; ++q) xa[ft][q] = (double)xc[ft][r0 + q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 16; ++q) xa[ft][q] = (ok[ft] && r0 + q < n_total) ? (double)xc[ft][r0 + q] : 0.0;
+            }
+            if (MODE == 1) {
+#pragma unroll
+                for (int q = 0; q < 16; ++q) xa[ft][q] *= xa[ft][q];
+            }
+        }
+        if (i0 + BS_K < n_pad) stage(buf ^ 1, i0 + BS_K);
+        const double* Bb = Bl[buf];
+#pragma unroll
+        for (int st = 0; st < 16; ++st) {
+            const int row = 16 * kq + st;
+#pragma unroll
+            for (int pt = 0; pt < 4; ++pt) {
+                const double bv = Bb[row * BS_LD + 16 * pt + m];
+#pragma unroll
+                for (int ft = 0; ft < 2; ++ft)
+                    acc[ft][pt] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ft][st], bv, acc[ft][pt], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+        buf ^= 1;
+    }
+    // lane (m, kq), register q of tile (ft, pt) holds column 32w + 16ft + kq + 4q against problem 16pt + m
+#pragma unroll
+    for (int ft = 0; ft < 2; ++ft) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t t = f0 + 32 * w + 16 * ft + kq + 4 * q;
+            if (t >= len) continue;
+            const int64_t j = cols ? (int64_t)cols[t] : t;
+#pragma unroll
+            for (int pt = 0; pt < 4; ++pt) {
+                const int b = 16 * pt + m;
+                if (b >= nprob) continue;
+                const double v = acc[ft][pt][q];
+                double o = v;
+                if (MODE == 2) {
+                    const int64_t bj = (int64_t)b * p + j;
+                    const bool kept = keep == nullptr || keep[bj] != 0;
+                    o = kept ? (v - c[bj] * bs[b].sum_r) / ((double)bs[b].n_rows * s[bj]) : 0.0;
+                }
+                out[(int64_t)b * p + j] = o;
+            }
+        }
+    }
+}
+
+// ---- per-problem set-up ---------------------------------------------------------------------------------
+// masks (problem-major bytes) -> row-major FP64 right-hand side and row counts
+__global__ void k_b_masks(const uint8_t* __restrict__ masks, int64_t n_total, int64_t n_pad, int nprob,
+                          double* __restrict__ Mb) {
+    const int64_t total = n_pad * BNP;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx / BNP;
+        const int b = (int)(idx % BNP);
+        Mb[idx] = (i < n_total && b < nprob && masks[(int64_t)b * n_total + i]) ? 1.0 : 0.0;
+    }
+}
+
+// one workgroup per problem: n_b, y_mean, y~ (into the row-major residual and Y~), ||y~||^2
+__global__ __launch_bounds__(1024) void k_b_center_y(const uint8_t* __restrict__ masks, const double* __restrict__ Y,
+                                                     int64_t n_total, double* __restrict__ Yt, double* __restrict__ R,
+                                                     BatchScalars* __restrict__ bs) {
+    __shared__ double buf[16];
+    const int b = blockIdx.x;
+    const uint8_t* mk = masks + (int64_t)b * n_total;
+    const double* y = Y + (int64_t)b * n_total;
+    double sy = 0.0, cnt = 0.0;
+    for (int64_t i = threadIdx.x; i < n_total; i += blockDim.x)
+        if (mk[i]) {
+            sy += y[i];
+            cnt += 1.0;
+        }
+    const double tot = block_sum(sy, buf), n = block_sum(cnt, buf);
+    const double mean = n > 0.0 ? tot / n : 0.0;
+    double ss = 0.0;
+    for (int64_t i = threadIdx.x; i < n_total; i += blockDim.x) {
+        const double v = mk[i] ? y[i] - mean : 0.0;
+        Yt[i * BNP + b] = v;
+        R[i * BNP + b] = v;
+        ss = fma(v, v, ss);
+    }
+    const double yy = block_sum(ss, buf);
+    if (threadIdx.x == 0) {
+        bs[b].y_mean = mean;
+        bs[b].yy = yy;
+        bs[b].n_rows = (int64_t)n;
+        bs[b].rss = yy;
+    }
+}
+
+// sum and sum of squares of each problem's residual column
+__global__ __launch_bounds__(1024) void k_b_sum_r(const double* __restrict__ R, int64_t n_total,
+                                                  BatchScalars* __restrict__ bs) {
+    __shared__ double buf[16];
+    const int b = blockIdx.x;
+    double a = 0.0, q = 0.0;
+    for (int64_t i = threadIdx.x; i < n_total; i += blockDim.x) {
+        const double v = R[i * BNP + b];
+        a += v;
+        q = fma(v, v, q);
+    }
+    const double ta = block_sum(a, buf), tq = block_sum(q, buf);
+    if (threadIdx.x == 0) {
+        bs[b].sum_r = ta;
+        bs[b].rss = tq;
+    }
+}
+
+// centers, scales, keep from the masked first and second moments
+__global__ void k_b_stats(const double* __restrict__ S1, const double* __restrict__ S2, int64_t p, int nprob,
+                          const BatchScalars* __restrict__ bs, double* __restrict__ c, double* __restrict__ s,
+                          uint8_t* __restrict__ keep) {
+    const int b = blockIdx.y;
+    if (b >= nprob) return;
+    const double n = (double)bs[b].n_rows;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < p; j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t bj = (int64_t)b * p + j;
+        const double mean = S1[bj] / n;
+        const double var = S2[bj] / n - mean * mean;
+        const double sd = sqrt(var > 0.0 ? var : 0.0);
+        c[bj] = mean;
+        s[bj] = sd;
+        keep[bj] = sd > 1e-6 ? 1 : 0;
+    }
+}
+
+// lambda_max and the column attaining it, per problem (ties to the smallest index)
+__global__ __launch_bounds__(1024) void k_b_argmax(const double* __restrict__ a, const uint8_t* __restrict__ keep,
+                                                   int64_t p, BatchScalars* __restrict__ bs) {
+    __shared__ double sv[1024];
+    __shared__ int64_t si[1024];
+    const int b = blockIdx.x;
+    double bv = -1.0;
+    int64_t bi = -1;
+    for (int64_t j = threadIdx.x; j < p; j += blockDim.x) {
+        const int64_t bj = (int64_t)b * p + j;
+        if (keep[bj]) {
+            const double v = fabs(a[bj]);
+            if (v > bv) {
+                bv = v;
+                bi = j;
+            }
+        }
+    }
+    sv[threadIdx.x] = bv;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const double ov = sv[threadIdx.x + w];
+            const int64_t oi = si[threadIdx.x + w];
+            if (ov > sv[threadIdx.x] || (ov == sv[threadIdx.x] && oi >= 0 && (si[threadIdx.x] < 0 || oi < si[threadIdx.x]))) {
+                sv[threadIdx.x] = ov;
+                si[threadIdx.x] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        bs[b].lmax = sv[0] < 0.0 ? 0.0 : sv[0];
+        bs[b].jstar = si[0];
+        bs[b].sign_star = (si[0] >= 0 && a[(int64_t)b * p + si[0]] < 0.0) ? -1.0 : 1.0;
+    }
+}
+
+// right-hand side column b = standardized column jstar_b on problem b's rows
+template <typename XT>
+__global__ void k_b_std_column(const XT* __restrict__ X, int64_t ldx, int64_t n_total, const uint8_t* __restrict__ masks,
+                               int64_t p, int nprob, const BatchScalars* __restrict__ bs, const double* __restrict__ c,
+                               const double* __restrict__ s, double* __restrict__ Bm) {
+    const int b = blockIdx.y;
+    const int64_t js = b < nprob ? bs[b].jstar : -1;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_total; i += (int64_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        if (js >= 0 && masks[(int64_t)b * n_total + i]) {
+            const int64_t bj = (int64_t)b * p + js;
+            v = ((double)X[js * ldx + i] - c[bj]) / s[bj];
+        }
+        Bm[i * BNP + b] = v;
+    }
+}
+
+// ---- screening ----------------------------------------------------------------------------------------
+__global__ void k_b_bedpp(int64_t p, int nprob, const double* __restrict__ a, const double* __restrict__ bb,
+                          const uint8_t* __restrict__ keep, int bedpp, const BatchScalars* __restrict__ bs,
+                          const double* __restrict__ lam, uint8_t* __restrict__ safe) {
+    const int b = blockIdx.y;
+    if (b >= nprob) return;
+    const double lm = bs[b].lmax, l = lam[b], sg = bs[b].sign_star;
+    double slack = bs[b].yy / (double)bs[b].n_rows - lm * lm;
+    if (slack < 0.0) slack = 0.0;
+    const double rhs = 2.0 * l * lm - (lm - l) * sqrt(slack);
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < p; j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t bj = (int64_t)b * p + j;
+        uint8_t o = keep[bj];
+        if (o && bedpp && fabs((lm + l) * a[bj] - (lm - l) * sg * lm * bb[bj]) < rhs) o = 0;
+        safe[bj] = o;
+    }
+}
+
+__global__ void k_b_ssr(int64_t p, int nprob, const uint8_t* __restrict__ safe, const double* __restrict__ beta,
+                        const double* __restrict__ zprev, int ssr, const double* __restrict__ thr,
+                        const uint8_t* __restrict__ want, uint8_t* __restrict__ strong) {
+    const int b = blockIdx.y;
+    if (b >= nprob || !want[b]) return;
+    const double t = thr[b];
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < p; j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t bj = (int64_t)b * p + j;
+        uint8_t o = 0;
+        if (safe[bj]) o = (!ssr || beta[bj] != 0.0 || fabs(zprev[bj]) >= t) ? 1 : 0;
+        strong[bj] = o;
+    }
+}
+
+// union over problems of a per-problem mask
+__global__ void k_b_union(int64_t p, int nprob, const uint8_t* __restrict__ mask, uint8_t* __restrict__ out) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < p; j += (int64_t)gridDim.x * blockDim.x) {
+        uint8_t o = 0;
+        for (int b = 0; b < nprob && !o; ++b) o = mask[(int64_t)b * p + j];
+        out[j] = o;
+    }
+}
+
+// post-convergence check per problem over the scanned list
+__global__ void k_b_viol(const int32_t* __restrict__ cols, const int64_t* __restrict__ len_dev, int64_t p, int nprob,
+                         const double* __restrict__ z, const uint8_t* __restrict__ in_s, uint8_t* __restrict__ inE,
+                         const double* __restrict__ lam, const uint8_t* __restrict__ want,
+                         BatchScalars* __restrict__ bs) {
+    const int b = blockIdx.y;
+    if (b >= nprob || !want[b]) return;
+    const int64_t len = *len_dev;
+    const double l = lam[b];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < len; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t bj = (int64_t)b * p + cols[t];
+        if (in_s[bj] && !inE[bj] && fabs(z[bj]) > l) {
+            inE[bj] = 1;
+            atomicAdd(&bs[b].n_viol, 1u);
+        }
+    }
+}
+
+// ---- ordered compaction, one problem per grid row -----------------------------------------------------
+constexpr int CT = 256, CI = 16, CTILE = CT * CI;
+
+__global__ __launch_bounds__(CT) void k_b_cmp_count(const uint8_t* __restrict__ mask, int64_t p,
+                                                    const uint8_t* __restrict__ want, int32_t* __restrict__ counts,
+                                                    int64_t nblk) {
+    __shared__ int32_t sh[CT / WAVE];
+    const int b = blockIdx.y;
+    if (!want[b]) return;
+    const uint8_t* mk = mask + (int64_t)b * p;
+    const int64_t base = (int64_t)blockIdx.x * CTILE + (int64_t)threadIdx.x * CI;
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < CI; ++k)
+        if (base + k < p && mk[base + k]) ++cnt;
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, WAVE);
+    if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < CT / WAVE; ++w) t += sh[w];
+        counts[(int64_t)b * nblk + blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_b_cmp_scan(int32_t* __restrict__ counts, int64_t nblk,
+                                                     const uint8_t* __restrict__ want, int64_t* __restrict__ total) {
+    __shared__ int64_t sh[1024];
+    __shared__ int64_t carry;
+    const int b = blockIdx.x;
+    if (!want[b]) return;
+    int32_t* cb = counts + (int64_t)b * nblk;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < nblk; b0 += blockDim.x) {
+        const int64_t k = b0 + threadIdx.x;
+        const int64_t v = k < nblk ? cb[k] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+            const int64_t add = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += add;
+            __syncthreads();
+        }
+        const int64_t incl = sh[threadIdx.x];
+        if (k < nblk) cb[k] = (int32_t)(carry + incl - v);
+        __syncthreads();
+        if (threadIdx.x == blockDim.x - 1) carry += incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) total[b] = carry;
+}
+
+__global__ __launch_bounds__(CT) void k_b_cmp_write(const uint8_t* __restrict__ mask, int64_t p,
+                                                    const uint8_t* __restrict__ want,
+                                                    const int32_t* __restrict__ offsets, int64_t nblk,
+                                                    int32_t* __restrict__ out) {
+    __shared__ int32_t sh[CT];
+    const int b = blockIdx.y;
+    if (!want[b]) return;
+    const uint8_t* mk = mask + (int64_t)b * p;
+    const int64_t base = (int64_t)blockIdx.x * CTILE + (int64_t)threadIdx.x * CI;
+    uint8_t f[CI];
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < CI; ++k) {
+        f[k] = (base + k < p) ? mk[base + k] : 0;
+        cnt += f[k] ? 1 : 0;
+    }
+    sh[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int off = 1; off < CT; off <<= 1) {
+        const int add = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int pos = offsets[(int64_t)b * nblk + blockIdx.x] + sh[threadIdx.x] - cnt;
+    int32_t* ob = out + (int64_t)b * p;
+#pragma unroll
+    for (int k = 0; k < CI; ++k)
+        if (f[k]) ob[pos++] = (int32_t)(base + k);
+}
+
+// ---- Gram pools, one per problem ------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_b_pool_add(const int32_t* __restrict__ sets, const int64_t* __restrict__ lens,
+                                                     int64_t p, const uint8_t* __restrict__ want,
+                                                     int32_t* __restrict__ pool_pos, int32_t* __restrict__ pool_list,
+                                                     BatchScalars* __restrict__ bs) {
+    __shared__ int32_t sh[1024];
+    __shared__ int64_t carry;
+    const int b = blockIdx.x;
+    if (!want[b]) return;
+    const int32_t* set = sets + (int64_t)b * p;
+    int32_t* pos_b = pool_pos + (int64_t)b * p;
+    int32_t* list_b = pool_list + (int64_t)b * p;
+    const int64_t len = lens[b];
+    const int64_t base_size = bs[b].pool_size;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < len; b0 += blockDim.x) {
+        const int64_t t = b0 + threadIdx.x;
+        int32_t j = -1;
+        int flag = 0;
+        if (t < len) {
+            j = set[t];
+            flag = pos_b[j] < 0 ? 1 : 0;
+        }
+        sh[threadIdx.x] = flag;
+        __syncthreads();
+        for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+            const int add = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (flag) {
+            const int64_t ps = base_size + carry + sh[threadIdx.x] - 1;
+            pos_b[j] = (int32_t)ps;
+            list_b[ps] = j;
+        }
+        __syncthreads();
+        if (threadIdx.x == blockDim.x - 1) carry += sh[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bs[b].n_new = carry;
+}
+
+// after a pool update: pool_size += n_new; and the per-round counters start again
+__global__ void k_b_commit(int nprob, const uint8_t* __restrict__ want, BatchScalars* __restrict__ bs) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nprob && want[b]) {
+        bs[b].pool_size += bs[b].n_new;
+        bs[b].n_new = 0;
+        bs[b].n_viol = 0u;
+    }
+}
+
+// Gram entries of problem b's new pool members against its pool (grid.z = problem; masked rows)
+constexpr int GK = 64, GN = 32, GR = 32;
+
+template <typename XT>
+__global__ __launch_bounds__(256) void k_b_gram_update(const XT* __restrict__ X, int64_t ldx, int64_t n_total,
+                                                       const uint8_t* __restrict__ masks, int64_t p,
+                                                       const int32_t* __restrict__ pool_list,
+                                                       const BatchScalars* __restrict__ bs,
+                                                       const double* __restrict__ c, const double* __restrict__ s,
+                                                       double* __restrict__ Gp, int64_t cap,
+                                                       const uint8_t* __restrict__ want) {
+    __shared__ double As[GR][GK + 1];
+    __shared__ double Bs[GR][GN + 1];
+    const int b = blockIdx.z;
+    if (!want[b]) return;
+    const int64_t N = bs[b].n_new, P0 = bs[b].pool_size, P = P0 + N;
+    const int64_t k0 = (int64_t)blockIdx.x * GK, t0 = (int64_t)blockIdx.y * GN;
+    if (k0 >= P || t0 >= N) return;
+    const int32_t* list = pool_list + (int64_t)b * p;
+    const uint8_t* mk = masks + (int64_t)b * n_total;
+    const double* cb = c + (int64_t)b * p;
+    const double* sb = s + (int64_t)b * p;
+    double* G = Gp + (int64_t)b * cap * cap;
+    const double nb = (double)bs[b].n_rows;
+    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+    double acc[4][2] = {};
+    const int a_col = tid / 4, a_row = (tid % 4) * 8;
+    const int b_col = tid / 8, b_row = (tid % 8) * 4;
+    const XT* acol = (k0 + a_col < P) ? X + (int64_t)list[k0 + a_col] * ldx : nullptr;
+    const XT* bcol = (t0 + b_col < N) ? X + (int64_t)list[P0 + t0 + b_col] * ldx : nullptr;
+    for (int64_t i0 = 0; i0 < n_total; i0 += GR) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t i = i0 + a_row + q;
+            As[a_row + q][a_col] = (acol && i < n_total) ? (double)acol[i] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = i0 + b_row + q;
+            Bs[b_row + q][b_col] = (bcol && i < n_total && mk[i]) ? (double)bcol[i] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int rr = 0; rr < GR; ++rr) {
+            double av[4], bv[2];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) av[q] = As[rr][tx + 16 * q];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) bv[q] = Bs[rr][ty + 16 * q];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int w2 = 0; w2 < 2; ++w2) acc[q][w2] = fma(av[q], bv[w2], acc[q][w2]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t k = k0 + tx + 16 * q;
+        if (k >= P) continue;
+        const int jk = list[k];
+#pragma unroll
+        for (int w2 = 0; w2 < 2; ++w2) {
+            const int64_t t = t0 + ty + 16 * w2;
+            if (t >= N) continue;
+            const int jt = list[P0 + t];
+            const double gv = (acc[q][w2] - nb * (cb[jk] * cb[jt])) / (nb * (sb[jk] * sb[jt]));
+            G[k * cap + (P0 + t)] = gv;
+            G[(P0 + t) * cap + k] = gv;
+        }
+    }
+}
+
+// working-set Gram, start gradient and coefficients of each problem (grid.y = problem)
+__global__ void k_b_gather(const int32_t* __restrict__ sets, const int64_t* __restrict__ lens, int64_t p,
+                           const uint8_t* __restrict__ want, const int32_t* __restrict__ pool_pos,
+                           const double* __restrict__ Gp, int64_t cap, const double* __restrict__ z,
+                           const double* __restrict__ beta, double* __restrict__ GE, int64_t ge_stride,
+                           double* __restrict__ g0, double* __restrict__ b0) {
+    const int b = blockIdx.y;
+    if (!want[b]) return;
+    const int64_t m = lens[b];
+    const int32_t* set = sets + (int64_t)b * p;
+    const int32_t* pos = pool_pos + (int64_t)b * p;
+    const double* G = Gp + (int64_t)b * cap * cap;
+    double* ge = GE + (int64_t)b * ge_stride;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < m * m; idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = idx / m, f = idx - e * m;
+        ge[idx] = G[(int64_t)pos[set[e]] * cap + pos[set[f]]];
+    }
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t bj = (int64_t)b * p + set[e];
+        g0[(int64_t)b * p + e] = z[bj];
+        b0[(int64_t)b * p + e] = beta[bj];
+    }
+}
+
+// ---- coordinate descent, one workgroup per problem ---------------------------------------------------------
+// The single-workgroup covariance solve (blocked chain in one wavefront, block changes pushed by the
+// workgroup) for problem blockIdx.x.
+constexpr int BCD_T = 1024, BCD_B = 64;
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    uint64_t u = __builtin_bit_cast(uint64_t, v);
+    uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, lane);
+    uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+__global__ __launch_bounds__(BCD_T) void k_b_gcd(const int32_t* __restrict__ sets, const int64_t* __restrict__ lens,
+                                                 int64_t p, const uint8_t* __restrict__ want,
+                                                 const double* __restrict__ GE, int64_t ge_stride,
+                                                 const double* __restrict__ g0, const double* __restrict__ b0,
+                                                 double* __restrict__ b1, double* __restrict__ beta,
+                                                 const double* __restrict__ lam, double tol, int max_sweeps,
+                                                 BatchScalars* __restrict__ bs) {
+    __shared__ double g[BCD_MAX];
+    __shared__ double bE[BCD_MAX];
+    __shared__ double Gbb[BCD_B * BCD_B];
+    __shared__ double dlt[BCD_B];
+    __shared__ int nz[BCD_B];
+    __shared__ int nnz_sh;
+    __shared__ double maxd_sh;
+    const int pb = blockIdx.x;
+    if (!want[pb]) return;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+    const int64_t m = lens[pb];
+    const double l = lam[pb];
+    const double* G = GE + (int64_t)pb * ge_stride;
+    const int32_t* set = sets + (int64_t)pb * p;
+    for (int64_t e = tid; e < m; e += BCD_T) {
+        g[e] = g0[(int64_t)pb * p + e];
+        bE[e] = b0[(int64_t)pb * p + e];
+    }
+    int sweeps = 0, status = 0;
+    if (tid == 0) maxd_sh = 0.0;
+    __syncthreads();
+    if (m > 0) {
+        for (;;) {
+            for (int64_t q0 = 0; q0 < m; q0 += BCD_B) {
+                const int bl = (int)((m - q0) < BCD_B ? (m - q0) : BCD_B);
+                for (int idx = tid; idx < BCD_B * BCD_B; idx += BCD_T) {
+                    const int t = idx / BCD_B, r = idx % BCD_B;
+                    Gbb[idx] = (t < bl && r < bl) ? G[(q0 + t) * m + q0 + r] : 0.0;
+                }
+                __syncthreads();
+                if (wv == 0) {
+                    double gl = lane < bl ? g[q0 + lane] : 0.0;
+                    double bv = lane < bl ? bE[q0 + lane] : 0.0;
+                    double dl = 0.0, wmax = 0.0;
+                    for (int t = 0; t < bl; ++t) {
+                        const double gt = readlane_f64(gl, t), bt = readlane_f64(bv, t);
+                        const double u = gt + bt;
+                        const double bn = u - fmin(fmax(u, -l), l);
+                        const double d = bn - bt;
+                        gl = fma(-d, Gbb[t * BCD_B + lane], gl);
+                        bv = lane == t ? bn : bv;
+                        dl = lane == t ? d : dl;
+                        wmax = fmax(wmax, fabs(d));
+                    }
+                    if (lane < bl) {
+                        g[q0 + lane] = gl;
+                        bE[q0 + lane] = bv;
+                        dlt[lane] = dl;
+                    }
+                    const uint64_t ball = __ballot(lane < bl && dl != 0.0);
+                    const int before = __popcll(ball & ((1ull << lane) - 1ull));
+                    if (lane < bl && dl != 0.0) nz[before] = lane;
+                    if (lane == 0) {
+                        nnz_sh = __popcll(ball);
+                        maxd_sh = fmax(maxd_sh, wmax);
+                    }
+                }
+                __syncthreads();
+                const int nnz = nnz_sh;
+                if (nnz > 0) {
+                    for (int64_t k = tid; k < m; k += BCD_T) {
+                        if (k >= q0 && k < q0 + bl) continue;
+                        double acc = g[k];
+                        for (int q = 0; q < nnz; ++q) {
+                            const int t = nz[q];
+                            acc = fma(-dlt[t], G[(q0 + t) * m + k], acc);
+                        }
+                        g[k] = acc;
+                    }
+                }
+                __syncthreads();
+            }
+            ++sweeps;
+            const double md = maxd_sh;
+            __syncthreads();
+            if (tid == 0) maxd_sh = 0.0;
+            if (md < tol) break;
+            if (sweeps >= max_sweeps) {
+                status = 1;
+                break;
+            }
+            __syncthreads();
+        }
+    } else {
+        sweeps = 1;
+    }
+    __syncthreads();
+    for (int64_t e = tid; e < m; e += BCD_T) {
+        b1[(int64_t)pb * p + e] = bE[e];
+        beta[(int64_t)pb * p + set[e]] = bE[e];
+    }
+    if (tid == 0) {
+        bs[pb].sweeps = sweeps;
+        bs[pb].status = status;
+    }
+}
+
+// residual update of every problem after its solve: R[:, b] -= X~_{E_b} (b1 - b0) on b's rows
+constexpr int BRU_CHUNK = 64;
+
+template <typename XT>
+__global__ __launch_bounds__(256) void k_b_r_update(const XT* __restrict__ X, int64_t ldx, int64_t n_total,
+                                                    const uint8_t* __restrict__ masks, const int32_t* __restrict__ sets,
+                                                    const int64_t* __restrict__ lens, int64_t p,
+                                                    const uint8_t* __restrict__ want, const double* __restrict__ b0,
+                                                    const double* __restrict__ b1, const double* __restrict__ c,
+                                                    const double* __restrict__ s, double* __restrict__ R) {
+    const int b = blockIdx.y;
+    if (!want[b]) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_total || !masks[(int64_t)b * n_total + i]) return;
+    const int64_t m = lens[b];
+    const int32_t* set = sets + (int64_t)b * p;
+    double acc = 0.0;
+    for (int64_t e = 0; e < m; ++e) {
+        const double d = b1[(int64_t)b * p + e] - b0[(int64_t)b * p + e];
+        if (d == 0.0) continue;
+        const int64_t bj = (int64_t)b * p + set[e];
+        acc = fma(d / s[bj], (double)X[(int64_t)set[e] * ldx + i] - c[bj], acc);
+    }
+    R[i * BNP + b] -= acc;
+}
+
+// per-lambda record of every problem
+__global__ __launch_bounds__(1024) void k_b_record(const int32_t* __restrict__ sets, const int64_t* __restrict__ lens,
+                                                   int64_t p, const double* __restrict__ beta, const double* __restrict__ c,
+                                                   const double* __restrict__ s, const BatchScalars* __restrict__ bs,
+                                                   const double* __restrict__ lam, LamStats* __restrict__ out,
+                                                   int k, int K, const int64_t* __restrict__ n_safe) {
+    __shared__ double buf[16];
+    const int b = blockIdx.x;
+    const int64_t m = lens ? lens[b] : 0;
+    const int32_t* set = sets + (int64_t)b * p;
+    double l1 = 0.0, cb = 0.0, na = 0.0;
+    for (int64_t t = threadIdx.x; t < m; t += blockDim.x) {
+        const int64_t bj = (int64_t)b * p + set[t];
+        const double v = beta[bj];
+        if (v != 0.0) {
+            l1 += fabs(v);
+            cb += c[bj] * v / s[bj];
+            na += 1.0;
+        }
+    }
+    const double tl1 = block_sum(l1, buf), tcb = block_sum(cb, buf), tna = block_sum(na, buf);
+    if (threadIdx.x == 0) {
+        LamStats* o = out + (int64_t)b * K + k;
+        o->rss = bs[b].rss;
+        o->l1 = tl1;
+        o->n_active = (int64_t)tna;
+        o->intercept = bs[b].y_mean - tcb;
+        o->obj = bs[b].rss / (2.0 * (double)bs[b].n_rows) + lam[b] * tl1;
+        o->n_strong = m;
+        o->n_safe = n_safe ? n_safe[b] : 0;
+        o->n_scan = 0;
+    }
+}
+
+}  // namespace
+
+// ---- launchers -------------------------------------------------------------------------------------------------
+int64_t batch_pad(int64_t n_total) { return (n_total + BS_K - 1) / BS_K * BS_K; }
+
+template <typename XT>
+static hipError_t bscan_typed(const Mat& mt, int mode, const int32_t* cols, const int64_t* len_dev, int64_t len_host,
+                              const double* B, int nprob, BatchScalars* bs, const double* c, const double* s,
+                              const uint8_t* keep, double* out, hipStream_t st) {
+    const int64_t n_pad = batch_pad(mt.n_total);
+    const int64_t work = len_dev ? mt.p : len_host;
+    const int g = (int)((work + BS_F - 1) / BS_F);
+    const XT* X = (const XT*)mt.X;
+    if (g <= 0) return hipSuccess;
+    if (mode == 0)
+        k_bscan<XT, 0><<<g, 256, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, cols, len_dev, len_host, B, nprob, mt.p, bs,
+                                          c, s, keep, out);
+    else if (mode == 1)
+        k_bscan<XT, 1><<<g, 256, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, cols, len_dev, len_host, B, nprob, mt.p, bs,
+                                          c, s, keep, out);
+    else
+        k_bscan<XT, 2><<<g, 256, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, cols, len_dev, len_host, B, nprob, mt.p, bs,
+                                          c, s, keep, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_bscan(const Mat& mt, int mode, const int32_t* cols, const int64_t* len_dev, int64_t len_host,
+                        const double* B, int nprob, BatchScalars* bs, const double* c, const double* s,
+                        const uint8_t* keep, double* out, hipStream_t st) {
+    if (mt.xtype == 0) return bscan_typed<double>(mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
+    return bscan_typed<float>(mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
+}
+
+hipError_t launch_b_masks(const uint8_t* masks, int64_t n_total, int nprob, double* Mb, hipStream_t st) {
+    const int64_t n_pad = batch_pad(n_total);
+    k_b_masks<<<grid_for(n_pad * BNP, 256, 4096), 256, 0, st>>>(masks, n_total, n_pad, nprob, Mb);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_center_y(const uint8_t* masks, const double* Y, int64_t n_total, int nprob, double* Yt, double* R,
+                             BatchScalars* bs, hipStream_t st) {
+    k_b_center_y<<<nprob, 1024, 0, st>>>(masks, Y, n_total, Yt, R, bs);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_sum_r(const double* R, int64_t n_total, int nprob, BatchScalars* bs, hipStream_t st) {
+    k_b_sum_r<<<nprob, 1024, 0, st>>>(R, n_total, bs);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_stats(const double* S1, const double* S2, int64_t p, int nprob, const BatchScalars* bs, double* c,
+                          double* s, uint8_t* keep, hipStream_t st) {
+    dim3 grid(grid_for(p, 256, 256), nprob);
+    k_b_stats<<<grid, 256, 0, st>>>(S1, S2, p, nprob, bs, c, s, keep);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_argmax(const double* a, const uint8_t* keep, int64_t p, int nprob, BatchScalars* bs,
+                           hipStream_t st) {
+    k_b_argmax<<<nprob, 1024, 0, st>>>(a, keep, p, bs);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_std_column(const Mat& mt, const uint8_t* masks, int nprob, const BatchScalars* bs, const double* c,
+                               const double* s, double* Bm, hipStream_t st) {
+    dim3 grid(grid_for(mt.n_total, 256, 64), BNP);
+    if (mt.xtype == 0)
+        k_b_std_column<double><<<grid, 256, 0, st>>>((const double*)mt.X, mt.ldx, mt.n_total, masks, mt.p, nprob, bs,
+                                                     c, s, Bm);
+    else
+        k_b_std_column<float><<<grid, 256, 0, st>>>((const float*)mt.X, mt.ldx, mt.n_total, masks, mt.p, nprob, bs, c,
+                                                    s, Bm);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_bedpp(int64_t p, int nprob, const double* a, const double* bb, const uint8_t* keep, bool bedpp,
+                          const BatchScalars* bs, const double* lam, uint8_t* safe, hipStream_t st) {
+    dim3 grid(grid_for(p, 256, 256), nprob);
+    k_b_bedpp<<<grid, 256, 0, st>>>(p, nprob, a, bb, keep, bedpp ? 1 : 0, bs, lam, safe);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_ssr(int64_t p, int nprob, const uint8_t* safe, const double* beta, const double* zprev, bool ssr,
+                        const double* thr, const uint8_t* want, uint8_t* strong, hipStream_t st) {
+    dim3 grid(grid_for(p, 256, 256), nprob);
+    k_b_ssr<<<grid, 256, 0, st>>>(p, nprob, safe, beta, zprev, ssr ? 1 : 0, thr, want, strong);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_union(int64_t p, int nprob, const uint8_t* mask, uint8_t* out, hipStream_t st) {
+    k_b_union<<<grid_for(p, 256, 2048), 256, 0, st>>>(p, nprob, mask, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_viol(const int32_t* cols, const int64_t* len_dev, int64_t p, int nprob, const double* z,
+                         const uint8_t* in_s, uint8_t* inE, const double* lam, const uint8_t* want, BatchScalars* bs,
+                         hipStream_t st) {
+    dim3 grid(grid_for(p, 256, 256), nprob);
+    k_b_viol<<<grid, 256, 0, st>>>(cols, len_dev, p, nprob, z, in_s, inE, lam, want, bs);
+    return hipGetLastError();
+}
+
+size_t b_compact_scratch_bytes(int64_t p) {
+    const int64_t nblk = (p + CTILE - 1) / CTILE;
+    return (size_t)BNP * (size_t)(nblk < 1 ? 1 : nblk) * sizeof(int32_t);
+}
+
+hipError_t launch_b_compact(const uint8_t* mask, int64_t p, int nprob, const uint8_t* want, int32_t* out,
+                            int64_t* lens, void* scratch, hipStream_t st) {
+    int64_t nblk = (p + CTILE - 1) / CTILE;
+    if (nblk < 1) nblk = 1;
+    int32_t* counts = (int32_t*)scratch;
+    dim3 grid((unsigned)nblk, nprob);
+    k_b_cmp_count<<<grid, CT, 0, st>>>(mask, p, want, counts, nblk);
+    k_b_cmp_scan<<<nprob, 1024, 0, st>>>(counts, nblk, want, lens);
+    k_b_cmp_write<<<grid, CT, 0, st>>>(mask, p, want, counts, nblk, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_pool_add(const int32_t* sets, const int64_t* lens, int64_t p, int nprob, const uint8_t* want,
+                             int32_t* pool_pos, int32_t* pool_list, BatchScalars* bs, hipStream_t st) {
+    k_b_pool_add<<<nprob, 1024, 0, st>>>(sets, lens, p, want, pool_pos, pool_list, bs);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_commit(int nprob, const uint8_t* want, BatchScalars* bs, hipStream_t st) {
+    k_b_commit<<<1, BNP, 0, st>>>(nprob, want, bs);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_gram_update(const Mat& mt, const uint8_t* masks, int nprob, const int32_t* pool_list,
+                                const BatchScalars* bs, const double* c, const double* s, double* Gp, int64_t cap,
+                                int64_t max_P, int64_t max_N, const uint8_t* want, hipStream_t st) {
+    if (max_N <= 0) return hipSuccess;
+    dim3 grid((unsigned)((max_P + GK - 1) / GK), (unsigned)((max_N + GN - 1) / GN), nprob);
+    if (mt.xtype == 0)
+        k_b_gram_update<double><<<grid, 256, 0, st>>>((const double*)mt.X, mt.ldx, mt.n_total, masks, mt.p, pool_list,
+                                                      bs, c, s, Gp, cap, want);
+    else
+        k_b_gram_update<float><<<grid, 256, 0, st>>>((const float*)mt.X, mt.ldx, mt.n_total, masks, mt.p, pool_list, bs,
+                                                     c, s, Gp, cap, want);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_gather(const int32_t* sets, const int64_t* lens, int64_t p, int nprob, const uint8_t* want,
+                           const int32_t* pool_pos, const double* Gp, int64_t cap, const double* z, const double* beta,
+                           double* GE, int64_t ge_stride, double* g0, double* b0, int64_t max_m, hipStream_t st) {
+    dim3 grid(grid_for(max_m * max_m, 256, 2048), nprob);
+    k_b_gather<<<grid, 256, 0, st>>>(sets, lens, p, want, pool_pos, Gp, cap, z, beta, GE, ge_stride, g0, b0);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_gcd(const int32_t* sets, const int64_t* lens, int64_t p, int nprob, const uint8_t* want,
+                        const double* GE, int64_t ge_stride, const double* g0, const double* b0, double* b1,
+                        double* beta, const double* lam, double tol, int max_sweeps, BatchScalars* bs,
+                        hipStream_t st) {
+    k_b_gcd<<<nprob, BCD_T, 0, st>>>(sets, lens, p, want, GE, ge_stride, g0, b0, b1, beta, lam, tol, max_sweeps, bs);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_r_update(const Mat& mt, const uint8_t* masks, const int32_t* sets, const int64_t* lens, int nprob,
+                             const uint8_t* want, const double* b0, const double* b1, const double* c,
+                             const double* s, double* R, hipStream_t st) {
+    dim3 grid((unsigned)((mt.n_total + 255) / 256), nprob);
+    if (mt.xtype == 0)
+        k_b_r_update<double><<<grid, 256, 0, st>>>((const double*)mt.X, mt.ldx, mt.n_total, masks, sets, lens, mt.p,
+                                                   want, b0, b1, c, s, R);
+    else
+        k_b_r_update<float><<<grid, 256, 0, st>>>((const float*)mt.X, mt.ldx, mt.n_total, masks, sets, lens, mt.p, want,
+                                                  b0, b1, c, s, R);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_record(const int32_t* sets, const int64_t* lens, int64_t p, int nprob, const double* beta,
+                           const double* c, const double* s, const BatchScalars* bs, const double* lam,
+                           LamStats* out, int k, int K, const int64_t* n_safe, hipStream_t st) {
+    k_b_record<<<nprob, 1024, 0, st>>>(sets, lens, p, beta, c, s, bs, lam, out, k, K, n_safe);
+    return hipGetLastError();
+}
+
+}  // namespace blk

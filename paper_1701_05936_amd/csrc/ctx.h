@@ -1,0 +1,76 @@
+// Context of libbl.so and helpers shared by the host-side drivers (api.cpp, api_batch.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "bl.h"
+#include "internal.h"
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+struct bl_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    blk::DevScalars* sc = nullptr;      // device
+    blk::DevScalars* sc_host = nullptr; // pinned host mirror
+    std::vector<DevBuf> bufs;
+    // Gram pool of the covariance solve (features that have been in a working set)
+    int64_t pool_size = 0;
+    int64_t pool_cap = 0;
+    double* gpool = nullptr;
+    // Gram pools of the batched form (one per problem, common capacity)
+    int64_t bpool_cap = 0;
+    int bpool_np = 0;                    // problems the batched pools were allocated for
+    double* bgpool = nullptr;
+    void* bpinned = nullptr;            // pinned host staging of the batched driver
+    // kernel timing
+    bool prof = false;
+    hipEvent_t ev[10] = {};
+    double pend_gram_bytes = 0.0, pend_ru_bytes = 0.0;  // bytes of the last solve, for the timing harvest
+    bl_kernel_profile kp[BL_PROF_COUNT] = {};
+};
+
+namespace blapi {
+
+enum BufId {
+    B_CMP = 0, B_ARGV, B_ARGI, B_YT, B_R, B_XS, B_A, B_B, B_Z0, B_Z1, B_S0, B_S1, B_E, B_LT, B_LE, B_LENS,
+    B_BETA, B_STATS, B_C, B_S, B_KEEP, B_MARK, B_POOLPOS, B_POOLLIST, B_GE, B_G0, B_B0, B_B1, B_RUPART, B_ZS,
+    B_DELTA, B_SYNC, B_PIECES, B_LB,
+    // batched form
+    BB_MASKS, BB_MB, BB_Y, BB_YT, BB_R, BB_B, BB_S1, BB_S2, BB_C, BB_S, BB_KEEP, BB_A, BB_BB, BB_Z0, BB_Z1, BB_SAFE,
+    BB_SAFEN, BB_STRONG, BB_UNION, BB_LT, BB_LE, BB_LENS, BB_LAM, BB_THR, BB_WANT, BB_BS, BB_BETA, BB_POS, BB_LIST,
+    BB_GE, BB_G0, BB_B0, BB_B1, BB_STATS, BB_CMP, BB_LSAFE, BB_SAFECNT, BB_WANTALL,
+    B_COUNT
+};
+
+bl_status fail(bl_ctx c, bl_status st, const char* fmt, ...);
+bl_status ensure(bl_ctx ctx, int id, size_t bytes, void** out);
+int elem_bytes(int xtype);
+bl_status check_ctx(bl_ctx ctx);
+bl_status check_matrix(bl_ctx ctx, const bl_matrix* X, blk::Mat* m);
+void prof_mark(bl_ctx ctx, int slot);
+void prof_add(bl_ctx ctx, int slot, int which, double bytes);
+
+}  // namespace blapi
+
+#define HIPCHK(expr)                                                                                        \
+    do {                                                                                                    \
+        hipError_t e_ = (expr);                                                                             \
+        if (e_ != hipSuccess) return blapi::fail(ctx, BL_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define ENSURE(id, bytes, ptr)                                                  \
+    do {                                                                        \
+        void* p_;                                                               \
+        bl_status s_ = blapi::ensure(ctx, (id), (size_t)(bytes), &p_);          \
+        if (s_ != BL_OK) return s_;                                             \
+        (ptr) = (decltype(ptr))p_;                                              \
+    } while (0)

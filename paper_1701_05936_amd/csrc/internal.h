@@ -191,6 +191,63 @@ hipError_t launch_band(const int32_t* cols, const int64_t* len_dev, const double
 hipError_t launch_viol(const int32_t* cols, const int64_t* len_dev, const double* z, const uint8_t* in_s, uint8_t* inE,
                        double lam, uint32_t* nviol, int64_t p, hipStream_t st);
 
+// ---- batched form (batch.hip) ----
+constexpr int BNP = 64;          // problems per batch (right-hand-side columns of the shared contraction)
+constexpr int BCD_MAX = 7168;    // largest working set of a problem in the batched solve
+
+struct BatchScalars {
+    double sum_r, rss, y_mean, yy, lmax, sign_star;
+    int64_t jstar, n_rows, n_new, pool_size;
+    uint32_t n_viol;
+    int32_t sweeps, status, pad;
+};
+int64_t batch_pad(int64_t n_total);  // rows of the row-major right-hand sides (multiple of 64)
+// out[b*p + j] for j = cols[t]: mode 0 raw x_j' B[:, b]; mode 1 (x_j o x_j)' B[:, b];
+// mode 2 (x_j' B[:, b] - c_bj sum_r(b)) / (n_b s_bj)
+hipError_t launch_bscan(const Mat& mt, int mode, const int32_t* cols, const int64_t* len_dev, int64_t len_host,
+                        const double* B, int nprob, BatchScalars* bs, const double* c, const double* s,
+                        const uint8_t* keep, double* out, hipStream_t st);
+hipError_t launch_b_masks(const uint8_t* masks, int64_t n_total, int nprob, double* Mb, hipStream_t st);
+hipError_t launch_b_center_y(const uint8_t* masks, const double* Y, int64_t n_total, int nprob, double* Yt, double* R,
+                             BatchScalars* bs, hipStream_t st);
+hipError_t launch_b_sum_r(const double* R, int64_t n_total, int nprob, BatchScalars* bs, hipStream_t st);
+hipError_t launch_b_stats(const double* S1, const double* S2, int64_t p, int nprob, const BatchScalars* bs, double* c,
+                          double* s, uint8_t* keep, hipStream_t st);
+hipError_t launch_b_argmax(const double* a, const uint8_t* keep, int64_t p, int nprob, BatchScalars* bs,
+                           hipStream_t st);
+hipError_t launch_b_std_column(const Mat& mt, const uint8_t* masks, int nprob, const BatchScalars* bs, const double* c,
+                               const double* s, double* Bm, hipStream_t st);
+hipError_t launch_b_bedpp(int64_t p, int nprob, const double* a, const double* bb, const uint8_t* keep, bool bedpp,
+                          const BatchScalars* bs, const double* lam, uint8_t* safe, hipStream_t st);
+hipError_t launch_b_ssr(int64_t p, int nprob, const uint8_t* safe, const double* beta, const double* zprev, bool ssr,
+                        const double* thr, const uint8_t* want, uint8_t* strong, hipStream_t st);
+hipError_t launch_b_union(int64_t p, int nprob, const uint8_t* mask, uint8_t* out, hipStream_t st);
+hipError_t launch_b_viol(const int32_t* cols, const int64_t* len_dev, int64_t p, int nprob, const double* z,
+                         const uint8_t* in_s, uint8_t* inE, const double* lam, const uint8_t* want, BatchScalars* bs,
+                         hipStream_t st);
+size_t b_compact_scratch_bytes(int64_t p);
+hipError_t launch_b_compact(const uint8_t* mask, int64_t p, int nprob, const uint8_t* want, int32_t* out,
+                            int64_t* lens, void* scratch, hipStream_t st);
+hipError_t launch_b_pool_add(const int32_t* sets, const int64_t* lens, int64_t p, int nprob, const uint8_t* want,
+                             int32_t* pool_pos, int32_t* pool_list, BatchScalars* bs, hipStream_t st);
+hipError_t launch_b_commit(int nprob, const uint8_t* want, BatchScalars* bs, hipStream_t st);
+hipError_t launch_b_gram_update(const Mat& mt, const uint8_t* masks, int nprob, const int32_t* pool_list,
+                                const BatchScalars* bs, const double* c, const double* s, double* Gp, int64_t cap,
+                                int64_t max_P, int64_t max_N, const uint8_t* want, hipStream_t st);
+hipError_t launch_b_gather(const int32_t* sets, const int64_t* lens, int64_t p, int nprob, const uint8_t* want,
+                           const int32_t* pool_pos, const double* Gp, int64_t cap, const double* z, const double* beta,
+                           double* GE, int64_t ge_stride, double* g0, double* b0, int64_t max_m, hipStream_t st);
+hipError_t launch_b_gcd(const int32_t* sets, const int64_t* lens, int64_t p, int nprob, const uint8_t* want,
+                        const double* GE, int64_t ge_stride, const double* g0, const double* b0, double* b1,
+                        double* beta, const double* lam, double tol, int max_sweeps, BatchScalars* bs,
+                        hipStream_t st);
+hipError_t launch_b_r_update(const Mat& mt, const uint8_t* masks, const int32_t* sets, const int64_t* lens, int nprob,
+                             const uint8_t* want, const double* b0, const double* b1, const double* c,
+                             const double* s, double* R, hipStream_t st);
+hipError_t launch_b_record(const int32_t* sets, const int64_t* lens, int64_t p, int nprob, const double* beta,
+                           const double* c, const double* s, const BatchScalars* bs, const double* lam,
+                           LamStats* out, int k, int K, const int64_t* n_safe, hipStream_t st);
+
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t st);
 hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t st);
 hipError_t launch_or_u8(uint8_t* dst, const uint8_t* src, int64_t n, hipStream_t st);

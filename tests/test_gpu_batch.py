@@ -1,0 +1,114 @@
+"""Batched form: many problems (responses x cross-validation row subsets) over one X.
+
+Every problem's path is compared with the FP64 oracle run on that problem alone
+(its response, its row mask), to the same bar as the plain path: max |d beta|
+<= 1e-6 and relative objective difference <= 1e-8 on the problem's own
+standardized scale, equal active-set sizes and BEDPP survivor counts.
+"""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+import paper_1701_05936_amd as bl
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def check_against_oracle(res, X64, Y, masks, K, ratio, problems, check_safe=True):
+    assert res.k_done == K
+    beta = res.beta.cpu().numpy()
+    for b in problems:
+        ref = oracle.fit_path(X64, Y[b], K=K, ratio=ratio, tol=1e-13, mask=None if masks is None else masks[b])
+        assert ref.k_done == K
+        np.testing.assert_allclose(res.lam[b], ref.lam, rtol=1e-12)
+        d = np.abs(beta[b] - ref.beta).max()
+        rd = np.abs((res.obj[b] - ref.obj) / ref.obj).max()
+        print(f"problem {b}: max|d beta| {d:.2e}, max RD {rd:.2e}, active at end {ref.n_active[-1]}")
+        assert d <= 1e-6, b
+        assert rd <= 1e-8, b
+        np.testing.assert_array_equal(res.n_active[b], ref.n_active)
+        icpt, _ = ref.original_scale()
+        np.testing.assert_allclose(res.intercept[b], icpt, atol=1e-6 * max(1.0, abs(ref.ybar)))
+        if check_safe:
+            np.testing.assert_array_equal(res.n_safe[b], ref.n_safe)
+
+
+def cv_problem(n, p, nresp, nsub, seed_shift=0):
+    rec = datagen.RECIPES["c4"].scaled(n=n, p=p, nresp=nresp, nsub=nsub, seed=104 + seed_shift)
+    prob = datagen.make(rec)
+    X32 = prob.Xt                     # (p, n) float32
+    Y = np.repeat(prob.y, nsub, axis=0)   # problem b = t * nsub + s uses response t
+    masks = prob.masks
+    return rec, X32, Y, masks
+
+
+@pytest.mark.parametrize("n,p,nresp,nsub,K", [(1500, 4000, 8, 2, 20), (643, 1111, 32, 2, 12)])
+def test_batch_matches_oracle_per_problem(gpu_ctx, n, p, nresp, nsub, K):
+    rec, X32, Y, masks = cv_problem(n, p, nresp, nsub)
+    ratio = rec.lambda_min_ratio
+    res = bl.fit_path_batch(gpu_ctx, to_dev(X32), to_dev(Y), to_dev(masks), nlambda=K, lambda_min_ratio=ratio,
+                            tol=1e-10)
+    B = Y.shape[0]
+    problems = range(B) if B <= 16 else [0, 1, 17, 30, 45, B - 1]
+    check_against_oracle(res, X32.astype(np.float64), Y, masks, K, ratio, problems)
+
+
+@pytest.mark.parametrize("rule", [bl.SCREEN_NONE, bl.SCREEN_SSR, bl.SCREEN_BEDPP, bl.SCREEN_SSR_BEDPP])
+def test_batch_all_rules_f64_all_rows(gpu_ctx, rule):
+    rec = datagen.RECIPES["c1"].scaled(n=420, p=1300)
+    Xt = datagen.design(rec)
+    Y = np.stack([datagen.response(rec, Xt, t) for t in range(5)])
+    K, ratio = 25, 0.05
+    res = bl.fit_path_batch(gpu_ctx, to_dev(Xt), to_dev(Y), None, nlambda=K, lambda_min_ratio=ratio, rule=rule,
+                            tol=1e-10)
+    check_against_oracle(res, Xt, Y, None, K, ratio, range(5),
+                         check_safe=rule in (bl.SCREEN_BEDPP, bl.SCREEN_SSR_BEDPP))
+    assert (res.sweeps[:, 0] == 0).all() and (res.n_active[:, 0] == 0).all()
+
+
+def test_batch_equals_single_problem_batches(gpu_ctx):
+    """A problem's path does not depend on which other problems share the batch."""
+    rec, X32, Y, masks = cv_problem(900, 1500, 4, 2, seed_shift=7)
+    Xd = to_dev(X32)
+    K = 15
+    full = bl.fit_path_batch(gpu_ctx, Xd, to_dev(Y), to_dev(masks), nlambda=K, lambda_min_ratio=0.1, tol=1e-10)
+    for b in (0, 5):
+        one = bl.fit_path_batch(gpu_ctx, Xd, to_dev(Y[b:b + 1]), to_dev(masks[b:b + 1]), nlambda=K,
+                                lambda_min_ratio=0.1, tol=1e-10)
+        np.testing.assert_allclose(one.beta[0].cpu().numpy(), full.beta[b].cpu().numpy(), atol=1e-9)
+        np.testing.assert_array_equal(one.n_active[0], full.n_active[b])
+
+
+def test_batch_is_deterministic(gpu_ctx):
+    rec, X32, Y, masks = cv_problem(700, 900, 6, 2, seed_shift=3)
+    Xd, Yd, Md = to_dev(X32), to_dev(Y), to_dev(masks)
+    r1 = bl.fit_path_batch(gpu_ctx, Xd, Yd, Md, nlambda=12, lambda_min_ratio=0.1, tol=1e-10)
+    r2 = bl.fit_path_batch(gpu_ctx, Xd, Yd, Md, nlambda=12, lambda_min_ratio=0.1, tol=1e-10)
+    assert torch.equal(r1.beta, r2.beta)
+    np.testing.assert_array_equal(r1.obj, r2.obj)
+
+
+def test_batch_rejects_invalid_inputs(gpu_ctx):
+    rec, X32, Y, masks = cv_problem(200, 150, 2, 2)
+    Xd, Yd = to_dev(X32), to_dev(Y)
+    with pytest.raises(bl.BLError) as e:      # more than 64 problems
+        bl.fit_path_batch(gpu_ctx, Xd, to_dev(np.tile(Y, (17, 1))), None, nlambda=5)
+    assert e.value.status == bl.BL_ERR_INVALID
+    bad = masks.copy()
+    bad[1] = 0                                # a problem without rows
+    with pytest.raises(bl.BLError) as e:
+        bl.fit_path_batch(gpu_ctx, Xd, Yd, to_dev(bad), nlambda=5)
+    assert e.value.status == bl.BL_ERR_INVALID
+    with pytest.raises(bl.BLError) as e:      # int8 storage is the precision form's, not the batch's
+        bl.fit_path_batch(gpu_ctx, to_dev(np.zeros((150, 200), dtype=np.int8)), Yd, None, nlambda=5)
+    assert e.value.status == bl.BL_ERR_UNSUPPORTED
+    with pytest.raises(bl.BLError) as e:
+        bl.fit_path_batch(gpu_ctx, Xd, Yd, None, nlambda=0)
+    assert e.value.status == bl.BL_ERR_INVALID
