@@ -56,7 +56,11 @@ typedef enum {
     BL_SCREEN_NONE = 0,       /* working set = every kept feature                                   */
     BL_SCREEN_SSR = 1,        /* sequential strong rule + check over all kept features              */
     BL_SCREEN_BEDPP = 2,      /* safe rule only: working set = BEDPP survivors, check over them     */
-    BL_SCREEN_SSR_BEDPP = 3   /* hybrid (default): strong rule and check restricted to BEDPP survivors */
+    BL_SCREEN_SSR_BEDPP = 3,  /* hybrid (default): strong rule and check restricted to BEDPP survivors */
+    BL_SCREEN_LEARNED = 4     /* hybrid + screening network: from the fourth lambda on, a strong-rule candidate
+                                 outside the previous active set enters the working set only if the network
+                                 scores it at or above opts->mlp_tau; the check over all BEDPP survivors is unchanged
+                                 and adds every violator back, so the solution is the hybrid rule's       */
 } bl_screen_rule;
 
 /* Design matrix.  X must be 16-byte aligned when ldx*sizeof(element) is a multiple of 16;
@@ -192,6 +196,17 @@ typedef struct {
     int32_t max_sweeps;        /* per CD solve                                                */
     int32_t max_rounds;        /* CD + check rounds per lambda before giving up (>= 1)        */
     int32_t precision;         /* bl_precision of the check scans                              */
+    /* learned form (rule BL_SCREEN_LEARNED): network parameters and score threshold in (0, 1)   */
+    const float* mlp;          /* DEVICE [BL_MLP_NPARAMS] or NULL                              */
+    double mlp_tau;
+    /* training records (any rule with the strong rule): for k >= 3 and every strong-rule candidate
+     * j outside the active set of lambda_{k-1}, features
+     *   ( |z_j(k-1)|/lambda_{k-1}, |z_j(k-2)|/lambda_{k-2}, |z_j(k-3)|/lambda_{k-3}, lambda_k/lambda_{k-1} )
+     * (a |z| that was not scanned at that lambda counts as 0) and label 1 if beta_j(lambda_k) != 0.
+     * Appended in lambda order, feature order within a lambda, until rec_cap records.            */
+    float* rec_feat;           /* DEVICE [rec_cap x 4] or NULL                                  */
+    float* rec_label;          /* DEVICE [rec_cap] or NULL                                      */
+    int64_t rec_cap;
 } bl_path_opts;
 
 /* Results of bl_fit_path.  Host arrays have K entries; any pointer may be NULL (not written). */
@@ -217,6 +232,7 @@ typedef struct {
     int64_t jstar;             /* out                                                          */
     int32_t k_done;            /* out: lambdas finished (results valid for k < k_done)         */
     double time_ms;            /* out: wall time of the call                                   */
+    int64_t n_recorded;        /* out: training records written (opts->rec_feat)              */
 } bl_path_result;
 
 /*
@@ -270,6 +286,50 @@ bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_batch* batc
                             bl_batch_result* res);
 
 /*
+ * Screening network of the learned form (the paper has none; it stands beside the strong rule,
+ * which stays the fallback, and the exact check, which stays the judge).
+ *   input f (4 floats, as recorded above) -> h1 = relu(W1 f + b1) (64) -> h2 = relu(W2 h1 + b2) (64)
+ *   -> logit o = w3 . h2 + b3 -> score sigmoid(o).
+ * Parameters: FP32 vector of BL_MLP_NPARAMS = 4545 in the order W1[64][4], b1[64], W2[64][64], b2[64],
+ * w3[64], b3 (row-major).  All arrays DEVICE, caller-owned; m < 2^31.
+ */
+#define BL_MLP_HIDDEN 64
+#define BL_MLP_NPARAMS (BL_MLP_HIDDEN * BL_MLP_HIDDEN + 7 * BL_MLP_HIDDEN + 1)
+
+/* prob[i] = score of feat[4i .. 4i+3]. */
+bl_status bl_mlp_forward(bl_ctx ctx, const float* feat, int64_t m, const float* params, float* prob);
+
+/* Mean binary cross-entropy L = (1/m) sum_i [log(1 + e^{o_i}) - y_i o_i] over all m samples and its
+ * gradient (grad [BL_MLP_NPARAMS] device, same layout as params); *loss (host) may be NULL.
+ * label[i] in {0, 1}. */
+bl_status bl_mlp_loss_grad(bl_ctx ctx, const float* feat, const float* label, int64_t m, const float* params,
+                           float* grad, double* loss);
+
+typedef struct {
+    int32_t epochs;            /* passes over the records                                         */
+    int32_t batch;             /* records per Adam step, multiple of 128                          */
+    double lr, beta1, beta2, eps;  /* Adam (Kingma and Ba): step lr m^/(sqrt(v^) + eps)           */
+    uint64_t seed;             /* order of the records within each epoch                          */
+    double target_recall;      /* tau: the largest 1/4096-grid score such that at least this
+                                  fraction of the positive records scores at or above it        */
+} bl_mlp_train_opts;
+
+typedef struct {
+    double loss_first;         /* mean loss over the first epoch's steps                          */
+    double loss_last;          /* mean loss over the last epoch's steps                           */
+    double tau;                /* threshold for opts->mlp_tau                                     */
+    double recall;             /* fraction of positive records scored >= tau                      */
+    double neg_pass;           /* fraction of negative records scored >= tau                      */
+    int64_t steps;
+    double time_ms;
+} bl_mlp_train_result;
+
+/* Adam on the mean cross-entropy, params (device) trained in place from their initial values.
+ * The steps of an epoch replay a captured HIP graph. */
+bl_status bl_mlp_train(bl_ctx ctx, const float* feat, const float* label, int64_t m, float* params,
+                       const bl_mlp_train_opts* opts, bl_mlp_train_result* res);
+
+/*
  * Kernel timing (diagnostics for measurement).  When enabled, bl_fit_path records HIP
  * events on the context stream around each launch of the scan, the CD solve and the
  * column statistics, and accumulates per kernel: launches, summed duration and the
@@ -282,16 +342,19 @@ bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_batch* batc
  *   gram      Gram entries of new pool members and the gather of the working set's Gram
  *   rupdate   residual update after a solve: m x n_total x sizeof(element)
  *   recheck   precision form: residual pieces, error band and FP64 re-scans of flagged and set columns
+ *   bscan     batched form: the shared X'R contraction, columns x n_total x sizeof(element) + n_total x nprob x 8
+ *             bytes and 2 x columns x n_total x nprob flops per launch
  * bl_profile(ctx, 1) enables and resets the counters, bl_profile(ctx, 0) disables.
  */
 typedef struct {
     int64_t launches;
     double total_ms;
     double bytes;
+    double flops;              /* algorithmic floating-point operations (matrix-core scans), else 0 */
 } bl_kernel_profile;
 
 enum { BL_PROF_SCAN = 0, BL_PROF_CD = 1, BL_PROF_COLSTATS = 2, BL_PROF_GRAM = 3, BL_PROF_RUPDATE = 4,
-       BL_PROF_RECHECK = 5, BL_PROF_COUNT = 6 };
+       BL_PROF_RECHECK = 5, BL_PROF_BSCAN = 6, BL_PROF_COUNT = 7 };
 
 bl_status bl_profile(bl_ctx ctx, int enable);
 bl_status bl_profile_get(bl_ctx ctx, int kernel, bl_kernel_profile* out);

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libbl.so")
 
 BL_OK, BL_ERR_INVALID, BL_ERR_NOMEM, BL_ERR_DEVICE, BL_ERR_NOT_CONVERGED, BL_ERR_UNSUPPORTED = range(6)
 X_F64, X_F32, X_I8 = 0, 1, 2
-SCREEN_NONE, SCREEN_SSR, SCREEN_BEDPP, SCREEN_SSR_BEDPP = 0, 1, 2, 3
+SCREEN_NONE, SCREEN_SSR, SCREEN_BEDPP, SCREEN_SSR_BEDPP, SCREEN_LEARNED = 0, 1, 2, 3, 4
 PREC_FP64, PREC_BF16X3 = 0, 1
 
 _STATUS_NAMES = {0: "BL_OK", 1: "BL_ERR_INVALID", 2: "BL_ERR_NOMEM", 3: "BL_ERR_DEVICE",
@@ -31,8 +31,10 @@ _STATUS_NAMES = {0: "BL_OK", 1: "BL_ERR_INVALID", 2: "BL_ERR_NOMEM", 3: "BL_ERR_
 # exported C symbols (kept in step with include/bl.h)
 EXPORTS = ("bl_create", "bl_destroy", "bl_last_error", "bl_device_info", "bl_standardize", "bl_lambda_max",
            "bl_bedpp_setup", "bl_screen", "bl_cd_solve", "bl_kkt_check", "bl_scan", "bl_fit_path",
-           "bl_fit_path_batch", "bl_profile", "bl_profile_get")
-PROF_SCAN, PROF_CD, PROF_COLSTATS, PROF_GRAM, PROF_RUPDATE, PROF_RECHECK = 0, 1, 2, 3, 4, 5
+           "bl_fit_path_batch", "bl_mlp_forward", "bl_mlp_loss_grad", "bl_mlp_train", "bl_profile", "bl_profile_get")
+MLP_HIDDEN = 64
+MLP_NPARAMS = MLP_HIDDEN * MLP_HIDDEN + 7 * MLP_HIDDEN + 1
+PROF_SCAN, PROF_CD, PROF_COLSTATS, PROF_GRAM, PROF_RUPDATE, PROF_RECHECK, PROF_BSCAN = 0, 1, 2, 3, 4, 5, 6
 
 
 class BLError(RuntimeError):
@@ -53,13 +55,16 @@ class _ScreenState(ctypes.Structure):
 
 
 class _KernelProfile(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+    _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("flops", ctypes.c_double)]
 
 
 class _PathOpts(ctypes.Structure):
     _fields_ = [("nlambda", ctypes.c_int32), ("lambda_min_ratio", ctypes.c_double), ("lambda_", ctypes.c_void_p),
                 ("rule", ctypes.c_int32), ("tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
-                ("max_rounds", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("max_rounds", ctypes.c_int32), ("precision", ctypes.c_int32), ("mlp", ctypes.c_void_p),
+                ("mlp_tau", ctypes.c_double), ("rec_feat", ctypes.c_void_p), ("rec_label", ctypes.c_void_p),
+                ("rec_cap", ctypes.c_int64)]
 
 
 class _PathResult(ctypes.Structure):
@@ -69,7 +74,19 @@ class _PathResult(ctypes.Structure):
                 ("rounds", ctypes.c_void_p), ("n_active", ctypes.c_void_p), ("n_strong", ctypes.c_void_p),
                 ("n_safe", ctypes.c_void_p), ("n_viol", ctypes.c_void_p), ("n_scanned", ctypes.c_void_p),
                 ("n_recheck", ctypes.c_void_p), ("y_mean", ctypes.c_double), ("lambda_max", ctypes.c_double), ("jstar", ctypes.c_int64),
-                ("k_done", ctypes.c_int32), ("time_ms", ctypes.c_double)]
+                ("k_done", ctypes.c_int32), ("time_ms", ctypes.c_double), ("n_recorded", ctypes.c_int64)]
+
+
+class _MlpTrainOpts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("target_recall", ctypes.c_double)]
+
+
+class _MlpTrainResult(ctypes.Structure):
+    _fields_ = [("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double), ("tau", ctypes.c_double),
+                ("recall", ctypes.c_double), ("neg_pass", ctypes.c_double), ("steps", ctypes.c_int64),
+                ("time_ms", ctypes.c_double)]
 
 
 class _Batch(ctypes.Structure):
@@ -112,6 +129,9 @@ def load_library(path: str = LIB_PATH):
     L.bl_scan.argtypes = [vp, P(_Matrix), vp, vp, vp, vp, i64, i32, vp, vp]
     L.bl_fit_path.argtypes = [vp, P(_Matrix), vp, P(_PathOpts), P(_PathResult)]
     L.bl_fit_path_batch.argtypes = [vp, P(_Matrix), P(_Batch), P(_PathOpts), P(_BatchResult)]
+    L.bl_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+    L.bl_mlp_loss_grad.argtypes = [vp, vp, vp, i64, vp, vp, P(dbl)]
+    L.bl_mlp_train.argtypes = [vp, vp, vp, i64, vp, P(_MlpTrainOpts), P(_MlpTrainResult)]
     L.bl_profile.argtypes = [vp, ctypes.c_int]
     L.bl_profile_get.argtypes = [vp, ctypes.c_int, P(_KernelProfile)]
     for name in EXPORTS:
@@ -198,7 +218,7 @@ class Context:
     def profile_get(self, kernel: int) -> dict:
         kp = _KernelProfile()
         self._check(load_library().bl_profile_get(self._h, kernel, ctypes.byref(kp)))
-        return {"launches": kp.launches, "total_ms": kp.total_ms, "bytes": kp.bytes}
+        return {"launches": kp.launches, "total_ms": kp.total_ms, "bytes": kp.bytes, "flops": kp.flops}
 
     def device_info(self):
         n = ctypes.c_int()
@@ -319,11 +339,15 @@ class PathResult:
     time_ms: float
     status: int
     message: str
+    n_recorded: int = 0
 
 
 def fit_path(ctx: Context, Xt, y, nlambda=100, lambda_min_ratio=0.1, lambdas=None, rule=SCREEN_SSR_BEDPP,
              tol=1e-8, max_sweeps=100000, max_rounds=100, row_mask=None, n_total=None, want_beta=True,
-             raise_on_error=True, precision=PREC_FP64) -> PathResult:
+             raise_on_error=True, precision=PREC_FP64, mlp=None, mlp_tau=0.0, rec_feat=None, rec_label=None
+             ) -> PathResult:
+    """Whole path.  Learned rule: rule=SCREEN_LEARNED with mlp (float32 device [MLP_NPARAMS]) and mlp_tau.
+    Training records: rec_feat (float32 device [cap, 4]) and rec_label (float32 device [cap])."""
     M = matrix(Xt, n_total, row_mask)
     K = int(nlambda)
     p = M.p
@@ -340,20 +364,30 @@ def fit_path(ctx: Context, Xt, y, nlambda=100, lambda_min_ratio=0.1, lambdas=Non
     if lambdas is not None:
         lam_in = np.ascontiguousarray(lambdas, dtype=np.float64)
         assert lam_in.size == K
+    rec_cap = 0
+    if rec_feat is not None:
+        if rec_label is None or rec_feat.dtype != torch.float32 or rec_label.dtype != torch.float32 \
+                or rec_feat.dim() != 2 or rec_feat.shape[1] != 4 or rec_label.numel() < rec_feat.shape[0]:
+            raise ValueError("rec_feat (cap, 4) and rec_label (cap,) must be float32 device tensors")
+        rec_cap = int(rec_feat.shape[0])
+    if mlp is not None and (mlp.dtype != torch.float32 or mlp.numel() != MLP_NPARAMS):
+        raise ValueError(f"mlp must be float32 with {MLP_NPARAMS} parameters")
     opts = _PathOpts(K, float(lambda_min_ratio), lam_in.ctypes.data if lam_in is not None else None, int(rule),
-                     float(tol), int(max_sweeps), int(max_rounds), int(precision))
+                     float(tol), int(max_sweeps), int(max_rounds), int(precision), _ptr(mlp), float(mlp_tau),
+                     _ptr(rec_feat), _ptr(rec_label), rec_cap)
     res = _PathResult(_ptr(beta), _ptr(c), _ptr(s), _ptr(keep), host["lam"].ctypes.data,
                       host["intercept"].ctypes.data, host["rss"].ctypes.data, host["obj"].ctypes.data,
                       host["sweeps"].ctypes.data, host["rounds"].ctypes.data, host["n_active"].ctypes.data,
                       host["n_strong"].ctypes.data, host["n_safe"].ctypes.data, host["n_viol"].ctypes.data,
-                      host["n_scanned"].ctypes.data, host["n_recheck"].ctypes.data, 0.0, 0.0, 0, 0, 0.0)
+                      host["n_scanned"].ctypes.data, host["n_recheck"].ctypes.data, 0.0, 0.0, 0, 0, 0.0, 0)
     st = load_library().bl_fit_path(ctx.handle, ctypes.byref(M), _ptr(y), ctypes.byref(opts), ctypes.byref(res))
     msg = load_library().bl_last_error(ctx.handle).decode(errors="replace") if st != BL_OK else ""
     if st != BL_OK and raise_on_error:
         raise BLError(st, msg)
     return PathResult(host["lam"], beta, c, s, keep, host["intercept"], host["rss"], host["obj"], host["sweeps"],
                       host["rounds"], host["n_active"], host["n_strong"], host["n_safe"], host["n_viol"],
-                      host["n_scanned"], host["n_recheck"], res.y_mean, res.lambda_max, res.jstar, res.k_done, res.time_ms, st, msg)
+                      host["n_scanned"], host["n_recheck"], res.y_mean, res.lambda_max, res.jstar, res.k_done, res.time_ms, st, msg,
+                      res.n_recorded)
 
 
 MAX_BATCH = 64
@@ -411,3 +445,58 @@ def fit_path_batch(ctx: Context, Xt, Y, masks=None, nlambda=100, lambda_min_rati
     return BatchResult(host["lam"], beta, host["intercept"], host["rss"], host["obj"], host["sweeps"],
                        host["rounds"], host["n_active"], host["n_strong"], host["n_safe"], host["n_viol"],
                        res.k_done, res.time_ms, st, msg)
+
+
+# ---- screening network of the learned form ----
+
+def mlp_init(seed: int = 0) -> np.ndarray:
+    """He-initialised parameter vector (float32, layout W1[64][4], b1, W2[64][64], b2, w3, b3)."""
+    rng = np.random.default_rng(seed)
+    H = MLP_HIDDEN
+    W1 = rng.normal(0.0, np.sqrt(2.0 / 4), size=(H, 4))
+    W2 = rng.normal(0.0, np.sqrt(2.0 / H), size=(H, H))
+    w3 = rng.normal(0.0, np.sqrt(1.0 / H), size=H)
+    return np.concatenate([W1.ravel(), np.zeros(H), W2.ravel(), np.zeros(H), w3, np.zeros(1)]).astype(np.float32)
+
+
+def _check_f32(t, name, n=None):
+    if t.dtype != torch.float32:
+        raise ValueError(f"{name} must be float32")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements")
+
+
+def mlp_forward(ctx: Context, feat, params):
+    _check_f32(feat, "feat")
+    _check_f32(params, "params", MLP_NPARAMS)
+    m = feat.numel() // 4
+    prob = torch.empty(m, dtype=torch.float32, device=feat.device)
+    ctx._check(load_library().bl_mlp_forward(ctx.handle, _ptr(feat), m, _ptr(params), _ptr(prob)))
+    return prob
+
+
+def mlp_loss_grad(ctx: Context, feat, label, params):
+    _check_f32(feat, "feat")
+    _check_f32(label, "label")
+    _check_f32(params, "params", MLP_NPARAMS)
+    m = feat.numel() // 4
+    grad = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=feat.device)
+    loss = ctypes.c_double()
+    ctx._check(load_library().bl_mlp_loss_grad(ctx.handle, _ptr(feat), _ptr(label), m, _ptr(params), _ptr(grad),
+                                               ctypes.byref(loss)))
+    return loss.value, grad
+
+
+def mlp_train(ctx: Context, feat, label, params, epochs=20, batch=4096, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+              seed=0, target_recall=0.995) -> dict:
+    """Trains params (float32 device, in place); returns losses, the threshold tau and its recall."""
+    _check_f32(feat, "feat")
+    _check_f32(label, "label")
+    _check_f32(params, "params", MLP_NPARAMS)
+    m = feat.numel() // 4
+    opts = _MlpTrainOpts(int(epochs), int(batch), float(lr), float(beta1), float(beta2), float(eps), int(seed),
+                         float(target_recall))
+    res = _MlpTrainResult()
+    ctx._check(load_library().bl_mlp_train(ctx.handle, _ptr(feat), _ptr(label), m, _ptr(params), ctypes.byref(opts),
+                                           ctypes.byref(res)))
+    return {k: getattr(res, k) for k, _ in _MlpTrainResult._fields_}

@@ -7,7 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbl.so")
-SOURCES = ["csrc/kernels.hip", "csrc/gram_cd.hip", "csrc/lowp.hip", "csrc/batch.hip", "csrc/api.cpp", "csrc/api_batch.cpp"]
+SOURCES = ["csrc/kernels.hip", "csrc/gram_cd.hip", "csrc/lowp.hip", "csrc/batch.hip", "csrc/mlp.hip", "csrc/api.cpp", "csrc/api_batch.cpp",
+           "csrc/api_mlp.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -113,13 +113,14 @@ void prof_mark(bl_ctx ctx, int slot) {
     if (ctx->prof) (void)hipEventRecord(ctx->ev[slot], ctx->stream);
 }
 // after the stream has been synchronized: add the pair (slot, slot+1) to kernel `which`
-void prof_add(bl_ctx ctx, int slot, int which, double bytes) {
+void prof_add(bl_ctx ctx, int slot, int which, double bytes, double flops) {
     if (!ctx->prof) return;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, ctx->ev[slot], ctx->ev[slot + 1]) == hipSuccess) {
         ctx->kp[which].launches += 1;
         ctx->kp[which].total_ms += ms;
         ctx->kp[which].bytes += bytes;
+        ctx->kp[which].flops += flops;
     }
 }
 
@@ -309,6 +310,7 @@ void bl_destroy(bl_ctx c) {
     if (c->gpool) (void)hipFree(c->gpool);
     if (c->bgpool) (void)hipFree(c->bgpool);
     if (c->bpinned) (void)hipHostFree(c->bpinned);
+    if (c->aux) (void)hipStreamDestroy(c->aux);
     if (c->sc) (void)hipFree(c->sc);
     if (c->sc_host) (void)hipHostFree(c->sc_host);
     delete c;
@@ -324,7 +326,7 @@ bl_status bl_profile(bl_ctx ctx, int enable) {
             if (!e) HIPCHK(hipEventCreate(&e));
     }
     ctx->prof = enable != 0;
-    for (auto& k : ctx->kp) k = bl_kernel_profile{0, 0.0, 0.0};
+    for (auto& k : ctx->kp) k = bl_kernel_profile{0, 0.0, 0.0, 0.0};
     return BL_OK;
 }
 
@@ -440,6 +442,8 @@ bl_status bl_screen(bl_ctx ctx, const bl_screen_state* st, double lambda_k, doub
     if (st->p < 1 || st->p > 2147483647LL) return fail(ctx, BL_ERR_INVALID, "bad p");
     if (!st->keep) return fail(ctx, BL_ERR_INVALID, "keep must be non-NULL");
     const int rule = st->rule;
+    if (rule == BL_SCREEN_LEARNED)
+        return fail(ctx, BL_ERR_UNSUPPORTED, "the learned rule needs the path's z history: it runs inside bl_fit_path");
     if (rule < BL_SCREEN_NONE || rule > BL_SCREEN_SSR_BEDPP) return fail(ctx, BL_ERR_INVALID, "unknown rule");
     const bool bedpp = rule == BL_SCREEN_BEDPP || rule == BL_SCREEN_SSR_BEDPP;
     const bool ssr = rule == BL_SCREEN_SSR || rule == BL_SCREEN_SSR_BEDPP;
@@ -630,11 +634,22 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
                 return fail(ctx, BL_ERR_INVALID, "user lambda must be non-increasing");
         }
     }
-    if (opts->rule < BL_SCREEN_NONE || opts->rule > BL_SCREEN_SSR_BEDPP) return fail(ctx, BL_ERR_INVALID, "unknown rule");
+    if (opts->rule < BL_SCREEN_NONE || opts->rule > BL_SCREEN_LEARNED) return fail(ctx, BL_ERR_INVALID, "unknown rule");
     if (!(opts->tol > 0.0) || opts->max_sweeps < 1 || opts->max_rounds < 1)
         return fail(ctx, BL_ERR_INVALID, "tol > 0, max_sweeps >= 1 and max_rounds >= 1 are required");
-    const bool bedpp = opts->rule == BL_SCREEN_BEDPP || opts->rule == BL_SCREEN_SSR_BEDPP;
-    const bool ssr = opts->rule == BL_SCREEN_SSR || opts->rule == BL_SCREEN_SSR_BEDPP;
+    const bool learned = opts->rule == BL_SCREEN_LEARNED;
+    const bool bedpp = opts->rule == BL_SCREEN_BEDPP || opts->rule == BL_SCREEN_SSR_BEDPP || learned;
+    const bool ssr = opts->rule == BL_SCREEN_SSR || opts->rule == BL_SCREEN_SSR_BEDPP || learned;
+    if (learned && (!opts->mlp || !(opts->mlp_tau >= 0.0 && opts->mlp_tau < 1.0)))
+        return fail(ctx, BL_ERR_INVALID, "the learned rule needs opts->mlp and 0 <= mlp_tau < 1");
+    const bool recording = opts->rec_cap > 0;
+    if (recording && (!opts->rec_feat || !opts->rec_label))
+        return fail(ctx, BL_ERR_INVALID, "rec_cap > 0 needs rec_feat and rec_label");
+    if (recording && !ssr) return fail(ctx, BL_ERR_INVALID, "training records need a rule with the strong rule");
+    res->n_recorded = 0;
+    const bool history = learned || recording;
+    const float tau_logit = learned && opts->mlp_tau > 0.0 ? (float)std::log(opts->mlp_tau / (1.0 - opts->mlp_tau))
+                                                           : -INFINITY;
     if (opts->precision != BL_PREC_FP64 && opts->precision != BL_PREC_BF16X3)
         return fail(ctx, BL_ERR_INVALID, "unknown precision");
     const bool lowp = opts->precision == BL_PREC_BF16X3;
@@ -670,6 +685,18 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
     if (res->center) c = res->center; else ENSURE(B_C, p * 8, c);
     if (res->scale) sc_ = res->scale; else ENSURE(B_S, p * 8, sc_);
     if (res->keep) keep = res->keep; else ENSURE(B_KEEP, p, keep);
+    float* zh = nullptr;          // |z|/lambda at the last three lambda values, slot k mod 3
+    uint8_t* cand = nullptr;      // strong-rule candidates outside the previous active set
+    int32_t* lC = nullptr;
+    int64_t* recn = nullptr;
+    if (history) {
+        ENSURE(B_ZH, (size_t)3 * p * 4, zh);
+        ENSURE(B_RECN, 8, recn);
+    }
+    if (recording) {
+        ENSURE(B_CAND, p, cand);
+        ENSURE(B_LC, p * 4, lC);
+    }
     __bf16* pieces = nullptr;
     uint8_t* flag = nullptr;
     int32_t* lB = nullptr;
@@ -764,9 +791,14 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
     HIPCHK(launch_bedpp(p, a, b, keep, bedpp, lmax, sgn, lam[0], bedpp_rhs(lmax, lam[0], v), safe_cur, st));
     HIPCHK(launch_compact(safe_cur, p, lT, len_cur, scr, st));
     int k_first = 0;
+    if (history) {
+        HIPCHK(launch_fill_u8((uint8_t*)zh, 0, (int64_t)3 * p * 4, st));
+        HIPCHK(hipMemsetAsync(recn, 0, 8, st));
+    }
     if (lam[0] >= lmax) {
         HIPCHK(launch_record(nullptr, lens + 3, len_cur, lens + 3, beta, c, sc_, ctx->sc, lam[0], stats + 0, st));
         if (res->beta) HIPCHK(hipMemcpyAsync(res->beta, beta, p * 8, hipMemcpyDeviceToDevice, st));
+        if (history) HIPCHK(launch_zhist_keep(keep, p, a, lam[0], zh, st));   // z at lambda_max is a
         k_first = 1;
     }
     for (int k = k_first; k < K; ++k) {
@@ -784,6 +816,10 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         HIPCHK(launch_compact(scan_mask, p, lT, len_next, scr, st));
         // working set E_k
         HIPCHK(launch_ssr(p, safe_cur, nullptr, beta, zprev, ssr, 2.0 * lk - lprev, strong, st));
+        const int s1 = (k + 2) % 3, s2 = (k + 1) % 3, s3 = k % 3;   // slots of lambda_{k-1}, _{k-2}, _{k-3}
+        if (history && k >= 3)
+            HIPCHK(launch_learned(strong, beta, zh, p, s1, s2, s3, (float)(lk / lam[k - 1]), opts->mlp, tau_logit,
+                                  learned ? 1 : 0, cand, st));
         HIPCHK(launch_compact(strong, p, lE, lens + 0, scr, st));
         int rounds = 0;
         int64_t viol_total = 0;
@@ -900,6 +936,16 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         h_recheck[k] = recheck_total;
         HIPCHK(launch_record(lE, lens + 0, len_cur, len_next, beta, c, sc_, ctx->sc, lk, stats + k, st));
         if (res->beta) HIPCHK(hipMemcpyAsync(res->beta + (size_t)k * p, beta, p * 8, hipMemcpyDeviceToDevice, st));
+        if (recording && k >= 3) {
+            HIPCHK(launch_compact(cand, p, lC, lens + 6, scr, st));
+            HIPCHK(launch_rec_feat(lC, lens + 6, zh, p, s1, s2, s3, (float)(lk / lam[k - 1]), beta, opts->rec_cap,
+                                   recn, opts->rec_feat, opts->rec_label, st));
+        }
+        if (history) {   // slot k mod 3 <- |z(lambda_k)| / lambda_k over the scanned columns
+            float* slot = zh + (size_t)(k % 3) * p;
+            HIPCHK(launch_fill_u8((uint8_t*)slot, 0, p * 4, st));
+            HIPCHK(launch_zhist(lT, len_next, 0, zcur, lk, slot, p, st));
+        }
         res->k_done = k + 1;
         // the scan at lambda_k is the strong-rule input at lambda_{k+1}
         zprev = zcur;
@@ -923,6 +969,11 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         if (res->n_recheck) res->n_recheck[k] = h_recheck[k];
         if (res->n_safe) res->n_safe[k] = hs[k].n_safe;
         if (res->n_strong) res->n_strong[k] = hs[k].n_strong;
+    }
+    if (recording) {
+        HIPCHK(hipMemcpyAsync(&ctx->sc_host->stage, recn, 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        res->n_recorded = ctx->sc_host->stage;
     }
     res->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     return final_status;

@@ -163,7 +163,7 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
     HIPCHK(launch_b_argmax(a, keep, p, NB, bs, st));
     if ((s = read_bs())) return s;
     prof_add(ctx, 0, BL_PROF_COLSTATS, 2.0 * p * nt * es);
-    prof_add(ctx, 2, BL_PROF_SCAN, (double)p * nt * es);
+    prof_add(ctx, 2, BL_PROF_BSCAN, (double)p * nt * es + (double)nt * NB * 8.0, 2.0 * p * nt * NB);
     std::vector<double> lmax(NB);
     for (int b = 0; b < NB; ++b) {
         const BatchScalars& h = hp->bs[b];
@@ -182,7 +182,7 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
         prof_mark(ctx, 3);
         HIPCHK(launch_b_sum_r(R, nt, NB, bs, st));    // back to the residual's sum and ||y~||^2
         HIPCHK(hipStreamSynchronize(st));
-        prof_add(ctx, 2, BL_PROF_SCAN, (double)p * nt * es);
+        prof_add(ctx, 2, BL_PROF_BSCAN, (double)p * nt * es + (double)nt * NB * 8.0, 2.0 * p * nt * NB);
     }
     // lambda grids (own lambda_max per problem) and strong-rule thresholds, resident on the device
     std::vector<double> lam((size_t)NB * K), lg((size_t)(K + 1) * BNP, 0.0), tg((size_t)K * BNP, 0.0);
@@ -278,7 +278,8 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
             for (int b = 0; b < NB; ++b)
                 if (act[b]) cd_bytes += (double)hp->bs[b].sweeps * hp->lens[b] * hp->lens[b] * 8.0;
             prof_add(ctx, 6, BL_PROF_CD, cd_bytes);
-            prof_add(ctx, 2, BL_PROF_SCAN, (double)hp->lenT * nt * es + (double)npad * BNP * 8.0);
+            prof_add(ctx, 2, BL_PROF_BSCAN, (double)hp->lenT * nt * es + (double)nt * NB * 8.0,
+                     2.0 * hp->lenT * nt * NB);
             bool any = false;
             for (int b = 0; b < NB; ++b) {
                 if (!act[b]) continue;

@@ -31,6 +31,7 @@ struct bl_ctx_s {
     int bpool_np = 0;                    // problems the batched pools were allocated for
     double* bgpool = nullptr;
     void* bpinned = nullptr;            // pinned host staging of the batched driver
+    hipStream_t aux = nullptr;          // library-owned stream for captured graphs (network training)
     // kernel timing
     bool prof = false;
     hipEvent_t ev[10] = {};
@@ -48,6 +49,8 @@ enum BufId {
     BB_MASKS, BB_MB, BB_Y, BB_YT, BB_R, BB_B, BB_S1, BB_S2, BB_C, BB_S, BB_KEEP, BB_A, BB_BB, BB_Z0, BB_Z1, BB_SAFE,
     BB_SAFEN, BB_STRONG, BB_UNION, BB_LT, BB_LE, BB_LENS, BB_LAM, BB_THR, BB_WANT, BB_BS, BB_BETA, BB_POS, BB_LIST,
     BB_GE, BB_G0, BB_B0, BB_B1, BB_STATS, BB_CMP, BB_LSAFE, BB_SAFECNT, BB_WANTALL,
+    // learned form and its network
+    B_ZH, B_CAND, B_RECN, B_LC, M_PART, M_LOSSP, M_MOM, M_VEL, M_STEP, M_PERM, M_LOSSH, M_PROB, M_HIST,
     B_COUNT
 };
 
@@ -57,7 +60,7 @@ int elem_bytes(int xtype);
 bl_status check_ctx(bl_ctx ctx);
 bl_status check_matrix(bl_ctx ctx, const bl_matrix* X, blk::Mat* m);
 void prof_mark(bl_ctx ctx, int slot);
-void prof_add(bl_ctx ctx, int slot, int which, double bytes);
+void prof_add(bl_ctx ctx, int slot, int which, double bytes, double flops = 0.0);
 
 }  // namespace blapi
 

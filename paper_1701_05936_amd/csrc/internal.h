@@ -248,6 +248,32 @@ hipError_t launch_b_record(const int32_t* sets, const int64_t* lens, int64_t p, 
                            const double* c, const double* s, const BatchScalars* bs, const double* lam,
                            LamStats* out, int k, int K, const int64_t* n_safe, hipStream_t st);
 
+// ---- screening network of the learned form (mlp.hip) ----
+constexpr int MLP_HIDDEN = 64;
+constexpr int MLP_NPARAMS = MLP_HIDDEN * MLP_HIDDEN + 7 * MLP_HIDDEN + 1;
+hipError_t launch_mlp_fwd(const float* feat, int64_t m, const float* P, float* prob, hipStream_t st);
+int mlp_grad_blocks(int64_t batch);
+// step: device counter (the minibatch is step mod nb of epoch step / nb, order given by perm[2e], perm[2e+1]:
+// sample (a (base + t) + c) mod m); step == nullptr: the single batch of all m samples in order
+hipError_t launch_mlp_grad(const float* feat, const float* label, int64_t m, int64_t batch, int64_t nb,
+                           const int64_t* perm, const int64_t* step, const float* P, float* partial,
+                           double* loss_part, hipStream_t st);
+hipError_t launch_mlp_adam(const float* partial, int nblk, const double* loss_part, float* P, float* mom, float* vel,
+                           const int64_t* step, int64_t m, int64_t batch, int64_t nb, double lr, double b1,
+                           double b2, double eps, int apply, float* grad_out, double* loss_out, hipStream_t st);
+hipError_t launch_step_inc(int64_t* step, hipStream_t st);
+hipError_t launch_mlp_hist(const float* prob, const float* label, int64_t m, int bins, uint32_t* hist,
+                           hipStream_t st);
+hipError_t launch_learned(uint8_t* strong, const double* beta, const float* zh, int64_t p, int s1, int s2, int s3,
+                          float ratio, const float* P, float tau_logit, int apply, uint8_t* cand, hipStream_t st);
+hipError_t launch_zhist(const int32_t* cols, const int64_t* len_dev, int64_t len_host, const double* z, double lam,
+                        float* slot, int64_t p, hipStream_t st);
+hipError_t launch_zhist_keep(const uint8_t* keep, int64_t p, const double* z, double lam, float* slot,
+                             hipStream_t st);
+hipError_t launch_rec_feat(const int32_t* list, const int64_t* len_dev, const float* zh, int64_t p, int s1, int s2,
+                           int s3, float ratio, const double* beta, int64_t cap, int64_t* count, float* feat,
+                           float* label, hipStream_t st);
+
 hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t st);
 hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t st);
 hipError_t launch_or_u8(uint8_t* dst, const uint8_t* src, int64_t n, hipStream_t st);
