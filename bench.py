@@ -17,6 +17,12 @@ Workloads (--workload):
                 64 problems = 32 responses x 2 cross-validation row subsets, 50 lambda
                 values each; plain single-problem paths on a sample of the problems are
                 timed beside it.
+  c5            learned-screening form: block AR(1) (rho 0.7, blocks of 100) design
+                5,000 x 1,000,000 float32 (20 GB), 300 nonzeros in 30 blocks, SNR 3, 100
+                lambda values down to 0.01 lambda_max.  The screening network is first
+                trained (on the GPU) on records of --train-paths strong-rule paths of the
+                same recipe at --train-p columns (not timed in value); the hybrid-rule path
+                on the full design is timed beside the learned one.
 
 Prints one JSON line (rank 0, N = 1).
 """
@@ -99,9 +105,30 @@ def timed(fn, steps, warmup, ctx, label):
     return results, elapsed
 
 
-def hbm_roofline(kern, name):
+def profiled_traffic(summary):
+    """HBM bytes per launch from a committed rocprofv3 counter summary under profiles/, or None when the kernel
+    source has changed since the counters were taken (the summary records the source's sha256)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", summary)
+    if not os.path.exists(path):
+        return None
+    traffic, src, sha = None, None, None
+    for line in open(path):
+        if line.startswith("traffic_bytes_per_launch:"):
+            traffic = float(line.split(":", 1)[1])
+        elif line.startswith("source:"):
+            parts = line.split()
+            src, sha = parts[1], parts[-1]
+    if traffic is None or src is None:
+        return None
+    cur = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+    return traffic if cur == sha else None
+
+
+def hbm_roofline(kern, name, traffic_summary=None):
     return {"bound": "hbm", "achieved": kern["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": kern["GBs"] / HBM_PEAK_GBS, "traffic": None, "kernel": name,
+            "frac": kern["GBs"] / HBM_PEAK_GBS,
+            "traffic": profiled_traffic(traffic_summary) if traffic_summary else None, "kernel": name,
             "avg_launch_ms": kern["avg_ms"], "GB_per_launch": kern["GB_per_launch"]}
 
 
@@ -119,7 +146,7 @@ def run_plain(args, rec, ctx, bl, Xd, Xt, yd, y):
                                f"{rec.nlambda} lambda to {rec.lambda_min_ratio} lambda_max, SSR-BEDPP, "
                                f"CD tol {args.tol:g}",
                    "n": rec.n, "p": rec.p, "nlambda": rec.nlambda},
-        "roofline": hbm_roofline(kernels["scan"], "k_scan (FP64 X)"),
+        "roofline": hbm_roofline(kernels["scan"], "k_scan (FP64 X)", "k_scan_c2_genotype_5000x500000_f64.md"),
         "kernels": kernels,
         "path": {"n_active_last": int(last.n_active[-1]), "sweeps": int(last.sweeps.sum()),
                  "columns_scanned": int(last.n_scanned.sum()), "violations": int(last.n_viol.sum())},
@@ -221,24 +248,129 @@ def run_batch(args, rec, ctx, bl, Xd, Xt, prob):
     return out
 
 
+def run_learned(args, rec, ctx, bl, Xd, Xt, yd, y):
+    import numpy as np
+    import torch
+
+    import datagen
+    dev = Xd.device
+    kw = dict(nlambda=rec.nlambda, lambda_min_ratio=rec.lambda_min_ratio, tol=args.tol)
+    # the hybrid-rule path on the full design first (also warms the context up)
+    plain, el_plain = timed(lambda: bl.fit_path(ctx, Xd, yd, rule=bl.SCREEN_SSR_BEDPP, **kw), 1, 0, ctx, "hybrid")
+    ctx.profile(False)
+    hp = plain[-1]
+    log(f"hybrid path: {int(hp.n_active[-1])} active at the end, working sets {int(hp.n_strong.sum())}, "
+        f"sweeps {int(hp.sweeps.sum())}")
+    # training records from strong-rule paths of the same recipe at a reduced column count
+    t_train = time.perf_counter()
+    cap = 40_000_000
+    feat = torch.zeros((cap, 4), dtype=torch.float32, device=dev)
+    lab = torch.zeros(cap, dtype=torch.float32, device=dev)
+    n_rec, paths, per_x = 0, 0, 10
+    # the same lambda grid (ratio per step) as the timed path, cut after --train-depth values: past that
+    # depth a reduced design's fit approaches n active features and its paths only cost time
+    step = rec.lambda_min_ratio ** (1.0 / (rec.nlambda - 1))
+    gpu_ms = 0.0
+    for xi in range((args.train_paths + per_x - 1) // per_x):
+        trec = rec.scaled(p=args.train_p, seed=rec.seed + 1000 + xi, nresp=per_x)
+        tp = datagen.make(trec)
+        Xtr = torch.from_numpy(tp.Xt).to(dev)
+        for t in range(per_x):
+            if paths >= args.train_paths:
+                break
+            ytr = torch.from_numpy(tp.y[t]).to(dev)
+            lmax = bl.fit_path(ctx, Xtr, ytr, nlambda=1, want_beta=False).lambda_max
+            grid = lmax * step ** np.arange(args.train_depth)
+            r = bl.fit_path(ctx, Xtr, ytr, nlambda=args.train_depth, lambdas=grid, rule=bl.SCREEN_SSR_BEDPP,
+                            tol=args.tol, rec_feat=feat[n_rec:], rec_label=lab[n_rec:], want_beta=False)
+            n_rec += r.n_recorded
+            paths += 1
+            gpu_ms += r.time_ms
+            log(f"training path {paths}: {r.time_ms:.0f} ms, {r.n_recorded} records, "
+                f"{int(r.n_active[-1])} active at the end")
+        del Xtr
+    P = torch.from_numpy(bl.mlp_init(1)).to(dev)
+    info = bl.mlp_train(ctx, feat[:n_rec].contiguous(), lab[:n_rec].contiguous(), P, epochs=args.train_epochs,
+                        batch=8192, lr=2e-3, seed=5, target_recall=args.target_recall)
+    log(f"trained on {n_rec} records: {info}")
+    positives = float(lab[:n_rec].sum())
+    del feat, lab
+    torch.cuda.empty_cache()
+    train_s = time.perf_counter() - t_train
+
+    results, elapsed = timed(lambda: bl.fit_path(ctx, Xd, yd, rule=bl.SCREEN_LEARNED, mlp=P, mlp_tau=info["tau"], **kw),
+                             args.steps, args.warmup, ctx, "learned")
+    kernels = kernel_table(ctx, bl, elapsed)
+    ctx.profile(False)
+    lr_ = results[-1]
+    dmax = float((lr_.beta - hp.beta).abs().max())
+    out = {
+        "value": args.steps / elapsed,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "dtype": "f32 X, f64 scans and CD, f32 screening network",
+        "config": {"workload": f"{rec.name}: block AR(1) rho {rec.rho} (blocks of {rec.block}) X {rec.n}x{rec.p} "
+                               f"float32, {rec.nnz} nonzeros, SNR {rec.snr}, {rec.nlambda} lambda to "
+                               f"{rec.lambda_min_ratio} lambda_max, learned screening (network-filtered strong rule "
+                               f"+ BEDPP + exact check), CD tol {args.tol:g}",
+                   "n": rec.n, "p": rec.p, "nlambda": rec.nlambda},
+        "roofline": hbm_roofline(kernels["scan"], "k_scan (f32 X)"),
+        "kernels": kernels,
+        "forms": {"plain_gpu_paths_per_s": 1.0 / el_plain, "speedup_vs_plain_gpu": (args.steps / elapsed) * el_plain,
+                  "max_abs_dbeta_vs_plain_path": dmax,
+                  "working_set_sum_learned": int(lr_.n_strong.sum()), "working_set_sum_plain": int(hp.n_strong.sum()),
+                  "violations_learned": int(lr_.n_viol.sum()), "violations_plain": int(hp.n_viol.sum()),
+                  "sweeps_learned": int(lr_.sweeps.sum()), "sweeps_plain": int(hp.sweeps.sum()),
+                  "training": {"paths": paths, "columns": args.train_p, "lambdas_per_path": args.train_depth,
+                               "records": n_rec, "positives": positives,
+                               "epochs": args.train_epochs, "tau": info["tau"], "recall": info["recall"],
+                               "neg_pass": info["neg_pass"], "loss_first": info["loss_first"],
+                               "loss_last": info["loss_last"], "train_ms": info["time_ms"],
+                               "path_gpu_ms": gpu_ms, "wall_s": train_s}},
+        "path": {"n_active_last": int(lr_.n_active[-1]), "sweeps": int(lr_.sweeps.sum()),
+                 "violations": int(lr_.n_viol.sum())},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a column sample) ...")
+        out["cpu_baseline"] = cpu_baseline(Xt, y, rec, args.cpu_cols, args.tol)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c4"))
+    ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c4", "c5"))
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--cpu-cols", type=int, default=None)
     ap.add_argument("--plain-sample", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", type=float, default=0.0,
+                    help="only copy a buffer of this many GB once (device to device) and exit: the reference "
+                         "kernel for scaling FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--train-paths", type=int, default=200)
+    ap.add_argument("--train-p", type=int, default=10000)
+    ap.add_argument("--train-depth", type=int, default=60)
+    ap.add_argument("--train-epochs", type=int, default=20)
+    ap.add_argument("--target-recall", type=float, default=0.995)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the column-sharded design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calib > 0:
+        import torch
+        n = int(args.copy_calib * 1e9) // 8
+        src = torch.arange(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}), flush=True)
+        return
     if args.cpu_cols is None:
-        args.cpu_cols = {"c2": 20000, "c3": 8000, "c4": 3000}[args.workload]
+        args.cpu_cols = {"c2": 20000, "c3": 1000, "c4": 3000, "c5": 500}[args.workload]
 
     import torch
 
@@ -269,7 +401,7 @@ def main():
     else:
         y = datagen.response(rec, Xt, 0)
         yd = torch.from_numpy(y).to(dev)
-        fn = run_precision if args.workload == "c3" else run_plain
+        fn = {"c2": run_plain, "c3": run_precision, "c5": run_learned}[args.workload]
         out = fn(args, rec, ctx, bl, Xd, Xt, yd, y)
     ctx.close()
     line = {"metric": METRIC, "value": out.pop("value"), "unit": "paths/s", "n_gpus": 1, "steps": args.steps,

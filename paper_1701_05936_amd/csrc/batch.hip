@@ -51,25 +51,28 @@ int grid_for(int64_t work, int per_block, int max_blocks) {
 }
 
 // ---- the shared contraction: OUT = X_cols' B on FP64 matrix cores ----------------------------------------
-// Workgroup tile: BS_F = 128 columns x 64 problems; wavefront w covers columns 32w .. 32w+31 (two 16-row MFMA
+// Workgroup tile: 32 WAVES columns x 64 problems; wavefront w covers columns 32w .. 32w+31 (two 16-row MFMA
 // tiles) against four 16-problem tiles.  Rows go in batches of BS_K = 64: lane (m, kq) holds 16 consecutive
 // rows of its column (rows i0 + 16kq .. +15) and feeds row i0 + 16kq + st at MFMA step st; the same rows of B
-// come from LDS (double buffered, padded rows against bank conflicts).
-constexpr int BS_F = 128;
+// come from LDS (double buffered, padded rows against bank conflicts).  The next batch's X values are loaded
+// into registers while the current batch is on the matrix cores.  WAVES (2, 4 or 8) is picked per shape by
+// the autotuner: wider workgroups stage each B batch for more columns, narrower ones give more workgroups.
 constexpr int BS_K = 64;
 constexpr int BS_LD = BNP + 2;   // LDS row stride of the staged B rows (doubles)
 
 // mode 0: raw dot products; mode 1: squared X (masked second moments); mode 2: standardized correlations
-template <typename XT, int MODE>
-__global__ __launch_bounds__(256) void k_bscan(const XT* __restrict__ X, int64_t ldx, int64_t n_total, int64_t n_pad,
-                                               const int32_t* __restrict__ cols, const int64_t* __restrict__ len_dev,
-                                               int64_t len_host, const double* __restrict__ B, int nprob,
-                                               int64_t p, BatchScalars* __restrict__ bs, const double* __restrict__ c,
-                                               const double* __restrict__ s, const uint8_t* __restrict__ keep,
-                                               double* __restrict__ out) {
+template <typename XT, int MODE, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_bscan(const XT* __restrict__ X, int64_t ldx, int64_t n_total,
+                                                      int64_t n_pad, const int32_t* __restrict__ cols,
+                                                      const int64_t* __restrict__ len_dev, int64_t len_host,
+                                                      const double* __restrict__ B, int nprob, int64_t p,
+                                                      BatchScalars* __restrict__ bs, const double* __restrict__ c,
+                                                      const double* __restrict__ s, const uint8_t* __restrict__ keep,
+                                                      double* __restrict__ out) {
+    constexpr int NT = 64 * WAVES, TF = 32 * WAVES;
     __shared__ double Bl[2][BS_K * BS_LD];
     const int64_t len = len_dev ? *len_dev : len_host;
-    const int64_t f0 = (int64_t)blockIdx.x * BS_F;
+    const int64_t f0 = (int64_t)blockIdx.x * TF;
     if (f0 >= len) return;
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
     const int m = lane & 15, kq = lane >> 4;
@@ -90,36 +93,46 @@ __global__ __launch_bounds__(256) void k_bscan(const XT* __restrict__ X, int64_t
         for (int pt = 0; pt < 4; ++pt) acc[ft][pt] = (f64x4){0.0, 0.0, 0.0, 0.0};
 
     auto stage = [&](int buf, int64_t i0) {
-        // 64 rows x 64 problems; each thread copies 16 doubles
-        for (int idx = tid; idx < BS_K * BNP / 2; idx += 256) {
+        // 64 rows x 64 problems
+        for (int idx = tid; idx < BS_K * BNP / 2; idx += NT) {
             const int row = idx / (BNP / 2), col2 = (idx % (BNP / 2)) * 2;
             const double* src = B + (i0 + row) * BNP + col2;
             Bl[buf][row * BS_LD + col2] = src[0];
             Bl[buf][row * BS_LD + col2 + 1] = src[1];
         }
     };
-    int buf = 0;
-    stage(0, 0);
-    __syncthreads();
-    for (int64_t i0 = 0; i0 < n_pad; i0 += BS_K) {
-        // rows of this batch for the lane's two columns (zero past n_total)
-        double xa[2][16];
+    // raw X values of the lane's rows of one batch (zero past n_total or for an idle column)
+    XT xr[2][16];
+    auto load = [&](int64_t i0) {
 #pragma unroll
         for (int ft = 0; ft < 2; ++ft) {
             const int64_t r0 = i0 + 16 * kq;
             if (ok[ft] && r0 + 16 <= n_total) {
 #pragma unroll
-                for (int q = 0; q < 16; ++q) xa[ft][q] = (double)xc[ft][r0 + q];
+                for (int q = 0; q < 16; ++q) xr[ft][q] = xc[ft][r0 + q];
             } else {
 #pragma unroll
-                for (int q = 0; q < 16; ++q) xa[ft][q] = (ok[ft] && r0 + q < n_total) ? (double)xc[ft][r0 + q] : 0.0;
-            }
-            if (MODE == 1) {
-#pragma unroll
-                for (int q = 0; q < 16; ++q) xa[ft][q] *= xa[ft][q];
+                for (int q = 0; q < 16; ++q) xr[ft][q] = (ok[ft] && r0 + q < n_total) ? xc[ft][r0 + q] : (XT)0;
             }
         }
-        if (i0 + BS_K < n_pad) stage(buf ^ 1, i0 + BS_K);
+    };
+    int buf = 0;
+    load(0);
+    stage(0, 0);
+    __syncthreads();
+    for (int64_t i0 = 0; i0 < n_pad; i0 += BS_K) {
+        double xa[2][16];
+#pragma unroll
+        for (int ft = 0; ft < 2; ++ft)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const double v = (double)xr[ft][q];
+                xa[ft][q] = MODE == 1 ? v * v : v;
+            }
+        if (i0 + BS_K < n_pad) {
+            load(i0 + BS_K);
+            stage(buf ^ 1, i0 + BS_K);
+        }
         const double* Bb = Bl[buf];
 #pragma unroll
         for (int st = 0; st < 16; ++st) {
@@ -774,32 +787,43 @@ __global__ __launch_bounds__(1024) void k_b_record(const int32_t* __restrict__ s
 // ---- launchers -------------------------------------------------------------------------------------------------
 int64_t batch_pad(int64_t n_total) { return (n_total + BS_K - 1) / BS_K * BS_K; }
 
-template <typename XT>
+template <typename XT, int WAVES>
 static hipError_t bscan_typed(const Mat& mt, int mode, const int32_t* cols, const int64_t* len_dev, int64_t len_host,
                               const double* B, int nprob, BatchScalars* bs, const double* c, const double* s,
                               const uint8_t* keep, double* out, hipStream_t st) {
+    constexpr int TF = 32 * WAVES;
     const int64_t n_pad = batch_pad(mt.n_total);
     const int64_t work = len_dev ? mt.p : len_host;
-    const int g = (int)((work + BS_F - 1) / BS_F);
+    const int g = (int)((work + TF - 1) / TF);
     const XT* X = (const XT*)mt.X;
     if (g <= 0) return hipSuccess;
     if (mode == 0)
-        k_bscan<XT, 0><<<g, 256, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, cols, len_dev, len_host, B, nprob, mt.p, bs,
-                                          c, s, keep, out);
+        k_bscan<XT, 0, WAVES><<<g, 64 * WAVES, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, cols, len_dev, len_host, B, nprob,
+                                                       mt.p, bs, c, s, keep, out);
     else if (mode == 1)
-        k_bscan<XT, 1><<<g, 256, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, cols, len_dev, len_host, B, nprob, mt.p, bs,
-                                          c, s, keep, out);
+        k_bscan<XT, 1, WAVES><<<g, 64 * WAVES, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, cols, len_dev, len_host, B, nprob,
+                                                       mt.p, bs, c, s, keep, out);
     else
-        k_bscan<XT, 2><<<g, 256, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, cols, len_dev, len_host, B, nprob, mt.p, bs,
-                                          c, s, keep, out);
+        k_bscan<XT, 2, WAVES><<<g, 64 * WAVES, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, cols, len_dev, len_host, B, nprob,
+                                                       mt.p, bs, c, s, keep, out);
     return hipGetLastError();
+}
+
+template <typename XT>
+static hipError_t bscan_waves(int waves, const Mat& mt, int mode, const int32_t* cols, const int64_t* len_dev,
+                              int64_t len_host, const double* B, int nprob, BatchScalars* bs, const double* c,
+                              const double* s, const uint8_t* keep, double* out, hipStream_t st) {
+    if (waves == 2) return bscan_typed<XT, 2>(mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
+    if (waves == 8) return bscan_typed<XT, 8>(mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
+    return bscan_typed<XT, 4>(mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
 }
 
 hipError_t launch_bscan(const Mat& mt, int mode, const int32_t* cols, const int64_t* len_dev, int64_t len_host,
                         const double* B, int nprob, BatchScalars* bs, const double* c, const double* s,
-                        const uint8_t* keep, double* out, hipStream_t st) {
-    if (mt.xtype == 0) return bscan_typed<double>(mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
-    return bscan_typed<float>(mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
+                        const uint8_t* keep, double* out, hipStream_t st, int waves) {
+    if (mt.xtype == 0)
+        return bscan_waves<double>(waves, mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
+    return bscan_waves<float>(waves, mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
 }
 
 hipError_t launch_b_masks(const uint8_t* masks, int64_t n_total, int nprob, double* Mb, hipStream_t st) {

@@ -204,9 +204,10 @@ struct BatchScalars {
 int64_t batch_pad(int64_t n_total);  // rows of the row-major right-hand sides (multiple of 64)
 // out[b*p + j] for j = cols[t]: mode 0 raw x_j' B[:, b]; mode 1 (x_j o x_j)' B[:, b];
 // mode 2 (x_j' B[:, b] - c_bj sum_r(b)) / (n_b s_bj)
+// waves per workgroup (2, 4 or 8): 32 waves columns per workgroup
 hipError_t launch_bscan(const Mat& mt, int mode, const int32_t* cols, const int64_t* len_dev, int64_t len_host,
                         const double* B, int nprob, BatchScalars* bs, const double* c, const double* s,
-                        const uint8_t* keep, double* out, hipStream_t st);
+                        const uint8_t* keep, double* out, hipStream_t st, int waves = 4);
 hipError_t launch_b_masks(const uint8_t* masks, int64_t n_total, int nprob, double* Mb, hipStream_t st);
 hipError_t launch_b_center_y(const uint8_t* masks, const double* Y, int64_t n_total, int nprob, double* Yt, double* R,
                              BatchScalars* bs, hipStream_t st);

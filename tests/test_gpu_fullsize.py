@@ -1,0 +1,138 @@
+"""Full-size parity: the plain path on the 5,000 x 500,000 genotype design (FP64, 20 GB) and the batched
+form on the 20,000 x 200,000 AR(1) design (64 problems), in the launch configurations bench.py times (CD tolerance 1e-10 here, 1e-8 there).
+
+The oracle cannot run these paths whole in seconds, so the checks use what the oracle computes column by
+column: sampled column statistics, lambda_max over every column (in chunks), and KKT certificates of the
+GPU coefficients at sampled lambda values, with z over every column computed by the oracle's scan.
+"""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+import oracle
+import paper_1701_05936_amd as bl
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+CHUNK = 25_000
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def chunked(Xt, fn):
+    """fn(block of columns as float64, offset) over all columns in chunks."""
+    p = Xt.shape[0]
+    out = []
+    for j0 in range(0, p, CHUNK):
+        out.append(fn(np.ascontiguousarray(Xt[j0:j0 + CHUNK], dtype=np.float64), j0))
+    return out
+
+
+def kkt_residuals(Xt, c, s, keep, yt, beta, lam, mask=None):
+    """max over inactive kept j of |z_j| / lam - 1, and max over active j of |z_j - lam sign(beta_j)| / lam."""
+    act = np.flatnonzero(beta)
+    r = yt.copy()
+    for j in act:   # residual from the active columns only, in FP64
+        xj = (Xt[j].astype(np.float64) - c[j]) / s[j]
+        if mask is not None:
+            xj = xj * mask
+        r -= beta[j] * xj
+    zs = chunked(Xt, lambda blk, j0: oracle.zscan(blk, c[j0:j0 + len(blk)], s[j0:j0 + len(blk)],
+                                                  keep[j0:j0 + len(blk)], r, mask))
+    z = np.concatenate(zs)
+    inactive = keep & (beta == 0)
+    out_viol = np.max(np.abs(z[inactive])) / lam - 1.0
+    on_act = np.max(np.abs(z[act] - lam * np.sign(beta[act]))) / lam if act.size else 0.0
+    return out_viol, on_act
+
+
+@pytest.fixture(scope="module")
+def c2_full(gpu_ctx):
+    rec = datagen.RECIPES["c2"]
+    log("generating c2 at full size ...")
+    Xt = datagen.design(rec)                 # (p, n) uint8 codes
+    y = datagen.response(rec, Xt, 0)
+    Xd = torch.from_numpy(Xt).to(DEV).to(torch.float64)
+    res = bl.fit_path(gpu_ctx, Xd, torch.from_numpy(y).to(DEV), nlambda=rec.nlambda,
+                      lambda_min_ratio=rec.lambda_min_ratio, rule=bl.SCREEN_SSR_BEDPP, tol=1e-10)
+    log(f"GPU path: {res.time_ms:.0f} ms, {res.n_active[-1]} active at the end")
+    beta = res.beta.cpu().numpy()
+    c, s, keep = res.center.cpu().numpy(), res.scale.cpu().numpy(), res.keep.cpu().numpy().astype(bool)
+    del Xd
+    torch.cuda.empty_cache()
+    return rec, Xt, y, res, beta, c, s, keep
+
+
+def test_c2_full_standardization_and_lambda_max(c2_full):
+    rec, Xt, y, res, beta, c, s, keep = c2_full
+    rng = np.random.default_rng(0)
+    cols = np.sort(rng.choice(Xt.shape[0], 300, replace=False))
+    oc, os_, okeep, n = oracle.standardize(Xt[cols].astype(np.float64))
+    np.testing.assert_allclose(c[cols], oc, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(s[cols], os_, rtol=1e-13)
+    np.testing.assert_array_equal(keep[cols], okeep.astype(bool))
+    # lambda_max and j* over every column, chunk by chunk
+    best, bj = -1.0, -1
+    for part, j0 in zip(chunked(Xt, lambda blk, j0: oracle.lambda_max(blk, c[j0:j0 + len(blk)], s[j0:j0 + len(blk)],
+                                                                        keep[j0:j0 + len(blk)], y)[2]),
+                        range(0, Xt.shape[0], CHUNK)):
+        a = np.where(keep[j0:j0 + part.size], np.abs(part), -1.0)
+        j = int(np.argmax(a))
+        if a[j] > best:
+            best, bj = float(a[j]), j0 + j
+    log(f"lambda_max {res.lambda_max:.15g} vs oracle {best:.15g}, j* {res.jstar} vs {bj}")
+    assert abs(res.lambda_max - best) <= 1e-12 * best
+    assert res.jstar == bj
+    assert res.k_done == rec.nlambda
+
+
+@pytest.mark.parametrize("k", [20, 60, 99])
+def test_c2_full_kkt_certificate(c2_full, k):
+    rec, Xt, y, res, beta, c, s, keep = c2_full
+    yt = y - y.mean()
+    lam = res.lam[k]
+    out_v, on_a = kkt_residuals(Xt, c, s, keep, yt, beta[k], lam)
+    log(f"k={k}: lambda {lam:.6g}, active {np.count_nonzero(beta[k])}, max inactive |z|/lambda - 1 = {out_v:.2e}, "
+        f"max active |z - lambda sign| / lambda = {on_a:.2e}")
+    # CD stops at max |d beta| < 1e-10: the optimality conditions hold to about that order in z
+    assert out_v <= 1e-6
+    assert on_a <= 1e-6
+
+
+@pytest.fixture(scope="module")
+def c4_full(gpu_ctx):
+    rec = datagen.RECIPES["c4"]
+    log("generating c4 at full size ...")
+    prob = datagen.make(rec)
+    Y = np.repeat(prob.y, rec.nsub, axis=0)
+    Xd = torch.from_numpy(prob.Xt).to(DEV)
+    res = bl.fit_path_batch(gpu_ctx, Xd, torch.from_numpy(Y).to(DEV), torch.from_numpy(prob.masks).to(DEV),
+                            nlambda=rec.nlambda, lambda_min_ratio=rec.lambda_min_ratio, rule=bl.SCREEN_SSR_BEDPP,
+                            tol=1e-10)
+    log(f"GPU batch: {res.time_ms:.0f} ms for {Y.shape[0]} problems")
+    beta = res.beta.cpu().numpy()
+    del Xd
+    torch.cuda.empty_cache()
+    return rec, prob, Y, res, beta
+
+
+@pytest.mark.parametrize("b,k", [(0, 49), (37, 25)])
+def test_c4_full_kkt_certificate(c4_full, b, k):
+    rec, prob, Y, res, beta, = c4_full
+    Xt, mask = prob.Xt, prob.masks[b]
+    # the problem's own standardization by the oracle, chunk by chunk
+    st = chunked(Xt, lambda blk, j0: oracle.standardize(blk, mask)[:3])
+    c = np.concatenate([t[0] for t in st])
+    s = np.concatenate([t[1] for t in st])
+    keep = np.concatenate([t[2] for t in st]).astype(bool)
+    y = Y[b]
+    yt = np.where(mask > 0, y - y[mask > 0].mean(), 0.0)
+    lam = res.lam[b, k]
+    out_v, on_a = kkt_residuals(Xt, c, s, keep, yt, beta[b, k], lam, mask)
+    log(f"problem {b}, k={k}: rows {int(mask.sum())}, active {np.count_nonzero(beta[b, k])}, "
+        f"inactive {out_v:.2e}, active {on_a:.2e}")
+    assert out_v <= 1e-6
+    assert on_a <= 1e-6
