@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "chain.h"
 #include "internal.h"
 
 namespace blk {
@@ -609,14 +610,7 @@ __global__ void k_b_gather(const int32_t* __restrict__ sets, const int64_t* __re
 // ---- coordinate descent, one workgroup per problem ---------------------------------------------------------
 // The single-workgroup covariance solve (blocked chain in one wavefront, block changes pushed by the
 // workgroup) for problem blockIdx.x.
-constexpr int BCD_T = 1024, BCD_B = 64;
-
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-    uint64_t u = __builtin_bit_cast(uint64_t, v);
-    uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, lane);
-    uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), lane);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
+constexpr int BCD_T = 512, BCD_B = 64;
 
 __global__ __launch_bounds__(BCD_T) void k_b_gcd(const int32_t* __restrict__ sets, const int64_t* __restrict__ lens,
                                                  int64_t p, const uint8_t* __restrict__ want,
@@ -659,16 +653,8 @@ __global__ __launch_bounds__(BCD_T) void k_b_gcd(const int32_t* __restrict__ set
                     double gl = lane < bl ? g[q0 + lane] : 0.0;
                     double bv = lane < bl ? bE[q0 + lane] : 0.0;
                     double dl = 0.0, wmax = 0.0;
-                    for (int t = 0; t < bl; ++t) {
-                        const double gt = readlane_f64(gl, t), bt = readlane_f64(bv, t);
-                        const double u = gt + bt;
-                        const double bn = u - fmin(fmax(u, -l), l);
-                        const double d = bn - bt;
-                        gl = fma(-d, Gbb[t * BCD_B + lane], gl);
-                        bv = lane == t ? bn : bv;
-                        dl = lane == t ? d : dl;
-                        wmax = fmax(wmax, fabs(d));
-                    }
+                    auto col = [&](int t) { return Gbb[t * BCD_B + lane]; };
+                    if (!chain_fast<BCD_B>(gl, bv, col, l, bl, dl, wmax)) chain_exact<BCD_B>(gl, bv, col, l, bl, dl, wmax);
                     if (lane < bl) {
                         g[q0 + lane] = gl;
                         bE[q0 + lane] = bv;

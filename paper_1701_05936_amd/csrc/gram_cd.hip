@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "chain.h"
 #include "internal.h"
 
 namespace blk {
@@ -30,16 +31,6 @@ namespace {
 
 constexpr int WAVE = 64;
 
-__device__ __forceinline__ double soft_threshold(double u, double l) {
-    return u > l ? u - l : (u < -l ? u + l : 0.0);
-}
-
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-    uint64_t b = __builtin_bit_cast(uint64_t, v);
-    uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, lane);
-    uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), lane);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
 
 template <typename XT>
 __device__ __forceinline__ double ld_x(const XT* p) { return (double)*p; }
@@ -176,7 +167,7 @@ __global__ void k_gather_start(const int32_t* __restrict__ set, int64_t m, const
 }
 
 // ---- the solve -----------------------------------------------------------------------------------------
-constexpr int GCD_THREADS = 1024;
+constexpr int GCD_THREADS = 512;
 
 __global__ __launch_bounds__(GCD_THREADS) void k_gcd(GcdArgs a) {
     __shared__ double g[GCD_MAX];
@@ -211,20 +202,9 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd(GcdArgs a) {
                     double gl = lane < bl ? g[b0 + lane] : 0.0;
                     double bv = lane < bl ? bE[b0 + lane] : 0.0;
                     double dl = 0.0, wmax = 0.0;
-                    for (int t = 0; t < bl; ++t) {
-                        const double gt = readlane_f64(gl, t);
-                        const double bt = readlane_f64(bv, t);
-                        const double bn = soft_threshold(gt + bt, lam);
-                        const double d = bn - bt;
-                        if (d != 0.0) {
-                            gl = fma(-d, Gbb[t * GCD_B + lane], gl);
-                            if (lane == t) {
-                                bv = bn;
-                                dl = d;
-                            }
-                            wmax = fmax(wmax, fabs(d));
-                        }
-                    }
+                    auto col = [&](int t) { return Gbb[t * GCD_B + lane]; };
+                    if (!chain_fast<GCD_B>(gl, bv, col, lam, bl, dl, wmax))
+                        chain_exact<GCD_B>(gl, bv, col, lam, bl, dl, wmax);
                     if (lane < bl) {
                         g[b0 + lane] = gl;
                         bE[b0 + lane] = bv;
@@ -350,6 +330,60 @@ __device__ __forceinline__ void load_gblock(const double* __restrict__ G, int64_
     for (int k = 0; k < PER; ++k) dst[t0 + k * STEP] = v[k];
 }
 
+// LDS arena shared by the two roles (a workgroup is either the leader or a helper)
+constexpr int LEAD_LDS = 3 * (SLACK + 1) * MB * MB + 2 * 2 * MB + (SLACK + 1) * MB + 2 * 2 * MB + 8;
+constexpr int HELP_LDS = HBATCH * HOWN * MB * MB + HBATCH * MB + HOWN * MB + (MT / MB) * HOWN * MB + 8;
+constexpr int ARENA = LEAD_LDS > HELP_LDS ? LEAD_LDS : HELP_LDS;
+
+// The working-set Gram matrix G (m x m, m <= 16,320, so byte offsets fit 32 bits) is read through a
+// buffer resource: an offset past its end reads 0, which pads partial blocks without branches.
+constexpr uint32_t GOFF_NONE = 0xFFFFFFF8u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t gram_rsrc(const double* G, int64_t m) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(G), (short)0, (int)(m * m * 8), 0x00020000);
+}
+__device__ __forceinline__ double gram_ld(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    const u2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
+    return __builtin_bit_cast(double, v);
+}
+// byte offset of G[(cb*MB + t) * m + rb*MB + l], or GOFF_NONE outside the blocks' lengths
+__device__ __forceinline__ uint32_t gram_off(int64_t m, int cb, int cl, int rb, int rl, int t, int l) {
+    return (t < cl && l < rl) ? (uint32_t)((((uint32_t)(cb * MB + t)) * (uint32_t)m + (uint32_t)(rb * MB + l)) * 8u)
+                              : GOFF_NONE;
+}
+
+constexpr int GSET = (SLACK + 1) * (MB * MB / WAVE);  // registers per lane for one set of Gram blocks
+
+// issue the loads of the Gram blocks of block rb against its own block and the SLACK blocks run before
+// it (sequence qb and the SLACK sequences before it) into v; store_gset writes them to dst[s][t * MB + l]
+__device__ __forceinline__ void load_gset(__amdgpu_buffer_rsrc_t rs, int64_t m, int nb, int64_t qb, int rb,
+                                          double (&v)[GSET], int lane) {
+    constexpr int PER = MB * MB / WAVE;
+    const int rl = blk_len(m, rb);
+    const int t0 = lane / MB, l = lane % MB;   // entry k of the lane: column t0 + 2k, row l
+    const uint32_t step = 2u * (uint32_t)m * 8u;
+#pragma unroll
+    for (int s = 0; s <= SLACK; ++s) {
+        int cbk = rb - s;
+        if (cbk < 0) cbk += nb;
+        const int cl = qb - s >= 0 ? blk_len(m, cbk) : 0;
+        const uint32_t base = (((uint32_t)(cbk * MB + t0)) * (uint32_t)m + (uint32_t)(rb * MB + l)) * 8u;
+        const bool row_ok = l < rl;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const bool ok = row_ok && t0 + 2 * k < cl;
+            v[s * PER + k] = gram_ld(rs, ok ? base + (uint32_t)k * step : GOFF_NONE);
+        }
+    }
+}
+__device__ __forceinline__ void store_gset(const double (&v)[GSET], double* dst, int lane) {
+    constexpr int PER = MB * MB / WAVE;
+#pragma unroll
+    for (int s = 0; s <= SLACK; ++s)
+#pragma unroll
+        for (int k = 0; k < PER; ++k) dst[s * MB * MB + lane + k * WAVE] = v[s * PER + k];
+}
+
 __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
     const int64_t m = a.m;
@@ -357,94 +391,114 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
     const int H = a.H;
     uint32_t* sync = a.sync;
     const uint32_t spin_limit = a.spin_limit;
+    __shared__ double arena[ARENA];
 
     if (blockIdx.x == 0) {
         // ---------------- leader ----------------
-        __shared__ double Gm[2][SLACK + 1][MB * MB];  // [buf][0] = G(b,b), [s] = G(b, block of q-s)
-        __shared__ double gb[2][MB], bb[2][MB];       // gradient and coefficients of the block to run
-        __shared__ double dh[SLACK + 1][MB];          // changes of the last blocks, by sequence mod (SLACK+1)
-        __shared__ double gout[2][MB], bout[2][MB];   // results of a block, staged for publishing
-        __shared__ double part[MT / MB][MB];
-        __shared__ double maxd_sh;
-        __shared__ int err_sh;
+        // Gram blocks of block b_j in buffer j mod 3: [0] = G(b_j, b_j), [s] = G(b_j, b_{j-s}); they are
+        // loaded two sequences ahead.  Before block b_q runs, the owner has applied every change below
+        // q - SLACK, wave 2 applied the changes of q - SLACK .. q - 2 while preparing the block (one
+        // sequence ahead), and wave 0 applies the change of q - 1 itself.
+        double* Gm = arena;                                    // [3][SLACK + 1][MB * MB]
+        double* gb = Gm + 3 * (SLACK + 1) * MB * MB;           // [2][MB] gradient of the block to run
+        double* bb = gb + 2 * MB;                              // [2][MB] its coefficients
+        double* dh = bb + 2 * MB;                              // [SLACK + 1][MB] changes by sequence mod (SLACK+1)
+        double* gout = dh + (SLACK + 1) * MB;                  // [2][MB] results of a block, for publishing
+        double* bout = gout + 2 * MB;
+        double* maxd_sh = bout + 2 * MB;
+        int* err_sh = (int*)(maxd_sh + 1);
         const double lam = a.lam;
         if (tid == 0) {
-            maxd_sh = 0.0;
-            err_sh = 0;
+            *maxd_sh = 0.0;
+            *err_sh = 0;
         }
-        // block of sequence 0
-        load_gblock<MT>(a.G, m, 0, 0, Gm[0][0], tid);
+        // sequences 0 and 1: Gram blocks, and the gradient of block 0; wave 3 keeps the loads of the next
+        // set in flight across each iteration (set q + 3 is loaded while set q + 2 is stored)
+        const __amdgpu_buffer_rsrc_t grs = gram_rsrc(a.G, m);
+        double gv[GSET];
+        if (wv < 2) {
+            load_gset(grs, m, nb, wv, wv, gv, lane);
+            store_gset(gv, Gm + wv * (SLACK + 1) * MB * MB, lane);
+        } else if (wv == 3) {
+            load_gset(grs, m, nb, 2, 2 % nb, gv, lane);
+        }
         if (tid < MB) {
             const bool ok = tid < blk_len(m, 0);
-            gb[0][tid] = ok ? ld_coh(a.g + tid) : 0.0;
-            bb[0][tid] = ok ? ld_coh(a.b + tid) : 0.0;
+            gb[tid] = ok ? ld_coh(a.g + tid) : 0.0;
+            bb[tid] = ok ? ld_coh(a.b + tid) : 0.0;
         }
         __syncthreads();
+        // wave 0 keeps the Gram columns of the block it runs next in registers (diagonal block and the
+        // block against the previous one) and the previous sequence's changes (lane t: coordinate t)
+        double gc[MB], go[MB], dlp = 0.0;
+        if (wv == 0) {
+#pragma unroll
+            for (int t = 0; t < MB; ++t) {
+                gc[t] = Gm[t * MB + (lane & (MB - 1))];
+                go[t] = Gm[MB * MB + t * MB + (lane & (MB - 1))];
+            }
+        }
         int sweeps = 0, status = 0;
         int64_t q = 0;
+        int b = 0;          // q mod nb
+        int pslot = 0;      // (q - 1) mod 2nb: slot of the previous sequence's changes
+        int g3 = 0;         // q mod 3
         for (;;) {
-            const int b = (int)(q % nb), cur = (int)(q & 1), nxt = cur ^ 1;
+            const int cur = (int)(q & 1), nxt = cur ^ 1;
+            const int pb = b == 0 ? nb - 1 : b - 1, nbk = b + 1 == nb ? 0 : b + 1;
+            const int g3n = g3 == 2 ? 0 : g3 + 1, g3nn = g3n == 2 ? 0 : g3n + 1;
             const int bl = blk_len(m, b);
             if (wv == 0) {
                 const int l32 = lane & (MB - 1);
-                // the SLACK most recent changes, oldest first (lane l = row l of the block)
-                double gl = lane < bl ? gb[cur][l32] : 0.0;
-                for (int s = SLACK; s >= 1; --s) {
-                    if (q - s < 0) continue;
-                    const double* Gs = Gm[cur][s];
-                    const double* ds = dh[(q - s) % (SLACK + 1)];
-                    double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
+                double gl = lane < bl ? gb[cur * MB + l32] : 0.0;
+                // the change of the previous sequence (lane l = row l of the block)
+                if (q >= 1) {
+                    double u0 = 0.0, u1 = 0.0;
 #pragma unroll
-                    for (int t = 0; t < MB; t += 4) {
-                        u0 = fma(Gs[t * MB + l32], ds[t], u0);
-                        u1 = fma(Gs[(t + 1) * MB + l32], ds[t + 1], u1);
-                        u2 = fma(Gs[(t + 2) * MB + l32], ds[t + 2], u2);
-                        u3 = fma(Gs[(t + 3) * MB + l32], ds[t + 3], u3);
+                    for (int t = 0; t < MB; t += 2) {
+                        u0 = fma(go[t], chain_readlane(dlp, t), u0);
+                        u1 = fma(go[t + 1], chain_readlane(dlp, t + 1), u1);
                     }
-                    gl -= (u0 + u1) + (u2 + u3);
+                    if (lane < bl) gl -= u0 + u1;
                 }
                 // the chain of block b, with the block's Gram column entries in registers
-                double gc[MB];
-#pragma unroll
-                for (int t = 0; t < MB; ++t) gc[t] = Gm[cur][0][t * MB + l32];
-                double bv = lane < bl ? bb[cur][l32] : 0.0;
+                double bv = lane < bl ? bb[cur * MB + l32] : 0.0;
                 double dl = 0.0, wmax = 0.0;
-                // rows past the block's length hold zeros, so their steps change nothing
+                // lanes past the block's length (and lanes 32..63) hold zeros, so nothing changes there
+                auto col = [&](int t) { return gc[t]; };
+                if (!chain_fast<MB>(gl, bv, col, lam, bl, dl, wmax)) chain_exact<MB>(gl, bv, col, lam, bl, dl, wmax);
+                if (lane < MB) {
+                    dh[(q % (SLACK + 1)) * MB + lane] = lane < bl ? dl : 0.0;
+                    gout[cur * MB + lane] = gl;
+                    bout[cur * MB + lane] = bv;
+                }
+                if (lane == 0) *maxd_sh = fmax(*maxd_sh, wmax);
+                dlp = lane < bl ? dl : 0.0;
+                // Gram columns of the next block (its buffer was filled during the previous iteration)
+                const double* Gn = Gm + g3n * (SLACK + 1) * MB * MB;
 #pragma unroll
                 for (int t = 0; t < MB; ++t) {
-                    const double gt = readlane_f64(gl, t);
-                    const double bt = readlane_f64(bv, t);
-                    const double u = gt + bt;
-                    const double bn = u - fmin(fmax(u, -lam), lam);  // soft threshold S(u, lam)
-                    const double d = bn - bt;
-                    gl = fma(-d, gc[t], gl);
-                    bv = lane == t ? bn : bv;
-                    dl = lane == t ? d : dl;
-                    wmax = fmax(wmax, fabs(d));
+                    gc[t] = Gn[t * MB + l32];
+                    go[t] = Gn[MB * MB + t * MB + l32];
                 }
-                if (lane < MB) {
-                    dh[q % (SLACK + 1)][lane] = lane < bl ? dl : 0.0;
-                    gout[cur][lane] = gl;
-                    bout[cur][lane] = bv;
-                }
-                if (lane == 0) maxd_sh = fmax(maxd_sh, wmax);
             } else if (wv == 1) {
                 // publish the previous block (sequence q-1)
                 if (q >= 1) {
-                    const int pb = (int)((q - 1) % nb), pl = blk_len(m, pb), pc = cur ^ 1;
+                    const int pl = blk_len(m, pb), pc = cur ^ 1;
                     const int64_t e0 = (int64_t)pb * MB;
                     if (lane < pl) {
-                        st_coh(a.delta + ((q - 1) % (2 * nb)) * MB + lane, dh[(q - 1) % (SLACK + 1)][lane]);
-                        st_coh(a.g + e0 + lane, gout[pc][lane]);
-                        st_coh(a.b + e0 + lane, bout[pc][lane]);
+                        st_coh(a.delta + (int64_t)pslot * MB + lane, dh[((q - 1) % (SLACK + 1)) * MB + lane]);
+                        st_coh(a.g + e0 + lane, gout[pc * MB + lane]);
+                        st_coh(a.b + e0 + lane, bout[pc * MB + lane]);
                     }
                     wait_mem();
                     if (lane == 0) st_flag(sync + SYNC_PUB, (uint32_t)q);
                 }
             } else if (wv == 2) {
-                // gradient and coefficients of the next block, once its owner is far enough
+                // prepare the next block (sequence q + 1): once its owner has applied every change below
+                // q + 1 - SLACK, take its gradient and apply the changes of q + 1 - SLACK .. q - 1
                 const int64_t qn = q + 1;
-                const int nbk = (int)(qn % nb), nl = blk_len(m, nbk);
+                const int nl = blk_len(m, nbk);
                 const int64_t need = qn - SLACK;
                 if (need > 0 && H > 0) {
                     const int owner = nbk % H;
@@ -458,31 +512,51 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
                             }
                             __builtin_amdgcn_s_sleep(1);
                         }
-                        if (bad) err_sh = 1;
+                        if (bad) *err_sh = 1;
                     }
                 }
                 const int64_t e0 = (int64_t)nbk * MB;
+                const int l32 = lane & (MB - 1), half = lane >> 5;
+                double gn = l32 < nl ? ld_coh(a.g + e0 + l32) : 0.0;
+                const double bn = l32 < nl ? ld_coh(a.b + e0 + l32) : 0.0;
+                // lanes 0..31 take columns 0..15 of each change block, lanes 32..63 columns 16..31
+                const double* Gn = Gm + g3n * (SLACK + 1) * MB * MB;
+                double u = 0.0;
+#pragma unroll
+                for (int o = SLACK; o >= 2; --o) {
+                    const int64_t sq = qn - o;
+                    if (sq < 0) continue;
+                    const double* Gs = Gn + o * MB * MB;
+                    const double* ds = dh + (sq % (SLACK + 1)) * MB;
+#pragma unroll
+                    for (int t = 0; t < MB / 2; ++t) {
+                        const int tt = half * (MB / 2) + t;
+                        u = fma(Gs[tt * MB + l32], ds[tt], u);
+                    }
+                }
+                u += __shfl_xor(u, 32, WAVE);
                 if (lane < MB) {
-                    gb[nxt][lane] = lane < nl ? ld_coh(a.g + e0 + lane) : 0.0;
-                    bb[nxt][lane] = lane < nl ? ld_coh(a.b + e0 + lane) : 0.0;
+                    gb[nxt * MB + lane] = gn - u;
+                    bb[nxt * MB + lane] = bn;
                 }
             } else {
-                // Gram blocks of the next block
-                const int64_t qn = q + 1;
-                const int nbk = (int)(qn % nb);
-                load_gblock<WAVE>(a.G, m, nbk, nbk, Gm[nxt][0], lane);
-                for (int s = 1; s <= SLACK; ++s) {
-                    if (qn - s < 0) continue;
-                    load_gblock<WAVE>(a.G, m, nbk, (int)((qn - s) % nb), Gm[nxt][s], lane);
-                }
+                // Gram blocks of the block after next (sequence q + 2), loaded during the last iteration;
+                // then the loads for sequence q + 3
+                store_gset(gv, Gm + g3nn * (SLACK + 1) * MB * MB, lane);
+                int b3 = nbk + 2;
+                if (b3 >= nb) b3 -= nb;
+                load_gset(grs, m, nb, q + 3, b3, gv, lane);
             }
             __syncthreads();
             const bool sweep_end = (b == nb - 1);
-            bool stop = err_sh != 0;
-            if (err_sh) status = 2;
+            b = nbk;
+            g3 = g3n;
+            pslot = (q >= 1) ? (pslot + 1 == 2 * nb ? 0 : pslot + 1) : 0;
+            bool stop = *err_sh != 0;
+            if (*err_sh) status = 2;
             if (sweep_end && !stop) {
                 ++sweeps;
-                const double md = maxd_sh;
+                const double md = *maxd_sh;
                 if (md < a.tol) stop = true;
                 else if (sweeps >= a.max_sweeps) {
                     status = 1;
@@ -490,7 +564,7 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
                 }
             }
             __syncthreads();
-            if (sweep_end && tid == 0) maxd_sh = 0.0;
+            if (sweep_end && tid == 0) *maxd_sh = 0.0;
             ++q;
             if (stop) break;
         }
@@ -499,8 +573,8 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
             const int pb = (int)((q - 1) % nb), pl = blk_len(m, pb), pc = (int)((q - 1) & 1);
             const int64_t e0 = (int64_t)pb * MB;
             if (lane < pl) {
-                st_coh(a.g + e0 + lane, gout[pc][lane]);
-                st_coh(a.b + e0 + lane, bout[pc][lane]);
+                st_coh(a.g + e0 + lane, gout[pc * MB + lane]);
+                st_coh(a.b + e0 + lane, bout[pc * MB + lane]);
             }
             wait_mem();
         }
@@ -516,17 +590,20 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
     }
 
     // ---------------- helper ----------------
-    __shared__ double Gh[HBATCH][HOWN][MB * MB];
-    __shared__ double dlt[HBATCH][MB];
-    __shared__ double gh[HOWN][MB];
-    __shared__ double hp[MT / MB][HOWN][MB];
-    __shared__ int64_t pub_sh;
-    __shared__ int quit_sh;
+    auto Gh = reinterpret_cast<double(*)[HOWN][MB * MB]>(arena);                         // [HBATCH][HOWN][MB*MB]
+    auto dlt = reinterpret_cast<double(*)[MB]>(arena + HBATCH * HOWN * MB * MB);           // [HBATCH][MB]
+    auto gh = reinterpret_cast<double(*)[MB]>(arena + HBATCH * HOWN * MB * MB + HBATCH * MB);  // [HOWN][MB]
+    auto hp = reinterpret_cast<double(*)[HOWN][MB]>(arena + HBATCH * HOWN * MB * MB + HBATCH * MB + HOWN * MB);
+    int64_t& pub_sh = *reinterpret_cast<int64_t*>(arena + HELP_LDS - 8);
+    int& quit_sh = *reinterpret_cast<int*>(arena + HELP_LDS - 7);
     const int h = blockIdx.x - 1;
     int own[HOWN];
     int nown = 0;
     for (int c = h; c < nb && nown < HOWN; c += H) own[nown++] = c;
+    const __amdgpu_buffer_rsrc_t grs = gram_rsrc(a.G, m);
     int64_t s0 = 0;  // next sequence to apply
+    int hb = 0;      // s0 mod nb
+    int hslot = 0;   // s0 mod 2nb
     for (;;) {
         if (tid == 0) {
             uint32_t spins = 0;
@@ -561,18 +638,23 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
             double hv[HOWN];
 #pragma unroll
             for (int k = 0; k < HBATCH; ++k) {
-                const int bq = (int)((s0 + k) % nb);
+                int bq = hb + k;
+                if (bq >= nb) bq -= nb;
+                int sl = hslot + k;
+                if (sl >= 2 * nb) sl -= 2 * nb;
                 const bool kin = k < nbat;
-                dv[k] = (kin && tid < blk_len(m, bq)) ? ld_coh(a.delta + ((s0 + k) % (2 * nb)) * MB + tid) : 0.0;
+                dv[k] = (kin && tid < blk_len(m, bq)) ? ld_coh(a.delta + (int64_t)sl * MB + tid) : 0.0;
 #pragma unroll
                 for (int o = 0; o < HOWN; ++o) {
-                    const bool use = kin && o < nown && (((own[o] - bq) % nb + nb) % nb) > SLACK;
-                    const int rl = use ? blk_len(m, own[o]) : 0, cl = use ? blk_len(m, bq) : 0;
-                    const int64_t r0 = use ? (int64_t)own[o] * MB : 0, c0 = (int64_t)bq * MB;
+                    int dist = own[o] - bq;
+                    if (dist < 0) dist += nb;
+                    const bool use = kin && o < nown && dist > SLACK;
+                    const int ob = o < nown ? own[o] : 0;
+                    const int rl = use ? blk_len(m, ob) : 0, cl = use ? blk_len(m, bq) : 0;
 #pragma unroll
                     for (int q2 = 0; q2 < PER; ++q2) {
-                        const int idx = tid + q2 * MT, t = idx / MB, l = idx % MB;
-                        gv[k][o][q2] = (t < cl && l < rl) ? a.G[(c0 + t) * m + r0 + l] : 0.0;
+                        const int idx = tid + q2 * MT;
+                        gv[k][o][q2] = gram_ld(grs, gram_off(m, bq, cl, ob, rl, idx / MB, idx % MB));
                     }
                 }
             }
@@ -594,9 +676,11 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
         __syncthreads();
         bool touched[HOWN] = {};
         for (int k = 0; k < nbat; ++k) {
-            const int bq = (int)((s0 + k) % nb);
+            int bq = hb + k;
+            if (bq >= nb) bq -= nb;
             for (int o = 0; o < nown; ++o) {
-                const int dist = (int)(((own[o] - bq) % nb + nb) % nb);
+                int dist = own[o] - bq;
+                if (dist < 0) dist += nb;
                 if (dist <= SLACK) continue;  // uniform
                 touched[o] = true;
                 const int l = tid % MB, pp = tid / MB;
@@ -621,6 +705,10 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
         wait_mem();
         __syncthreads();
         s0 += nbat;
+        hb += nbat;
+        if (hb >= nb) hb -= nb;
+        hslot += nbat;
+        if (hslot >= 2 * nb) hslot -= 2 * nb;
         if (tid == 0) st_flag(sync + SYNC_APPLIED + 16 * h, (uint32_t)s0);
     }
 }
