@@ -235,7 +235,7 @@ def run_batch(args, rec, ctx, bl, Xd, Xt, prob):
                      "kernel": "k_bscan (X'R, 64 right-hand sides, FP64 MFMA)", "avg_launch_ms": bs["avg_ms"],
                      "TFLOP_per_launch": bs["TFLOP_per_launch"], "GBs": bs["GBs"]},
         "kernels": kernels,
-        "forms": {"plain_gpu_paths_per_s": plain_pps, "plain_sample": sample,
+        "forms": {"plain_gpu_paths_per_s": plain_pps, "plain_sample": sample, "scan_cols_autotuned": res.scan_cols,
                   "speedup_vs_plain_gpu": paths_per_s / plain_pps,
                   "max_abs_dbeta_vs_plain_path": dmax},
         "path": {"sweeps": int(res.sweeps.sum()), "violations": int(res.n_viol.sum()),

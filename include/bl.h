@@ -256,7 +256,8 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
  * rows, standardization, lambda grid (its own lambda_max, the ratio of opts),
  * screening sets and coefficients.  The problems advance through their grids in
  * lockstep; every pass over X (column statistics, lambda_max and BEDPP products,
- * post-convergence scans) serves all problems at once on FP64 matrix cores.
+ * post-convergence scans) serves all problems at once on FP64 matrix cores.  The screening
+ * kernels of a lambda step are captured once per call in a HIP graph and replayed.
  * Options as bl_fit_path (opts->lambda must be NULL, precision FP64); X->row_mask
  * must be NULL; X is f32 or f64.
  */
@@ -264,7 +265,11 @@ typedef struct {
     int32_t nprob;             /* 1..64                                                                */
     const double* Y;           /* DEVICE [nprob x n_total]: response of problem b at Y[b*n_total + i]   */
     const uint8_t* masks;      /* DEVICE [nprob x n_total]: 1 = row i is in problem b's fit; NULL = all */
+    int32_t flags;             /* BL_BATCH_EAGER: launch each lambda step's screening kernels one by one
+                                  instead of replaying the captured HIP graph (same results)            */
 } bl_batch;
+
+enum { BL_BATCH_EAGER = 1 };
 
 typedef struct {
     double* beta;              /* DEVICE [nprob x K x p] (problem-major, then lambda) or NULL           */
@@ -280,6 +285,9 @@ typedef struct {
     int64_t* n_viol;           /* host [nprob x K]                                                     */
     int32_t k_done;            /* out: lambda indices finished by every problem                        */
     double time_ms;            /* out                                                                  */
+    int32_t scan_cols;         /* out: columns per workgroup of the shared scan, picked by timing the
+                                  candidates (64, 128, 256, with or without register prefetch) on this
+                                  shape once per context                                               */
 } bl_batch_result;
 
 bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_batch* batch, const bl_path_opts* opts,

@@ -90,7 +90,8 @@ class _MlpTrainResult(ctypes.Structure):
 
 
 class _Batch(ctypes.Structure):
-    _fields_ = [("nprob", ctypes.c_int32), ("Y", ctypes.c_void_p), ("masks", ctypes.c_void_p)]
+    _fields_ = [("nprob", ctypes.c_int32), ("Y", ctypes.c_void_p), ("masks", ctypes.c_void_p),
+                ("flags", ctypes.c_int32)]
 
 
 class _BatchResult(ctypes.Structure):
@@ -98,7 +99,7 @@ class _BatchResult(ctypes.Structure):
                 ("rss", ctypes.c_void_p), ("obj", ctypes.c_void_p), ("sweeps", ctypes.c_void_p),
                 ("rounds", ctypes.c_void_p), ("n_active", ctypes.c_void_p), ("n_strong", ctypes.c_void_p),
                 ("n_safe", ctypes.c_void_p), ("n_viol", ctypes.c_void_p), ("k_done", ctypes.c_int32),
-                ("time_ms", ctypes.c_double)]
+                ("time_ms", ctypes.c_double), ("scan_cols", ctypes.c_int32)]
 
 
 _lib = None
@@ -410,11 +411,15 @@ class BatchResult:
     time_ms: float
     status: int
     message: str
+    scan_cols: int = 0
+
+
+BATCH_EAGER = 1
 
 
 def fit_path_batch(ctx: Context, Xt, Y, masks=None, nlambda=100, lambda_min_ratio=0.1, rule=SCREEN_SSR_BEDPP,
                    tol=1e-8, max_sweeps=100000, max_rounds=100, n_total=None, want_beta=True,
-                   raise_on_error=True) -> BatchResult:
+                   raise_on_error=True, eager=False) -> BatchResult:
     """Batched form: B <= 64 problems over one X.  Y (B, n_total) float64 device; masks (B, n_total) uint8
     device or None (all rows in every problem)."""
     M = matrix(Xt, n_total, None)
@@ -431,12 +436,12 @@ def fit_path_batch(ctx: Context, Xt, Y, masks=None, nlambda=100, lambda_min_rati
     host = {k: np.zeros((B, K)) for k in ("lam", "intercept", "rss", "obj")}
     host.update({k: np.zeros((B, K), dtype=np.int32) for k in ("sweeps", "rounds")})
     host.update({k: np.zeros((B, K), dtype=np.int64) for k in ("n_active", "n_strong", "n_safe", "n_viol")})
-    bt = _Batch(B, _ptr(Y), _ptr(masks))
+    bt = _Batch(B, _ptr(Y), _ptr(masks), BATCH_EAGER if eager else 0)
     opts = _PathOpts(K, float(lambda_min_ratio), None, int(rule), float(tol), int(max_sweeps), int(max_rounds),
                      PREC_FP64)
     res = _BatchResult(_ptr(beta), *[host[k].ctypes.data for k in ("lam", "intercept", "rss", "obj", "sweeps",
                                                                   "rounds", "n_active", "n_strong", "n_safe",
-                                                                  "n_viol")], 0, 0.0)
+                                                                  "n_viol")], 0, 0.0, 0)
     L = load_library()
     st = L.bl_fit_path_batch(ctx.handle, ctypes.byref(M), ctypes.byref(bt), ctypes.byref(opts), ctypes.byref(res))
     msg = L.bl_last_error(ctx.handle).decode(errors="replace") if st != BL_OK else ""
@@ -444,7 +449,7 @@ def fit_path_batch(ctx: Context, Xt, Y, masks=None, nlambda=100, lambda_min_rati
         raise BLError(st, msg)
     return BatchResult(host["lam"], beta, host["intercept"], host["rss"], host["obj"], host["sweeps"],
                        host["rounds"], host["n_active"], host["n_strong"], host["n_safe"], host["n_viol"],
-                       res.k_done, res.time_ms, st, msg)
+                       res.k_done, res.time_ms, st, msg, res.scan_cols)
 
 
 # ---- screening network of the learned form ----

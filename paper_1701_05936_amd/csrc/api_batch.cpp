@@ -44,6 +44,58 @@ bl_status bpool_reserve(bl_ctx ctx, int nprob, int64_t need, const std::vector<i
     return BL_OK;
 }
 
+// Pick the variant of the shared scan for this shape (workgroup width, register prefetch): time each
+// candidate on up to 32,768 columns (raw products against the row masks) and keep the fastest.  Every candidate computes each
+// column's products in the same order, so the choice never changes results.
+bl_status tune_bscan(bl_ctx ctx, const Mat& m, const double* B, int nprob, BatchScalars* bs, double* out) {
+    if (ctx->bscan_n == m.n_total && ctx->bscan_p == m.p && ctx->bscan_x == m.xtype) return BL_OK;
+    hipStream_t st = ctx->stream;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(ctx, BL_ERR_DEVICE, "hipEventCreate failed");
+    }
+    const int64_t cols = m.p < 32768 ? m.p : 32768;
+    float best = 1e30f;
+    int pick = 1;
+    bl_status s = BL_OK;
+    for (int w = 0; w < BSCAN_VARIANTS; ++w) {
+        hipError_t e = launch_bscan(m, 0, nullptr, nullptr, cols, B, nprob, bs, nullptr, nullptr, nullptr, out, st, w);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int r = 0; r < 2 && e == hipSuccess; ++r)
+            e = launch_bscan(m, 0, nullptr, nullptr, cols, B, nprob, bs, nullptr, nullptr, nullptr, out, st, w);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            s = fail(ctx, BL_ERR_DEVICE, "scan tuning: %s", hipGetErrorString(e));
+            break;
+        }
+        if (ms < best) {
+            best = ms;
+            pick = w;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != BL_OK) return s;
+    ctx->bscan_n = m.n_total;
+    ctx->bscan_p = m.p;
+    ctx->bscan_x = m.xtype;
+    ctx->bscan_waves = pick;
+    return BL_OK;
+}
+
+struct GraphSet {
+    hipGraphExec_t x[2] = {nullptr, nullptr};
+    ~GraphSet() {
+        for (auto& g : x)
+            if (g) (void)hipGraphExecDestroy(g);
+    }
+};
+
 }  // namespace
 
 extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_batch* bt, const bl_path_opts* opts,
@@ -121,6 +173,8 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
     ENSURE(BB_B1, P8, b1);
     ENSURE(BB_STATS, (size_t)NB * K * sizeof(LamStats), stats);
     ENSURE(BB_CMP, std::max(b_compact_scratch_bytes(p), compact_scratch_bytes(p)), cmp);
+    int64_t* kdev;   // lambda step counter read by the replayed screening graph
+    ENSURE(BB_KDEV, 8, kdev);
 
     // pinned host staging: every write to it is followed by a stream synchronization before the next one
     struct Pinned {
@@ -151,14 +205,17 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
     if (!bt->masks) HIPCHK(launch_fill_u8(masks, 1, (int64_t)NB * nt, st));
     HIPCHK(launch_b_masks(masks, nt, NB, Mb, st));
     HIPCHK(launch_b_center_y(masks, bt->Y, nt, NB, Yt, R, bs, st));
+    if ((s = tune_bscan(ctx, m, Mb, NB, bs, S1))) return s;
+    const int waves = ctx->bscan_waves;   // the variant picked for this shape
+    res->scan_cols = bscan_variant_cols(waves);
     prof_mark(ctx, 0);
-    HIPCHK(launch_bscan(m, 0, nullptr, nullptr, p, Mb, NB, bs, nullptr, nullptr, nullptr, S1, st));
-    HIPCHK(launch_bscan(m, 1, nullptr, nullptr, p, Mb, NB, bs, nullptr, nullptr, nullptr, S2, st));
+    HIPCHK(launch_bscan(m, 0, nullptr, nullptr, p, Mb, NB, bs, nullptr, nullptr, nullptr, S1, st, waves));
+    HIPCHK(launch_bscan(m, 1, nullptr, nullptr, p, Mb, NB, bs, nullptr, nullptr, nullptr, S2, st, waves));
     prof_mark(ctx, 1);
     HIPCHK(launch_b_stats(S1, S2, p, NB, bs, c, sd, keep, st));
     HIPCHK(launch_b_sum_r(R, nt, NB, bs, st));
     prof_mark(ctx, 2);
-    HIPCHK(launch_bscan(m, 2, nullptr, nullptr, p, Yt, NB, bs, c, sd, keep, a, st));
+    HIPCHK(launch_bscan(m, 2, nullptr, nullptr, p, Yt, NB, bs, c, sd, keep, a, st, waves));
     prof_mark(ctx, 3);
     HIPCHK(launch_b_argmax(a, keep, p, NB, bs, st));
     if ((s = read_bs())) return s;
@@ -178,7 +235,7 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
         HIPCHK(launch_b_std_column(m, masks, NB, bs, c, sd, Bm, st));
         HIPCHK(launch_b_sum_r(Bm, nt, NB, bs, st));   // the mode-2 scan subtracts c_j * (sum of the right-hand side)
         prof_mark(ctx, 2);
-        HIPCHK(launch_bscan(m, 2, nullptr, nullptr, p, Bm, NB, bs, c, sd, keep, bb, st));
+        HIPCHK(launch_bscan(m, 2, nullptr, nullptr, p, Bm, NB, bs, c, sd, keep, bb, st, waves));
         prof_mark(ctx, 3);
         HIPCHK(launch_b_sum_r(R, nt, NB, bs, st));    // back to the residual's sum and ||y~||^2
         HIPCHK(hipStreamSynchronize(st));
@@ -189,9 +246,10 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
     for (int b = 0; b < NB; ++b)
         for (int k = 0; k < K; ++k)
             lam[(size_t)b * K + k] = K == 1 ? lmax[b] : lmax[b] * std::pow(opts->lambda_min_ratio, (double)k / (K - 1));
-    for (int k = 0; k < K; ++k)
+    for (int k = 0; k <= K; ++k)   // row K repeats row K-1: the last step's "next" safe set is its own
         for (int b = 0; b < NB; ++b) {
-            lg[(size_t)k * BNP + b] = lam[(size_t)b * K + k];
+            lg[(size_t)k * BNP + b] = lam[(size_t)b * K + (k < K ? k : K - 1)];
+            if (k == K) continue;
             tg[(size_t)k * BNP + b] = k > 0 ? 2.0 * lam[(size_t)b * K + k] - lam[(size_t)b * K + k - 1] : lam[(size_t)b * K];
         }
     HIPCHK(hipMemcpyAsync(lamg, lg.data(), lg.size() * 8, hipMemcpyHostToDevice, st));
@@ -205,12 +263,51 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
     std::vector<int32_t> h_sweeps((size_t)NB * K, 0), h_rounds((size_t)NB * K, 0);
     std::vector<int64_t> h_viol((size_t)NB * K, 0);
     int64_t ge_cap = 0;  // per-problem stride of the working-set Gram buffer (elements)
-    double* zprev = a;   // z of every problem at its previous lambda (a at lambda_max)
+    // z of every problem at its previous lambda: at step k it is in z1 for odd k, z0 for even k (z at
+    // lambda_max is a, copied to z1 for step 1)
+    HIPCHK(hipMemcpyAsync(z1, a, P8, hipMemcpyDeviceToDevice, st));
+    double* zprev = z1;
     double* zcur = z0;
     bl_status final_status = BL_OK;
 
+    // Screening of a lambda step: S_k per problem and its size, the scan list (union over problems of
+    // S_{k+1}; of S_k at the last step, whose row K of the grid repeats K-1) and the working sets E_k.
+    // With kd the step comes from the device counter (graph replays), otherwise from k.
+    auto screen_step = [&](hipStream_t s2, const int64_t* kd, int k, const double* zp) -> hipError_t {
+        const int ko = kd ? 0 : k;
+        hipError_t e = launch_b_bedpp(p, NB, a, bb, keep, bedpp, bs, lamg, ko, kd, safe, s2);
+        if (e == hipSuccess) e = launch_b_compact(safe, p, NB, want_all, lsafe, safecnt, cmp, s2);
+        if (e == hipSuccess) e = launch_b_bedpp(p, NB, a, bb, keep, bedpp, bs, lamg, ko + 1, kd, safen, s2);
+        if (e == hipSuccess) e = launch_b_union(p, NB, safen, uni, s2);
+        if (e == hipSuccess) e = launch_compact(uni, p, lT, lenT, cmp, s2);
+        if (e == hipSuccess) e = launch_b_ssr(p, NB, safe, beta, zp, ssr, thrg, ko, kd, want_all, strong, s2);
+        if (e == hipSuccess) e = launch_b_compact(strong, p, NB, want_all, lE, lens, cmp, s2);
+        return e;
+    };
+    GraphSet graphs;
+    const bool use_graph = !(bt->flags & BL_BATCH_EAGER) && K > 2;
+    if (use_graph) {
+        if (!ctx->aux) HIPCHK(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+        for (int par = 0; par < 2; ++par) {
+            hipGraph_t g = nullptr;
+            HIPCHK(hipStreamBeginCapture(ctx->aux, hipStreamCaptureModeThreadLocal));
+            const hipError_t ce = screen_step(ctx->aux, kdev, 0, par ? z1 : z0);
+            const hipError_t ee = hipStreamEndCapture(ctx->aux, &g);
+            hipError_t ie = hipSuccess;
+            if (ce == hipSuccess && ee == hipSuccess) ie = hipGraphInstantiate(&graphs.x[par], g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
+            if (ce != hipSuccess || ee != hipSuccess || ie != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(ctx, BL_ERR_DEVICE, "capturing the screening step: %s",
+                            hipGetErrorString(ce != hipSuccess ? ce : (ee != hipSuccess ? ee : ie)));
+            }
+        }
+    }
+    HIPCHK(hipMemsetAsync(kdev, 0, 8, st));
+    HIPCHK(launch_b_kinc(kdev, st));   // the counter holds the step being screened: 1
+
     // lambda index 0 is lambda_max of every problem: beta = 0
-    HIPCHK(launch_b_bedpp(p, NB, a, bb, keep, bedpp, bs, lamg, safe, st));
+    HIPCHK(launch_b_bedpp(p, NB, a, bb, keep, bedpp, bs, lamg, 0, nullptr, safe, st));
     HIPCHK(launch_b_compact(safe, p, NB, want_all, lsafe, safecnt, cmp, st));
     HIPCHK(launch_b_record(lE, lens, p, NB, beta, c, sd, bs, lamg, stats, 0, K, safecnt, st));
     if (res->beta)
@@ -219,18 +316,8 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
 
     for (int k = 1; k < K; ++k) {
         const double* lam_k = lamg + (size_t)k * BNP;
-        // S_k per problem and its size; the scan list is the union over problems of S_{k+1} (of S_k at the end)
-        HIPCHK(launch_b_bedpp(p, NB, a, bb, keep, bedpp, bs, lam_k, safe, st));
-        HIPCHK(launch_b_compact(safe, p, NB, want_all, lsafe, safecnt, cmp, st));
-        if (k + 1 < K) {
-            HIPCHK(launch_b_bedpp(p, NB, a, bb, keep, bedpp, bs, lam_k + BNP, safen, st));
-            HIPCHK(launch_b_union(p, NB, safen, uni, st));
-        } else {
-            HIPCHK(launch_b_union(p, NB, safe, uni, st));
-        }
-        HIPCHK(launch_compact(uni, p, lT, lenT, cmp, st));
-        HIPCHK(launch_b_ssr(p, NB, safe, beta, zprev, ssr, thrg + (size_t)k * BNP, want_all, strong, st));
-        HIPCHK(launch_b_compact(strong, p, NB, want_all, lE, lens, cmp, st));
+        if (use_graph) HIPCHK(hipGraphLaunch(graphs.x[k & 1], st));
+        else HIPCHK(screen_step(st, nullptr, k, zprev));
         std::vector<uint8_t> act(NB, 1);
         std::vector<int> rounds(NB, 0);
         const uint8_t* wv = want_all;
@@ -268,7 +355,7 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
             HIPCHK(launch_b_sum_r(R, nt, NB, bs, st));
             // post-convergence scan of every problem over the union list, then each problem's check
             prof_mark(ctx, 2);
-            HIPCHK(launch_bscan(m, 2, lT, lenT, 0, R, NB, bs, c, sd, keep, zcur, st));
+            HIPCHK(launch_bscan(m, 2, lT, lenT, 0, R, NB, bs, c, sd, keep, zcur, st, waves));
             prof_mark(ctx, 3);
             if (ssr) HIPCHK(launch_b_viol(lT, lenT, p, NB, zcur, safe, strong, lam_k, wv, bs, st));
             HIPCHK(hipMemcpyAsync(&hp->lenT, lenT, 8, hipMemcpyDeviceToHost, st));
@@ -310,6 +397,7 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
         if (res->beta)
             HIPCHK(hipMemcpy2DAsync(res->beta + (size_t)k * p, (size_t)K * p * 8, beta, p * 8, p * 8, NB,
                                     hipMemcpyDeviceToDevice, st));
+        HIPCHK(launch_b_kinc(kdev, st));
         res->k_done = k + 1;
         zprev = zcur;
         zcur = (zcur == z0) ? z1 : z0;

@@ -56,13 +56,14 @@ int grid_for(int64_t work, int per_block, int max_blocks) {
 // tiles) against four 16-problem tiles.  Rows go in batches of BS_K = 64: lane (m, kq) holds 16 consecutive
 // rows of its column (rows i0 + 16kq .. +15) and feeds row i0 + 16kq + st at MFMA step st; the same rows of B
 // come from LDS (double buffered, padded rows against bank conflicts).  The next batch's X values are loaded
-// into registers while the current batch is on the matrix cores.  WAVES (2, 4 or 8) is picked per shape by
-// the autotuner: wider workgroups stage each B batch for more columns, narrower ones give more workgroups.
+// into registers while the current batch is on the matrix cores when PF is set (more registers, fewer waves
+// in flight).  WAVES (2, 4 or 8) and PF are picked per shape by the autotuner: wider workgroups stage each
+// B batch for more columns, narrower ones give more workgroups.
 constexpr int BS_K = 64;
 constexpr int BS_LD = BNP + 2;   // LDS row stride of the staged B rows (doubles)
 
 // mode 0: raw dot products; mode 1: squared X (masked second moments); mode 2: standardized correlations
-template <typename XT, int MODE, int WAVES>
+template <typename XT, int MODE, int WAVES, bool PF>
 __global__ __launch_bounds__(64 * WAVES) void k_bscan(const XT* __restrict__ X, int64_t ldx, int64_t n_total,
                                                       int64_t n_pad, const int32_t* __restrict__ cols,
                                                       const int64_t* __restrict__ len_dev, int64_t len_host,
@@ -118,10 +119,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_bscan(const XT* __restrict__ X, 
         }
     };
     int buf = 0;
-    load(0);
+    if (PF) load(0);
     stage(0, 0);
     __syncthreads();
     for (int64_t i0 = 0; i0 < n_pad; i0 += BS_K) {
+        if (!PF) load(i0);
         double xa[2][16];
 #pragma unroll
         for (int ft = 0; ft < 2; ++ft)
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_bscan(const XT* __restrict__ X, 
                 xa[ft][q] = MODE == 1 ? v * v : v;
             }
         if (i0 + BS_K < n_pad) {
-            load(i0 + BS_K);
+            if (PF) load(i0 + BS_K);
             stage(buf ^ 1, i0 + BS_K);
         }
         const double* Bb = Bl[buf];
@@ -312,11 +314,18 @@ __global__ void k_b_std_column(const XT* __restrict__ X, int64_t ldx, int64_t n_
 }
 
 // ---- screening ----------------------------------------------------------------------------------------
+// lambda values of step k: lamg[k * BNP + b]; k = koff, plus *kdev when kdev is given (graph replays)
+__device__ __forceinline__ const double* step_row(const double* lamg, int koff, const int64_t* kdev) {
+    return lamg + ((kdev ? *kdev : 0) + koff) * (int64_t)BNP;
+}
+
 __global__ void k_b_bedpp(int64_t p, int nprob, const double* __restrict__ a, const double* __restrict__ bb,
                           const uint8_t* __restrict__ keep, int bedpp, const BatchScalars* __restrict__ bs,
-                          const double* __restrict__ lam, uint8_t* __restrict__ safe) {
+                          const double* __restrict__ lamg, int koff, const int64_t* __restrict__ kdev,
+                          uint8_t* __restrict__ safe) {
     const int b = blockIdx.y;
     if (b >= nprob) return;
+    const double* lam = step_row(lamg, koff, kdev);
     const double lm = bs[b].lmax, l = lam[b], sg = bs[b].sign_star;
     double slack = bs[b].yy / (double)bs[b].n_rows - lm * lm;
     if (slack < 0.0) slack = 0.0;
@@ -330,11 +339,12 @@ __global__ void k_b_bedpp(int64_t p, int nprob, const double* __restrict__ a, co
 }
 
 __global__ void k_b_ssr(int64_t p, int nprob, const uint8_t* __restrict__ safe, const double* __restrict__ beta,
-                        const double* __restrict__ zprev, int ssr, const double* __restrict__ thr,
-                        const uint8_t* __restrict__ want, uint8_t* __restrict__ strong) {
+                        const double* __restrict__ zprev, int ssr, const double* __restrict__ thrg, int koff,
+                        const int64_t* __restrict__ kdev, const uint8_t* __restrict__ want,
+                        uint8_t* __restrict__ strong) {
     const int b = blockIdx.y;
     if (b >= nprob || !want[b]) return;
-    const double t = thr[b];
+    const double t = step_row(thrg, koff, kdev)[b];
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < p; j += (int64_t)gridDim.x * blockDim.x) {
         const int64_t bj = (int64_t)b * p + j;
         uint8_t o = 0;
@@ -773,7 +783,7 @@ __global__ __launch_bounds__(1024) void k_b_record(const int32_t* __restrict__ s
 // ---- launchers -------------------------------------------------------------------------------------------------
 int64_t batch_pad(int64_t n_total) { return (n_total + BS_K - 1) / BS_K * BS_K; }
 
-template <typename XT, int WAVES>
+template <typename XT, int WAVES, bool PF>
 static hipError_t bscan_typed(const Mat& mt, int mode, const int32_t* cols, const int64_t* len_dev, int64_t len_host,
                               const double* B, int nprob, BatchScalars* bs, const double* c, const double* s,
                               const uint8_t* keep, double* out, hipStream_t st) {
@@ -784,32 +794,42 @@ static hipError_t bscan_typed(const Mat& mt, int mode, const int32_t* cols, cons
     const XT* X = (const XT*)mt.X;
     if (g <= 0) return hipSuccess;
     if (mode == 0)
-        k_bscan<XT, 0, WAVES><<<g, 64 * WAVES, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, cols, len_dev, len_host, B, nprob,
+        k_bscan<XT, 0, WAVES, PF><<<g, 64 * WAVES, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, cols, len_dev, len_host, B, nprob,
                                                        mt.p, bs, c, s, keep, out);
     else if (mode == 1)
-        k_bscan<XT, 1, WAVES><<<g, 64 * WAVES, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, cols, len_dev, len_host, B, nprob,
+        k_bscan<XT, 1, WAVES, PF><<<g, 64 * WAVES, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, cols, len_dev, len_host, B, nprob,
                                                        mt.p, bs, c, s, keep, out);
     else
-        k_bscan<XT, 2, WAVES><<<g, 64 * WAVES, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, cols, len_dev, len_host, B, nprob,
+        k_bscan<XT, 2, WAVES, PF><<<g, 64 * WAVES, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, cols, len_dev, len_host, B, nprob,
                                                        mt.p, bs, c, s, keep, out);
     return hipGetLastError();
 }
 
 template <typename XT>
-static hipError_t bscan_waves(int waves, const Mat& mt, int mode, const int32_t* cols, const int64_t* len_dev,
+static hipError_t bscan_waves(int variant, const Mat& mt, int mode, const int32_t* cols, const int64_t* len_dev,
                               int64_t len_host, const double* B, int nprob, BatchScalars* bs, const double* c,
                               const double* s, const uint8_t* keep, double* out, hipStream_t st) {
-    if (waves == 2) return bscan_typed<XT, 2>(mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
-    if (waves == 8) return bscan_typed<XT, 8>(mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
-    return bscan_typed<XT, 4>(mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
+#define BSCAN_CASE(V, W, P) \
+    case V: return bscan_typed<XT, W, P>(mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
+    switch (variant) {
+        BSCAN_CASE(0, 2, false)
+        BSCAN_CASE(2, 8, false)
+        BSCAN_CASE(3, 2, true)
+        BSCAN_CASE(4, 4, true)
+        BSCAN_CASE(5, 8, true)
+        default: return bscan_typed<XT, 4, false>(mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
+    }
+#undef BSCAN_CASE
 }
+
+int bscan_variant_cols(int variant) { return 32 * (variant % 3 == 0 ? 2 : (variant % 3 == 1 ? 4 : 8)); }
 
 hipError_t launch_bscan(const Mat& mt, int mode, const int32_t* cols, const int64_t* len_dev, int64_t len_host,
                         const double* B, int nprob, BatchScalars* bs, const double* c, const double* s,
-                        const uint8_t* keep, double* out, hipStream_t st, int waves) {
+                        const uint8_t* keep, double* out, hipStream_t st, int variant) {
     if (mt.xtype == 0)
-        return bscan_waves<double>(waves, mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
-    return bscan_waves<float>(waves, mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
+        return bscan_waves<double>(variant, mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
+    return bscan_waves<float>(variant, mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
 }
 
 hipError_t launch_b_masks(const uint8_t* masks, int64_t n_total, int nprob, double* Mb, hipStream_t st) {
@@ -855,16 +875,18 @@ hipError_t launch_b_std_column(const Mat& mt, const uint8_t* masks, int nprob, c
 }
 
 hipError_t launch_b_bedpp(int64_t p, int nprob, const double* a, const double* bb, const uint8_t* keep, bool bedpp,
-                          const BatchScalars* bs, const double* lam, uint8_t* safe, hipStream_t st) {
+                          const BatchScalars* bs, const double* lamg, int koff, const int64_t* kdev, uint8_t* safe,
+                          hipStream_t st) {
     dim3 grid(grid_for(p, 256, 256), nprob);
-    k_b_bedpp<<<grid, 256, 0, st>>>(p, nprob, a, bb, keep, bedpp ? 1 : 0, bs, lam, safe);
+    k_b_bedpp<<<grid, 256, 0, st>>>(p, nprob, a, bb, keep, bedpp ? 1 : 0, bs, lamg, koff, kdev, safe);
     return hipGetLastError();
 }
 
 hipError_t launch_b_ssr(int64_t p, int nprob, const uint8_t* safe, const double* beta, const double* zprev, bool ssr,
-                        const double* thr, const uint8_t* want, uint8_t* strong, hipStream_t st) {
+                        const double* thrg, int koff, const int64_t* kdev, const uint8_t* want, uint8_t* strong,
+                        hipStream_t st) {
     dim3 grid(grid_for(p, 256, 256), nprob);
-    k_b_ssr<<<grid, 256, 0, st>>>(p, nprob, safe, beta, zprev, ssr ? 1 : 0, thr, want, strong);
+    k_b_ssr<<<grid, 256, 0, st>>>(p, nprob, safe, beta, zprev, ssr ? 1 : 0, thrg, koff, kdev, want, strong);
     return hipGetLastError();
 }
 
@@ -949,6 +971,13 @@ hipError_t launch_b_r_update(const Mat& mt, const uint8_t* masks, const int32_t*
     else
         k_b_r_update<float><<<grid, 256, 0, st>>>((const float*)mt.X, mt.ldx, mt.n_total, masks, sets, lens, mt.p, want,
                                                   b0, b1, c, s, R);
+    return hipGetLastError();
+}
+
+__global__ void k_b_kinc(int64_t* kdev) { *kdev += 1; }
+
+hipError_t launch_b_kinc(int64_t* kdev, hipStream_t st) {
+    k_b_kinc<<<1, 1, 0, st>>>(kdev);
     return hipGetLastError();
 }
 

@@ -31,7 +31,10 @@ struct bl_ctx_s {
     int bpool_np = 0;                    // problems the batched pools were allocated for
     double* bgpool = nullptr;
     void* bpinned = nullptr;            // pinned host staging of the batched driver
-    hipStream_t aux = nullptr;          // library-owned stream for captured graphs (network training)
+    hipStream_t aux = nullptr;          // library-owned stream for captured graphs
+    // batched scan variant picked for the last shape (n_total, p, xtype)
+    int64_t bscan_n = -1, bscan_p = -1;
+    int bscan_x = -1, bscan_waves = 1;
     // kernel timing
     bool prof = false;
     hipEvent_t ev[10] = {};
@@ -50,7 +53,7 @@ enum BufId {
     BB_SAFEN, BB_STRONG, BB_UNION, BB_LT, BB_LE, BB_LENS, BB_LAM, BB_THR, BB_WANT, BB_BS, BB_BETA, BB_POS, BB_LIST,
     BB_GE, BB_G0, BB_B0, BB_B1, BB_STATS, BB_CMP, BB_LSAFE, BB_SAFECNT, BB_WANTALL,
     // learned form and its network
-    B_ZH, B_CAND, B_RECN, B_LC, M_PART, M_LOSSP, M_MOM, M_VEL, M_STEP, M_PERM, M_LOSSH, M_PROB, M_HIST,
+    B_ZH, B_CAND, B_RECN, B_LC, BB_KDEV, M_PART, M_LOSSP, M_MOM, M_VEL, M_STEP, M_PERM, M_LOSSH, M_PROB, M_HIST,
     B_COUNT
 };
 

@@ -204,10 +204,13 @@ struct BatchScalars {
 int64_t batch_pad(int64_t n_total);  // rows of the row-major right-hand sides (multiple of 64)
 // out[b*p + j] for j = cols[t]: mode 0 raw x_j' B[:, b]; mode 1 (x_j o x_j)' B[:, b];
 // mode 2 (x_j' B[:, b] - c_bj sum_r(b)) / (n_b s_bj)
-// waves per workgroup (2, 4 or 8): 32 waves columns per workgroup
+// variant 0..5: workgroups of 2, 4, 8 waves (64, 128, 256 columns), without (0-2) or with (3-5) register
+// prefetch of the next row batch
+constexpr int BSCAN_VARIANTS = 6;
+int bscan_variant_cols(int variant);
 hipError_t launch_bscan(const Mat& mt, int mode, const int32_t* cols, const int64_t* len_dev, int64_t len_host,
                         const double* B, int nprob, BatchScalars* bs, const double* c, const double* s,
-                        const uint8_t* keep, double* out, hipStream_t st, int waves = 4);
+                        const uint8_t* keep, double* out, hipStream_t st, int variant = 1);
 hipError_t launch_b_masks(const uint8_t* masks, int64_t n_total, int nprob, double* Mb, hipStream_t st);
 hipError_t launch_b_center_y(const uint8_t* masks, const double* Y, int64_t n_total, int nprob, double* Yt, double* R,
                              BatchScalars* bs, hipStream_t st);
@@ -218,10 +221,14 @@ hipError_t launch_b_argmax(const double* a, const uint8_t* keep, int64_t p, int 
                            hipStream_t st);
 hipError_t launch_b_std_column(const Mat& mt, const uint8_t* masks, int nprob, const BatchScalars* bs, const double* c,
                                const double* s, double* Bm, hipStream_t st);
+// lambda (threshold) of problem b at step k = koff (+ *kdev if kdev): lamg[k * BNP + b]
 hipError_t launch_b_bedpp(int64_t p, int nprob, const double* a, const double* bb, const uint8_t* keep, bool bedpp,
-                          const BatchScalars* bs, const double* lam, uint8_t* safe, hipStream_t st);
+                          const BatchScalars* bs, const double* lamg, int koff, const int64_t* kdev, uint8_t* safe,
+                          hipStream_t st);
 hipError_t launch_b_ssr(int64_t p, int nprob, const uint8_t* safe, const double* beta, const double* zprev, bool ssr,
-                        const double* thr, const uint8_t* want, uint8_t* strong, hipStream_t st);
+                        const double* thrg, int koff, const int64_t* kdev, const uint8_t* want, uint8_t* strong,
+                        hipStream_t st);
+hipError_t launch_b_kinc(int64_t* kdev, hipStream_t st);
 hipError_t launch_b_union(int64_t p, int nprob, const uint8_t* mask, uint8_t* out, hipStream_t st);
 hipError_t launch_b_viol(const int32_t* cols, const int64_t* len_dev, int64_t p, int nprob, const double* z,
                          const uint8_t* in_s, uint8_t* inE, const double* lam, const uint8_t* want, BatchScalars* bs,

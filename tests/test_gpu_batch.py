@@ -86,6 +86,19 @@ def test_batch_equals_single_problem_batches(gpu_ctx):
         np.testing.assert_array_equal(one.n_active[0], full.n_active[b])
 
 
+def test_graph_replayed_steps_equal_eager_launches(gpu_ctx):
+    """The screening kernels of every lambda step replayed from the captured graph give the eagerly
+    launched results bit for bit; the autotuned scan width is one of the candidates."""
+    rec, X32, Y, masks = cv_problem(800, 1700, 5, 2, seed_shift=11)
+    Xd, Yd, Md = to_dev(X32), to_dev(Y), to_dev(masks)
+    g = bl.fit_path_batch(gpu_ctx, Xd, Yd, Md, nlambda=20, lambda_min_ratio=0.1, tol=1e-10)
+    e = bl.fit_path_batch(gpu_ctx, Xd, Yd, Md, nlambda=20, lambda_min_ratio=0.1, tol=1e-10, eager=True)
+    assert torch.equal(g.beta, e.beta)
+    np.testing.assert_array_equal(g.n_strong, e.n_strong)
+    np.testing.assert_array_equal(g.n_safe, e.n_safe)
+    assert g.scan_cols in (64, 128, 256)
+
+
 def test_batch_is_deterministic(gpu_ctx):
     rec, X32, Y, masks = cv_problem(700, 900, 6, 2, seed_shift=3)
     Xd, Yd, Md = to_dev(X32), to_dev(Y), to_dev(masks)
