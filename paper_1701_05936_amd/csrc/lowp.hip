@@ -24,6 +24,12 @@ namespace {
 
 constexpr int WAVE = 64;
 constexpr int SCAN_KC = 128;    // rows per load batch (4 MFMA steps of 32 rows)
+constexpr int SCAN_U = 4;       // batches whose loads are in flight together
+
+// Rows of a 128-row batch fed by lane group g (lanes 16g..16g+15) at MFMA step st: 8 consecutive rows,
+// arranged so that each 16-byte load instruction of the wave covers whole 64-byte spans of a column
+// (steps 0, 1: rows 16g .. 16g+15; steps 2, 3: rows 64+16g .. 64+16g+15).
+__device__ __forceinline__ int lane_row(int g, int st) { return st < 2 ? 16 * g + 8 * st : 64 + 16 * g + 8 * (st - 2); }
 constexpr int SCAN_PROMOTE = 32; // rows per FP32 chunk: the accumulator goes to FP64 after every MFMA step
 constexpr int NPIECE = LOWP_PIECES;
 
@@ -93,26 +99,56 @@ __global__ __launch_bounds__(256) void k_scan_bf16(const int8_t* __restrict__ X,
         double acc64[4] = {0.0, 0.0, 0.0, 0.0};
         const bool bpiece = m < NPIECE;
         const __bf16* pr = P + (int64_t)(bpiece ? m : 0) * n_pad;
-        int64_t i0 = 0;
-        for (; i0 < nfull; i0 += SCAN_KC) {
-            v4i32 w0 = {0, 0, 0, 0}, w1 = {0, 0, 0, 0};
-            if (valid) {
-                const v4i32* xp = reinterpret_cast<const v4i32*>(xc + i0 + 32 * g);
-                w0 = __builtin_nontemporal_load(xp);
-                w1 = __builtin_nontemporal_load(xp + 1);
+        // one batch of SCAN_KC rows: 4 MFMA steps of 32 rows, each FP32 result promoted to FP64
+        auto batch = [&](const v4i32& w0, const v4i32& w1, int64_t ib) {
+            // residual pieces of the 4 steps first (one wait for all), zero in lanes past the pieces
+            bf16x8 bq[4];
+            const bf16x8 bzero = {};
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                const bf16x8 t = *reinterpret_cast<const bf16x8*>(pr + ib + lane_row(g, st));
+                bq[st] = bpiece ? t : bzero;
             }
             const uint32_t wd[8] = {(uint32_t)w0.x, (uint32_t)w0.y, (uint32_t)w0.z, (uint32_t)w0.w,
                                     (uint32_t)w1.x, (uint32_t)w1.y, (uint32_t)w1.z, (uint32_t)w1.w};
+            // the 4 steps go to the matrix cores back to back; each 32-row FP32 result is then promoted
+            f32x4 r[4];
 #pragma unroll
             for (int st = 0; st < 4; ++st) {
                 const bf16x8 a = codes_to_bf16(wd[2 * st], wd[2 * st + 1]);
-                bf16x8 b = {};
-                if (bpiece) b = *reinterpret_cast<const bf16x8*>(pr + i0 + 32 * g + 8 * st);
                 const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
-                const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, zero, 0, 0, 0);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc64[q] += (double)acc[q];
+                r[st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bq[st], zero, 0, 0, 0);
             }
+#pragma unroll
+            for (int st = 0; st < 4; ++st)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc64[q] += (double)r[st][q];
+        };
+        // SCAN_U batches' loads are issued before the first is used (memory parallelism per wave)
+        int64_t i0 = 0;
+        for (; i0 + SCAN_U * SCAN_KC <= nfull; i0 += SCAN_U * SCAN_KC) {
+            v4i32 w[SCAN_U][2];
+#pragma unroll
+            for (int u = 0; u < SCAN_U; ++u) {
+                w[u][0] = (v4i32){0, 0, 0, 0};
+                w[u][1] = (v4i32){0, 0, 0, 0};
+                if (valid) {
+                    const v4i32* xp = reinterpret_cast<const v4i32*>(xc + i0 + u * SCAN_KC + 16 * g);
+                    w[u][0] = __builtin_nontemporal_load(xp);
+                    w[u][1] = __builtin_nontemporal_load(xp + 4);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SCAN_U; ++u) batch(w[u][0], w[u][1], i0 + u * SCAN_KC);
+        }
+        for (; i0 < nfull; i0 += SCAN_KC) {
+            v4i32 w0 = {0, 0, 0, 0}, w1 = {0, 0, 0, 0};
+            if (valid) {
+                const v4i32* xp = reinterpret_cast<const v4i32*>(xc + i0 + 16 * g);
+                w0 = __builtin_nontemporal_load(xp);
+                w1 = __builtin_nontemporal_load(xp + 4);
+            }
+            batch(w0, w1, i0);
         }
         if (i0 < n_total) {
             // ragged tail: codes past n_total meet zero residual pieces, but are not read
@@ -122,7 +158,7 @@ __global__ __launch_bounds__(256) void k_scan_bf16(const int8_t* __restrict__ X,
                 uint32_t w = 0;
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
-                    const int64_t i = i0 + 32 * g + 4 * k + b;
+                    const int64_t i = i0 + (k < 4 ? 16 * g + 4 * k : 64 + 16 * g + 4 * (k - 4)) + b;
                     const uint32_t v = (valid && i < n_total) ? (uint32_t)(uint8_t)xc[i] : 0u;
                     w |= v << (8 * b);
                 }
@@ -132,7 +168,7 @@ __global__ __launch_bounds__(256) void k_scan_bf16(const int8_t* __restrict__ X,
             for (int st = 0; st < 4; ++st) {
                 const bf16x8 a = codes_to_bf16(wd[2 * st], wd[2 * st + 1]);
                 bf16x8 b = {};
-                if (bpiece) b = *reinterpret_cast<const bf16x8*>(pr + i0 + 32 * g + 8 * st);
+                if (bpiece) b = *reinterpret_cast<const bf16x8*>(pr + i0 + lane_row(g, st));
                 const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
                 const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, zero, 0, 0, 0);
 #pragma unroll
