@@ -73,7 +73,7 @@ def cpu_baseline(Xt, y, rec, cols, tol, mask=None, what="path"):
 
 def kernel_table(ctx, bl, elapsed):
     names = (("scan", bl.PROF_SCAN), ("bscan", bl.PROF_BSCAN), ("cd", bl.PROF_CD), ("colstats", bl.PROF_COLSTATS),
-             ("gram", bl.PROF_GRAM), ("recheck", bl.PROF_RECHECK))
+             ("gram", bl.PROF_GRAM), ("recheck", bl.PROF_RECHECK), ("setup_scan", bl.PROF_SETUP))
     kernels = {}
     for k, v in names:
         pr = ctx.profile_get(v)
@@ -180,7 +180,8 @@ def run_precision(args, rec, ctx, bl, Xd, Xt, yd, y):
                                f"{rec.nlambda} lambda to {rec.lambda_min_ratio} lambda_max, SSR-BEDPP, "
                                f"CD tol {args.tol:g}",
                    "n": rec.n, "p": rec.p, "nlambda": rec.nlambda},
-        "roofline": hbm_roofline(kernels["scan"], "k_scan_bf16 (int8 X, BF16 MFMA)"),
+        "roofline": hbm_roofline(kernels["scan"], "k_scan_bf16 (int8 X, BF16 MFMA)",
+                                 "k_scan_bf16_c3_genotype_10000x2000000_i8.md"),
         "kernels": kernels,
         "forms": {"plain_gpu_same_storage_paths_per_s": 1.0 / el_plain,
                   "speedup_vs_plain_gpu": (args.steps / elapsed) * el_plain,
@@ -231,7 +232,8 @@ def run_batch(args, rec, ctx, bl, Xd, Xt, prob):
                                f"CD tol {args.tol:g}; value counts problem paths",
                    "n": rec.n, "p": rec.p, "nlambda": rec.nlambda, "nprob": NB},
         "roofline": {"bound": "mfma", "achieved": bs["TFLOPs"], "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": bs["TFLOPs"] / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
+                     "frac": bs["TFLOPs"] / FP64_MFMA_PEAK_TFLOPS,
+                     "traffic": profiled_traffic("k_bscan_c4_ar1_20000x200000_f32_64rhs.md"),
                      "kernel": "k_bscan (X'R, 64 right-hand sides, FP64 MFMA)", "avg_launch_ms": bs["avg_ms"],
                      "TFLOP_per_launch": bs["TFLOP_per_launch"], "GBs": bs["GBs"]},
         "kernels": kernels,

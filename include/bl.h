@@ -350,6 +350,8 @@ bl_status bl_mlp_train(bl_ctx ctx, const float* feat, const float* label, int64_
  *   gram      Gram entries of new pool members and the gather of the working set's Gram
  *   rupdate   residual update after a solve: m x n_total x sizeof(element)
  *   recheck   precision form: residual pieces, error band and FP64 re-scans of flagged and set columns
+ *   setup     precision form: the two FP64 set-up scans (lambda_max and BEDPP products); the plain
+ *             path counts them under scan (same kernel)
  *   bscan     batched form: the shared X'R contraction, columns x n_total x sizeof(element) + n_total x nprob x 8
  *             bytes and 2 x columns x n_total x nprob flops per launch
  * bl_profile(ctx, 1) enables and resets the counters, bl_profile(ctx, 0) disables.
@@ -362,7 +364,7 @@ typedef struct {
 } bl_kernel_profile;
 
 enum { BL_PROF_SCAN = 0, BL_PROF_CD = 1, BL_PROF_COLSTATS = 2, BL_PROF_GRAM = 3, BL_PROF_RUPDATE = 4,
-       BL_PROF_RECHECK = 5, BL_PROF_BSCAN = 6, BL_PROF_COUNT = 7 };
+       BL_PROF_RECHECK = 5, BL_PROF_BSCAN = 6, BL_PROF_SETUP = 7, BL_PROF_COUNT = 8 };
 
 bl_status bl_profile(bl_ctx ctx, int enable);
 bl_status bl_profile_get(bl_ctx ctx, int kernel, bl_kernel_profile* out);

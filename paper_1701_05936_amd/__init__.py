@@ -34,7 +34,7 @@ EXPORTS = ("bl_create", "bl_destroy", "bl_last_error", "bl_device_info", "bl_sta
            "bl_fit_path_batch", "bl_mlp_forward", "bl_mlp_loss_grad", "bl_mlp_train", "bl_profile", "bl_profile_get")
 MLP_HIDDEN = 64
 MLP_NPARAMS = MLP_HIDDEN * MLP_HIDDEN + 7 * MLP_HIDDEN + 1
-PROF_SCAN, PROF_CD, PROF_COLSTATS, PROF_GRAM, PROF_RUPDATE, PROF_RECHECK, PROF_BSCAN = 0, 1, 2, 3, 4, 5, 6
+PROF_SCAN, PROF_CD, PROF_COLSTATS, PROF_GRAM, PROF_RUPDATE, PROF_RECHECK, PROF_BSCAN, PROF_SETUP = range(8)
 
 
 class BLError(RuntimeError):

@@ -732,7 +732,9 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
     HIPCHK(launch_argmax_abs(a, keep, p, pv, pi, ctx->sc, st));
     if ((s = read_scalars(ctx))) return s;
     prof_add(ctx, 0, BL_PROF_COLSTATS, (double)p * col_bytes);
-    prof_add(ctx, 2, BL_PROF_SCAN, (double)p * col_bytes + nt * 8.0);
+    // the set-up scans are FP64 scans; in the precision form they are kept apart from its BF16 check scans
+    const int setup_slot = lowp ? BL_PROF_SETUP : BL_PROF_SCAN;
+    prof_add(ctx, 2, setup_slot, (double)p * col_bytes + nt * 8.0);
     const double ybar = ctx->sc_host->y_mean, yy = ctx->sc_host->yy, lmax = ctx->sc_host->lmax;
     const int64_t jstar = ctx->sc_host->jstar;
     if (!std::isfinite(ybar) || !std::isfinite(yy)) return fail(ctx, BL_ERR_INVALID, "y has NaN or Inf");
@@ -755,7 +757,7 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         HIPCHK(launch_scan(m, sa, st));
         prof_mark(ctx, 3);
         HIPCHK(hipStreamSynchronize(st));
-        prof_add(ctx, 2, BL_PROF_SCAN, (double)p * col_bytes + nt * 8.0);
+        prof_add(ctx, 2, setup_slot, (double)p * col_bytes + nt * 8.0);
     }
     std::vector<double> lam(K);
     if (opts->lambda) {

@@ -134,8 +134,8 @@ __global__ __launch_bounds__(256) void k_scan_bf16(const int8_t* __restrict__ X,
                 w[u][1] = (v4i32){0, 0, 0, 0};
                 if (valid) {
                     const v4i32* xp = reinterpret_cast<const v4i32*>(xc + i0 + u * SCAN_KC + 16 * g);
-                    w[u][0] = __builtin_nontemporal_load(xp);
-                    w[u][1] = __builtin_nontemporal_load(xp + 4);
+                    w[u][0] = xp[0];
+                    w[u][1] = xp[4];
                 }
             }
 #pragma unroll
@@ -145,8 +145,8 @@ __global__ __launch_bounds__(256) void k_scan_bf16(const int8_t* __restrict__ X,
             v4i32 w0 = {0, 0, 0, 0}, w1 = {0, 0, 0, 0};
             if (valid) {
                 const v4i32* xp = reinterpret_cast<const v4i32*>(xc + i0 + 16 * g);
-                w0 = __builtin_nontemporal_load(xp);
-                w1 = __builtin_nontemporal_load(xp + 4);
+                w0 = xp[0];
+                w1 = xp[4];
             }
             batch(w0, w1, i0);
         }
