@@ -331,7 +331,13 @@ __device__ __forceinline__ void load_gblock(const double* __restrict__ G, int64_
 }
 
 // LDS arena shared by the two roles (a workgroup is either the leader or a helper)
-constexpr int LEAD_LDS = 3 * (SLACK + 1) * MB * MB + 2 * 2 * MB + (SLACK + 1) * MB + 2 * 2 * MB + 8;
+// leader rings: Gram sets (GR), changes (DR, at least SLACK + 2), chain results awaiting publication (OR)
+constexpr int GR = 4, DR = 8, OR = 4;
+// leader counters in LDS: chains run, blocks prepared, blocks published, Gram sets loaded (each a count of
+// sequences), the sequence count at which the chain stopped (INT_MAX while running), an error flag, and
+// the solve's results
+enum { LC_CHAIN, LC_PREP, LC_PUB, LC_GRAM, LC_STOP, LC_ERR, LC_SWEEPS, LC_STATUS, LC_N };
+constexpr int LEAD_LDS = GR * (SLACK + 1) * MB * MB + 2 * 2 * MB + DR * MB + 2 * OR * MB + 8;
 constexpr int HELP_LDS = HBATCH * HOWN * MB * MB + HBATCH * MB + HOWN * MB + (MT / MB) * HOWN * MB + 8;
 constexpr int ARENA = LEAD_LDS > HELP_LDS ? LEAD_LDS : HELP_LDS;
 
@@ -352,16 +358,28 @@ __device__ __forceinline__ uint32_t gram_off(int64_t m, int cb, int cl, int rb, 
                               : GOFF_NONE;
 }
 
-constexpr int GSET = (SLACK + 1) * (MB * MB / WAVE);  // registers per lane for one set of Gram blocks
+// The leader loads Gram sets with 16-byte loads: lane l covers rows 2 (l % 16) and 2 (l % 16) + 1 of
+// columns l / 16 + 4k, k < GPER.  32 loads per lane stay under the 63 memory operations a wave can keep
+// in flight, so issuing a set never waits for the first of its own loads to return.
+constexpr int GPER = MB * MB / (2 * WAVE);   // 16-byte loads per lane for one Gram block
+constexpr int GSET = (SLACK + 1) * GPER;      // for one set of SLACK + 1 blocks
+constexpr uint32_t GOFF_NONE2 = 0xFFFFFFF0u;  // out of range for a 16-byte load
+
+__device__ __forceinline__ double2 gram_ld2(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    const u4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0);
+    return __builtin_bit_cast(double2, v);
+}
 
 // issue the loads of the Gram blocks of block rb against its own block and the SLACK blocks run before
-// it (sequence qb and the SLACK sequences before it) into v; store_gset writes them to dst[s][t * MB + l]
+// it (sequence qb and the SLACK sequences before it) into v; store_gset writes them to dst[s][t * MB + l].
+// Rows past the block's length are zeroed: by the range check when both rows are out, by a select when
+// only the second one is.
 __device__ __forceinline__ void load_gset(__amdgpu_buffer_rsrc_t rs, int64_t m, int nb, int64_t qb, int rb,
-                                          double (&v)[GSET], int lane) {
-    constexpr int PER = MB * MB / WAVE;
+                                          double2 (&v)[GSET], int lane) {
     const int rl = blk_len(m, rb);
-    const int t0 = lane / MB, l = lane % MB;   // entry k of the lane: column t0 + 2k, row l
-    const uint32_t step = 2u * (uint32_t)m * 8u;
+    const int t0 = lane >> 4, l = 2 * (lane & 15);
+    const uint32_t step = 4u * (uint32_t)m * 8u;
 #pragma unroll
     for (int s = 0; s <= SLACK; ++s) {
         int cbk = rb - s;
@@ -370,219 +388,270 @@ __device__ __forceinline__ void load_gset(__amdgpu_buffer_rsrc_t rs, int64_t m, 
         const uint32_t base = (((uint32_t)(cbk * MB + t0)) * (uint32_t)m + (uint32_t)(rb * MB + l)) * 8u;
         const bool row_ok = l < rl;
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const bool ok = row_ok && t0 + 2 * k < cl;
-            v[s * PER + k] = gram_ld(rs, ok ? base + (uint32_t)k * step : GOFF_NONE);
+        for (int k = 0; k < GPER; ++k) {
+            const bool ok = row_ok && t0 + 4 * k < cl;
+            v[s * GPER + k] = gram_ld2(rs, ok ? base + (uint32_t)k * step : GOFF_NONE2);
         }
     }
+    if (l + 1 >= rl) {
+#pragma unroll
+        for (int k = 0; k < GSET; ++k) v[k].y = 0.0;
+    }
 }
-__device__ __forceinline__ void store_gset(const double (&v)[GSET], double* dst, int lane) {
-    constexpr int PER = MB * MB / WAVE;
+__device__ __forceinline__ void store_gset(const double2 (&v)[GSET], double* dst, int lane) {
+    const int t0 = lane >> 4, l = 2 * (lane & 15);
 #pragma unroll
     for (int s = 0; s <= SLACK; ++s)
 #pragma unroll
-        for (int k = 0; k < PER; ++k) dst[s * MB * MB + lane + k * WAVE] = v[s * PER + k];
+        for (int k = 0; k < GPER; ++k)
+            *reinterpret_cast<double2*>(dst + s * MB * MB + (t0 + 4 * k) * MB + l) = v[s * GPER + k];
+}
+
+__device__ __forceinline__ int lc_get(const int* c, int i) {
+    return __hip_atomic_load(c + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// raise a counter after this wave's stores to LDS: a wave's LDS operations complete in order, and the
+// compiler fence keeps the stores before it
+__device__ __forceinline__ void lc_set(int* c, int i, int v) {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    if ((threadIdx.x & (WAVE - 1)) == 0) __hip_atomic_store(c + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+// wait until ready() holds; false if the solve failed, if the wait outlasts `limit` wall-clock ticks (then
+// it fails the solve), or (exit_on_stop) once the chain has stopped
+template <typename Ready>
+__device__ __forceinline__ bool lead_wait(int* ctr, Ready ready, uint64_t limit, bool exit_on_stop) {
+    uint64_t t0 = 0;
+    for (uint32_t n = 0;; ++n) {
+        if (__builtin_amdgcn_readfirstlane((int)ready())) break;
+        if (__builtin_amdgcn_readfirstlane(lc_get(ctr, LC_ERR))) return false;
+        if (exit_on_stop && __builtin_amdgcn_readfirstlane(lc_get(ctr, LC_STOP)) != INT_MAX) return false;
+        if ((n & 63u) == 63u) {
+            const uint64_t t = wall_clock64();
+            if (t0 == 0) {
+                t0 = t;
+            } else if (t - t0 > limit) {
+                lc_set(ctr, LC_ERR, 1);
+                return false;
+            }
+        }
+        if (exit_on_stop) __builtin_amdgcn_s_sleep(1);
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    return true;
+}
+// store Gram set j (registers v) into ring slot j mod GR once the chain that last used the slot is done
+__device__ __forceinline__ bool lead_gram_store(int* ctr, const double2 (&v)[GSET], double* Gm, int64_t j,
+                                                uint64_t limit, int lane) {
+    if (!lead_wait(ctr, [&] { return (int64_t)lc_get(ctr, LC_CHAIN) > j - GR; }, limit, true)) return false;
+    store_gset(v, Gm + (int)(j % GR) * (SLACK + 1) * MB * MB, lane);
+    lc_set(ctr, LC_GRAM, (int)(j + 1));
+    return true;
 }
 
 __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
-    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+    // the wave index is uniform across the wave: taken through a scalar register, the per-wave branches
+    // below compile to scalar jumps instead of execution-masked code that every wave walks through
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
     const int64_t m = a.m;
     const int nb = (int)((m + MB - 1) / MB);
     const int H = a.H;
     uint32_t* sync = a.sync;
     const uint32_t spin_limit = a.spin_limit;
-    __shared__ double arena[ARENA];
+    __shared__ __attribute__((aligned(16))) double arena[ARENA];
 
     if (blockIdx.x == 0) {
         // ---------------- leader ----------------
-        // Gram blocks of block b_j in buffer j mod 3: [0] = G(b_j, b_j), [s] = G(b_j, b_{j-s}); they are
-        // loaded two sequences ahead.  Before block b_q runs, the owner has applied every change below
-        // q - SLACK, wave 2 applied the changes of q - SLACK .. q - 2 while preparing the block (one
-        // sequence ahead), and wave 0 applies the change of q - 1 itself.
-        double* Gm = arena;                                    // [3][SLACK + 1][MB * MB]
-        double* gb = Gm + 3 * (SLACK + 1) * MB * MB;           // [2][MB] gradient of the block to run
-        double* bb = gb + 2 * MB;                              // [2][MB] its coefficients
-        double* dh = bb + 2 * MB;                              // [SLACK + 1][MB] changes by sequence mod (SLACK+1)
-        double* gout = dh + (SLACK + 1) * MB;                  // [2][MB] results of a block, for publishing
-        double* bout = gout + 2 * MB;
-        double* maxd_sh = bout + 2 * MB;
-        int* err_sh = (int*)(maxd_sh + 1);
-        const double lam = a.lam;
-        if (tid == 0) {
-            *maxd_sh = 0.0;
-            *err_sh = 0;
-        }
-        // sequences 0 and 1: Gram blocks, and the gradient of block 0; wave 3 keeps the loads of the next
-        // set in flight across each iteration (set q + 3 is loaded while set q + 2 is stored)
-        const __amdgpu_buffer_rsrc_t grs = gram_rsrc(a.G, m);
-        double gv[GSET];
-        if (wv < 2) {
-            load_gset(grs, m, nb, wv, wv, gv, lane);
-            store_gset(gv, Gm + wv * (SLACK + 1) * MB * MB, lane);
-        } else if (wv == 3) {
-            load_gset(grs, m, nb, 2, 2 % nb, gv, lane);
-        }
-        if (tid < MB) {
-            const bool ok = tid < blk_len(m, 0);
-            gb[tid] = ok ? ld_coh(a.g + tid) : 0.0;
-            bb[tid] = ok ? ld_coh(a.b + tid) : 0.0;
-        }
+        // Four waves, each running its own loop; they hand work to each other through counters in LDS
+        // (no workgroup barrier inside the solve), so a wave waiting on memory holds up only the waves
+        // that need its result.  For the block b_q run at sequence q:
+        //   wave 3 loads the Gram set of q into ring slot q mod GR: [0] = G(b_q, b_q), [s] = G(b_q, b_{q-s});
+        //   wave 2 prepares the block: once the owner has applied every change below q - SLACK it takes
+        //          the block's gradient and coefficients and applies the changes of q - SLACK .. q - 2;
+        //   wave 0 applies the change of q - 1 and runs the chain;
+        //   wave 1 publishes the change, gradient and coefficients of the block for the helpers.
+        double* Gm = arena;                               // [GR][SLACK + 1][MB * MB]
+        double* gp = Gm + GR * (SLACK + 1) * MB * MB;     // [2][MB] prepared gradient, slot q mod 2
+        double* bp = gp + 2 * MB;                         // [2][MB] prepared coefficients
+        double* dh = bp + 2 * MB;                         // [DR][MB] changes, slot q mod DR
+        double* go = dh + DR * MB;                        // [OR][MB] chain results (gradient), slot q mod OR
+        double* bo = go + OR * MB;                        // [OR][MB] chain results (coefficients)
+        int* ctr = reinterpret_cast<int*>(bo + OR * MB);  // counters, see LC_*
+        if (tid < LC_N) ctr[tid] = tid == LC_STOP ? INT_MAX : 0;
         __syncthreads();
-        // wave 0 keeps the Gram columns of the block it runs next in registers (diagonal block and the
-        // block against the previous one) and the previous sequence's changes (lane t: coordinate t)
-        double gc[MB], go[MB], dlp = 0.0;
+        const __amdgpu_buffer_rsrc_t grs = gram_rsrc(a.G, m);
+        const uint64_t limit = (uint64_t)spin_limit * 100u;   // wall-clock ticks (100 MHz) of any one wait
         if (wv == 0) {
+            // ---- the chain ----
+            const int l32 = lane & (MB - 1);
+            const double lam = a.lam;
+            double gc[MB], gq[MB], dlp = 0.0, maxd = 0.0;
+            int sweeps = 0, status = 0, b = 0;
+            int64_t q = 0;
+            bool ok = lead_wait(ctr, [&] { return lc_get(ctr, LC_GRAM) > 0; }, limit, false);
+            if (ok) {
 #pragma unroll
-            for (int t = 0; t < MB; ++t) {
-                gc[t] = Gm[t * MB + (lane & (MB - 1))];
-                go[t] = Gm[MB * MB + t * MB + (lane & (MB - 1))];
+                for (int t = 0; t < MB; ++t) {
+                    gc[t] = Gm[t * MB + l32];
+                    gq[t] = Gm[MB * MB + t * MB + l32];
+                }
             }
-        }
-        int sweeps = 0, status = 0;
-        int64_t q = 0;
-        int b = 0;          // q mod nb
-        int pslot = 0;      // (q - 1) mod 2nb: slot of the previous sequence's changes
-        int g3 = 0;         // q mod 3
-        for (;;) {
-            const int cur = (int)(q & 1), nxt = cur ^ 1;
-            const int pb = b == 0 ? nb - 1 : b - 1, nbk = b + 1 == nb ? 0 : b + 1;
-            const int g3n = g3 == 2 ? 0 : g3 + 1, g3nn = g3n == 2 ? 0 : g3n + 1;
-            const int bl = blk_len(m, b);
-            if (wv == 0) {
-                const int l32 = lane & (MB - 1);
-                double gl = lane < bl ? gb[cur * MB + l32] : 0.0;
-                // the change of the previous sequence (lane l = row l of the block)
+            while (ok) {
+                // the prepared block, and free result slots (their publication is done)
+                ok = lead_wait(ctr, [&] { return lc_get(ctr, LC_PREP) > q && lc_get(ctr, LC_PUB) > q - OR; },
+                               limit, false);
+                if (!ok) break;
+                const int cur = (int)(q & 1), bl = blk_len(m, b);
+                double gl = lane < bl ? gp[cur * MB + l32] : 0.0;
+                const double bv0 = lane < bl ? bp[cur * MB + l32] : 0.0;
                 if (q >= 1) {
                     double u0 = 0.0, u1 = 0.0;
 #pragma unroll
                     for (int t = 0; t < MB; t += 2) {
-                        u0 = fma(go[t], chain_readlane(dlp, t), u0);
-                        u1 = fma(go[t + 1], chain_readlane(dlp, t + 1), u1);
+                        u0 = fma(gq[t], chain_readlane(dlp, t), u0);
+                        u1 = fma(gq[t + 1], chain_readlane(dlp, t + 1), u1);
                     }
                     if (lane < bl) gl -= u0 + u1;
                 }
-                // the chain of block b, with the block's Gram column entries in registers
-                double bv = lane < bl ? bb[cur * MB + l32] : 0.0;
-                double dl = 0.0, wmax = 0.0;
-                // lanes past the block's length (and lanes 32..63) hold zeros, so nothing changes there
+                double bv = bv0, dl = 0.0, wmax = 0.0;
                 auto col = [&](int t) { return gc[t]; };
-                if (!chain_fast<MB>(gl, bv, col, lam, bl, dl, wmax)) chain_exact<MB>(gl, bv, col, lam, bl, dl, wmax);
+                if (!chain_fast<MB>(gl, bv, col, lam, bl, dl, wmax))
+                    chain_exact<MB>(gl, bv, col, lam, bl, dl, wmax);
                 if (lane < MB) {
-                    dh[(q % (SLACK + 1)) * MB + lane] = lane < bl ? dl : 0.0;
-                    gout[cur * MB + lane] = gl;
-                    bout[cur * MB + lane] = bv;
+                    dh[(int)(q & (DR - 1)) * MB + lane] = lane < bl ? dl : 0.0;
+                    go[(int)(q & (OR - 1)) * MB + lane] = gl;
+                    bo[(int)(q & (OR - 1)) * MB + lane] = bv;
                 }
-                if (lane == 0) *maxd_sh = fmax(*maxd_sh, wmax);
                 dlp = lane < bl ? dl : 0.0;
-                // Gram columns of the next block (its buffer was filled during the previous iteration)
-                const double* Gn = Gm + g3n * (SLACK + 1) * MB * MB;
+                maxd = fmax(maxd, wmax);
+                bool stop = false;
+                if (b == nb - 1) {
+                    ++sweeps;
+                    if (maxd < a.tol) stop = true;
+                    else if (sweeps >= a.max_sweeps) {
+                        status = 1;
+                        stop = true;
+                    }
+                    maxd = 0.0;
+                }
+                ++q;
+                if (stop) lc_set(ctr, LC_STOP, (int)q);
+                lc_set(ctr, LC_CHAIN, (int)q);
+                if (stop) break;
+                b = b + 1 == nb ? 0 : b + 1;
+                // the Gram columns of the next block
+                ok = lead_wait(ctr, [&] { return lc_get(ctr, LC_GRAM) > q; }, limit, false);
+                if (!ok) break;
+                const double* Gn = Gm + (int)(q % GR) * (SLACK + 1) * MB * MB;
 #pragma unroll
                 for (int t = 0; t < MB; ++t) {
                     gc[t] = Gn[t * MB + l32];
-                    go[t] = Gn[MB * MB + t * MB + l32];
+                    gq[t] = Gn[MB * MB + t * MB + l32];
                 }
-            } else if (wv == 1) {
-                // publish the previous block (sequence q-1)
-                if (q >= 1) {
-                    const int pl = blk_len(m, pb), pc = cur ^ 1;
-                    const int64_t e0 = (int64_t)pb * MB;
-                    if (lane < pl) {
-                        st_coh(a.delta + (int64_t)pslot * MB + lane, dh[((q - 1) % (SLACK + 1)) * MB + lane]);
-                        st_coh(a.g + e0 + lane, gout[pc * MB + lane]);
-                        st_coh(a.b + e0 + lane, bout[pc * MB + lane]);
-                    }
-                    wait_mem();
-                    if (lane == 0) st_flag(sync + SYNC_PUB, (uint32_t)q);
+            }
+            if (!ok) {
+                status = 2;
+                lc_set(ctr, LC_ERR, 1);
+                lc_set(ctr, LC_STOP, (int)q);
+            }
+            if (lane == 0) {
+                ctr[LC_SWEEPS] = sweeps;
+                ctr[LC_STATUS] = status;
+            }
+        } else if (wv == 1) {
+            // ---- publishing: every chain result, in sequence order ----
+            // (the wait ends on the stop only once every result up to it is published: the chain raises the
+            // stop count before the chain count, so leaving on the stop flag alone could drop the last block)
+            int bq = 0, slot = 0;
+            for (int64_t q = 0;; ++q) {
+                const bool ok = lead_wait(
+                    ctr, [&] { return lc_get(ctr, LC_CHAIN) > q || lc_get(ctr, LC_STOP) <= q; }, limit, false);
+                if (!ok || lc_get(ctr, LC_CHAIN) <= q) break;
+                const int pl = blk_len(m, bq), rs = (int)(q & (OR - 1));
+                const int64_t e0 = (int64_t)bq * MB;
+                if (lane < pl) {
+                    st_coh(a.delta + (int64_t)slot * MB + lane, dh[(int)(q & (DR - 1)) * MB + lane]);
+                    st_coh(a.g + e0 + lane, go[rs * MB + lane]);
+                    st_coh(a.b + e0 + lane, bo[rs * MB + lane]);
                 }
-            } else if (wv == 2) {
-                // prepare the next block (sequence q + 1): once its owner has applied every change below
-                // q + 1 - SLACK, take its gradient and apply the changes of q + 1 - SLACK .. q - 1
-                const int64_t qn = q + 1;
-                const int nl = blk_len(m, nbk);
-                const int64_t need = qn - SLACK;
-                if (need > 0 && H > 0) {
-                    const int owner = nbk % H;
-                    uint32_t spins = 0;
-                    bool bad = false;
-                    if (lane == 0) {
-                        while ((int64_t)ld_flag(sync + SYNC_APPLIED + 16 * owner) < need) {
-                            if (ld_flag(sync + SYNC_ERR) || ++spins > spin_limit) {
-                                bad = true;
-                                break;
-                            }
-                            __builtin_amdgcn_s_sleep(1);
-                        }
-                        if (bad) *err_sh = 1;
-                    }
+                wait_mem();
+                if (lane == 0) st_flag(sync + SYNC_PUB, (uint32_t)(q + 1));
+                lc_set(ctr, LC_PUB, (int)(q + 1));
+                bq = bq + 1 == nb ? 0 : bq + 1;
+                slot = slot + 1 == 2 * nb ? 0 : slot + 1;
+            }
+        } else if (wv == 2) {
+            // ---- preparing the block of sequence q ----
+            const int l32 = lane & (MB - 1), half = lane >> 5;
+            int bq = 0;
+            for (int64_t q = 0;; ++q) {
+                if (lc_get(ctr, LC_STOP) != INT_MAX) break;
+                const int nl = blk_len(m, bq);
+                const int64_t need = q - SLACK;
+                bool ok = true;
+                if (need > 0) {
+                    const int owner = bq % H;
+                    ok = lead_wait(ctr, [&] { return (int64_t)ld_flag(sync + SYNC_APPLIED + 16 * owner) >= need; },
+                                   limit, true);
                 }
-                const int64_t e0 = (int64_t)nbk * MB;
-                const int l32 = lane & (MB - 1), half = lane >> 5;
-                double gn = l32 < nl ? ld_coh(a.g + e0 + l32) : 0.0;
+                // the block's coefficients were last set at sequence q - nb: wait for their publication
+                if (ok && q >= nb) ok = lead_wait(ctr, [&] { return lc_get(ctr, LC_PUB) > q - nb; }, limit, true);
+                if (!ok) break;
+                const int64_t e0 = (int64_t)bq * MB;
+                const double gn = l32 < nl ? ld_coh(a.g + e0 + l32) : 0.0;
                 const double bn = l32 < nl ? ld_coh(a.b + e0 + l32) : 0.0;
-                // lanes 0..31 take columns 0..15 of each change block, lanes 32..63 columns 16..31
-                const double* Gn = Gm + g3n * (SLACK + 1) * MB * MB;
+                // the changes up to q - 2, the Gram set of q, and a free slot (the chain of q - 2 is done)
+                ok = lead_wait(ctr, [&] { return lc_get(ctr, LC_CHAIN) >= q - 1 && lc_get(ctr, LC_GRAM) > q; },
+                               limit, true);
+                if (!ok) break;
+                const double* Gn = Gm + (int)(q % GR) * (SLACK + 1) * MB * MB;
                 double u = 0.0;
 #pragma unroll
                 for (int o = SLACK; o >= 2; --o) {
-                    const int64_t sq = qn - o;
+                    const int64_t sq = q - o;
                     if (sq < 0) continue;
                     const double* Gs = Gn + o * MB * MB;
-                    const double* ds = dh + (sq % (SLACK + 1)) * MB;
+                    const double* ds = dh + (int)(sq & (DR - 1)) * MB;
+                    double gs[MB / 2], dd[MB / 2];
 #pragma unroll
                     for (int t = 0; t < MB / 2; ++t) {
                         const int tt = half * (MB / 2) + t;
-                        u = fma(Gs[tt * MB + l32], ds[tt], u);
+                        gs[t] = Gs[tt * MB + l32];
+                        dd[t] = ds[tt];
                     }
+#pragma unroll
+                    for (int t = 0; t < MB / 2; ++t) u = fma(gs[t], dd[t], u);
                 }
                 u += __shfl_xor(u, 32, WAVE);
                 if (lane < MB) {
-                    gb[nxt * MB + lane] = gn - u;
-                    bb[nxt * MB + lane] = bn;
+                    gp[(int)(q & 1) * MB + lane] = gn - u;
+                    bp[(int)(q & 1) * MB + lane] = bn;
                 }
-            } else {
-                // Gram blocks of the block after next (sequence q + 2), loaded during the last iteration;
-                // then the loads for sequence q + 3
-                store_gset(gv, Gm + g3nn * (SLACK + 1) * MB * MB, lane);
-                int b3 = nbk + 2;
-                if (b3 >= nb) b3 -= nb;
-                load_gset(grs, m, nb, q + 3, b3, gv, lane);
+                lc_set(ctr, LC_PREP, (int)(q + 1));
+                bq = bq + 1 == nb ? 0 : bq + 1;
             }
-            __syncthreads();
-            const bool sweep_end = (b == nb - 1);
-            b = nbk;
-            g3 = g3n;
-            pslot = (q >= 1) ? (pslot + 1 == 2 * nb ? 0 : pslot + 1) : 0;
-            bool stop = *err_sh != 0;
-            if (*err_sh) status = 2;
-            if (sweep_end && !stop) {
-                ++sweeps;
-                const double md = *maxd_sh;
-                if (md < a.tol) stop = true;
-                else if (sweeps >= a.max_sweeps) {
-                    status = 1;
-                    stop = true;
-                }
+        } else {
+            // ---- Gram sets, two in flight: set j + 1 is loading while set j is stored ----
+            double2 va[GSET], vb[GSET];
+            int bj = 0;
+            load_gset(grs, m, nb, 0, 0, va, lane);
+            for (int64_t j = 0;; j += 2) {
+                int b1 = bj + 1 == nb ? 0 : bj + 1;
+                load_gset(grs, m, nb, j + 1, b1, vb, lane);
+                if (!lead_gram_store(ctr, va, Gm, j, limit, lane)) break;
+                int b2 = b1 + 1 == nb ? 0 : b1 + 1;
+                load_gset(grs, m, nb, j + 2, b2, va, lane);
+                if (!lead_gram_store(ctr, vb, Gm, j + 1, limit, lane)) break;
+                bj = b2;
             }
-            __syncthreads();
-            if (sweep_end && tid == 0) *maxd_sh = 0.0;
-            ++q;
-            if (stop) break;
-        }
-        // publish the last block, then stop the helpers
-        if (wv == 0 && status != 2) {
-            const int pb = (int)((q - 1) % nb), pl = blk_len(m, pb), pc = (int)((q - 1) & 1);
-            const int64_t e0 = (int64_t)pb * MB;
-            if (lane < pl) {
-                st_coh(a.g + e0 + lane, gout[pc * MB + lane]);
-                st_coh(a.b + e0 + lane, bout[pc * MB + lane]);
-            }
+            // the loads still in flight complete before the wave ends
             wait_mem();
         }
         __syncthreads();
         if (tid == 0) {
+            const int status = ctr[LC_STATUS];
             st_flag(sync + SYNC_STOP, 1u);
             if (status == 2) st_flag(sync + SYNC_ERR, 1u);
-            a.sc->round.sweeps = sweeps;
+            a.sc->round.sweeps = ctr[LC_SWEEPS];
             a.sc->round.status = status;
             a.sc->round.cd_len = (int32_t)m;
         }

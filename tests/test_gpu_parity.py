@@ -190,10 +190,14 @@ def test_fit_path_is_deterministic(gpu_ctx):
     prob = datagen.make("c2", n=1500, p=3000)
     Xd = upload(prob.Xt, np.float64)
     yd = to_dev(prob.y[0])
+    # the working sets late in this path use the multi-workgroup solve, whose waves hand results to each
+    # other asynchronously: repeated paths must still agree bit for bit
     r1 = bl.fit_path(gpu_ctx, Xd, yd, nlambda=30, lambda_min_ratio=0.05)
-    r2 = bl.fit_path(gpu_ctx, Xd, yd, nlambda=30, lambda_min_ratio=0.05)
-    assert torch.equal(r1.beta, r2.beta)
-    np.testing.assert_array_equal(r1.obj, r2.obj)
+    assert r1.n_strong.max() > 300
+    for _ in range(3):
+        r2 = bl.fit_path(gpu_ctx, Xd, yd, nlambda=30, lambda_min_ratio=0.05)
+        assert torch.equal(r1.beta, r2.beta)
+        np.testing.assert_array_equal(r1.obj, r2.obj)
 
 
 def test_single_column_and_tiny_rows(gpu_ctx):
@@ -252,7 +256,7 @@ def test_not_converged_reports_progress(gpu_ctx):
     assert np.abs(beta - ref.beta[: res.k_done]).max() <= 1e-6
 
 
-@pytest.mark.parametrize("m_set", [300, 1500, 4000])
+@pytest.mark.parametrize("m_set", [300, 777, 1500, 4000])
 def test_cd_solve_large_working_set(gpu_ctx, m_set):
     """Working sets large enough for the multi-workgroup covariance solve (and its block tail)."""
     prob = datagen.make("c1", n=900, p=m_set + 500)
