@@ -49,40 +49,39 @@ __device__ __forceinline__ void chain_exact(double& gl, double& bv, Col col, dou
 }
 
 // Status-keeping chain; returns false (and changes nothing) if a coordinate might change status.
-// The loop carries only the pending changes dv_l = g_l - lambda sign(beta_l) (sign -1 for beta_l = 0):
-// a taken step reads d_t = dv_t and subtracts d_t G[t][.]; the gradient is dv + lambda sign(beta).
-// A zero coefficient l is stepped over; it is certain to stay zero if |g_l| at the end of the block
-// plus sum_t |d_t G[t][l]| (a bound on how far the block moved g_l) is at most lambda.
+// The loop carries the pending changes dv_l = g_l - lambda sign(beta_l) (sign -1 for beta_l = 0): a taken
+// step reads d_t = dv_t and subtracts d_t G[t][.]; the gradient is dv + lambda sign(beta).  The step's lane
+// read comes from a masked copy dm that is held at zero on the lanes of zero coefficients (their Gram
+// entries are zeroed in its update), so a zero coefficient's step reads d = 0 without a scalar select on
+// the dependency chain; the full vector dv, the bound sums and the per-lane changes are updated beside it
+// with the same operations in the same order.  A zero coefficient l is certain to stay zero if |g_l| at
+// the end of the block plus sum_t |d_t G[t][l]| (a bound on how far the block moved g_l) is at most lambda.
 template <int NB, typename Col>
 __device__ __forceinline__ bool chain_fast(double& gl, double& bv, Col col, double lam, int bl, double& dl,
                                            double& wmax) {
     const int lane = threadIdx.x & 63;
     const uint64_t lanes = chain_below(bl);
     const uint64_t amask = __ballot(bv != 0.0) & lanes;
+    const bool act = (amask >> lane) & 1ull;
     const double ls = bv > 0.0 ? lam : -lam;
     double dv = gl - ls;
-    double dsv[NB];   // the changes, wave-uniform
-#pragma unroll
-    for (int t = 0; t < NB; ++t) {
-        // a zero coefficient's step is the exact no-op d = 0 (selected, not branched around)
-        const double r = chain_readlane(dv, t);
-        const double d = ((amask >> t) & 1ull) ? r : 0.0;
-        dv = fma(-d, col(t), dv);
-        dsv[t] = d;
-    }
-    // checks and per-lane results: no step depends on another here
+    double dm = act ? dv : 0.0;
     double b0 = 0.0, b1 = 0.0, w0 = 0.0, w1 = 0.0, ds = 0.0;
 #pragma unroll
     for (int t = 0; t < NB; ++t) {
-        const double d = fabs(dsv[t]);
+        const double d = chain_readlane(dm, t);   // +0 for a zero coefficient: its lane of dm stays +0
+        const double c = col(t);
+        dm = fma(-d, act ? c : 0.0, dm);
+        dv = fma(-d, c, dv);
+        const double ad = fabs(d);
         if (t & 1) {
-            b1 = fma(d, fabs(col(t)), b1);
-            w1 = fmax(w1, d);
+            b1 = fma(ad, fabs(c), b1);
+            w1 = fmax(w1, ad);
         } else {
-            b0 = fma(d, fabs(col(t)), b0);
-            w0 = fmax(w0, d);
+            b0 = fma(ad, fabs(c), b0);
+            w0 = fmax(w0, ad);
         }
-        ds = lane == t ? dsv[t] : ds;
+        ds = lane == t ? d : ds;
     }
     const double g2 = dv + ls;
     uint64_t viol = __ballot(fabs(g2) + (b0 + b1) > lam) & ~amask & lanes;

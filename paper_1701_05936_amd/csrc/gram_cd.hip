@@ -484,7 +484,7 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
             // ---- the chain ----
             const int l32 = lane & (MB - 1);
             const double lam = a.lam;
-            double gc[MB], gq[MB], dlp = 0.0, maxd = 0.0;
+            double gc[MB], gq[MB], maxd = 0.0;
             int sweeps = 0, status = 0, b = 0;
             int64_t q = 0;
             bool ok = lead_wait(ctr, [&] { return lc_get(ctr, LC_GRAM) > 0; }, limit, false);
@@ -504,11 +504,15 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
                 double gl = lane < bl ? gp[cur * MB + l32] : 0.0;
                 const double bv0 = lane < bl ? bp[cur * MB + l32] : 0.0;
                 if (q >= 1) {
+                    // the previous change, read back from the change ring as a broadcast (every lane reads
+                    // the same address): lane reads would all pass through one scalar register pair here
+                    const double* dp = dh + (int)((q - 1) & (DR - 1)) * MB;
                     double u0 = 0.0, u1 = 0.0;
 #pragma unroll
                     for (int t = 0; t < MB; t += 2) {
-                        u0 = fma(gq[t], chain_readlane(dlp, t), u0);
-                        u1 = fma(gq[t + 1], chain_readlane(dlp, t + 1), u1);
+                        const double2 d2 = *reinterpret_cast<const double2*>(dp + t);
+                        u0 = fma(gq[t], d2.x, u0);
+                        u1 = fma(gq[t + 1], d2.y, u1);
                     }
                     if (lane < bl) gl -= u0 + u1;
                 }
@@ -521,7 +525,6 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
                     go[(int)(q & (OR - 1)) * MB + lane] = gl;
                     bo[(int)(q & (OR - 1)) * MB + lane] = bv;
                 }
-                dlp = lane < bl ? dl : 0.0;
                 maxd = fmax(maxd, wmax);
                 bool stop = false;
                 if (b == nb - 1) {
