@@ -96,4 +96,79 @@ __device__ __forceinline__ bool chain_fast(double& gl, double& bv, Col col, doub
     return true;
 }
 
+// The status-keeping chain for a wave that runs the blocks one after the other.  Only the dependency chain
+// is inside the step loop: the lane read of the masked pending changes and one FMA, plus a select that
+// keeps step t's change in lane t of ds.  The full pending-change vector, the bound sums and the largest
+// change are formed after the loop from ds, stored to dsh (NB doubles of LDS, 16-byte aligned, written and
+// read by this wave only) and read back as broadcasts, with the same operations in the same order as the
+// step-by-step form, so the results are identical.  The next block's first update is folded into that
+// post-pass: gn(t) returns the Gram entry between coordinate t of this block and this
+// lane's coordinate of the next block, and un receives sum_t gn(t) d_t (even and odd t summed separately,
+// then added).
+template <int NB, typename Col, typename ColN>
+__device__ __forceinline__ bool chain_fast_next(double& gl, double& bv, Col col, ColN gn, double lam, int bl,
+                                                double& dl, double& wmax, double* dsh, double& un) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t lanes = chain_below(bl);
+    const uint64_t amask = __ballot(bv != 0.0) & lanes;
+    const bool act = (amask >> lane) & 1ull;
+    const double ls = bv > 0.0 ? lam : -lam;
+    const double dv0 = gl - ls;
+    double dm = act ? dv0 : 0.0;
+    double ds = 0.0;
+    // the Gram entries of the masked copy: zero on the lanes of zero coefficients, so those lanes stay +0
+    // (every lane runs the loop: a lane read of a lane outside the running set would be undefined)
+    double cm[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) cm[t] = act ? col(t) : 0.0;
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+        // step t's change is lane t of dm before the step: keep it there, then broadcast it
+        ds = lane == t ? dm : ds;
+        const double d = chain_readlane(dm, t);   // +0 for a zero coefficient: its lane of dm stays +0
+        dm = fma(-d, cm[t], dm);
+    }
+    if (lane < NB) dsh[lane] = ds;
+    double dv = dv0, b0 = 0.0, b1 = 0.0, w0 = 0.0, w1 = 0.0, u0 = 0.0, u1 = 0.0;
+#pragma unroll
+    for (int t = 0; t < NB; t += 2) {
+        const double2 d2 = *reinterpret_cast<const double2*>(dsh + t);
+        const double c0 = col(t), c1 = col(t + 1);
+        dv = fma(-d2.x, c0, dv);
+        dv = fma(-d2.y, c1, dv);
+        b0 = fma(fabs(d2.x), fabs(c0), b0);
+        w0 = fmax(w0, fabs(d2.x));
+        b1 = fma(fabs(d2.y), fabs(c1), b1);
+        w1 = fmax(w1, fabs(d2.y));
+        u0 = fma(gn(t), d2.x, u0);
+        u1 = fma(gn(t + 1), d2.y, u1);
+    }
+    un = u0 + u1;
+    const double g2 = dv + ls;
+    uint64_t viol = __ballot(fabs(g2) + (b0 + b1) > lam) & ~amask & lanes;
+    const double bn = bv + ds;
+    // nonzero coefficients must keep their sign
+    viol |= __ballot(bv > 0.0 ? !(bn > 0.0) : (bv < 0.0 ? !(bn < 0.0) : false)) & lanes;
+    if (viol) return false;
+    gl = g2;
+    bv = bn;
+    dl = ds;
+    wmax = fmax(wmax, fmax(w0, w1));
+    return true;
+}
+
+// sum_t gn(t) dsh[t] over a block's changes dsh (NB doubles of LDS read as broadcasts), even and odd t
+// summed separately, then added: the update chain_fast_next folds into its post-pass
+template <int NB, typename ColN>
+__device__ __forceinline__ double chain_next_update(ColN gn, const double* dsh) {
+    double u0 = 0.0, u1 = 0.0;
+#pragma unroll
+    for (int t = 0; t < NB; t += 2) {
+        const double2 d2 = *reinterpret_cast<const double2*>(dsh + t);
+        u0 = fma(gn(t), d2.x, u0);
+        u1 = fma(gn(t + 1), d2.y, u1);
+    }
+    return u0 + u1;
+}
+
 }  // namespace blk

@@ -282,7 +282,7 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd(GcdArgs a) {
 // Every wait is bounded: on time-out the waiter raises an error flag that all
 // others see, and the host reports a device error.
 constexpr int MB = 32;      // coordinates per block
-constexpr int SLACK = 3;    // most recent blocks whose changes the leader applies itself
+constexpr int SLACK = 5;    // most recent blocks whose changes the leader applies itself
 constexpr int MT = 256;     // threads per workgroup
 constexpr int HBATCH = 4;   // sequences a helper applies per round trip at most
 constexpr int HOWN = 2;     // blocks a helper owns at most
@@ -332,7 +332,7 @@ __device__ __forceinline__ void load_gblock(const double* __restrict__ G, int64_
 
 // LDS arena shared by the two roles (a workgroup is either the leader or a helper)
 // leader rings: Gram sets (GR), changes (DR, at least SLACK + 2), chain results awaiting publication (OR)
-constexpr int GR = 4, DR = 8, OR = 4;
+constexpr int GR = 3, DR = 8, OR = 4;
 // leader counters in LDS: chains run, blocks prepared, blocks published, Gram sets loaded (each a count of
 // sequences), the sequence count at which the chain stopped (INT_MAX while running), an error flag, and
 // the solve's results
@@ -484,16 +484,15 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
             // ---- the chain ----
             const int l32 = lane & (MB - 1);
             const double lam = a.lam;
-            double gc[MB], gq[MB], maxd = 0.0;
+            // gc: Gram columns of the block to run; gn: its entries against the block after it, which takes
+            // un = sum_t gn[t] d_t from this block's changes, formed in the chain's post-pass
+            double gc[MB], gn[MB], un = 0.0, maxd = 0.0;
             int sweeps = 0, status = 0, b = 0;
             int64_t q = 0;
             bool ok = lead_wait(ctr, [&] { return lc_get(ctr, LC_GRAM) > 0; }, limit, false);
             if (ok) {
 #pragma unroll
-                for (int t = 0; t < MB; ++t) {
-                    gc[t] = Gm[t * MB + l32];
-                    gq[t] = Gm[MB * MB + t * MB + l32];
-                }
+                for (int t = 0; t < MB; ++t) gc[t] = Gm[t * MB + l32];
             }
             while (ok) {
                 // the prepared block, and free result slots (their publication is done)
@@ -503,25 +502,25 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
                 const int cur = (int)(q & 1), bl = blk_len(m, b);
                 double gl = lane < bl ? gp[cur * MB + l32] : 0.0;
                 const double bv0 = lane < bl ? bp[cur * MB + l32] : 0.0;
-                if (q >= 1) {
-                    // the previous change, read back from the change ring as a broadcast (every lane reads
-                    // the same address): lane reads would all pass through one scalar register pair here
-                    const double* dp = dh + (int)((q - 1) & (DR - 1)) * MB;
-                    double u0 = 0.0, u1 = 0.0;
+                if (q >= 1 && lane < bl) gl -= un;   // the previous block's changes
+                // the next block's entries against this one (its Gram set is loaded whether or not the
+                // chain stops after this block)
+                ok = lead_wait(ctr, [&] { return lc_get(ctr, LC_GRAM) > q + 1; }, limit, false);
+                if (!ok) break;
+                const double* Gn1 = Gm + (int)((q + 1) % GR) * (SLACK + 1) * MB * MB;
 #pragma unroll
-                    for (int t = 0; t < MB; t += 2) {
-                        const double2 d2 = *reinterpret_cast<const double2*>(dp + t);
-                        u0 = fma(gq[t], d2.x, u0);
-                        u1 = fma(gq[t + 1], d2.y, u1);
-                    }
-                    if (lane < bl) gl -= u0 + u1;
-                }
+                for (int t = 0; t < MB; ++t) gn[t] = Gn1[MB * MB + t * MB + l32];
                 double bv = bv0, dl = 0.0, wmax = 0.0;
                 auto col = [&](int t) { return gc[t]; };
-                if (!chain_fast<MB>(gl, bv, col, lam, bl, dl, wmax))
+                auto coln = [&](int t) { return gn[t]; };
+                double* dq = dh + (int)(q & (DR - 1)) * MB;   // this block's change slot
+                if (!chain_fast_next<MB>(gl, bv, col, coln, lam, bl, dl, wmax, dq, un)) {
                     chain_exact<MB>(gl, bv, col, lam, bl, dl, wmax);
+                    if (lane < MB) dq[lane] = lane < bl ? dl : 0.0;
+                    un = chain_next_update<MB>(coln, dq);
+                }
                 if (lane < MB) {
-                    dh[(int)(q & (DR - 1)) * MB + lane] = lane < bl ? dl : 0.0;
+                    dq[lane] = lane < bl ? dl : 0.0;
                     go[(int)(q & (OR - 1)) * MB + lane] = gl;
                     bo[(int)(q & (OR - 1)) * MB + lane] = bv;
                 }
@@ -541,15 +540,10 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
                 lc_set(ctr, LC_CHAIN, (int)q);
                 if (stop) break;
                 b = b + 1 == nb ? 0 : b + 1;
-                // the Gram columns of the next block
-                ok = lead_wait(ctr, [&] { return lc_get(ctr, LC_GRAM) > q; }, limit, false);
-                if (!ok) break;
+                // the Gram columns of the next block (its set was waited for above)
                 const double* Gn = Gm + (int)(q % GR) * (SLACK + 1) * MB * MB;
 #pragma unroll
-                for (int t = 0; t < MB; ++t) {
-                    gc[t] = Gn[t * MB + l32];
-                    gq[t] = Gn[MB * MB + t * MB + l32];
-                }
+                for (int t = 0; t < MB; ++t) gc[t] = Gn[t * MB + l32];
             }
             if (!ok) {
                 status = 2;
