@@ -1,9 +1,12 @@
-"""Full-size parity: the plain path on the 5,000 x 500,000 genotype design (FP64, 20 GB) and the batched
-form on the 20,000 x 200,000 AR(1) design (64 problems), in the launch configurations bench.py times (CD tolerance 1e-10 here, 1e-8 there).
+"""Full-size parity in the launch configurations bench.py times (CD tolerance 1e-10 here, 1e-8 there): the
+plain path on the 5,000 x 500,000 genotype design (FP64, 20 GB), the precision form on the 10,000 x
+2,000,000 genotype design (int8, 20 GB), the batched form on the 20,000 x 200,000 AR(1) design (64
+problems) and the learned form on the 5,000 x 1,000,000 block-AR(1) design (float32, 20 GB).
 
 The oracle cannot run these paths whole in seconds, so the checks use what the oracle computes column by
 column: sampled column statistics, lambda_max over every column (in chunks), and KKT certificates of the
-GPU coefficients at sampled lambda values, with z over every column computed by the oracle's scan.
+GPU coefficients at sampled lambda values, with z computed by the oracle's scan over every column (c2, c4)
+or over every active column and a seeded sample of 50,000 others (c3, c5).
 """
 import numpy as np
 import pytest
@@ -134,5 +137,119 @@ def test_c4_full_kkt_certificate(c4_full, b, k):
     out_v, on_a = kkt_residuals(Xt, c, s, keep, yt, beta[b, k], lam, mask)
     log(f"problem {b}, k={k}: rows {int(mask.sum())}, active {np.count_nonzero(beta[b, k])}, "
         f"inactive {out_v:.2e}, active {on_a:.2e}")
+    assert out_v <= 1e-6
+    assert on_a <= 1e-6
+
+
+def kkt_sampled(Xt, y, beta, lam, n_sample=50_000, seed=0):
+    """KKT residuals of beta at lam over every active column and n_sample seeded other columns, with the
+    columns' standardization, the residual and z all computed by the oracle (all rows in use)."""
+    act = np.flatnonzero(beta)
+    rng = np.random.default_rng(seed)
+    others = np.setdiff1d(np.arange(Xt.shape[0]), act)
+    samp = np.sort(rng.choice(others, size=min(n_sample, others.size), replace=False))
+    cols = np.concatenate([act, samp])
+    blk = np.ascontiguousarray(Xt[cols], dtype=np.float64)
+    c, s, keep, _ = oracle.standardize(blk)
+    assert keep[:act.size].all()
+    r = y - y.mean()
+    for i, j in enumerate(act):
+        r -= beta[j] * (blk[i] - c[i]) / s[i]
+    z = oracle.zscan(blk, c, s, keep, r)
+    zi = z[act.size:][keep[act.size:]]
+    out_viol = np.max(np.abs(zi)) / lam - 1.0
+    on_act = np.max(np.abs(z[:act.size] - lam * np.sign(beta[act]))) / lam if act.size else 0.0
+    return out_viol, on_act, act.size
+
+
+@pytest.fixture(scope="module")
+def c3_full(gpu_ctx):
+    rec = datagen.RECIPES["c3"]
+    log("generating c3 at full size ...")
+    Xt = datagen.design(rec)                 # (p, n) uint8 codes
+    y = datagen.response(rec, Xt, 0)
+    Xd = torch.from_numpy(Xt.view(np.int8)).to(DEV)
+    yd = torch.from_numpy(y).to(DEV)
+    kw = dict(nlambda=rec.nlambda, lambda_min_ratio=rec.lambda_min_ratio, rule=bl.SCREEN_SSR_BEDPP, tol=1e-10)
+    lp = bl.fit_path(gpu_ctx, Xd, yd, precision=bl.PREC_BF16X3, **kw)
+    hp = bl.fit_path(gpu_ctx, Xd, yd, precision=bl.PREC_FP64, **kw)
+    log(f"precision form {lp.time_ms:.0f} ms, FP64 scans {hp.time_ms:.0f} ms, {lp.n_active[-1]} active at the end, "
+        f"{int(lp.n_recheck.sum())} FP64 rechecks")
+    del Xd
+    torch.cuda.empty_cache()
+    return rec, Xt, y, lp, hp
+
+
+def test_c3_full_precision_form_equals_fp64_path(c3_full):
+    """The BF16 matrix-core scans take every decision the FP64 scans take: identical coefficients."""
+    rec, Xt, y, lp, hp = c3_full
+    assert lp.k_done == rec.nlambda and hp.k_done == rec.nlambda
+    assert torch.equal(lp.beta, hp.beta)
+    np.testing.assert_array_equal(lp.n_active, hp.n_active)
+    np.testing.assert_array_equal(lp.n_strong, hp.n_strong)
+
+
+@pytest.mark.parametrize("k", [30, 99])
+def test_c3_full_kkt_certificate_sampled(c3_full, k):
+    rec, Xt, y, lp, hp = c3_full
+    beta = lp.beta[k].cpu().numpy()
+    lam = lp.lam[k]
+    out_v, on_a, na = kkt_sampled(Xt, y, beta, lam)
+    log(f"c3 k={k}: lambda {lam:.6g}, active {na}, max sampled inactive |z|/lambda - 1 = {out_v:.2e}, "
+        f"max active |z - lambda sign| / lambda = {on_a:.2e}")
+    assert out_v <= 1e-6
+    assert on_a <= 1e-6
+
+
+@pytest.fixture(scope="module")
+def c5_full(gpu_ctx):
+    """The learned form on the full c5 design over the first 60 lambda values of its grid, with a network
+    trained on 10 recorded strong-rule paths of a 10,000-column design of the same recipe."""
+    rec = datagen.RECIPES["c5"]
+    depth = 60
+    step = rec.lambda_min_ratio ** (1.0 / (rec.nlambda - 1))
+    tr = rec.scaled(p=10_000, seed=rec.seed + 1000, nresp=10)
+    tp = datagen.make(tr)
+    Xtr = torch.from_numpy(tp.Xt).to(DEV)
+    cap = 4_000_000
+    feat = torch.zeros((cap, 4), dtype=torch.float32, device=DEV)
+    lab = torch.zeros(cap, dtype=torch.float32, device=DEV)
+    n_rec = 0
+    for t in range(tr.nresp):
+        ytr = torch.from_numpy(tp.y[t]).to(DEV)
+        lmax = bl.fit_path(gpu_ctx, Xtr, ytr, nlambda=1, want_beta=False).lambda_max
+        r = bl.fit_path(gpu_ctx, Xtr, ytr, nlambda=depth, lambdas=lmax * step ** np.arange(depth),
+                        rule=bl.SCREEN_SSR_BEDPP, tol=1e-8, rec_feat=feat[n_rec:], rec_label=lab[n_rec:],
+                        want_beta=False)
+        n_rec += r.n_recorded
+    P = torch.from_numpy(bl.mlp_init(1)).to(DEV)
+    info = bl.mlp_train(gpu_ctx, feat[:n_rec].contiguous(), lab[:n_rec].contiguous(), P, epochs=10, batch=8192,
+                        lr=2e-3, seed=5, target_recall=0.995)
+    del Xtr, feat, lab
+    log(f"trained on {n_rec} records: recall {info['recall']:.4f}, tau {info['tau']:.4g}")
+    log("generating c5 at full size ...")
+    Xt = datagen.design(rec)                 # (p, n) float32
+    y = datagen.response(rec, Xt, 0)
+    Xd = torch.from_numpy(Xt).to(DEV)
+    yd = torch.from_numpy(y).to(DEV)
+    lmax = bl.fit_path(gpu_ctx, Xd, yd, nlambda=1, want_beta=False).lambda_max
+    res = bl.fit_path(gpu_ctx, Xd, yd, nlambda=depth, lambdas=lmax * step ** np.arange(depth),
+                      rule=bl.SCREEN_LEARNED, mlp=P, mlp_tau=info["tau"], tol=1e-10)
+    log(f"learned path: {res.time_ms:.0f} ms, {res.n_active[-1]} active at the end, "
+        f"{int(res.n_viol.sum())} violations repaired, working sets {int(res.n_strong.sum())}")
+    del Xd
+    torch.cuda.empty_cache()
+    return rec, Xt, y, res
+
+
+@pytest.mark.parametrize("k", [30, 59])
+def test_c5_full_learned_kkt_certificate_sampled(c5_full, k):
+    rec, Xt, y, res = c5_full
+    assert res.k_done == 60
+    beta = res.beta[k].cpu().numpy()
+    lam = res.lam[k]
+    out_v, on_a, na = kkt_sampled(Xt, y, beta, lam)
+    log(f"c5 k={k}: lambda {lam:.6g}, active {na}, max sampled inactive |z|/lambda - 1 = {out_v:.2e}, "
+        f"max active |z - lambda sign| / lambda = {on_a:.2e}")
     assert out_v <= 1e-6
     assert on_a <= 1e-6
