@@ -76,68 +76,97 @@ __global__ __launch_bounds__(1024) void k_pool_add(const int32_t* __restrict__ s
 
 // ---- Gram entries of new pool members ----------------------------------------------------------------
 // C[k, t] = x~_{pool[k]}' x~_{pool[P0 + t]} / n for k < P, t < N, written to G[k, P0+t] and G[P0+t, k].
-constexpr int GT_K = 64;   // pool columns per tile
-constexpr int GT_N = 32;   // new columns per tile
-constexpr int GT_R = 32;   // rows per LDS chunk
+// The raw products sum_i x_{pool[k], i} x_{pool[P0+t], i} (over the fitted rows) are formed on FP64 matrix
+// cores (v_mfma_f64_16x16x4f64).  A workgroup holds a 32 x 16 tile of C; its four waves take a quarter of
+// the rows each (64 rows a step, the next step's values loaded while the current one is multiplied) and
+// their partial tiles are added in wave order through LDS.  Lane (m, kq) feeds rows i0 + 16 kq ..
+// i0 + 16 kq + 15 of pool columns kb + m and kb + 16 + m and of new column tb + m, read straight from X;
+// register q of its result holds C[kb + kq + 4q (+ 16), tb + m].  The standardization
+// (C - n c_k c_t) / (n s_k s_t) is applied on the way out.  A pair of two new columns appears in two tiles;
+// only the one with k - P0 <= t writes it (both triangles), so G stays exactly symmetric.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int GM_W = 4;    // waves per workgroup (row quarters)
+constexpr int GM_K = 32;   // pool columns per workgroup
+constexpr int GM_N = 16;   // new columns per workgroup
+constexpr int GM_R = 64;   // rows per step
 
 template <typename XT, bool MASK>
-__global__ __launch_bounds__(256) void k_gram_update(const XT* __restrict__ X, int64_t ldx, int64_t n_total,
-                                                     const uint8_t* __restrict__ mask,
-                                                     const int32_t* __restrict__ pool_list, int64_t P, int64_t P0,
-                                                     int64_t N, const double* __restrict__ c,
-                                                     const double* __restrict__ s, double n_rows,
-                                                     double* __restrict__ G, int64_t ldg) {
-    __shared__ double As[GT_R][GT_K + 1];
-    __shared__ double Bs[GT_R][GT_N + 1];
-    const int tid = threadIdx.x;
-    const int64_t k0 = (int64_t)blockIdx.x * GT_K, t0 = (int64_t)blockIdx.y * GT_N;
-    const int tx = tid % 16, ty = tid / 16;  // thread computes k = k0 + tx + 16*a (a < 4), t = t0 + ty + 16*b (b < 2)
-    double acc[4][2] = {};
-    // loaders: A chunk GT_R x GT_K -> 8 elements per thread; B chunk GT_R x GT_N -> 4 per thread
-    const int a_col = tid / 4, a_row = (tid % 4) * 8;
-    const int b_col = tid / 8, b_row = (tid % 8) * 4;
-    const XT* acol = (k0 + a_col < P) ? X + (int64_t)pool_list[k0 + a_col] * ldx : nullptr;
-    const XT* bcol = (t0 + b_col < N) ? X + (int64_t)pool_list[P0 + t0 + b_col] * ldx : nullptr;
-    for (int64_t i0 = 0; i0 < n_total; i0 += GT_R) {
+__global__ __launch_bounds__(64 * GM_W) void k_gram_update(const XT* __restrict__ X, int64_t ldx, int64_t n_total,
+                                                          const uint8_t* __restrict__ mask,
+                                                          const int32_t* __restrict__ pool_list, int64_t P,
+                                                          int64_t P0, int64_t N, const double* __restrict__ c,
+                                                          const double* __restrict__ s, double n_rows,
+                                                          double* __restrict__ G, int64_t ldg) {
+    __shared__ f64x4 red[GM_W - 1][2][WAVE];
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const int m = lane & 15, kq = lane >> 4;
+    const int64_t kb = (int64_t)blockIdx.x * GM_K, tb = (int64_t)blockIdx.y * GM_N;
+    const XT* ac[2];
+    bool aok[2];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int64_t i = i0 + a_row + q;
-            As[a_row + q][a_col] = (acol && i < n_total) ? ld_x(acol + i) : 0.0;
+    for (int f = 0; f < 2; ++f) {
+        const int64_t k = kb + 16 * f + m;
+        aok[f] = k < P;
+        ac[f] = X + (int64_t)(aok[f] ? pool_list[k] : 0) * ldx;
+    }
+    const bool bok = tb + m < N;
+    const XT* bc = X + (int64_t)(bok ? pool_list[P0 + tb + m] : 0) * ldx;
+    // this wave's steps
+    const int64_t ns = (n_total + GM_R - 1) / GM_R;
+    const int64_t s0 = ns * w / GM_W, s1 = ns * (w + 1) / GM_W;
+    XT ra[2][16], rb[16];
+    bool rm[16];
+    auto load = [&](int64_t step) {
+        const int64_t r0 = step * GM_R + 16 * kq;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const bool in = r0 + q < n_total;
+            ra[0][q] = (aok[0] && in) ? ac[0][r0 + q] : (XT)0;
+            ra[1][q] = (aok[1] && in) ? ac[1][r0 + q] : (XT)0;
+            rb[q] = (bok && in) ? bc[r0 + q] : (XT)0;
+            rm[q] = MASK ? (in && mask[r0 + q] != 0) : true;
         }
+    };
+    f64x4 acc[2] = {(f64x4){0.0, 0.0, 0.0, 0.0}, (f64x4){0.0, 0.0, 0.0, 0.0}};
+    if (s0 < s1) load(s0);
+    for (int64_t step = s0; step < s1; ++step) {
+        double av[2][16], bv[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            av[0][q] = (double)ra[0][q];
+            av[1][q] = (double)ra[1][q];
+            bv[q] = rm[q] ? (double)rb[q] : 0.0;
+        }
+        if (step + 1 < s1) load(step + 1);
+#pragma unroll
+        for (int st = 0; st < 16; ++st) {
+            acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0][st], bv[st], acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1][st], bv[st], acc[1], 0, 0, 0);
+        }
+    }
+    if (w > 0) {
+        red[w - 1][0][lane] = acc[0];
+        red[w - 1][1][lane] = acc[1];
+    }
+    __syncthreads();
+    if (w > 0) return;
+#pragma unroll
+    for (int v = 0; v < GM_W - 1; ++v) {
+        acc[0] += red[v][0][lane];
+        acc[1] += red[v][1][lane];
+    }
+    const int64_t t = tb + m;
+    if (t >= N) return;
+    const int jt = pool_list[P0 + t];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int64_t i = i0 + b_row + q;
-            double v = (bcol && i < n_total) ? ld_x(bcol + i) : 0.0;
-            if (MASK && i < n_total && !mask[i]) v = 0.0;
-            Bs[b_row + q][b_col] = v;
-        }
-        __syncthreads();
-#pragma unroll 8
-        for (int rr = 0; rr < GT_R; ++rr) {
-            double av[4], bv[2];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) av[q] = As[rr][tx + 16 * q];
-#pragma unroll
-            for (int q = 0; q < 2; ++q) bv[q] = Bs[rr][ty + 16 * q];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int w = 0; w < 2; ++w) acc[q][w] = fma(av[q], bv[w], acc[q][w]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t k = k0 + tx + 16 * q;
-        if (k >= P) continue;
-        const int jk = pool_list[k];
-#pragma unroll
-        for (int w = 0; w < 2; ++w) {
-            const int64_t t = t0 + ty + 16 * w;
-            if (t >= N) continue;
-            const int jt = pool_list[P0 + t];
-            // symmetric in (jk, jt): two tiles write each new-by-new entry and must agree bitwise
-            const double gv = (acc[q][w] - n_rows * (c[jk] * c[jt])) / (n_rows * (s[jk] * s[jt]));
+            const int64_t k = kb + 16 * f + kq + 4 * q;
+            if (k >= P) continue;
+            if (k >= P0 && k - P0 > t) continue;   // written by the tile of its mirror
+            const int jk = pool_list[k];
+            const double gv = (acc[f][q] - n_rows * (c[jk] * c[jt])) / (n_rows * (s[jk] * s[jt]));
             G[k * ldg + (P0 + t)] = gv;
             G[(P0 + t) * ldg + k] = gv;
         }
@@ -833,13 +862,13 @@ template <typename XT>
 static hipError_t gram_typed(const Mat& m, const int32_t* pool_list, int64_t P, int64_t P0, int64_t N,
                              const double* c, const double* s, double n_rows, double* G, int64_t ldg,
                              hipStream_t st) {
-    dim3 grid((unsigned)((P + GT_K - 1) / GT_K), (unsigned)((N + GT_N - 1) / GT_N));
+    dim3 grid((unsigned)((P + GM_K - 1) / GM_K), (unsigned)((N + GM_N - 1) / GM_N));
     if (m.mask)
-        k_gram_update<XT, true><<<grid, 256, 0, st>>>((const XT*)m.X, m.ldx, m.n_total, m.mask, pool_list, P, P0, N,
-                                                      c, s, n_rows, G, ldg);
+        k_gram_update<XT, true><<<grid, 64 * GM_W, 0, st>>>((const XT*)m.X, m.ldx, m.n_total, m.mask, pool_list, P,
+                                                             P0, N, c, s, n_rows, G, ldg);
     else
-        k_gram_update<XT, false><<<grid, 256, 0, st>>>((const XT*)m.X, m.ldx, m.n_total, m.mask, pool_list, P, P0, N,
-                                                       c, s, n_rows, G, ldg);
+        k_gram_update<XT, false><<<grid, 64 * GM_W, 0, st>>>((const XT*)m.X, m.ldx, m.n_total, m.mask, pool_list,
+                                                              P, P0, N, c, s, n_rows, G, ldg);
     return hipGetLastError();
 }
 
