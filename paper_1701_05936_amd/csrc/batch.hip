@@ -520,73 +520,102 @@ __global__ void k_b_commit(int nprob, const uint8_t* __restrict__ want, BatchSca
     }
 }
 
-// Gram entries of problem b's new pool members against its pool (grid.z = problem; masked rows)
-constexpr int GK = 64, GN = 32, GR = 32;
+// Gram entries of problem b's new pool members against its pool (grid.z = problem; masked rows), on FP64
+// matrix cores: each workgroup holds a 32 x 16 tile of C[k, t] = sum_i m_b(i) x_{pool[k], i} x_{pool[P0+t], i},
+// its four waves take a quarter of the rows each (64 rows a step, the next step's values loaded while the
+// current one is multiplied) and their partial tiles are added in wave order through LDS.  Lane (m, kq)
+// feeds rows i0 + 16 kq .. + 15 of pool columns kb + m, kb + 16 + m and new column tb + m; register q of its
+// result holds C[kb + kq + 4q (+ 16), tb + m].  A pair of two new columns is written by the tile with
+// k - P0 <= t only, so each problem's G stays exactly symmetric.
+constexpr int BG_W = 4, BG_K = 32, BG_N = 16, BG_R = 64;
 
 template <typename XT>
-__global__ __launch_bounds__(256) void k_b_gram_update(const XT* __restrict__ X, int64_t ldx, int64_t n_total,
-                                                       const uint8_t* __restrict__ masks, int64_t p,
-                                                       const int32_t* __restrict__ pool_list,
-                                                       const BatchScalars* __restrict__ bs,
-                                                       const double* __restrict__ c, const double* __restrict__ s,
-                                                       double* __restrict__ Gp, int64_t cap,
-                                                       const uint8_t* __restrict__ want) {
-    __shared__ double As[GR][GK + 1];
-    __shared__ double Bs[GR][GN + 1];
+__global__ __launch_bounds__(64 * BG_W) void k_b_gram_update(const XT* __restrict__ X, int64_t ldx, int64_t n_total,
+                                                            const uint8_t* __restrict__ masks, int64_t p,
+                                                            const int32_t* __restrict__ pool_list,
+                                                            const BatchScalars* __restrict__ bs,
+                                                            const double* __restrict__ c,
+                                                            const double* __restrict__ s, double* __restrict__ Gp,
+                                                            int64_t cap, const uint8_t* __restrict__ want) {
+    __shared__ f64x4 red[BG_W - 1][2][WAVE];
     const int b = blockIdx.z;
     if (!want[b]) return;
     const int64_t N = bs[b].n_new, P0 = bs[b].pool_size, P = P0 + N;
-    const int64_t k0 = (int64_t)blockIdx.x * GK, t0 = (int64_t)blockIdx.y * GN;
-    if (k0 >= P || t0 >= N) return;
+    const int64_t kb = (int64_t)blockIdx.x * BG_K, tb = (int64_t)blockIdx.y * BG_N;
+    if (kb >= P || tb >= N) return;   // whole workgroup, before its barrier
     const int32_t* list = pool_list + (int64_t)b * p;
     const uint8_t* mk = masks + (int64_t)b * n_total;
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const int m = lane & 15, kq = lane >> 4;
+    const XT* ac[2];
+    bool aok[2];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+        const int64_t k = kb + 16 * f + m;
+        aok[f] = k < P;
+        ac[f] = X + (int64_t)(aok[f] ? list[k] : 0) * ldx;
+    }
+    const bool bok = tb + m < N;
+    const XT* bc = X + (int64_t)(bok ? list[P0 + tb + m] : 0) * ldx;
+    const int64_t ns = (n_total + BG_R - 1) / BG_R;
+    const int64_t s0 = ns * w / BG_W, s1 = ns * (w + 1) / BG_W;
+    XT ra[2][16], rb[16];
+    bool rm[16];
+    auto load = [&](int64_t step) {
+        const int64_t r0 = step * BG_R + 16 * kq;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const bool in = r0 + q < n_total;
+            ra[0][q] = (aok[0] && in) ? ac[0][r0 + q] : (XT)0;
+            ra[1][q] = (aok[1] && in) ? ac[1][r0 + q] : (XT)0;
+            rb[q] = (bok && in) ? bc[r0 + q] : (XT)0;
+            rm[q] = in && mk[r0 + q] != 0;
+        }
+    };
+    f64x4 acc[2] = {(f64x4){0.0, 0.0, 0.0, 0.0}, (f64x4){0.0, 0.0, 0.0, 0.0}};
+    if (s0 < s1) load(s0);
+    for (int64_t step = s0; step < s1; ++step) {
+        double av[2][16], bv[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            av[0][q] = (double)ra[0][q];
+            av[1][q] = (double)ra[1][q];
+            bv[q] = rm[q] ? (double)rb[q] : 0.0;
+        }
+        if (step + 1 < s1) load(step + 1);
+#pragma unroll
+        for (int st = 0; st < 16; ++st) {
+            acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0][st], bv[st], acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1][st], bv[st], acc[1], 0, 0, 0);
+        }
+    }
+    if (w > 0) {
+        red[w - 1][0][lane] = acc[0];
+        red[w - 1][1][lane] = acc[1];
+    }
+    __syncthreads();
+    if (w > 0) return;
+#pragma unroll
+    for (int v = 0; v < BG_W - 1; ++v) {
+        acc[0] += red[v][0][lane];
+        acc[1] += red[v][1][lane];
+    }
+    const int64_t t = tb + m;
+    if (t >= N) return;
     const double* cb = c + (int64_t)b * p;
     const double* sb = s + (int64_t)b * p;
     double* G = Gp + (int64_t)b * cap * cap;
     const double nb = (double)bs[b].n_rows;
-    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-    double acc[4][2] = {};
-    const int a_col = tid / 4, a_row = (tid % 4) * 8;
-    const int b_col = tid / 8, b_row = (tid % 8) * 4;
-    const XT* acol = (k0 + a_col < P) ? X + (int64_t)list[k0 + a_col] * ldx : nullptr;
-    const XT* bcol = (t0 + b_col < N) ? X + (int64_t)list[P0 + t0 + b_col] * ldx : nullptr;
-    for (int64_t i0 = 0; i0 < n_total; i0 += GR) {
+    const int jt = list[P0 + t];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int64_t i = i0 + a_row + q;
-            As[a_row + q][a_col] = (acol && i < n_total) ? (double)acol[i] : 0.0;
-        }
+    for (int f = 0; f < 2; ++f) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int64_t i = i0 + b_row + q;
-            Bs[b_row + q][b_col] = (bcol && i < n_total && mk[i]) ? (double)bcol[i] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll 8
-        for (int rr = 0; rr < GR; ++rr) {
-            double av[4], bv[2];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) av[q] = As[rr][tx + 16 * q];
-#pragma unroll
-            for (int q = 0; q < 2; ++q) bv[q] = Bs[rr][ty + 16 * q];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int w2 = 0; w2 < 2; ++w2) acc[q][w2] = fma(av[q], bv[w2], acc[q][w2]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t k = k0 + tx + 16 * q;
-        if (k >= P) continue;
-        const int jk = list[k];
-#pragma unroll
-        for (int w2 = 0; w2 < 2; ++w2) {
-            const int64_t t = t0 + ty + 16 * w2;
-            if (t >= N) continue;
-            const int jt = list[P0 + t];
-            const double gv = (acc[q][w2] - nb * (cb[jk] * cb[jt])) / (nb * (sb[jk] * sb[jt]));
+            const int64_t k = kb + 16 * f + kq + 4 * q;
+            if (k >= P) continue;
+            if (k >= P0 && k - P0 > t) continue;   // written by the tile of its mirror
+            const int jk = list[k];
+            const double gv = (acc[f][q] - nb * (cb[jk] * cb[jt])) / (nb * (sb[jk] * sb[jt]));
             G[k * cap + (P0 + t)] = gv;
             G[(P0 + t) * cap + k] = gv;
         }
@@ -935,12 +964,12 @@ hipError_t launch_b_gram_update(const Mat& mt, const uint8_t* masks, int nprob, 
                                 const BatchScalars* bs, const double* c, const double* s, double* Gp, int64_t cap,
                                 int64_t max_P, int64_t max_N, const uint8_t* want, hipStream_t st) {
     if (max_N <= 0) return hipSuccess;
-    dim3 grid((unsigned)((max_P + GK - 1) / GK), (unsigned)((max_N + GN - 1) / GN), nprob);
+    dim3 grid((unsigned)((max_P + BG_K - 1) / BG_K), (unsigned)((max_N + BG_N - 1) / BG_N), nprob);
     if (mt.xtype == 0)
-        k_b_gram_update<double><<<grid, 256, 0, st>>>((const double*)mt.X, mt.ldx, mt.n_total, masks, mt.p, pool_list,
+        k_b_gram_update<double><<<grid, 64 * BG_W, 0, st>>>((const double*)mt.X, mt.ldx, mt.n_total, masks, mt.p, pool_list,
                                                       bs, c, s, Gp, cap, want);
     else
-        k_b_gram_update<float><<<grid, 256, 0, st>>>((const float*)mt.X, mt.ldx, mt.n_total, masks, mt.p, pool_list, bs,
+        k_b_gram_update<float><<<grid, 64 * BG_W, 0, st>>>((const float*)mt.X, mt.ldx, mt.n_total, masks, mt.p, pool_list, bs,
                                                      c, s, Gp, cap, want);
     return hipGetLastError();
 }
