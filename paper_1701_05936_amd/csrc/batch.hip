@@ -57,14 +57,14 @@ int grid_for(int64_t work, int per_block, int max_blocks) {
 // rows of its column (rows i0 + 16kq .. +15) and feeds row i0 + 16kq + st at MFMA step st; the same rows of B
 // come from LDS (double buffered, padded rows against bank conflicts).  The next batch's X values are loaded
 // into registers while the current batch is on the matrix cores when PF is set (more registers, fewer waves
-// in flight).  WAVES (2, 4 or 8) and PF are picked per shape by the autotuner: wider workgroups stage each
+// in flight); X values are converted to FP64 only as the matrix cores take them.  WAVES (2, 4 or 8) and PF are picked per shape by the autotuner: wider workgroups stage each
 // B batch for more columns, narrower ones give more workgroups.
 constexpr int BS_K = 64;
 constexpr int BS_LD = BNP + 2;   // LDS row stride of the staged B rows (doubles)
 
 // mode 0: raw dot products; mode 1: squared X (masked second moments); mode 2: standardized correlations
 template <typename XT, int MODE, int WAVES, bool PF>
-__global__ __launch_bounds__(64 * WAVES) void k_bscan(const XT* __restrict__ X, int64_t ldx, int64_t n_total,
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2))) void k_bscan(const XT* __restrict__ X, int64_t ldx, int64_t n_total,
                                                       int64_t n_pad, const int32_t* __restrict__ cols,
                                                       const int64_t* __restrict__ len_dev, int64_t len_host,
                                                       const double* __restrict__ B, int nprob, int64_t p,
@@ -94,62 +94,73 @@ __global__ __launch_bounds__(64 * WAVES) void k_bscan(const XT* __restrict__ X, 
 #pragma unroll
         for (int pt = 0; pt < 4; ++pt) acc[ft][pt] = (f64x4){0.0, 0.0, 0.0, 0.0};
 
-    auto stage = [&](int buf, int64_t i0) {
-        // 64 rows x 64 problems
-        for (int idx = tid; idx < BS_K * BNP / 2; idx += NT) {
-            const int row = idx / (BNP / 2), col2 = (idx % (BNP / 2)) * 2;
-            const double* src = B + (i0 + row) * BNP + col2;
-            Bl[buf][row * BS_LD + col2] = src[0];
-            Bl[buf][row * BS_LD + col2 + 1] = src[1];
-        }
+    // a batch of B (64 rows x 64 problems) is staged in two halves: its loads are issued before the current
+    // batch goes to the matrix cores and its LDS stores after, so the wave does not wait on them in between
+    constexpr int SPT = BS_K * BNP / NT;   // B values per thread
+    double sreg[SPT];
+    auto stage_load = [&](int64_t i0) {
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) sreg[q] = B[(i0 + (tid + q * NT) / BNP) * BNP + (tid + q * NT) % BNP];
     };
-    // raw X values of the lane's rows of one batch (zero past n_total or for an idle column)
-    XT xr[2][16];
-    auto load = [&](int64_t i0) {
+    auto stage_store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) Bl[buf][((tid + q * NT) / BNP) * BS_LD + (tid + q * NT) % BNP] = sreg[q];
+    };
+    // raw X values of the lane's rows of one batch (zero past n_total or for an idle column), converted to
+    // FP64 as the matrix cores take them; with PF the next batch's values load into xn meanwhile
+    XT xr[2][16], xn[2][16];
+    auto load = [&](XT (&dst)[2][16], int64_t i0) {
 #pragma unroll
         for (int ft = 0; ft < 2; ++ft) {
             const int64_t r0 = i0 + 16 * kq;
             if (ok[ft] && r0 + 16 <= n_total) {
 #pragma unroll
-                for (int q = 0; q < 16; ++q) xr[ft][q] = xc[ft][r0 + q];
+                for (int q = 0; q < 16; ++q) dst[ft][q] = xc[ft][r0 + q];
             } else {
 #pragma unroll
-                for (int q = 0; q < 16; ++q) xr[ft][q] = (ok[ft] && r0 + q < n_total) ? xc[ft][r0 + q] : (XT)0;
+                for (int q = 0; q < 16; ++q) dst[ft][q] = (ok[ft] && r0 + q < n_total) ? xc[ft][r0 + q] : (XT)0;
             }
         }
     };
     int buf = 0;
-    if (PF) load(0);
-    stage(0, 0);
+    if (PF) load(xr, 0);
+    stage_load(0);
+    stage_store(0);
     __syncthreads();
     for (int64_t i0 = 0; i0 < n_pad; i0 += BS_K) {
-        if (!PF) load(i0);
-        double xa[2][16];
-#pragma unroll
-        for (int ft = 0; ft < 2; ++ft)
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const double v = (double)xr[ft][q];
-                xa[ft][q] = MODE == 1 ? v * v : v;
-            }
-        if (i0 + BS_K < n_pad) {
-            if (PF) load(i0 + BS_K);
-            stage(buf ^ 1, i0 + BS_K);
+        if (!PF) load(xr, i0);
+        const bool more = i0 + BS_K < n_pad;
+        if (more) {
+            if (PF) load(xn, i0 + BS_K);
+            stage_load(i0 + BS_K);
         }
         const double* Bb = Bl[buf];
 #pragma unroll
         for (int st = 0; st < 16; ++st) {
             const int row = 16 * kq + st;
+            double xa[2];
+#pragma unroll
+            for (int ft = 0; ft < 2; ++ft) {
+                const double v = (double)xr[ft][st];
+                xa[ft] = MODE == 1 ? v * v : v;
+            }
 #pragma unroll
             for (int pt = 0; pt < 4; ++pt) {
                 const double bv = Bb[row * BS_LD + 16 * pt + m];
 #pragma unroll
                 for (int ft = 0; ft < 2; ++ft)
-                    acc[ft][pt] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ft][st], bv, acc[ft][pt], 0, 0, 0);
+                    acc[ft][pt] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ft], bv, acc[ft][pt], 0, 0, 0);
             }
         }
+        if (more) stage_store(buf ^ 1);   // the other buffer was last read before the previous barrier
         __syncthreads();
         buf ^= 1;
+        if (PF) {
+#pragma unroll
+            for (int ft = 0; ft < 2; ++ft)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) xr[ft][q] = xn[ft][q];
+        }
     }
     // lane (m, kq), register q of tile (ft, pt) holds column 32w + 16ft + kq + 4q against problem 16pt + m
 #pragma unroll
