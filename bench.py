@@ -11,8 +11,10 @@ Workloads (--workload):
                 nonzero coefficients ~ N(0,1), SNR 1, 100 lambda values down to
                 0.05 lambda_max, hybrid BEDPP + strong-rule screening, CD tolerance 1e-8.
   c3            precision form: genotype 10,000 x 2,000,000 stored as int8 (20 GB),
-                200 nonzeros, scans on BF16 matrix cores with FP64 decisions; the
-                plain FP64-scan path on the same int8 storage is timed beside it.
+                200 nonzeros, scans on int8 matrix cores (--precision-form i8x4, the
+                default) or BF16 matrix cores (bf16x3) with FP64 decisions; the plain
+                FP64-scan path on the same int8 storage and the other form are timed
+                beside it.
   c4            batched form: AR(1) (rho 0.5) design 20,000 x 200,000 float32 (16 GB),
                 64 problems = 32 responses x 2 cross-validation row subsets, 50 lambda
                 values each; plain single-problem paths on a sample of the problems are
@@ -157,11 +159,24 @@ def run_plain(args, rec, ctx, bl, Xd, Xt, yd, y):
     return out
 
 
+PRECISION_FORMS = {
+    # form: (bl constant name, dtype, workload text, dominant kernel, counter summary under profiles/)
+    "i8x4": ("PREC_I8X4", "i8 codes, int8 matrix-core scan against 4 int8 residual pieces, f64 decisions",
+             "int8 x4 power-of-two residual pieces, exact int32 sums", "k_scan_i8 (int8 X, int8 MFMA)",
+             "k_scan_i8_c3_genotype_10000x2000000_i8.md"),
+    "bf16x3": ("PREC_BF16X3", "i8 codes, bf16x3 matrix-core scan, f64 decisions",
+               "BF16 x3 residual pieces, FP32 partial sums promoted to FP64", "k_scan_bf16 (int8 X, BF16 MFMA)",
+               "k_scan_bf16_c3_genotype_10000x2000000_i8.md"),
+}
+
+
 def run_precision(args, rec, ctx, bl, Xd, Xt, yd, y):
     import torch
+    const, dtype, text, kname, summary = PRECISION_FORMS[args.precision_form]
+    prec = getattr(bl, const)
     kw = dict(nlambda=rec.nlambda, lambda_min_ratio=rec.lambda_min_ratio, rule=bl.SCREEN_SSR_BEDPP, tol=args.tol)
-    results, elapsed = timed(lambda: bl.fit_path(ctx, Xd, yd, precision=bl.PREC_BF16X3, **kw), args.steps,
-                             args.warmup, ctx, "bf16x3")
+    results, elapsed = timed(lambda: bl.fit_path(ctx, Xd, yd, precision=prec, **kw), args.steps,
+                             args.warmup, ctx, args.precision_form)
     kernels = kernel_table(ctx, bl, elapsed)
     ctx.profile(False)
     lp = results[-1]
@@ -171,22 +186,31 @@ def run_precision(args, rec, ctx, bl, Xd, Xt, yd, y):
     hp = plain[-1]
     same = bool(torch.equal(lp.beta, hp.beta))
     dmax = float((lp.beta - hp.beta).abs().max())
+    forms = {"plain_gpu_same_storage_paths_per_s": 1.0 / el_plain,
+             "speedup_vs_plain_gpu": (args.steps / elapsed) * el_plain,
+             "max_abs_dbeta_vs_fp64_path": dmax, "beta_bitwise_equal_to_fp64_path": same,
+             "fp64_rechecks": int(lp.n_recheck.sum())}
+    for other in PRECISION_FORMS:
+        if other == args.precision_form or args.no_other_forms:
+            continue
+        op = getattr(bl, PRECISION_FORMS[other][0])
+        res_o, el_o = timed(lambda: bl.fit_path(ctx, Xd, yd, precision=op, **kw), 1, 0, ctx, other)
+        ctx.profile(False)
+        forms[f"{other}_paths_per_s"] = 1.0 / el_o
+        forms[f"{other}_beta_bitwise_equal_to_fp64_path"] = bool(torch.equal(res_o[-1].beta, hp.beta))
+        forms[f"{other}_fp64_rechecks"] = int(res_o[-1].n_recheck.sum())
     out = {
         "value": args.steps / elapsed,
         "ms_per_step": elapsed * 1e3 / args.steps,
-        "dtype": "i8 codes, bf16x3 matrix-core scan, f64 decisions",
+        "dtype": dtype,
         "config": {"workload": f"{rec.name}: genotype X {rec.n}x{rec.p} stored int8, precision form "
-                               f"(BF16 x3 residual pieces, FP32 partial sums promoted to FP64), "
+                               f"({text}), "
                                f"{rec.nlambda} lambda to {rec.lambda_min_ratio} lambda_max, SSR-BEDPP, "
                                f"CD tol {args.tol:g}",
                    "n": rec.n, "p": rec.p, "nlambda": rec.nlambda},
-        "roofline": hbm_roofline(kernels["scan"], "k_scan_bf16 (int8 X, BF16 MFMA)",
-                                 "k_scan_bf16_c3_genotype_10000x2000000_i8.md"),
+        "roofline": hbm_roofline(kernels["scan"], kname, summary),
         "kernels": kernels,
-        "forms": {"plain_gpu_same_storage_paths_per_s": 1.0 / el_plain,
-                  "speedup_vs_plain_gpu": (args.steps / elapsed) * el_plain,
-                  "max_abs_dbeta_vs_fp64_path": dmax, "beta_bitwise_equal_to_fp64_path": same,
-                  "fp64_rechecks": int(lp.n_recheck.sum())},
+        "forms": forms,
         "path": {"n_active_last": int(lp.n_active[-1]), "sweeps": int(lp.sweeps.sum()),
                  "violations": int(lp.n_viol.sum())},
     }
@@ -347,6 +371,9 @@ def main():
     ap.add_argument("--cpu-cols", type=int, default=None)
     ap.add_argument("--plain-sample", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision-form", default="i8x4", choices=tuple(PRECISION_FORMS),
+                    help="matrix-core form of the c3 check scans (the other form is timed once beside it)")
+    ap.add_argument("--no-other-forms", action="store_true", help="c3: skip the other precision form's path")
     ap.add_argument("--copy-calib", type=float, default=0.0,
                     help="only copy a buffer of this many GB once (device to device) and exit: the reference "
                          "kernel for scaling FETCH_SIZE / WRITE_SIZE counters")

@@ -167,9 +167,12 @@ bl_status bl_kkt_check(bl_ctx ctx, const bl_matrix* X, const double* center, con
 /* Arithmetic of the check scans. */
 typedef enum {
     BL_PREC_FP64 = 0,      /* FP64 vector scan (any X type)                                          */
-    BL_PREC_BF16X3 = 1     /* int8 X only: BF16 matrix cores against three BF16 pieces of the residual,
+    BL_PREC_BF16X3 = 1,    /* int8 X only: BF16 matrix cores against three BF16 pieces of the residual,
                               FP32 chunks promoted to FP64; decisions within the error bound are
                               re-taken on the FP64 scan, so they equal the FP64 decisions            */
+    BL_PREC_I8X4 = 2       /* int8 X only: int8 matrix cores against four int8 pieces of the residual
+                              with power-of-two scales, exact integer sums; decisions within the
+                              error bound are re-taken on the FP64 scan, as for BL_PREC_BF16X3       */
 } bl_precision;
 
 /*
@@ -180,8 +183,14 @@ typedef enum {
  *   u_r = (2^-8 + 2^-24)^3 (residual left after three BF16 pieces, relative to |r_i|),
  *   g32 = 32 u / (1 - 32 u), u = 2^-24 (FP32 chunks of 32 rows), g64 = 65536 * 2^-53 (FP64 sums of up
  *   to 2^16 chunk and piece terms; n_total <= 2^21),
- * plus 1e-14 |z_j|.  BL_ERR_UNSUPPORTED for BF16X3 unless X is int8 with 16-byte aligned
- * columns (X pointer and ldx a multiple of 16) and n_total <= 2^21.
+ * plus 1e-14 |z_j|.  For BL_PREC_I8X4 the residual is r = sum_k s_k q_k + t with int8 pieces q_1..q_4,
+ * s_1 = 2^E the smallest power of two with max|r_i| <= 127 s_1 and s_{k+1} = s_k / 128, and
+ *   err_j = ((||t||_2 + g3 ||w||_2)(1 + 2^-20) + g64 ||r||_2) sqrt(n (s_j^2 + c_j^2)) / (n s_j) + 1e-14 |z_j|,
+ *   w_i = sum_k s_k |q_ik|, g3 = 3 u / (1 - 3 u), u = 2^-53 (the FP64 sum of the four exact integer
+ *   dot products), g64 as above.  The I8X4 scan reads columns in whole 16-byte words: the bytes after
+ *   row n_total - 1 in the aligned word that holds it are read and multiplied by zero pieces.
+ * BL_ERR_UNSUPPORTED for BF16X3 and I8X4 unless X is int8 with 16-byte aligned columns (X pointer
+ * and ldx a multiple of 16) and n_total <= 2^21.
  */
 bl_status bl_scan(bl_ctx ctx, const bl_matrix* X, const double* center, const double* scale, const double* r,
                   const int32_t* cols, int64_t len, int32_t precision, double* z, double* err);

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libbl.so")
 BL_OK, BL_ERR_INVALID, BL_ERR_NOMEM, BL_ERR_DEVICE, BL_ERR_NOT_CONVERGED, BL_ERR_UNSUPPORTED = range(6)
 X_F64, X_F32, X_I8 = 0, 1, 2
 SCREEN_NONE, SCREEN_SSR, SCREEN_BEDPP, SCREEN_SSR_BEDPP, SCREEN_LEARNED = 0, 1, 2, 3, 4
-PREC_FP64, PREC_BF16X3 = 0, 1
+PREC_FP64, PREC_BF16X3, PREC_I8X4 = 0, 1, 2
 
 _STATUS_NAMES = {0: "BL_OK", 1: "BL_ERR_INVALID", 2: "BL_ERR_NOMEM", 3: "BL_ERR_DEVICE",
                  4: "BL_ERR_NOT_CONVERGED", 5: "BL_ERR_UNSUPPORTED"}
@@ -303,7 +303,7 @@ def kkt_check(ctx: Context, Xt, c, s, r, lam, check_set, exclude=None, z=None, r
 
 
 def scan(ctx: Context, Xt, c, s, r, cols, precision=PREC_FP64, row_mask=None, n_total=None, want_err=False):
-    """z over cols (and, for the BF16 form, the guaranteed error bound per column)."""
+    """z over cols (and, for the matrix-core forms, the guaranteed error bound per column)."""
     M = matrix(Xt, n_total, row_mask)
     if cols.dtype != torch.int32:
         raise TypeError("cols must be int32")

@@ -575,9 +575,10 @@ bl_status bl_scan(bl_ctx ctx, const bl_matrix* X, const double* center, const do
     if (!center || !scale || !r || !z) return fail(ctx, BL_ERR_INVALID, "array arguments must be non-NULL");
     if (len < 0 || len > m.p) return fail(ctx, BL_ERR_INVALID, "len out of range");
     if (len > 0 && !cols) return fail(ctx, BL_ERR_INVALID, "cols is NULL");
-    if (precision != BL_PREC_FP64 && precision != BL_PREC_BF16X3) return fail(ctx, BL_ERR_INVALID, "unknown precision");
-    if (precision == BL_PREC_BF16X3 && !lowp_supported(m))
-        return fail(ctx, BL_ERR_UNSUPPORTED, "BF16 scan needs int8 X with 16-byte aligned columns");
+    if (precision != BL_PREC_FP64 && precision != BL_PREC_BF16X3 && precision != BL_PREC_I8X4)
+        return fail(ctx, BL_ERR_INVALID, "unknown precision");
+    if (precision != BL_PREC_FP64 && !lowp_supported(m))
+        return fail(ctx, BL_ERR_UNSUPPORTED, "matrix-core scans need int8 X with 16-byte aligned columns");
     int64_t n;
     if ((s = rows_in_fit(ctx, m, &n))) return s;
     if ((s = set_n_rows(ctx, n))) return s;
@@ -595,17 +596,25 @@ bl_status bl_scan(bl_ctx ctx, const bl_matrix* X, const double* center, const do
             sa.z = z;
             HIPCHK(launch_scan(m, sa, st));
         } else {
-            __bf16* pieces;
+            const bool i8 = precision == BL_PREC_I8X4;
+            void* pieces;
             int64_t* lens;
-            ENSURE(B_PIECES, (size_t)LOWP_PIECES * lowp_pad(m.n_total) * 2, pieces);
+            ENSURE(B_PIECES, lowp_piece_bytes(m.n_total), pieces);
             ENSURE(B_LENS, 8 * sizeof(int64_t), lens);
-            HIPCHK(launch_r_pieces(r, m.n_total, pieces, st));
-            HIPCHK(launch_scan_bf16(m, pieces, cols, nullptr, len, ctx->sc, center, scale, nullptr, z, st));
+            if (i8) {
+                HIPCHK(launch_r_pieces_i8(r, m.n_total, (int8_t*)pieces, ctx->sc, st));
+                HIPCHK(launch_scan_i8(m, (const int8_t*)pieces, cols, nullptr, len, ctx->sc, center, scale, nullptr, z,
+                                      st));
+            } else {
+                HIPCHK(launch_r_pieces(r, m.n_total, (__bf16*)pieces, st));
+                HIPCHK(launch_scan_bf16(m, (const __bf16*)pieces, cols, nullptr, len, ctx->sc, center, scale, nullptr,
+                                        z, st));
+            }
             if (err) {
                 ctx->sc_host->stage = len;
                 HIPCHK(hipMemcpyAsync(lens + 5, &ctx->sc_host->stage, sizeof(int64_t), hipMemcpyHostToDevice, st));
                 HIPCHK(launch_band(cols, lens + 5, z, center, scale, ctx->sc, -1.0, nullptr, nullptr, -1.0, nullptr,
-                                   err, m.p, st));
+                                   err, m.p, i8, st));
             }
         }
     }
@@ -650,11 +659,12 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
     const bool history = learned || recording;
     const float tau_logit = learned && opts->mlp_tau > 0.0 ? (float)std::log(opts->mlp_tau / (1.0 - opts->mlp_tau))
                                                            : -INFINITY;
-    if (opts->precision != BL_PREC_FP64 && opts->precision != BL_PREC_BF16X3)
+    if (opts->precision != BL_PREC_FP64 && opts->precision != BL_PREC_BF16X3 && opts->precision != BL_PREC_I8X4)
         return fail(ctx, BL_ERR_INVALID, "unknown precision");
-    const bool lowp = opts->precision == BL_PREC_BF16X3;
+    const bool lowp = opts->precision != BL_PREC_FP64;
+    const bool i8 = opts->precision == BL_PREC_I8X4;
     if (lowp && !lowp_supported(m))
-        return fail(ctx, BL_ERR_UNSUPPORTED, "BF16 scan needs int8 X with 16-byte aligned columns");
+        return fail(ctx, BL_ERR_UNSUPPORTED, "matrix-core scans need int8 X with 16-byte aligned columns");
     const int64_t p = m.p, nt = m.n_total;
     hipStream_t st = ctx->stream;
 
@@ -697,11 +707,11 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         ENSURE(B_CAND, p, cand);
         ENSURE(B_LC, p * 4, lC);
     }
-    __bf16* pieces = nullptr;
+    void* pieces = nullptr;
     uint8_t* flag = nullptr;
     int32_t* lB = nullptr;
     if (lowp) {
-        ENSURE(B_PIECES, (size_t)LOWP_PIECES * lowp_pad(nt) * 2, pieces);
+        ENSURE(B_PIECES, lowp_piece_bytes(nt), pieces);
         ENSURE(B_MARK, p, flag);
         ENSURE(B_LB, p * 4, lB);
     }
@@ -871,17 +881,25 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
                 HIPCHK(launch_scan(m, ka, st));
                 prof_mark(ctx, 3);
             } else {
-                // BF16 matrix-core scan, then exact FP64 re-scans of the values near a threshold
-                HIPCHK(launch_r_pieces(r, nt, pieces, st));
-                prof_mark(ctx, 2);
-                HIPCHK(launch_scan_bf16(m, pieces, lT, len_next, 0, ctx->sc, c, sc_, keep, zcur, st));
-                prof_mark(ctx, 3);
+                // matrix-core scan, then exact FP64 re-scans of the values near a threshold
+                if (i8) {
+                    HIPCHK(launch_r_pieces_i8(r, nt, (int8_t*)pieces, ctx->sc, st));
+                    prof_mark(ctx, 2);
+                    HIPCHK(launch_scan_i8(m, (const int8_t*)pieces, lT, len_next, 0, ctx->sc, c, sc_, keep, zcur, st));
+                    prof_mark(ctx, 3);
+                } else {
+                    HIPCHK(launch_r_pieces(r, nt, (__bf16*)pieces, st));
+                    prof_mark(ctx, 2);
+                    HIPCHK(launch_scan_bf16(m, (const __bf16*)pieces, lT, len_next, 0, ctx->sc, c, sc_, keep, zcur,
+                                            st));
+                    prof_mark(ctx, 3);
+                }
                 prof_mark(ctx, 8);
                 HIPCHK(hipMemcpyAsync(&ctx->sc->round.scan_len, len_next, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
                 HIPCHK(launch_fill_u8(flag, 0, p, st));
                 const double thr2 = (ssr && k + 1 < K) ? 2.0 * lam[k + 1] - lk : -1.0;
                 HIPCHK(launch_band(lT, len_next, zcur, c, sc_, ctx->sc, ssr ? lk : -1.0, safe_cur, strong, thr2, flag,
-                                   nullptr, p, st));
+                                   nullptr, p, i8, st));
                 HIPCHK(launch_compact(flag, p, lB, lens + 4, scr, st));
                 ScanArgs ba{};
                 ba.cols = lB;

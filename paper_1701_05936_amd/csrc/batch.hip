@@ -64,7 +64,7 @@ constexpr int BS_LD = BNP + 2;   // LDS row stride of the staged B rows (doubles
 
 // mode 0: raw dot products; mode 1: squared X (masked second moments); mode 2: standardized correlations
 template <typename XT, int MODE, int WAVES, bool PF>
-__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2))) void k_bscan(const XT* __restrict__ X, int64_t ldx, int64_t n_total,
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVES >= 4 ? 2 : 1))) void k_bscan(const XT* __restrict__ X, int64_t ldx, int64_t n_total,
                                                       int64_t n_pad, const int32_t* __restrict__ cols,
                                                       const int64_t* __restrict__ len_dev, int64_t len_host,
                                                       const double* __restrict__ B, int nprob, int64_t p,

@@ -38,6 +38,8 @@ struct DevScalars {
     int64_t n_new;     // features the last pool update added
     int64_t stage;     // host staging slot for small device-to-host and host-to-device copies
     RoundInfo round;
+    double i8_scale[4];   // power-of-two scales of the int8 residual pieces (int8 matrix-core form)
+    double i8_a;          // that form's bound numerator: (||remainder||_2 + gamma_3 ||sum_k s_k |q_k| ||_2)(1 + 2^-20)
 };
 
 struct Mat {
@@ -174,20 +176,28 @@ size_t r_update_scratch_bytes(int64_t n_total, int64_t m);
 hipError_t launch_r_update(const Mat& mt, const int32_t* set, int64_t m, const double* b0, const double* b1,
                            const double* c, const double* s, double* part, double* r, hipStream_t st);
 
-// ---- precision form: int8 codes on BF16 matrix cores (lowp.hip) ----
+// ---- precision forms: int8 codes on BF16 or int8 matrix cores (lowp.hip) ----
 constexpr int LOWP_PIECES = 3;  // BF16 pieces of the residual
 int64_t lowp_pad(int64_t n_total);          // rows of each residual piece buffer (multiple of 128)
+size_t lowp_piece_bytes(int64_t n_total);  // piece buffer of either form
 double lowp_coef();                         // error coefficient of the scan bound
 bool lowp_supported(const Mat& m);          // int8 X, 16-byte aligned columns
 hipError_t launch_r_pieces(const double* r, int64_t n_total, __bf16* pieces, hipStream_t st);
 hipError_t launch_scan_bf16(const Mat& m, const __bf16* pieces, const int32_t* cols, const int64_t* len_dev,
                             int64_t len_host, const DevScalars* sc, const double* c, const double* s,
                             const uint8_t* keep, double* z, hipStream_t st);
+// int8 codes on int8 matrix cores against LOWP_I8_PIECES int8 pieces of the residual
+constexpr int LOWP_I8_PIECES = 4;
+// pieces [LOWP_I8_PIECES][lowp_pad(n_total)] int8 plus sc->i8_scale and sc->i8_a (one workgroup)
+hipError_t launch_r_pieces_i8(const double* r, int64_t n_total, int8_t* pieces, DevScalars* sc, hipStream_t st);
+hipError_t launch_scan_i8(const Mat& m, const int8_t* pieces, const int32_t* cols, const int64_t* len_dev,
+                          int64_t len_host, const DevScalars* sc, const double* c, const double* s,
+                          const uint8_t* keep, double* z, hipStream_t st);
 // flag[j] = 1 (flag pre-zeroed) when |z_j| is within its bound of lam (j in in_s, not in excl) or of thr2 (>= 0);
-// err_out[j] = the bound (either pointer may be null)
+// err_out[j] = the bound (either pointer may be null); i8 selects the int8 form's bound
 hipError_t launch_band(const int32_t* cols, const int64_t* len_dev, const double* z, const double* c, const double* s,
                        const DevScalars* sc, double lam, const uint8_t* in_s, const uint8_t* excl, double thr2,
-                       uint8_t* flag, double* err_out, int64_t p, hipStream_t st);
+                       uint8_t* flag, double* err_out, int64_t p, bool i8, hipStream_t st);
 hipError_t launch_viol(const int32_t* cols, const int64_t* len_dev, const double* z, const uint8_t* in_s, uint8_t* inE,
                        double lam, uint32_t* nviol, int64_t p, hipStream_t st);
 

@@ -1,5 +1,6 @@
-// Precision form of the scan: int8 design codes on BF16 matrix cores.
+// Precision forms of the scan: int8 design codes on BF16 or on int8 matrix cores.
 //
+// BF16 form:
 // z_j = (x_j' r - c_j sum(r)) / (n s_j) is computed as Z = X_T' [r1 r2 r3] with
 //   r1 = bf16(r), r2 = bf16(r - r1), r3 = bf16(r - r1 - r2)   (residual pieces, FP64 differences)
 // on v_mfma_f32_16x16x32_bf16.  Int8 codes convert to BF16 exactly (|x| <= 256),
@@ -13,6 +14,13 @@
 // a wavefront load covers 16 full 128-byte segments.  The MFMA reduction order
 // over rows is free, so step s of a batch feeds rows i0 + 32g + 8s .. +7 of lane
 // group g to both operands.  The residual pieces sit in LDS.
+//
+// int8 form: the residual is split into four int8 pieces with power-of-two scales,
+//   r = s_1 q_1 + s_2 q_2 + s_3 q_3 + s_4 q_4 + t,   s_{k+1} = s_k / 128,
+// each s_k q_k and the remainder t exact in FP64.  X_T' [q_1 .. q_4] runs on v_mfma_i32_16x16x64_i8
+// with exact int32 sums (moved to FP64 every 1,024 rows, far below 2^31 / (128 x 127) rows), and
+// x_j' r = sum_k s_k D_jk + x_j' t.  The only errors are x_j' t (bounded by ||x_j||_2 ||t||_2) and the
+// FP64 sum of the four scaled integers; the codes are fed to the matrix cores as loaded.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -197,24 +205,217 @@ __global__ __launch_bounds__(256) void k_scan_bf16(const int8_t* __restrict__ X,
     }
 }
 
-// Bound on |z~_j - z_j| for the BF16 scan (see lowp.hip header):
-//   (u_r + (1 + 2^-7) gamma_32 + gamma64) * ||x_j||_2 ||r||_2 / (n s_j),  ||x_j||_2^2 = n (s_j^2 + c_j^2)
-__device__ __forceinline__ double lowp_bound(double cj, double sj, double n, double rnorm, double coef) {
-    return coef * sqrt(n * (sj * sj + cj * cj)) * rnorm / (n * sj);
+// ---- int8 form ----
+// keeps the loads above it issued before the work below it: neither the IR passes (memory clobber) nor the
+// machine scheduler (sched_barrier) move them down to their first use
+__device__ __forceinline__ void issue_fence() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+constexpr int I8P = LOWP_I8_PIECES;
+constexpr int I8_SHIFT = 7;             // s_{k+1} = s_k 2^-7: the remainder after piece k is at most s_k / 2 = 64 s_{k+1}
+constexpr int PIECE_THREADS = 1024;
+
+// the same value in every thread of the workgroup (wave partials combined in wave order)
+__device__ double block_reduce(double v, bool take_max, double* red) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        const double w = __shfl_xor(v, o, WAVE);
+        v = take_max ? fmax(v, w) : v + w;
+    }
+    __syncthreads();
+    if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < (int)(blockDim.x / WAVE); ++k) t = take_max ? fmax(t, red[k]) : t + red[k];
+    return t;
+}
+
+// r -> pieces q_1..q_4 (rows n_total..n_pad-1 zero), scales s_k = 2^(E - 7(k-1)) with s_1 = 2^E the
+// smallest such power where max|r| <= 127 s_1 (E >= -1000, so every s_k q_k stays a normal FP64 number),
+// and the bound numerator (||t||_2 + gamma_3 ||w||_2)(1 + 2^-20), w_i = sum_k s_k |q_ik| (the FP64 sum of
+// the four scaled integer dot products errs by at most gamma_3 sum_i |x_i| w_i).  One workgroup.
+__global__ __launch_bounds__(PIECE_THREADS) void k_r_pieces_i8(const double* __restrict__ r, int64_t n_total,
+                                                             int64_t n_pad, int8_t* __restrict__ pc,
+                                                             DevScalars* __restrict__ sc) {
+    __shared__ double red[PIECE_THREADS / WAVE];
+    double mx = 0.0;
+    for (int64_t i = threadIdx.x; i < n_total; i += blockDim.x) mx = fmax(mx, fabs(r[i]));
+    mx = block_reduce(mx, true, red);
+    int E = -1000;
+    if (mx > 0.0) {
+        int e;
+        (void)frexp(mx / 127.0, &e);
+        if (mx > 127.0 * ldexp(1.0, e)) ++e;    // mx / 127 was rounded down
+        E = e > -1000 ? e : -1000;
+    }
+    double e2 = 0.0, w2 = 0.0;
+    for (int64_t i = threadIdx.x; i < n_pad; i += blockDim.x) {
+        double t = i < n_total ? r[i] : 0.0;
+        double w = 0.0;
+#pragma unroll
+        for (int k = 0; k < I8P; ++k) {
+            const int ek = E - I8_SHIFT * k;
+            const double q = fmin(127.0, fmax(-127.0, rint(ldexp(t, -ek))));
+            pc[(int64_t)k * n_pad + i] = (int8_t)(int)q;
+            const double sq = ldexp(q, ek);
+            t -= sq;                              // exact: |t - sq| <= 2^(ek-1) on the grid of t
+            w += fabs(sq);
+        }
+        e2 = fma(t, t, e2);
+        w2 = fma(w, w, w2);
+    }
+    e2 = block_reduce(e2, false, red);
+    w2 = block_reduce(w2, false, red);
+    if (threadIdx.x == 0) {
+        const double u = 1.0 / 9007199254740992.0;
+#pragma unroll
+        for (int k = 0; k < I8P; ++k) sc->i8_scale[k] = ldexp(1.0, E - I8_SHIFT * k);
+        sc->i8_a = (sqrt(e2) + 3.0 * u / (1.0 - 3.0 * u) * sqrt(w2)) * (1.0 + 1.0 / 1048576.0);
+    }
+}
+
+// Tile as in the BF16 form: a wavefront owns 16 columns; lane (m, g) loads rows i0 + 16g .. +15 and
+// i0 + 64 + 16g .. +15 of column m per 128-row batch and hands each 16-byte word straight to an int8
+// MFMA step of 64 rows; lane (n, g) of the B operand supplies the same rows of piece n (lanes n >= 4
+// repeat a piece; their outputs are not used).  The loads of the next SCAN_U batches are issued before
+// the current ones go to the matrix cores.  The last, partial batch is read as whole 16-byte words that
+// start before row n_total: with 16-byte aligned columns such a word ends within the column's padded
+// length (and within the aligned block holding row n_total - 1), and its rows past n_total meet zero pieces.
+template <bool PLDS>
+__global__ __launch_bounds__(256) void k_scan_i8(const int8_t* __restrict__ X, int64_t ldx, int64_t n_total,
+                                                 int64_t n_pad, const int8_t* __restrict__ pieces,
+                                                 const int32_t* __restrict__ cols, const int64_t* __restrict__ len_dev,
+                                                 int64_t len_host, const DevScalars* __restrict__ sc,
+                                                 const double* __restrict__ c, const double* __restrict__ s,
+                                                 const uint8_t* __restrict__ keep, double* __restrict__ z) {
+    extern __shared__ v4i32 pl8[];
+    const int64_t len = len_dev ? *len_dev : len_host;
+    const int wpb = blockDim.x / WAVE;
+    const int64_t ngroups = (len + 15) / 16;
+    const int64_t gw0 = (int64_t)blockIdx.x * wpb;
+    if (gw0 >= ngroups) return;
+    const int8_t* P = pieces;
+    if constexpr (PLDS) {
+        const v4i32* src = reinterpret_cast<const v4i32*>(pieces);
+        const int64_t nv = (int64_t)I8P * n_pad / 16;
+        for (int64_t k = threadIdx.x; k < nv; k += blockDim.x) pl8[k] = src[k];
+        __syncthreads();
+        P = reinterpret_cast<const int8_t*>(pl8);
+    }
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int m = lane & 15, g = lane >> 4;
+    const double sum_r = sc->sum_r;
+    const double inv_n = 1.0 / (double)sc->n_rows;
+    const double scale_m = sc->i8_scale[m & (I8P - 1)];
+    constexpr int64_t IT_ROWS = SCAN_U * SCAN_KC;
+    const int64_t nit = n_total / IT_ROWS;                 // iterations of SCAN_U full batches
+    const int8_t* pr = P + (int64_t)(m & (I8P - 1)) * n_pad + 16 * g;
+    const v4i32 vzero = {0, 0, 0, 0};
+    for (int64_t grp = gw0 + threadIdx.x / WAVE; grp < ngroups; grp += (int64_t)gridDim.x * wpb) {
+        // lanes past the end of the list read column 0 (their sums are not written)
+        const int64_t t = grp * 16 + m;
+        const bool valid = t < len;
+        const int64_t j = valid ? (cols ? (int64_t)cols[t] : t) : 0;
+        const int8_t* xc = X + j * ldx + 16 * g;
+        double acc64[4] = {0.0, 0.0, 0.0, 0.0};
+        v4i32 acc = vzero;
+        // two register sets take turns (no copies between them, so no wait on the loads in flight); the
+        // prefetch is unconditional (the last iteration is loaded again) so every path has the same loads
+        // in flight and the waits before the matrix-core steps cover only the set they consume
+        v4i32 wa[SCAN_U][2], wb[SCAN_U][2];
+        auto load_it = [&](v4i32 (&dst)[SCAN_U][2], int64_t it) {
+#pragma unroll
+            for (int u = 0; u < SCAN_U; ++u) {
+                const v4i32* xp = reinterpret_cast<const v4i32*>(xc + it * IT_ROWS + u * SCAN_KC);
+                dst[u][0] = xp[0];
+                dst[u][1] = xp[4];
+            }
+        };
+        auto flush = [&]() {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc64[q] += (double)acc[q];
+            acc = vzero;
+        };
+        auto compute_it = [&](const v4i32 (&w)[SCAN_U][2], int64_t it) {
+            const int64_t i0 = it * IT_ROWS;
+#pragma unroll
+            for (int u = 0; u < SCAN_U; ++u) {
+                const v4i32 b0 = *reinterpret_cast<const v4i32*>(pr + i0 + u * SCAN_KC);
+                const v4i32 b1 = *reinterpret_cast<const v4i32*>(pr + i0 + u * SCAN_KC + 64);
+                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(w[u][0], b0, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(w[u][1], b1, acc, 0, 0, 0);
+            }
+        };
+        // pairs of iterations with no branch between a prefetch and its use (a branch lets the compiler sink
+        // the prefetch below it); the int32 sums go to FP64 after every pair
+        if (nit > 0) load_it(wa, 0);
+        for (int64_t it = 0; it + 1 < nit; it += 2) {
+            load_it(wb, it + 1);
+            issue_fence();
+            compute_it(wa, it);
+            load_it(wa, it + 2 < nit ? it + 2 : nit - 1);
+            issue_fence();
+            compute_it(wb, it + 1);
+            flush();
+        }
+        if (nit & 1) compute_it(wa, nit - 1);     // wa holds iteration nit - 1
+        // the remaining (fewer than SCAN_U) batches, the last one possibly partial
+        for (int64_t i0 = nit * IT_ROWS; i0 < n_total; i0 += SCAN_KC) {
+            v4i32 a0 = vzero, a1 = vzero;
+            if (i0 + 16 * g < n_total) a0 = *reinterpret_cast<const v4i32*>(xc + i0);
+            if (i0 + 64 + 16 * g < n_total) a1 = *reinterpret_cast<const v4i32*>(xc + i0 + 64);
+            const v4i32 b0 = *reinterpret_cast<const v4i32*>(pr + i0);
+            const v4i32 b1 = *reinterpret_cast<const v4i32*>(pr + i0 + 64);
+            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b0, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b1, acc, 0, 0, 0);
+        }
+        flush();
+        // lane (piece m, group g) holds the exact integer sums of columns 4g..4g+3 of this group for piece m;
+        // scale them (exact) and add the four pieces in FP64
+        double tot[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double v = acc64[q] * scale_m;
+            const double v1 = __shfl(v, lane + 1, WAVE);
+            const double v2 = __shfl(v, lane + 2, WAVE);
+            const double v3 = __shfl(v, lane + 3, WAVE);
+            tot[q] = ((v + v1) + v2) + v3;
+        }
+        if (m == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t tt = grp * 16 + 4 * g + q;
+                if (tt < len) {
+                    const int64_t jj = cols ? (int64_t)cols[tt] : tt;
+                    const bool kept = keep == nullptr || keep[jj] != 0;
+                    z[jj] = kept ? (tot[q] - c[jj] * sum_r) * inv_n / s[jj] : 0.0;
+                }
+            }
+        }
+    }
+}
+
+// Bound on |z~_j - z_j| (see the header of this file): A ||x_j||_2 / (n s_j), ||x_j||_2^2 = n (s_j^2 + c_j^2), with
+//   BF16 form: A = (u_r + (1 + 2^-7) gamma_32 + gamma_64) ||r||_2,
+//   int8 form: A = sc->i8_a + gamma_64 ||r||_2   (gamma_64 covers the FP64 scan that re-takes the decisions)
+__device__ __forceinline__ double lowp_bound(double cj, double sj, double n, double A) {
+    return A * sqrt(n * (sj * sj + cj * cj)) / (n * sj);
 }
 
 // flag[j] = 1 when a decision on z~_j lies within its bound: the check against lam (only for
 // j in in_s and not in excl), or the strong-rule threshold thr2 (when thr2 >= 0)
 __global__ void k_band(const int32_t* __restrict__ cols, const int64_t* __restrict__ len_dev, const double* __restrict__ z,
                        const double* __restrict__ c, const double* __restrict__ s, const DevScalars* __restrict__ sc,
-                       double coef, double lam, const uint8_t* __restrict__ in_s, const uint8_t* __restrict__ excl,
-                       double thr2, uint8_t* __restrict__ flag, double* __restrict__ err_out) {
+                       double coef, int i8, double lam, const uint8_t* __restrict__ in_s,
+                       const uint8_t* __restrict__ excl, double thr2, uint8_t* __restrict__ flag,
+                       double* __restrict__ err_out) {
     const int64_t len = *len_dev;
     const double n = (double)sc->n_rows;
-    const double rnorm = sqrt(sc->rss);
+    const double A = coef * sqrt(sc->rss) + (i8 ? sc->i8_a : 0.0);
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < len; t += (int64_t)gridDim.x * blockDim.x) {
         const int j = cols[t];
-        const double d = lowp_bound(c[j], s[j], n, rnorm, coef) + 1e-14 * fabs(z[j]);
+        const double d = lowp_bound(c[j], s[j], n, A) + 1e-14 * fabs(z[j]);
         const double az = fabs(z[j]);
         bool f = false;
         if ((in_s == nullptr || in_s[j]) && (excl == nullptr || !excl[j]) && fabs(az - lam) <= d) f = true;
@@ -248,6 +449,11 @@ int grid_for(int64_t work, int per_block, int max_blocks) {
 }  // namespace
 
 int64_t lowp_pad(int64_t n_total) { return (n_total + SCAN_KC - 1) / SCAN_KC * SCAN_KC; }
+
+size_t lowp_piece_bytes(int64_t n_total) {
+    const size_t bf = (size_t)NPIECE * lowp_pad(n_total) * sizeof(__bf16), i8 = (size_t)I8P * lowp_pad(n_total);
+    return bf > i8 ? bf : i8;
+}
 
 double lowp_coef() {
     const double u8 = 1.0 / 256.0, u24 = 1.0 / 16777216.0, u53 = 1.0 / 9007199254740992.0;
@@ -289,11 +495,38 @@ hipError_t launch_scan_bf16(const Mat& m, const __bf16* pieces, const int32_t* c
     return hipGetLastError();
 }
 
+hipError_t launch_r_pieces_i8(const double* r, int64_t n_total, int8_t* pieces, DevScalars* sc, hipStream_t st) {
+    k_r_pieces_i8<<<1, PIECE_THREADS, 0, st>>>(r, n_total, lowp_pad(n_total), pieces, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_i8(const Mat& m, const int8_t* pieces, const int32_t* cols, const int64_t* len_dev,
+                          int64_t len_host, const DevScalars* sc, const double* c, const double* s,
+                          const uint8_t* keep, double* z, hipStream_t st) {
+    const int64_t n_pad = lowp_pad(m.n_total);
+    const size_t lds = (size_t)I8P * n_pad;
+    const int64_t work = len_dev ? m.p : len_host;
+    const int64_t groups = (work + 15) / 16;
+    const int threads = 256, wpb = threads / WAVE;
+    if (lds <= 64 * 1024) {
+        const int per_cu = lds <= 40 * 1024 ? 4 : 2;
+        const int g = grid_for(groups, wpb, device_cu_count() * per_cu);
+        k_scan_i8<true><<<g, threads, lds, st>>>((const int8_t*)m.X, m.ldx, m.n_total, n_pad, pieces, cols, len_dev,
+                                                 len_host, sc, c, s, keep, z);
+    } else {
+        const int g = grid_for(groups, wpb, device_cu_count() * 8);
+        k_scan_i8<false><<<g, threads, 0, st>>>((const int8_t*)m.X, m.ldx, m.n_total, n_pad, pieces, cols, len_dev,
+                                                len_host, sc, c, s, keep, z);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_band(const int32_t* cols, const int64_t* len_dev, const double* z, const double* c, const double* s,
                        const DevScalars* sc, double lam, const uint8_t* in_s, const uint8_t* excl, double thr2,
-                       uint8_t* flag, double* err_out, int64_t p, hipStream_t st) {
-    k_band<<<grid_for(p, 256, device_cu_count() * 8), 256, 0, st>>>(cols, len_dev, z, c, s, sc, lowp_coef(), lam,
-                                                                     in_s, excl, thr2, flag, err_out);
+                       uint8_t* flag, double* err_out, int64_t p, bool i8, hipStream_t st) {
+    const double coef = i8 ? 65536.0 / 9007199254740992.0 : lowp_coef();
+    k_band<<<grid_for(p, 256, device_cu_count() * 8), 256, 0, st>>>(cols, len_dev, z, c, s, sc, coef, i8 ? 1 : 0,
+                                                                     lam, in_s, excl, thr2, flag, err_out);
     return hipGetLastError();
 }
 
