@@ -171,27 +171,32 @@ def c3_full(gpu_ctx):
     Xd = torch.from_numpy(Xt.view(np.int8)).to(DEV)
     yd = torch.from_numpy(y).to(DEV)
     kw = dict(nlambda=rec.nlambda, lambda_min_ratio=rec.lambda_min_ratio, rule=bl.SCREEN_SSR_BEDPP, tol=1e-10)
-    lp = bl.fit_path(gpu_ctx, Xd, yd, precision=bl.PREC_BF16X3, **kw)
+    lp = bl.fit_path(gpu_ctx, Xd, yd, precision=bl.PREC_I8X4, **kw)
+    bp = bl.fit_path(gpu_ctx, Xd, yd, precision=bl.PREC_BF16X3, **kw)
+    bp.beta = bp.beta.cpu()
     hp = bl.fit_path(gpu_ctx, Xd, yd, precision=bl.PREC_FP64, **kw)
-    log(f"precision form {lp.time_ms:.0f} ms, FP64 scans {hp.time_ms:.0f} ms, {lp.n_active[-1]} active at the end, "
-        f"{int(lp.n_recheck.sum())} FP64 rechecks")
+    log(f"int8 form {lp.time_ms:.0f} ms, BF16 form {bp.time_ms:.0f} ms, FP64 scans {hp.time_ms:.0f} ms, "
+        f"{lp.n_active[-1]} active at the end, {int(lp.n_recheck.sum())} / {int(bp.n_recheck.sum())} FP64 rechecks")
     del Xd
     torch.cuda.empty_cache()
-    return rec, Xt, y, lp, hp
+    return rec, Xt, y, lp, bp, hp
 
 
-def test_c3_full_precision_form_equals_fp64_path(c3_full):
-    """The BF16 matrix-core scans take every decision the FP64 scans take: identical coefficients."""
-    rec, Xt, y, lp, hp = c3_full
-    assert lp.k_done == rec.nlambda and hp.k_done == rec.nlambda
+def test_c3_full_precision_forms_equal_fp64_path(c3_full):
+    """The int8 and the BF16 matrix-core scans take every decision the FP64 scans take: identical
+    coefficients."""
+    rec, Xt, y, lp, bp, hp = c3_full
+    assert lp.k_done == rec.nlambda and bp.k_done == rec.nlambda and hp.k_done == rec.nlambda
     assert torch.equal(lp.beta, hp.beta)
-    np.testing.assert_array_equal(lp.n_active, hp.n_active)
-    np.testing.assert_array_equal(lp.n_strong, hp.n_strong)
+    assert torch.equal(bp.beta, hp.beta.cpu())
+    for form in (lp, bp):
+        np.testing.assert_array_equal(form.n_active, hp.n_active)
+        np.testing.assert_array_equal(form.n_strong, hp.n_strong)
 
 
 @pytest.mark.parametrize("k", [30, 99])
 def test_c3_full_kkt_certificate_sampled(c3_full, k):
-    rec, Xt, y, lp, hp = c3_full
+    rec, Xt, y, lp, bp, hp = c3_full
     beta = lp.beta[k].cpu().numpy()
     lam = lp.lam[k]
     out_v, on_a, na = kkt_sampled(Xt, y, beta, lam)
