@@ -173,6 +173,131 @@ __global__ __launch_bounds__(64 * GM_W) void k_gram_update(const XT* __restrict_
     }
 }
 
+// The same update for int8 codes on the int8 matrix cores.  The raw cross-products sum_i x_ik x_it over the
+// fitted rows are integers: the int32 sums of v_mfma_i32_16x16x64_i8 (moved to FP64 after every 128 rows) are
+// exact, as are the FP64 kernel's sums (every partial sum is an integer below 2^53), so both kernels produce
+// the same Gram entries bit for bit.  Lane (m, kq) loads 16 consecutive codes of its column (rows 16 kq .. of a
+// 64-row step) and hands the word to the matrix cores as it is.  Columns, ldx and the row mask are 16-byte
+// aligned; the word holding the last row is read whole (it lies within the column's padded length), and its
+// rows past n_total, like the rows outside the fit, are cleared in the B operand.  The output layout of this
+// instruction is row 4 kq + q (the FP64 one above is kq + 4 q).
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+constexpr int GI_R = 64;   // rows per int8 step
+
+// 0xFF in each nonzero byte of v, 0x00 elsewhere
+__device__ __forceinline__ uint32_t bytes_nonzero(uint32_t v) {
+    const uint32_t h = (((v & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | v) & 0x80808080u;
+    return (h >> 7) * 0xFFu;
+}
+// 0xFF in the first nv bytes (nv clamped to 0..4)
+__device__ __forceinline__ uint32_t bytes_below(int64_t nv) {
+    return nv >= 4 ? 0xFFFFFFFFu : (nv <= 0 ? 0u : ((1u << (8 * (int)nv)) - 1u));
+}
+// keeps the loads above it issued before the work below it (see the int8 scan)
+__device__ __forceinline__ void issue_fence_g() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <bool MASK>
+__global__ __launch_bounds__(64 * GM_W) void k_gram_update_i8(const int8_t* __restrict__ X, int64_t ldx,
+                                                             int64_t n_total, const uint8_t* __restrict__ mask,
+                                                             const int32_t* __restrict__ pool_list, int64_t P,
+                                                             int64_t P0, int64_t N, const double* __restrict__ c,
+                                                             const double* __restrict__ s, double n_rows,
+                                                             double* __restrict__ G, int64_t ldg) {
+    __shared__ f64x4 red[GM_W - 1][2][WAVE];
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const int m = lane & 15, kq = lane >> 4;
+    const int64_t kb = (int64_t)blockIdx.x * GM_K, tb = (int64_t)blockIdx.y * GM_N;
+    const int8_t* ac[2];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+        const int64_t k = kb + 16 * f + m;
+        ac[f] = X + (int64_t)(k < P ? pool_list[k] : 0) * ldx;
+    }
+    const bool bok = tb + m < N;
+    const int8_t* bc = X + (int64_t)(bok ? pool_list[P0 + tb + m] : 0) * ldx;
+    const int64_t ns = (n_total + GI_R - 1) / GI_R;
+    const int64_t s0 = ns * w / GM_W, s1 = ns * (w + 1) / GM_W;
+    const int64_t last_word = (n_total - 1) & ~(int64_t)15;
+    // raw words of a step (an in-bounds word where the step's rows end before this lane's 16)
+    auto load = [&](int64_t step, i32x4& a0, i32x4& a1, i32x4& bw, i32x4& mw) {
+        const int64_t r0 = step * GI_R + 16 * kq;
+        const int64_t rl = r0 < n_total ? r0 : last_word;
+        a0 = *reinterpret_cast<const i32x4*>(ac[0] + rl);
+        a1 = *reinterpret_cast<const i32x4*>(ac[1] + rl);
+        bw = *reinterpret_cast<const i32x4*>(bc + rl);
+        if constexpr (MASK) mw = *reinterpret_cast<const i32x4*>(mask + rl);
+    };
+    i32x4 acc[2] = {(i32x4){0, 0, 0, 0}, (i32x4){0, 0, 0, 0}};
+    f64x4 a64[2] = {(f64x4){0.0, 0.0, 0.0, 0.0}, (f64x4){0.0, 0.0, 0.0, 0.0}};
+    // B's bytes of rows past n_total or outside the fit are cleared as the step is consumed (clearing them at
+    // the load would wait for the load)
+    auto mma = [&](int64_t step, const i32x4& a0, const i32x4& a1, const i32x4& braw, const i32x4& mw) {
+        const int64_t r0 = step * GI_R + 16 * kq;
+        i32x4 bw;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            uint32_t keep = bytes_below(n_total - r0 - 4 * d);
+            if constexpr (MASK) keep &= bytes_nonzero((uint32_t)mw[d]);
+            bw[d] = (int)((uint32_t)braw[d] & keep);
+        }
+        acc[0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, bw, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, bw, acc[1], 0, 0, 0);
+    };
+    auto flush = [&]() {
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a64[f][q] += (double)acc[f][q];
+            acc[f] = (i32x4){0, 0, 0, 0};
+        }
+    };
+    // pairs of steps, two register sets taking turns (no branch between a prefetch and its use)
+    i32x4 xa0, xa1, xb, xm = {-1, -1, -1, -1}, ya0, ya1, yb, ym = {-1, -1, -1, -1};
+    if (s0 < s1) load(s0, xa0, xa1, xb, xm);
+    int64_t step = s0;
+    for (; step + 1 < s1; step += 2) {
+        load(step + 1, ya0, ya1, yb, ym);
+        issue_fence_g();
+        mma(step, xa0, xa1, xb, xm);
+        load(step + 2 < s1 ? step + 2 : s1 - 1, xa0, xa1, xb, xm);
+        issue_fence_g();
+        mma(step + 1, ya0, ya1, yb, ym);
+        flush();
+    }
+    if (step < s1) mma(step, xa0, xa1, xb, xm);
+    flush();
+    if (w > 0) {
+        red[w - 1][0][lane] = a64[0];
+        red[w - 1][1][lane] = a64[1];
+    }
+    __syncthreads();
+    if (w > 0) return;
+#pragma unroll
+    for (int v = 0; v < GM_W - 1; ++v) {
+        a64[0] += red[v][0][lane];
+        a64[1] += red[v][1][lane];
+    }
+    const int64_t t = tb + m;
+    if (t >= N) return;
+    const int jt = pool_list[P0 + t];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t k = kb + 16 * f + 4 * kq + q;
+            if (k >= P) continue;
+            if (k >= P0 && k - P0 > t) continue;   // written by the tile of its mirror
+            const int jk = pool_list[k];
+            const double gv = (a64[f][q] - n_rows * (c[jk] * c[jt])) / (n_rows * (s[jk] * s[jt]));
+            G[k * ldg + (P0 + t)] = gv;
+            G[(P0 + t) * ldg + k] = gv;
+        }
+    }
+}
+
 // G_E[e, f] = G_pool[pos(set[e]), pos(set[f])] (symmetric, m x m)
 __global__ void k_gather_gram(const int32_t* __restrict__ set, int64_t m, const int32_t* __restrict__ pool_pos,
                               const double* __restrict__ Gp, int64_t ldg, double* __restrict__ GE) {
@@ -863,6 +988,19 @@ static hipError_t gram_typed(const Mat& m, const int32_t* pool_list, int64_t P, 
                              const double* c, const double* s, double n_rows, double* G, int64_t ldg,
                              hipStream_t st) {
     dim3 grid((unsigned)((P + GM_K - 1) / GM_K), (unsigned)((N + GM_N - 1) / GM_N));
+    if constexpr (sizeof(XT) == 1) {
+        // int8 matrix cores when every column (and the row mask) is 16-byte aligned
+        const bool al = (uintptr_t)m.X % 16 == 0 && m.ldx % 16 == 0 && (uintptr_t)m.mask % 16 == 0;
+        if (al && m.n_total > 0) {
+            if (m.mask)
+                k_gram_update_i8<true><<<grid, 64 * GM_W, 0, st>>>((const int8_t*)m.X, m.ldx, m.n_total, m.mask,
+                                                                    pool_list, P, P0, N, c, s, n_rows, G, ldg);
+            else
+                k_gram_update_i8<false><<<grid, 64 * GM_W, 0, st>>>((const int8_t*)m.X, m.ldx, m.n_total, m.mask,
+                                                                     pool_list, P, P0, N, c, s, n_rows, G, ldg);
+            return hipGetLastError();
+        }
+    }
     if (m.mask)
         k_gram_update<XT, true><<<grid, 64 * GM_W, 0, st>>>((const XT*)m.X, m.ldx, m.n_total, m.mask, pool_list, P,
                                                              P0, N, c, s, n_rows, G, ldg);
