@@ -11,8 +11,8 @@ Workloads (--workload):
                 nonzero coefficients ~ N(0,1), SNR 1, 100 lambda values down to
                 0.05 lambda_max, hybrid BEDPP + strong-rule screening, CD tolerance 1e-8.
   c3            precision form: genotype 10,000 x 2,000,000 stored as int8 (20 GB),
-                200 nonzeros, scans on int8 matrix cores (--precision-form i8x4, the
-                default) or BF16 matrix cores (bf16x3) with FP64 decisions; the plain
+                200 nonzeros, scans as int8 dot products (--precision-form i8x4, the
+                default) or on BF16 matrix cores (bf16x3) with FP64 decisions; the plain
                 FP64-scan path on the same int8 storage and the other form are timed
                 beside it.
   c4            batched form: AR(1) (rho 0.5) design 20,000 x 200,000 float32 (16 GB),
@@ -161,8 +161,8 @@ def run_plain(args, rec, ctx, bl, Xd, Xt, yd, y):
 
 PRECISION_FORMS = {
     # form: (bl constant name, dtype, workload text, dominant kernel, counter summary under profiles/)
-    "i8x4": ("PREC_I8X4", "i8 codes, int8 matrix-core scan against 4 int8 residual pieces, f64 decisions",
-             "int8 x4 power-of-two residual pieces, exact int32 sums", "k_scan_i8 (int8 X, int8 MFMA)",
+    "i8x4": ("PREC_I8X4", "i8 codes, int8 dot-product scan against 4 int8 residual pieces, f64 decisions",
+             "int8 x4 power-of-two residual pieces, exact int32 sums", "k_scan_i8 (int8 X, int8 dot4)",
              "k_scan_i8_c3_genotype_10000x2000000_i8.md"),
     "bf16x3": ("PREC_BF16X3", "i8 codes, bf16x3 matrix-core scan, f64 decisions",
                "BF16 x3 residual pieces, FP32 partial sums promoted to FP64", "k_scan_bf16 (int8 X, BF16 MFMA)",

@@ -170,7 +170,7 @@ typedef enum {
     BL_PREC_BF16X3 = 1,    /* int8 X only: BF16 matrix cores against three BF16 pieces of the residual,
                               FP32 chunks promoted to FP64; decisions within the error bound are
                               re-taken on the FP64 scan, so they equal the FP64 decisions            */
-    BL_PREC_I8X4 = 2       /* int8 X only: int8 matrix cores against four int8 pieces of the residual
+    BL_PREC_I8X4 = 2       /* int8 X only: int8 dot products against four int8 pieces of the residual
                               with power-of-two scales, exact integer sums; decisions within the
                               error bound are re-taken on the FP64 scan, as for BL_PREC_BF16X3       */
 } bl_precision;

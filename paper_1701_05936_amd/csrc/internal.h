@@ -178,7 +178,8 @@ hipError_t launch_r_update(const Mat& mt, const int32_t* set, int64_t m, const d
 
 // ---- precision forms: int8 codes on BF16 or int8 matrix cores (lowp.hip) ----
 constexpr int LOWP_PIECES = 3;  // BF16 pieces of the residual
-int64_t lowp_pad(int64_t n_total);          // rows of each residual piece buffer (multiple of 128)
+int64_t lowp_pad(int64_t n_total);          // rows of each BF16 residual piece (multiple of 128)
+int64_t lowp_pad_i8(int64_t n_total);       // rows of each int8 residual piece (multiple of 512)
 size_t lowp_piece_bytes(int64_t n_total);  // piece buffer of either form
 double lowp_coef();                         // error coefficient of the scan bound
 bool lowp_supported(const Mat& m);          // int8 X, 16-byte aligned columns
@@ -190,6 +191,7 @@ hipError_t launch_scan_bf16(const Mat& m, const __bf16* pieces, const int32_t* c
 constexpr int LOWP_I8_PIECES = 4;
 // pieces [LOWP_I8_PIECES][lowp_pad(n_total)] int8 plus sc->i8_scale and sc->i8_a (one workgroup)
 hipError_t launch_r_pieces_i8(const double* r, int64_t n_total, int8_t* pieces, DevScalars* sc, hipStream_t st);
+// cols must be non-null
 hipError_t launch_scan_i8(const Mat& m, const int8_t* pieces, const int32_t* cols, const int64_t* len_dev,
                           int64_t len_host, const DevScalars* sc, const double* c, const double* s,
                           const uint8_t* keep, double* z, hipStream_t st);

@@ -1,4 +1,4 @@
-// Precision forms of the scan: int8 design codes on BF16 or on int8 matrix cores.
+// Precision forms of the scan: int8 design codes on BF16 matrix cores, or on int8 dot products.
 //
 // BF16 form:
 // z_j = (x_j' r - c_j sum(r)) / (n s_j) is computed as Z = X_T' [r1 r2 r3] with
@@ -17,10 +17,9 @@
 //
 // int8 form: the residual is split into four int8 pieces with power-of-two scales,
 //   r = s_1 q_1 + s_2 q_2 + s_3 q_3 + s_4 q_4 + t,   s_{k+1} = s_k / 128,
-// each s_k q_k and the remainder t exact in FP64.  X_T' [q_1 .. q_4] runs on v_mfma_i32_16x16x64_i8
-// with exact int32 sums (moved to FP64 every 1,024 rows, far below 2^31 / (128 x 127) rows), and
-// x_j' r = sum_k s_k D_jk + x_j' t.  The only errors are x_j' t (bounded by ||x_j||_2 ||t||_2) and the
-// FP64 sum of the four scaled integers; the codes are fed to the matrix cores as loaded.
+// each s_k q_k and the remainder t exact in FP64.  D_jk = x_j' q_k runs on v_dot4_i32_i8 over coalesced
+// column streams with exact integer sums, and x_j' r = sum_k s_k D_jk + x_j' t.  The only errors are x_j' t
+// (bounded by ||x_j||_2 ||t||_2) and the FP64 sum of the four scaled integers; the codes are used as loaded.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -275,14 +274,31 @@ __global__ __launch_bounds__(PIECE_THREADS) void k_r_pieces_i8(const double* __r
     }
 }
 
-// Tile as in the BF16 form: a wavefront owns 16 columns; lane (m, g) loads rows i0 + 16g .. +15 and
-// i0 + 64 + 16g .. +15 of column m per 128-row batch and hands each 16-byte word straight to an int8
-// MFMA step of 64 rows; lane (n, g) of the B operand supplies the same rows of piece n (lanes n >= 4
-// repeat a piece; their outputs are not used).  The loads of the next SCAN_U batches are issued before
-// the current ones go to the matrix cores.  The last, partial batch is read as whole 16-byte words that
-// start before row n_total: with 16-byte aligned columns such a word ends within the column's padded
-// length (and within the aligned block holding row n_total - 1), and its rows past n_total meet zero pieces.
-template <bool PLDS>
+// The scan is a matrix-vector product bound by HBM: each wavefront streams I8_COLS columns at a time, lane l
+// reading rows 16 l .. 16 l + 15 of a 1,024-row chunk of each (one 1 KB coalesced load per column and chunk),
+// and multiplies every 4-byte word into the four pieces' words with v_dot4_i32_i8 (exact int32 sums; a lane
+// sees at most n / 64 rows, so |sum| < 2^15 n / 64 < 2^31 for n <= 2^21).  The pieces sit in LDS (16-byte
+// reads at 16-byte lane strides).  The next chunk's loads are in flight while the current one is multiplied.
+// The last, partial chunk reads each word that starts past the last row at the last word instead (in bounds);
+// the pieces are zero on every row past n_total, so those products vanish.
+constexpr int I8_COLS = 4;
+constexpr int64_t I8_CHUNK = (int64_t)WAVE * 16;
+
+// exact sum over the wavefront of per-lane int32 values below 2^29 in magnitude (4-lane partials stay below
+// 2^31; from there on the sums are FP64 integers below 2^53)
+__device__ __forceinline__ double wave_isum(int v) {
+    v += __shfl_xor(v, 1, WAVE);
+    v += __shfl_xor(v, 2, WAVE);
+    double d = (double)v;
+#pragma unroll
+    for (int o = 4; o < WAVE; o <<= 1) d += __shfl_xor(d, o, WAVE);
+    return d;
+}
+
+// KEEP: a keep array is given (a template parameter rather than a null test: a pointer chosen at run time between
+// it and a constant turns the load into one the wait counters cannot order, and every chunk would then wait for
+// all loads in flight)
+template <bool PLDS, bool KEEP>
 __global__ __launch_bounds__(256) void k_scan_i8(const int8_t* __restrict__ X, int64_t ldx, int64_t n_total,
                                                  int64_t n_pad, const int8_t* __restrict__ pieces,
                                                  const int32_t* __restrict__ cols, const int64_t* __restrict__ len_dev,
@@ -292,9 +308,9 @@ __global__ __launch_bounds__(256) void k_scan_i8(const int8_t* __restrict__ X, i
     extern __shared__ v4i32 pl8[];
     const int64_t len = len_dev ? *len_dev : len_host;
     const int wpb = blockDim.x / WAVE;
-    const int64_t ngroups = (len + 15) / 16;
+    const int64_t nunits = (len + I8_COLS - 1) / I8_COLS;
     const int64_t gw0 = (int64_t)blockIdx.x * wpb;
-    if (gw0 >= ngroups) return;
+    if (gw0 >= nunits) return;
     const int8_t* P = pieces;
     if constexpr (PLDS) {
         const v4i32* src = reinterpret_cast<const v4i32*>(pieces);
@@ -304,95 +320,98 @@ __global__ __launch_bounds__(256) void k_scan_i8(const int8_t* __restrict__ X, i
         P = reinterpret_cast<const int8_t*>(pl8);
     }
     const int lane = threadIdx.x & (WAVE - 1);
-    const int m = lane & 15, g = lane >> 4;
     const double sum_r = sc->sum_r;
     const double inv_n = 1.0 / (double)sc->n_rows;
-    const double scale_m = sc->i8_scale[m & (I8P - 1)];
-    constexpr int64_t IT_ROWS = SCAN_U * SCAN_KC;
-    const int64_t nit = n_total / IT_ROWS;                 // iterations of SCAN_U full batches
-    const int8_t* pr = P + (int64_t)(m & (I8P - 1)) * n_pad + 16 * g;
-    const v4i32 vzero = {0, 0, 0, 0};
-    for (int64_t grp = gw0 + threadIdx.x / WAVE; grp < ngroups; grp += (int64_t)gridDim.x * wpb) {
-        // lanes past the end of the list read column 0 (their sums are not written)
-        const int64_t t = grp * 16 + m;
-        const bool valid = t < len;
-        const int64_t j = valid ? (cols ? (int64_t)cols[t] : t) : 0;
-        const int8_t* xc = X + j * ldx + 16 * g;
-        double acc64[4] = {0.0, 0.0, 0.0, 0.0};
-        v4i32 acc = vzero;
-        // two register sets take turns (no copies between them, so no wait on the loads in flight); the
-        // prefetch is unconditional (the last iteration is loaded again) so every path has the same loads
-        // in flight and the waits before the matrix-core steps cover only the set they consume
-        v4i32 wa[SCAN_U][2], wb[SCAN_U][2];
-        auto load_it = [&](v4i32 (&dst)[SCAN_U][2], int64_t it) {
+    double sk[I8P];
 #pragma unroll
-            for (int u = 0; u < SCAN_U; ++u) {
-                const v4i32* xp = reinterpret_cast<const v4i32*>(xc + it * IT_ROWS + u * SCAN_KC);
-                dst[u][0] = xp[0];
-                dst[u][1] = xp[4];
-            }
-        };
-        auto flush = [&]() {
+    for (int k = 0; k < I8P; ++k) sk[k] = sc->i8_scale[k];
+    const int64_t nch = (n_total + I8_CHUNK - 1) / I8_CHUNK;   // chunks per column, the last partial
+    const int64_t last_word = (n_total - 1) & ~(int64_t)15;
+    const int64_t ustride = (int64_t)gridDim.x * wpb;
+    const int8_t* pl = P + 16 * lane;
+    // column cc of unit u (entries past the end of the list read column 0; their sums are not written); the
+    // index load is unconditional (clamped), so nothing waits for it before its use
+    auto column = [&](int64_t u, int cc) -> int64_t {
+        const int64_t t_ = u * I8_COLS + cc;
+        const int64_t jl = cols[t_ < len ? t_ : len - 1];
+        return t_ < len ? jl : 0;
+    };
+    // the unit is the same in every lane (readfirstlane makes that visible to the compiler, so the column
+    // indices and statistics live in scalar registers)
+    int64_t unit = __builtin_amdgcn_readfirstlane((int)(gw0 + threadIdx.x / WAVE));
+    int64_t jc[I8_COLS];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc64[q] += (double)acc[q];
-            acc = vzero;
-        };
-        auto compute_it = [&](const v4i32 (&w)[SCAN_U][2], int64_t it) {
-            const int64_t i0 = it * IT_ROWS;
+    for (int cc = 0; cc < I8_COLS; ++cc) jc[cc] = column(unit < nunits ? unit : gw0, cc);
+    for (; unit < nunits; unit += ustride) {
+        // the next unit's column indices a unit ahead, this unit's statistics at its start
+        int64_t jn[I8_COLS];
+        const int64_t un = unit + ustride < nunits ? unit + ustride : unit;
 #pragma unroll
-            for (int u = 0; u < SCAN_U; ++u) {
-                const v4i32 b0 = *reinterpret_cast<const v4i32*>(pr + i0 + u * SCAN_KC);
-                const v4i32 b1 = *reinterpret_cast<const v4i32*>(pr + i0 + u * SCAN_KC + 64);
-                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(w[u][0], b0, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(w[u][1], b1, acc, 0, 0, 0);
-            }
+        for (int cc = 0; cc < I8_COLS; ++cc) jn[cc] = column(un, cc);
+        double cj[I8_COLS], sj[I8_COLS];
+        bool kept[I8_COLS];
+        const int8_t* xc[I8_COLS];
+#pragma unroll
+        for (int cc = 0; cc < I8_COLS; ++cc) {
+            cj[cc] = c[jc[cc]];
+            sj[cc] = s[jc[cc]];
+            kept[cc] = KEEP ? keep[jc[cc]] != 0 : true;
+            xc[cc] = X + jc[cc] * ldx;
+        }
+        int acc[I8_COLS][I8P];
+#pragma unroll
+        for (int cc = 0; cc < I8_COLS; ++cc)
+#pragma unroll
+            for (int k = 0; k < I8P; ++k) acc[cc][k] = 0;
+        auto load = [&](v4i32 (&dst)[I8_COLS], int64_t ch) {
+            const int64_t row = ch * I8_CHUNK + 16 * lane;
+            const int64_t rl = row < last_word ? row : last_word;
+#pragma unroll
+            for (int cc = 0; cc < I8_COLS; ++cc) dst[cc] = *reinterpret_cast<const v4i32*>(xc[cc] + rl);
         };
-        // pairs of iterations with no branch between a prefetch and its use (a branch lets the compiler sink
-        // the prefetch below it); the int32 sums go to FP64 after every pair
-        if (nit > 0) load_it(wa, 0);
-        for (int64_t it = 0; it + 1 < nit; it += 2) {
-            load_it(wb, it + 1);
+        auto compute = [&](const v4i32 (&w)[I8_COLS], int64_t ch) {
+            v4i32 pw[I8P];
+#pragma unroll
+            for (int k = 0; k < I8P; ++k) pw[k] = *reinterpret_cast<const v4i32*>(pl + k * n_pad + ch * I8_CHUNK);
+#pragma unroll
+            for (int cc = 0; cc < I8_COLS; ++cc)
+#pragma unroll
+                for (int k = 0; k < I8P; ++k)
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) acc[cc][k] = __builtin_amdgcn_sdot4(w[cc][d], pw[k][d], acc[cc][k], false);
+        };
+        // pairs of chunks, two register sets taking turns (no branch between a prefetch and its use)
+        v4i32 wa[I8_COLS], wb[I8_COLS];
+        load(wa, 0);
+        issue_fence();
+        for (int64_t ch = 0; ch + 1 < nch; ch += 2) {
+            load(wb, ch + 1);
             issue_fence();
-            compute_it(wa, it);
-            load_it(wa, it + 2 < nit ? it + 2 : nit - 1);
+            compute(wa, ch);
+            load(wa, ch + 2 < nch ? ch + 2 : nch - 1);
             issue_fence();
-            compute_it(wb, it + 1);
-            flush();
+            compute(wb, ch + 1);
         }
-        if (nit & 1) compute_it(wa, nit - 1);     // wa holds iteration nit - 1
-        // the remaining (fewer than SCAN_U) batches, the last one possibly partial
-        for (int64_t i0 = nit * IT_ROWS; i0 < n_total; i0 += SCAN_KC) {
-            v4i32 a0 = vzero, a1 = vzero;
-            if (i0 + 16 * g < n_total) a0 = *reinterpret_cast<const v4i32*>(xc + i0);
-            if (i0 + 64 + 16 * g < n_total) a1 = *reinterpret_cast<const v4i32*>(xc + i0 + 64);
-            const v4i32 b0 = *reinterpret_cast<const v4i32*>(pr + i0);
-            const v4i32 b1 = *reinterpret_cast<const v4i32*>(pr + i0 + 64);
-            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b0, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b1, acc, 0, 0, 0);
-        }
-        flush();
-        // lane (piece m, group g) holds the exact integer sums of columns 4g..4g+3 of this group for piece m;
-        // scale them (exact) and add the four pieces in FP64
-        double tot[4];
+        if (nch & 1) compute(wa, nch - 1);
+        // exact column sums per piece, scaled (exact) and added in FP64; lane cc writes column cc
+        double zv = 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const double v = acc64[q] * scale_m;
-            const double v1 = __shfl(v, lane + 1, WAVE);
-            const double v2 = __shfl(v, lane + 2, WAVE);
-            const double v3 = __shfl(v, lane + 3, WAVE);
-            tot[q] = ((v + v1) + v2) + v3;
-        }
-        if (m == 0) {
+        for (int cc = 0; cc < I8_COLS; ++cc) {
+            double v[I8P];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int64_t tt = grp * 16 + 4 * g + q;
-                if (tt < len) {
-                    const int64_t jj = cols ? (int64_t)cols[tt] : tt;
-                    const bool kept = keep == nullptr || keep[jj] != 0;
-                    z[jj] = kept ? (tot[q] - c[jj] * sum_r) * inv_n / s[jj] : 0.0;
-                }
-            }
+            for (int k = 0; k < I8P; ++k) v[k] = wave_isum(acc[cc][k]) * sk[k];
+            const double tot = ((v[0] + v[1]) + v[2]) + v[3];
+            const double zc = kept[cc] ? (tot - cj[cc] * sum_r) * inv_n / sj[cc] : 0.0;
+            zv = lane == cc ? zc : zv;
         }
+        if (lane < I8_COLS && unit * I8_COLS + lane < len) {
+            int64_t jw = jc[0];
+#pragma unroll
+            for (int cc = 1; cc < I8_COLS; ++cc) jw = lane == cc ? jc[cc] : jw;
+            z[jw] = zv;
+        }
+#pragma unroll
+        for (int cc = 0; cc < I8_COLS; ++cc) jc[cc] = jn[cc];
     }
 }
 
@@ -450,8 +469,11 @@ int grid_for(int64_t work, int per_block, int max_blocks) {
 
 int64_t lowp_pad(int64_t n_total) { return (n_total + SCAN_KC - 1) / SCAN_KC * SCAN_KC; }
 
+// rows of each int8 piece: whole 1,024-row chunks (the scan reads the pieces of every row of a chunk)
+int64_t lowp_pad_i8(int64_t n_total) { return (n_total + I8_CHUNK - 1) / I8_CHUNK * I8_CHUNK; }
+
 size_t lowp_piece_bytes(int64_t n_total) {
-    const size_t bf = (size_t)NPIECE * lowp_pad(n_total) * sizeof(__bf16), i8 = (size_t)I8P * lowp_pad(n_total);
+    const size_t bf = (size_t)NPIECE * lowp_pad(n_total) * sizeof(__bf16), i8 = (size_t)I8P * lowp_pad_i8(n_total);
     return bf > i8 ? bf : i8;
 }
 
@@ -496,28 +518,35 @@ hipError_t launch_scan_bf16(const Mat& m, const __bf16* pieces, const int32_t* c
 }
 
 hipError_t launch_r_pieces_i8(const double* r, int64_t n_total, int8_t* pieces, DevScalars* sc, hipStream_t st) {
-    k_r_pieces_i8<<<1, PIECE_THREADS, 0, st>>>(r, n_total, lowp_pad(n_total), pieces, sc);
+    k_r_pieces_i8<<<1, PIECE_THREADS, 0, st>>>(r, n_total, lowp_pad_i8(n_total), pieces, sc);
     return hipGetLastError();
 }
 
 hipError_t launch_scan_i8(const Mat& m, const int8_t* pieces, const int32_t* cols, const int64_t* len_dev,
                           int64_t len_host, const DevScalars* sc, const double* c, const double* s,
                           const uint8_t* keep, double* z, hipStream_t st) {
-    const int64_t n_pad = lowp_pad(m.n_total);
+    if (!cols) return hipErrorInvalidValue;   // the kernel reads the column list unconditionally
+    const int64_t n_pad = lowp_pad_i8(m.n_total);
     const size_t lds = (size_t)I8P * n_pad;
     const int64_t work = len_dev ? m.p : len_host;
-    const int64_t groups = (work + 15) / 16;
+    const int64_t groups = (work + I8_COLS - 1) / I8_COLS;
     const int threads = 256, wpb = threads / WAVE;
-    if (lds <= 64 * 1024) {
-        const int per_cu = lds <= 40 * 1024 ? 4 : 2;
-        const int g = grid_for(groups, wpb, device_cu_count() * per_cu);
-        k_scan_i8<true><<<g, threads, lds, st>>>((const int8_t*)m.X, m.ldx, m.n_total, n_pad, pieces, cols, len_dev,
-                                                 len_host, sc, c, s, keep, z);
-    } else {
-        const int g = grid_for(groups, wpb, device_cu_count() * 8);
-        k_scan_i8<false><<<g, threads, 0, st>>>((const int8_t*)m.X, m.ldx, m.n_total, n_pad, pieces, cols, len_dev,
-                                                len_host, sc, c, s, keep, z);
-    }
+    const int8_t* X = (const int8_t*)m.X;
+    const bool plds = lds <= 64 * 1024;
+    const int g = grid_for(groups, wpb, device_cu_count() * (plds ? (lds <= 40 * 1024 ? 4 : 2) : 8));
+    const size_t dyn = plds ? lds : 0;
+    if (plds && keep)
+        k_scan_i8<true, true><<<g, threads, dyn, st>>>(X, m.ldx, m.n_total, n_pad, pieces, cols, len_dev, len_host, sc,
+                                                       c, s, keep, z);
+    else if (plds)
+        k_scan_i8<true, false><<<g, threads, dyn, st>>>(X, m.ldx, m.n_total, n_pad, pieces, cols, len_dev, len_host, sc,
+                                                        c, s, keep, z);
+    else if (keep)
+        k_scan_i8<false, true><<<g, threads, dyn, st>>>(X, m.ldx, m.n_total, n_pad, pieces, cols, len_dev, len_host, sc,
+                                                        c, s, keep, z);
+    else
+        k_scan_i8<false, false><<<g, threads, dyn, st>>>(X, m.ldx, m.n_total, n_pad, pieces, cols, len_dev, len_host,
+                                                         sc, c, s, keep, z);
     return hipGetLastError();
 }
 
