@@ -50,6 +50,7 @@ struct Mat {
 };
 
 int device_cu_count();
+int64_t device_lds_per_block();   // dynamic LDS bytes one workgroup may take
 
 // column statistics: center, scale, keep; n_rows written to *n_rows_dev (device) when not null
 hipError_t launch_colstats(const Mat& m, double* c, double* s, uint8_t* keep, int64_t n_rows, hipStream_t st);

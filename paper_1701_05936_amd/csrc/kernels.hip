@@ -114,7 +114,34 @@ __device__ __forceinline__ double wave_col_dot(const XT* __restrict__ x, const d
     const int lane = threadIdx.x & (WAVE - 1);
     double acc0 = 0.0, acc1 = 0.0;
     int64_t base = 0;
-    if constexpr (VEC) {
+    if constexpr (VEC && sizeof(XT) == 1) {
+        // int8 codes: lane l takes the 4-byte word of rows 4l .. 4l+3 of each 256-row step (one coalesced
+        // 256-byte load per wavefront), so its residual values are 32 contiguous bytes at a 32-byte lane stride
+        // (16 codes per lane would put the lanes 128 bytes apart: LDS bank conflicts, 8 bytes of r per code)
+        constexpr int64_t STEP = (int64_t)WAVE * 4;
+        constexpr int UI = 2 * U;
+        const int64_t nfull = (n / STEP) * STEP;
+        auto word = [&](int v, const double* rr, double acc) {
+            acc = fma((double)(int)(int8_t)(v & 0xff), rr[0], acc);
+            acc = fma((double)(int)(int8_t)((v >> 8) & 0xff), rr[1], acc);
+            acc = fma((double)(int)(int8_t)((v >> 16) & 0xff), rr[2], acc);
+            return fma((double)(v >> 24), rr[3], acc);
+        };
+        for (; base + UI * STEP <= nfull; base += UI * STEP) {
+            int v[UI];
+#pragma unroll
+            for (int u = 0; u < UI; ++u)
+                v[u] = __builtin_nontemporal_load(reinterpret_cast<const int*>(x + base + u * STEP + 4 * lane));
+#pragma unroll
+            for (int u = 0; u < UI; ++u) {
+                const double* rr = r + base + u * STEP + 4 * lane;
+                if (u & 1) acc1 = word(v[u], rr, acc1);
+                else acc0 = word(v[u], rr, acc0);
+            }
+        }
+        for (; base < nfull; base += STEP)
+            acc0 = word(*reinterpret_cast<const int*>(x + base + 4 * lane), r + base + 4 * lane, acc0);
+    } else if constexpr (VEC) {
         using VT = typename Vec16<XT>::T;
         constexpr int W = Vec16<XT>::W;
         constexpr int64_t STEP = (int64_t)WAVE * W;
@@ -154,7 +181,7 @@ template <typename XT, bool MASK>
 __global__ __launch_bounds__(256) void k_colstats(const XT* __restrict__ X, int64_t ldx, int64_t n_total, int64_t p,
                                                   const uint8_t* __restrict__ mask, int64_t n_rows,
                                                   double* __restrict__ c, double* __restrict__ s,
-                                                  uint8_t* __restrict__ keep) {
+                                                  uint8_t* __restrict__ keep, bool vec) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
@@ -165,11 +192,47 @@ __global__ __launch_bounds__(256) void k_colstats(const XT* __restrict__ X, int6
         if constexpr (sizeof(XT) == 1) {
             // integer codes: exact sums
             int64_t s1 = 0, s2 = 0;
-            for (int64_t i = lane; i < n_total; i += WAVE) {
-                if (MASK && !mask[i]) continue;
-                int64_t v = (int64_t)x[i];
-                s1 += v;
-                s2 += v * v;
+            if (vec) {
+                // 16-byte words, four per lane in flight (a word that starts past the last row is read at the
+                // last word instead and cleared); sum x and x^2 with v_dot4_i32_i8, exact in int32 per lane
+                // (a lane sees at most n / 64 rows: |sum x^2| < 2^14 n / 64 < 2^31 for n <= 2^23)
+                const int64_t last_word = (n_total - 1) & ~(int64_t)15;
+                int a1 = 0, a2 = 0;
+                for (int64_t base = 16 * lane; base < n_total; base += 4 * 16 * WAVE) {
+                    v4i32 w[4], mk[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int64_t r0 = base + u * 16 * WAVE;
+                        const int64_t rl = r0 < last_word ? r0 : last_word;
+                        w[u] = *reinterpret_cast<const v4i32*>(x + rl);
+                        if constexpr (MASK) mk[u] = *reinterpret_cast<const v4i32*>(mask + rl);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int64_t r0 = base + u * 16 * WAVE;
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) {
+                            const int64_t nv = n_total - r0 - 4 * d;
+                            uint32_t keepb = nv >= 4 ? 0xFFFFFFFFu : (nv <= 0 ? 0u : ((1u << (8 * (int)nv)) - 1u));
+                            if constexpr (MASK) {
+                                const uint32_t mv = (uint32_t)mk[u][d];
+                                keepb &= (((((mv & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | mv) & 0x80808080u) >> 7) * 0xFFu;
+                            }
+                            const int v = (int)((uint32_t)w[u][d] & keepb);
+                            a1 = __builtin_amdgcn_sdot4(v, 0x01010101, a1, false);
+                            a2 = __builtin_amdgcn_sdot4(v, v, a2, false);
+                        }
+                    }
+                }
+                s1 = a1;
+                s2 = a2;
+            } else {
+                for (int64_t i = lane; i < n_total; i += WAVE) {
+                    if (MASK && !mask[i]) continue;
+                    int64_t v = (int64_t)x[i];
+                    s1 += v;
+                    s2 += v * v;
+                }
             }
             s1 = wave_sum_i64(s1);
             s2 = wave_sum_i64(s2);
@@ -722,21 +785,39 @@ int device_cu_count() {
     return cached;
 }
 
+// dynamic LDS one workgroup may take on this device (64 KB assumed when the query fails)
+int64_t device_lds_per_block() {
+    static int64_t cached = 0;
+    if (!cached) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+            cached = v;
+        else
+            cached = 64 * 1024;
+    }
+    return cached;
+}
+
 hipError_t launch_colstats(const Mat& m, double* c, double* s, uint8_t* keep, int64_t n_rows, hipStream_t st) {
     const int g = grid_for(m.p, 4, device_cu_count() * 16);
     const bool mk = m.mask != nullptr;
+    // int8 codes read as 16-byte words: columns (and the row mask) 16-byte aligned, and few enough rows that a
+    // lane's int32 sum of squares cannot overflow
+    const bool vec = m.xtype == 2 && (uintptr_t)m.X % 16 == 0 && m.ldx % 16 == 0 && (uintptr_t)m.mask % 16 == 0 &&
+                     m.n_total <= (int64_t(1) << 22);
     switch (m.xtype) {
         case 0:
-            if (mk) k_colstats<double, true><<<g, 256, 0, st>>>((const double*)m.X, m.ldx, m.n_total, m.p, m.mask, n_rows, c, s, keep);
-            else k_colstats<double, false><<<g, 256, 0, st>>>((const double*)m.X, m.ldx, m.n_total, m.p, m.mask, n_rows, c, s, keep);
+            if (mk) k_colstats<double, true><<<g, 256, 0, st>>>((const double*)m.X, m.ldx, m.n_total, m.p, m.mask, n_rows, c, s, keep, vec);
+            else k_colstats<double, false><<<g, 256, 0, st>>>((const double*)m.X, m.ldx, m.n_total, m.p, m.mask, n_rows, c, s, keep, vec);
             break;
         case 1:
-            if (mk) k_colstats<float, true><<<g, 256, 0, st>>>((const float*)m.X, m.ldx, m.n_total, m.p, m.mask, n_rows, c, s, keep);
-            else k_colstats<float, false><<<g, 256, 0, st>>>((const float*)m.X, m.ldx, m.n_total, m.p, m.mask, n_rows, c, s, keep);
+            if (mk) k_colstats<float, true><<<g, 256, 0, st>>>((const float*)m.X, m.ldx, m.n_total, m.p, m.mask, n_rows, c, s, keep, vec);
+            else k_colstats<float, false><<<g, 256, 0, st>>>((const float*)m.X, m.ldx, m.n_total, m.p, m.mask, n_rows, c, s, keep, vec);
             break;
         default:
-            if (mk) k_colstats<int8_t, true><<<g, 256, 0, st>>>((const int8_t*)m.X, m.ldx, m.n_total, m.p, m.mask, n_rows, c, s, keep);
-            else k_colstats<int8_t, false><<<g, 256, 0, st>>>((const int8_t*)m.X, m.ldx, m.n_total, m.p, m.mask, n_rows, c, s, keep);
+            if (mk) k_colstats<int8_t, true><<<g, 256, 0, st>>>((const int8_t*)m.X, m.ldx, m.n_total, m.p, m.mask, n_rows, c, s, keep, vec);
+            else k_colstats<int8_t, false><<<g, 256, 0, st>>>((const int8_t*)m.X, m.ldx, m.n_total, m.p, m.mask, n_rows, c, s, keep, vec);
     }
     return hipGetLastError();
 }
@@ -771,8 +852,9 @@ template <typename XT>
 static hipError_t scan_typed(const Mat& m, const ScanArgs& a, hipStream_t st) {
     const int threads = 512;
     const int wpb = threads / WAVE;
+    // r in LDS while two workgroups of 8 waves still fit a CU (160 KB of LDS per CU on gfx950)
     const size_t lds = (size_t)m.n_total * sizeof(double);
-    const bool rlds = lds <= 64 * 1024;
+    const bool rlds = lds <= 80 * 1024 && (int64_t)lds <= device_lds_per_block();
     const bool vec = (((uintptr_t)m.X) % 16 == 0) && ((m.ldx * (int64_t)sizeof(XT)) % 16 == 0);
     const int64_t work = a.len_dev ? m.p : a.len_host;  // upper bound when the length lives on the device
     const int per_cu = rlds ? (lds <= 40 * 1024 ? 4 : (lds <= 53 * 1024 ? 3 : 2)) : 4;
