@@ -276,8 +276,9 @@ __global__ __launch_bounds__(PIECE_THREADS) void k_r_pieces_i8(const double* __r
 
 // The scan is a matrix-vector product bound by HBM: each wavefront streams I8_COLS columns at a time, lane l
 // reading rows 16 l .. 16 l + 15 of a 1,024-row chunk of each (one 1 KB coalesced load per column and chunk),
-// and multiplies every 4-byte word into the four pieces' words with v_dot4_i32_i8 (exact int32 sums; a lane
-// sees at most n / 64 rows, so |sum| < 2^15 n / 64 < 2^31 for n <= 2^21).  The pieces sit in LDS (16-byte
+// and multiplies every 4-byte word into the four pieces' words with v_dot4_i32_i8 (exact int32 sums:
+// |x_i q_ik| <= 128 * 127 < 2^14 and a lane sees at most 2^15 rows for n <= 2^21, so a lane's sum stays below
+// 2^29, as wave_isum needs).  The pieces sit in LDS (16-byte
 // reads at 16-byte lane strides).  The next chunk's loads are in flight while the current one is multiplied.
 // The last, partial chunk reads each word that starts past the last row at the last word instead (in bounds);
 // the pieces are zero on every row past n_total, so those products vanish.
