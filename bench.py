@@ -339,7 +339,7 @@ def run_learned(args, rec, ctx, bl, Xd, Xt, yd, y):
                                f"{rec.lambda_min_ratio} lambda_max, learned screening (network-filtered strong rule "
                                f"+ BEDPP + exact check), CD tol {args.tol:g}",
                    "n": rec.n, "p": rec.p, "nlambda": rec.nlambda},
-        "roofline": hbm_roofline(kernels["scan"], "k_scan (f32 X)"),
+        "roofline": hbm_roofline(kernels["scan"], "k_scan (f32 X)", "k_scan_c5_blockar1_5000x1000000_f32.md"),
         "kernels": kernels,
         "forms": {"plain_gpu_paths_per_s": 1.0 / el_plain, "speedup_vs_plain_gpu": (args.steps / elapsed) * el_plain,
                   "max_abs_dbeta_vs_plain_path": dmax,
