@@ -90,7 +90,22 @@ constexpr int GM_K = 32;   // pool columns per workgroup
 constexpr int GM_N = 16;   // new columns per workgroup
 constexpr int GM_R = 64;   // rows per step
 
-template <typename XT, bool MASK>
+// 16 consecutive elements of a column, read as 16-byte words (p 16-byte aligned)
+template <typename XT>
+__device__ __forceinline__ void load16(const XT* p, XT (&dst)[16]) {
+    typedef int v4w __attribute__((ext_vector_type(4)));
+    constexpr int NV = 16 * (int)sizeof(XT) / 16;
+    v4w t[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) t[i] = reinterpret_cast<const v4w*>(p)[i];
+    __builtin_memcpy(dst, t, sizeof(t));
+}
+
+// VEC: columns and the row mask are 16-byte aligned; every step whose 64 rows lie below n_total then reads
+// each lane's 16 values with plain 16-byte loads (no per-element test), the next step's loads in flight during
+// the current step's matrix-core work; only a final partial step takes the element-wise guarded path.  The
+// operands and the matrix-core sequence are the same either way.
+template <typename XT, bool MASK, bool VEC>
 __global__ __launch_bounds__(64 * GM_W) void k_gram_update(const XT* __restrict__ X, int64_t ldx, int64_t n_total,
                                                           const uint8_t* __restrict__ mask,
                                                           const int32_t* __restrict__ pool_list, int64_t P,
@@ -128,8 +143,7 @@ __global__ __launch_bounds__(64 * GM_W) void k_gram_update(const XT* __restrict_
         }
     };
     f64x4 acc[2] = {(f64x4){0.0, 0.0, 0.0, 0.0}, (f64x4){0.0, 0.0, 0.0, 0.0}};
-    if (s0 < s1) load(s0);
-    for (int64_t step = s0; step < s1; ++step) {
+    auto step_mfma = [&]() {
         double av[2][16], bv[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
@@ -137,12 +151,49 @@ __global__ __launch_bounds__(64 * GM_W) void k_gram_update(const XT* __restrict_
             av[1][q] = (double)ra[1][q];
             bv[q] = rm[q] ? (double)rb[q] : 0.0;
         }
-        if (step + 1 < s1) load(step + 1);
+        return [=, &acc]() {
 #pragma unroll
-        for (int st = 0; st < 16; ++st) {
-            acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0][st], bv[st], acc[0], 0, 0, 0);
-            acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1][st], bv[st], acc[1], 0, 0, 0);
+            for (int st = 0; st < 16; ++st) {
+                acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0][st], bv[st], acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1][st], bv[st], acc[1], 0, 0, 0);
+            }
+        };
+    };
+    int64_t sg = s0;   // first step of the guarded path
+    if constexpr (VEC) {
+        // full steps: whole 16-row segments for every lane
+        auto load_full = [&](int64_t step) {
+            const int64_t r0 = step * GM_R + 16 * kq;
+            load16<XT>(ac[0] + r0, ra[0]);
+            load16<XT>(ac[1] + r0, ra[1]);
+            load16<XT>(bc + r0, rb);
+            if constexpr (MASK) {
+                typedef int v4w __attribute__((ext_vector_type(4)));
+                const v4w mw = *reinterpret_cast<const v4w*>(mask + r0);
+#pragma unroll
+                for (int q = 0; q < 16; ++q) rm[q] = ((mw[q >> 2] >> (8 * (q & 3))) & 0xff) != 0;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 16; ++q) rm[q] = true;
+            }
+        };
+        const int64_t nfs = n_total / GM_R;
+        const int64_t f1 = s1 < nfs ? s1 : nfs;
+        if (s0 < f1) load_full(s0);
+        for (int64_t step = s0; step < f1; ++step) {
+            auto run = step_mfma();                          // the current step's operands, converted
+            load_full(step + 1 < f1 ? step + 1 : f1 - 1);   // unconditional (the last full step reloads)
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
+            run();
         }
+        sg = s0 > f1 ? s0 : f1;
+    }
+    if (sg < s1) load(sg);
+    for (int64_t step = sg; step < s1; ++step) {
+        auto run = step_mfma();
+        if (step + 1 < s1) load(step + 1);
+        run();
     }
     if (w > 0) {
         red[w - 1][0][lane] = acc[0];
@@ -1001,12 +1052,19 @@ static hipError_t gram_typed(const Mat& m, const int32_t* pool_list, int64_t P, 
             return hipGetLastError();
         }
     }
-    if (m.mask)
-        k_gram_update<XT, true><<<grid, 64 * GM_W, 0, st>>>((const XT*)m.X, m.ldx, m.n_total, m.mask, pool_list, P,
-                                                             P0, N, c, s, n_rows, G, ldg);
+    const bool vec = (uintptr_t)m.X % 16 == 0 && (m.ldx * (int64_t)sizeof(XT)) % 16 == 0 && (uintptr_t)m.mask % 16 == 0;
+    if (m.mask && vec)
+        k_gram_update<XT, true, true><<<grid, 64 * GM_W, 0, st>>>((const XT*)m.X, m.ldx, m.n_total, m.mask,
+                                                                   pool_list, P, P0, N, c, s, n_rows, G, ldg);
+    else if (m.mask)
+        k_gram_update<XT, true, false><<<grid, 64 * GM_W, 0, st>>>((const XT*)m.X, m.ldx, m.n_total, m.mask,
+                                                                    pool_list, P, P0, N, c, s, n_rows, G, ldg);
+    else if (vec)
+        k_gram_update<XT, false, true><<<grid, 64 * GM_W, 0, st>>>((const XT*)m.X, m.ldx, m.n_total, m.mask,
+                                                                    pool_list, P, P0, N, c, s, n_rows, G, ldg);
     else
-        k_gram_update<XT, false><<<grid, 64 * GM_W, 0, st>>>((const XT*)m.X, m.ldx, m.n_total, m.mask, pool_list,
-                                                              P, P0, N, c, s, n_rows, G, ldg);
+        k_gram_update<XT, false, false><<<grid, 64 * GM_W, 0, st>>>((const XT*)m.X, m.ldx, m.n_total, m.mask,
+                                                                     pool_list, P, P0, N, c, s, n_rows, G, ldg);
     return hipGetLastError();
 }
 
