@@ -538,9 +538,23 @@ __global__ void k_b_commit(int nprob, const uint8_t* __restrict__ want, BatchSca
 // feeds rows i0 + 16 kq .. + 15 of pool columns kb + m, kb + 16 + m and new column tb + m; register q of its
 // result holds C[kb + kq + 4q (+ 16), tb + m].  A pair of two new columns is written by the tile with
 // k - P0 <= t only, so each problem's G stays exactly symmetric.
+// VEC: columns and every problem's mask row are 16-byte aligned: full 64-row steps read each lane's 16 values
+// as 16-byte words with no per-element test (the same operands as the guarded path, which only a final partial
+// step takes), the next step's loads in flight during the current step's matrix-core work.
 constexpr int BG_W = 4, BG_K = 32, BG_N = 16, BG_R = 64;
 
+// 16 consecutive elements of a column, read as 16-byte words (p 16-byte aligned)
 template <typename XT>
+__device__ __forceinline__ void bload16(const XT* p, XT (&dst)[16]) {
+    typedef int v4w __attribute__((ext_vector_type(4)));
+    constexpr int NV = 16 * (int)sizeof(XT) / 16;
+    v4w t[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) t[i] = reinterpret_cast<const v4w*>(p)[i];
+    __builtin_memcpy(dst, t, sizeof(t));
+}
+
+template <typename XT, bool VEC>
 __global__ __launch_bounds__(64 * BG_W) void k_b_gram_update(const XT* __restrict__ X, int64_t ldx, int64_t n_total,
                                                             const uint8_t* __restrict__ masks, int64_t p,
                                                             const int32_t* __restrict__ pool_list,
@@ -584,8 +598,7 @@ __global__ __launch_bounds__(64 * BG_W) void k_b_gram_update(const XT* __restric
         }
     };
     f64x4 acc[2] = {(f64x4){0.0, 0.0, 0.0, 0.0}, (f64x4){0.0, 0.0, 0.0, 0.0}};
-    if (s0 < s1) load(s0);
-    for (int64_t step = s0; step < s1; ++step) {
+    auto step_mfma = [&]() {
         double av[2][16], bv[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
@@ -593,12 +606,43 @@ __global__ __launch_bounds__(64 * BG_W) void k_b_gram_update(const XT* __restric
             av[1][q] = (double)ra[1][q];
             bv[q] = rm[q] ? (double)rb[q] : 0.0;
         }
-        if (step + 1 < s1) load(step + 1);
+        return [=, &acc]() {
 #pragma unroll
-        for (int st = 0; st < 16; ++st) {
-            acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0][st], bv[st], acc[0], 0, 0, 0);
-            acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1][st], bv[st], acc[1], 0, 0, 0);
+            for (int st = 0; st < 16; ++st) {
+                acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0][st], bv[st], acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1][st], bv[st], acc[1], 0, 0, 0);
+            }
+        };
+    };
+    int64_t sg = s0;   // first step of the guarded path
+    if constexpr (VEC) {
+        auto load_full = [&](int64_t step) {
+            const int64_t r0 = step * BG_R + 16 * kq;
+            bload16<XT>(ac[0] + r0, ra[0]);
+            bload16<XT>(ac[1] + r0, ra[1]);
+            bload16<XT>(bc + r0, rb);
+            typedef int v4w __attribute__((ext_vector_type(4)));
+            const v4w mw = *reinterpret_cast<const v4w*>(mk + r0);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) rm[q] = ((mw[q >> 2] >> (8 * (q & 3))) & 0xff) != 0;
+        };
+        const int64_t nfs = n_total / BG_R;
+        const int64_t f1 = s1 < nfs ? s1 : nfs;
+        if (s0 < f1) load_full(s0);
+        for (int64_t step = s0; step < f1; ++step) {
+            auto run = step_mfma();                          // the current step's operands, converted
+            load_full(step + 1 < f1 ? step + 1 : f1 - 1);   // unconditional (the last full step reloads)
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
+            run();
         }
+        sg = s0 > f1 ? s0 : f1;
+    }
+    if (sg < s1) load(sg);
+    for (int64_t step = sg; step < s1; ++step) {
+        auto run = step_mfma();
+        if (step + 1 < s1) load(step + 1);
+        run();
     }
     if (w > 0) {
         red[w - 1][0][lane] = acc[0];
@@ -976,12 +1020,21 @@ hipError_t launch_b_gram_update(const Mat& mt, const uint8_t* masks, int nprob, 
                                 int64_t max_P, int64_t max_N, const uint8_t* want, hipStream_t st) {
     if (max_N <= 0) return hipSuccess;
     dim3 grid((unsigned)((max_P + BG_K - 1) / BG_K), (unsigned)((max_N + BG_N - 1) / BG_N), nprob);
-    if (mt.xtype == 0)
-        k_b_gram_update<double><<<grid, 64 * BG_W, 0, st>>>((const double*)mt.X, mt.ldx, mt.n_total, masks, mt.p, pool_list,
-                                                      bs, c, s, Gp, cap, want);
+    const size_t es = mt.xtype == 0 ? 8 : 4;
+    const bool vec = (uintptr_t)mt.X % 16 == 0 && (mt.ldx * (int64_t)es) % 16 == 0 && (uintptr_t)masks % 16 == 0 &&
+                     mt.n_total % 16 == 0;
+    if (mt.xtype == 0 && vec)
+        k_b_gram_update<double, true><<<grid, 64 * BG_W, 0, st>>>((const double*)mt.X, mt.ldx, mt.n_total, masks, mt.p,
+                                                                  pool_list, bs, c, s, Gp, cap, want);
+    else if (mt.xtype == 0)
+        k_b_gram_update<double, false><<<grid, 64 * BG_W, 0, st>>>((const double*)mt.X, mt.ldx, mt.n_total, masks, mt.p,
+                                                                   pool_list, bs, c, s, Gp, cap, want);
+    else if (vec)
+        k_b_gram_update<float, true><<<grid, 64 * BG_W, 0, st>>>((const float*)mt.X, mt.ldx, mt.n_total, masks, mt.p,
+                                                                 pool_list, bs, c, s, Gp, cap, want);
     else
-        k_b_gram_update<float><<<grid, 64 * BG_W, 0, st>>>((const float*)mt.X, mt.ldx, mt.n_total, masks, mt.p, pool_list, bs,
-                                                     c, s, Gp, cap, want);
+        k_b_gram_update<float, false><<<grid, 64 * BG_W, 0, st>>>((const float*)mt.X, mt.ldx, mt.n_total, masks, mt.p,
+                                                                  pool_list, bs, c, s, Gp, cap, want);
     return hipGetLastError();
 }
 
