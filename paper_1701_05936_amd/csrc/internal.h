@@ -190,7 +190,7 @@ hipError_t launch_scan_bf16(const Mat& m, const __bf16* pieces, const int32_t* c
                             const uint8_t* keep, double* z, hipStream_t st);
 // int8 codes on int8 matrix cores against LOWP_I8_PIECES int8 pieces of the residual
 constexpr int LOWP_I8_PIECES = 4;
-// pieces [LOWP_I8_PIECES][lowp_pad(n_total)] int8 plus sc->i8_scale and sc->i8_a (one workgroup)
+// pieces [LOWP_I8_PIECES][lowp_pad_i8(n_total)] int8 plus sc->i8_scale and sc->i8_a (one workgroup)
 hipError_t launch_r_pieces_i8(const double* r, int64_t n_total, int8_t* pieces, DevScalars* sc, hipStream_t st);
 // cols must be non-null
 hipError_t launch_scan_i8(const Mat& m, const int8_t* pieces, const int32_t* cols, const int64_t* len_dev,
