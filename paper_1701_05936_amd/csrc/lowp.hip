@@ -104,18 +104,14 @@ __global__ __launch_bounds__(256) void k_scan_bf16(const int8_t* __restrict__ X,
         const int64_t j = valid ? (cols ? (int64_t)cols[t] : t) : 0;
         const int8_t* xc = X + j * ldx;
         double acc64[4] = {0.0, 0.0, 0.0, 0.0};
-        const bool bpiece = m < NPIECE;
-        const __bf16* pr = P + (int64_t)(bpiece ? m : 0) * n_pad;
+        // lanes past the pieces (m >= 3) read piece 0: their matrix-core outputs are never used
+        const __bf16* pr = P + (int64_t)(m < NPIECE ? m : 0) * n_pad;
         // one batch of SCAN_KC rows: 4 MFMA steps of 32 rows, each FP32 result promoted to FP64
         auto batch = [&](const v4i32& w0, const v4i32& w1, int64_t ib) {
-            // residual pieces of the 4 steps first (one wait for all), zero in lanes past the pieces
+            // residual pieces of the 4 steps first (one wait for all)
             bf16x8 bq[4];
-            const bf16x8 bzero = {};
 #pragma unroll
-            for (int st = 0; st < 4; ++st) {
-                const bf16x8 t = *reinterpret_cast<const bf16x8*>(pr + ib + lane_row(g, st));
-                bq[st] = bpiece ? t : bzero;
-            }
+            for (int st = 0; st < 4; ++st) bq[st] = *reinterpret_cast<const bf16x8*>(pr + ib + lane_row(g, st));
             const uint32_t wd[8] = {(uint32_t)w0.x, (uint32_t)w0.y, (uint32_t)w0.z, (uint32_t)w0.w,
                                     (uint32_t)w1.x, (uint32_t)w1.y, (uint32_t)w1.z, (uint32_t)w1.w};
             // the 4 steps go to the matrix cores back to back; each 32-row FP32 result is then promoted
@@ -134,28 +130,19 @@ __global__ __launch_bounds__(256) void k_scan_bf16(const int8_t* __restrict__ X,
         // SCAN_U batches' loads are issued before the first is used (memory parallelism per wave)
         int64_t i0 = 0;
         for (; i0 + SCAN_U * SCAN_KC <= nfull; i0 += SCAN_U * SCAN_KC) {
-            v4i32 w[SCAN_U][2];
+            v4i32 w[SCAN_U][2];   // lanes past the end of the list read column 0 (their sums are not written)
 #pragma unroll
             for (int u = 0; u < SCAN_U; ++u) {
-                w[u][0] = (v4i32){0, 0, 0, 0};
-                w[u][1] = (v4i32){0, 0, 0, 0};
-                if (valid) {
-                    const v4i32* xp = reinterpret_cast<const v4i32*>(xc + i0 + u * SCAN_KC + 16 * g);
-                    w[u][0] = xp[0];
-                    w[u][1] = xp[4];
-                }
+                const v4i32* xp = reinterpret_cast<const v4i32*>(xc + i0 + u * SCAN_KC + 16 * g);
+                w[u][0] = xp[0];
+                w[u][1] = xp[4];
             }
 #pragma unroll
             for (int u = 0; u < SCAN_U; ++u) batch(w[u][0], w[u][1], i0 + u * SCAN_KC);
         }
         for (; i0 < nfull; i0 += SCAN_KC) {
-            v4i32 w0 = {0, 0, 0, 0}, w1 = {0, 0, 0, 0};
-            if (valid) {
-                const v4i32* xp = reinterpret_cast<const v4i32*>(xc + i0 + 16 * g);
-                w0 = xp[0];
-                w1 = xp[4];
-            }
-            batch(w0, w1, i0);
+            const v4i32* xp = reinterpret_cast<const v4i32*>(xc + i0 + 16 * g);
+            batch(xp[0], xp[4], i0);
         }
         if (i0 < n_total) {
             // ragged tail: codes past n_total meet zero residual pieces, but are not read
@@ -174,8 +161,7 @@ __global__ __launch_bounds__(256) void k_scan_bf16(const int8_t* __restrict__ X,
 #pragma unroll
             for (int st = 0; st < 4; ++st) {
                 const bf16x8 a = codes_to_bf16(wd[2 * st], wd[2 * st + 1]);
-                bf16x8 b = {};
-                if (bpiece) b = *reinterpret_cast<const bf16x8*>(pr + i0 + lane_row(g, st));
+                const bf16x8 b = *reinterpret_cast<const bf16x8*>(pr + i0 + lane_row(g, st));
                 const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
                 const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, zero, 0, 0, 0);
 #pragma unroll
