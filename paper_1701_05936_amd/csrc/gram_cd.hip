@@ -90,6 +90,13 @@ constexpr int GM_K = 32;   // pool columns per workgroup
 constexpr int GM_N = 16;   // new columns per workgroup
 constexpr int GM_R = 64;   // rows per step
 
+// keeps the loads above it issued before the work below it: neither the IR passes (memory clobber) nor the
+// machine scheduler (sched_barrier) move them down to their first use
+__device__ __forceinline__ void issue_fence_g() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 // 16 consecutive elements of a column, read as 16-byte words (p 16-byte aligned)
 template <typename XT>
 __device__ __forceinline__ void load16(const XT* p, XT (&dst)[16]) {
@@ -183,8 +190,7 @@ __global__ __launch_bounds__(64 * GM_W) void k_gram_update(const XT* __restrict_
         for (int64_t step = s0; step < f1; ++step) {
             auto run = step_mfma();                          // the current step's operands, converted
             load_full(step + 1 < f1 ? step + 1 : f1 - 1);   // unconditional (the last full step reloads)
-            asm volatile("" ::: "memory");
-            __builtin_amdgcn_sched_barrier(0);
+            issue_fence_g();
             run();
         }
         sg = s0 > f1 ? s0 : f1;
@@ -243,11 +249,6 @@ __device__ __forceinline__ uint32_t bytes_nonzero(uint32_t v) {
 // 0xFF in the first nv bytes (nv clamped to 0..4)
 __device__ __forceinline__ uint32_t bytes_below(int64_t nv) {
     return nv >= 4 ? 0xFFFFFFFFu : (nv <= 0 ? 0u : ((1u << (8 * (int)nv)) - 1u));
-}
-// keeps the loads above it issued before the work below it (see the int8 scan)
-__device__ __forceinline__ void issue_fence_g() {
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_sched_barrier(0);
 }
 
 template <bool MASK>
