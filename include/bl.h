@@ -179,9 +179,9 @@ typedef enum {
  * The scan alone (Section 3.1.1, type (3)): z[j] = (x_j' r - c_j sum(r)) / (n s_j) for j in
  * cols[0..len-1], in the given precision.  For BL_PREC_BF16X3, err[j] (device, may be NULL)
  * receives the bound on |z[j] - exact| the precision form guarantees:
- *   err_j = (u_r + (1 + 2^-7) g32 + g64) sqrt(n (s_j^2 + c_j^2)) ||r||_2 / (n s_j),
+ *   err_j = (u_r + (1 + 2^-7) gc + g64) sqrt(n (s_j^2 + c_j^2)) ||r||_2 / (n s_j),
  *   u_r = (2^-8 + 2^-24)^3 (residual left after three BF16 pieces, relative to |r_i|),
- *   g32 = 32 u / (1 - 32 u), u = 2^-24 (FP32 chunks of 32 rows), g64 = 65536 * 2^-53 (FP64 sums of up
+ *   gc = 64 u / (1 - 64 u), u = 2^-24 (FP32 chunks of 64 rows), g64 = 65536 * 2^-53 (FP64 sums of up
  *   to 2^16 chunk and piece terms; n_total <= 2^21),
  * plus 1e-14 |z_j|.  For BL_PREC_I8X4 the residual is r = sum_k s_k q_k + t with int8 pieces q_1..q_4,
  * s_1 = 2^E the smallest power of two with max|r_i| <= 127 s_1 and s_{k+1} = s_k / 128, and

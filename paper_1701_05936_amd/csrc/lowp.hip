@@ -5,7 +5,7 @@
 //   r1 = bf16(r), r2 = bf16(r - r1), r3 = bf16(r - r1 - r2)   (residual pieces, FP64 differences)
 // on v_mfma_f32_16x16x32_bf16.  Int8 codes convert to BF16 exactly (|x| <= 256),
 // each product x * r_c is exact in FP32, the FP32 accumulator is promoted to FP64
-// after every 32-row MFMA step, and the three pieces are added in FP64.  The error of z_j is
+// after every 64 rows (two chained MFMA steps), and the three pieces are added in FP64.  The error of z_j is
 // bounded column by column (lowp_bound); a decision whose value lies within that
 // bound of its threshold is taken again on the exact FP64 scan.
 //
@@ -37,7 +37,7 @@ constexpr int SCAN_U = 4;       // batches whose loads are in flight together
 // arranged so that each 16-byte load instruction of the wave covers whole 64-byte spans of a column
 // (steps 0, 1: rows 16g .. 16g+15; steps 2, 3: rows 64+16g .. 64+16g+15).
 __device__ __forceinline__ int lane_row(int g, int st) { return st < 2 ? 16 * g + 8 * st : 64 + 16 * g + 8 * (st - 2); }
-constexpr int SCAN_PROMOTE = 32; // rows per FP32 chunk: the accumulator goes to FP64 after every MFMA step
+constexpr int SCAN_PROMOTE = 64; // rows per FP32 chunk: the accumulator goes to FP64 after every two MFMA steps
 constexpr int NPIECE = LOWP_PIECES;
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) void k_scan_bf16(const int8_t* __restrict__ X,
         double acc64[4] = {0.0, 0.0, 0.0, 0.0};
         // lanes past the pieces (m >= 3) read piece 0: their matrix-core outputs are never used
         const __bf16* pr = P + (int64_t)(m < NPIECE ? m : 0) * n_pad;
-        // one batch of SCAN_KC rows: 4 MFMA steps of 32 rows, each FP32 result promoted to FP64
+        // one batch of SCAN_KC rows: 4 MFMA steps of 32 rows, FP32 sums of 64 rows promoted to FP64
         auto batch = [&](const v4i32& w0, const v4i32& w1, int64_t ib) {
             // residual pieces of the 4 steps first (one wait for all)
             bf16x8 bq[4];
@@ -114,18 +114,19 @@ __global__ __launch_bounds__(256) void k_scan_bf16(const int8_t* __restrict__ X,
             for (int st = 0; st < 4; ++st) bq[st] = *reinterpret_cast<const bf16x8*>(pr + ib + lane_row(g, st));
             const uint32_t wd[8] = {(uint32_t)w0.x, (uint32_t)w0.y, (uint32_t)w0.z, (uint32_t)w0.w,
                                     (uint32_t)w1.x, (uint32_t)w1.y, (uint32_t)w1.z, (uint32_t)w1.w};
-            // the 4 steps go to the matrix cores back to back; each 32-row FP32 result is then promoted
-            f32x4 r[4];
+            // the 4 steps go to the matrix cores back to back as two chains of two (steps 0, 2 and 1, 3); each
+            // chain's 64-row FP32 sum is then promoted
+            f32x4 r[2];
 #pragma unroll
             for (int st = 0; st < 4; ++st) {
                 const bf16x8 a = codes_to_bf16(wd[2 * st], wd[2 * st + 1]);
                 const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
-                r[st] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bq[st], zero, 0, 0, 0);
+                r[st & 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bq[st], st < 2 ? zero : r[st & 1], 0, 0, 0);
             }
 #pragma unroll
-            for (int st = 0; st < 4; ++st)
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc64[q] += (double)r[st][q];
+                for (int q = 0; q < 4; ++q) acc64[q] += (double)r[h][q];
         };
         // SCAN_U batches' loads are issued before the first is used (memory parallelism per wave)
         int64_t i0 = 0;
@@ -158,15 +159,18 @@ __global__ __launch_bounds__(256) void k_scan_bf16(const int8_t* __restrict__ X,
                 }
                 wd[k] = w;
             }
+            f32x4 r[2];
 #pragma unroll
             for (int st = 0; st < 4; ++st) {
                 const bf16x8 a = codes_to_bf16(wd[2 * st], wd[2 * st + 1]);
                 const bf16x8 b = *reinterpret_cast<const bf16x8*>(pr + i0 + lane_row(g, st));
                 const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
-                const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, zero, 0, 0, 0);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc64[q] += (double)acc[q];
+                r[st & 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, st < 2 ? zero : r[st & 1], 0, 0, 0);
             }
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc64[q] += (double)r[h][q];
         }
         // lane (piece m, group g) holds columns 4g..4g+3 of this group for piece m; add the pieces
         double tot[4];
@@ -403,7 +407,7 @@ __global__ __launch_bounds__(256) void k_scan_i8(const int8_t* __restrict__ X, i
 }
 
 // Bound on |z~_j - z_j| (see the header of this file): A ||x_j||_2 / (n s_j), ||x_j||_2^2 = n (s_j^2 + c_j^2), with
-//   BF16 form: A = (u_r + (1 + 2^-7) gamma_32 + gamma_64) ||r||_2,
+//   BF16 form: A = (u_r + (1 + 2^-7) gamma_c + gamma_64) ||r||_2, gamma_c for FP32 chunks of 64 rows,
 //   int8 form: A = sc->i8_a + gamma_64 ||r||_2   (gamma_64 covers the FP64 scan that re-takes the decisions)
 __device__ __forceinline__ double lowp_bound(double cj, double sj, double n, double A) {
     return A * sqrt(n * (sj * sj + cj * cj)) / (n * sj);
@@ -468,9 +472,9 @@ double lowp_coef() {
     const double u8 = 1.0 / 256.0, u24 = 1.0 / 16777216.0, u53 = 1.0 / 9007199254740992.0;
     double ur = 1.0;
     for (int k = 0; k < NPIECE; ++k) ur *= (u8 + u24);  // residual left after the pieces, relative to |r_i|
-    const double g32 = SCAN_PROMOTE * u24 / (1.0 - SCAN_PROMOTE * u24);
-    const double g64 = 65536.0 * u53;                   // FP64 chunk and piece additions (n / 32 + 3 terms)
-    return ur + (1.0 + 1.0 / 128.0) * g32 + g64;
+    const double gc = SCAN_PROMOTE * u24 / (1.0 - SCAN_PROMOTE * u24);   // FP32 sums of SCAN_PROMOTE products
+    const double g64 = 65536.0 * u53;                   // FP64 chunk and piece additions (n / 64 + 3 terms)
+    return ur + (1.0 + 1.0 / 128.0) * gc + g64;
 }
 
 bool lowp_supported(const Mat& m) {
