@@ -385,8 +385,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the column-sharded design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (it would shard X by columns and "
+              "exchange only screening candidates and violators per lambda); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.copy_calib > 0:
         import torch
