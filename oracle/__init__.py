@@ -233,7 +233,7 @@ class Path:
         return icpt, b
 
 
-SCREEN_NONE, SCREEN_SSR = 0, 1
+SCREEN_NONE, SCREEN_SSR, SCREEN_ACTIVE = 0, 1, 2
 
 
 def fit_path(Xt, y, K=100, ratio=0.1, screen=SCREEN_SSR, tol=1e-13, max_sweeps=100000, mask=None) -> Path:

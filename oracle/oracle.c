@@ -299,6 +299,8 @@ double or_duality_gap(int64_t n_total, int64_t p, const double* X, int64_t ldx, 
  * sequential strong rule (or not screened) and repaired by a post-convergence
  * check over every kept feature:
  *   E_k = {j : beta_j != 0} u {j : |z_j(prev)| >= 2 l_k - l_{k-1}}
+ * (OR_SCREEN_ACTIVE keeps only the first part, the previous active set: a
+ * deliberately weak screen under which the check must add features back)
  *   repeat: CD over E_k; z = scan of all kept j;
  *           V = {j not in E_k : |z_j| > l_k}; stop if V is empty; E_k u= V.
  * BEDPP is evaluated only to report its survivor count; the solve never uses
@@ -352,6 +354,8 @@ int or_fit_path(int64_t n_total, int64_t p, const double* X, int64_t ldx, const 
                 }
                 if (screen == OR_SCREEN_NONE)
                     inE[j] = 1;
+                else if (screen == OR_SCREEN_ACTIVE)
+                    inE[j] = bcur[j] != 0.0 ? 1 : 0;
                 else
                     inE[j] = (bcur[j] != 0.0 || fabs(zprev[j]) >= thr) ? 1 : 0;
             }

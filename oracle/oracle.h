@@ -58,7 +58,9 @@ typedef struct {
     double* gap;         /* relative duality gap (P - D) / P                      */
 } or_path_stats;
 
-enum { OR_SCREEN_NONE = 0, OR_SCREEN_SSR = 1 };
+/* OR_SCREEN_ACTIVE: working set = previous active set only, so every feature entering the path is
+ * found by the post-convergence check (exercises the repair branch) */
+enum { OR_SCREEN_NONE = 0, OR_SCREEN_SSR = 1, OR_SCREEN_ACTIVE = 2 };
 
 int or_fit_path(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
                 const double* y, int64_t K, double ratio, int screen, double tol, int64_t max_sweeps,

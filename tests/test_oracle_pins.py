@@ -379,3 +379,156 @@ def test_mlp_gradient_matches_finite_differences():
     prob = oracle.mlp_forward(feat, params, H)
     bce = -np.mean(label * np.log(prob) + (1 - label) * np.log(1 - prob))
     assert loss == pytest.approx(bce, rel=1e-10)
+
+
+# ---------------------------------------------------------------------------------------------
+# the post-convergence check repairs a deliberately weak screen (Section 2.2: the strong rule is
+# heuristic and needs the check; here the working set is only the previous active set, so every
+# feature that enters the path must be found and added by the check)
+# ---------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_weak_screen_is_repaired_by_the_check(name):
+    prob = datagen.make(name, n=160, p=260)
+    Xt = prob.Xt.astype(np.float64)
+    y = prob.y[0]
+    weak = oracle.fit_path(Xt, y, K=25, ratio=0.05, screen=oracle.SCREEN_ACTIVE)
+    full = oracle.fit_path(Xt, y, K=25, ratio=0.05, screen=oracle.SCREEN_NONE)
+    assert weak.status == 0 and weak.k_done == 25
+    # the check found features the screen left out, and the path was solved again after adding them
+    assert weak.n_viol.sum() > 0
+    assert weak.n_rounds.max() >= 2
+    assert np.all(weak.n_rounds[weak.n_viol > 0] >= 2)
+    np.testing.assert_allclose(weak.beta, full.beta, atol=1e-11)
+    np.testing.assert_array_equal(weak.n_active, full.n_active)
+
+
+# ---------------------------------------------------------------------------------------------
+# duality gap, residual: closed forms and numpy
+# ---------------------------------------------------------------------------------------------
+
+def test_duality_gap_closed_form_at_beta_zero():
+    # at beta = 0 and lambda < lambda_max the dual point is y~ / (n lambda_max), so
+    # P = ||y~||^2 / 2 and D = ||y~||^2 / 2 * (1 - (1 - lambda/lambda_max)^2): gap = (1 - lambda/lambda_max)^2;
+    # at lambda >= lambda_max the dual point y~ / (n lambda) closes the gap
+    rng = np.random.default_rng(14)
+    Xt = rng.normal(size=(50, 90)) + rng.normal(size=(50, 1))
+    y = Xt[3] - Xt[8] + rng.normal(size=90)
+    mask = (rng.uniform(size=90) < 0.85).astype(np.uint8)
+    c, s, keep, n = oracle.standardize(Xt, mask)
+    ybar, yt, a, lmax, js = oracle.lambda_max(Xt, c, s, keep, y, mask)
+    beta = np.zeros(50)
+    for frac in (0.9, 0.5, 0.1):
+        g = oracle.duality_gap(Xt, c, s, keep, yt, yt, beta, frac * lmax, mask)
+        assert g == pytest.approx((1.0 - frac) ** 2, rel=1e-12)
+    assert abs(oracle.duality_gap(Xt, c, s, keep, yt, yt, beta, 1.5 * lmax, mask)) <= 1e-15
+
+
+def test_duality_gap_bounds_the_suboptimality():
+    # P(beta) - P(beta*) <= P - D for any beta (weak duality), with P* from a converged solve
+    rng = np.random.default_rng(15)
+    Xt = rng.normal(size=(30, 70))
+    y = 1.5 * Xt[2] + rng.normal(size=70)
+    c, s, keep, n = oracle.standardize(Xt)
+    ybar, yt, a, lmax, js = oracle.lambda_max(Xt, c, s, keep, y)
+    lam = 0.2 * lmax
+    bopt = np.zeros(30)
+    ropt = yt.copy()
+    assert oracle.cd(Xt, c, s, lam, np.arange(30), bopt, ropt, tol=1e-15)[0]
+    popt = oracle.objective(ropt, bopt, lam) * n
+    for t in range(5):
+        beta = bopt + rng.normal(scale=0.05, size=30) * (rng.uniform(size=30) < 0.5)
+        r = oracle.residual(Xt, c, s, yt, beta)
+        P = oracle.objective(r, beta, lam) * n
+        gap = oracle.duality_gap(Xt, c, s, keep, yt, r, beta, lam)
+        assert P - popt <= gap * P * (1 + 1e-9) + 1e-12
+        assert gap > 0
+
+
+def test_residual_matches_numpy():
+    rng = np.random.default_rng(16)
+    Xt = datagen.genotype_u8(16, 77, 40).astype(np.float64)
+    mask = (rng.uniform(size=77) < 0.75).astype(np.uint8)
+    c, s, keep, n = oracle.standardize(Xt, mask)
+    ybar, yt, a, lmax, js = oracle.lambda_max(Xt, c, s, keep, rng.normal(size=77), mask)
+    beta = rng.normal(size=40) * (rng.uniform(size=40) < 0.3)
+    yt = yt.copy()
+    yt[mask == 0] = 1e3          # rows outside the fit do not enter: r is 0 there
+    r = oracle.residual(Xt, c, s, yt, beta, mask)
+    Xtil, _, _ = std_numpy(Xt, mask)
+    expect = np.zeros(77)
+    expect[mask.astype(bool)] = yt[mask.astype(bool)] - Xtil @ beta
+    np.testing.assert_allclose(r, expect, rtol=1e-12, atol=1e-12)
+    assert np.all(r[mask == 0] == 0.0)
+
+
+# ---------------------------------------------------------------------------------------------
+# screening network: forward pass against numpy written from the definition
+# (input f -> relu(W1 f + b1) -> relu(W2 h1 + b2) -> w3 . h2 + b3 -> logistic)
+# ---------------------------------------------------------------------------------------------
+
+def test_mlp_forward_matches_numpy_definition():
+    H = 7
+    rng = np.random.default_rng(17)
+    params = rng.normal(scale=0.8, size=oracle.n_params(H))
+    feat = rng.uniform(-1, 2, size=(40, 4))
+    W1 = params[: 4 * H].reshape(H, 4)
+    b1 = params[4 * H: 5 * H]
+    W2 = params[5 * H: 5 * H + H * H].reshape(H, H)
+    b2 = params[5 * H + H * H: 6 * H + H * H]
+    w3 = params[6 * H + H * H: 7 * H + H * H]
+    b3 = params[7 * H + H * H]
+    h1 = np.maximum(feat @ W1.T + b1, 0.0)
+    h2 = np.maximum(h1 @ W2.T + b2, 0.0)
+    o = h2 @ w3 + b3
+    expect = 1.0 / (1.0 + np.exp(-o))
+    # the ReLUs cut something on this input (otherwise a missing ReLU would go unnoticed)
+    assert (feat @ W1.T + b1 < 0).any() and (h1 @ W2.T + b2 < 0).any()
+    np.testing.assert_allclose(oracle.mlp_forward(feat, params, H), expect, rtol=1e-13, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------------------------
+# BEDPP discard power: the closed form against the EDPP ball test written with explicit vectors
+# (Wang, Wonka & Ye 2015, basic EDPP with the reference point at lambda_max, which the paper's
+# Section 2.2 cites): with lambda' = n lambda, theta0 = y~ / (n lambda_max), v1 = sign(x~_*' y~) x~_*,
+# v2 = y~ / lambda' - theta0, v2p = v2 - (v1.v2 / ||v1||^2) v1, feature j is discarded when
+# |x~_j' (theta0 + v2p / 2)| < 1 - ||v2p|| ||x~_j|| / 2.
+# ---------------------------------------------------------------------------------------------
+
+def edpp_ball_discard(Xtil, yt, lam):
+    n = Xtil.shape[0]
+    corr = Xtil.T @ yt
+    js = int(np.argmax(np.abs(corr)))
+    lmp = np.abs(corr[js])                  # n lambda_max
+    theta0 = yt / lmp
+    v1 = np.sign(corr[js]) * Xtil[:, js]
+    v2 = yt / (n * lam) - theta0
+    v2p = v2 - (v1 @ v2) / (v1 @ v1) * v1
+    lhs = np.abs(Xtil.T @ (theta0 + 0.5 * v2p))
+    rhs = 1.0 - 0.5 * np.linalg.norm(v2p) * np.linalg.norm(Xtil, axis=0)
+    return lhs < rhs, lhs - rhs
+
+
+@pytest.mark.parametrize("seed,design", [(51, "gaussian"), (52, "genotype"), (53, "ar1")])
+def test_bedpp_discards_exactly_the_edpp_ball_set(seed, design):
+    n, p = 150, 600
+    if design == "gaussian":
+        Xt = datagen.gaussian_f64(seed, n, p)
+    elif design == "genotype":
+        Xt = datagen.genotype_u8(seed, n, p).astype(np.float64)
+    else:
+        Xt = datagen.ar1_f32(seed, n, p, 0.6).astype(np.float64)
+    rng = np.random.default_rng(seed)
+    y = Xt[rng.choice(p, 8, replace=False)].T @ rng.normal(size=8) + rng.normal(size=n)
+    a, b, keep, lmax, sg, v = bedpp_inputs(Xt, y)
+    Xtil, _, _ = std_numpy(Xt)
+    yt = y - y.mean()
+    total = 0
+    for frac in np.geomspace(0.99, 0.2, 12):
+        lam = frac * lmax
+        d = oracle.bedpp_discard(a, b, keep, lmax, sg, v, lam)
+        ball, margin = edpp_ball_discard(Xtil, yt, lam)
+        undecided = np.abs(margin) < 1e-10          # within rounding of the boundary
+        assert np.array_equal(d[~undecided], ball[~undecided]), f"lambda/lambda_max = {frac:.3f}"
+        total += d.sum()
+    assert total > 0
