@@ -57,10 +57,14 @@ typedef enum {
     BL_SCREEN_SSR = 1,        /* sequential strong rule + check over all kept features              */
     BL_SCREEN_BEDPP = 2,      /* safe rule only: working set = BEDPP survivors, check over them     */
     BL_SCREEN_SSR_BEDPP = 3,  /* hybrid (default): strong rule and check restricted to BEDPP survivors */
-    BL_SCREEN_LEARNED = 4     /* hybrid + screening network: from the fourth lambda on, a strong-rule candidate
+    BL_SCREEN_LEARNED = 4,    /* hybrid + screening network: from the fourth lambda on, a strong-rule candidate
                                  outside the previous active set enters the working set only if the network
                                  scores it at or above opts->mlp_tau; the check over all BEDPP survivors is unchanged
                                  and adds every violator back, so the solution is the hybrid rule's       */
+    BL_SCREEN_ACTIVE = 5      /* working set = previous active set (within the BEDPP survivors) only: no strong
+                                 rule, so every feature that enters the path is found by the check over the
+                                 BEDPP survivors and added back (Section 2.2: the check is what makes a
+                                 heuristic screen exact).  Slow on purpose; it exercises the repair loop.  */
 } bl_screen_rule;
 
 /* Design matrix.  X must be 16-byte aligned when ldx*sizeof(element) is a multiple of 16;
@@ -81,6 +85,27 @@ void bl_destroy(bl_ctx ctx);
 const char* bl_last_error(bl_ctx ctx);
 /* Number of compute units and the device name the context runs on (host outputs). */
 bl_status bl_device_info(bl_ctx ctx, int* n_cu, char* name, int name_len);
+
+/*
+ * Size limits of the coordinate-descent solve (host struct, read and written by value).
+ *   cov_max     largest working set solved in covariance form; larger sets run the residual-form
+ *               solve.  Default 16,320; 0 keeps the current value.
+ *   cd_helpers  most helper workgroups the multi-workgroup covariance solve may launch besides its
+ *               leader.  Every workgroup of that solve must be resident at once, so bl_create sets
+ *               it to (workgroups of that kernel resident per compute unit) x (compute units) - 1,
+ *               at most 255.  Sets whose multi-workgroup solve would need more helpers run the
+ *               single-workgroup solve (up to 7,168 features) or else the residual-form solve.
+ *               A value above the resident count is rejected (BL_ERR_INVALID); -1 keeps the current.
+ *   resident    out: workgroups of the multi-workgroup solve that fit on the device at once.
+ */
+typedef struct {
+    int64_t cov_max;
+    int32_t cd_helpers;
+    int32_t resident;
+} bl_limits;
+
+bl_status bl_get_limits(bl_ctx ctx, bl_limits* out);
+bl_status bl_set_limits(bl_ctx ctx, const bl_limits* in);
 
 /*
  * Column centers and scales over the fitted rows (Section 3.1: only c and s are
@@ -138,13 +163,17 @@ bl_status bl_screen(bl_ctx ctx, const bl_screen_state* st, double lambda_k, doub
                     const double* z_prev, uint8_t* safe, uint8_t* strong, int64_t* n_safe, int64_t* n_strong);
 
 /*
- * Cyclic coordinate descent at fixed lambda over the features set[0..set_len-1]
- * (visited in that order; int32 indices into 0..p-1, distinct, kept), warm-started
- * from beta [p] and its residual r [n_total] = ytilde - X~ beta, both updated in place.
+ * Cyclic coordinate descent at fixed lambda (Section 1: the pathwise coordinate descent the
+ * package is built on; Section 3.1.1: its inner products are type (3), x~_j' r, computed from raw
+ * X with the stored c and s) over the features set[0..set_len-1] (visited in that order; int32
+ * indices into 0..p-1, distinct, kept), warm-started from beta [p] and its residual
+ * r [n_total] = ytilde - X~ beta, both updated in place.
  * Coordinate step: u = z_j(r) + beta_j, beta_j' = S(u, lambda), r -= (beta_j' - beta_j) x~_j.
  * Stops when the largest |beta_j' - beta_j| of a sweep is < tol.  sweeps (host) = sweeps run.
  * Returns BL_ERR_NOT_CONVERGED after max_sweeps sweeps (beta, r are then the last iterate).
- * n_total <= 16384 in this build (BL_ERR_UNSUPPORTED otherwise).
+ * Working sets up to bl_limits.cov_max features are solved in covariance form (Gram entries of the
+ * set, type (1) products); larger sets update r after every coordinate, which this build supports
+ * for n_total <= 16384 only (BL_ERR_UNSUPPORTED otherwise).
  */
 bl_status bl_cd_solve(bl_ctx ctx, const bl_matrix* X, const double* center, const double* scale,
                       double lambda, const int32_t* set, int64_t set_len, double* beta, double* r, double tol,
@@ -216,6 +245,17 @@ typedef struct {
     float* rec_feat;           /* DEVICE [rec_cap x 4] or NULL                                  */
     float* rec_label;          /* DEVICE [rec_cap] or NULL                                      */
     int64_t rec_cap;
+    /* resume (warm starts, Section 1): k_start = 0 runs the whole path.  k_start >= 1 starts at lambda
+     * index k_start from beta_init = beta(lambda_{k_start - 1}) (DEVICE [p], standardized scale, the row
+     * the earlier call wrote) and, if r_init is not NULL, its residual (DEVICE [n_total], rows outside
+     * the fit 0).  Given the residual the earlier call ended that lambda with, the resumed rows are
+     * bit-identical to the uninterrupted call's; with r_init NULL the residual is recomputed from
+     * beta_init (equal up to rounding).  Results are written for k >= k_start only; k_done counts from
+     * 0.  Not with the learned rule or training records (they need the history of earlier lambdas). */
+    int32_t k_start;
+    const double* beta_init;
+    const double* r_init;
+    double* r_out;             /* DEVICE [n_total] or NULL: the residual at the last finished lambda  */
 } bl_path_opts;
 
 /* Results of bl_fit_path.  Host arrays have K entries; any pointer may be NULL (not written). */

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libbl.so")
 
 BL_OK, BL_ERR_INVALID, BL_ERR_NOMEM, BL_ERR_DEVICE, BL_ERR_NOT_CONVERGED, BL_ERR_UNSUPPORTED = range(6)
 X_F64, X_F32, X_I8 = 0, 1, 2
-SCREEN_NONE, SCREEN_SSR, SCREEN_BEDPP, SCREEN_SSR_BEDPP, SCREEN_LEARNED = 0, 1, 2, 3, 4
+SCREEN_NONE, SCREEN_SSR, SCREEN_BEDPP, SCREEN_SSR_BEDPP, SCREEN_LEARNED, SCREEN_ACTIVE = 0, 1, 2, 3, 4, 5
 PREC_FP64, PREC_BF16X3, PREC_I8X4 = 0, 1, 2
 
 _STATUS_NAMES = {0: "BL_OK", 1: "BL_ERR_INVALID", 2: "BL_ERR_NOMEM", 3: "BL_ERR_DEVICE",
@@ -31,7 +31,8 @@ _STATUS_NAMES = {0: "BL_OK", 1: "BL_ERR_INVALID", 2: "BL_ERR_NOMEM", 3: "BL_ERR_
 # exported C symbols (kept in step with include/bl.h)
 EXPORTS = ("bl_create", "bl_destroy", "bl_last_error", "bl_device_info", "bl_standardize", "bl_lambda_max",
            "bl_bedpp_setup", "bl_screen", "bl_cd_solve", "bl_kkt_check", "bl_scan", "bl_fit_path",
-           "bl_fit_path_batch", "bl_mlp_forward", "bl_mlp_loss_grad", "bl_mlp_train", "bl_profile", "bl_profile_get")
+           "bl_fit_path_batch", "bl_mlp_forward", "bl_mlp_loss_grad", "bl_mlp_train", "bl_profile", "bl_profile_get",
+           "bl_get_limits", "bl_set_limits")
 MLP_HIDDEN = 64
 MLP_NPARAMS = MLP_HIDDEN * MLP_HIDDEN + 7 * MLP_HIDDEN + 1
 PROF_SCAN, PROF_CD, PROF_COLSTATS, PROF_GRAM, PROF_RUPDATE, PROF_RECHECK, PROF_BSCAN, PROF_SETUP = range(8)
@@ -64,7 +65,12 @@ class _PathOpts(ctypes.Structure):
                 ("rule", ctypes.c_int32), ("tol", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32), ("precision", ctypes.c_int32), ("mlp", ctypes.c_void_p),
                 ("mlp_tau", ctypes.c_double), ("rec_feat", ctypes.c_void_p), ("rec_label", ctypes.c_void_p),
-                ("rec_cap", ctypes.c_int64)]
+                ("rec_cap", ctypes.c_int64), ("k_start", ctypes.c_int32), ("beta_init", ctypes.c_void_p),
+                ("r_init", ctypes.c_void_p), ("r_out", ctypes.c_void_p)]
+
+
+class _Limits(ctypes.Structure):
+    _fields_ = [("cov_max", ctypes.c_int64), ("cd_helpers", ctypes.c_int32), ("resident", ctypes.c_int32)]
 
 
 class _PathResult(ctypes.Structure):
@@ -135,6 +141,8 @@ def load_library(path: str = LIB_PATH):
     L.bl_mlp_train.argtypes = [vp, vp, vp, i64, vp, P(_MlpTrainOpts), P(_MlpTrainResult)]
     L.bl_profile.argtypes = [vp, ctypes.c_int]
     L.bl_profile_get.argtypes = [vp, ctypes.c_int, P(_KernelProfile)]
+    L.bl_get_limits.argtypes = [vp, P(_Limits)]
+    L.bl_set_limits.argtypes = [vp, P(_Limits)]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("bl_destroy", "bl_last_error"):
@@ -220,6 +228,17 @@ class Context:
         kp = _KernelProfile()
         self._check(load_library().bl_profile_get(self._h, kernel, ctypes.byref(kp)))
         return {"launches": kp.launches, "total_ms": kp.total_ms, "bytes": kp.bytes, "flops": kp.flops}
+
+    def limits(self) -> dict:
+        """Coordinate-descent size limits: cov_max, cd_helpers and the resident workgroup count."""
+        lm = _Limits()
+        self._check(load_library().bl_get_limits(self._h, ctypes.byref(lm)))
+        return {"cov_max": lm.cov_max, "cd_helpers": lm.cd_helpers, "resident": lm.resident}
+
+    def set_limits(self, cov_max: int = 0, cd_helpers: int = -1):
+        """Lower (or restore) the limits; 0 / -1 keep the current value."""
+        lm = _Limits(int(cov_max), int(cd_helpers), 0)
+        self._check(load_library().bl_set_limits(self._h, ctypes.byref(lm)))
 
     def device_info(self):
         n = ctypes.c_int()
@@ -345,10 +364,12 @@ class PathResult:
 
 def fit_path(ctx: Context, Xt, y, nlambda=100, lambda_min_ratio=0.1, lambdas=None, rule=SCREEN_SSR_BEDPP,
              tol=1e-8, max_sweeps=100000, max_rounds=100, row_mask=None, n_total=None, want_beta=True,
-             raise_on_error=True, precision=PREC_FP64, mlp=None, mlp_tau=0.0, rec_feat=None, rec_label=None
-             ) -> PathResult:
+             raise_on_error=True, precision=PREC_FP64, mlp=None, mlp_tau=0.0, rec_feat=None, rec_label=None,
+             k_start=0, beta_init=None, r_init=None, r_out=None) -> PathResult:
     """Whole path.  Learned rule: rule=SCREEN_LEARNED with mlp (float32 device [MLP_NPARAMS]) and mlp_tau.
-    Training records: rec_feat (float32 device [cap, 4]) and rec_label (float32 device [cap])."""
+    Training records: rec_feat (float32 device [cap, 4]) and rec_label (float32 device [cap]).
+    Resume: k_start >= 1 with beta_init (float64 device [p], beta at lambda index k_start - 1) and
+    optionally r_init (float64 device [n_total], its residual); r_out receives the final residual."""
     M = matrix(Xt, n_total, row_mask)
     K = int(nlambda)
     p = M.p
@@ -375,7 +396,8 @@ def fit_path(ctx: Context, Xt, y, nlambda=100, lambda_min_ratio=0.1, lambdas=Non
         raise ValueError(f"mlp must be float32 with {MLP_NPARAMS} parameters")
     opts = _PathOpts(K, float(lambda_min_ratio), lam_in.ctypes.data if lam_in is not None else None, int(rule),
                      float(tol), int(max_sweeps), int(max_rounds), int(precision), _ptr(mlp), float(mlp_tau),
-                     _ptr(rec_feat), _ptr(rec_label), rec_cap)
+                     _ptr(rec_feat), _ptr(rec_label), rec_cap, int(k_start), _ptr(beta_init), _ptr(r_init),
+                     _ptr(r_out))
     res = _PathResult(_ptr(beta), _ptr(c), _ptr(s), _ptr(keep), host["lam"].ctypes.data,
                       host["intercept"].ctypes.data, host["rss"].ctypes.data, host["obj"].ctypes.data,
                       host["sweeps"].ctypes.data, host["rounds"].ctypes.data, host["n_active"].ctypes.data,

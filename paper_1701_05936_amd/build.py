@@ -1,30 +1,50 @@
-"""Compile the HIP library libbl.so for gfx950 (in-tree, next to this file)."""
+"""Compile the HIP library libbl.so for gfx950 (in-tree, next to this file).
+
+Each source is compiled to its own object in parallel (objects under _build/, kept out of git), then
+the objects are linked into libbl.so.
+"""
 from __future__ import annotations
 
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbl.so")
-SOURCES = ["csrc/kernels.hip", "csrc/gram_cd.hip", "csrc/lowp.hip", "csrc/batch.hip", "csrc/mlp.hip", "csrc/api.cpp", "csrc/api_batch.cpp",
-           "csrc/api_mlp.cpp"]
+OBJ_DIR = os.path.join(HERE, "_build")
+SOURCES = ["csrc/kernels.hip", "csrc/gram_cd.hip", "csrc/lowp.hip", "csrc/batch.hip", "csrc/mlp.hip",
+           "csrc/cv.hip", "csrc/api.cpp", "csrc/api_batch.cpp", "csrc/api_mlp.cpp", "csrc/api_cv.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 instructions anywhere in this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 
 
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJ_DIR, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"), "-c",
+           os.path.join(HERE, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return obj
+
+
 def build(force: bool = True, verbose: bool = False) -> str:
     if not force and os.path.exists(LIB):
         return LIB
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    sources = [s for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+    jobs = max(1, min(len(sources), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), sources))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-           *[os.path.join(HERE, s) for s in SOURCES], "-o", tmp]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -5,6 +5,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 
 #include "ctx.h"
@@ -170,7 +171,13 @@ bl_status solve_set(bl_ctx ctx, const Mat& mt, const int32_t* set, const int64_t
                     double lam, double tol, int max_sweeps) {
     hipStream_t st = ctx->stream;
     const double es = (double)elem_bytes(mt.xtype);
-    if (m > gram_cd_max()) {
+    // covariance form up to cov_max features; the multi-workgroup solve only with every workgroup resident,
+    // else the single-workgroup solve (its gradient lives in LDS: GCD_MAX features) or the residual form
+    int H = gcd_multi_helpers(m);
+    const bool cov = m <= ctx->cov_max && (H <= ctx->cd_helpers || m <= GCD_MAX);
+    if (H > ctx->cd_helpers) H = 0;
+    ctx->last_residual = !cov;
+    if (!cov) {
         if (!cd_supported(mt.n_total))
             return fail(ctx, BL_ERR_UNSUPPORTED, "working set of %lld features with n_total %lld is too large",
                         (long long)m, (long long)mt.n_total);
@@ -213,7 +220,6 @@ bl_status solve_set(bl_ctx ctx, const Mat& mt, const int32_t* set, const int64_t
     HIPCHK(launch_gather_gram(set, m, pos, ctx->gpool, ctx->pool_cap, GE, st));
     HIPCHK(launch_gather_start(set, m, z, beta, g0, b0, st));
     prof_mark(ctx, 5);
-    const int H = gcd_multi_helpers(m);
     if (H > 0) {
         // leader + helper workgroups; g0 holds the working gradient, b1 the working coefficients
         double* dl;
@@ -294,7 +300,32 @@ bl_status bl_create(bl_ctx* out, int device, void* hip_stream) {
         return BL_ERR_NOMEM;
     }
     std::memset(c->sc_host, 0, sizeof(DevScalars));
+    // every workgroup of the multi-workgroup solve waits on the others, so all of them must be resident
+    c->cd_resident = gcd_multi_resident();
+    c->cd_helpers = std::min(255, std::max(0, c->cd_resident - 1));
+    c->cov_max = gram_cd_max();
     *out = c;
+    return BL_OK;
+}
+
+bl_status bl_get_limits(bl_ctx ctx, bl_limits* out) {
+    if (!ctx) return BL_ERR_INVALID;
+    if (!out) return fail(ctx, BL_ERR_INVALID, "out is NULL");
+    out->cov_max = ctx->cov_max;
+    out->cd_helpers = ctx->cd_helpers;
+    out->resident = ctx->cd_resident;
+    return BL_OK;
+}
+
+bl_status bl_set_limits(bl_ctx ctx, const bl_limits* in) {
+    if (!ctx) return BL_ERR_INVALID;
+    if (!in) return fail(ctx, BL_ERR_INVALID, "in is NULL");
+    if (in->cov_max < 0) return fail(ctx, BL_ERR_INVALID, "cov_max must be >= 0");
+    if (in->cd_helpers < -1 || in->cd_helpers > 255 || in->cd_helpers > ctx->cd_resident - 1)
+        return fail(ctx, BL_ERR_INVALID, "cd_helpers must be -1 or in 0..%d (resident workgroups - 1, at most 255)",
+                    std::min(255, std::max(0, ctx->cd_resident - 1)));
+    if (in->cov_max > 0) ctx->cov_max = in->cov_max;
+    if (in->cd_helpers >= 0) ctx->cd_helpers = in->cd_helpers;
     return BL_OK;
 }
 
@@ -444,11 +475,13 @@ bl_status bl_screen(bl_ctx ctx, const bl_screen_state* st, double lambda_k, doub
     const int rule = st->rule;
     if (rule == BL_SCREEN_LEARNED)
         return fail(ctx, BL_ERR_UNSUPPORTED, "the learned rule needs the path's z history: it runs inside bl_fit_path");
-    if (rule < BL_SCREEN_NONE || rule > BL_SCREEN_SSR_BEDPP) return fail(ctx, BL_ERR_INVALID, "unknown rule");
-    const bool bedpp = rule == BL_SCREEN_BEDPP || rule == BL_SCREEN_SSR_BEDPP;
+    if (rule < BL_SCREEN_NONE || rule > BL_SCREEN_ACTIVE) return fail(ctx, BL_ERR_INVALID, "unknown rule");
+    const bool active_only = rule == BL_SCREEN_ACTIVE;
+    const bool bedpp = rule == BL_SCREEN_BEDPP || rule == BL_SCREEN_SSR_BEDPP || active_only;
     const bool ssr = rule == BL_SCREEN_SSR || rule == BL_SCREEN_SSR_BEDPP;
     if (bedpp && (!st->a || !st->b)) return fail(ctx, BL_ERR_INVALID, "BEDPP needs a and b");
     if (ssr && !z_prev) return fail(ctx, BL_ERR_INVALID, "strong rule needs z_prev");
+    if (active_only && !st->active) return fail(ctx, BL_ERR_INVALID, "the active-set rule needs the active mask");
     if (!(std::isfinite(lambda_k) && lambda_k > 0.0)) return fail(ctx, BL_ERR_INVALID, "lambda_k must be finite and > 0");
     if (ssr && !(std::isfinite(lambda_prev) && lambda_prev >= lambda_k))
         return fail(ctx, BL_ERR_INVALID, "lambda_prev must be finite and >= lambda_k");
@@ -458,7 +491,9 @@ bl_status bl_screen(bl_ctx ctx, const bl_screen_state* st, double lambda_k, doub
     const double rhs = bedpp ? bedpp_rhs(st->lambda_max, lambda_k, st->v) : 0.0;
     const double sgn = st->sign_star < 0 ? -1.0 : 1.0;
     HIPCHK(launch_bedpp(p, st->a, st->b, st->keep, bedpp, st->lambda_max, sgn, lambda_k, rhs, safe, ctx->stream));
-    HIPCHK(launch_ssr(p, safe, st->active, nullptr, z_prev, ssr, 2.0 * lambda_k - lambda_prev, strong, ctx->stream));
+    // the active-set rule: the strong rule's test with an infinite threshold keeps the active features only
+    HIPCHK(launch_ssr(p, safe, st->active, nullptr, active_only ? nullptr : z_prev, ssr || active_only,
+                      active_only ? INFINITY : 2.0 * lambda_k - lambda_prev, strong, ctx->stream));
     void* scr;
     int32_t* lst;
     int64_t* lens;
@@ -643,12 +678,17 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
                 return fail(ctx, BL_ERR_INVALID, "user lambda must be non-increasing");
         }
     }
-    if (opts->rule < BL_SCREEN_NONE || opts->rule > BL_SCREEN_LEARNED) return fail(ctx, BL_ERR_INVALID, "unknown rule");
+    if (opts->rule < BL_SCREEN_NONE || opts->rule > BL_SCREEN_ACTIVE) return fail(ctx, BL_ERR_INVALID, "unknown rule");
     if (!(opts->tol > 0.0) || opts->max_sweeps < 1 || opts->max_rounds < 1)
         return fail(ctx, BL_ERR_INVALID, "tol > 0, max_sweeps >= 1 and max_rounds >= 1 are required");
     const bool learned = opts->rule == BL_SCREEN_LEARNED;
-    const bool bedpp = opts->rule == BL_SCREEN_BEDPP || opts->rule == BL_SCREEN_SSR_BEDPP || learned;
+    const bool active_only = opts->rule == BL_SCREEN_ACTIVE;
+    const bool bedpp = opts->rule == BL_SCREEN_BEDPP || opts->rule == BL_SCREEN_SSR_BEDPP || learned || active_only;
     const bool ssr = opts->rule == BL_SCREEN_SSR || opts->rule == BL_SCREEN_SSR_BEDPP || learned;
+    const bool check = ssr || active_only;   // rules with a post-convergence check
+    const int k_start = opts->k_start;
+    if (k_start < 0 || k_start >= K) return fail(ctx, BL_ERR_INVALID, "k_start must be in 0..nlambda-1");
+    if (k_start > 0 && !opts->beta_init) return fail(ctx, BL_ERR_INVALID, "k_start > 0 needs beta_init");
     if (learned && (!opts->mlp || !(opts->mlp_tau >= 0.0 && opts->mlp_tau < 1.0)))
         return fail(ctx, BL_ERR_INVALID, "the learned rule needs opts->mlp and 0 <= mlp_tau < 1");
     const bool recording = opts->rec_cap > 0;
@@ -657,6 +697,8 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
     if (recording && !ssr) return fail(ctx, BL_ERR_INVALID, "training records need a rule with the strong rule");
     res->n_recorded = 0;
     const bool history = learned || recording;
+    if (k_start > 0 && history)
+        return fail(ctx, BL_ERR_UNSUPPORTED, "resuming needs no z history: not with the learned rule or training records");
     const float tau_logit = learned && opts->mlp_tau > 0.0 ? (float)std::log(opts->mlp_tau / (1.0 - opts->mlp_tau))
                                                            : -INFINITY;
     if (opts->precision != BL_PREC_FP64 && opts->precision != BL_PREC_BF16X3 && opts->precision != BL_PREC_I8X4)
@@ -807,12 +849,56 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         HIPCHK(launch_fill_u8((uint8_t*)zh, 0, (int64_t)3 * p * 4, st));
         HIPCHK(hipMemsetAsync(recn, 0, 8, st));
     }
-    if (lam[0] >= lmax) {
+    if (k_start > 0) {
+        // resume at lambda_{k_start} from beta(lambda_{k_start - 1}) and its residual
+        HIPCHK(hipMemcpyAsync(beta, opts->beta_init, p * 8, hipMemcpyDeviceToDevice, st));
+        if (opts->r_init) {
+            HIPCHK(hipMemcpyAsync(r, opts->r_init, nt * 8, hipMemcpyDeviceToDevice, st));
+        } else {
+            // r = y~ - X~ beta over the nonzero coefficients (the strong-rule test with an infinite
+            // threshold keeps the kept features with beta_j != 0)
+            HIPCHK(launch_ssr(p, keep, nullptr, beta, nullptr, true, INFINITY, strong, st));
+            HIPCHK(launch_compact(strong, p, lE, lens + 0, scr, st));
+            HIPCHK(hipMemcpyAsync(&ctx->sc_host->n_new, lens + 0, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            const int64_t mz = ctx->sc_host->n_new;
+            if (mz > 0) {
+                double *g0, *b0, *b1, *part;
+                ENSURE(B_G0, (mz + 1) * 8, g0);
+                ENSURE(B_B0, (mz + 1) * 8, b0);
+                ENSURE(B_B1, (mz + 1) * 8, b1);
+                ENSURE(B_RUPART, r_update_scratch_bytes(nt, mz), part);
+                HIPCHK(launch_gather_start(lE, mz, beta, beta, g0, b1, st));
+                HIPCHK(launch_fill_f64(b0, 0.0, mz, st));
+                HIPCHK(launch_r_update(m, lE, mz, b0, b1, c, sc_, part, r, st));
+            }
+        }
+        HIPCHK(launch_sum_r(m, r, ctx->sc, true, st));
+        // z at lambda_{k_start - 1} over S_{k_start}: the strong rule's input, as the uninterrupted path's
+        // check scan at that lambda left it
+        const double lr = lam[k_start];
+        HIPCHK(launch_bedpp(p, a, b, keep, bedpp, lmax, sgn, lr, bedpp_rhs(lmax, lr, v), safe_next, st));
+        HIPCHK(launch_compact(safe_next, p, lT, len_next, scr, st));
+        ScanArgs za{};
+        za.cols = lT;
+        za.len_dev = len_next;
+        za.r = r;
+        za.sc = ctx->sc;
+        za.c = c;
+        za.s = sc_;
+        za.keep = keep;
+        za.z = z1;
+        HIPCHK(launch_scan(m, za, st));
+        zprev = z1;
+        zcur = z0;
+        k_first = k_start;
+    } else if (lam[0] >= lmax) {
         HIPCHK(launch_record(nullptr, lens + 3, len_cur, lens + 3, beta, c, sc_, ctx->sc, lam[0], stats + 0, st));
         if (res->beta) HIPCHK(hipMemcpyAsync(res->beta, beta, p * 8, hipMemcpyDeviceToDevice, st));
         if (history) HIPCHK(launch_zhist_keep(keep, p, a, lam[0], zh, st));   // z at lambda_max is a
         k_first = 1;
     }
+    const int k_row0 = k_start;   // first row of results this call writes
     for (int k = k_first; k < K; ++k) {
         const double lk = lam[k];
         const double lprev = k > 0 ? lam[k - 1] : lmax;
@@ -827,7 +913,8 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         }
         HIPCHK(launch_compact(scan_mask, p, lT, len_next, scr, st));
         // working set E_k
-        HIPCHK(launch_ssr(p, safe_cur, nullptr, beta, zprev, ssr, 2.0 * lk - lprev, strong, st));
+        HIPCHK(launch_ssr(p, safe_cur, nullptr, beta, zprev, check, active_only ? INFINITY : 2.0 * lk - lprev, strong,
+                          st));
         const int s1 = (k + 2) % 3, s2 = (k + 1) % 3, s3 = k % 3;   // slots of lambda_{k-1}, _{k-2}, _{k-3}
         if (history && k >= 3)
             HIPCHK(launch_learned(strong, beta, zh, p, s1, s2, s3, (float)(lk / lam[k - 1]), opts->mlp, tau_logit,
@@ -870,7 +957,7 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
                 ka.s = sc_;
                 ka.keep = keep;
                 ka.z = zcur;
-                ka.check = ssr;
+                ka.check = check;
                 ka.lam = lk;
                 ka.in_s = safe_cur;
                 ka.excl = strong;
@@ -898,7 +985,7 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
                 HIPCHK(hipMemcpyAsync(&ctx->sc->round.scan_len, len_next, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
                 HIPCHK(launch_fill_u8(flag, 0, p, st));
                 const double thr2 = (ssr && k + 1 < K) ? 2.0 * lam[k + 1] - lk : -1.0;
-                HIPCHK(launch_band(lT, len_next, zcur, c, sc_, ctx->sc, ssr ? lk : -1.0, safe_cur, strong, thr2, flag,
+                HIPCHK(launch_band(lT, len_next, zcur, c, sc_, ctx->sc, check ? lk : -1.0, safe_cur, strong, thr2, flag,
                                    nullptr, p, i8, st));
                 HIPCHK(launch_compact(flag, p, lB, lens + 4, scr, st));
                 ScanArgs ba{};
@@ -911,14 +998,14 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
                 ba.keep = keep;
                 ba.z = zcur;
                 HIPCHK(launch_scan(m, ba, st));
-                if (ssr) HIPCHK(launch_viol(lT, len_next, zcur, safe_cur, strong, lk, &ctx->sc->round.n_viol, p, st));
+                if (check) HIPCHK(launch_viol(lT, len_next, zcur, safe_cur, strong, lk, &ctx->sc->round.n_viol, p, st));
                 prof_mark(ctx, 9);
                 HIPCHK(hipMemcpyAsync(&ctx->sc_host->stage, lens + 4, sizeof(int64_t), hipMemcpyDeviceToHost, st));
             }
             HIPCHK(hipMemcpyAsync(&ctx->sc_host->round, &ctx->sc->round, sizeof(RoundInfo), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             const RoundInfo ri = ctx->sc_host->round;
-            if (m_len > gram_cd_max()) {
+            if (ctx->last_residual) {
                 prof_add(ctx, 0, BL_PROF_CD, (double)ri.sweeps * ri.cd_len * col_bytes);
             } else {
                 prof_add(ctx, 0, BL_PROF_CD, (double)ri.sweeps * (double)m_len * (double)m_len * 8.0);
@@ -972,12 +1059,13 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         zcur = (zcur == z0) ? z1 : z0;
         (void)zspare;
     }
-    if (k_first == 1 && res->k_done < 1) res->k_done = 1;
+    if (k_start == 0 && k_first == 1 && res->k_done < 1) res->k_done = 1;
+    if (opts->r_out) HIPCHK(hipMemcpyAsync(opts->r_out, r, nt * 8, hipMemcpyDeviceToDevice, st));
     // results
     std::vector<LamStats> hs(K);
     HIPCHK(hipMemcpyAsync(hs.data(), stats, (size_t)K * sizeof(LamStats), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    for (int k = 0; k < res->k_done; ++k) {
+    for (int k = k_row0; k < res->k_done; ++k) {
         if (res->intercept) res->intercept[k] = hs[k].intercept;
         if (res->rss) res->rss[k] = hs[k].rss;
         if (res->obj) res->obj[k] = hs[k].obj;

@@ -117,12 +117,16 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
     if (opts->lambda) return fail(ctx, BL_ERR_UNSUPPORTED, "batched form: user lambda grids are not supported");
     if (K > 1 && !(opts->lambda_min_ratio > 0.0 && opts->lambda_min_ratio < 1.0))
         return fail(ctx, BL_ERR_INVALID, "lambda_min_ratio must be in (0, 1)");
-    if (opts->rule < BL_SCREEN_NONE || opts->rule > BL_SCREEN_SSR_BEDPP) return fail(ctx, BL_ERR_INVALID, "unknown rule");
+    if (opts->rule < BL_SCREEN_NONE || opts->rule > BL_SCREEN_ACTIVE) return fail(ctx, BL_ERR_INVALID, "unknown rule");
+    if (opts->rule == BL_SCREEN_LEARNED) return fail(ctx, BL_ERR_UNSUPPORTED, "batched form: no learned rule");
+    if (opts->k_start != 0) return fail(ctx, BL_ERR_UNSUPPORTED, "batched form: no resume (k_start must be 0)");
     if (!(opts->tol > 0.0) || opts->max_sweeps < 1 || opts->max_rounds < 1)
         return fail(ctx, BL_ERR_INVALID, "tol > 0, max_sweeps >= 1 and max_rounds >= 1 are required");
     if (opts->precision != BL_PREC_FP64) return fail(ctx, BL_ERR_UNSUPPORTED, "batched form: FP64 scans only");
-    const bool bedpp = opts->rule == BL_SCREEN_BEDPP || opts->rule == BL_SCREEN_SSR_BEDPP;
-    const bool ssr = opts->rule == BL_SCREEN_SSR || opts->rule == BL_SCREEN_SSR_BEDPP;
+    // the active-set rule keeps only the previous active set: the strong rule with an infinite threshold
+    const bool active_only = opts->rule == BL_SCREEN_ACTIVE;
+    const bool bedpp = opts->rule == BL_SCREEN_BEDPP || opts->rule == BL_SCREEN_SSR_BEDPP || active_only;
+    const bool ssr = opts->rule == BL_SCREEN_SSR || opts->rule == BL_SCREEN_SSR_BEDPP || active_only;
     const int64_t p = m.p, nt = m.n_total, npad = batch_pad(nt);
     const double es = (double)elem_bytes(m.xtype);
     hipStream_t st = ctx->stream;
@@ -250,7 +254,8 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
         for (int b = 0; b < NB; ++b) {
             lg[(size_t)k * BNP + b] = lam[(size_t)b * K + (k < K ? k : K - 1)];
             if (k == K) continue;
-            tg[(size_t)k * BNP + b] = k > 0 ? 2.0 * lam[(size_t)b * K + k] - lam[(size_t)b * K + k - 1] : lam[(size_t)b * K];
+            tg[(size_t)k * BNP + b] = active_only ? INFINITY
+                                      : (k > 0 ? 2.0 * lam[(size_t)b * K + k] - lam[(size_t)b * K + k - 1] : lam[(size_t)b * K]);
         }
     HIPCHK(hipMemcpyAsync(lamg, lg.data(), lg.size() * 8, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(thrg, tg.data(), tg.size() * 8, hipMemcpyHostToDevice, st));

@@ -35,6 +35,11 @@ struct bl_ctx_s {
     // batched scan variant picked for the last shape (n_total, p, xtype)
     int64_t bscan_n = -1, bscan_p = -1;
     int bscan_x = -1, bscan_waves = 1;
+    // limits of the coordinate-descent solve (bl_limits)
+    int64_t cov_max = 0;                // largest working set of the covariance solve
+    int cd_helpers = 0;                 // most helper workgroups of the multi-workgroup solve
+    int cd_resident = 0;                // workgroups of that solve resident on the device at once
+    bool last_residual = false;         // the last solve_set ran the residual-form solve
     // kernel timing
     bool prof = false;
     hipEvent_t ev[10] = {};

@@ -1107,6 +1107,15 @@ int gcd_multi_helpers(int64_t m) {
     return (nb + HOWN - 1) / HOWN;
 }
 
+int gcd_multi_resident() {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gcd_multi, MT, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return per_cu * device_cu_count();
+}
+
 size_t gcd_multi_sync_words(int H) { return (size_t)(SYNC_APPLIED + 16 * (H + 1)); }
 
 hipError_t launch_gcd_multi(const GcdMultiArgs& a, hipStream_t st) {

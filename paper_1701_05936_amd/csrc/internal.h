@@ -168,6 +168,7 @@ struct GcdMultiArgs {
     DevScalars* sc;
 };
 int gcd_multi_helpers(int64_t m);  // 0: use the single-workgroup solve
+int gcd_multi_resident();          // workgroups of the multi-workgroup solve resident on the device at once
 int64_t gram_cd_max();              // largest working set of the covariance solve
 size_t gcd_multi_sync_words(int H);
 hipError_t launch_gcd_multi(const GcdMultiArgs& a, hipStream_t st);

@@ -460,7 +460,7 @@ __global__ void k_ssr(int64_t p, const uint8_t* __restrict__ safe, const uint8_t
         uint8_t out = 0;
         if (safe[j]) {
             bool act = active ? active[j] != 0 : (beta ? beta[j] != 0.0 : false);
-            out = (!ssr || act || fabs(zprev[j]) >= thr) ? 1 : 0;
+            out = (!ssr || act || (zprev && fabs(zprev[j]) >= thr)) ? 1 : 0;
         }
         strong[j] = out;
     }

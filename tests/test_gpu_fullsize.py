@@ -5,8 +5,8 @@ problems) and the learned form on the 5,000 x 1,000,000 block-AR(1) design (floa
 
 The oracle cannot run these paths whole in seconds, so the checks use what the oracle computes column by
 column: sampled column statistics, lambda_max over every column (in chunks), and KKT certificates of the
-GPU coefficients at sampled lambda values, with z computed by the oracle's scan over every column (c2, c4)
-or over every active column and a seeded sample of 50,000 others (c3, c5).
+GPU coefficients at sampled lambda values, with the standardization, the residual and z computed by the
+oracle over every column, in chunks.
 """
 import numpy as np
 import pytest
@@ -141,25 +141,11 @@ def test_c4_full_kkt_certificate(c4_full, b, k):
     assert on_a <= 1e-6
 
 
-def kkt_sampled(Xt, y, beta, lam, n_sample=50_000, seed=0):
-    """KKT residuals of beta at lam over every active column and n_sample seeded other columns, with the
-    columns' standardization, the residual and z all computed by the oracle (all rows in use)."""
-    act = np.flatnonzero(beta)
-    rng = np.random.default_rng(seed)
-    others = np.setdiff1d(np.arange(Xt.shape[0]), act)
-    samp = np.sort(rng.choice(others, size=min(n_sample, others.size), replace=False))
-    cols = np.concatenate([act, samp])
-    blk = np.ascontiguousarray(Xt[cols], dtype=np.float64)
-    c, s, keep, _ = oracle.standardize(blk)
-    assert keep[:act.size].all()
-    r = y - y.mean()
-    for i, j in enumerate(act):
-        r -= beta[j] * (blk[i] - c[i]) / s[i]
-    z = oracle.zscan(blk, c, s, keep, r)
-    zi = z[act.size:][keep[act.size:]]
-    out_viol = np.max(np.abs(zi)) / lam - 1.0
-    on_act = np.max(np.abs(z[:act.size] - lam * np.sign(beta[act]))) / lam if act.size else 0.0
-    return out_viol, on_act, act.size
+def oracle_stats(Xt, mask=None):
+    """The oracle's column statistics over every column, chunk by chunk."""
+    st = chunked(Xt, lambda blk, j0: oracle.standardize(blk, mask)[:3])
+    return (np.concatenate([t[0] for t in st]), np.concatenate([t[1] for t in st]),
+            np.concatenate([t[2] for t in st]).astype(bool))
 
 
 @pytest.fixture(scope="module")
@@ -179,13 +165,15 @@ def c3_full(gpu_ctx):
         f"{lp.n_active[-1]} active at the end, {int(lp.n_recheck.sum())} / {int(bp.n_recheck.sum())} FP64 rechecks")
     del Xd
     torch.cuda.empty_cache()
-    return rec, Xt, y, lp, bp, hp
+    log("oracle column statistics of c3 ...")
+    stats = oracle_stats(Xt)
+    return rec, Xt, y, lp, bp, hp, stats
 
 
 def test_c3_full_precision_forms_equal_fp64_path(c3_full):
     """The int8 and the BF16 matrix-core scans take every decision the FP64 scans take: identical
     coefficients."""
-    rec, Xt, y, lp, bp, hp = c3_full
+    rec, Xt, y, lp, bp, hp, stats = c3_full
     assert lp.k_done == rec.nlambda and bp.k_done == rec.nlambda and hp.k_done == rec.nlambda
     assert torch.equal(lp.beta, hp.beta)
     assert torch.equal(bp.beta, hp.beta.cpu())
@@ -195,23 +183,24 @@ def test_c3_full_precision_forms_equal_fp64_path(c3_full):
 
 
 @pytest.mark.parametrize("k", [30, 99])
-def test_c3_full_kkt_certificate_sampled(c3_full, k):
-    rec, Xt, y, lp, bp, hp = c3_full
+def test_c3_full_kkt_certificate(c3_full, k):
+    rec, Xt, y, lp, bp, hp, (c, s, keep) = c3_full
     beta = lp.beta[k].cpu().numpy()
     lam = lp.lam[k]
-    out_v, on_a, na = kkt_sampled(Xt, y, beta, lam)
-    log(f"c3 k={k}: lambda {lam:.6g}, active {na}, max sampled inactive |z|/lambda - 1 = {out_v:.2e}, "
-        f"max active |z - lambda sign| / lambda = {on_a:.2e}")
+    out_v, on_a = kkt_residuals(Xt, c, s, keep, y - y.mean(), beta, lam)
+    log(f"c3 k={k}: lambda {lam:.6g}, active {np.count_nonzero(beta)}, max inactive |z|/lambda - 1 over all "
+        f"columns = {out_v:.2e}, max active |z - lambda sign| / lambda = {on_a:.2e}")
     assert out_v <= 1e-6
     assert on_a <= 1e-6
 
 
 @pytest.fixture(scope="module")
 def c5_full(gpu_ctx):
-    """The learned form on the full c5 design over the first 60 lambda values of its grid, with a network
-    trained on 10 recorded strong-rule paths of a 10,000-column design of the same recipe."""
+    """The learned form on the full c5 design over its whole 100-lambda grid, with a network trained on 10
+    recorded strong-rule paths (first 60 lambda values) of a 10,000-column design of the same recipe."""
     rec = datagen.RECIPES["c5"]
     depth = 60
+    full = rec.nlambda
     step = rec.lambda_min_ratio ** (1.0 / (rec.nlambda - 1))
     tr = rec.scaled(p=10_000, seed=rec.seed + 1000, nresp=10)
     tp = datagen.make(tr)
@@ -238,23 +227,25 @@ def c5_full(gpu_ctx):
     Xd = torch.from_numpy(Xt).to(DEV)
     yd = torch.from_numpy(y).to(DEV)
     lmax = bl.fit_path(gpu_ctx, Xd, yd, nlambda=1, want_beta=False).lambda_max
-    res = bl.fit_path(gpu_ctx, Xd, yd, nlambda=depth, lambdas=lmax * step ** np.arange(depth),
+    res = bl.fit_path(gpu_ctx, Xd, yd, nlambda=full, lambda_min_ratio=rec.lambda_min_ratio,
                       rule=bl.SCREEN_LEARNED, mlp=P, mlp_tau=info["tau"], tol=1e-10)
     log(f"learned path: {res.time_ms:.0f} ms, {res.n_active[-1]} active at the end, "
         f"{int(res.n_viol.sum())} violations repaired, working sets {int(res.n_strong.sum())}")
     del Xd
     torch.cuda.empty_cache()
-    return rec, Xt, y, res
+    log("oracle column statistics of c5 ...")
+    stats = oracle_stats(Xt)
+    return rec, Xt, y, res, stats
 
 
-@pytest.mark.parametrize("k", [30, 59])
-def test_c5_full_learned_kkt_certificate_sampled(c5_full, k):
-    rec, Xt, y, res = c5_full
-    assert res.k_done == 60
+@pytest.mark.parametrize("k", [30, 59, 80, 99])
+def test_c5_full_learned_kkt_certificate(c5_full, k):
+    rec, Xt, y, res, (c, s, keep) = c5_full
+    assert res.k_done == rec.nlambda
     beta = res.beta[k].cpu().numpy()
     lam = res.lam[k]
-    out_v, on_a, na = kkt_sampled(Xt, y, beta, lam)
-    log(f"c5 k={k}: lambda {lam:.6g}, active {na}, max sampled inactive |z|/lambda - 1 = {out_v:.2e}, "
-        f"max active |z - lambda sign| / lambda = {on_a:.2e}")
+    out_v, on_a = kkt_residuals(Xt, c, s, keep, y - y.mean(), beta, lam)
+    log(f"c5 k={k}: lambda {lam:.6g}, active {np.count_nonzero(beta)}, max inactive |z|/lambda - 1 over all "
+        f"columns = {out_v:.2e}, max active |z - lambda sign| / lambda = {on_a:.2e}")
     assert out_v <= 1e-6
     assert on_a <= 1e-6
