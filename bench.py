@@ -48,12 +48,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(Xt, y, rec, cols, tol, mask=None, what="path"):
-    """The FP64 oracle, as it is, on a column sample of the same design (bounded CPU work)."""
+def _oracle_leg(Xt, y, rec, cols, tol, mask, what, threads):
     import numpy as np
 
     import oracle
 
+    oracle.set_threads(threads)
     p = Xt.shape[0]
     stride = max(1, p // cols)
     sample = Xt[::stride][:cols].astype(np.float64)
@@ -65,12 +65,76 @@ def cpu_baseline(Xt, y, rec, cols, tol, mask=None, what="path"):
         "unit": "paths/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": (f"one full {rec.nlambda}-lambda {what} of the FP64 oracle (OpenMP column scans) on every "
-                   f"{stride}th column ({sample.shape[0]} of {p} columns, all {sample.shape[1]} rows, same y, "
-                   f"tol {tol:g}); {dt:.1f} s per path; a linear-in-p extrapolation to all columns would be "
-                   f"{1.0 / (dt * p / sample.shape[0]):.3g} paths/s"),
+        "sample": (f"one full {rec.nlambda}-lambda {what} of the FP64 oracle (OpenMP column scans, "
+                   f"{oracle.num_threads()} threads) on every {stride}th column ({sample.shape[0]} of {p} columns, "
+                   f"all {sample.shape[1]} rows, same y, tol {tol:g}); {dt:.1f} s per path; a linear-in-p "
+                   f"extrapolation to all columns would be {1.0 / (dt * p / sample.shape[0]):.3g} paths/s"),
         "k_done": int(path.k_done),
     }
+
+
+def cpu_baseline(Xt, y, rec, cols, tol, mask=None, what="path"):
+    """The FP64 oracle, as it is, on a column sample of the same design (bounded CPU work): with every host
+    thread, and with one thread on a tenth of the sample."""
+    import oracle
+
+    threads = oracle.num_threads()
+    out = _oracle_leg(Xt, y, rec, cols, tol, mask, what, threads)
+    out["one_thread"] = _oracle_leg(Xt, y, rec, max(100, cols // 10), tol, mask, what, 1)
+    oracle.set_threads(threads)
+    return out
+
+
+ERR_CHUNK = 20_000
+
+
+def path_error(Xt, y, beta_rows, lams, ks, mask=None):
+    """Accuracy of GPU coefficients at lambda indices ks, certified by the FP64 oracle over every column of X
+    (in chunks): the oracle's column statistics, the residual of the GPU coefficients, z = X~'r/n, then
+      kkt_inactive = max over kept j with beta_j = 0 of |z_j| / lambda - 1   (<= 0 at the optimum),
+      kkt_active   = max over beta_j != 0 of |z_j - lambda sign(beta_j)| / lambda,
+      gap          = relative duality gap (P - D) / P with P = n Q(beta), theta = r / (n max(lambda, max|z|)),
+                     D = ||y~||^2 / 2 - ||y~ - n lambda theta||^2 / 2: an upper bound on the relative
+                     objective error of beta against the exact solution."""
+    import numpy as np
+
+    import oracle
+
+    p = Xt.shape[0]
+    m = None if mask is None else mask.astype(np.float64)
+    c, s, keep = np.empty(p), np.empty(p), np.empty(p, dtype=bool)
+    for j0 in range(0, p, ERR_CHUNK):
+        blk = np.asarray(Xt[j0:j0 + ERR_CHUNK], dtype=np.float64)
+        cc, ss, kk, n = oracle.standardize(blk, mask)
+        c[j0:j0 + len(blk)], s[j0:j0 + len(blk)], keep[j0:j0 + len(blk)] = cc, ss, kk
+    rows = y if mask is None else y[mask > 0]
+    yt = y - rows.mean()
+    if m is not None:
+        yt = yt * m
+    out = {}
+    for k in ks:
+        beta, lam = beta_rows[k], float(lams[k])
+        act = np.flatnonzero(beta)
+        r = yt.copy()
+        for j in act:
+            xj = (np.asarray(Xt[j], dtype=np.float64) - c[j]) / s[j]
+            r -= beta[j] * (xj if m is None else xj * m)
+        z = np.empty(p)
+        for j0 in range(0, p, ERR_CHUNK):
+            blk = np.asarray(Xt[j0:j0 + ERR_CHUNK], dtype=np.float64)
+            z[j0:j0 + len(blk)] = oracle.zscan(blk, c[j0:j0 + len(blk)], s[j0:j0 + len(blk)], keep[j0:j0 + len(blk)],
+                                               r, mask)
+        inactive = keep & (beta == 0)
+        zmax = float(np.max(np.abs(z[keep])))
+        P = float(r @ r) / 2.0 + n * lam * float(np.abs(beta).sum())
+        theta = r / (n * max(lam, zmax))
+        D = float(yt @ yt) / 2.0 - float(np.sum((yt - n * lam * theta) ** 2)) / 2.0
+        out[str(k)] = {"lambda": lam, "active": int(act.size),
+                       "kkt_inactive": float(np.max(np.abs(z[inactive])) / lam - 1.0),
+                       "kkt_active": float(np.max(np.abs(z[act] - lam * np.sign(beta[act]))) / lam) if act.size
+                       else 0.0,
+                       "rel_duality_gap": (P - D) / P}
+    return out
 
 
 def kernel_table(ctx, bl, elapsed):
@@ -87,6 +151,11 @@ def kernel_table(ctx, bl, elapsed):
             if pr["flops"]:
                 kernels[k]["TFLOP_per_launch"] = pr["flops"] / pr["launches"] / 1e12
                 kernels[k]["TFLOPs"] = pr["flops"] / (pr["total_ms"] * 1e-3) / 1e12
+            if k == "cd" and pr["units"]:
+                # coordinate descent is latency-bound: its figure of merit is time per coordinate update
+                kernels[k]["updates"] = pr["units"]
+                kernels[k]["updates_per_s"] = pr["units"] / (pr["total_ms"] * 1e-3)
+                kernels[k]["ns_per_update"] = pr["total_ms"] * 1e6 / pr["units"]
     return kernels
 
 
@@ -153,10 +222,17 @@ def run_plain(args, rec, ctx, bl, Xd, Xt, yd, y):
         "path": {"n_active_last": int(last.n_active[-1]), "sweeps": int(last.sweeps.sum()),
                  "columns_scanned": int(last.n_scanned.sum()), "violations": int(last.n_viol.sum())},
     }
+    if not args.no_error:
+        log("error of the last timed path: oracle KKT certificates and duality gaps over every column ...")
+        out["error"] = {"what": "oracle over every column, at the CD tolerance timed",
+                        "per_lambda": path_error(Xt, y, last.beta.cpu().numpy(), last.lam, ERROR_KS)}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a column sample) ...")
         out["cpu_baseline"] = cpu_baseline(Xt, y, rec, args.cpu_cols, args.tol)
     return out
+
+
+ERROR_KS = (20, 60, 99)
 
 
 PRECISION_FORMS = {
@@ -214,6 +290,10 @@ def run_precision(args, rec, ctx, bl, Xd, Xt, yd, y):
         "path": {"n_active_last": int(lp.n_active[-1]), "sweeps": int(lp.sweeps.sum()),
                  "violations": int(lp.n_viol.sum())},
     }
+    if not args.no_error:
+        log("error of the last timed path: oracle KKT certificates and duality gaps over every column ...")
+        out["error"] = {"what": "oracle over every column, at the CD tolerance timed",
+                        "per_lambda": path_error(Xt, y, lp.beta.cpu().numpy(), lp.lam, ERROR_KS)}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a column sample) ...")
         out["cpu_baseline"] = cpu_baseline(Xt, y, rec, args.cpu_cols, args.tol)
@@ -267,6 +347,11 @@ def run_batch(args, rec, ctx, bl, Xd, Xt, prob):
         "path": {"sweeps": int(res.sweeps.sum()), "violations": int(res.n_viol.sum()),
                  "n_active_last_mean": float(res.n_active[:, -1].mean())},
     }
+    if not args.no_error:
+        log("error of problem 0 of the last timed batch: oracle certificates over every column ...")
+        out["error"] = {"what": "oracle over every column for problem 0 (its rows), at the CD tolerance timed",
+                        "per_lambda": path_error(Xt, Y[0], res.beta[0].cpu().numpy(), res.lam[0], (10, 30, 49),
+                                                 mask=prob.masks[0])}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a column sample, one problem) ...")
         out["cpu_baseline"] = cpu_baseline(Xt, Y[0], rec, args.cpu_cols, args.tol, mask=prob.masks[0],
@@ -355,10 +440,64 @@ def run_learned(args, rec, ctx, bl, Xd, Xt, yd, y):
         "path": {"n_active_last": int(lr_.n_active[-1]), "sweeps": int(lr_.sweeps.sum()),
                  "violations": int(lr_.n_viol.sum())},
     }
+    if not args.no_error:
+        log("error of the last timed path: oracle KKT certificates and duality gaps over every column ...")
+        out["error"] = {"what": "oracle over every column, at the CD tolerance timed",
+                        "per_lambda": path_error(Xt, y, lr_.beta.cpu().numpy(), lr_.lam, ERROR_KS)}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a column sample) ...")
         out["cpu_baseline"] = cpu_baseline(Xt, y, rec, args.cpu_cols, args.tol)
     return out
+
+
+def _load_design(rec, dev):
+    import torch
+
+    import datagen
+    t = time.perf_counter()
+    prob = datagen.make(rec) if rec.name == "c4" else None
+    Xt = prob.Xt if prob is not None else datagen.design(rec)
+    log(f"generated {rec.name} X {Xt.shape[1]}x{Xt.shape[0]} {Xt.dtype} in {time.perf_counter() - t:.1f} s")
+    storage = {"f64": torch.float64, "f32": torch.float32, "i8": torch.int8}[rec.storage]
+    if storage == torch.int8:
+        Xd = torch.from_numpy(Xt.view("int8")).to(dev)
+    else:
+        Xd = torch.from_numpy(Xt).to(dev)
+        if Xd.dtype != storage:
+            Xd = Xd.to(storage)
+    torch.cuda.synchronize()
+    log(f"X resident on GPU: {Xd.numel() * Xd.element_size() / 1e9:.1f} GB as {storage}")
+    return prob, Xt, Xd
+
+
+def run_forms(args, ctx, bl, dev):
+    """The precision form (c3: int8 storage, int8 dot-product scans, against the FP64-scan path on the same
+    storage) and the batched form (c4: 64 problems in lockstep, against single-problem paths), each timed
+    over one step after one warm-up at the same CD tolerance, with the headline's context."""
+    import copy
+
+    import torch
+
+    import datagen
+    sub = copy.copy(args)
+    sub.steps, sub.warmup, sub.no_cpu_baseline, sub.no_error = 1, 1, True, True
+    forms = {}
+    rec = datagen.RECIPES["c3"]
+    _, Xt, Xd = _load_design(rec, dev)
+    y = datagen.response(rec, Xt, 0)
+    o = run_precision(sub, rec, ctx, bl, Xd, Xt, torch.from_numpy(y).to(dev), y)
+    forms["c3_precision"] = {"workload": o["config"]["workload"], "paths_per_s": o["value"], "dtype": o["dtype"],
+                             "roofline": o["roofline"], **o["forms"]}
+    del Xd, Xt
+    torch.cuda.empty_cache()
+    rec = datagen.RECIPES["c4"]
+    prob, Xt, Xd = _load_design(rec, dev)
+    o = run_batch(sub, rec, ctx, bl, Xd, Xt, prob)
+    forms["c4_batched"] = {"workload": o["config"]["workload"], "problem_paths_per_s": o["value"],
+                           "dtype": o["dtype"], "roofline": o["roofline"], **o["forms"]}
+    del Xd, Xt, prob
+    torch.cuda.empty_cache()
+    return forms
 
 
 def main():
@@ -382,6 +521,9 @@ def main():
     ap.add_argument("--train-depth", type=int, default=60)
     ap.add_argument("--train-epochs", type=int, default=20)
     ap.add_argument("--target-recall", type=float, default=0.995)
+    ap.add_argument("--no-error", action="store_true", help="skip the oracle's error certificate of the timed path")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="c2: skip timing the precision (c3) and batched (c4) forms beside the headline")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -407,21 +549,8 @@ def main():
     import paper_1701_05936_amd as bl
 
     rec = datagen.RECIPES[args.workload]
-    t = time.perf_counter()
-    prob = datagen.make(rec) if args.workload == "c4" else None
-    Xt = prob.Xt if prob is not None else datagen.design(rec)
-    log(f"generated {rec.name} X {Xt.shape[1]}x{Xt.shape[0]} {Xt.dtype} in {time.perf_counter() - t:.1f} s")
-
     dev = torch.device("cuda", 0)
-    storage = {"f64": torch.float64, "f32": torch.float32, "i8": torch.int8}[rec.storage]
-    if storage == torch.int8:
-        Xd = torch.from_numpy(Xt.view("int8")).to(dev)
-    else:
-        Xd = torch.from_numpy(Xt).to(dev)
-        if Xd.dtype != storage:
-            Xd = Xd.to(storage)
-    torch.cuda.synchronize()
-    log(f"X resident on GPU: {Xd.numel() * Xd.element_size() / 1e9:.1f} GB as {storage}")
+    prob, Xt, Xd = _load_design(rec, dev)
 
     ctx = bl.Context(0)
     n_cu, name = ctx.device_info()
@@ -432,6 +561,10 @@ def main():
         yd = torch.from_numpy(y).to(dev)
         fn = {"c2": run_plain, "c3": run_precision, "c5": run_learned}[args.workload]
         out = fn(args, rec, ctx, bl, Xd, Xt, yd, y)
+    if args.workload == "c2" and not args.no_forms:
+        del Xd, Xt
+        torch.cuda.empty_cache()
+        out["forms"] = run_forms(args, ctx, bl, dev)
     ctx.close()
     line = {"metric": METRIC, "value": out.pop("value"), "unit": "paths/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": out.pop("ms_per_step"), "higher_is_better": True,

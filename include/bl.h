@@ -410,6 +410,8 @@ typedef struct {
     double total_ms;
     double bytes;
     double flops;              /* algorithmic floating-point operations (matrix-core scans), else 0 */
+    double units;              /* CD: coordinate updates (sweeps x working-set size, summed over solves and
+                                  problems); scans: columns scanned; else 0                            */
 } bl_kernel_profile;
 
 enum { BL_PROF_SCAN = 0, BL_PROF_CD = 1, BL_PROF_COLSTATS = 2, BL_PROF_GRAM = 3, BL_PROF_RUPDATE = 4,

@@ -41,6 +41,8 @@ def _load():
         i64, dbl, vp, i32 = ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_int
         L.or_num_threads.argtypes = []
         L.or_num_threads.restype = i32
+        L.or_set_threads.argtypes = [i32]
+        L.or_set_threads.restype = None
         L.or_standardize.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp]
         L.or_standardize.restype = i64
         L.or_zscan.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp, vp, vp]
@@ -96,6 +98,11 @@ def _mask(mask, n_total):
 
 def num_threads() -> int:
     return int(_load().or_num_threads())
+
+
+def set_threads(t: int) -> None:
+    """Thread count of the oracle's OpenMP column scans."""
+    _load().or_set_threads(int(t))
 
 
 def standardize(Xt, mask=None):

@@ -43,6 +43,15 @@ int or_num_threads(void) {
 #endif
 }
 
+/* set the thread count of the column scans (no effect without OpenMP) */
+void or_set_threads(int t) {
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
 #define KEEP_MIN_SD 1e-6
 
 static int64_t count_rows(int64_t n_total, const uint8_t* mask) {

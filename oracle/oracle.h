@@ -22,6 +22,7 @@ extern "C" {
 #endif
 
 int or_num_threads(void);
+void or_set_threads(int t);
 int64_t or_standardize(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
                        double* c, double* s, uint8_t* keep);
 void or_zscan(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,

@@ -57,7 +57,7 @@ class _ScreenState(ctypes.Structure):
 
 class _KernelProfile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double),
-                ("flops", ctypes.c_double)]
+                ("flops", ctypes.c_double), ("units", ctypes.c_double)]
 
 
 class _PathOpts(ctypes.Structure):
@@ -227,7 +227,8 @@ class Context:
     def profile_get(self, kernel: int) -> dict:
         kp = _KernelProfile()
         self._check(load_library().bl_profile_get(self._h, kernel, ctypes.byref(kp)))
-        return {"launches": kp.launches, "total_ms": kp.total_ms, "bytes": kp.bytes, "flops": kp.flops}
+        return {"launches": kp.launches, "total_ms": kp.total_ms, "bytes": kp.bytes, "flops": kp.flops,
+                "units": kp.units}
 
     def limits(self) -> dict:
         """Coordinate-descent size limits: cov_max, cd_helpers and the resident workgroup count."""

@@ -114,7 +114,7 @@ void prof_mark(bl_ctx ctx, int slot) {
     if (ctx->prof) (void)hipEventRecord(ctx->ev[slot], ctx->stream);
 }
 // after the stream has been synchronized: add the pair (slot, slot+1) to kernel `which`
-void prof_add(bl_ctx ctx, int slot, int which, double bytes, double flops) {
+void prof_add(bl_ctx ctx, int slot, int which, double bytes, double flops, double units) {
     if (!ctx->prof) return;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, ctx->ev[slot], ctx->ev[slot + 1]) == hipSuccess) {
@@ -122,6 +122,7 @@ void prof_add(bl_ctx ctx, int slot, int which, double bytes, double flops) {
         ctx->kp[which].total_ms += ms;
         ctx->kp[which].bytes += bytes;
         ctx->kp[which].flops += flops;
+        ctx->kp[which].units += units;
     }
 }
 
@@ -357,7 +358,7 @@ bl_status bl_profile(bl_ctx ctx, int enable) {
             if (!e) HIPCHK(hipEventCreate(&e));
     }
     ctx->prof = enable != 0;
-    for (auto& k : ctx->kp) k = bl_kernel_profile{0, 0.0, 0.0, 0.0};
+    for (auto& k : ctx->kp) k = bl_kernel_profile{0, 0.0, 0.0, 0.0, 0.0};
     return BL_OK;
 }
 
@@ -786,7 +787,7 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
     prof_add(ctx, 0, BL_PROF_COLSTATS, (double)p * col_bytes);
     // the set-up scans are FP64 scans; in the precision form they are kept apart from its BF16 check scans
     const int setup_slot = lowp ? BL_PROF_SETUP : BL_PROF_SCAN;
-    prof_add(ctx, 2, setup_slot, (double)p * col_bytes + nt * 8.0);
+    prof_add(ctx, 2, setup_slot, (double)p * col_bytes + nt * 8.0, 0.0, (double)p);
     const double ybar = ctx->sc_host->y_mean, yy = ctx->sc_host->yy, lmax = ctx->sc_host->lmax;
     const int64_t jstar = ctx->sc_host->jstar;
     if (!std::isfinite(ybar) || !std::isfinite(yy)) return fail(ctx, BL_ERR_INVALID, "y has NaN or Inf");
@@ -809,7 +810,7 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         HIPCHK(launch_scan(m, sa, st));
         prof_mark(ctx, 3);
         HIPCHK(hipStreamSynchronize(st));
-        prof_add(ctx, 2, setup_slot, (double)p * col_bytes + nt * 8.0);
+        prof_add(ctx, 2, setup_slot, (double)p * col_bytes + nt * 8.0, 0.0, (double)p);
     }
     std::vector<double> lam(K);
     if (opts->lambda) {
@@ -1006,13 +1007,15 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
             HIPCHK(hipStreamSynchronize(st));
             const RoundInfo ri = ctx->sc_host->round;
             if (ctx->last_residual) {
-                prof_add(ctx, 0, BL_PROF_CD, (double)ri.sweeps * ri.cd_len * col_bytes);
+                prof_add(ctx, 0, BL_PROF_CD, (double)ri.sweeps * ri.cd_len * col_bytes, 0.0,
+                         (double)ri.sweeps * ri.cd_len);
             } else {
-                prof_add(ctx, 0, BL_PROF_CD, (double)ri.sweeps * (double)m_len * (double)m_len * 8.0);
+                prof_add(ctx, 0, BL_PROF_CD, (double)ri.sweeps * (double)m_len * (double)m_len * 8.0, 0.0,
+                         (double)ri.sweeps * (double)m_len);
                 prof_add(ctx, 4, BL_PROF_GRAM, ctx->pend_gram_bytes);
                 prof_add(ctx, 6, BL_PROF_RUPDATE, ctx->pend_ru_bytes);
             }
-            prof_add(ctx, 2, BL_PROF_SCAN, (double)ri.scan_len * col_bytes + nt * 8.0);
+            prof_add(ctx, 2, BL_PROF_SCAN, (double)ri.scan_len * col_bytes + nt * 8.0, 0.0, (double)ri.scan_len);
             if (lowp) {
                 const int64_t nb_ = ctx->sc_host->stage;
                 recheck_total += nb_;

@@ -366,12 +366,15 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
             HIPCHK(hipMemcpyAsync(&hp->lenT, lenT, 8, hipMemcpyDeviceToHost, st));
             if ((s = read_bs())) return s;
             prof_add(ctx, 4, BL_PROF_GRAM, (double)max_N * (double)max_P * nt * es);
-            double cd_bytes = 0.0;
+            double cd_bytes = 0.0, cd_updates = 0.0;
             for (int b = 0; b < NB; ++b)
-                if (act[b]) cd_bytes += (double)hp->bs[b].sweeps * hp->lens[b] * hp->lens[b] * 8.0;
-            prof_add(ctx, 6, BL_PROF_CD, cd_bytes);
+                if (act[b]) {
+                    cd_bytes += (double)hp->bs[b].sweeps * hp->lens[b] * hp->lens[b] * 8.0;
+                    cd_updates += (double)hp->bs[b].sweeps * hp->lens[b];
+                }
+            prof_add(ctx, 6, BL_PROF_CD, cd_bytes, 0.0, cd_updates);
             prof_add(ctx, 2, BL_PROF_BSCAN, (double)hp->lenT * nt * es + (double)nt * NB * 8.0,
-                     2.0 * hp->lenT * nt * NB);
+                     2.0 * hp->lenT * nt * NB, (double)hp->lenT);
             bool any = false;
             for (int b = 0; b < NB; ++b) {
                 if (!act[b]) continue;
