@@ -237,3 +237,12 @@ def make(rec: Recipe | str, **scale) -> Problem:
     y = np.stack([response(rec, Xt, t) for t in range(rec.nresp)])
     masks = cv_row_masks(rec) if rec.nsub > 1 else None
     return Problem(rec, Xt, y, masks)
+
+
+def cv_folds(n: int, nfolds: int, seed: int) -> np.ndarray:
+    """Fold of each of n rows (int32 in 0..nfolds-1): a seeded permutation cut into nfolds nearly equal parts."""
+    perm = np.random.default_rng([seed, 17]).permutation(n)
+    fold = np.empty(n, dtype=np.int32)
+    for f, part in enumerate(np.array_split(perm, nfolds)):
+        fold[part] = f
+    return fold

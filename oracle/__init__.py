@@ -63,7 +63,7 @@ def _load():
         L.or_objective.restype = dbl
         L.or_duality_gap.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp, vp, vp, vp, dbl]
         L.or_duality_gap.restype = dbl
-        L.or_fit_path.argtypes = [i64, i64, vp, i64, vp, vp, i64, dbl, i32, dbl, i64,
+        L.or_fit_path.argtypes = [i64, i64, vp, i64, vp, vp, i64, dbl, vp, i32, dbl, i64,
                                   vp, vp, vp, vp, vp, vp, ctypes.POINTER(_Stats), vp]
         L.or_fit_path.restype = i32
         L.or_mlp_forward.argtypes = [i64, i64, vp, vp, vp]
@@ -243,8 +243,15 @@ class Path:
 SCREEN_NONE, SCREEN_SSR, SCREEN_ACTIVE = 0, 1, 2
 
 
-def fit_path(Xt, y, K=100, ratio=0.1, screen=SCREEN_SSR, tol=1e-13, max_sweeps=100000, mask=None) -> Path:
+def fit_path(Xt, y, K=100, ratio=0.1, screen=SCREEN_SSR, tol=1e-13, max_sweeps=100000, mask=None,
+             lambdas=None) -> Path:
+    """The path over the geometric grid from lambda_max, or over the decreasing grid `lambdas` (K values)."""
     Xt, ld = _design(Xt)
+    lam_in = None
+    if lambdas is not None:
+        lam_in = _f64(lambdas)
+        if lam_in.size != K or np.any(np.diff(lam_in) > 0) or np.any(lam_in <= 0):
+            raise ValueError("lambdas must hold K positive non-increasing values")
     p, n_total = Xt.shape
     m = _mask(mask, n_total)
     y = _f64(y)
@@ -257,7 +264,8 @@ def fit_path(Xt, y, K=100, ratio=0.1, screen=SCREEN_SSR, tol=1e-13, max_sweeps=1
     arr.update({k: np.zeros(K) for k in ("rss", "obj", "gap")})
     st = _Stats(**{k: v.ctypes.data for k, v in arr.items()})
     k_done = ctypes.c_int64()
-    rc = _load().or_fit_path(n_total, p, _ptr(Xt), ld, _ptr(m), _ptr(y), K, ratio, screen, tol, max_sweeps,
+    rc = _load().or_fit_path(n_total, p, _ptr(Xt), ld, _ptr(m), _ptr(y), K, ratio, _ptr(lam_in), screen, tol,
+                             max_sweeps,
                              _ptr(c), _ptr(s), _ptr(keep), _ptr(lam), _ptr(beta), ctypes.addressof(ybar),
                              ctypes.byref(st), ctypes.addressof(k_done))
     if rc == 2:
@@ -285,3 +293,61 @@ def mlp_loss_grad(feat, label, params, H):
     grad = np.empty_like(params)
     loss = _load().or_mlp_loss_grad(feat.shape[0], H, _ptr(feat), _ptr(label), _ptr(params), _ptr(grad))
     return loss, grad
+
+
+# ---- cross-validation (Section 3.1.2; Section 5.2 shows its curve, lambda.min and the error there) ----
+
+@dataclass
+class CV:
+    lam: np.ndarray        # (K,) the full-data grid every fold is fitted on
+    pred: np.ndarray       # (K, n_total) prediction of each row by the model of its own fold (rows in no fold: 0)
+    loss: np.ndarray       # (K, N) squared errors of the N rows that belong to a fold, in row order
+    cve: np.ndarray        # (K,) mean of loss over the N rows
+    cvse: np.ndarray       # (K,) standard error of that mean
+    fold_err: np.ndarray   # (nfolds, K) mean squared error over the rows of each fold
+    k_min: int
+    k_1se: int
+    paths: list            # the fold paths (Path)
+
+
+def cv_summary(loss):
+    """cve = mean over rows, cvse = sample SD over rows / sqrt(N), k_min = first smallest cve, k_1se = the
+    smallest k (largest lambda) with cve[k] <= cve[k_min] + cvse[k_min]."""
+    loss = np.asarray(loss, dtype=np.float64)
+    N = loss.shape[1]
+    cve = loss.mean(axis=1)
+    cvse = loss.std(axis=1, ddof=1) / np.sqrt(N) if N > 1 else np.zeros(loss.shape[0])
+    k_min = int(np.argmin(cve))
+    k_1se = int(np.flatnonzero(cve <= cve[k_min] + cvse[k_min])[0])
+    return cve, cvse, k_min, k_1se
+
+
+def cv_path(Xt, y, fold, nfolds, K=100, ratio=0.1, tol=1e-13) -> CV:
+    """K-fold cross-validation of the lasso path.  The grid comes from the full data's lambda_max; fold f is
+    fitted on the rows with fold != f (a row mask, X is not copied) over that grid and predicts the rows with
+    fold == f on the original scale: y^_i = intercept + sum_j x_ij beta_j / s_j.  Rows with fold < 0 are in
+    no fold (neither fitted nor predicted)."""
+    Xt, ld = _design(Xt)
+    p, n_total = Xt.shape
+    fold = np.asarray(fold, dtype=np.int64)
+    y = _f64(y)
+    inrows = fold >= 0
+    c, s, keep, n = standardize(Xt, inrows.astype(np.uint8))
+    ybar, yt, a, lmax, js = lambda_max(Xt, c, s, keep, y, inrows.astype(np.uint8))
+    lam = lambda_grid(lmax, ratio, K)
+    pred = np.zeros((K, n_total))
+    fold_err = np.zeros((nfolds, K))
+    paths = []
+    for f in range(nfolds):
+        train = (inrows & (fold != f)).astype(np.uint8)
+        test = fold == f
+        path = fit_path(Xt, y, K=K, ratio=ratio, tol=tol, mask=train, lambdas=lam)
+        if path.k_done != K:
+            raise RuntimeError(f"fold {f}: the oracle path stopped at {path.k_done}")
+        icpt, b = path.original_scale()
+        pred[:, test] = icpt[:, None] + b @ Xt[:, test]
+        fold_err[f] = np.mean((y[test][None, :] - pred[:, test]) ** 2, axis=1)
+        paths.append(path)
+    loss = (y[inrows][None, :] - pred[:, inrows]) ** 2
+    cve, cvse, k_min, k_1se = cv_summary(loss)
+    return CV(lam, pred, loss, cve, cvse, fold_err, k_min, k_1se, paths)

@@ -304,7 +304,8 @@ double or_duality_gap(int64_t n_total, int64_t p, const double* X, int64_t ldx, 
 }
 
 /*
- * The lasso path over the geometric grid with warm starts, screened by the
+ * The lasso path over the geometric grid (or the decreasing grid lam_in when it is not NULL: cross-
+ * validation fits every fold on the full-data grid) with warm starts, screened by the
  * sequential strong rule (or not screened) and repaired by a post-convergence
  * check over every kept feature:
  *   E_k = {j : beta_j != 0} u {j : |z_j(prev)| >= 2 l_k - l_{k-1}}
@@ -317,9 +318,9 @@ double or_duality_gap(int64_t n_total, int64_t p, const double* X, int64_t ldx, 
  * CD did not converge (k_done then counts the finished lambdas), 2 on bad input.
  */
 int or_fit_path(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
-                const double* y, int64_t K, double ratio, int screen, double tol, int64_t max_sweeps,
-                double* c, double* s, uint8_t* keep, double* lambda, double* beta, double* ybar,
-                or_path_stats* st, int64_t* k_done) {
+                const double* y, int64_t K, double ratio, const double* lam_in, int screen, double tol,
+                int64_t max_sweeps, double* c, double* s, uint8_t* keep, double* lambda, double* beta,
+                double* ybar, or_path_stats* st, int64_t* k_done) {
     *k_done = 0;
     if (p <= 0 || K <= 0) return 2;
     int64_t n = or_standardize(n_total, p, X, ldx, mask, c, s, keep);
@@ -347,15 +348,20 @@ int or_fit_path(int64_t n_total, int64_t p, const double* X, int64_t ldx, const 
     for (int64_t i = 0; i < n_total; ++i) v += ytilde[i] * ytilde[i];
     v /= (double)n;
     double sgn = a[jstar] >= 0 ? 1.0 : -1.0;
-    or_lambda_grid(lmax, ratio, K, lambda);
+    if (lam_in)
+        memcpy(lambda, lam_in, sizeof(double) * (size_t)K);
+    else
+        or_lambda_grid(lmax, ratio, K, lambda);
     memcpy(r, ytilde, sizeof(double) * (size_t)n_total);
     memcpy(zprev, a, sizeof(double) * (size_t)p);
 
     for (int64_t k = 0; k < K; ++k) {
         double lk = lambda[k];
         int64_t sweeps_k = 0, viol_k = 0, rounds_k = 0, nE = 0;
-        if (k > 0) {
-            double thr = 2.0 * lk - lambda[k - 1];
+        /* beta = 0 solves every lambda >= lambda_max; below it, warm start from the previous lambda
+         * (lambda_max, with z = a, before the first point of the grid) */
+        if (lk < lmax) {
+            double thr = 2.0 * lk - (k > 0 ? lambda[k - 1] : lmax);
             for (int64_t j = 0; j < p; ++j) {
                 if (!keep[j]) {
                     inE[j] = 0;

@@ -64,7 +64,8 @@ typedef struct {
 enum { OR_SCREEN_NONE = 0, OR_SCREEN_SSR = 1, OR_SCREEN_ACTIVE = 2 };
 
 int or_fit_path(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
-                const double* y, int64_t K, double ratio, int screen, double tol, int64_t max_sweeps,
+                const double* y, int64_t K, double ratio, const double* lam_in, int screen, double tol,
+                int64_t max_sweeps,
                 double* c, double* s, uint8_t* keep, double* lambda, double* beta /* p x K */,
                 double* ybar, or_path_stats* st, int64_t* k_done);
 

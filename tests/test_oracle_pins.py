@@ -532,3 +532,103 @@ def test_bedpp_discards_exactly_the_edpp_ball_set(seed, design):
         assert np.array_equal(d[~undecided], ball[~undecided]), f"lambda/lambda_max = {frac:.3f}"
         total += d.sum()
     assert total > 0
+
+
+# ---------------------------------------------------------------------------------------------
+# user lambda grids and cross-validation (Section 3.1.2: folds are row subsets of one X; Section 5.2:
+# the cross-validation curve, lambda.min and the error there)
+# ---------------------------------------------------------------------------------------------
+
+def test_user_grid_equal_to_the_geometric_grid_gives_the_same_path():
+    prob = datagen.make("c1", n=120, p=260)
+    a = oracle.fit_path(prob.Xt, prob.y[0], K=20, ratio=0.05)
+    b = oracle.fit_path(prob.Xt, prob.y[0], K=20, ratio=0.05, lambdas=a.lam)
+    np.testing.assert_array_equal(a.beta, b.beta)
+    np.testing.assert_array_equal(a.lam, b.lam)
+
+
+def test_user_grid_above_and_below_lambda_max_brute_force():
+    n, p = 40, 8
+    rng = np.random.default_rng(61)
+    Xt = rng.normal(size=(p, n)) + rng.normal(size=(p, 1))
+    mask = np.ones(n, dtype=np.uint8)
+    mask[rng.choice(n, 7, replace=False)] = 0
+    y = 1.2 * Xt[1] - 0.8 * Xt[6] + rng.normal(size=n)
+    c, s, keep, nn = oracle.standardize(Xt, mask)
+    ybar, yt, a, lmax, js = oracle.lambda_max(Xt, c, s, keep, y, mask)
+    lams = lmax * np.array([1.7, 1.0, 0.62, 0.31, 0.08])
+    path = oracle.fit_path(Xt, y, K=5, mask=mask, lambdas=lams)
+    Xtil, _, _ = std_numpy(Xt, mask)
+    ym = y[mask.astype(bool)]
+    assert np.all(path.beta[:2] == 0.0) and path.sweeps[0] == 0
+    for k in (2, 3, 4):
+        sols = brute_force_lasso(Xtil, ym - ym.mean(), lams[k])
+        assert len(sols) == 1
+        np.testing.assert_allclose(path.beta[k], sols[0], atol=1e-10)
+
+
+def test_cv_summary_on_a_hand_worked_example():
+    # rows of the loss matrix and what they give, worked by hand:
+    #   k=0: 1, 1, 1, 1.8  -> mean 1.2, deviations -.2 -.2 -.2 .6, sample variance .48/3 = .16, SE .4/2 = .2
+    #   k=1: 0, 2, 0, 2    -> mean 1.0, sample variance 4/3, SE sqrt(4/3)/2 = sqrt(1/3)
+    #   k=2: 1.1 (x4)      -> mean 1.1, SE 0
+    # smallest mean at k=1; 1.0 + sqrt(1/3) = 1.577 admits k=0 (1.2), the largest lambda
+    loss = np.array([[1, 1, 1, 1.8], [0, 2, 0, 2], [1.1, 1.1, 1.1, 1.1]])
+    cve, cvse, k_min, k_1se = oracle.cv_summary(loss)
+    np.testing.assert_allclose(cve, [1.2, 1.0, 1.1], rtol=1e-15)
+    np.testing.assert_allclose(cvse, [0.2, np.sqrt(1.0 / 3.0), 0.0], rtol=1e-14, atol=1e-15)
+    assert k_min == 1 and k_1se == 0
+    # ties: the first smallest
+    cve, cvse, k_min, k_1se = oracle.cv_summary(np.array([[2.0, 2.0], [1.0, 1.0], [1.0, 1.0]]))
+    assert k_min == 1 and k_1se == 1
+
+
+def test_cv_single_feature_closed_form():
+    """p = 1: every fold's coefficient is the soft threshold of its correlation (unit curvature), so the
+    held-out predictions, their squared errors and the CV curve follow in closed form."""
+    rng = np.random.default_rng(71)
+    n = 53
+    x = rng.normal(2.0, 1.5, size=n)
+    y = 0.7 * x + rng.normal(size=n)
+    fold = datagen.cv_folds(n, 5, 3)
+    K, ratio = 9, 0.05
+    cv = oracle.cv_path(x[None, :], y, fold, 5, K=K, ratio=ratio)
+    # full-data grid
+    xc = x - x.mean()
+    lmax = abs(xc @ (y - y.mean())) / n / x.std()
+    np.testing.assert_allclose(cv.lam, lmax * ratio ** (np.arange(K) / (K - 1)), rtol=1e-13)
+    pred = np.zeros((K, n))
+    for f in range(5):
+        tr = fold != f
+        xt, ytr = x[tr], y[tr]
+        c, sd = xt.mean(), xt.std()
+        a = ((xt - c) / sd) @ (ytr - ytr.mean()) / tr.sum()
+        for k, lam in enumerate(cv.lam):
+            slope = soft(a, lam) / sd
+            pred[k, ~tr] = ytr.mean() + slope * (x[~tr] - c)
+    np.testing.assert_allclose(cv.pred, pred, rtol=1e-11, atol=1e-11)
+    loss = (y[None, :] - pred) ** 2
+    np.testing.assert_allclose(cv.cve, loss.mean(axis=1), rtol=1e-11)
+
+
+def test_cv_brute_force_folds():
+    """p = 7: each fold's solution at every lambda of the full-data grid equals the unique sign pattern
+    meeting the optimality conditions on the fold's training rows."""
+    n, p = 48, 7
+    rng = np.random.default_rng(81)
+    Xt = datagen.genotype_u8(81, n, p).astype(np.float64)
+    y = Xt[2] - 0.6 * Xt[5] + rng.normal(size=n)
+    fold = datagen.cv_folds(n, 4, 9)
+    cv = oracle.cv_path(Xt, y, fold, 4, K=6, ratio=0.05)
+    for f in range(4):
+        tr = (fold != f).astype(np.uint8)
+        Xtil, c, s = std_numpy(Xt, tr)
+        ym = y[tr.astype(bool)]
+        for k in (2, 5):
+            sols = brute_force_lasso(Xtil, ym - ym.mean(), cv.lam[k])
+            assert len(sols) == 1
+            np.testing.assert_allclose(cv.paths[f].beta[k], sols[0], atol=1e-10)
+            b = sols[0] / s
+            te = fold == f
+            np.testing.assert_allclose(cv.pred[k, te], ym.mean() + (Xt[:, te].T - c) @ b, atol=1e-9)
+    assert 0 <= cv.k_1se <= cv.k_min < 6
