@@ -193,6 +193,22 @@ bl_status bl_kkt_check(bl_ctx ctx, const bl_matrix* X, const double* center, con
                        const double* r, double lambda, const int32_t* check_set, int64_t len,
                        const uint8_t* exclude, double* z, int32_t* violators, int64_t* n_viol);
 
+/*
+ * bl_kkt_check for callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same arguments, semantics and outputs as
+ * bl_kkt_check, with no allocation of any kind.  Its working memory (violator marks, compaction counts,
+ * lengths) is one fixed device array of BL_NOALLOC_BYTES bytes per GPU that the library holds until the
+ * process ends; its device address is looked up when a context is created on that GPU.
+ * p <= BL_NOALLOC_MAX_P (BL_ERR_UNSUPPORTED beyond).  Every call on one GPU shares that array and it
+ * keeps the last call's contents (each call clears what it needs): calls that overlap on one GPU, from two
+ * contexts or two host threads, race and must be serialized by the caller.
+ */
+#define BL_NOALLOC_MAX_P 4194304
+#define BL_NOALLOC_BYTES (BL_NOALLOC_MAX_P + 8192 + 256)
+bl_status bl_kkt_check_noalloc(bl_ctx ctx, const bl_matrix* X, const double* center, const double* scale,
+                               const double* r, double lambda, const int32_t* check_set, int64_t len,
+                               const uint8_t* exclude, double* z, int32_t* violators, int64_t* n_viol);
+
 /* Arithmetic of the check scans. */
 typedef enum {
     BL_PREC_FP64 = 0,      /* FP64 vector scan (any X type)                                          */

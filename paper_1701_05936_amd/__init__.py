@@ -32,7 +32,8 @@ _STATUS_NAMES = {0: "BL_OK", 1: "BL_ERR_INVALID", 2: "BL_ERR_NOMEM", 3: "BL_ERR_
 EXPORTS = ("bl_create", "bl_destroy", "bl_last_error", "bl_device_info", "bl_standardize", "bl_lambda_max",
            "bl_bedpp_setup", "bl_screen", "bl_cd_solve", "bl_kkt_check", "bl_scan", "bl_fit_path",
            "bl_fit_path_batch", "bl_mlp_forward", "bl_mlp_loss_grad", "bl_mlp_train", "bl_profile", "bl_profile_get",
-           "bl_get_limits", "bl_set_limits")
+           "bl_get_limits", "bl_set_limits", "bl_kkt_check_noalloc")
+NOALLOC_MAX_P = 4194304
 MLP_HIDDEN = 64
 MLP_NPARAMS = MLP_HIDDEN * MLP_HIDDEN + 7 * MLP_HIDDEN + 1
 PROF_SCAN, PROF_CD, PROF_COLSTATS, PROF_GRAM, PROF_RUPDATE, PROF_RECHECK, PROF_BSCAN, PROF_SETUP = range(8)
@@ -133,6 +134,7 @@ def load_library(path: str = LIB_PATH):
     L.bl_screen.argtypes = [vp, P(_ScreenState), dbl, dbl, vp, vp, vp, P(i64), P(i64)]
     L.bl_cd_solve.argtypes = [vp, P(_Matrix), vp, vp, dbl, vp, i64, vp, vp, dbl, i32, P(i32)]
     L.bl_kkt_check.argtypes = [vp, P(_Matrix), vp, vp, vp, dbl, vp, i64, vp, vp, vp, P(i64)]
+    L.bl_kkt_check_noalloc.argtypes = [vp, P(_Matrix), vp, vp, vp, dbl, vp, i64, vp, vp, vp, P(i64)]
     L.bl_scan.argtypes = [vp, P(_Matrix), vp, vp, vp, vp, i64, i32, vp, vp]
     L.bl_fit_path.argtypes = [vp, P(_Matrix), vp, P(_PathOpts), P(_PathResult)]
     L.bl_fit_path_batch.argtypes = [vp, P(_Matrix), P(_Batch), P(_PathOpts), P(_BatchResult)]
@@ -320,6 +322,21 @@ def kkt_check(ctx: Context, Xt, c, s, r, lam, check_set, exclude=None, z=None, r
                                            _ptr(check_set) if check_set.numel() else None, check_set.numel(),
                                            _ptr(exclude), _ptr(z), _ptr(viol), ctypes.byref(nv)))
     return z, viol[: nv.value]
+
+
+def kkt_check_noalloc(ctx: Context, Xt, c, s, r, lam, check_set, z, viol, exclude=None, row_mask=None,
+                      n_total=None):
+    """The check through bl_kkt_check_noalloc, which allocates nothing: z (float64 [p]) and viol (int32, at
+    least max(1, len(check_set)) entries) are the caller's.  Returns the number of violators."""
+    M = matrix(Xt, n_total, row_mask)
+    if check_set.dtype != torch.int32 or viol.dtype != torch.int32 or viol.numel() < max(1, check_set.numel()):
+        raise ValueError("check_set and viol must be int32, viol with room for every checked column")
+    nv = ctypes.c_int64()
+    ctx._check(load_library().bl_kkt_check_noalloc(ctx.handle, ctypes.byref(M), _ptr(c), _ptr(s), _ptr(r), lam,
+                                                   _ptr(check_set) if check_set.numel() else None,
+                                                   check_set.numel(), _ptr(exclude), _ptr(z), _ptr(viol),
+                                                   ctypes.byref(nv)))
+    return nv.value
 
 
 def scan(ctx: Context, Xt, c, s, r, cols, precision=PREC_FP64, row_mask=None, n_total=None, want_err=False):

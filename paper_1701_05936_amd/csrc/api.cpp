@@ -305,6 +305,8 @@ bl_status bl_create(bl_ctx* out, int device, void* hip_stream) {
     c->cd_resident = gcd_multi_resident();
     c->cd_helpers = std::min(255, std::max(0, c->cd_resident - 1));
     c->cov_max = gram_cd_max();
+    // this GPU's copy of the allocation-free check's array (an error surfaces when that entry point is called)
+    (void)noalloc_setup(device);
     *out = c;
     return BL_OK;
 }

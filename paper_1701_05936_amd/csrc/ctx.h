@@ -68,6 +68,7 @@ int elem_bytes(int xtype);
 bl_status check_ctx(bl_ctx ctx);
 bl_status check_matrix(bl_ctx ctx, const bl_matrix* X, blk::Mat* m);
 void prof_mark(bl_ctx ctx, int slot);
+hipError_t noalloc_setup(int device);   // device address of the allocation-free check's array (noalloc.hip)
 void prof_add(bl_ctx ctx, int slot, int which, double bytes, double flops = 0.0, double units = 0.0);
 
 }  // namespace blapi
