@@ -323,8 +323,10 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
  * lockstep; every pass over X (column statistics, lambda_max and BEDPP products,
  * post-convergence scans) serves all problems at once on FP64 matrix cores.  The screening
  * kernels of a lambda step are captured once per call in a HIP graph and replayed.
- * Options as bl_fit_path (opts->lambda must be NULL, precision FP64); X->row_mask
- * must be NULL; X is f32 or f64.
+ * Options as bl_fit_path (precision FP64, no learned rule, no resume); X->row_mask must be NULL; X is
+ * f32 or f64.  opts->lambda NULL gives each problem its own grid from its own lambda_max; a host grid
+ * (K decreasing values) is shared by every problem, as cross-validation needs (Section 3.1.2), and is
+ * solved from its first point (beta = 0 where that point is at or above the problem's lambda_max).
  */
 typedef struct {
     int32_t nprob;             /* 1..64                                                                */
@@ -357,6 +359,47 @@ typedef struct {
 
 bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_batch* batch, const bl_path_opts* opts,
                             bl_batch_result* res);
+
+/*
+ * K-fold cross-validation of the lasso path (Section 3.1.2: every fold is a row subset of the one X, chosen
+ * by a mask, never a copy; Section 5.2: the cross-validation curve with standard errors and the lambda at
+ * its minimum).  The grid comes from the full data, the rows with fold >= 0: their path is fitted first
+ * (bl_fit_path, written to res->beta when not NULL).  Fold f is then fitted on the rows with fold >= 0
+ * and fold != f over that same grid, all folds in one bl_fit_path_batch call, and predicts its held-out
+ * rows (fold == f) on the original scale:
+ *   y^_i(lambda_k) = intercept_fk + sum_j x_ij beta_fkj / s_fj     (s_fj: column SD over fold f's rows)
+ *   loss_ik = (y_i - y^_i(lambda_k))^2 over the N rows with fold >= 0
+ *   cve_k = mean_i loss_ik,  cvse_k = sqrt(sum_i (loss_ik - cve_k)^2 / (N - 1)) / sqrt(N)
+ *   fold_err[f*K + k] = mean of loss_ik over the rows of fold f
+ *   k_min = the first k with the smallest cve_k (lambda.min); k_1se = the smallest k (largest lambda)
+ *           with cve_k <= cve_kmin + cvse_kmin.
+ * X: f32 or f64, row_mask NULL.  Options as bl_fit_path_batch (opts->lambda NULL: the grid is
+ * lambda_max ratio^(k/(K-1)) of the full data; else that host grid).  Every fold must hold a row.
+ */
+typedef struct {
+    int32_t nfolds;            /* 2..64                                                                 */
+    const int32_t* fold;       /* DEVICE [n_total]: fold of row i in 0..nfolds-1, or -1 (row left out)  */
+    const double* y;           /* DEVICE [n_total]                                                      */
+} bl_cv;
+
+typedef struct {
+    double* beta;              /* DEVICE [K x p] or NULL: the full-data path, standardized scale          */
+    double* fold_beta;         /* DEVICE [nfolds x K x p] or NULL: each fold's path on its own scale      */
+    double* pred;              /* DEVICE [K x n_total] or NULL: held-out predictions (0 where fold = -1)  */
+    double* lambda;            /* host [K]                                                               */
+    double* cve;               /* host [K]                                                               */
+    double* cvse;              /* host [K]                                                               */
+    double* fold_err;          /* host [nfolds x K]                                                      */
+    int32_t k_min;             /* out */
+    int32_t k_1se;             /* out */
+    double lambda_min;         /* out */
+    double lambda_1se;         /* out */
+    int64_t n_rows;            /* out: N                                                                 */
+    int32_t k_done;            /* out: K on success                                                      */
+    double time_ms;            /* out                                                                    */
+} bl_cv_result;
+
+bl_status bl_cv_fit(bl_ctx ctx, const bl_matrix* X, const bl_cv* cv, const bl_path_opts* opts, bl_cv_result* res);
 
 /*
  * Screening network of the learned form (the paper has none; it stands beside the strong rule,

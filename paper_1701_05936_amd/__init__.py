@@ -32,7 +32,7 @@ _STATUS_NAMES = {0: "BL_OK", 1: "BL_ERR_INVALID", 2: "BL_ERR_NOMEM", 3: "BL_ERR_
 EXPORTS = ("bl_create", "bl_destroy", "bl_last_error", "bl_device_info", "bl_standardize", "bl_lambda_max",
            "bl_bedpp_setup", "bl_screen", "bl_cd_solve", "bl_kkt_check", "bl_scan", "bl_fit_path",
            "bl_fit_path_batch", "bl_mlp_forward", "bl_mlp_loss_grad", "bl_mlp_train", "bl_profile", "bl_profile_get",
-           "bl_get_limits", "bl_set_limits", "bl_kkt_check_noalloc")
+           "bl_get_limits", "bl_set_limits", "bl_kkt_check_noalloc", "bl_cv_fit")
 NOALLOC_MAX_P = 4194304
 MLP_HIDDEN = 64
 MLP_NPARAMS = MLP_HIDDEN * MLP_HIDDEN + 7 * MLP_HIDDEN + 1
@@ -68,6 +68,18 @@ class _PathOpts(ctypes.Structure):
                 ("mlp_tau", ctypes.c_double), ("rec_feat", ctypes.c_void_p), ("rec_label", ctypes.c_void_p),
                 ("rec_cap", ctypes.c_int64), ("k_start", ctypes.c_int32), ("beta_init", ctypes.c_void_p),
                 ("r_init", ctypes.c_void_p), ("r_out", ctypes.c_void_p)]
+
+
+class _Cv(ctypes.Structure):
+    _fields_ = [("nfolds", ctypes.c_int32), ("fold", ctypes.c_void_p), ("y", ctypes.c_void_p)]
+
+
+class _CvResult(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_void_p), ("fold_beta", ctypes.c_void_p), ("pred", ctypes.c_void_p),
+                ("lambda_", ctypes.c_void_p), ("cve", ctypes.c_void_p), ("cvse", ctypes.c_void_p),
+                ("fold_err", ctypes.c_void_p), ("k_min", ctypes.c_int32), ("k_1se", ctypes.c_int32),
+                ("lambda_min", ctypes.c_double), ("lambda_1se", ctypes.c_double), ("n_rows", ctypes.c_int64),
+                ("k_done", ctypes.c_int32), ("time_ms", ctypes.c_double)]
 
 
 class _Limits(ctypes.Structure):
@@ -143,6 +155,7 @@ def load_library(path: str = LIB_PATH):
     L.bl_mlp_train.argtypes = [vp, vp, vp, i64, vp, P(_MlpTrainOpts), P(_MlpTrainResult)]
     L.bl_profile.argtypes = [vp, ctypes.c_int]
     L.bl_profile_get.argtypes = [vp, ctypes.c_int, P(_KernelProfile)]
+    L.bl_cv_fit.argtypes = [vp, P(_Matrix), P(_Cv), P(_PathOpts), P(_CvResult)]
     L.bl_get_limits.argtypes = [vp, P(_Limits)]
     L.bl_set_limits.argtypes = [vp, P(_Limits)]
     for name in EXPORTS:
@@ -459,7 +472,7 @@ BATCH_EAGER = 1
 
 def fit_path_batch(ctx: Context, Xt, Y, masks=None, nlambda=100, lambda_min_ratio=0.1, rule=SCREEN_SSR_BEDPP,
                    tol=1e-8, max_sweeps=100000, max_rounds=100, n_total=None, want_beta=True,
-                   raise_on_error=True, eager=False) -> BatchResult:
+                   raise_on_error=True, eager=False, lambdas=None) -> BatchResult:
     """Batched form: B <= 64 problems over one X.  Y (B, n_total) float64 device; masks (B, n_total) uint8
     device or None (all rows in every problem)."""
     M = matrix(Xt, n_total, None)
@@ -477,8 +490,12 @@ def fit_path_batch(ctx: Context, Xt, Y, masks=None, nlambda=100, lambda_min_rati
     host.update({k: np.zeros((B, K), dtype=np.int32) for k in ("sweeps", "rounds")})
     host.update({k: np.zeros((B, K), dtype=np.int64) for k in ("n_active", "n_strong", "n_safe", "n_viol")})
     bt = _Batch(B, _ptr(Y), _ptr(masks), BATCH_EAGER if eager else 0)
-    opts = _PathOpts(K, float(lambda_min_ratio), None, int(rule), float(tol), int(max_sweeps), int(max_rounds),
-                     PREC_FP64)
+    lam_in = None
+    if lambdas is not None:
+        lam_in = np.ascontiguousarray(lambdas, dtype=np.float64)
+        assert lam_in.size == K
+    opts = _PathOpts(K, float(lambda_min_ratio), lam_in.ctypes.data if lam_in is not None else None, int(rule),
+                     float(tol), int(max_sweeps), int(max_rounds), PREC_FP64)
     res = _BatchResult(_ptr(beta), *[host[k].ctypes.data for k in ("lam", "intercept", "rss", "obj", "sweeps",
                                                                   "rounds", "n_active", "n_strong", "n_safe",
                                                                   "n_viol")], 0, 0.0, 0)
@@ -490,6 +507,54 @@ def fit_path_batch(ctx: Context, Xt, Y, masks=None, nlambda=100, lambda_min_rati
     return BatchResult(host["lam"], beta, host["intercept"], host["rss"], host["obj"], host["sweeps"],
                        host["rounds"], host["n_active"], host["n_strong"], host["n_safe"], host["n_viol"],
                        res.k_done, res.time_ms, st, msg, res.scan_cols)
+
+
+@dataclass
+class CVResult:
+    lam: np.ndarray              # (K,) the full-data grid
+    cve: np.ndarray              # (K,) cross-validation error (mean held-out squared error)
+    cvse: np.ndarray             # (K,) its standard error
+    fold_err: np.ndarray         # (nfolds, K)
+    k_min: int
+    k_1se: int
+    lambda_min: float
+    lambda_1se: float
+    n_rows: int
+    beta: torch.Tensor | None    # (K, p) full-data path, standardized scale
+    fold_beta: torch.Tensor | None   # (nfolds, K, p)
+    pred: torch.Tensor | None    # (K, n_total) held-out predictions
+    time_ms: float
+
+
+def cv_fit(ctx: Context, Xt, y, fold, nfolds, nlambda=100, lambda_min_ratio=0.1, lambdas=None,
+           rule=SCREEN_SSR_BEDPP, tol=1e-8, max_sweeps=100000, max_rounds=100, n_total=None, want_beta=True,
+           want_fold_beta=True, want_pred=True) -> CVResult:
+    """K-fold cross-validation (bl_cv_fit).  fold: int32 device [n_total] with values in -1..nfolds-1."""
+    M = matrix(Xt, n_total, None)
+    nt, p, K = M.n_total, M.p, int(nlambda)
+    if fold.dtype != torch.int32 or fold.numel() != nt:
+        raise ValueError("fold must be int32 with n_total entries")
+    if y.dtype != torch.float64 or y.numel() != nt:
+        raise ValueError("y must be float64 with n_total entries")
+    dev = _dev(ctx)
+    beta = torch.empty((K, p), dtype=torch.float64, device=dev) if want_beta else None
+    fbeta = torch.empty((nfolds, K, p), dtype=torch.float64, device=dev) if want_fold_beta else None
+    pred = torch.empty((K, nt), dtype=torch.float64, device=dev) if want_pred else None
+    lam, cve, cvse = np.zeros(K), np.zeros(K), np.zeros(K)
+    ferr = np.zeros((nfolds, K))
+    lam_in = None
+    if lambdas is not None:
+        lam_in = np.ascontiguousarray(lambdas, dtype=np.float64)
+        assert lam_in.size == K
+    opts = _PathOpts(K, float(lambda_min_ratio), lam_in.ctypes.data if lam_in is not None else None, int(rule),
+                     float(tol), int(max_sweeps), int(max_rounds), PREC_FP64)
+    cvs = _Cv(int(nfolds), _ptr(fold), _ptr(y))
+    res = _CvResult(_ptr(beta), _ptr(fbeta), _ptr(pred), lam.ctypes.data, cve.ctypes.data, cvse.ctypes.data,
+                    ferr.ctypes.data)
+    ctx._check(load_library().bl_cv_fit(ctx.handle, ctypes.byref(M), ctypes.byref(cvs), ctypes.byref(opts),
+                                        ctypes.byref(res)))
+    return CVResult(lam, cve, cvse, ferr, res.k_min, res.k_1se, res.lambda_min, res.lambda_1se, res.n_rows, beta,
+                    fbeta, pred, res.time_ms)
 
 
 # ---- screening network of the learned form ----

@@ -39,10 +39,9 @@ def build(force: bool = True, verbose: bool = False) -> str:
     if not force and os.path.exists(LIB):
         return LIB
     os.makedirs(OBJ_DIR, exist_ok=True)
-    sources = [s for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
-    jobs = max(1, min(len(sources), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), sources))
+        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

@@ -114,9 +114,17 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
     if (!bt->Y) return fail(ctx, BL_ERR_INVALID, "Y is NULL");
     const int K = opts->nlambda;
     if (K < 1) return fail(ctx, BL_ERR_INVALID, "nlambda must be >= 1");
-    if (opts->lambda) return fail(ctx, BL_ERR_UNSUPPORTED, "batched form: user lambda grids are not supported");
-    if (K > 1 && !(opts->lambda_min_ratio > 0.0 && opts->lambda_min_ratio < 1.0))
+    const bool user_grid = opts->lambda != nullptr;   // one grid shared by every problem (cross-validation)
+    if (user_grid) {
+        for (int k = 0; k < K; ++k) {
+            if (!(std::isfinite(opts->lambda[k]) && opts->lambda[k] > 0.0))
+                return fail(ctx, BL_ERR_INVALID, "user lambda[%d] must be finite and > 0", k);
+            if (k > 0 && !(opts->lambda[k] <= opts->lambda[k - 1]))
+                return fail(ctx, BL_ERR_INVALID, "user lambda must be non-increasing");
+        }
+    } else if (K > 1 && !(opts->lambda_min_ratio > 0.0 && opts->lambda_min_ratio < 1.0)) {
         return fail(ctx, BL_ERR_INVALID, "lambda_min_ratio must be in (0, 1)");
+    }
     if (opts->rule < BL_SCREEN_NONE || opts->rule > BL_SCREEN_ACTIVE) return fail(ctx, BL_ERR_INVALID, "unknown rule");
     if (opts->rule == BL_SCREEN_LEARNED) return fail(ctx, BL_ERR_UNSUPPORTED, "batched form: no learned rule");
     if (opts->k_start != 0) return fail(ctx, BL_ERR_UNSUPPORTED, "batched form: no resume (k_start must be 0)");
@@ -249,13 +257,15 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
     std::vector<double> lam((size_t)NB * K), lg((size_t)(K + 1) * BNP, 0.0), tg((size_t)K * BNP, 0.0);
     for (int b = 0; b < NB; ++b)
         for (int k = 0; k < K; ++k)
-            lam[(size_t)b * K + k] = K == 1 ? lmax[b] : lmax[b] * std::pow(opts->lambda_min_ratio, (double)k / (K - 1));
+            lam[(size_t)b * K + k] = user_grid ? opts->lambda[k]
+                                   : (K == 1 ? lmax[b] : lmax[b] * std::pow(opts->lambda_min_ratio, (double)k / (K - 1)));
     for (int k = 0; k <= K; ++k)   // row K repeats row K-1: the last step's "next" safe set is its own
         for (int b = 0; b < NB; ++b) {
             lg[(size_t)k * BNP + b] = lam[(size_t)b * K + (k < K ? k : K - 1)];
             if (k == K) continue;
+            // the strong rule's previous lambda before the grid's first point is lambda_max (z there is a)
             tg[(size_t)k * BNP + b] = active_only ? INFINITY
-                                      : (k > 0 ? 2.0 * lam[(size_t)b * K + k] - lam[(size_t)b * K + k - 1] : lam[(size_t)b * K]);
+                                      : 2.0 * lam[(size_t)b * K + k] - (k > 0 ? lam[(size_t)b * K + k - 1] : lmax[b]);
         }
     HIPCHK(hipMemcpyAsync(lamg, lg.data(), lg.size() * 8, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(thrg, tg.data(), tg.size() * 8, hipMemcpyHostToDevice, st));
@@ -268,11 +278,13 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
     std::vector<int32_t> h_sweeps((size_t)NB * K, 0), h_rounds((size_t)NB * K, 0);
     std::vector<int64_t> h_viol((size_t)NB * K, 0);
     int64_t ge_cap = 0;  // per-problem stride of the working-set Gram buffer (elements)
-    // z of every problem at its previous lambda: at step k it is in z1 for odd k, z0 for even k (z at
-    // lambda_max is a, copied to z1 for step 1)
-    HIPCHK(hipMemcpyAsync(z1, a, P8, hipMemcpyDeviceToDevice, st));
-    double* zprev = z1;
-    double* zcur = z0;
+    // z of every problem at its previous lambda: at step k it is in z1 for odd k, z0 for even k.  With the
+    // grid from each problem's lambda_max the path starts at step 1 from z = a (copied to z1); a shared
+    // user grid starts at step 0 (beta = 0 for problems whose lambda_max is at most lambda_0), z = a in z0
+    const int k_first = user_grid ? 0 : 1;
+    double* zprev = k_first ? z1 : z0;
+    double* zcur = k_first ? z0 : z1;
+    HIPCHK(hipMemcpyAsync(zprev, a, P8, hipMemcpyDeviceToDevice, st));
     bl_status final_status = BL_OK;
 
     // Screening of a lambda step: S_k per problem and its size, the scan list (union over problems of
@@ -309,17 +321,18 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
         }
     }
     HIPCHK(hipMemsetAsync(kdev, 0, 8, st));
-    HIPCHK(launch_b_kinc(kdev, st));   // the counter holds the step being screened: 1
+    if (k_first == 1) {
+        HIPCHK(launch_b_kinc(kdev, st));   // the counter holds the step being screened: 1
+        // lambda index 0 is lambda_max of every problem: beta = 0
+        HIPCHK(launch_b_bedpp(p, NB, a, bb, keep, bedpp, bs, lamg, 0, nullptr, safe, st));
+        HIPCHK(launch_b_compact(safe, p, NB, want_all, lsafe, safecnt, cmp, st));
+        HIPCHK(launch_b_record(lE, lens, p, NB, beta, c, sd, bs, lamg, stats, 0, K, safecnt, st));
+        if (res->beta)
+            HIPCHK(hipMemcpy2DAsync(res->beta, (size_t)K * p * 8, beta, p * 8, p * 8, NB, hipMemcpyDeviceToDevice, st));
+        res->k_done = 1;
+    }
 
-    // lambda index 0 is lambda_max of every problem: beta = 0
-    HIPCHK(launch_b_bedpp(p, NB, a, bb, keep, bedpp, bs, lamg, 0, nullptr, safe, st));
-    HIPCHK(launch_b_compact(safe, p, NB, want_all, lsafe, safecnt, cmp, st));
-    HIPCHK(launch_b_record(lE, lens, p, NB, beta, c, sd, bs, lamg, stats, 0, K, safecnt, st));
-    if (res->beta)
-        HIPCHK(hipMemcpy2DAsync(res->beta, (size_t)K * p * 8, beta, p * 8, p * 8, NB, hipMemcpyDeviceToDevice, st));
-    res->k_done = 1;
-
-    for (int k = 1; k < K; ++k) {
+    for (int k = k_first; k < K; ++k) {
         const double* lam_k = lamg + (size_t)k * BNP;
         if (use_graph) HIPCHK(hipGraphLaunch(graphs.x[k & 1], st));
         else HIPCHK(screen_step(st, nullptr, k, zprev));

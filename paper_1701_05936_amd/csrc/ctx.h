@@ -59,6 +59,9 @@ enum BufId {
     BB_GE, BB_G0, BB_B0, BB_B1, BB_STATS, BB_CMP, BB_LSAFE, BB_SAFECNT, BB_WANTALL,
     // learned form and its network
     B_ZH, B_CAND, B_RECN, B_LC, BB_KDEV, M_PART, M_LOSSP, M_MOM, M_VEL, M_STEP, M_PERM, M_LOSSH, M_PROB, M_HIST,
+    // cross-validation
+    CV_MASKS, CV_TEST, CV_Y, CV_ALL, CV_ROWS, CV_RLENS, CV_MARK, CV_ULIST, CV_ULENS, CV_FBETA, CV_PRED, CV_LOSS,
+    CV_ICPT, CV_OUT, CV_CMP, CV_WANT, CV_LAM,
     B_COUNT
 };
 

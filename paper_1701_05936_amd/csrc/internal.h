@@ -300,4 +300,16 @@ hipError_t launch_fill_u8(uint8_t* p, uint8_t v, int64_t n, hipStream_t st);
 hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t st);
 hipError_t launch_or_u8(uint8_t* dst, const uint8_t* src, int64_t n, hipStream_t st);
 
+
+// ---- cross-validation (cv.hip) ----
+hipError_t launch_cv_setup(const int32_t* fold, const double* y, int64_t n_total, int nfolds, uint8_t* masks,
+                           uint8_t* test, double* Y, uint8_t* all_rows, hipStream_t st);
+hipError_t launch_cv_union(const double* beta, int64_t p, int K, int nfolds, uint8_t* mark, hipStream_t st);
+hipError_t launch_cv_predict(const Mat& m, int nfolds, int K, int64_t max_rows, const double* beta, const double* s,
+                             const int32_t* ulist, const int64_t* ulens, const int32_t* rows, const int64_t* rlens,
+                             const double* icpt, const double* y, double* pred, double* loss, hipStream_t st);
+hipError_t launch_cv_reduce(const double* loss, const uint8_t* all_rows, const int32_t* rows, const int64_t* rlens,
+                            int64_t n_total, int K, int nfolds, double* cve, double* cvse, double* ferr,
+                            hipStream_t st);
+
 }  // namespace blk
