@@ -59,6 +59,15 @@ def _load():
         L.or_cd.restype = i32
         L.or_residual.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp, vp, vp]
         L.or_residual.restype = None
+        L.or_cd_enet.argtypes = [i64, i64, vp, i64, vp, vp, vp, dbl, dbl, vp, vp, i64, vp, vp, dbl, i64, vp]
+        L.or_cd_enet.restype = i32
+        L.or_objective_enet.argtypes = [i64, vp, vp, i64, vp, dbl, dbl, vp]
+        L.or_objective_enet.restype = dbl
+        L.or_duality_gap_enet.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp, vp, vp, vp, dbl, dbl, vp]
+        L.or_duality_gap_enet.restype = dbl
+        L.or_fit_path_enet.argtypes = [i64, i64, vp, i64, vp, vp, i64, dbl, vp, dbl, vp, i32, dbl, i64,
+                                       vp, vp, vp, vp, vp, vp, vp, vp]
+        L.or_fit_path_enet.restype = i32
         L.or_objective.argtypes = [i64, vp, vp, i64, vp, dbl]
         L.or_objective.restype = dbl
         L.or_duality_gap.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp, vp, vp, vp, dbl]
@@ -171,8 +180,18 @@ def lambda_grid(lambda_max, ratio, K):
     return lam
 
 
-def cd(Xt, c, s, lam, sset, beta, r, tol=1e-13, max_sweeps=100000, mask=None):
-    """Cyclic CD in place on beta and r; returns (converged, sweeps)."""
+def _weights(w, p):
+    if w is None:
+        return None
+    w = _f64(w)
+    if w.shape != (p,) or np.any(~np.isfinite(w)) or np.any(w <= 0):
+        raise ValueError("penalty weights must be p finite positive values")
+    return w
+
+
+def cd(Xt, c, s, lam, sset, beta, r, tol=1e-13, max_sweeps=100000, mask=None, alpha=1.0, penalty_factor=None):
+    """Cyclic CD in place on beta and r; returns (converged, sweeps).  alpha < 1 or penalty_factor: the
+    elastic-net step."""
     Xt, ld = _design(Xt)
     p, n_total = Xt.shape
     m = _mask(mask, n_total)
@@ -181,8 +200,13 @@ def cd(Xt, c, s, lam, sset, beta, r, tol=1e-13, max_sweeps=100000, mask=None):
     assert beta.dtype == np.float64 and beta.flags.c_contiguous
     assert r.dtype == np.float64 and r.flags.c_contiguous
     sw = ctypes.c_int64()
-    rc = _load().or_cd(n_total, p, _ptr(Xt), ld, _ptr(m), _ptr(c), _ptr(s), lam, _ptr(sset), sset.size,
-                       _ptr(beta), _ptr(r), tol, max_sweeps, ctypes.addressof(sw))
+    w = _weights(penalty_factor, p)
+    if alpha == 1.0 and w is None:
+        rc = _load().or_cd(n_total, p, _ptr(Xt), ld, _ptr(m), _ptr(c), _ptr(s), lam, _ptr(sset), sset.size,
+                           _ptr(beta), _ptr(r), tol, max_sweeps, ctypes.addressof(sw))
+    else:
+        rc = _load().or_cd_enet(n_total, p, _ptr(Xt), ld, _ptr(m), _ptr(c), _ptr(s), lam, float(alpha), _ptr(w),
+                                _ptr(sset), sset.size, _ptr(beta), _ptr(r), tol, max_sweeps, ctypes.addressof(sw))
     return rc == 0, sw.value
 
 
@@ -196,20 +220,28 @@ def residual(Xt, c, s, ytilde, beta, mask=None):
     return r
 
 
-def objective(r, beta, lam, mask=None):
+def objective(r, beta, lam, mask=None, alpha=1.0, penalty_factor=None):
     r = _f64(r)
     m = _mask(mask, r.size)
     beta = _f64(beta)
-    return _load().or_objective(r.size, _ptr(m), _ptr(r), beta.size, _ptr(beta), lam)
+    w = _weights(penalty_factor, beta.size)
+    if alpha == 1.0 and w is None:
+        return _load().or_objective(r.size, _ptr(m), _ptr(r), beta.size, _ptr(beta), lam)
+    return _load().or_objective_enet(r.size, _ptr(m), _ptr(r), beta.size, _ptr(beta), lam, float(alpha), _ptr(w))
 
 
-def duality_gap(Xt, c, s, keep, ytilde, r, beta, lam, mask=None):
+def duality_gap(Xt, c, s, keep, ytilde, r, beta, lam, mask=None, alpha=1.0, penalty_factor=None):
     Xt, ld = _design(Xt)
     p, n_total = Xt.shape
     m = _mask(mask, n_total)
     k = np.ascontiguousarray(keep, dtype=np.uint8)
-    return _load().or_duality_gap(n_total, p, _ptr(Xt), ld, _ptr(m), _ptr(_f64(c)), _ptr(_f64(s)), _ptr(k),
-                                  _ptr(_f64(ytilde)), _ptr(_f64(r)), _ptr(_f64(beta)), lam)
+    w = _weights(penalty_factor, p)
+    if alpha == 1.0 and w is None:
+        return _load().or_duality_gap(n_total, p, _ptr(Xt), ld, _ptr(m), _ptr(_f64(c)), _ptr(_f64(s)), _ptr(k),
+                                      _ptr(_f64(ytilde)), _ptr(_f64(r)), _ptr(_f64(beta)), lam)
+    return _load().or_duality_gap_enet(n_total, p, _ptr(Xt), ld, _ptr(m), _ptr(_f64(c)), _ptr(_f64(s)), _ptr(k),
+                                       _ptr(_f64(ytilde)), _ptr(_f64(r)), _ptr(_f64(beta)), lam, float(alpha),
+                                       _ptr(w))
 
 
 @dataclass
@@ -244,8 +276,9 @@ SCREEN_NONE, SCREEN_SSR, SCREEN_ACTIVE = 0, 1, 2
 
 
 def fit_path(Xt, y, K=100, ratio=0.1, screen=SCREEN_SSR, tol=1e-13, max_sweeps=100000, mask=None,
-             lambdas=None) -> Path:
-    """The path over the geometric grid from lambda_max, or over the decreasing grid `lambdas` (K values)."""
+             lambdas=None, alpha=1.0, penalty_factor=None) -> Path:
+    """The path over the geometric grid from lambda_max, or over the decreasing grid `lambdas` (K values).
+    alpha < 1 and/or penalty_factor (p positive weights): the elastic net with feature weights."""
     Xt, ld = _design(Xt)
     lam_in = None
     if lambdas is not None:
@@ -264,8 +297,9 @@ def fit_path(Xt, y, K=100, ratio=0.1, screen=SCREEN_SSR, tol=1e-13, max_sweeps=1
     arr.update({k: np.zeros(K) for k in ("rss", "obj", "gap")})
     st = _Stats(**{k: v.ctypes.data for k, v in arr.items()})
     k_done = ctypes.c_int64()
-    rc = _load().or_fit_path(n_total, p, _ptr(Xt), ld, _ptr(m), _ptr(y), K, ratio, _ptr(lam_in), screen, tol,
-                             max_sweeps,
+    w = _weights(penalty_factor, p)
+    rc = _load().or_fit_path_enet(n_total, p, _ptr(Xt), ld, _ptr(m), _ptr(y), K, ratio, _ptr(lam_in),
+                                  float(alpha), _ptr(w), screen, tol, max_sweeps,
                              _ptr(c), _ptr(s), _ptr(keep), _ptr(lam), _ptr(beta), ctypes.addressof(ybar),
                              ctypes.byref(st), ctypes.addressof(k_done))
     if rc == 2:

@@ -219,9 +219,26 @@ void or_lambda_grid(double lambda_max, double ratio, int64_t K, double* lam) {
  * (the curvature (1/n) ||x~_j||^2 is 1).  Returns 0 when the largest |change|
  * over a sweep fell below tol, 1 when max_sweeps ran out.
  */
+/* penalty weight of feature j (penalty.factor): w[j], or 1 without weights */
+static double pw(const double* w, int64_t j) { return w ? w[j] : 1.0; }
+
 int or_cd(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
           const double* c, const double* s, double lambda, const int64_t* set, int64_t set_len,
           double* beta, double* r, double tol, int64_t max_sweeps, int64_t* sweeps) {
+    return or_cd_enet(n_total, p, X, ldx, mask, c, s, lambda, 1.0, NULL, set, set_len, beta, r, tol, max_sweeps,
+                      sweeps);
+}
+
+/*
+ * The same descent for the elastic-net penalty with feature weights (Section 1: the package fits
+ * lasso and elastic-net penalties), lambda sum_j w_j (alpha |beta_j| + (1 - alpha) beta_j^2 / 2):
+ * the coordinate minimizer is S(g + beta_j, lambda alpha w_j) / (1 + lambda (1 - alpha) w_j).
+ * alpha = 1 and w = NULL is the lasso step above.
+ */
+int or_cd_enet(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
+               const double* c, const double* s, double lambda, double alpha, const double* w,
+               const int64_t* set, int64_t set_len, double* beta, double* r, double tol, int64_t max_sweeps,
+               int64_t* sweeps) {
     (void)p;
     int64_t n = count_rows(n_total, mask);
     for (int64_t sweep = 1; sweep <= max_sweeps; ++sweep) {
@@ -233,7 +250,8 @@ int or_cd(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_
             for (int64_t i = 0; i < n_total; ++i)
                 if (in_fit(mask, i)) g += ((x[i] - c[j]) / s[j]) * r[i];
             g /= (double)n;
-            double bnew = soft_threshold(g + beta[j], lambda);
+            double bnew = soft_threshold(g + beta[j], lambda * alpha * pw(w, j)) /
+                          (1.0 + lambda * (1.0 - alpha) * pw(w, j));
             double delta = bnew - beta[j];
             if (delta != 0.0) {
                 for (int64_t i = 0; i < n_total; ++i)
@@ -272,6 +290,55 @@ double or_objective(int64_t n_total, const uint8_t* mask, const double* r, int64
         if (in_fit(mask, i)) rss += r[i] * r[i];
     for (int64_t j = 0; j < p; ++j) l1 += fabs(beta[j]);
     return rss / (2.0 * (double)n) + lambda * l1;
+}
+
+/* Elastic-net objective ||r||^2/(2n) + lambda sum_j w_j (alpha |beta_j| + (1 - alpha) beta_j^2 / 2) */
+double or_objective_enet(int64_t n_total, const uint8_t* mask, const double* r, int64_t p, const double* beta,
+                         double lambda, double alpha, const double* w) {
+    int64_t n = count_rows(n_total, mask);
+    double rss = 0.0, pen = 0.0;
+    for (int64_t i = 0; i < n_total; ++i)
+        if (in_fit(mask, i)) rss += r[i] * r[i];
+    for (int64_t j = 0; j < p; ++j)
+        pen += pw(w, j) * (alpha * fabs(beta[j]) + 0.5 * (1.0 - alpha) * beta[j] * beta[j]);
+    return rss / (2.0 * (double)n) + lambda * pen;
+}
+
+/*
+ * Relative duality gap of the elastic net, through its lasso form on augmented data: rows
+ * sqrt(n lambda (1 - alpha) w_j) e_j' appended to X~ (and 0 to y~) turn the ridge part into squared
+ * error, leaving the weighted lasso (1/2)||b - A beta||^2 + sum_j mu_j |beta_j| with mu_j = n lambda
+ * alpha w_j.  Its residual rho = (r, -sqrt(n lambda (1 - alpha) w) beta) scaled by
+ * t = min(1, min_j mu_j / |a_j' rho|), a_j' rho = n (z_j - lambda (1 - alpha) w_j beta_j), is dual
+ * feasible: D = ||y~||^2/2 - (||y~ - t r||^2 + t^2 n lambda (1 - alpha) sum_j w_j beta_j^2)/2 and
+ * P = n Q.  With alpha = 1 and no weights it is the lasso gap below.
+ */
+double or_duality_gap_enet(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
+                           const double* c, const double* s, const uint8_t* keep, const double* ytilde,
+                           const double* r, const double* beta, double lambda, double alpha, const double* w) {
+    int64_t n = count_rows(n_total, mask);
+    double* z = (double*)malloc(sizeof(double) * (size_t)p);
+    or_zscan(n_total, p, X, ldx, mask, c, s, keep, r, z);
+    double t = 1.0, ridge = 0.0;
+    for (int64_t j = 0; j < p; ++j) {
+        if (!keep[j]) continue;
+        double ar = (double)n * fabs(z[j] - lambda * (1.0 - alpha) * pw(w, j) * beta[j]);
+        double mu = (double)n * lambda * alpha * pw(w, j);
+        if (ar > 0.0 && mu / ar < t) t = mu / ar;
+        ridge += pw(w, j) * beta[j] * beta[j];
+    }
+    free(z);
+    double primal = (double)n * or_objective_enet(n_total, mask, r, p, beta, lambda, alpha, w);
+    double yy = 0.0, dd = 0.0;
+    for (int64_t i = 0; i < n_total; ++i) {
+        if (!in_fit(mask, i)) continue;
+        double d = ytilde[i] - t * r[i];
+        yy += ytilde[i] * ytilde[i];
+        dd += d * d;
+    }
+    dd += t * t * (double)n * lambda * (1.0 - alpha) * ridge;
+    double dual = 0.5 * yy - 0.5 * dd;
+    return primal > 0.0 ? (primal - dual) / primal : 0.0;
 }
 
 /*
@@ -321,7 +388,24 @@ int or_fit_path(int64_t n_total, int64_t p, const double* X, int64_t ldx, const 
                 const double* y, int64_t K, double ratio, const double* lam_in, int screen, double tol,
                 int64_t max_sweeps, double* c, double* s, uint8_t* keep, double* lambda, double* beta,
                 double* ybar, or_path_stats* st, int64_t* k_done) {
+    return or_fit_path_enet(n_total, p, X, ldx, mask, y, K, ratio, lam_in, 1.0, NULL, screen, tol, max_sweeps, c,
+                            s, keep, lambda, beta, ybar, st, k_done);
+}
+
+/*
+ * The path for the elastic-net penalty with feature weights (alpha in (0, 1], w_j > 0 or NULL).  What
+ * changes against the lasso: lambda_max = max_j |a_j| / (alpha w_j); the strong rule keeps j when
+ * |z_j(prev)| >= alpha w_j (2 l_k - l_{k-1}); a violation is |z_j| > l_k alpha w_j; the CD step is
+ * or_cd_enet's; the objective and gap are the elastic net's.  BEDPP is a lasso rule: with alpha < 1 or
+ * weights, n_safe reports every kept feature (no safe rule).
+ */
+int or_fit_path_enet(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
+                     const double* y, int64_t K, double ratio, const double* lam_in, double alpha, const double* w,
+                     int screen, double tol, int64_t max_sweeps, double* c, double* s, uint8_t* keep,
+                     double* lambda, double* beta, double* ybar, or_path_stats* st, int64_t* k_done) {
     *k_done = 0;
+    if (!(alpha > 0.0 && alpha <= 1.0)) return 2;
+    const int enet = alpha < 1.0 || w != NULL;
     if (p <= 0 || K <= 0) return 2;
     int64_t n = or_standardize(n_total, p, X, ldx, mask, c, s, keep);
     if (n <= 0) return 2;
@@ -342,6 +426,11 @@ int or_fit_path(int64_t n_total, int64_t p, const double* X, int64_t ldx, const 
     if (or_lambda_max(n_total, p, X, ldx, mask, c, s, keep, y, ybar, ytilde, a, &lmax, &jstar)) {
         status = 2;
         goto done;
+    }
+    if (enet) {
+        lmax = 0.0;
+        for (int64_t j = 0; j < p; ++j)
+            if (keep[j] && fabs(a[j]) / (alpha * pw(w, j)) > lmax) lmax = fabs(a[j]) / (alpha * pw(w, j));
     }
     or_bedpp_b(n_total, p, X, ldx, mask, c, s, keep, jstar, b);
     double v = 0.0;
@@ -372,14 +461,15 @@ int or_fit_path(int64_t n_total, int64_t p, const double* X, int64_t ldx, const 
                 else if (screen == OR_SCREEN_ACTIVE)
                     inE[j] = bcur[j] != 0.0 ? 1 : 0;
                 else
-                    inE[j] = (bcur[j] != 0.0 || fabs(zprev[j]) >= thr) ? 1 : 0;
+                    inE[j] = (bcur[j] != 0.0 || fabs(zprev[j]) >= thr * alpha * pw(w, j)) ? 1 : 0;
             }
             for (;;) {
                 nE = 0;
                 for (int64_t j = 0; j < p; ++j)
                     if (inE[j]) set[nE++] = j;
                 int64_t sw = 0;
-                int rc = or_cd(n_total, p, X, ldx, mask, c, s, lk, set, nE, bcur, r, tol, max_sweeps, &sw);
+                int rc = or_cd_enet(n_total, p, X, ldx, mask, c, s, lk, alpha, w, set, nE, bcur, r, tol, max_sweeps,
+                                    &sw);
                 sweeps_k += sw;
                 rounds_k += 1;
                 if (rc) {
@@ -389,7 +479,7 @@ int or_fit_path(int64_t n_total, int64_t p, const double* X, int64_t ldx, const 
                 or_zscan(n_total, p, X, ldx, mask, c, s, keep, r, z);
                 int64_t nv = 0;
                 for (int64_t j = 0; j < p; ++j) {
-                    if (keep[j] && !inE[j] && fabs(z[j]) > lk) {
+                    if (keep[j] && !inE[j] && fabs(z[j]) > lk * alpha * pw(w, j)) {
                         inE[j] = 1;
                         ++nv;
                     }
@@ -407,13 +497,18 @@ int or_fit_path(int64_t n_total, int64_t p, const double* X, int64_t ldx, const 
             if (st->n_strong) st->n_strong[k] = nE;
             if (st->n_viol) st->n_viol[k] = viol_k;
             if (st->n_rounds) st->n_rounds[k] = rounds_k;
-            if (st->n_safe) st->n_safe[k] = p - or_bedpp_discard(p, a, b, keep, lmax, sgn, v, lk, disc);
+            if (st->n_safe) {
+                int64_t nk = 0;
+                for (int64_t j = 0; j < p; ++j) nk += keep[j] != 0;
+                st->n_safe[k] = enet ? nk : p - or_bedpp_discard(p, a, b, keep, lmax, sgn, v, lk, disc);
+            }
             if (st->n_active) st->n_active[k] = nact;
             double rss = 0.0;
             for (int64_t i = 0; i < n_total; ++i) rss += r[i] * r[i];
             if (st->rss) st->rss[k] = rss;
-            if (st->obj) st->obj[k] = or_objective(n_total, mask, r, p, bcur, lk);
-            if (st->gap) st->gap[k] = or_duality_gap(n_total, p, X, ldx, mask, c, s, keep, ytilde, r, bcur, lk);
+            if (st->obj) st->obj[k] = or_objective_enet(n_total, mask, r, p, bcur, lk, alpha, w);
+            if (st->gap)
+                st->gap[k] = or_duality_gap_enet(n_total, p, X, ldx, mask, c, s, keep, ytilde, r, bcur, lk, alpha, w);
         }
         *k_done = k + 1;
     }

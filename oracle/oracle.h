@@ -78,4 +78,20 @@ double or_mlp_loss_grad(int64_t m, int64_t H, const double* feat, const double* 
 #ifdef __cplusplus
 }
 #endif
+
+/* elastic net with feature weights (w may be NULL: all 1); alpha = 1, w = NULL is the lasso */
+int or_cd_enet(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
+               const double* c, const double* s, double lambda, double alpha, const double* w,
+               const int64_t* set, int64_t set_len, double* beta, double* r, double tol, int64_t max_sweeps,
+               int64_t* sweeps);
+double or_objective_enet(int64_t n_total, const uint8_t* mask, const double* r, int64_t p, const double* beta,
+                         double lambda, double alpha, const double* w);
+double or_duality_gap_enet(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
+                           const double* c, const double* s, const uint8_t* keep, const double* ytilde,
+                           const double* r, const double* beta, double lambda, double alpha, const double* w);
+int or_fit_path_enet(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
+                     const double* y, int64_t K, double ratio, const double* lam_in, double alpha, const double* w,
+                     int screen, double tol, int64_t max_sweeps, double* c, double* s, uint8_t* keep,
+                     double* lambda, double* beta, double* ybar, or_path_stats* st, int64_t* k_done);
+
 #endif

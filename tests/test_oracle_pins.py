@@ -632,3 +632,120 @@ def test_cv_brute_force_folds():
             te = fold == f
             np.testing.assert_allclose(cv.pred[k, te], ym.mean() + (Xt[:, te].T - c) @ b, atol=1e-9)
     assert 0 <= cv.k_1se <= cv.k_min < 6
+
+
+# ---------------------------------------------------------------------------------------------
+# elastic net and penalty factors (Section 1: the package fits lasso and elastic-net penalties; the
+# penalty of feature j is lambda w_j (alpha |beta_j| + (1 - alpha) beta_j^2 / 2))
+# ---------------------------------------------------------------------------------------------
+
+def enet_brute_force(Xtil, yt, lam, alpha, w):
+    """Sign patterns again, with the ridge part on the diagonal and weighted thresholds."""
+    n, p = Xtil.shape
+    G = Xtil.T @ Xtil / n
+    q = Xtil.T @ yt / n
+    found = []
+    for sig in itertools.product((-1, 0, 1), repeat=p):
+        sig = np.array(sig)
+        A = np.flatnonzero(sig)
+        beta = np.zeros(p)
+        if A.size:
+            H = G[np.ix_(A, A)] + np.diag(lam * (1 - alpha) * w[A])
+            beta[A] = np.linalg.solve(H, q[A] - lam * alpha * w[A] * sig[A])
+            if not np.all(np.sign(beta[A]) == sig[A]):
+                continue
+        grad = q - G @ beta
+        off = np.setdiff1d(np.arange(p), A)
+        if np.all(np.abs(grad[off]) <= lam * alpha * w[off] * (1 + 1e-12)):
+            found.append(beta)
+    return found
+
+
+def test_enet_unit_weights_and_alpha_one_is_the_lasso():
+    prob = datagen.make("c1", n=150, p=320)
+    a = oracle.fit_path(prob.Xt, prob.y[0], K=25, ratio=0.05)
+    b = oracle.fit_path(prob.Xt, prob.y[0], K=25, ratio=0.05, alpha=1.0, penalty_factor=np.ones(320))
+    np.testing.assert_array_equal(a.beta, b.beta)
+    np.testing.assert_array_equal(a.lam, b.lam)
+
+
+def test_enet_orthogonal_design_closed_form():
+    n, p = 64, 10
+    Xt = orthogonal_design(n, p, 91)
+    rng = np.random.default_rng(92)
+    y = Xt.T @ rng.normal(size=p) + rng.normal(size=n)
+    w = rng.uniform(0.3, 2.0, size=p)
+    alpha = 0.4
+    path = oracle.fit_path(Xt, y, K=20, ratio=0.02, alpha=alpha, penalty_factor=w)
+    Xtil, c, s = std_numpy(Xt)
+    a = Xtil.T @ (y - y.mean()) / n
+    assert path.lam[0] == pytest.approx(np.max(np.abs(a) / (alpha * w)), rel=1e-13)
+    for k, lam in enumerate(path.lam):
+        expect = soft(a, lam * alpha * w) / (1 + lam * (1 - alpha) * w)
+        np.testing.assert_allclose(path.beta[k], expect, atol=1e-11)
+
+
+@pytest.mark.parametrize("alpha,weighted", [(0.5, False), (0.8, True), (1.0, True)])
+def test_enet_brute_force_with_row_mask(alpha, weighted):
+    n, p = 42, 8
+    rng = np.random.default_rng(101)
+    Xt = rng.normal(size=(p, n)) + rng.normal(size=(p, 1))
+    mask = np.ones(n, dtype=np.uint8)
+    mask[rng.choice(n, 6, replace=False)] = 0
+    y = Xt[0] - 1.5 * Xt[4] + 0.5 * Xt[6] + rng.normal(size=n)
+    w = rng.uniform(0.5, 2.0, size=p) if weighted else np.ones(p)
+    path = oracle.fit_path(Xt, y, K=10, ratio=0.03, mask=mask, alpha=alpha,
+                           penalty_factor=w if weighted else None)
+    Xtil, c, s = std_numpy(Xt, mask)
+    ym = y[mask.astype(bool)]
+    assert np.all(path.beta[0] == 0.0)
+    for k in (2, 5, 9):
+        sols = enet_brute_force(Xtil, ym - ym.mean(), path.lam[k], alpha, w)
+        assert len(sols) == 1
+        np.testing.assert_allclose(path.beta[k], sols[0], atol=1e-10)
+
+
+def test_enet_weights_scale_with_lambda():
+    """The penalty depends on lambda w_j only: weights times c with lambda over c is the same fit."""
+    prob = datagen.make("c2", n=120, p=200)
+    Xt = prob.Xt.astype(np.float64)
+    w = np.random.default_rng(3).uniform(0.5, 1.5, size=200)
+    a = oracle.fit_path(Xt, prob.y[0], K=12, ratio=0.1, alpha=0.7, penalty_factor=w)
+    b = oracle.fit_path(Xt, prob.y[0], K=12, alpha=0.7, penalty_factor=4.0 * w, lambdas=a.lam / 4.0)
+    np.testing.assert_allclose(b.beta, a.beta, atol=1e-11)
+
+
+def test_enet_duality_gap_closed_form_at_beta_zero():
+    """At beta = 0 the scaled residual is t y~ with t = lambda / lambda_max, so the gap is (1 - t)^2."""
+    prob = datagen.make("c1", n=90, p=140)
+    Xt = prob.Xt
+    c, s, keep, n = oracle.standardize(Xt)
+    ybar, yt, a, lmax_l, js = oracle.lambda_max(Xt, c, s, keep, prob.y[0])
+    w = np.random.default_rng(4).uniform(0.5, 2.0, size=140)
+    alpha = 0.6
+    lmax = np.max(np.abs(a) / (alpha * w))
+    for frac in (0.9, 0.5, 0.1):
+        lam = frac * lmax
+        gap = oracle.duality_gap(Xt, c, s, keep, yt, yt, np.zeros(140), lam, alpha=alpha, penalty_factor=w)
+        assert gap == pytest.approx((1 - frac) ** 2, rel=1e-12)
+
+
+def test_enet_path_certificates():
+    prob = datagen.make("c4", n=200, p=400, nresp=1, nsub=1)
+    Xt = prob.Xt.astype(np.float64)
+    w = np.random.default_rng(5).uniform(0.25, 4.0, size=400)
+    path = oracle.fit_path(Xt, prob.y[0], K=30, ratio=0.02, alpha=0.3, penalty_factor=w)
+    assert path.k_done == 30
+    assert np.max(path.gap[1:]) <= 1e-10
+    # stationarity: z_j - lambda (1 - alpha) w_j beta_j = lambda alpha w_j sign(beta_j) on the support
+    c, s, keep, n = path.c, path.s, path.keep, Xt.shape[1]
+    yt = prob.y[0] - prob.y[0].mean()
+    for k in (10, 29):
+        b = path.beta[k]
+        r = oracle.residual(Xt, c, s, yt, b)
+        z = oracle.zscan(Xt, c, s, keep, r)
+        lam = path.lam[k]
+        act = b != 0
+        np.testing.assert_allclose(z[act] - lam * 0.7 * w[act] * b[act], lam * 0.3 * w[act] * np.sign(b[act]),
+                                   atol=1e-9 * lam)
+        assert np.all(np.abs(z[~act]) <= lam * 0.3 * w[~act] * (1 + 1e-9))
