@@ -272,6 +272,16 @@ typedef struct {
     const double* beta_init;
     const double* r_init;
     double* r_out;             /* DEVICE [n_total] or NULL: the residual at the last finished lambda  */
+    /* elastic net and penalty factors (Section 1: the package fits lasso and elastic-net penalties): the
+     * penalty becomes lambda sum_j w_j (alpha |beta_j| + (1 - alpha) beta_j^2 / 2).  alpha in (0, 1]
+     * (0 is read as 1, the lasso); penalty_factor = w, DEVICE [p] of finite w_j > 0, or NULL (all 1).
+     * Then lambda_max = max_j |a_j| / (alpha w_j), the strong rule keeps j when |z_j(k-1)| >= alpha w_j
+     * (2 lambda_k - lambda_{k-1}), a violation is |z_j| > lambda_k alpha w_j, the CD step is
+     * S(u, lambda alpha w_j) / (1 + lambda (1 - alpha) w_j), and obj is the elastic-net objective.
+     * BEDPP is a lasso rule: with alpha < 1 or weights the rules run without it (BEDPP alone keeps every
+     * feature).  Not with the precision forms, the learned rule or the batched form (BL_ERR_UNSUPPORTED). */
+    double alpha;
+    const double* penalty_factor;
 } bl_path_opts;
 
 /* Results of bl_fit_path.  Host arrays have K entries; any pointer may be NULL (not written). */

@@ -67,7 +67,8 @@ class _PathOpts(ctypes.Structure):
                 ("max_rounds", ctypes.c_int32), ("precision", ctypes.c_int32), ("mlp", ctypes.c_void_p),
                 ("mlp_tau", ctypes.c_double), ("rec_feat", ctypes.c_void_p), ("rec_label", ctypes.c_void_p),
                 ("rec_cap", ctypes.c_int64), ("k_start", ctypes.c_int32), ("beta_init", ctypes.c_void_p),
-                ("r_init", ctypes.c_void_p), ("r_out", ctypes.c_void_p)]
+                ("r_init", ctypes.c_void_p), ("r_out", ctypes.c_void_p), ("alpha", ctypes.c_double),
+                ("penalty_factor", ctypes.c_void_p)]
 
 
 class _Cv(ctypes.Structure):
@@ -396,11 +397,12 @@ class PathResult:
 def fit_path(ctx: Context, Xt, y, nlambda=100, lambda_min_ratio=0.1, lambdas=None, rule=SCREEN_SSR_BEDPP,
              tol=1e-8, max_sweeps=100000, max_rounds=100, row_mask=None, n_total=None, want_beta=True,
              raise_on_error=True, precision=PREC_FP64, mlp=None, mlp_tau=0.0, rec_feat=None, rec_label=None,
-             k_start=0, beta_init=None, r_init=None, r_out=None) -> PathResult:
+             k_start=0, beta_init=None, r_init=None, r_out=None, alpha=1.0, penalty_factor=None) -> PathResult:
     """Whole path.  Learned rule: rule=SCREEN_LEARNED with mlp (float32 device [MLP_NPARAMS]) and mlp_tau.
     Training records: rec_feat (float32 device [cap, 4]) and rec_label (float32 device [cap]).
     Resume: k_start >= 1 with beta_init (float64 device [p], beta at lambda index k_start - 1) and
-    optionally r_init (float64 device [n_total], its residual); r_out receives the final residual."""
+    optionally r_init (float64 device [n_total], its residual); r_out receives the final residual.
+    Elastic net: alpha in (0, 1] and penalty_factor (float64 device [p], positive) or None."""
     M = matrix(Xt, n_total, row_mask)
     K = int(nlambda)
     p = M.p
@@ -428,7 +430,7 @@ def fit_path(ctx: Context, Xt, y, nlambda=100, lambda_min_ratio=0.1, lambdas=Non
     opts = _PathOpts(K, float(lambda_min_ratio), lam_in.ctypes.data if lam_in is not None else None, int(rule),
                      float(tol), int(max_sweeps), int(max_rounds), int(precision), _ptr(mlp), float(mlp_tau),
                      _ptr(rec_feat), _ptr(rec_label), rec_cap, int(k_start), _ptr(beta_init), _ptr(r_init),
-                     _ptr(r_out))
+                     _ptr(r_out), float(alpha), _ptr(penalty_factor))
     res = _PathResult(_ptr(beta), _ptr(c), _ptr(s), _ptr(keep), host["lam"].ctypes.data,
                       host["intercept"].ctypes.data, host["rss"].ctypes.data, host["obj"].ctypes.data,
                       host["sweeps"].ctypes.data, host["rounds"].ctypes.data, host["n_active"].ctypes.data,

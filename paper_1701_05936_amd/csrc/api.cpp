@@ -7,6 +7,7 @@
 #include <cmath>
 #include <algorithm>
 #include <cstring>
+#include <vector>
 
 #include "ctx.h"
 
@@ -169,14 +170,17 @@ bl_status pool_reserve(bl_ctx ctx, int64_t need) {
 // sc->sum_r, sc->rss and sc->round.{sweeps, status, cd_len}.
 bl_status solve_set(bl_ctx ctx, const Mat& mt, const int32_t* set, const int64_t* len_dev, int64_t m,
                     const double* z, double* beta, double* r, const double* c, const double* s, double n_rows,
-                    double lam, double tol, int max_sweeps) {
+                    double lam, double tol, int max_sweeps, double alpha = 1.0, const double* w = nullptr) {
     hipStream_t st = ctx->stream;
     const double es = (double)elem_bytes(mt.xtype);
-    // covariance form up to cov_max features; the multi-workgroup solve only with every workgroup resident,
-    // else the single-workgroup solve (its gradient lives in LDS: GCD_MAX features) or the residual form
+    const bool enet = alpha < 1.0 || w != nullptr;
+    // covariance form up to cov_max features; the multi-workgroup solve only with every workgroup resident
+    // and one threshold for every coordinate, else the single-workgroup solve (its gradient lives in LDS:
+    // GCD_MAX features) or the residual form
     int H = gcd_multi_helpers(m);
-    const bool cov = m <= ctx->cov_max && (H <= ctx->cd_helpers || m <= GCD_MAX);
-    if (H > ctx->cd_helpers) H = 0;
+    const bool multi_ok = H <= ctx->cd_helpers && w == nullptr;
+    const bool cov = m <= ctx->cov_max && (multi_ok || m <= GCD_MAX);
+    if (!multi_ok) H = 0;
     ctx->last_residual = !cov;
     if (!cov) {
         if (!cd_supported(mt.n_total))
@@ -193,6 +197,8 @@ bl_status solve_set(bl_ctx ctx, const Mat& mt, const int32_t* set, const int64_t
         ca.tol = tol;
         ca.max_sweeps = max_sweeps;
         ca.sc = ctx->sc;
+        ca.alpha = alpha;
+        ca.w = w;
         prof_mark(ctx, 0);
         HIPCHK(launch_cd(mt, ca, st));
         prof_mark(ctx, 1);
@@ -220,6 +226,14 @@ bl_status solve_set(bl_ctx ctx, const Mat& mt, const int32_t* set, const int64_t
     ctx->pool_size += n_new;
     HIPCHK(launch_gather_gram(set, m, pos, ctx->gpool, ctx->pool_cap, GE, st));
     HIPCHK(launch_gather_start(set, m, z, beta, g0, b0, st));
+    // the elastic net solved as a lasso in gamma = q beta with a unit-diagonal Gram (launch_enet_scale)
+    double* lamv = nullptr;
+    double lam_solve = lam;
+    if (enet) {
+        if (w) ENSURE(B_LAMV, (m + 1) * 8, lamv);
+        HIPCHK(launch_enet_scale(set, m, w, lam, alpha, GE, g0, b0, lamv, st));
+        if (!w) lam_solve = lam * alpha / std::sqrt(1.0 + lam * (1.0 - alpha));
+    }
     prof_mark(ctx, 5);
     if (H > 0) {
         // leader + helper workgroups; g0 holds the working gradient, b1 the working coefficients
@@ -239,7 +253,7 @@ bl_status solve_set(bl_ctx ctx, const Mat& mt, const int32_t* set, const int64_t
         ma.sync = sy;
         ma.H = H;
         ma.spin_limit = 2000000u;  // about two seconds of polling per wait
-        ma.lam = lam;
+        ma.lam = lam_solve;
         ma.tol = tol;
         ma.max_sweeps = max_sweeps;
         ma.sc = ctx->sc;
@@ -256,7 +270,8 @@ bl_status solve_set(bl_ctx ctx, const Mat& mt, const int32_t* set, const int64_t
         ga.b1 = b1;
         ga.set = set;
         ga.beta = beta;
-        ga.lam = lam;
+        ga.lam = lam_solve;
+        ga.lamv = lamv;
         ga.tol = tol;
         ga.max_sweeps = max_sweeps;
         ga.sc = ctx->sc;
@@ -264,6 +279,7 @@ bl_status solve_set(bl_ctx ctx, const Mat& mt, const int32_t* set, const int64_t
         HIPCHK(launch_gcd(ga, st));
         prof_mark(ctx, 1);
     }
+    if (enet) HIPCHK(launch_enet_unscale(set, m, w, lam, alpha, b0, b1, beta, st));
     prof_mark(ctx, 6);
     HIPCHK(launch_r_update(mt, set, m, b0, b1, c, s, part, r, st));
     HIPCHK(launch_sum_r(mt, r, ctx->sc, true, st));
@@ -686,7 +702,15 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         return fail(ctx, BL_ERR_INVALID, "tol > 0, max_sweeps >= 1 and max_rounds >= 1 are required");
     const bool learned = opts->rule == BL_SCREEN_LEARNED;
     const bool active_only = opts->rule == BL_SCREEN_ACTIVE;
-    const bool bedpp = opts->rule == BL_SCREEN_BEDPP || opts->rule == BL_SCREEN_SSR_BEDPP || learned || active_only;
+    // elastic net and penalty factors; BEDPP is a lasso rule and stays off for them
+    const double alpha = opts->alpha == 0.0 ? 1.0 : opts->alpha;
+    if (!(alpha > 0.0 && alpha <= 1.0)) return fail(ctx, BL_ERR_INVALID, "alpha must be in (0, 1]");
+    const double* pf = opts->penalty_factor;
+    const bool enet = alpha < 1.0 || pf != nullptr;
+    if (enet && (learned || opts->precision != BL_PREC_FP64))
+        return fail(ctx, BL_ERR_UNSUPPORTED, "elastic net / penalty factors: FP64 scans and no learned rule");
+    const bool bedpp =
+        !enet && (opts->rule == BL_SCREEN_BEDPP || opts->rule == BL_SCREEN_SSR_BEDPP || learned || active_only);
     const bool ssr = opts->rule == BL_SCREEN_SSR || opts->rule == BL_SCREEN_SSR_BEDPP || learned;
     const bool check = ssr || active_only;   // rules with a post-convergence check
     const int k_start = opts->k_start;
@@ -712,6 +736,14 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         return fail(ctx, BL_ERR_UNSUPPORTED, "matrix-core scans need int8 X with 16-byte aligned columns");
     const int64_t p = m.p, nt = m.n_total;
     hipStream_t st = ctx->stream;
+    if (pf) {
+        std::vector<double> hw(p);
+        HIPCHK(hipMemcpyAsync(hw.data(), pf, p * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int64_t j = 0; j < p; ++j)
+            if (!(std::isfinite(hw[j]) && hw[j] > 0.0))
+                return fail(ctx, BL_ERR_INVALID, "penalty_factor[%lld] must be finite and > 0", (long long)j);
+    }
 
     double *yt, *r, *xs, *a, *b, *z0, *z1, *beta, *c, *sc_, *pv;
     uint8_t *s0, *s1, *strong, *keep;
@@ -790,8 +822,18 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
     // the set-up scans are FP64 scans; in the precision form they are kept apart from its BF16 check scans
     const int setup_slot = lowp ? BL_PROF_SETUP : BL_PROF_SCAN;
     prof_add(ctx, 2, setup_slot, (double)p * col_bytes + nt * 8.0, 0.0, (double)p);
-    const double ybar = ctx->sc_host->y_mean, yy = ctx->sc_host->yy, lmax = ctx->sc_host->lmax;
+    const double ybar = ctx->sc_host->y_mean, yy = ctx->sc_host->yy;
+    double lmax = ctx->sc_host->lmax;
     const int64_t jstar = ctx->sc_host->jstar;
+    if (enet && jstar >= 0) {
+        // lambda_max of the elastic net: the largest |a_j| / (alpha w_j) over kept columns
+        double* lt;
+        ENSURE(B_LMT, p * 8, lt);
+        HIPCHK(launch_enet_lmax_terms(a, pf, alpha, p, lt, st));
+        HIPCHK(launch_argmax_abs(lt, keep, p, pv, pi, ctx->sc, st));
+        if ((s = read_scalars(ctx))) return s;
+        lmax = ctx->sc_host->lmax;
+    }
     if (!std::isfinite(ybar) || !std::isfinite(yy)) return fail(ctx, BL_ERR_INVALID, "y has NaN or Inf");
     if (jstar < 0) return fail(ctx, BL_ERR_INVALID, "no column is kept (all constant)");
     if (!std::isfinite(lmax)) return fail(ctx, BL_ERR_INVALID, "X or y has NaN or Inf");
@@ -916,8 +958,8 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         }
         HIPCHK(launch_compact(scan_mask, p, lT, len_next, scr, st));
         // working set E_k
-        HIPCHK(launch_ssr(p, safe_cur, nullptr, beta, zprev, check, active_only ? INFINITY : 2.0 * lk - lprev, strong,
-                          st));
+        HIPCHK(launch_ssr(p, safe_cur, nullptr, beta, zprev, check, active_only ? INFINITY : (2.0 * lk - lprev) * alpha,
+                          strong, st, pf));
         const int s1 = (k + 2) % 3, s2 = (k + 1) % 3, s3 = k % 3;   // slots of lambda_{k-1}, _{k-2}, _{k-3}
         if (history && k >= 3)
             HIPCHK(launch_learned(strong, beta, zh, p, s1, s2, s3, (float)(lk / lam[k - 1]), opts->mlp, tau_logit,
@@ -947,7 +989,7 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
                 recheck_total += m_len;
             }
             if ((s = solve_set(ctx, m, lE, lens + 0, m_len, zsrc, beta, r, c, sc_, (double)n, lk, opts->tol,
-                               opts->max_sweeps)))
+                               opts->max_sweeps, alpha, pf)))
                 return s;
             HIPCHK(hipMemsetAsync(&ctx->sc->round.n_viol, 0, sizeof(uint32_t), st));
             if (!lowp) {
@@ -961,7 +1003,8 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
                 ka.keep = keep;
                 ka.z = zcur;
                 ka.check = check;
-                ka.lam = lk;
+                ka.lam = lk * alpha;   // the check threshold lambda_k alpha w_j
+                ka.w = pf;
                 ka.in_s = safe_cur;
                 ka.excl = strong;
                 ka.mark = strong;
@@ -1046,7 +1089,7 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         h_rounds[k] = rounds;
         h_viol[k] = viol_total;
         h_recheck[k] = recheck_total;
-        HIPCHK(launch_record(lE, lens + 0, len_cur, len_next, beta, c, sc_, ctx->sc, lk, stats + k, st));
+        HIPCHK(launch_record(lE, lens + 0, len_cur, len_next, beta, c, sc_, ctx->sc, lk, stats + k, st, alpha, pf));
         if (res->beta) HIPCHK(hipMemcpyAsync(res->beta + (size_t)k * p, beta, p * 8, hipMemcpyDeviceToDevice, st));
         if (recording && k >= 3) {
             HIPCHK(launch_compact(cand, p, lC, lens + 6, scr, st));

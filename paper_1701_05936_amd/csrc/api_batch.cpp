@@ -128,6 +128,8 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
     if (opts->rule < BL_SCREEN_NONE || opts->rule > BL_SCREEN_ACTIVE) return fail(ctx, BL_ERR_INVALID, "unknown rule");
     if (opts->rule == BL_SCREEN_LEARNED) return fail(ctx, BL_ERR_UNSUPPORTED, "batched form: no learned rule");
     if (opts->k_start != 0) return fail(ctx, BL_ERR_UNSUPPORTED, "batched form: no resume (k_start must be 0)");
+    if ((opts->alpha != 0.0 && opts->alpha != 1.0) || opts->penalty_factor)
+        return fail(ctx, BL_ERR_UNSUPPORTED, "batched form: lasso only (no elastic net or penalty factors)");
     if (!(opts->tol > 0.0) || opts->max_sweeps < 1 || opts->max_rounds < 1)
         return fail(ctx, BL_ERR_INVALID, "tol > 0, max_sweeps >= 1 and max_rounds >= 1 are required");
     if (opts->precision != BL_PREC_FP64) return fail(ctx, BL_ERR_UNSUPPORTED, "batched form: FP64 scans only");

@@ -26,7 +26,8 @@ __device__ __forceinline__ double chain_readlane(double v, int lane) {
 
 __device__ __forceinline__ uint64_t chain_below(int t) { return t >= 64 ? ~0ull : ((1ull << t) - 1ull); }
 
-// Plain chain over steps t < bl: soft threshold written out, one coordinate after the other.
+// Plain chain over steps t < bl: soft threshold written out, one coordinate after the other.  lam is
+// this lane's threshold (the same in every lane unless the penalty weights differ); step t uses lane t's.
 template <int NB, typename Col>
 __device__ __forceinline__ void chain_exact(double& gl, double& bv, Col col, double lam, int bl, double& dl,
                                             double& wmax) {
@@ -37,8 +38,9 @@ __device__ __forceinline__ void chain_exact(double& gl, double& bv, Col col, dou
         if (t < bl) {
             const double gt = chain_readlane(gl, t);
             const double bt = chain_readlane(bv0, t);
+            const double lt = chain_readlane(lam, t);
             const double u = gt + bt;
-            const double bn = u - fmin(fmax(u, -lam), lam);  // S(u, lambda)
+            const double bn = u - fmin(fmax(u, -lt), lt);  // S(u, lambda_t)
             const double d = bn - bt;
             gl = fma(-d, col(t), gl);
             bv = lane == t ? bn : bv;
@@ -48,7 +50,8 @@ __device__ __forceinline__ void chain_exact(double& gl, double& bv, Col col, dou
     }
 }
 
-// Status-keeping chain; returns false (and changes nothing) if a coordinate might change status.
+// Status-keeping chain; returns false (and changes nothing) if a coordinate might change status.  lam is
+// this lane's threshold, as in chain_exact.
 // The loop carries the pending changes dv_l = g_l - lambda sign(beta_l) (sign -1 for beta_l = 0): a taken
 // step reads d_t = dv_t and subtracts d_t G[t][.]; the gradient is dv + lambda sign(beta).  The step's lane
 // read comes from a masked copy dm that is held at zero on the lanes of zero coefficients (their Gram

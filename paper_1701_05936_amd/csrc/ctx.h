@@ -62,6 +62,8 @@ enum BufId {
     // cross-validation
     CV_MASKS, CV_TEST, CV_Y, CV_ALL, CV_ROWS, CV_RLENS, CV_MARK, CV_ULIST, CV_ULENS, CV_FBETA, CV_PRED, CV_LOSS,
     CV_ICPT, CV_OUT, CV_CMP, CV_WANT, CV_LAM,
+    // elastic net
+    B_LAMV, B_PF, B_LMT,
     B_COUNT
 };
 

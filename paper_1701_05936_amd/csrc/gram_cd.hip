@@ -407,10 +407,11 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd(GcdArgs a) {
                     // the sequential chain of this block, one coordinate per step
                     double gl = lane < bl ? g[b0 + lane] : 0.0;
                     double bv = lane < bl ? bE[b0 + lane] : 0.0;
+                    const double ll = (a.lamv && lane < bl) ? a.lamv[b0 + lane] : lam;   // this lane's threshold
                     double dl = 0.0, wmax = 0.0;
                     auto col = [&](int t) { return Gbb[t * GCD_B + lane]; };
-                    if (!chain_fast<GCD_B>(gl, bv, col, lam, bl, dl, wmax))
-                        chain_exact<GCD_B>(gl, bv, col, lam, bl, dl, wmax);
+                    if (!chain_fast<GCD_B>(gl, bv, col, ll, bl, dl, wmax))
+                        chain_exact<GCD_B>(gl, bv, col, ll, bl, dl, wmax);
                     if (lane < bl) {
                         g[b0 + lane] = gl;
                         bE[b0 + lane] = bv;
@@ -1105,6 +1106,65 @@ int gcd_multi_helpers(int64_t m) {
     const int nb = (int)((m + MB - 1) / MB);
     if (nb < 2 * (SLACK + 2)) return 0;  // small sets: the single-workgroup solve
     return (nb + HOWN - 1) / HOWN;
+}
+
+// ---- elastic net in the covariance solve ----------------------------------------------------------------
+__device__ __forceinline__ double enet_q(const double* w, int j, double lr) { return sqrt(1.0 + lr * (w ? w[j] : 1.0)); }
+
+__global__ void k_enet_scale_vec(const int32_t* __restrict__ set, int64_t m, const double* __restrict__ w, double lam,
+                                 double alpha, double* __restrict__ g0, double* __restrict__ b0,
+                                 double* __restrict__ lamv) {
+    const double lr = lam * (1.0 - alpha);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        const int j = set[e];
+        const double wj = w ? w[j] : 1.0;
+        const double q = enet_q(w, j, lr);
+        g0[e] = (g0[e] - lr * wj * b0[e]) / q;
+        b0[e] = b0[e] * q;
+        if (lamv) lamv[e] = lam * alpha * wj / q;
+    }
+}
+
+// G~[e][f] = G[e][f] / (q_e q_f), G~[e][e] = (G[e][e] + lam (1 - alpha) w_e) / q_e^2
+__global__ void k_enet_scale_gram(const int32_t* __restrict__ set, int64_t m, const double* __restrict__ w, double lam,
+                                  double alpha, double* __restrict__ GE) {
+    const double lr = lam * (1.0 - alpha);
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < m * m;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = idx / m, f = idx % m;
+        const int je = set[e], jf = set[f];
+        const double qe = enet_q(w, je, lr), qf = enet_q(w, jf, lr);
+        GE[idx] = e == f ? (GE[idx] + lr * (w ? w[je] : 1.0)) / (qe * qe) : GE[idx] / (qe * qf);
+    }
+}
+
+__global__ void k_enet_unscale(const int32_t* __restrict__ set, int64_t m, const double* __restrict__ w, double lam,
+                               double alpha, double* __restrict__ b0, double* __restrict__ b1,
+                               double* __restrict__ beta) {
+    const double lr = lam * (1.0 - alpha);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        const int j = set[e];
+        const double q = enet_q(w, j, lr);
+        b0[e] = b0[e] / q;
+        const double b = b1[e] / q;
+        b1[e] = b;
+        beta[j] = b;
+    }
+}
+
+hipError_t launch_enet_scale(const int32_t* set, int64_t m, const double* w, double lam, double alpha, double* GE,
+                             double* g0, double* b0, double* lamv, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    k_enet_scale_vec<<<grid_for(m, 256, 1024), 256, 0, st>>>(set, m, w, lam, alpha, g0, b0, lamv);
+    k_enet_scale_gram<<<grid_for(m * m, 256, 8192), 256, 0, st>>>(set, m, w, lam, alpha, GE);
+    return hipGetLastError();
+}
+
+hipError_t launch_enet_unscale(const int32_t* set, int64_t m, const double* w, double lam, double alpha, double* b0,
+                               double* b1, double* beta, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    k_enet_unscale<<<grid_for(m, 256, 1024), 256, 0, st>>>(set, m, w, lam, alpha, b0, b1, beta);
+    return hipGetLastError();
 }
 
 int gcd_multi_resident() {

@@ -84,6 +84,7 @@ struct ScanArgs {
     uint8_t* mark;
     uint32_t* nviol;
     int64_t* len_out;   // when not null, block 0 stores the scanned length here
+    const double* w;    // check threshold lam * w[j] (elastic-net penalty weights) when not null
 };
 hipError_t launch_scan(const Mat& m, const ScanArgs& a, hipStream_t st);
 
@@ -94,9 +95,13 @@ hipError_t launch_argmax_abs(const double* a, const uint8_t* keep, int64_t p, do
 // safe[j] = keep[j] && !BEDPP-discard(j)  (bedpp false: safe = keep); counts into *cnt (device, += )
 hipError_t launch_bedpp(int64_t p, const double* a, const double* b, const uint8_t* keep, bool bedpp, double lmax,
                         double sgn, double lam, double rhs, uint8_t* safe, hipStream_t st);
-// strong[j] = safe[j] && (act(j) || (ssr && |zprev_j| >= thr)); act(j) = active ? active[j] : beta[j] != 0
+// strong[j] = safe[j] && (act(j) || (ssr && |zprev_j| >= thr w_j)); act(j) = active ? active[j] : beta[j] != 0;
+// w null: w_j = 1
 hipError_t launch_ssr(int64_t p, const uint8_t* safe, const uint8_t* active, const double* beta, const double* zprev,
-                      bool ssr, double thr, uint8_t* strong, hipStream_t st);
+                      bool ssr, double thr, uint8_t* strong, hipStream_t st, const double* w = nullptr);
+// out[j] = |a_j| / (alpha w_j) (the elastic net's lambda_max is its largest kept value)
+hipError_t launch_enet_lmax_terms(const double* a, const double* w, double alpha, int64_t p, double* out,
+                                  hipStream_t st);
 
 // ordered compaction of a uint8 mask: out[0..len) = ascending j with mask[j] != 0; *len_dev = len
 size_t compact_scratch_bytes(int64_t p);
@@ -116,14 +121,17 @@ struct CdArgs {
     double tol;
     int max_sweeps;
     DevScalars* sc;
+    double alpha;         // elastic-net mixing (1: lasso)
+    const double* w;      // penalty weights or null (all 1)
 };
 bool cd_supported(int64_t n_total);
 hipError_t launch_cd(const Mat& m, const CdArgs& a, hipStream_t st);
 
 // per-lambda record: stats over the set (beta nonzero only there) into *out
+// obj = rss / (2n) + lam sum_j w_j (alpha |beta_j| + (1 - alpha) beta_j^2 / 2) (lasso: alpha 1, w null)
 hipError_t launch_record(const int32_t* set, const int64_t* len_dev, const int64_t* len_safe, const int64_t* len_scan,
                          const double* beta, const double* c, const double* s, const DevScalars* sc, double lam,
-                         LamStats* out, hipStream_t st);
+                         LamStats* out, hipStream_t st, double alpha = 1.0, const double* w = nullptr);
 
 // ---- coordinate descent with covariance updates (gram_cd.hip) ----
 constexpr int GCD_B = 64;       // coordinates per sequential block
@@ -140,6 +148,7 @@ struct GcdArgs {
     double lam, tol;
     int max_sweeps;
     DevScalars* sc;
+    const double* lamv;   // per set position threshold (weighted penalties) or null (lam for all)
 };
 hipError_t launch_pool_add(const int32_t* set, const int64_t* len_dev, int64_t len_host, int32_t* pool_pos,
                            int32_t* pool_list, int64_t pool_size, int64_t* n_new_out, hipStream_t st);
@@ -169,6 +178,14 @@ struct GcdMultiArgs {
 };
 int gcd_multi_helpers(int64_t m);  // 0: use the single-workgroup solve
 int gcd_multi_resident();          // workgroups of the multi-workgroup solve resident on the device at once
+// Elastic net in the covariance solve: with q_e = sqrt(1 + lam (1 - alpha) w_e) the working set's problem in
+// gamma_e = q_e beta_e is a lasso with unit-diagonal Gram G~ = Q^-1 (G + lam (1 - alpha) W) Q^-1, gradient
+// g~_e = (z_e - lam (1 - alpha) w_e beta_e) / q_e and thresholds lam alpha w_e / q_e (lamv, when w is not null).
+hipError_t launch_enet_scale(const int32_t* set, int64_t m, const double* w, double lam, double alpha, double* GE,
+                             double* g0, double* b0, double* lamv, hipStream_t st);
+// back to beta: b0 /= q, b1 /= q, beta[set[e]] = b1[e]
+hipError_t launch_enet_unscale(const int32_t* set, int64_t m, const double* w, double lam, double alpha, double* b0,
+                               double* b1, double* beta, hipStream_t st);
 int64_t gram_cd_max();              // largest working set of the covariance solve
 size_t gcd_multi_sync_words(int H);
 hipError_t launch_gcd_multi(const GcdMultiArgs& a, hipStream_t st);

@@ -370,7 +370,7 @@ __global__ __launch_bounds__(512) void k_scan(const XT* __restrict__ X, int64_t 
             double z = kept ? (dot - a.c[j] * sum_r) * inv_n / a.s[j] : 0.0;
             a.z[j] = z;
             if (a.check && kept && (a.in_s == nullptr || a.in_s[j]) && (a.excl == nullptr || a.excl[j] == 0) &&
-                fabs(z) > a.lam) {
+                fabs(z) > (a.w ? a.lam * a.w[j] : a.lam)) {
                 a.mark[j] = 1;
                 atomicAdd(a.nviol, 1u);
             }
@@ -455,15 +455,21 @@ __global__ void k_bedpp(int64_t p, const double* __restrict__ a, const double* _
 
 __global__ void k_ssr(int64_t p, const uint8_t* __restrict__ safe, const uint8_t* __restrict__ active,
                       const double* __restrict__ beta, const double* __restrict__ zprev, int ssr, double thr,
-                      uint8_t* __restrict__ strong) {
+                      const double* __restrict__ w, uint8_t* __restrict__ strong) {
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < p; j += (int64_t)gridDim.x * blockDim.x) {
         uint8_t out = 0;
         if (safe[j]) {
             bool act = active ? active[j] != 0 : (beta ? beta[j] != 0.0 : false);
-            out = (!ssr || act || (zprev && fabs(zprev[j]) >= thr)) ? 1 : 0;
+            out = (!ssr || act || (zprev && fabs(zprev[j]) >= (w ? thr * w[j] : thr))) ? 1 : 0;
         }
         strong[j] = out;
     }
+}
+
+__global__ void k_enet_lmax_terms(const double* __restrict__ a, const double* __restrict__ w, double alpha, int64_t p,
+                                  double* __restrict__ out) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < p; j += (int64_t)gridDim.x * blockDim.x)
+        out[j] = fabs(a[j]) / (alpha * (w ? w[j] : 1.0));
 }
 
 // ---- ordered compaction of a byte mask -------------------------------------------------------------
@@ -585,7 +591,7 @@ __global__ __launch_bounds__(CD_THREADS) void k_cd(const XT* __restrict__ X, int
     if (m > 0) {
         // Register ring with the next D coordinates: column values, center, 1/scale.
         double xr[D][R];
-        double cr[D], sr[D];
+        double cr[D], sr[D], wr[D];
         int64_t pf = 0;  // set position of the next coordinate to prefetch
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -593,6 +599,7 @@ __global__ __launch_bounds__(CD_THREADS) void k_cd(const XT* __restrict__ X, int
             pf = (pf + 1 == m) ? 0 : pf + 1;
             cr[d] = a.c[j];
             sr[d] = 1.0 / a.s[j];
+            wr[d] = a.w ? a.w[j] : 1.0;
             const __amdgpu_buffer_rsrc_t rs = column_rsrc(X + (int64_t)j * ldx, n_total * (int64_t)sizeof(XT));
 #pragma unroll
             for (int q = 0; q < R; ++q)
@@ -632,7 +639,9 @@ __global__ __launch_bounds__(CD_THREADS) void k_cd(const XT* __restrict__ X, int
                     if (pend_pos == pos) bj = pend_val;
                     if (tid == 0) bwin[pend_pos] = pend_val;
                 }
-                const double bnew = soft_threshold(dot * isj * inv_n + bj, lam);
+                // elastic-net step S(u, lam alpha w) / (1 + lam (1 - alpha) w); the lasso step when alpha = 1, w = 1
+                const double bnew = soft_threshold(dot * isj * inv_n + bj, lam * a.alpha * wr[d]) /
+                                    (1.0 + lam * (1.0 - a.alpha) * wr[d]);
                 const double delta = bnew - bj;
                 pend = delta != 0.0;
                 if (pend) {
@@ -650,6 +659,7 @@ __global__ __launch_bounds__(CD_THREADS) void k_cd(const XT* __restrict__ X, int
                     pf = (pf + 1 == m) ? 0 : pf + 1;
                     cr[d] = a.c[j];
                     sr[d] = 1.0 / a.s[j];
+                    wr[d] = a.w ? a.w[j] : 1.0;
                     const __amdgpu_buffer_rsrc_t rs =
                         column_rsrc(X + (int64_t)j * ldx, n_total * (int64_t)sizeof(XT));
 #pragma unroll
@@ -720,10 +730,12 @@ __global__ __launch_bounds__(1024) void k_record(const int32_t* __restrict__ set
                                                  const int64_t* __restrict__ len_scan,
                                                  const double* __restrict__ beta, const double* __restrict__ c,
                                                  const double* __restrict__ s, const DevScalars* __restrict__ sc,
-                                                 double lam, LamStats* __restrict__ out) {
+                                                 double lam, LamStats* __restrict__ out, double alpha,
+                                                 const double* __restrict__ w) {
     __shared__ double buf[16];
     const int64_t m = set ? *len_dev : 0;
-    double l1 = 0.0, cb = 0.0, na = 0.0;
+    const bool enet = alpha < 1.0 || w != nullptr;
+    double l1 = 0.0, cb = 0.0, na = 0.0, pen = 0.0;
     for (int64_t t = threadIdx.x; t < m; t += blockDim.x) {
         const int j = set[t];
         const double b = beta[j];
@@ -731,18 +743,20 @@ __global__ __launch_bounds__(1024) void k_record(const int32_t* __restrict__ set
             l1 += fabs(b);
             cb += c[j] * b / s[j];
             na += 1.0;
+            if (enet) pen += (w ? w[j] : 1.0) * (alpha * fabs(b) + 0.5 * (1.0 - alpha) * b * b);
         }
     }
     double tl1 = block_sum(l1, buf);
     double tcb = block_sum(cb, buf);
     double tna = block_sum(na, buf);
+    double tpen = enet ? block_sum(pen, buf) : 0.0;
     if (threadIdx.x == 0) {
         const double rss = sc->rss;
         out->rss = rss;
         out->l1 = tl1;
         out->n_active = (int64_t)tna;
         out->intercept = sc->y_mean - tcb;
-        out->obj = rss / (2.0 * (double)sc->n_rows) + lam * tl1;
+        out->obj = rss / (2.0 * (double)sc->n_rows) + lam * (enet ? tpen : tl1);
         out->n_strong = m;
         out->n_safe = len_safe ? *len_safe : 0;
         out->n_scan = len_scan ? *len_scan : 0;
@@ -894,9 +908,15 @@ hipError_t launch_bedpp(int64_t p, const double* a, const double* b, const uint8
 }
 
 hipError_t launch_ssr(int64_t p, const uint8_t* safe, const uint8_t* active, const double* beta, const double* zprev,
-                      bool ssr, double thr, uint8_t* strong, hipStream_t st) {
+                      bool ssr, double thr, uint8_t* strong, hipStream_t st, const double* w) {
     const int g = grid_for(p, 256, device_cu_count() * 8);
-    k_ssr<<<g, 256, 0, st>>>(p, safe, active, beta, zprev, ssr ? 1 : 0, thr, strong);
+    k_ssr<<<g, 256, 0, st>>>(p, safe, active, beta, zprev, ssr ? 1 : 0, thr, w, strong);
+    return hipGetLastError();
+}
+
+hipError_t launch_enet_lmax_terms(const double* a, const double* w, double alpha, int64_t p, double* out,
+                                  hipStream_t st) {
+    k_enet_lmax_terms<<<grid_for(p, 256, 4096), 256, 0, st>>>(a, w, alpha, p, out);
     return hipGetLastError();
 }
 
@@ -943,8 +963,8 @@ hipError_t launch_cd(const Mat& m, const CdArgs& a, hipStream_t st) {
 
 hipError_t launch_record(const int32_t* set, const int64_t* len_dev, const int64_t* len_safe, const int64_t* len_scan,
                          const double* beta, const double* c, const double* s, const DevScalars* sc, double lam,
-                         LamStats* out, hipStream_t st) {
-    k_record<<<1, 1024, 0, st>>>(set, len_dev, len_safe, len_scan, beta, c, s, sc, lam, out);
+                         LamStats* out, hipStream_t st, double alpha, const double* w) {
+    k_record<<<1, 1024, 0, st>>>(set, len_dev, len_safe, len_scan, beta, c, s, sc, lam, out, alpha, w);
     return hipGetLastError();
 }
 
