@@ -325,6 +325,29 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
                       bl_path_result* res);
 
 /*
+ * The path with X in host memory (Section 2.1: the package keeps X, which may exceed RAM, in a memory-
+ * mapped file and streams what each step needs; here X may exceed the GPU's memory and stays in host
+ * memory).  X->X is a HOST pointer: memory from hipHostMalloc (pinned) moves at full PCIe speed, pageable
+ * memory works but slower.  y, X->row_mask and every output are device arrays as for bl_fit_path.  Column
+ * panels of hs->panel_cols columns (0: about 512 MB per panel) are copied to the device on a library stream,
+ * two in flight, while the previous panel is scanned: the set-up passes stream every panel, and each check
+ * scan only the panels holding a BEDPP survivor (panels of discarded features are never moved).  Columns
+ * that enter a working set are kept in a device cache, which their Gram entries and the residual updates
+ * read.  The results equal bl_fit_path's on the same X in device memory bit for bit.  FP64 scans only, no
+ * learned rule; working sets must stay within the covariance solve's limits (bl_limits), and a resume
+ * needs r_init (BL_ERR_UNSUPPORTED otherwise).  hs (may be NULL) receives the streaming counters.
+ */
+typedef struct {
+    int64_t panel_cols;        /* in: columns per panel (0: about 512 MB); out: the value used           */
+    int64_t panels_streamed;   /* out: panel copies to the device                                        */
+    int64_t panels_skipped;    /* out: panels scans did not need (no listed column in them)               */
+    double bytes_streamed;     /* out: host-to-device bytes (panels, cached columns, the BEDPP column)    */
+} bl_host_stream;
+
+bl_status bl_fit_path_host(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_path_opts* opts,
+                           bl_host_stream* hs, bl_path_result* res);
+
+/*
  * Batched form: nprob <= 64 lasso problems over one design matrix (Section 3.1.2:
  * cross-validation fits and several responses share X; each problem selects its
  * rows with its own mask instead of copying X).  Problem b has its own response,

@@ -32,7 +32,7 @@ _STATUS_NAMES = {0: "BL_OK", 1: "BL_ERR_INVALID", 2: "BL_ERR_NOMEM", 3: "BL_ERR_
 EXPORTS = ("bl_create", "bl_destroy", "bl_last_error", "bl_device_info", "bl_standardize", "bl_lambda_max",
            "bl_bedpp_setup", "bl_screen", "bl_cd_solve", "bl_kkt_check", "bl_scan", "bl_fit_path",
            "bl_fit_path_batch", "bl_mlp_forward", "bl_mlp_loss_grad", "bl_mlp_train", "bl_profile", "bl_profile_get",
-           "bl_get_limits", "bl_set_limits", "bl_kkt_check_noalloc", "bl_cv_fit")
+           "bl_get_limits", "bl_set_limits", "bl_kkt_check_noalloc", "bl_cv_fit", "bl_fit_path_host")
 NOALLOC_MAX_P = 4194304
 MLP_HIDDEN = 64
 MLP_NPARAMS = MLP_HIDDEN * MLP_HIDDEN + 7 * MLP_HIDDEN + 1
@@ -81,6 +81,11 @@ class _CvResult(ctypes.Structure):
                 ("fold_err", ctypes.c_void_p), ("k_min", ctypes.c_int32), ("k_1se", ctypes.c_int32),
                 ("lambda_min", ctypes.c_double), ("lambda_1se", ctypes.c_double), ("n_rows", ctypes.c_int64),
                 ("k_done", ctypes.c_int32), ("time_ms", ctypes.c_double)]
+
+
+class _HostStream(ctypes.Structure):
+    _fields_ = [("panel_cols", ctypes.c_int64), ("panels_streamed", ctypes.c_int64),
+                ("panels_skipped", ctypes.c_int64), ("bytes_streamed", ctypes.c_double)]
 
 
 class _Limits(ctypes.Structure):
@@ -157,6 +162,7 @@ def load_library(path: str = LIB_PATH):
     L.bl_profile.argtypes = [vp, ctypes.c_int]
     L.bl_profile_get.argtypes = [vp, ctypes.c_int, P(_KernelProfile)]
     L.bl_cv_fit.argtypes = [vp, P(_Matrix), P(_Cv), P(_PathOpts), P(_CvResult)]
+    L.bl_fit_path_host.argtypes = [vp, P(_Matrix), vp, P(_PathOpts), P(_HostStream), P(_PathResult)]
     L.bl_get_limits.argtypes = [vp, P(_Limits)]
     L.bl_set_limits.argtypes = [vp, P(_Limits)]
     for name in EXPORTS:
@@ -404,6 +410,37 @@ def fit_path(ctx: Context, Xt, y, nlambda=100, lambda_min_ratio=0.1, lambdas=Non
     optionally r_init (float64 device [n_total], its residual); r_out receives the final residual.
     Elastic net: alpha in (0, 1] and penalty_factor (float64 device [p], positive) or None."""
     M = matrix(Xt, n_total, row_mask)
+    return _fit_path(ctx, M, y, nlambda, lambda_min_ratio, lambdas, rule, tol, max_sweeps, max_rounds, want_beta,
+                     raise_on_error, precision, mlp, mlp_tau, rec_feat, rec_label, k_start, beta_init, r_init, r_out,
+                     alpha, penalty_factor, None)
+
+
+def fit_path_host(ctx: Context, Xt, y, nlambda=100, lambda_min_ratio=0.1, lambdas=None, rule=SCREEN_SSR_BEDPP,
+                  tol=1e-8, max_sweeps=100000, max_rounds=100, row_mask=None, n_total=None, want_beta=True,
+                  raise_on_error=True, k_start=0, beta_init=None, r_init=None, r_out=None, alpha=1.0,
+                  penalty_factor=None, panel_cols=0, precision=PREC_FP64):
+    """The path with X in host memory (bl_fit_path_host): Xt is a CPU tensor (p, ld), pinned for full PCIe
+    speed; y, row_mask and the outputs are on the device.  Returns (PathResult, streaming counters)."""
+    if Xt.dim() != 2 or Xt.is_cuda:
+        raise ValueError("Xt must be a 2-D CPU tensor (p, ld)")
+    if Xt.dtype not in _XTYPES or not Xt.is_contiguous():
+        raise TypeError("Xt must be a contiguous float64, float32 or int8 tensor")
+    p, ld = Xt.shape
+    nt = ld if n_total is None else int(n_total)
+    if row_mask is not None and (row_mask.dtype != torch.uint8 or row_mask.numel() != nt):
+        raise ValueError("row_mask must be uint8 with n_total entries")
+    M = _Matrix(ctypes.c_void_p(Xt.data_ptr()), _XTYPES[Xt.dtype], nt, p, ld, _ptr(row_mask))
+    hs = _HostStream(int(panel_cols), 0, 0, 0.0)
+    res = _fit_path(ctx, M, y, nlambda, lambda_min_ratio, lambdas, rule, tol, max_sweeps, max_rounds, want_beta,
+                    raise_on_error, precision, None, 0.0, None, None, k_start, beta_init, r_init, r_out, alpha,
+                    penalty_factor, hs)
+    return res, {"panel_cols": hs.panel_cols, "panels_streamed": hs.panels_streamed,
+                 "panels_skipped": hs.panels_skipped, "bytes_streamed": hs.bytes_streamed}
+
+
+def _fit_path(ctx, M, y, nlambda, lambda_min_ratio, lambdas, rule, tol, max_sweeps, max_rounds, want_beta,
+              raise_on_error, precision, mlp, mlp_tau, rec_feat, rec_label, k_start, beta_init, r_init, r_out,
+              alpha, penalty_factor, hs) -> PathResult:
     K = int(nlambda)
     p = M.p
     dev = _dev(ctx)
@@ -436,7 +473,11 @@ def fit_path(ctx: Context, Xt, y, nlambda=100, lambda_min_ratio=0.1, lambdas=Non
                       host["sweeps"].ctypes.data, host["rounds"].ctypes.data, host["n_active"].ctypes.data,
                       host["n_strong"].ctypes.data, host["n_safe"].ctypes.data, host["n_viol"].ctypes.data,
                       host["n_scanned"].ctypes.data, host["n_recheck"].ctypes.data, 0.0, 0.0, 0, 0, 0.0, 0)
-    st = load_library().bl_fit_path(ctx.handle, ctypes.byref(M), _ptr(y), ctypes.byref(opts), ctypes.byref(res))
+    if hs is None:
+        st = load_library().bl_fit_path(ctx.handle, ctypes.byref(M), _ptr(y), ctypes.byref(opts), ctypes.byref(res))
+    else:
+        st = load_library().bl_fit_path_host(ctx.handle, ctypes.byref(M), _ptr(y), ctypes.byref(opts),
+                                             ctypes.byref(hs), ctypes.byref(res))
     msg = load_library().bl_last_error(ctx.handle).decode(errors="replace") if st != BL_OK else ""
     if st != BL_OK and raise_on_error:
         raise BLError(st, msg)

@@ -165,12 +165,242 @@ bl_status pool_reserve(bl_ctx ctx, int64_t need) {
     return BL_OK;
 }
 
+// X as the path reads it: resident in HBM (m.X a device pointer), or in host memory (host = true), streamed
+// to the device in panels of panel_cols columns (column-major, so a panel is one contiguous copy).
+struct XAccess {
+    Mat m;
+    bool host = false;
+    int64_t panel_cols = 0;
+    bl_host_stream* hs = nullptr;   // streaming counters (host X)
+};
+
+size_t x_es(const Mat& m) { return (size_t)elem_bytes(m.xtype); }
+
+// the two panel buffers, their events and the copy stream (all library-owned, default priority)
+bl_status panels_ready(bl_ctx ctx, const XAccess& xa) {
+    const size_t bytes = (size_t)xa.panel_cols * (size_t)xa.m.ldx * x_es(xa.m);
+    if (ctx->panel_cap < bytes) {
+        for (int b = 0; b < 2; ++b) {
+            if (ctx->panel[b]) (void)hipFree(ctx->panel[b]);
+            ctx->panel[b] = nullptr;
+        }
+        ctx->panel_cap = 0;
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        ctx->panel_used[0] = ctx->panel_used[1] = false;
+        for (int b = 0; b < 2; ++b)
+            if (hipMalloc(&ctx->panel[b], bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(ctx, BL_ERR_NOMEM, "panel buffers of %zu bytes do not fit", bytes);
+            }
+        ctx->panel_cap = bytes;
+    }
+    for (int b = 0; b < 2; ++b) {
+        if (!ctx->ev_copy[b]) HIPCHK(hipEventCreateWithFlags(&ctx->ev_copy[b], hipEventDisableTiming));
+        if (!ctx->ev_free[b]) HIPCHK(hipEventCreateWithFlags(&ctx->ev_free[b], hipEventDisableTiming));
+    }
+    if (!ctx->aux) HIPCHK(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+    return BL_OK;
+}
+
+// Stream the panels holding the columns [j0, j1) of each listed range, two in flight: panel i is copied on
+// the aux stream into buffer i mod 2 once the main stream has finished with that buffer, and the main
+// stream runs fn(panel device pointer, j0, j1) after the copy.  fn enqueues its kernels on ctx->stream.
+template <typename Fn>
+bl_status stream_panels(bl_ctx ctx, const XAccess& xa, const std::vector<std::pair<int64_t, int64_t>>& ranges, Fn fn) {
+    bl_status s;
+    if ((s = panels_ready(ctx, xa))) return s;
+    const size_t col_bytes = (size_t)xa.m.ldx * x_es(xa.m);
+    bool* used = ctx->panel_used;   // across calls: a buffer may still be read by the last call's kernels
+    for (size_t i = 0; i < ranges.size(); ++i) {
+        const int b = (int)(i & 1);
+        const int64_t j0 = ranges[i].first, j1 = ranges[i].second;
+        if (used[b]) HIPCHK(hipStreamWaitEvent(ctx->aux, ctx->ev_free[b], 0));
+        const size_t bytes = (size_t)(j1 - j0) * col_bytes;
+        HIPCHK(hipMemcpyAsync(ctx->panel[b], (const char*)xa.m.X + (size_t)j0 * col_bytes, bytes, hipMemcpyHostToDevice,
+                              ctx->aux));
+        HIPCHK(hipEventRecord(ctx->ev_copy[b], ctx->aux));
+        HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->ev_copy[b], 0));
+        if ((s = fn(ctx->panel[b], j0, j1))) return s;
+        HIPCHK(hipEventRecord(ctx->ev_free[b], ctx->stream));
+        used[b] = true;
+        if (xa.hs) {
+            xa.hs->panels_streamed += 1;
+            xa.hs->bytes_streamed += (double)bytes;
+        }
+    }
+    return BL_OK;
+}
+
+// every panel of X
+std::vector<std::pair<int64_t, int64_t>> all_panels(const XAccess& xa) {
+    std::vector<std::pair<int64_t, int64_t>> out;
+    for (int64_t j0 = 0; j0 < xa.m.p; j0 += xa.panel_cols) out.emplace_back(j0, std::min(xa.m.p, j0 + xa.panel_cols));
+    return out;
+}
+
+// column statistics of every column
+bl_status x_colstats(bl_ctx ctx, const XAccess& xa, double* c, double* sd, uint8_t* keep, int64_t n) {
+    if (!xa.host) {
+        HIPCHK(launch_colstats(xa.m, c, sd, keep, n, ctx->stream));
+        return BL_OK;
+    }
+    return stream_panels(ctx, xa, all_panels(xa), [&](void* buf, int64_t j0, int64_t j1) -> bl_status {
+        Mat pm = xa.m;
+        pm.X = buf;
+        pm.p = j1 - j0;
+        HIPCHK(launch_colstats(pm, c + j0, sd + j0, keep + j0, n, ctx->stream));
+        return BL_OK;
+    });
+}
+
+// identity column list 0..p-1 (device), for scans of every column of a panel
+bl_status ident_list(bl_ctx ctx, int64_t p, int32_t** out) {
+    DevBuf& b = ctx->bufs[H_IDENT];
+    const bool fresh = b.cap < (size_t)p * 4;
+    int32_t* id;
+    ENSURE(H_IDENT, p * 4, id);
+    if (fresh || ctx->ident_len < p) {
+        std::vector<int32_t> h(p);
+        for (int64_t j = 0; j < p; ++j) h[j] = (int32_t)j;
+        HIPCHK(hipMemcpyAsync(id, h.data(), p * 4, hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        ctx->ident_len = p;
+    }
+    *out = id;
+    return BL_OK;
+}
+
+// the scan of ScanArgs a (kernels.hip) over X wherever it lives.  Host X: the listed columns' panels only
+// (BEDPP survivors steer which panels move); each panel's launch reads the columns through a pointer
+// offset so that global column indices address the panel buffer.
+bl_status x_scan(bl_ctx ctx, const XAccess& xa, const ScanArgs& a) {
+    hipStream_t st = ctx->stream;
+    if (!xa.host) {
+        HIPCHK(launch_scan(xa.m, a, st));
+        return BL_OK;
+    }
+    const int64_t p = xa.m.p;
+    std::vector<int32_t> hl;
+    const int32_t* cols = a.cols;
+    int64_t len = a.len_host;
+    bl_status s;
+    if (cols) {
+        if (a.len_dev) {
+            HIPCHK(hipMemcpyAsync(&ctx->sc_host->stage, a.len_dev, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            len = ctx->sc_host->stage;
+        }
+        hl.resize((size_t)std::max<int64_t>(len, 1));
+        if (len > 0) {
+            HIPCHK(hipMemcpyAsync(hl.data(), cols, len * 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
+    } else {
+        int32_t* id;
+        if ((s = ident_list(ctx, p, &id))) return s;
+        cols = id;
+    }
+    // the panels that hold listed columns (lists are ascending), with the list range of each
+    std::vector<std::pair<int64_t, int64_t>> ranges;
+    std::vector<std::pair<int64_t, int64_t>> spans;
+    int64_t t = 0;
+    for (int64_t j0 = 0; j0 < p && t < len; j0 += xa.panel_cols) {
+        const int64_t j1 = std::min(p, j0 + xa.panel_cols);
+        const int64_t t0 = t;
+        if (a.cols) {
+            while (t < len && hl[t] < j1) ++t;
+        } else {
+            t = std::min(len, j1);
+        }
+        if (t > t0) {
+            ranges.emplace_back(j0, j1);
+            spans.emplace_back(t0, t);
+        }
+    }
+    if (xa.hs) xa.hs->panels_skipped += (p + xa.panel_cols - 1) / xa.panel_cols - (int64_t)ranges.size();
+    size_t k = 0;
+    s = stream_panels(ctx, xa, ranges, [&](void* buf, int64_t j0, int64_t j1) -> bl_status {
+        (void)j1;
+        Mat pm = xa.m;
+        pm.X = (const char*)buf - (ptrdiff_t)((size_t)j0 * (size_t)xa.m.ldx * x_es(xa.m));
+        ScanArgs pa = a;
+        pa.cols = cols + spans[k].first;
+        pa.len_dev = nullptr;
+        pa.len_host = spans[k].second - spans[k].first;
+        pa.len_out = nullptr;
+        ++k;
+        HIPCHK(launch_scan(pm, pa, ctx->stream));
+        return BL_OK;
+    });
+    if (s) return s;
+    if (a.len_out) {
+        ctx->sc_host->stage = len;
+        HIPCHK(hipMemcpyAsync(a.len_out, &ctx->sc_host->stage, sizeof(int64_t), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    return BL_OK;
+}
+
+// v = standardized column j (fitted rows) wherever X lives
+bl_status x_std_column(bl_ctx ctx, const XAccess& xa, int64_t j, const double* c, const double* sd, double* v) {
+    if (!xa.host) {
+        HIPCHK(launch_std_column(xa.m, j, c, sd, v, ctx->stream));
+        return BL_OK;
+    }
+    void* col;
+    const size_t cb = (size_t)xa.m.ldx * x_es(xa.m);
+    ENSURE(H_COL, cb, col);
+    HIPCHK(hipMemcpyAsync(col, (const char*)xa.m.X + (size_t)j * cb, cb, hipMemcpyHostToDevice, ctx->stream));
+    Mat pm = xa.m;
+    pm.X = col;
+    pm.p = 1;
+    HIPCHK(launch_std_column(pm, 0, c + j, sd + j, v, ctx->stream));
+    if (xa.hs) xa.hs->bytes_streamed += (double)cb;
+    return BL_OK;
+}
+
 // Cyclic CD at lambda over set[0..m) (length also at *len_dev), warm-started from beta and r.
 // z[j] must hold x~_j' r / n at the current r for every j of the set.  Updates beta, r,
 // sc->sum_r, sc->rss and sc->round.{sweeps, status, cd_len}.
-bl_status solve_set(bl_ctx ctx, const Mat& mt, const int32_t* set, const int64_t* len_dev, int64_t m,
+// Host X: the device cache of the pool features' columns (pool order), grown keeping its contents.
+// The column bytes are those of the current X: a cache laid out for another X is rebuilt (the pool, which the
+// cache follows, starts empty on every path).
+bl_status xcache_reserve(bl_ctx ctx, const XAccess& xa, int64_t need) {
+    const size_t cb = (size_t)xa.m.ldx * x_es(xa.m);
+    const bool same = cb == ctx->xcache_cb;
+    if (need <= ctx->xcache_cap && same) return BL_OK;
+    const int64_t keep = same ? ctx->pool_size : 0;
+    int64_t cap = std::max<int64_t>({need, same ? 2 * ctx->xcache_cap : 0, 256});
+    void* nb = nullptr;
+    double *nc = nullptr, *ns = nullptr;
+    if (hipMalloc(&nb, (size_t)cap * cb) != hipSuccess || hipMalloc((void**)&nc, (size_t)cap * 8) != hipSuccess ||
+        hipMalloc((void**)&ns, (size_t)cap * 8) != hipSuccess) {
+        (void)hipGetLastError();
+        if (nb) (void)hipFree(nb);
+        if (nc) (void)hipFree(nc);
+        return fail(ctx, BL_ERR_NOMEM, "device cache of %lld columns does not fit", (long long)cap);
+    }
+    if (keep > 0) {
+        HIPCHK(hipMemcpyAsync(nb, ctx->xcache, (size_t)keep * cb, hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(nc, ctx->xcache_c, (size_t)keep * 8, hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(ns, ctx->xcache_s, (size_t)keep * 8, hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (ctx->xcache) (void)hipFree(ctx->xcache);
+    if (ctx->xcache_c) (void)hipFree(ctx->xcache_c);
+    if (ctx->xcache_s) (void)hipFree(ctx->xcache_s);
+    ctx->xcache = nb;
+    ctx->xcache_c = nc;
+    ctx->xcache_s = ns;
+    ctx->xcache_cap = cap;
+    ctx->xcache_cb = cb;
+    return BL_OK;
+}
+
+bl_status solve_set(bl_ctx ctx, const XAccess& xa, const int32_t* set, const int64_t* len_dev, int64_t m,
                     const double* z, double* beta, double* r, const double* c, const double* s, double n_rows,
                     double lam, double tol, int max_sweeps, double alpha = 1.0, const double* w = nullptr) {
+    const Mat& mt = xa.m;
     hipStream_t st = ctx->stream;
     const double es = (double)elem_bytes(mt.xtype);
     const bool enet = alpha < 1.0 || w != nullptr;
@@ -182,6 +412,9 @@ bl_status solve_set(bl_ctx ctx, const Mat& mt, const int32_t* set, const int64_t
     const bool cov = m <= ctx->cov_max && (multi_ok || m <= GCD_MAX);
     if (!multi_ok) H = 0;
     ctx->last_residual = !cov;
+    if (!cov && xa.host)
+        return fail(ctx, BL_ERR_UNSUPPORTED, "X in host memory: working set of %lld features above the covariance "
+                    "solve's limits", (long long)m);
     if (!cov) {
         if (!cd_supported(mt.n_total))
             return fail(ctx, BL_ERR_UNSUPPORTED, "working set of %lld features with n_total %lld is too large",
@@ -220,8 +453,45 @@ bl_status solve_set(bl_ctx ctx, const Mat& mt, const int32_t* set, const int64_t
     const int64_t n_new = ctx->sc_host->n_new;
     bl_status s_;
     if ((s_ = pool_reserve(ctx, ctx->pool_size + n_new))) return s_;
-    HIPCHK(launch_gram_update(mt, list, ctx->pool_size + n_new, ctx->pool_size, n_new, c, s, n_rows, ctx->gpool,
-                              ctx->pool_cap, st));
+    // the residual update below reads X through (Mat, set, c, s); with X in host memory those are the cache
+    Mat xm = mt;
+    const int32_t* xset = set;
+    const double *xc = c, *xs = s;
+    if (!xa.host) {
+        HIPCHK(launch_gram_update(mt, list, ctx->pool_size + n_new, ctx->pool_size, n_new, c, s, n_rows, ctx->gpool,
+                                  ctx->pool_cap, st));
+    } else {
+        // copy the new pool features' columns into the cache (pool order) with their statistics, then
+        // take the Gram entries from the cache in pool order: the same tiles over the same columns
+        if ((s_ = xcache_reserve(ctx, xa, ctx->pool_size + n_new))) return s_;
+        double* cc = ctx->xcache_c;
+        double* scc = ctx->xcache_s;
+        int32_t *id, *setc;
+        ENSURE(H_SETC, (size_t)(m + 1) * 4, setc);
+        const size_t cb = (size_t)mt.ldx * x_es(mt);
+        if (n_new > 0) {
+            std::vector<int32_t> hj(n_new);
+            HIPCHK(hipMemcpyAsync(hj.data(), list + ctx->pool_size, n_new * 4, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (int64_t t = 0; t < n_new; ++t)
+                HIPCHK(hipMemcpyAsync((char*)ctx->xcache + (size_t)(ctx->pool_size + t) * cb,
+                                      (const char*)mt.X + (size_t)hj[t] * cb, (size_t)mt.n_total * x_es(mt),
+                                      hipMemcpyHostToDevice, st));
+            if (xa.hs) xa.hs->bytes_streamed += (double)n_new * (double)mt.n_total * (double)x_es(mt);
+            HIPCHK(launch_gather_start(list + ctx->pool_size, n_new, c, s, cc + ctx->pool_size, scc + ctx->pool_size,
+                                       st));
+        }
+        bl_status si;
+        if ((si = ident_list(ctx, std::max<int64_t>(ctx->xcache_cap, 1), &id))) return si;
+        xm.X = ctx->xcache;
+        xm.p = ctx->xcache_cap;
+        HIPCHK(launch_gram_update(xm, id, ctx->pool_size + n_new, ctx->pool_size, n_new, cc, scc, n_rows, ctx->gpool,
+                                  ctx->pool_cap, st));
+        HIPCHK(launch_map_pos(set, m, pos, setc, st));
+        xset = setc;
+        xc = cc;
+        xs = scc;
+    }
     const double gram_bytes = (double)(ctx->pool_size + 2 * n_new) * mt.n_total * es + (double)m * m * 8.0;
     ctx->pool_size += n_new;
     HIPCHK(launch_gather_gram(set, m, pos, ctx->gpool, ctx->pool_cap, GE, st));
@@ -281,7 +551,7 @@ bl_status solve_set(bl_ctx ctx, const Mat& mt, const int32_t* set, const int64_t
     }
     if (enet) HIPCHK(launch_enet_unscale(set, m, w, lam, alpha, b0, b1, beta, st));
     prof_mark(ctx, 6);
-    HIPCHK(launch_r_update(mt, set, m, b0, b1, c, s, part, r, st));
+    HIPCHK(launch_r_update(xm, xset, m, b0, b1, xc, xs, part, r, st));
     HIPCHK(launch_sum_r(mt, r, ctx->sc, true, st));
     prof_mark(ctx, 7);
     ctx->pend_gram_bytes = gram_bytes;
@@ -357,6 +627,14 @@ void bl_destroy(bl_ctx c) {
         if (b.p) (void)hipFree(b.p);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
+    for (int b = 0; b < 2; ++b) {
+        if (c->panel[b]) (void)hipFree(c->panel[b]);
+        if (c->ev_copy[b]) (void)hipEventDestroy(c->ev_copy[b]);
+        if (c->ev_free[b]) (void)hipEventDestroy(c->ev_free[b]);
+    }
+    if (c->xcache) (void)hipFree(c->xcache);
+    if (c->xcache_c) (void)hipFree(c->xcache_c);
+    if (c->xcache_s) (void)hipFree(c->xcache_s);
     if (c->gpool) (void)hipFree(c->gpool);
     if (c->bgpool) (void)hipFree(c->bgpool);
     if (c->bpinned) (void)hipHostFree(c->bpinned);
@@ -559,7 +837,9 @@ bl_status bl_cd_solve(bl_ctx ctx, const bl_matrix* X, const double* center, cons
         HIPCHK(launch_scan(m, sa, ctx->stream));
     }
     if ((s = pool_reset(ctx, m.p))) return s;
-    if ((s = solve_set(ctx, m, set, nullptr, set_len, zs, beta, r, center, scale, (double)n, lambda, tol,
+    XAccess xa;
+    xa.m = m;
+    if ((s = solve_set(ctx, xa, set, nullptr, set_len, zs, beta, r, center, scale, (double)n, lambda, tol,
                        max_sweeps)))
         return s;
     if ((s = read_scalars(ctx))) return s;
@@ -676,13 +956,16 @@ bl_status bl_scan(bl_ctx ctx, const bl_matrix* X, const double* center, const do
     return BL_OK;
 }
 
-bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_path_opts* opts,
-                      bl_path_result* res) {
+}  // extern "C"
+
+namespace {
+
+// The path over X wherever it lives (XAccess): bl_fit_path (X in HBM) and bl_fit_path_host (X in host memory).
+bl_status fit_path_impl(bl_ctx ctx, const XAccess& xa, const double* y, const bl_path_opts* opts,
+                        bl_path_result* res) {
     auto t_start = std::chrono::steady_clock::now();
-    bl_status s = check_ctx(ctx);
-    if (s) return s;
-    Mat m;
-    if ((s = check_matrix(ctx, X, &m))) return s;
+    bl_status s;
+    const Mat& m = xa.m;
     if (!y || !opts || !res) return fail(ctx, BL_ERR_INVALID, "y/opts/res must be non-NULL");
     res->k_done = 0;
     const int K = opts->nlambda;
@@ -801,7 +1084,7 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
     const double es = (double)elem_bytes(m.xtype);
     const double col_bytes = (double)nt * es;
     prof_mark(ctx, 0);
-    HIPCHK(launch_colstats(m, c, sc_, keep, n, st));
+    if ((s = x_colstats(ctx, xa, c, sc_, keep, n))) return s;
     prof_mark(ctx, 1);
     HIPCHK(launch_center_y(m, y, yt, r, ctx->sc, st));
     HIPCHK(launch_sum_r(m, yt, ctx->sc, true, st));
@@ -814,7 +1097,7 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
     sa.keep = keep;
     sa.z = a;
     prof_mark(ctx, 2);
-    HIPCHK(launch_scan(m, sa, st));
+    if ((s = x_scan(ctx, xa, sa))) return s;
     prof_mark(ctx, 3);
     HIPCHK(launch_argmax_abs(a, keep, p, pv, pi, ctx->sc, st));
     if ((s = read_scalars(ctx))) return s;
@@ -846,12 +1129,12 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         sgn = ctx->sc_host->rss < 0 ? -1.0 : 1.0;
     }
     if (bedpp) {
-        HIPCHK(launch_std_column(m, jstar, c, sc_, xs, st));
+        if ((s = x_std_column(ctx, xa, jstar, c, sc_, xs))) return s;
         HIPCHK(launch_sum_r(m, xs, ctx->sc, false, st));
         sa.r = xs;
         sa.z = b;
         prof_mark(ctx, 2);
-        HIPCHK(launch_scan(m, sa, st));
+        if ((s = x_scan(ctx, xa, sa))) return s;
         prof_mark(ctx, 3);
         HIPCHK(hipStreamSynchronize(st));
         prof_add(ctx, 2, setup_slot, (double)p * col_bytes + nt * 8.0, 0.0, (double)p);
@@ -899,6 +1182,8 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         HIPCHK(hipMemcpyAsync(beta, opts->beta_init, p * 8, hipMemcpyDeviceToDevice, st));
         if (opts->r_init) {
             HIPCHK(hipMemcpyAsync(r, opts->r_init, nt * 8, hipMemcpyDeviceToDevice, st));
+        } else if (xa.host) {
+            return fail(ctx, BL_ERR_UNSUPPORTED, "X in host memory: resuming needs r_init");
         } else {
             // r = y~ - X~ beta over the nonzero coefficients (the strong-rule test with an infinite
             // threshold keeps the kept features with beta_j != 0)
@@ -933,7 +1218,7 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
         za.s = sc_;
         za.keep = keep;
         za.z = z1;
-        HIPCHK(launch_scan(m, za, st));
+        if ((s = x_scan(ctx, xa, za))) return s;
         zprev = z1;
         zcur = z0;
         k_first = k_start;
@@ -988,7 +1273,7 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
                 HIPCHK(launch_scan(m, ea, st));
                 recheck_total += m_len;
             }
-            if ((s = solve_set(ctx, m, lE, lens + 0, m_len, zsrc, beta, r, c, sc_, (double)n, lk, opts->tol,
+            if ((s = solve_set(ctx, xa, lE, lens + 0, m_len, zsrc, beta, r, c, sc_, (double)n, lk, opts->tol,
                                opts->max_sweeps, alpha, pf)))
                 return s;
             HIPCHK(hipMemsetAsync(&ctx->sc->round.n_viol, 0, sizeof(uint32_t), st));
@@ -1011,7 +1296,7 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
                 ka.nviol = &ctx->sc->round.n_viol;
                 ka.len_out = &ctx->sc->round.scan_len;
                 prof_mark(ctx, 2);
-                HIPCHK(launch_scan(m, ka, st));
+                if ((s = x_scan(ctx, xa, ka))) return s;
                 prof_mark(ctx, 3);
             } else {
                 // matrix-core scan, then exact FP64 re-scans of the values near a threshold
@@ -1133,6 +1418,44 @@ bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_
     }
     res->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     return final_status;
+}
+
+}  // namespace
+
+extern "C" {
+
+bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_path_opts* opts,
+                      bl_path_result* res) {
+    bl_status s = check_ctx(ctx);
+    if (s) return s;
+    XAccess xa;
+    if ((s = check_matrix(ctx, X, &xa.m))) return s;
+    return fit_path_impl(ctx, xa, y, opts, res);
+}
+
+bl_status bl_fit_path_host(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_path_opts* opts,
+                           bl_host_stream* hs, bl_path_result* res) {
+    bl_status s = check_ctx(ctx);
+    if (s) return s;
+    XAccess xa;
+    if ((s = check_matrix(ctx, X, &xa.m))) return s;
+    if (!opts || !res) return fail(ctx, BL_ERR_INVALID, "opts/res must be non-NULL");
+    if (opts->precision != BL_PREC_FP64 || opts->rule == BL_SCREEN_LEARNED)
+        return fail(ctx, BL_ERR_UNSUPPORTED, "X in host memory: FP64 scans and no learned rule");
+    const size_t cb = (size_t)xa.m.ldx * (size_t)elem_bytes(xa.m.xtype);
+    int64_t pc = hs && hs->panel_cols > 0 ? hs->panel_cols : (int64_t)std::max<size_t>(1, ((size_t)512 << 20) / cb);
+    if (pc > xa.m.p) pc = xa.m.p;
+    xa.host = true;
+    xa.panel_cols = pc;
+    xa.hs = hs;
+    if (hs) {
+        hs->panel_cols = pc;
+        hs->panels_streamed = 0;
+        hs->panels_skipped = 0;
+        hs->bytes_streamed = 0.0;
+    }
+    // the context's Gram pool indexes the device cache of this X: start both empty
+    return fit_path_impl(ctx, xa, y, opts, res);
 }
 
 }  // extern "C"

@@ -40,6 +40,18 @@ struct bl_ctx_s {
     int cd_helpers = 0;                 // most helper workgroups of the multi-workgroup solve
     int cd_resident = 0;                // workgroups of that solve resident on the device at once
     bool last_residual = false;         // the last solve_set ran the residual-form solve
+    // X in host memory: two device panel buffers streamed on `aux`, and the device cache of the columns
+    // of the Gram pool's features
+    void* panel[2] = {nullptr, nullptr};
+    size_t panel_cap = 0;
+    hipEvent_t ev_copy[2] = {}, ev_free[2] = {};
+    bool panel_used[2] = {false, false};   // ev_free[b] marks the main stream's last use of panel b
+    void* xcache = nullptr;
+    double* xcache_c = nullptr;         // column centers and scales of the cached columns (pool order)
+    double* xcache_s = nullptr;
+    int64_t xcache_cap = 0;             // columns
+    size_t xcache_cb = 0;               // bytes per cached column
+    int64_t ident_len = 0;              // valid entries of the identity column list (H_IDENT)
     // kernel timing
     bool prof = false;
     hipEvent_t ev[10] = {};
@@ -64,6 +76,8 @@ enum BufId {
     CV_ICPT, CV_OUT, CV_CMP, CV_WANT, CV_LAM,
     // elastic net
     B_LAMV, B_PF, B_LMT,
+    // X in host memory
+    H_IDENT, H_SETC, H_COL,
     B_COUNT
 };
 

@@ -1152,6 +1152,18 @@ __global__ void k_enet_unscale(const int32_t* __restrict__ set, int64_t m, const
     }
 }
 
+__global__ void k_map_pos(const int32_t* __restrict__ set, int64_t m, const int32_t* __restrict__ pos,
+                          int32_t* __restrict__ out) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = pos[set[e]];
+}
+
+hipError_t launch_map_pos(const int32_t* set, int64_t m, const int32_t* pool_pos, int32_t* out, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    k_map_pos<<<grid_for(m, 256, 1024), 256, 0, st>>>(set, m, pool_pos, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_enet_scale(const int32_t* set, int64_t m, const double* w, double lam, double alpha, double* GE,
                              double* g0, double* b0, double* lamv, hipStream_t st) {
     if (m <= 0) return hipSuccess;

@@ -183,6 +183,8 @@ int gcd_multi_resident();          // workgroups of the multi-workgroup solve re
 // g~_e = (z_e - lam (1 - alpha) w_e beta_e) / q_e and thresholds lam alpha w_e / q_e (lamv, when w is not null).
 hipError_t launch_enet_scale(const int32_t* set, int64_t m, const double* w, double lam, double alpha, double* GE,
                              double* g0, double* b0, double* lamv, hipStream_t st);
+// out[e] = pool_pos[set[e]]
+hipError_t launch_map_pos(const int32_t* set, int64_t m, const int32_t* pool_pos, int32_t* out, hipStream_t st);
 // back to beta: b0 /= q, b1 /= q, beta[set[e]] = b1[e]
 hipError_t launch_enet_unscale(const int32_t* set, int64_t m, const double* w, double lam, double alpha, double* b0,
                                double* b1, double* beta, hipStream_t st);

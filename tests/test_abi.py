@@ -41,7 +41,7 @@ def test_struct_layouts_match_the_header(tmp_path):
                "bl_path_result": bl._PathResult, "bl_kernel_profile": bl._KernelProfile, "bl_batch": bl._Batch,
                "bl_batch_result": bl._BatchResult, "bl_mlp_train_opts": bl._MlpTrainOpts,
                "bl_mlp_train_result": bl._MlpTrainResult, "bl_limits": bl._Limits, "bl_cv": bl._Cv,
-               "bl_cv_result": bl._CvResult}
+               "bl_cv_result": bl._CvResult, "bl_host_stream": bl._HostStream}
     renames = {"lambda_": "lambda"}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bl.h"', "int main(void) {"]
     for cname, cls in mirrors.items():
