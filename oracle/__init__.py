@@ -68,6 +68,17 @@ def _load():
         L.or_fit_path_enet.argtypes = [i64, i64, vp, i64, vp, vp, i64, dbl, vp, dbl, vp, i32, dbl, i64,
                                        vp, vp, vp, vp, vp, vp, vp, vp]
         L.or_fit_path_enet.restype = i32
+        L.or_logistic_objective.argtypes = [i64, vp, vp, vp, i64, vp, dbl]
+        L.or_logistic_objective.restype = dbl
+        L.or_logistic_gap.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp, vp, vp, vp, dbl]
+        L.or_logistic_gap.restype = dbl
+        L.or_logistic_safe_threshold.argtypes = [i64, i64, dbl, dbl]
+        L.or_logistic_safe_threshold.restype = dbl
+        L.or_logistic_discard.argtypes = [i64, vp, vp, dbl, vp]
+        L.or_logistic_discard.restype = i64
+        L.or_fit_path_logistic.argtypes = [i64, i64, vp, i64, vp, vp, i64, dbl, i32, dbl, i64,
+                                           vp, vp, vp, vp, vp, vp, vp, vp]
+        L.or_fit_path_logistic.restype = i32
         L.or_objective.argtypes = [i64, vp, vp, i64, vp, dbl]
         L.or_objective.restype = dbl
         L.or_duality_gap.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp, vp, vp, vp, dbl]
@@ -385,3 +396,73 @@ def cv_path(Xt, y, fold, nfolds, K=100, ratio=0.1, tol=1e-13) -> CV:
     loss = (y[inrows][None, :] - pred[:, inrows]) ** 2
     cve, cvse, k_min, k_1se = cv_summary(loss)
     return CV(lam, pred, loss, cve, cvse, fold_err, k_min, k_1se, paths)
+
+
+# ---- lasso-penalized logistic regression (y in {0, 1}) ----
+
+@dataclass
+class LogisticPath:
+    lam: np.ndarray
+    beta: np.ndarray       # (K, p) standardized scale
+    b0: np.ndarray         # (K,) intercept on the standardized scale
+    c: np.ndarray
+    s: np.ndarray
+    keep: np.ndarray
+    sweeps: np.ndarray
+    n_strong: np.ndarray
+    n_viol: np.ndarray
+    n_rounds: np.ndarray
+    n_safe: np.ndarray
+    n_active: np.ndarray
+    obj: np.ndarray
+    gap: np.ndarray
+    k_done: int
+    status: int
+
+    def original_scale(self):
+        s = np.where(self.keep, self.s, 1.0)
+        b = np.where(self.keep[None, :], self.beta / s[None, :], 0.0)
+        return self.b0 - b @ self.c, b
+
+
+def fit_path_logistic(Xt, y, K=100, ratio=0.1, screen=SCREEN_SSR, tol=1e-12, max_iter=100000, mask=None
+                      ) -> LogisticPath:
+    Xt, ld = _design(Xt)
+    p, n_total = Xt.shape
+    m = _mask(mask, n_total)
+    y = _f64(y)
+    c, s = np.empty(p), np.empty(p)
+    keep = np.empty(p, dtype=np.uint8)
+    lam = np.empty(K)
+    beta = np.zeros((K, p))
+    b0 = np.zeros(K)
+    arr = {k: np.zeros(K, dtype=np.int64) for k in ("sweeps", "n_strong", "n_viol", "n_rounds", "n_safe", "n_active")}
+    arr.update({k: np.zeros(K) for k in ("rss", "obj", "gap")})
+    st = _Stats(**{k: v.ctypes.data for k, v in arr.items()})
+    k_done = ctypes.c_int64()
+    rc = _load().or_fit_path_logistic(n_total, p, _ptr(Xt), ld, _ptr(m), _ptr(y), K, ratio, screen, tol, max_iter,
+                                      _ptr(c), _ptr(s), _ptr(keep), _ptr(lam), _ptr(beta), _ptr(b0),
+                                      ctypes.byref(st), ctypes.addressof(k_done))
+    if rc == 2:
+        raise ValueError("fit_path_logistic: bad input")
+    arr.pop("rss")
+    return LogisticPath(lam, beta, b0, c, s, keep.astype(bool), k_done=k_done.value, status=rc, **arr)
+
+
+def logistic_objective(y, eta, beta, lam, mask=None):
+    y, eta, beta = _f64(y), _f64(eta), _f64(beta)
+    m = _mask(mask, y.size)
+    return _load().or_logistic_objective(y.size, _ptr(m), _ptr(y), _ptr(eta), beta.size, _ptr(beta), lam)
+
+
+def logistic_gap(Xt, c, s, keep, y, eta, beta, lam, mask=None):
+    Xt, ld = _design(Xt)
+    p, n_total = Xt.shape
+    m = _mask(mask, n_total)
+    k = np.ascontiguousarray(keep, dtype=np.uint8)
+    return _load().or_logistic_gap(n_total, p, _ptr(Xt), ld, _ptr(m), _ptr(_f64(c)), _ptr(_f64(s)), _ptr(k),
+                                   _ptr(_f64(y)), _ptr(_f64(eta)), _ptr(_f64(beta)), lam)
+
+
+def logistic_safe_threshold(n, n1, lambda_max, lam):
+    return _load().or_logistic_safe_threshold(int(n), int(n1), float(lambda_max), float(lam))

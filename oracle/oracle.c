@@ -527,6 +527,273 @@ done:
 }
 
 /*
+ * Lasso-penalized logistic regression (Section 1: the package fits sparse logistic regression; Section 2.2
+ * pairs the strong rule with a safe rule for it).  y_i in {0, 1}, eta_i = b0 + x~_i' beta,
+ *   Q(b0, beta) = (1/n) sum_i [log(1 + e^{eta_i}) - y_i eta_i] + lambda ||beta||_1   (b0 unpenalized).
+ * z_j = x~_j' (y - pi) / n is the negative gradient, pi_i = 1 / (1 + e^{-eta_i}).  At beta = 0 the optimal
+ * intercept is logit(y-bar) and lambda_max = max_j |x~_j' (y - y-bar)| / n.
+ */
+static double sigmoid(double e) { return e >= 0.0 ? 1.0 / (1.0 + exp(-e)) : exp(e) / (1.0 + exp(e)); }
+static double log1pexp(double e) { return e > 0.0 ? e + log1p(exp(-e)) : log1p(exp(e)); }
+
+double or_logistic_objective(int64_t n_total, const uint8_t* mask, const double* y, const double* eta, int64_t p,
+                             const double* beta, double lambda) {
+    int64_t n = count_rows(n_total, mask);
+    double loss = 0.0, l1 = 0.0;
+    for (int64_t i = 0; i < n_total; ++i)
+        if (in_fit(mask, i)) loss += log1pexp(eta[i]) - y[i] * eta[i];
+    for (int64_t j = 0; j < p; ++j) l1 += fabs(beta[j]);
+    return loss / (double)n + lambda * l1;
+}
+
+/* negative binary entropy t log t + (1 - t) log(1 - t), 0 at t = 0 and t = 1 */
+static double negent(double t) {
+    double a = t > 0.0 ? t * log(t) : 0.0;
+    double b = t < 1.0 ? (1.0 - t) * log(1.0 - t) : 0.0;
+    return a + b;
+}
+
+/*
+ * Relative duality gap of (b0, beta) at lambda.  With f_i(e) = log(1 + e^e) - y_i e the primal is
+ * P = sum_i f_i(eta_i) + n lambda ||beta||_1 and the dual D(theta) = -sum_i f_i*(-n lambda theta_i) with
+ * f_i*(u) = negent(u + y_i), over ||X~' theta||_inf <= 1 and sum_i theta_i = 0.  The dual point is the scaled
+ * negative gradient theta = (y - pi) / max(n lambda, ||X~'(y - pi)||_inf).
+ */
+double or_logistic_gap(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
+                       const double* c, const double* s, const uint8_t* keep, const double* y, const double* eta,
+                       const double* beta, double lambda) {
+    int64_t n = count_rows(n_total, mask);
+    double* g = (double*)calloc((size_t)n_total, sizeof(double));
+    double* z = (double*)malloc(sizeof(double) * (size_t)p);
+    for (int64_t i = 0; i < n_total; ++i) g[i] = in_fit(mask, i) ? y[i] - sigmoid(eta[i]) : 0.0;
+    or_zscan(n_total, p, X, ldx, mask, c, s, keep, g, z);
+    double zmax = 0.0;
+    for (int64_t j = 0; j < p; ++j)
+        if (keep[j] && fabs(z[j]) * (double)n > zmax) zmax = fabs(z[j]) * (double)n;
+    double nl = (double)n * lambda;
+    double scale = zmax > nl ? zmax : nl;
+    double primal = (double)n * or_logistic_objective(n_total, mask, y, eta, p, beta, lambda);
+    double dual = 0.0;
+    for (int64_t i = 0; i < n_total; ++i)
+        if (in_fit(mask, i)) dual -= negent(y[i] - nl * g[i] / scale);
+    free(g);
+    free(z);
+    return primal > 0.0 ? (primal - dual) / primal : 0.0;
+}
+
+/*
+ * The safe rule paired with the strong rule for logistic regression.  The rule the paper names (Slores) is not
+ * printed in it; this one plays its part with the same inputs and cost as BEDPP: the gap-safe sphere around
+ * the dual point known exactly at lambda_max (beta = 0, b0 = logit(y-bar), theta_max = (y - y-bar)/(n lambda_max)),
+ * evaluated at lambda.  f_i has f_i'' <= 1/4, so the dual is 4 (n lambda)^2-strongly concave and the dual
+ * optimum lies within r = sqrt(G / 2) / (n lambda) of theta_max, G the gap of (logit(y-bar), 0) and theta_max
+ * at lambda.  With ||x~_j||_2 = sqrt(n), j is discarded when |x~_j' theta_max| + r sqrt(n) < 1, i.e.
+ *   |a_j| < lambda_max (1 - sqrt(G / (2 n)) / lambda),   a_j = x~_j' (y - y-bar) / n.
+ * G depends on lambda only through rho = lambda / lambda_max (closed form over the n1 ones and n0 zeros).
+ * Returns that threshold on |a_j|; or_logistic_discard applies it.
+ */
+double or_logistic_safe_threshold(int64_t n, int64_t n1, double lambda_max, double lambda) {
+    double yb = (double)n1 / (double)n;
+    double n0 = (double)(n - n1);
+    double P = -((double)n1 * log(yb) + n0 * log(1.0 - yb));
+    double rho = lambda / lambda_max;
+    if (rho > 1.0) rho = 1.0;
+    double D = -((double)n1 * negent(1.0 - rho * (1.0 - yb)) + n0 * negent(rho * yb));
+    double G = P - D;
+    if (G < 0.0) G = 0.0;
+    return lambda_max * (1.0 - sqrt(G / (2.0 * (double)n)) / lambda);
+}
+
+int64_t or_logistic_discard(int64_t p, const double* a, const uint8_t* keep, double thr, uint8_t* discard) {
+    int64_t cnt = 0;
+    for (int64_t j = 0; j < p; ++j) {
+        discard[j] = (!keep[j] || fabs(a[j]) < thr) ? 1 : 0;
+        cnt += discard[j];
+    }
+    return cnt;
+}
+
+/*
+ * The logistic lasso path with warm starts, the strong rule on z of the previous lambda and the
+ * post-convergence check over every kept feature, as for the linear path.  Each solve is iteratively
+ * reweighted least squares with cyclic coordinate descent on its quadratic model (the pathwise method the
+ * package builds on): weights w_i = pi_i (1 - pi_i) (at least 1e-5), working residual r_i = (y_i - pi_i) / w_i,
+ * coordinate step beta_j' = S(sum_i w_i x~_ij r_i / n + v_j beta_j, lambda) / v_j with v_j = sum_i w_i x~_ij^2 / n,
+ * intercept step sum_i w_i r_i / sum_i w_i; inner sweeps until the largest change is below tol, outer
+ * iterations until an iteration changes no coefficient (intercept included) by tol or more.
+ * beta is p x K, b0 has K entries (standardized scale).  Returns 0, 1 (not converged) or 2 (bad input,
+ * e.g. y not in {0, 1} or constant on the fitted rows).
+ */
+int or_fit_path_logistic(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
+                         const double* y, int64_t K, double ratio, int screen, double tol, int64_t max_iter,
+                         double* c, double* s, uint8_t* keep, double* lambda, double* beta, double* b0out,
+                         or_path_stats* st, int64_t* k_done) {
+    *k_done = 0;
+    if (p <= 0 || K <= 0) return 2;
+    int64_t n = or_standardize(n_total, p, X, ldx, mask, c, s, keep);
+    if (n <= 0) return 2;
+    int64_t n1 = 0;
+    for (int64_t i = 0; i < n_total; ++i) {
+        if (!in_fit(mask, i)) continue;
+        if (y[i] != 0.0 && y[i] != 1.0) return 2;
+        n1 += y[i] == 1.0;
+    }
+    if (n1 == 0 || n1 == n) return 2;
+    double yb = (double)n1 / (double)n;
+    double* ym = (double*)calloc((size_t)n_total, sizeof(double));
+    double* eta = (double*)calloc((size_t)n_total, sizeof(double));
+    double* w = (double*)calloc((size_t)n_total, sizeof(double));
+    double* r = (double*)calloc((size_t)n_total, sizeof(double));
+    double* g = (double*)calloc((size_t)n_total, sizeof(double));
+    double* a = (double*)calloc((size_t)p, sizeof(double));
+    double* z = (double*)calloc((size_t)p, sizeof(double));
+    double* zprev = (double*)calloc((size_t)p, sizeof(double));
+    double* bcur = (double*)calloc((size_t)p, sizeof(double));
+    uint8_t* inE = (uint8_t*)calloc((size_t)p, 1);
+    uint8_t* disc = (uint8_t*)calloc((size_t)p, 1);
+    int status = 0;
+    for (int64_t i = 0; i < n_total; ++i) ym[i] = in_fit(mask, i) ? y[i] - yb : 0.0;
+    or_zscan(n_total, p, X, ldx, mask, c, s, keep, ym, a);
+    double lmax = 0.0;
+    for (int64_t j = 0; j < p; ++j)
+        if (keep[j] && fabs(a[j]) > lmax) lmax = fabs(a[j]);
+    or_lambda_grid(lmax, ratio, K, lambda);
+    double b0 = log(yb / (1.0 - yb));
+    for (int64_t i = 0; i < n_total; ++i) eta[i] = in_fit(mask, i) ? b0 : 0.0;
+    memcpy(zprev, a, sizeof(double) * (size_t)p);
+
+    for (int64_t k = 0; k < K; ++k) {
+        double lk = lambda[k];
+        int64_t sweeps_k = 0, viol_k = 0, rounds_k = 0, nE = 0;
+        if (lk < lmax) {
+            double thr = 2.0 * lk - (k > 0 ? lambda[k - 1] : lmax);
+            for (int64_t j = 0; j < p; ++j) {
+                if (!keep[j]) inE[j] = 0;
+                else if (screen == OR_SCREEN_NONE) inE[j] = 1;
+                else if (screen == OR_SCREEN_ACTIVE) inE[j] = bcur[j] != 0.0;
+                else inE[j] = (bcur[j] != 0.0 || fabs(zprev[j]) >= thr) ? 1 : 0;
+            }
+            for (;;) {
+                nE = 0;
+                for (int64_t j = 0; j < p; ++j) nE += inE[j];
+                /* IRLS over E */
+                int64_t it = 0;
+                for (;;) {
+                    double wsum = 0.0;
+                    for (int64_t i = 0; i < n_total; ++i) {
+                        if (!in_fit(mask, i)) continue;
+                        double pi = sigmoid(eta[i]);
+                        double wi = pi * (1.0 - pi);
+                        if (wi < 1e-5) wi = 1e-5;
+                        w[i] = wi;
+                        r[i] = (y[i] - pi) / wi;
+                        wsum += wi;
+                    }
+                    double outer_max = 0.0;
+                    for (int64_t sweep = 1;; ++sweep) {
+                        double mx = 0.0;
+                        /* intercept */
+                        double num = 0.0;
+                        for (int64_t i = 0; i < n_total; ++i)
+                            if (in_fit(mask, i)) num += w[i] * r[i];
+                        double d0 = num / wsum;
+                        if (d0 != 0.0) {
+                            b0 += d0;
+                            for (int64_t i = 0; i < n_total; ++i)
+                                if (in_fit(mask, i)) {
+                                    r[i] -= d0;
+                                    eta[i] += d0;
+                                }
+                        }
+                        if (fabs(d0) > mx) mx = fabs(d0);
+                        for (int64_t j = 0; j < p; ++j) {
+                            if (!inE[j]) continue;
+                            const double* x = X + j * ldx;
+                            double xwr = 0.0, xwx = 0.0;
+                            for (int64_t i = 0; i < n_total; ++i) {
+                                if (!in_fit(mask, i)) continue;
+                                double xt = (x[i] - c[j]) / s[j];
+                                xwr += w[i] * xt * r[i];
+                                xwx += w[i] * xt * xt;
+                            }
+                            xwr /= (double)n;
+                            xwx /= (double)n;
+                            double bnew = soft_threshold(xwr + xwx * bcur[j], lk) / xwx;
+                            double dlt = bnew - bcur[j];
+                            if (dlt != 0.0) {
+                                for (int64_t i = 0; i < n_total; ++i) {
+                                    if (!in_fit(mask, i)) continue;
+                                    double xt = (x[i] - c[j]) / s[j];
+                                    r[i] -= dlt * xt;
+                                    eta[i] += dlt * xt;
+                                }
+                                bcur[j] = bnew;
+                            }
+                            if (fabs(dlt) > mx) mx = fabs(dlt);
+                        }
+                        ++sweeps_k;
+                        if (mx > outer_max) outer_max = mx;
+                        if (mx < tol) break;
+                        if (sweeps_k > max_iter) {
+                            status = 1;
+                            goto done;
+                        }
+                    }
+                    ++it;
+                    if (outer_max < tol) break;
+                    if (it > max_iter) {
+                        status = 1;
+                        goto done;
+                    }
+                }
+                rounds_k += 1;
+                for (int64_t i = 0; i < n_total; ++i) g[i] = in_fit(mask, i) ? y[i] - sigmoid(eta[i]) : 0.0;
+                or_zscan(n_total, p, X, ldx, mask, c, s, keep, g, z);
+                int64_t nv = 0;
+                for (int64_t j = 0; j < p; ++j)
+                    if (keep[j] && !inE[j] && fabs(z[j]) > lk) {
+                        inE[j] = 1;
+                        ++nv;
+                    }
+                viol_k += nv;
+                if (nv == 0) break;
+            }
+            memcpy(zprev, z, sizeof(double) * (size_t)p);
+        }
+        memcpy(beta + k * p, bcur, sizeof(double) * (size_t)p);
+        b0out[k] = b0;
+        if (st) {
+            int64_t nact = 0;
+            for (int64_t j = 0; j < p; ++j) nact += bcur[j] != 0.0;
+            if (st->sweeps) st->sweeps[k] = sweeps_k;
+            if (st->n_strong) st->n_strong[k] = nE;
+            if (st->n_viol) st->n_viol[k] = viol_k;
+            if (st->n_rounds) st->n_rounds[k] = rounds_k;
+            if (st->n_active) st->n_active[k] = nact;
+            if (st->n_safe)
+                st->n_safe[k] = p - or_logistic_discard(p, a, keep, or_logistic_safe_threshold(n, n1, lmax, lk), disc);
+            if (st->rss) st->rss[k] = 0.0;
+            if (st->obj) st->obj[k] = or_logistic_objective(n_total, mask, y, eta, p, bcur, lk);
+            if (st->gap) st->gap[k] = or_logistic_gap(n_total, p, X, ldx, mask, c, s, keep, y, eta, bcur, lk);
+        }
+        *k_done = k + 1;
+    }
+done:
+    free(ym);
+    free(eta);
+    free(w);
+    free(r);
+    free(g);
+    free(a);
+    free(z);
+    free(zprev);
+    free(bcur);
+    free(inE);
+    free(disc);
+    return status;
+}
+
+/*
  * Screening network used by the learned form: 4 inputs -> H (ReLU) -> H (ReLU)
  * -> 1 logit -> logistic.  Parameter vector layout:
  *   W1[H][4], b1[H], W2[H][H], b2[H], w3[H], b3.

@@ -75,6 +75,20 @@ void or_mlp_forward(int64_t m, int64_t H, const double* feat /* m x 4 row-major 
 double or_mlp_loss_grad(int64_t m, int64_t H, const double* feat, const double* label, const double* params,
                         double* grad);
 
+
+/* lasso-penalized logistic regression (y in {0, 1}); b0 [K] intercepts on the standardized scale */
+double or_logistic_objective(int64_t n_total, const uint8_t* mask, const double* y, const double* eta, int64_t p,
+                             const double* beta, double lambda);
+double or_logistic_gap(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
+                       const double* c, const double* s, const uint8_t* keep, const double* y, const double* eta,
+                       const double* beta, double lambda);
+double or_logistic_safe_threshold(int64_t n, int64_t n1, double lambda_max, double lambda);
+int64_t or_logistic_discard(int64_t p, const double* a, const uint8_t* keep, double thr, uint8_t* discard);
+int or_fit_path_logistic(int64_t n_total, int64_t p, const double* X, int64_t ldx, const uint8_t* mask,
+                         const double* y, int64_t K, double ratio, int screen, double tol, int64_t max_iter,
+                         double* c, double* s, uint8_t* keep, double* lambda, double* beta, double* b0out,
+                         or_path_stats* st, int64_t* k_done);
+
 #ifdef __cplusplus
 }
 #endif

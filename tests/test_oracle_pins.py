@@ -749,3 +749,123 @@ def test_enet_path_certificates():
         np.testing.assert_allclose(z[act] - lam * 0.7 * w[act] * b[act], lam * 0.3 * w[act] * np.sign(b[act]),
                                    atol=1e-9 * lam)
         assert np.all(np.abs(z[~act]) <= lam * 0.3 * w[~act] * (1 + 1e-9))
+
+
+# ---------------------------------------------------------------------------------------------
+# lasso-penalized logistic regression (Section 1; Section 2.2's hybrid rule for it)
+# ---------------------------------------------------------------------------------------------
+
+def logistic_problem(seed, n, p, design="gaussian", nnz=4):
+    rng = np.random.default_rng(seed)
+    if design == "gaussian":
+        Xt = rng.normal(size=(p, n))
+    elif design == "genotype":
+        Xt = datagen.genotype_u8(seed, n, p).astype(np.float64)
+    else:
+        Xt = datagen.ar1_f32(seed, n, p, 0.6).astype(np.float64)
+    Xs = (Xt - Xt.mean(1, keepdims=True)) / Xt.std(1, keepdims=True)
+    coef = np.zeros(p)
+    coef[rng.choice(p, nnz, replace=False)] = rng.uniform(0.5, 1.5, nnz) * rng.choice([-1, 1], nnz)
+    eta = Xs.T @ coef + 0.3
+    y = (rng.uniform(size=n) < 1.0 / (1.0 + np.exp(-eta))).astype(np.float64)
+    return Xt, y
+
+
+def scipy_logistic_lasso(Xtil, y, lam):
+    """An independent solve: L-BFGS-B on the smooth split beta = u - v, u, v >= 0 (library routine)."""
+    from scipy.optimize import minimize
+    n, p = Xtil.shape
+
+    def f(v):
+        b0, u, w = v[0], v[1:p + 1], v[p + 1:]
+        eta = b0 + Xtil @ (u - w)
+        pi = 1.0 / (1.0 + np.exp(-eta))
+        loss = np.mean(np.logaddexp(0.0, eta) - y * eta) + lam * (u.sum() + w.sum())
+        g = (pi - y) / n
+        gb = Xtil.T @ g
+        return loss, np.concatenate([[g.sum()], gb + lam, -gb + lam])
+
+    x0 = np.zeros(2 * p + 1)
+    bounds = [(None, None)] + [(0.0, None)] * (2 * p)
+    r = minimize(f, x0, jac=True, method="L-BFGS-B", bounds=bounds,
+                 options={"ftol": 1e-15, "gtol": 1e-12, "maxiter": 20000, "maxcor": 30})
+    return r.x[0], r.x[1:p + 1] - r.x[p + 1:]
+
+
+@pytest.mark.parametrize("design", ["gaussian", "genotype", "ar1"])
+def test_logistic_path_matches_an_independent_solver(design):
+    n, p = 120, 6
+    Xt, y = logistic_problem(1, n, p, design)
+    path = oracle.fit_path_logistic(Xt, y, K=12, ratio=0.05)
+    assert path.status == 0 and path.k_done == 12
+    Xtil, c, s = std_numpy(Xt)
+    for k in (3, 7, 11):
+        b0, b = scipy_logistic_lasso(Xtil, y, path.lam[k])
+        np.testing.assert_allclose(path.beta[k], b, atol=2e-6)
+        assert path.b0[k] == pytest.approx(b0, abs=2e-6)
+
+
+def test_logistic_lambda_max_and_intercept_closed_form():
+    Xt, y = logistic_problem(2, 150, 40)
+    path = oracle.fit_path_logistic(Xt, y, K=10, ratio=0.1)
+    Xtil, c, s = std_numpy(Xt)
+    yb = y.mean()
+    assert path.lam[0] == pytest.approx(np.max(np.abs(Xtil.T @ (y - yb))) / 150, rel=1e-13)
+    assert np.all(path.beta[0] == 0.0) and path.sweeps[0] == 0
+    assert path.b0[0] == pytest.approx(np.log(yb / (1 - yb)), rel=1e-14)
+
+
+def test_logistic_single_feature_by_scalar_minimization():
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(3)
+    n = 90
+    x = rng.normal(1.0, 2.0, size=n)
+    y = (rng.uniform(size=n) < 1 / (1 + np.exp(-(0.8 * (x - 1) / 2 - 0.2)))).astype(float)
+    path = oracle.fit_path_logistic(x[None, :], y, K=8, ratio=0.05)
+    xt = (x - x.mean()) / x.std()
+    for k in range(1, 8):
+        lam = path.lam[k]
+        obj = lambda v: np.mean(np.logaddexp(0, v[0] + v[1] * xt) - y * (v[0] + v[1] * xt)) + lam * abs(v[1])
+        r = minimize(obj, [0.0, 0.1], method="Nelder-Mead", options={"xatol": 1e-11, "fatol": 1e-15,
+                                                                     "maxiter": 20000})
+        assert path.beta[k][0] == pytest.approx(r.x[1], abs=1e-6)
+
+
+@pytest.mark.parametrize("design", ["gaussian", "genotype", "ar1"])
+def test_logistic_kkt_and_gap_along_the_path(design):
+    Xt, y = logistic_problem(4, 300, 500, design, nnz=15)
+    mask = (np.random.default_rng(5).uniform(size=300) < 0.9).astype(np.uint8)
+    path = oracle.fit_path_logistic(Xt, y, K=30, ratio=0.03, mask=mask)
+    assert path.k_done == 30
+    assert np.max(path.gap) <= 1e-10
+    rows = mask.astype(bool)
+    for k in (10, 29):
+        c, s = path.c, path.s
+        Xtil = ((Xt[:, rows].T - c) / s)
+        eta = path.b0[k] + Xtil @ path.beta[k]
+        pi = 1 / (1 + np.exp(-eta))
+        z = Xtil.T @ (y[rows] - pi) / rows.sum()
+        b = path.beta[k]
+        lam = path.lam[k]
+        assert abs(np.sum(y[rows] - pi)) <= 1e-8 * rows.sum()
+        np.testing.assert_allclose(z[b != 0], lam * np.sign(b[b != 0]), atol=1e-8 * lam)
+        assert np.all(np.abs(z[b == 0]) <= lam * (1 + 1e-8))
+
+
+@pytest.mark.parametrize("seed,design", [(6, "gaussian"), (7, "genotype"), (8, "ar1")])
+def test_logistic_safe_rule_is_safe(seed, design):
+    Xt, y = logistic_problem(seed, 250, 400, design, nnz=10)
+    path = oracle.fit_path_logistic(Xt, y, K=40, ratio=0.02, screen=oracle.SCREEN_NONE)
+    c, s, keep, n = oracle.standardize(Xt)
+    a = oracle.zscan(Xt, c, s, keep, y - y.mean())
+    n1 = int(y.sum())
+    discarded_total = 0
+    for k, lam in enumerate(path.lam):
+        thr = oracle.logistic_safe_threshold(250, n1, path.lam[0], lam)
+        disc = np.abs(a) < thr
+        discarded_total += disc.sum()
+        assert np.all(path.beta[k][disc] == 0.0), k
+        assert path.n_safe[k] == 400 - disc.sum()
+    assert discarded_total > 0
+    # at lambda_max the gap is 0 and the test is |a_j| < lambda_max
+    assert oracle.logistic_safe_threshold(250, n1, path.lam[0], path.lam[0]) == pytest.approx(path.lam[0], rel=1e-14)
