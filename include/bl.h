@@ -282,7 +282,12 @@ typedef struct {
      * feature).  Not with the precision forms, the learned rule or the batched form (BL_ERR_UNSUPPORTED). */
     double alpha;
     const double* penalty_factor;
+    /* model family: BL_FAMILY_GAUSSIAN (0, the lasso above) or BL_FAMILY_BINOMIAL (lasso-penalized logistic
+     * regression, y in {0, 1}; see bl_fit_path) */
+    int32_t family;
 } bl_path_opts;
+
+enum { BL_FAMILY_GAUSSIAN = 0, BL_FAMILY_BINOMIAL = 1 };
 
 /* Results of bl_fit_path.  Host arrays have K entries; any pointer may be NULL (not written). */
 typedef struct {
@@ -320,6 +325,19 @@ typedef struct {
  * The scan at lambda_k also supplies the strong-rule input for lambda_{k+1}.
  * y [n_total] device.  Returns BL_ERR_NOT_CONVERGED if CD or max_rounds gave out
  * (res->k_done tells how far the path got).
+ *
+ * family BL_FAMILY_BINOMIAL (Section 1: sparse logistic regression; Section 2.2: its hybrid rule pairs the
+ * strong rule with a safe rule): y_i in {0, 1} on the fitted rows (both values present), eta = b0 + X~ beta,
+ *   Q(b0, beta) = (1/n) sum_i [log(1 + e^eta_i) - y_i eta_i] + lambda ||beta||_1, b0 unpenalized,
+ * z_j = x~_j' (y - pi) / n with pi = 1/(1 + e^-eta) in the strong rule and the check, lambda_max =
+ * max |x~_j'(y - y_mean)| / n.  The safe part of rules BEDPP / SSR_BEDPP is the gap-safe sphere around the
+ * dual point known exactly at lambda_max: j is discarded at lambda when |a_j| < lambda_max (1 - sqrt(G / (2 n))
+ * / lambda), G the duality gap of (logit(y_mean), 0) at lambda (Slores, the rule the paper names, is not printed
+ * in it).  Each solve majorizes the loss with curvature 1/4 and minimizes the bound with the lasso coordinate
+ * descent (threshold 4 lambda on the residual 4 (y - pi), intercept stepped by the residual's mean) until a
+ * majorization step changes no coefficient by tol.  Outputs: intercept = original-scale intercept, rss = the
+ * deviance 2 sum_i [log(1 + e^eta_i) - y_i eta_i], obj = Q, y_mean = mean of y.  FP64 scans, lasso penalty,
+ * no learned rule or resume (BL_ERR_UNSUPPORTED).
  */
 bl_status bl_fit_path(bl_ctx ctx, const bl_matrix* X, const double* y, const bl_path_opts* opts,
                       bl_path_result* res);

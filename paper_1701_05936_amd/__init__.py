@@ -24,6 +24,7 @@ BL_OK, BL_ERR_INVALID, BL_ERR_NOMEM, BL_ERR_DEVICE, BL_ERR_NOT_CONVERGED, BL_ERR
 X_F64, X_F32, X_I8 = 0, 1, 2
 SCREEN_NONE, SCREEN_SSR, SCREEN_BEDPP, SCREEN_SSR_BEDPP, SCREEN_LEARNED, SCREEN_ACTIVE = 0, 1, 2, 3, 4, 5
 PREC_FP64, PREC_BF16X3, PREC_I8X4 = 0, 1, 2
+FAMILY_GAUSSIAN, FAMILY_BINOMIAL = 0, 1
 
 _STATUS_NAMES = {0: "BL_OK", 1: "BL_ERR_INVALID", 2: "BL_ERR_NOMEM", 3: "BL_ERR_DEVICE",
                  4: "BL_ERR_NOT_CONVERGED", 5: "BL_ERR_UNSUPPORTED"}
@@ -68,7 +69,7 @@ class _PathOpts(ctypes.Structure):
                 ("mlp_tau", ctypes.c_double), ("rec_feat", ctypes.c_void_p), ("rec_label", ctypes.c_void_p),
                 ("rec_cap", ctypes.c_int64), ("k_start", ctypes.c_int32), ("beta_init", ctypes.c_void_p),
                 ("r_init", ctypes.c_void_p), ("r_out", ctypes.c_void_p), ("alpha", ctypes.c_double),
-                ("penalty_factor", ctypes.c_void_p)]
+                ("penalty_factor", ctypes.c_void_p), ("family", ctypes.c_int32)]
 
 
 class _Cv(ctypes.Structure):
@@ -403,7 +404,8 @@ class PathResult:
 def fit_path(ctx: Context, Xt, y, nlambda=100, lambda_min_ratio=0.1, lambdas=None, rule=SCREEN_SSR_BEDPP,
              tol=1e-8, max_sweeps=100000, max_rounds=100, row_mask=None, n_total=None, want_beta=True,
              raise_on_error=True, precision=PREC_FP64, mlp=None, mlp_tau=0.0, rec_feat=None, rec_label=None,
-             k_start=0, beta_init=None, r_init=None, r_out=None, alpha=1.0, penalty_factor=None) -> PathResult:
+             k_start=0, beta_init=None, r_init=None, r_out=None, alpha=1.0, penalty_factor=None,
+             family=FAMILY_GAUSSIAN) -> PathResult:
     """Whole path.  Learned rule: rule=SCREEN_LEARNED with mlp (float32 device [MLP_NPARAMS]) and mlp_tau.
     Training records: rec_feat (float32 device [cap, 4]) and rec_label (float32 device [cap]).
     Resume: k_start >= 1 with beta_init (float64 device [p], beta at lambda index k_start - 1) and
@@ -412,13 +414,13 @@ def fit_path(ctx: Context, Xt, y, nlambda=100, lambda_min_ratio=0.1, lambdas=Non
     M = matrix(Xt, n_total, row_mask)
     return _fit_path(ctx, M, y, nlambda, lambda_min_ratio, lambdas, rule, tol, max_sweeps, max_rounds, want_beta,
                      raise_on_error, precision, mlp, mlp_tau, rec_feat, rec_label, k_start, beta_init, r_init, r_out,
-                     alpha, penalty_factor, None)
+                     alpha, penalty_factor, None, family)
 
 
 def fit_path_host(ctx: Context, Xt, y, nlambda=100, lambda_min_ratio=0.1, lambdas=None, rule=SCREEN_SSR_BEDPP,
                   tol=1e-8, max_sweeps=100000, max_rounds=100, row_mask=None, n_total=None, want_beta=True,
                   raise_on_error=True, k_start=0, beta_init=None, r_init=None, r_out=None, alpha=1.0,
-                  penalty_factor=None, panel_cols=0, precision=PREC_FP64):
+                  penalty_factor=None, panel_cols=0, precision=PREC_FP64, family=FAMILY_GAUSSIAN):
     """The path with X in host memory (bl_fit_path_host): Xt is a CPU tensor (p, ld), pinned for full PCIe
     speed; y, row_mask and the outputs are on the device.  Returns (PathResult, streaming counters)."""
     if Xt.dim() != 2 or Xt.is_cuda:
@@ -433,14 +435,14 @@ def fit_path_host(ctx: Context, Xt, y, nlambda=100, lambda_min_ratio=0.1, lambda
     hs = _HostStream(int(panel_cols), 0, 0, 0.0)
     res = _fit_path(ctx, M, y, nlambda, lambda_min_ratio, lambdas, rule, tol, max_sweeps, max_rounds, want_beta,
                     raise_on_error, precision, None, 0.0, None, None, k_start, beta_init, r_init, r_out, alpha,
-                    penalty_factor, hs)
+                    penalty_factor, hs, family)
     return res, {"panel_cols": hs.panel_cols, "panels_streamed": hs.panels_streamed,
                  "panels_skipped": hs.panels_skipped, "bytes_streamed": hs.bytes_streamed}
 
 
 def _fit_path(ctx, M, y, nlambda, lambda_min_ratio, lambdas, rule, tol, max_sweeps, max_rounds, want_beta,
               raise_on_error, precision, mlp, mlp_tau, rec_feat, rec_label, k_start, beta_init, r_init, r_out,
-              alpha, penalty_factor, hs) -> PathResult:
+              alpha, penalty_factor, hs, family=FAMILY_GAUSSIAN) -> PathResult:
     K = int(nlambda)
     p = M.p
     dev = _dev(ctx)
@@ -467,7 +469,7 @@ def _fit_path(ctx, M, y, nlambda, lambda_min_ratio, lambdas, rule, tol, max_swee
     opts = _PathOpts(K, float(lambda_min_ratio), lam_in.ctypes.data if lam_in is not None else None, int(rule),
                      float(tol), int(max_sweeps), int(max_rounds), int(precision), _ptr(mlp), float(mlp_tau),
                      _ptr(rec_feat), _ptr(rec_label), rec_cap, int(k_start), _ptr(beta_init), _ptr(r_init),
-                     _ptr(r_out), float(alpha), _ptr(penalty_factor))
+                     _ptr(r_out), float(alpha), _ptr(penalty_factor), int(family))
     res = _PathResult(_ptr(beta), _ptr(c), _ptr(s), _ptr(keep), host["lam"].ctypes.data,
                       host["intercept"].ctypes.data, host["rss"].ctypes.data, host["obj"].ctypes.data,
                       host["sweeps"].ctypes.data, host["rounds"].ctypes.data, host["n_active"].ctypes.data,

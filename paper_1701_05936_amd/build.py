@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbl.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 SOURCES = ["csrc/kernels.hip", "csrc/gram_cd.hip", "csrc/lowp.hip", "csrc/batch.hip", "csrc/mlp.hip",
-           "csrc/cv.hip", "csrc/noalloc.hip", "csrc/api.cpp", "csrc/api_batch.cpp", "csrc/api_mlp.cpp", "csrc/api_cv.cpp"]
+           "csrc/cv.hip", "csrc/logit.hip", "csrc/noalloc.hip", "csrc/api.cpp", "csrc/api_batch.cpp", "csrc/api_mlp.cpp", "csrc/api_cv.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -960,9 +960,293 @@ bl_status bl_scan(bl_ctx ctx, const bl_matrix* X, const double* center, const do
 
 namespace {
 
+// Logistic safe rule: the |a_j| threshold of the gap-safe sphere around the dual point known at lambda_max
+// (beta = 0, b0 = logit(y-bar)); G is that point's duality gap at lambda, in closed form over the n1 ones.
+double logit_entropy(double t) {
+    const double a = t > 0.0 ? t * std::log(t) : 0.0;
+    const double b = t < 1.0 ? (1.0 - t) * std::log(1.0 - t) : 0.0;
+    return a + b;
+}
+
+double logit_safe_threshold(double n, double n1, double lmax, double lam) {
+    const double yb = n1 / n, n0 = n - n1;
+    const double P = -(n1 * std::log(yb) + n0 * std::log(1.0 - yb));
+    const double rho = std::min(1.0, lam / lmax);
+    const double D = -(n1 * logit_entropy(1.0 - rho * (1.0 - yb)) + n0 * logit_entropy(rho * yb));
+    const double G = std::max(0.0, P - D);
+    return lmax * (1.0 - std::sqrt(G / (2.0 * n)) / lam);
+}
+
+// The logistic lasso path (family BL_FAMILY_BINOMIAL; include/bl.h states the model and the rules).
+bl_status fit_logistic(bl_ctx ctx, const XAccess& xa, const double* y, const bl_path_opts* opts,
+                       bl_path_result* res) {
+    auto t_start = std::chrono::steady_clock::now();
+    bl_status s;
+    const Mat& m = xa.m;
+    if (!y || !opts || !res) return fail(ctx, BL_ERR_INVALID, "y/opts/res must be non-NULL");
+    res->k_done = 0;
+    res->n_recorded = 0;
+    const int K = opts->nlambda;
+    if (K < 1) return fail(ctx, BL_ERR_INVALID, "nlambda must be >= 1");
+    if (!opts->lambda && !(opts->lambda_min_ratio > 0.0 && opts->lambda_min_ratio < 1.0) && K > 1)
+        return fail(ctx, BL_ERR_INVALID, "lambda_min_ratio must be in (0, 1)");
+    if (opts->lambda)
+        for (int k = 0; k < K; ++k) {
+            if (!(std::isfinite(opts->lambda[k]) && opts->lambda[k] > 0.0))
+                return fail(ctx, BL_ERR_INVALID, "user lambda[%d] must be finite and > 0", k);
+            if (k > 0 && !(opts->lambda[k] <= opts->lambda[k - 1]))
+                return fail(ctx, BL_ERR_INVALID, "user lambda must be non-increasing");
+        }
+    if (opts->rule < BL_SCREEN_NONE || opts->rule > BL_SCREEN_ACTIVE) return fail(ctx, BL_ERR_INVALID, "unknown rule");
+    if (!(opts->tol > 0.0) || opts->max_sweeps < 1 || opts->max_rounds < 1)
+        return fail(ctx, BL_ERR_INVALID, "tol > 0, max_sweeps >= 1 and max_rounds >= 1 are required");
+    if (opts->rule == BL_SCREEN_LEARNED || opts->precision != BL_PREC_FP64 || opts->k_start != 0 ||
+        opts->rec_cap > 0 || (opts->alpha != 0.0 && opts->alpha != 1.0) || opts->penalty_factor)
+        return fail(ctx, BL_ERR_UNSUPPORTED, "logistic regression: FP64 scans, lasso penalty, no learned rule, resume "
+                    "or training records");
+    const bool active_only = opts->rule == BL_SCREEN_ACTIVE;
+    const bool safe_rule = opts->rule == BL_SCREEN_BEDPP || opts->rule == BL_SCREEN_SSR_BEDPP || active_only;
+    const bool ssr = opts->rule == BL_SCREEN_SSR || opts->rule == BL_SCREEN_SSR_BEDPP;
+    const bool check = ssr || active_only;
+    const int64_t p = m.p, nt = m.n_total;
+    hipStream_t st = ctx->stream;
+
+    double *yt, *r, *r0c, *g, *eta, *a, *z0, *z1, *zs, *beta, *c, *sc_, *pv;
+    uint8_t *s0, *s1, *strong, *keep;
+    int32_t *lT, *lE;
+    int64_t *lens, *pi;
+    LamStats* stats;
+    void* scr;
+    ENSURE(B_YT, nt * 8, yt);
+    ENSURE(B_R, nt * 8, r);
+    ENSURE(L_R0C, nt * 8, r0c);
+    ENSURE(L_G, nt * 8, g);
+    ENSURE(L_ETA, nt * 8, eta);
+    ENSURE(B_A, p * 8, a);
+    ENSURE(B_Z0, p * 8, z0);
+    ENSURE(B_Z1, p * 8, z1);
+    ENSURE(B_ZS, p * 8, zs);
+    ENSURE(B_BETA, p * 8, beta);
+    ENSURE(B_S0, p, s0);
+    ENSURE(B_S1, p, s1);
+    ENSURE(B_E, p, strong);
+    ENSURE(B_LT, p * 4, lT);
+    ENSURE(B_LE, p * 4, lE);
+    ENSURE(B_LENS, 8 * 8, lens);
+    ENSURE(B_STATS, (size_t)K * sizeof(LamStats), stats);
+    ENSURE(B_CMP, compact_scratch_bytes(p), scr);
+    ENSURE(B_ARGV, 256 * 8, pv);
+    ENSURE(B_ARGI, 256 * 8, pi);
+    if (res->center) c = res->center; else ENSURE(B_C, p * 8, c);
+    if (res->scale) sc_ = res->scale; else ENSURE(B_S, p * 8, sc_);
+    if (res->keep) keep = res->keep; else ENSURE(B_KEEP, p, keep);
+
+    if ((s = pool_reset(ctx, p))) return s;
+    int64_t n;
+    if ((s = rows_in_fit(ctx, m, &n))) return s;
+    if ((s = set_n_rows(ctx, n))) return s;
+    const double es = (double)elem_bytes(m.xtype);
+    const double col_bytes = (double)nt * es;
+    HIPCHK(launch_logit_check_y(m, y, ctx->sc, st));
+    if ((s = read_scalars(ctx))) return s;
+    const double n1 = ctx->sc_host->lg_n1;
+    if (ctx->sc_host->lg_bad > 0.0) return fail(ctx, BL_ERR_INVALID, "logistic regression: y must be 0 or 1 on the fitted rows");
+    if (n1 < 1.0 || n1 > (double)n - 1.0) return fail(ctx, BL_ERR_INVALID, "logistic regression: y is constant on the fitted rows");
+    prof_mark(ctx, 0);
+    if ((s = x_colstats(ctx, xa, c, sc_, keep, n))) return s;
+    prof_mark(ctx, 1);
+    // a_j = x~_j'(y - y-bar) / n and lambda_max
+    HIPCHK(launch_center_y(m, y, yt, nullptr, ctx->sc, st));
+    HIPCHK(launch_sum_r(m, yt, ctx->sc, false, st));
+    ScanArgs sa{};
+    sa.len_host = p;
+    sa.r = yt;
+    sa.sc = ctx->sc;
+    sa.c = c;
+    sa.s = sc_;
+    sa.keep = keep;
+    sa.z = a;
+    prof_mark(ctx, 2);
+    if ((s = x_scan(ctx, xa, sa))) return s;
+    prof_mark(ctx, 3);
+    HIPCHK(launch_argmax_abs(a, keep, p, pv, pi, ctx->sc, st));
+    if ((s = read_scalars(ctx))) return s;
+    prof_add(ctx, 0, BL_PROF_COLSTATS, (double)p * col_bytes);
+    prof_add(ctx, 2, BL_PROF_SCAN, (double)p * col_bytes + nt * 8.0, 0.0, (double)p);
+    const double ybar = ctx->sc_host->y_mean, lmax = ctx->sc_host->lmax;
+    if (ctx->sc_host->jstar < 0) return fail(ctx, BL_ERR_INVALID, "no column is kept (all constant)");
+    if (!std::isfinite(lmax) || !(lmax > 0.0)) return fail(ctx, BL_ERR_INVALID, "X has NaN or Inf, or lambda_max is 0");
+    std::vector<double> lam(K);
+    for (int k = 0; k < K; ++k)
+        lam[k] = opts->lambda ? opts->lambda[k]
+                              : (K == 1 ? lmax : lmax * std::pow(opts->lambda_min_ratio, (double)k / (double)(K - 1)));
+    if (res->lambda)
+        for (int k = 0; k < K; ++k) res->lambda[k] = lam[k];
+    res->y_mean = ybar;
+    res->lambda_max = lmax;
+    res->jstar = ctx->sc_host->jstar;
+
+    // beta = 0 with the intercept logit(y-bar) solves every lambda >= lambda_max
+    HIPCHK(launch_fill_f64(beta, 0.0, p, st));
+    HIPCHK(launch_logit_init(m, std::log(ybar / (1.0 - ybar)), eta, ctx->sc, st));
+    HIPCHK(hipMemsetAsync(lens, 0, 8 * 8, st));
+    std::vector<int32_t> h_sweeps(K, 0), h_rounds(K, 0);
+    std::vector<int64_t> h_viol(K, 0);
+    // safe[j] at lambda: kept and, with the safe rule, |a_j| at or above the sphere's threshold
+    auto safe_at = [&](double l, uint8_t* out) -> hipError_t {
+        return launch_ssr(p, keep, nullptr, nullptr, a, safe_rule, safe_rule ? logit_safe_threshold((double)n, n1, lmax, l)
+                                                                              : 0.0, out, st);
+    };
+    uint8_t* safe_cur = s0;
+    uint8_t* safe_next = s1;
+    double* zprev = a;
+    double* zcur = z0;
+    int64_t* len_cur = lens + 1;
+    int64_t* len_next = lens + 2;
+    bl_status final_status = BL_OK;
+    int k_first = 0;
+    if (lam[0] >= lmax) {
+        HIPCHK(safe_at(lam[0], safe_cur));
+        HIPCHK(launch_compact(safe_cur, p, lT, len_cur, scr, st));
+        HIPCHK(launch_logit_loss(m, y, eta, ctx->sc, st));
+        HIPCHK(launch_record(nullptr, lens + 3, len_cur, lens + 3, beta, c, sc_, ctx->sc, lam[0], stats + 0, st));
+        if (res->beta) HIPCHK(hipMemcpyAsync(res->beta, beta, p * 8, hipMemcpyDeviceToDevice, st));
+        k_first = 1;
+    }
+    for (int k = k_first; k < K; ++k) {
+        const double lk = lam[k];
+        const double lprev = k > 0 ? lam[k - 1] : lmax;
+        HIPCHK(safe_at(lk, safe_cur));
+        HIPCHK(launch_compact(safe_cur, p, lT, len_cur, scr, st));
+        uint8_t* scan_mask = safe_cur;
+        if (k + 1 < K) {
+            HIPCHK(safe_at(lam[k + 1], safe_next));
+            scan_mask = safe_next;
+        }
+        HIPCHK(launch_compact(scan_mask, p, lT, len_next, scr, st));
+        HIPCHK(launch_ssr(p, safe_cur, nullptr, beta, zprev, check, active_only ? INFINITY : 2.0 * lk - lprev, strong,
+                          st));
+        HIPCHK(launch_compact(strong, p, lE, lens + 0, scr, st));
+        int rounds = 0, sweeps_total = 0;
+        int64_t viol_total = 0;
+        for (;;) {
+            HIPCHK(hipMemcpyAsync(&ctx->sc_host->n_new, lens + 0, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            const int64_t m_len = ctx->sc_host->n_new;
+            // majorize-minimize steps over the working set
+            for (int it = 0;; ++it) {
+                HIPCHK(launch_logit_resid(m, y, eta, g, r, st));   // r = 4 (y - pi)
+                HIPCHK(launch_sum_r(m, r, ctx->sc, false, st));
+                HIPCHK(launch_logit_center(m, r, r0c, ctx->sc, st));   // intercept step, r centered, copy in r0c
+                HIPCHK(launch_sum_r(m, r, ctx->sc, false, st));
+                ScanArgs ga{};
+                ga.cols = lE;
+                ga.len_dev = lens + 0;
+                ga.r = r;
+                ga.sc = ctx->sc;
+                ga.c = c;
+                ga.s = sc_;
+                ga.keep = keep;
+                ga.z = zs;
+                if ((s = x_scan(ctx, xa, ga))) return s;
+                if ((s = solve_set(ctx, xa, lE, lens + 0, m_len, zs, beta, r, c, sc_, (double)n, 4.0 * lk, opts->tol,
+                                   opts->max_sweeps)))
+                    return s;
+                HIPCHK(launch_logit_eta(m, r0c, r, eta, ctx->sc, st));
+                if ((s = read_scalars(ctx))) return s;
+                const RoundInfo ri = ctx->sc_host->round;
+                sweeps_total += ri.sweeps;
+                if (ri.status == 2) {
+                    final_status = fail(ctx, BL_ERR_DEVICE, "CD workgroups timed out waiting for each other at lambda index %d", k);
+                    break;
+                }
+                if (ri.status != 0) {
+                    final_status = fail(ctx, BL_ERR_NOT_CONVERGED, "CD did not converge at lambda index %d", k);
+                    break;
+                }
+                // a step that moved no coefficient (intercept included) by tol ends the solve
+                if (ri.sweeps <= 1 && std::fabs(ctx->sc_host->lg_db0) < opts->tol) break;
+                if (it + 1 >= opts->max_sweeps) {
+                    final_status = fail(ctx, BL_ERR_NOT_CONVERGED, "majorization steps exhausted at lambda index %d", k);
+                    break;
+                }
+            }
+            if (final_status != BL_OK) break;
+            // the check: z = x~'(y - pi)/n over S_{k+1}, violators in S_k outside the working set
+            HIPCHK(launch_logit_resid(m, y, eta, g, nullptr, st));
+            HIPCHK(launch_sum_r(m, g, ctx->sc, false, st));
+            HIPCHK(hipMemsetAsync(&ctx->sc->round.n_viol, 0, sizeof(uint32_t), st));
+            ScanArgs ka{};
+            ka.cols = lT;
+            ka.len_dev = len_next;
+            ka.r = g;
+            ka.sc = ctx->sc;
+            ka.c = c;
+            ka.s = sc_;
+            ka.keep = keep;
+            ka.z = zcur;
+            ka.check = check;
+            ka.lam = lk;
+            ka.in_s = safe_cur;
+            ka.excl = strong;
+            ka.mark = strong;
+            ka.nviol = &ctx->sc->round.n_viol;
+            ka.len_out = &ctx->sc->round.scan_len;
+            prof_mark(ctx, 2);
+            if ((s = x_scan(ctx, xa, ka))) return s;
+            prof_mark(ctx, 3);
+            if ((s = read_scalars(ctx))) return s;
+            prof_add(ctx, 2, BL_PROF_SCAN, (double)ctx->sc_host->round.scan_len * col_bytes + nt * 8.0, 0.0,
+                     (double)ctx->sc_host->round.scan_len);
+            ++rounds;
+            const uint32_t nv = ctx->sc_host->round.n_viol;
+            viol_total += nv;
+            if (nv == 0) break;
+            if (rounds >= opts->max_rounds) {
+                final_status = fail(ctx, BL_ERR_NOT_CONVERGED, "check rounds exhausted at lambda index %d", k);
+                break;
+            }
+            HIPCHK(launch_compact(strong, p, lE, lens + 0, scr, st));
+        }
+        if (final_status != BL_OK) break;
+        h_sweeps[k] = sweeps_total;
+        h_rounds[k] = rounds;
+        h_viol[k] = viol_total;
+        HIPCHK(launch_logit_loss(m, y, eta, ctx->sc, st));
+        HIPCHK(launch_record(lE, lens + 0, len_cur, len_next, beta, c, sc_, ctx->sc, lk, stats + k, st));
+        if (res->beta) HIPCHK(hipMemcpyAsync(res->beta + (size_t)k * p, beta, p * 8, hipMemcpyDeviceToDevice, st));
+        res->k_done = k + 1;
+        zprev = zcur;
+        zcur = (zcur == z0) ? z1 : z0;
+    }
+    if (k_first == 1 && res->k_done < 1) res->k_done = 1;
+    std::vector<LamStats> hs(K);
+    HIPCHK(hipMemcpyAsync(hs.data(), stats, (size_t)K * sizeof(LamStats), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int k = 0; k < res->k_done; ++k) {
+        if (res->intercept) res->intercept[k] = hs[k].intercept;
+        if (res->rss) res->rss[k] = hs[k].rss;
+        if (res->obj) res->obj[k] = hs[k].obj;
+        if (res->n_active) res->n_active[k] = hs[k].n_active;
+        if (res->sweeps) res->sweeps[k] = h_sweeps[k];
+        if (res->rounds) res->rounds[k] = h_rounds[k];
+        if (res->n_viol) res->n_viol[k] = h_viol[k];
+        if (res->n_scanned) res->n_scanned[k] = hs[k].n_scan * h_rounds[k];
+        if (res->n_recheck) res->n_recheck[k] = 0;
+        if (res->n_safe) res->n_safe[k] = hs[k].n_safe;
+        if (res->n_strong) res->n_strong[k] = hs[k].n_strong;
+    }
+    if (opts->r_out) HIPCHK(hipMemcpyAsync(opts->r_out, g, nt * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    res->time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    return final_status;
+}
+
 // The path over X wherever it lives (XAccess): bl_fit_path (X in HBM) and bl_fit_path_host (X in host memory).
 bl_status fit_path_impl(bl_ctx ctx, const XAccess& xa, const double* y, const bl_path_opts* opts,
                         bl_path_result* res) {
+    if (opts && opts->family == BL_FAMILY_BINOMIAL) return fit_logistic(ctx, xa, y, opts, res);
+    if (opts && opts->family != BL_FAMILY_GAUSSIAN) return fail(ctx, BL_ERR_INVALID, "unknown family %d", opts->family);
     auto t_start = std::chrono::steady_clock::now();
     bl_status s;
     const Mat& m = xa.m;

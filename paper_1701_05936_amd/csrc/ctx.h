@@ -78,6 +78,8 @@ enum BufId {
     B_LAMV, B_PF, B_LMT,
     // X in host memory
     H_IDENT, H_SETC, H_COL,
+    // logistic regression
+    L_ETA, L_G, L_R0C,
     B_COUNT
 };
 

@@ -40,6 +40,11 @@ struct DevScalars {
     RoundInfo round;
     double i8_scale[4];   // power-of-two scales of the int8 residual pieces (int8 matrix-core form)
     double i8_a;          // that form's bound numerator: (||remainder||_2 + gamma_3 ||sum_k s_k |q_k| ||_2)(1 + 2^-20)
+    // logistic regression
+    double lg_b0;         // intercept (standardized scale)
+    double lg_db0;        // the last majorization step's intercept change
+    double lg_n1;         // fitted rows with y = 1
+    double lg_bad;        // fitted rows with y outside {0, 1}
 };
 
 struct Mat {
@@ -330,5 +335,22 @@ hipError_t launch_cv_predict(const Mat& m, int nfolds, int K, int64_t max_rows, 
 hipError_t launch_cv_reduce(const double* loss, const uint8_t* all_rows, const int32_t* rows, const int64_t* rlens,
                             int64_t n_total, int K, int nfolds, double* cve, double* cvse, double* ferr,
                             hipStream_t st);
+
+
+// ---- lasso-penalized logistic regression (logit.hip) ----
+// sc->lg_n1 = fitted rows with y = 1, sc->lg_bad = fitted rows with y outside {0, 1}
+hipError_t launch_logit_check_y(const Mat& m, const double* y, DevScalars* sc, hipStream_t st);
+// eta = b0 (fitted rows, 0 elsewhere), sc->lg_b0 = b0
+hipError_t launch_logit_init(const Mat& m, double b0, double* eta, DevScalars* sc, hipStream_t st);
+// g = y - sigmoid(eta) on fitted rows (0 elsewhere); r0 = 4 g when r0 is not null
+hipError_t launch_logit_resid(const Mat& m, const double* y, const double* eta, double* g, double* r0, hipStream_t st);
+// majorization step of the intercept: db0 = sum(r0) / n (sc->sum_r, sc->n_rows), r0 -= db0 on fitted rows,
+// sc->lg_db0 = db0, sc->lg_b0 += db0; keeps a copy of r0 in r0c
+hipError_t launch_logit_center(const Mat& m, double* r0, double* r0c, DevScalars* sc, hipStream_t st);
+// eta += db0 + (r0c - r) on fitted rows (the change of the linear predictor over the solve)
+hipError_t launch_logit_eta(const Mat& m, const double* r0c, const double* r, double* eta, const DevScalars* sc,
+                            hipStream_t st);
+// sc->rss = 2 sum_i [log(1 + e^eta_i) - y_i eta_i] (the deviance) and sc->y_mean = sc->lg_b0, for launch_record
+hipError_t launch_logit_loss(const Mat& m, const double* y, const double* eta, DevScalars* sc, hipStream_t st);
 
 }  // namespace blk
