@@ -517,7 +517,7 @@ BATCH_EAGER = 1
 
 def fit_path_batch(ctx: Context, Xt, Y, masks=None, nlambda=100, lambda_min_ratio=0.1, rule=SCREEN_SSR_BEDPP,
                    tol=1e-8, max_sweeps=100000, max_rounds=100, n_total=None, want_beta=True,
-                   raise_on_error=True, eager=False, lambdas=None) -> BatchResult:
+                   raise_on_error=True, eager=False, lambdas=None, precision=PREC_FP64) -> BatchResult:
     """Batched form: B <= 64 problems over one X.  Y (B, n_total) float64 device; masks (B, n_total) uint8
     device or None (all rows in every problem)."""
     M = matrix(Xt, n_total, None)
@@ -540,7 +540,7 @@ def fit_path_batch(ctx: Context, Xt, Y, masks=None, nlambda=100, lambda_min_rati
         lam_in = np.ascontiguousarray(lambdas, dtype=np.float64)
         assert lam_in.size == K
     opts = _PathOpts(K, float(lambda_min_ratio), lam_in.ctypes.data if lam_in is not None else None, int(rule),
-                     float(tol), int(max_sweeps), int(max_rounds), PREC_FP64)
+                     float(tol), int(max_sweeps), int(max_rounds), int(precision))
     res = _BatchResult(_ptr(beta), *[host[k].ctypes.data for k in ("lam", "intercept", "rss", "obj", "sweeps",
                                                                   "rounds", "n_active", "n_strong", "n_safe",
                                                                   "n_viol")], 0, 0.0, 0)

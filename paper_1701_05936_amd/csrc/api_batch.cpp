@@ -132,7 +132,10 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
         return fail(ctx, BL_ERR_UNSUPPORTED, "batched form: lasso only (no elastic net or penalty factors)");
     if (!(opts->tol > 0.0) || opts->max_sweeps < 1 || opts->max_rounds < 1)
         return fail(ctx, BL_ERR_INVALID, "tol > 0, max_sweeps >= 1 and max_rounds >= 1 are required");
-    if (opts->precision != BL_PREC_FP64) return fail(ctx, BL_ERR_UNSUPPORTED, "batched form: FP64 scans only");
+    // check scans: FP64 matrix cores, or (f32 X) BF16 matrix cores with FP64 re-scans of the decisions in the band
+    const bool bf = opts->precision == BL_PREC_BF16X3;
+    if (opts->precision != BL_PREC_FP64 && !(bf && m.xtype == BL_X_F32))
+        return fail(ctx, BL_ERR_UNSUPPORTED, "batched form: FP64 scans, or BF16X3 scans of f32 X");
     // the active-set rule keeps only the previous active set: the strong rule with an infinite threshold
     const bool active_only = opts->rule == BL_SCREEN_ACTIVE;
     const bool bedpp = opts->rule == BL_SCREEN_BEDPP || opts->rule == BL_SCREEN_SSR_BEDPP || active_only;
@@ -189,12 +192,25 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
     ENSURE(BB_CMP, std::max(b_compact_scratch_bytes(p), compact_scratch_bytes(p)), cmp);
     int64_t* kdev;   // lambda step counter read by the replayed screening graph
     ENSURE(BB_KDEV, 8, kdev);
+    __bf16* Rp = nullptr;
+    uint8_t* flag = nullptr;
+    int32_t *lF = nullptr, *lU = nullptr;
+    int64_t* lenF = lens + BNP + 2;
+    int64_t* lenU = lens + BNP + 3;
+    const double bf_rel = bf ? bscan_bf16_rel(nt) : 0.0;
+    ENSURE(BB_LU, p * 4, lU);
+    if (bf) {
+        ENSURE(BB_RP, (size_t)bscan_bf16_pieces_bytes(nt), Rp);
+        ENSURE(BB_FLAG, p, flag);
+        ENSURE(BB_LF, p * 4, lF);
+    }
 
     // pinned host staging: every write to it is followed by a stream synchronization before the next one
     struct Pinned {
         uint8_t want[BNP];
         int64_t lens[BNP];
         int64_t lenT;
+        int64_t lenF, lenU;   // BF16 form: flagged columns re-scanned, working-set union scanned exactly
         BatchScalars bs[BNP];
     };
     if (!ctx->bpinned && hipHostMalloc(&ctx->bpinned, sizeof(Pinned), hipHostMallocDefault) != hipSuccess) {
@@ -360,13 +376,27 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
             prof_mark(ctx, 4);
             HIPCHK(launch_b_gram_update(m, masks, NB, list, bs, c, sd, ctx->bgpool, ctx->bpool_cap, max_P, max_N, wv, st));
             HIPCHK(launch_b_commit(NB, wv, bs, st));
+            prof_mark(ctx, 5);
             for (int b = 0; b < NB; ++b)
                 if (act[b]) pool_size[b] += hp->bs[b].n_new;
             if (max_m * max_m > ge_cap) ge_cap = std::max<int64_t>(max_m * max_m, 2 * ge_cap);
             ENSURE(BB_GE, (size_t)NB * std::max<int64_t>(ge_cap, 1) * 8, GE);
+            {
+                // every solve starts from FP64 gradients of its working set taken by one scan of the union of the
+                // working sets, split over row ranges (a short list): the same values whichever form the check
+                // scans take, so the BF16 form's solves see the FP64 form's inputs
+                HIPCHK(launch_b_union(p, NB, strong, uni, st));
+                HIPCHK(launch_compact(uni, p, lU, lenU, cmp, st));
+                HIPCHK(hipMemcpyAsync(&hp->lenU, lenU, 8, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                double* part;
+                ENSURE(BB_PART, bscan_split_part_bytes(nt, hp->lenU), part);
+                prof_mark(ctx, 8);
+                HIPCHK(launch_bscan_split(m, lU, hp->lenU, R, NB, bs, c, sd, keep, part, it == 0 ? zprev : zcur, st));
+                prof_mark(ctx, 9);
+            }
             HIPCHK(launch_b_gather(lE, lens, p, NB, wv, pos, ctx->bgpool, ctx->bpool_cap, it == 0 ? zprev : zcur, beta,
                                    GE, ge_cap, g0, b0, max_m, st));
-            prof_mark(ctx, 5);
             prof_mark(ctx, 6);
             HIPCHK(launch_b_gcd(lE, lens, p, NB, wv, GE, ge_cap, g0, b0, b1, beta, lam_k, opts->tol, opts->max_sweeps, bs,
                                 st));
@@ -374,9 +404,27 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
             HIPCHK(launch_b_r_update(m, masks, lE, lens, NB, wv, b0, b1, c, sd, R, st));
             HIPCHK(launch_b_sum_r(R, nt, NB, bs, st));
             // post-convergence scan of every problem over the union list, then each problem's check
-            prof_mark(ctx, 2);
-            HIPCHK(launch_bscan(m, 2, lT, lenT, 0, R, NB, bs, c, sd, keep, zcur, st, waves));
-            prof_mark(ctx, 3);
+            if (!bf) {
+                prof_mark(ctx, 2);
+                HIPCHK(launch_bscan(m, 2, lT, lenT, 0, R, NB, bs, c, sd, keep, zcur, st, waves));
+                prof_mark(ctx, 3);
+            } else {
+                HIPCHK(launch_b_r_pieces(R, nt, NB, Rp, st));
+                prof_mark(ctx, 2);
+                HIPCHK(launch_bscan_bf16(m, lT, lenT, 0, Rp, NB, bs, c, sd, keep, zcur, st));
+                prof_mark(ctx, 3);
+                // decisions within the bound of a threshold (this check, the next strong rule) are re-taken on
+                // the FP64 scan of those columns
+                HIPCHK(launch_fill_u8(flag, 0, p, st));
+                HIPCHK(launch_b_band(lT, lenT, p, NB, zcur, c, sd, keep, bs, lam_k,
+                                     (ssr && k + 1 < K) ? thrg + (size_t)(k + 1) * BNP : nullptr, bf_rel, flag, st));
+                HIPCHK(launch_compact(flag, p, lF, lenF, cmp, st));
+                HIPCHK(hipMemcpyAsync(&hp->lenF, lenF, 8, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                double* part;
+                ENSURE(BB_PART, bscan_split_part_bytes(nt, hp->lenF), part);
+                HIPCHK(launch_bscan_split(m, lF, hp->lenF, R, NB, bs, c, sd, keep, part, zcur, st));
+            }
             if (ssr) HIPCHK(launch_b_viol(lT, lenT, p, NB, zcur, safe, strong, lam_k, wv, bs, st));
             HIPCHK(hipMemcpyAsync(&hp->lenT, lenT, 8, hipMemcpyDeviceToHost, st));
             if ((s = read_bs())) return s;
@@ -388,8 +436,10 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
                     cd_updates += (double)hp->bs[b].sweeps * hp->lens[b];
                 }
             prof_add(ctx, 6, BL_PROF_CD, cd_bytes, 0.0, cd_updates);
-            prof_add(ctx, 2, BL_PROF_BSCAN, (double)hp->lenT * nt * es + (double)nt * NB * 8.0,
+            prof_add(ctx, 2, BL_PROF_BSCAN, (double)hp->lenT * nt * es + (double)nt * NB * (bf ? 6.0 : 8.0),
                      2.0 * hp->lenT * nt * NB, (double)hp->lenT);
+            // the FP64 scan of the working sets' union (BF16 form: the band's re-scans are not in this figure)
+            prof_add(ctx, 8, BL_PROF_RECHECK, (double)hp->lenU * nt * es, 0.0, (double)hp->lenU);
             bool any = false;
             for (int b = 0; b < NB; ++b) {
                 if (!act[b]) continue;

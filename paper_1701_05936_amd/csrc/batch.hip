@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+
 #include "chain.h"
 #include "internal.h"
 
@@ -62,7 +64,9 @@ int grid_for(int64_t work, int per_block, int max_blocks) {
 constexpr int BS_K = 64;
 constexpr int BS_LD = BNP + 2;   // LDS row stride of the staged B rows (doubles)
 
-// mode 0: raw dot products; mode 1: squared X (masked second moments); mode 2: standardized correlations
+// mode 0: raw dot products; mode 1: squared X (masked second moments); mode 2: standardized correlations;
+// mode 3: raw dot products of the rows [rc * blockIdx.y, rc * (blockIdx.y + 1)) only, written to
+// out[(blockIdx.y * len + t) * BNP + b] (split over rows for short column lists; k_bscan_reduce adds them)
 template <typename XT, int MODE, int WAVES, bool PF>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVES >= 4 ? 2 : 1))) void k_bscan(const XT* __restrict__ X, int64_t ldx, int64_t n_total,
                                                       int64_t n_pad, const int32_t* __restrict__ cols,
@@ -70,12 +74,14 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVE
                                                       const double* __restrict__ B, int nprob, int64_t p,
                                                       BatchScalars* __restrict__ bs, const double* __restrict__ c,
                                                       const double* __restrict__ s, const uint8_t* __restrict__ keep,
-                                                      double* __restrict__ out) {
+                                                      double* __restrict__ out, int64_t rc) {
     constexpr int NT = 64 * WAVES, TF = 32 * WAVES;
     __shared__ double Bl[2][BS_K * BS_LD];
     const int64_t len = len_dev ? *len_dev : len_host;
     const int64_t f0 = (int64_t)blockIdx.x * TF;
     if (f0 >= len) return;
+    const int64_t row0 = MODE == 3 ? rc * (int64_t)blockIdx.y : 0;
+    const int64_t row1 = MODE == 3 ? (row0 + rc < n_pad ? row0 + rc : n_pad) : n_pad;
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
     const int m = lane & 15, kq = lane >> 4;
     // the two columns this lane feeds (tiles ft = 0, 1)
@@ -123,13 +129,13 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVE
         }
     };
     int buf = 0;
-    if (PF) load(xr, 0);
-    stage_load(0);
+    if (PF) load(xr, row0);
+    stage_load(row0);
     stage_store(0);
     __syncthreads();
-    for (int64_t i0 = 0; i0 < n_pad; i0 += BS_K) {
+    for (int64_t i0 = row0; i0 < row1; i0 += BS_K) {
         if (!PF) load(xr, i0);
-        const bool more = i0 + BS_K < n_pad;
+        const bool more = i0 + BS_K < row1;
         if (more) {
             if (PF) load(xn, i0 + BS_K);
             stage_load(i0 + BS_K);
@@ -181,9 +187,227 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVE
                     const bool kept = keep == nullptr || keep[bj] != 0;
                     o = kept ? (v - c[bj] * bs[b].sum_r) / ((double)bs[b].n_rows * s[bj]) : 0.0;
                 }
-                out[(int64_t)b * p + j] = o;
+                if (MODE == 3)
+                    out[((int64_t)blockIdx.y * len + t) * BNP + b] = v;
+                else
+                    out[(int64_t)b * p + j] = o;
             }
         }
+    }
+}
+
+// ---- the shared contraction on BF16 matrix cores (f32 X) ----------------------------------------------
+// The check scans of the batched form as Z = X_cols' R with both operands split into three BF16 pieces:
+//   x = x1 + x2 + x3 (f32 x: x1 = bf16(x), x2 = bf16(x - x1), x3 = bf16(x - x1 - x2), exact for normal x),
+//   r = r1 + r2 + r3 (FP64 r, remainder below (2^-8 + 2^-24)^3 |r|),
+// and the six products of order at most 4 taken on v_mfma_f32_16x16x32_bf16 (x1r1; x1r2 + x2r1;
+// x1r3 + x2r2 + x3r1: the dropped x2r3, x3r2, x3r3 are below 2^-23 |x| |r|).  Each of the three groups sums
+// in its own FP32 accumulator for 64 rows (two 32-row steps), then goes to FP64.  The error per (column,
+// problem) is bounded by bscan_bf16_rel() sqrt(n_b (s^2 + c^2)) ||r_b||_2 / (n_b s) (plus the FP64 scan's own
+// rounding, so that decisions outside the band equal the FP64 scan's); decisions within the band are
+// re-taken on the FP64 scan.
+// Tile: a wavefront owns 16 columns against the 64 problems (four 16-problem tiles); lane (m, g) feeds rows
+// 8g .. 8g+7 of a 32-row step of column m (A) and of problem 16 nt + m (B).  The residual pieces of a
+// 64-row chunk sit in LDS, [piece][problem][row] with a padded row stride, double buffered.
+constexpr int BF_K = 64;          // rows per chunk (two 32-row matrix-core steps)
+constexpr int BF_RS = BF_K + 8;   // LDS stride of a (piece, problem) row block, bf16 elements (144 bytes)
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+
+// residual pieces of every problem, problem-major per piece: Rp[(c * BNP + b) * n_pad + i]
+__global__ void k_b_r_pieces(const double* __restrict__ R, int64_t n_total, int64_t n_pad, int nprob,
+                             __bf16* __restrict__ Rp) {
+    const int64_t total = n_pad * BNP;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx % n_pad;
+        const int b = (int)(idx / n_pad);
+        double rem = (i < n_total && b < nprob) ? R[i * BNP + b] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const __bf16 v = (__bf16)(float)rem;
+            Rp[((int64_t)c * BNP + b) * n_pad + i] = v;
+            rem -= (double)(float)v;
+        }
+    }
+}
+
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_bscan_bf16(const float* __restrict__ X, int64_t ldx, int64_t n_total,
+                                                           int64_t n_pad, const __bf16* __restrict__ Rp,
+                                                           const int32_t* __restrict__ cols,
+                                                           const int64_t* __restrict__ len_dev, int64_t len_host,
+                                                           int nprob, int64_t p, const BatchScalars* __restrict__ bs,
+                                                           const double* __restrict__ c, const double* __restrict__ s,
+                                                           const uint8_t* __restrict__ keep, double* __restrict__ out) {
+    constexpr int NT = 64 * WAVES;
+    __shared__ __bf16 Rl[2][3 * BNP * BF_RS];
+    const int64_t len = len_dev ? *len_dev : len_host;
+    const int64_t f0 = (int64_t)blockIdx.x * 16 * WAVES;
+    if (f0 >= len) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid / 64;
+    const int m = lane & 15, g = lane >> 4;
+    const int64_t t = f0 + 16 * w + m;
+    const bool ok = t < len;
+    const int64_t j = ok ? (cols ? (int64_t)cols[t] : t) : 0;   // lanes past the list read column 0, unused
+    const float* xc = X + j * ldx;
+    // staging of one chunk's pieces: 3 x 64 problems x 64 rows = 1536 16-byte blocks
+    constexpr int SB = 3 * BNP * (BF_K / 8);
+    constexpr int SPT = (SB + NT - 1) / NT;
+    v4i32 sreg[SPT];
+    auto stage_load = [&](int64_t i0) {
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+            const int blk = tid + q * NT;
+            if (blk < SB) {
+                const int cb = blk / (BF_K / 8), r8 = blk % (BF_K / 8);
+                sreg[q] = *reinterpret_cast<const v4i32*>(Rp + (int64_t)cb * n_pad + i0 + 8 * r8);
+            }
+        }
+    };
+    auto stage_store = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+            const int blk = tid + q * NT;
+            if (blk < SB) {
+                const int cb = blk / (BF_K / 8), r8 = blk % (BF_K / 8);
+                *reinterpret_cast<v4i32*>(&Rl[buf][cb * BF_RS + 8 * r8]) = sreg[q];
+            }
+        }
+    };
+    // the lane's 16 values of a chunk: rows i0 + 32 ks + 8 g .. +7 for ks = 0, 1 (zero past n_total); the next
+    // two chunks' loads are in flight while a chunk is on the matrix cores
+    float xr[16], xn[16], xm[16];
+    auto load_x = [&](float (&dst)[16], int64_t i0) {
+        if (i0 + BF_K <= n_total) {
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                const float4* src = reinterpret_cast<const float4*>(xc + i0 + 32 * ks + 8 * g);
+                const float4 a = src[0], b = src[1];
+                dst[8 * ks + 0] = a.x; dst[8 * ks + 1] = a.y; dst[8 * ks + 2] = a.z; dst[8 * ks + 3] = a.w;
+                dst[8 * ks + 4] = b.x; dst[8 * ks + 5] = b.y; dst[8 * ks + 6] = b.z; dst[8 * ks + 7] = b.w;
+            }
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int64_t i = i0 + 32 * ks + 8 * g + q;
+                    dst[8 * ks + q] = i < n_total ? xc[i] : 0.f;
+                }
+        }
+    };
+    double acc64[4][4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc64[nt][q] = 0.0;
+    int buf = 0;
+    load_x(xr, 0);
+    if (BF_K < n_pad) load_x(xn, BF_K);
+    stage_load(0);
+    stage_store(0);
+    __syncthreads();
+    for (int64_t i0 = 0; i0 < n_pad; i0 += BF_K) {
+        const bool more = i0 + BF_K < n_pad;
+        if (i0 + 2 * BF_K < n_pad) load_x(xm, i0 + 2 * BF_K);
+        if (more) stage_load(i0 + BF_K);
+        const __bf16* Rb = Rl[buf];
+        f32x4 a1[4], a2[4], a3[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            a1[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            a2[nt] = a1[nt];
+            a3[nt] = a1[nt];
+        }
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            f32x8 xv;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) xv[q] = xr[8 * ks + q];
+            const bf16x8 x1 = __builtin_convertvector(xv, bf16x8);
+            const f32x8 d1 = xv - __builtin_convertvector(x1, f32x8);
+            const bf16x8 x2 = __builtin_convertvector(d1, bf16x8);
+            const f32x8 d2 = d1 - __builtin_convertvector(x2, f32x8);
+            const bf16x8 x3 = __builtin_convertvector(d2, bf16x8);
+            const int roff = 32 * ks + 8 * g;
+            // all twelve residual fragments of the step first (one wait), then the 24 matrix-core steps ordered
+            // so that steps on the same accumulator are at least four apart
+            bf16x8 rb[3][4];
+#pragma unroll
+            for (int pc = 0; pc < 3; ++pc)
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+                    rb[pc][nt] = *reinterpret_cast<const bf16x8*>(Rb + (pc * BNP + 16 * nt + m) * BF_RS + roff);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) a1[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, rb[0][nt], a1[nt], 0, 0, 0);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) a2[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, rb[1][nt], a2[nt], 0, 0, 0);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) a3[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, rb[2][nt], a3[nt], 0, 0, 0);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) a2[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x2, rb[0][nt], a2[nt], 0, 0, 0);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) a3[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x2, rb[1][nt], a3[nt], 0, 0, 0);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) a3[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x3, rb[0][nt], a3[nt], 0, 0, 0);
+        }
+        // the chunk's three FP32 sums go to FP64 (smallest first)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc64[nt][q] += ((double)a3[nt][q] + (double)a2[nt][q]) + (double)a1[nt][q];
+        if (more) stage_store(buf ^ 1);   // the other buffer was last read before the previous barrier
+        __syncthreads();
+        buf ^= 1;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            xr[q] = xn[q];
+            xn[q] = xm[q];
+        }
+    }
+    // lane (m, g), register q of problem tile nt: column 16 w + 4 g + q of the workgroup, problem 16 nt + m
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t tq = f0 + 16 * w + 4 * g + q;
+        if (tq >= len) continue;
+        const int64_t jq = cols ? (int64_t)cols[tq] : tq;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const int b = 16 * nt + m;
+            if (b >= nprob) continue;
+            const int64_t bj = (int64_t)b * p + jq;
+            const bool kept = keep == nullptr || keep[bj] != 0;
+            out[bj] = kept ? (acc64[nt][q] - c[bj] * bs[b].sum_r) / ((double)bs[b].n_rows * s[bj]) : 0.0;
+        }
+    }
+}
+
+// Flag the columns whose matrix-core z, for some problem, lies within its error bound of a threshold the path
+// decides on: lambda_k (the check) or thr_k+1 = 2 lambda_{k+1} - lambda_k (the next strong rule; thr null: none).
+// rel = bscan_bf16_rel(n_total).
+__global__ void k_b_band(const int32_t* __restrict__ cols, const int64_t* __restrict__ len_dev, int64_t p, int nprob,
+                         const double* __restrict__ z, const double* __restrict__ c, const double* __restrict__ s,
+                         const uint8_t* __restrict__ keep, const BatchScalars* __restrict__ bs,
+                         const double* __restrict__ lam, const double* __restrict__ thr, double rel,
+                         uint8_t* __restrict__ flag) {
+    const int64_t len = *len_dev;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < len; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = cols[t];
+        uint8_t f = 0;
+        for (int b = 0; b < nprob && !f; ++b) {
+            const int64_t bj = (int64_t)b * p + j;
+            if (keep[bj] == 0) continue;
+            const double nb = (double)bs[b].n_rows;
+            const double sj = s[bj], cj = c[bj];
+            const double az = fabs(z[bj]);
+            const double err = rel * sqrt(nb * (sj * sj + cj * cj)) * sqrt(bs[b].rss) / (nb * sj) + 1e-14 * az;
+            if (fabs(az - lam[b]) <= err) f = 1;
+            if (thr && fabs(az - thr[b]) <= err) f = 1;
+        }
+        flag[j] = f;
     }
 }
 
@@ -879,13 +1103,49 @@ static hipError_t bscan_typed(const Mat& mt, int mode, const int32_t* cols, cons
     if (g <= 0) return hipSuccess;
     if (mode == 0)
         k_bscan<XT, 0, WAVES, PF><<<g, 64 * WAVES, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, cols, len_dev, len_host, B, nprob,
-                                                       mt.p, bs, c, s, keep, out);
+                                                       mt.p, bs, c, s, keep, out, n_pad);
     else if (mode == 1)
         k_bscan<XT, 1, WAVES, PF><<<g, 64 * WAVES, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, cols, len_dev, len_host, B, nprob,
-                                                       mt.p, bs, c, s, keep, out);
+                                                       mt.p, bs, c, s, keep, out, n_pad);
     else
         k_bscan<XT, 2, WAVES, PF><<<g, 64 * WAVES, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, cols, len_dev, len_host, B, nprob,
-                                                       mt.p, bs, c, s, keep, out);
+                                                       mt.p, bs, c, s, keep, out, n_pad);
+    return hipGetLastError();
+}
+
+// sum of the row-range partials in range order, then the standardized correlation of each (column, problem)
+__global__ void k_bscan_reduce(const double* __restrict__ part, int nch, int64_t len, const int32_t* __restrict__ cols,
+                               int64_t p, int nprob, const BatchScalars* __restrict__ bs, const double* __restrict__ c,
+                               const double* __restrict__ s, const uint8_t* __restrict__ keep, double* __restrict__ out) {
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < len * BNP;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = idx / BNP;
+        const int b = (int)(idx % BNP);
+        if (b >= nprob) continue;
+        double v = 0.0;
+        for (int q = 0; q < nch; ++q) v += part[((int64_t)q * len + t) * BNP + b];
+        const int64_t j = cols[t];
+        const int64_t bj = (int64_t)b * p + j;
+        const bool kept = keep == nullptr || keep[bj] != 0;
+        out[bj] = kept ? (v - c[bj] * bs[b].sum_r) / ((double)bs[b].n_rows * s[bj]) : 0.0;
+    }
+}
+
+constexpr int SPLIT_ROWS = 2048;   // rows per partial of the split scan (a multiple of BS_K)
+
+template <typename XT>
+static hipError_t bscan_split_typed(const Mat& mt, const int32_t* cols, int64_t len, const double* B, int nprob,
+                                    const BatchScalars* bs, const double* c, const double* s, const uint8_t* keep,
+                                    double* part, double* out, hipStream_t st) {
+    constexpr int W = 2, TF = 32 * W;
+    const int64_t n_pad = batch_pad(mt.n_total);
+    const int nch = (int)((n_pad + SPLIT_ROWS - 1) / SPLIT_ROWS);
+    dim3 grid((unsigned)((len + TF - 1) / TF), (unsigned)nch);
+    k_bscan<XT, 3, W, false><<<grid, 64 * W, 0, st>>>((const XT*)mt.X, mt.ldx, mt.n_total, n_pad, cols, nullptr, len, B,
+                                                      nprob, mt.p, nullptr, nullptr, nullptr, nullptr, part,
+                                                      SPLIT_ROWS);
+    k_bscan_reduce<<<grid_for(len * BNP, 256, 4096), 256, 0, st>>>(part, nch, len, cols, mt.p, nprob, bs, c, s, keep,
+                                                                    out);
     return hipGetLastError();
 }
 
@@ -908,12 +1168,65 @@ static hipError_t bscan_waves(int variant, const Mat& mt, int mode, const int32_
 
 int bscan_variant_cols(int variant) { return 32 * (variant % 3 == 0 ? 2 : (variant % 3 == 1 ? 4 : 8)); }
 
+size_t bscan_split_part_bytes(int64_t n_total, int64_t len) {
+    const int64_t nch = (batch_pad(n_total) + SPLIT_ROWS - 1) / SPLIT_ROWS;
+    return (size_t)nch * (size_t)(len > 0 ? len : 1) * BNP * sizeof(double);
+}
+
+hipError_t launch_bscan_split(const Mat& mt, const int32_t* cols, int64_t len, const double* B, int nprob,
+                              const BatchScalars* bs, const double* c, const double* s, const uint8_t* keep,
+                              double* part, double* out, hipStream_t st) {
+    if (len <= 0) return hipSuccess;
+    if (mt.xtype == 0) return bscan_split_typed<double>(mt, cols, len, B, nprob, bs, c, s, keep, part, out, st);
+    return bscan_split_typed<float>(mt, cols, len, B, nprob, bs, c, s, keep, part, out, st);
+}
+
 hipError_t launch_bscan(const Mat& mt, int mode, const int32_t* cols, const int64_t* len_dev, int64_t len_host,
                         const double* B, int nprob, BatchScalars* bs, const double* c, const double* s,
                         const uint8_t* keep, double* out, hipStream_t st, int variant) {
     if (mt.xtype == 0)
         return bscan_waves<double>(variant, mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
     return bscan_waves<float>(variant, mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
+}
+
+// Relative factor of the BF16 scan's bound on |z~ - z_fp64| (times sqrt(n_b (s^2 + c^2)) ||r_b||_2 / (n_b s)):
+// residual pieces' remainder (2^-8 + 2^-24)^3, the dropped products 2 * 2^-24 (1 + 2^-7) + 2^-32, the X split
+// 2^-24 (exact for normal f32 values; kept for subnormal ones), FP32 sums of 64 rows (group x1r1: 65 u; the
+// groups 2^-7 and 2^-15 smaller: 130 u 2^-7 + 195 u 2^-15), the FP64 sums of the chunks and groups, and
+// the FP64 scan's own rounding over n rows (2 n 2^-53).
+double bscan_bf16_rel(int64_t n_total) {
+    const double u = std::ldexp(1.0, -24), u64 = std::ldexp(1.0, -53);
+    const double ur = std::pow(std::ldexp(1.0, -8) + u, 3.0);
+    const double dropped = 2.0 * u * (1.0 + std::ldexp(1.0, -7)) + std::ldexp(1.0, -32);
+    const double gc = 65.0 * u + 130.0 * u * std::ldexp(1.0, -7) + 195.0 * u * std::ldexp(1.0, -15);
+    const double g64 = (double)(n_total / BF_K + 8) * u64 + 2.0 * (double)n_total * u64;
+    return (ur + dropped + u + gc) * (1.0 + 1e-6) + g64;
+}
+
+int64_t bscan_bf16_pieces_bytes(int64_t n_total) { return (int64_t)3 * BNP * batch_pad(n_total) * 2; }
+
+hipError_t launch_b_r_pieces(const double* R, int64_t n_total, int nprob, __bf16* Rp, hipStream_t st) {
+    const int64_t n_pad = batch_pad(n_total);
+    k_b_r_pieces<<<grid_for(n_pad * BNP, 256, 4096), 256, 0, st>>>(R, n_total, n_pad, nprob, Rp);
+    return hipGetLastError();
+}
+
+hipError_t launch_bscan_bf16(const Mat& mt, const int32_t* cols, const int64_t* len_dev, int64_t len_host,
+                             const __bf16* Rp, int nprob, const BatchScalars* bs, const double* c, const double* s,
+                             const uint8_t* keep, double* out, hipStream_t st) {
+    constexpr int W = 8;
+    const int64_t work = len_dev ? mt.p : len_host;
+    const int g = grid_for(work, 16 * W, 1 << 20);
+    k_bscan_bf16<W><<<g, 64 * W, 0, st>>>((const float*)mt.X, mt.ldx, mt.n_total, batch_pad(mt.n_total), Rp, cols,
+                                          len_dev, len_host, nprob, mt.p, bs, c, s, keep, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_band(const int32_t* cols, const int64_t* len_dev, int64_t p, int nprob, const double* z,
+                         const double* c, const double* s, const uint8_t* keep, const BatchScalars* bs,
+                         const double* lam, const double* thr, double rel, uint8_t* flag, hipStream_t st) {
+    k_b_band<<<grid_for(p, 256, 4096), 256, 0, st>>>(cols, len_dev, p, nprob, z, c, s, keep, bs, lam, thr, rel, flag);
+    return hipGetLastError();
 }
 
 hipError_t launch_b_masks(const uint8_t* masks, int64_t n_total, int nprob, double* Mb, hipStream_t st) {

@@ -80,6 +80,8 @@ enum BufId {
     H_IDENT, H_SETC, H_COL,
     // logistic regression
     L_ETA, L_G, L_R0C,
+    // batched BF16 scans
+    BB_RP, BB_FLAG, BB_LF, BB_LU, BB_PART,
     B_COUNT
 };
 

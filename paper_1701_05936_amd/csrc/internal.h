@@ -246,6 +246,22 @@ int64_t batch_pad(int64_t n_total);  // rows of the row-major right-hand sides (
 // prefetch of the next row batch
 constexpr int BSCAN_VARIANTS = 6;
 int bscan_variant_cols(int variant);
+// the standardized correlations of a short column list (len from the host) split over row ranges: more
+// workgroups than the one-pass scan, the ranges added in order by a second kernel (part: scratch)
+size_t bscan_split_part_bytes(int64_t n_total, int64_t len);
+hipError_t launch_bscan_split(const Mat& mt, const int32_t* cols, int64_t len, const double* B, int nprob,
+                              const BatchScalars* bs, const double* c, const double* s, const uint8_t* keep,
+                              double* part, double* out, hipStream_t st);
+// BF16 form of the batched check scan (f32 X): residual pieces, the scan, its bound and the band flags
+double bscan_bf16_rel(int64_t n_total);
+int64_t bscan_bf16_pieces_bytes(int64_t n_total);
+hipError_t launch_b_r_pieces(const double* R, int64_t n_total, int nprob, __bf16* Rp, hipStream_t st);
+hipError_t launch_bscan_bf16(const Mat& mt, const int32_t* cols, const int64_t* len_dev, int64_t len_host,
+                             const __bf16* Rp, int nprob, const BatchScalars* bs, const double* c, const double* s,
+                             const uint8_t* keep, double* out, hipStream_t st);
+hipError_t launch_b_band(const int32_t* cols, const int64_t* len_dev, int64_t p, int nprob, const double* z,
+                         const double* c, const double* s, const uint8_t* keep, const BatchScalars* bs,
+                         const double* lam, const double* thr, double rel, uint8_t* flag, hipStream_t st);
 hipError_t launch_bscan(const Mat& mt, int mode, const int32_t* cols, const int64_t* len_dev, int64_t len_host,
                         const double* B, int nprob, BatchScalars* bs, const double* c, const double* s,
                         const uint8_t* keep, double* out, hipStream_t st, int variant = 1);
