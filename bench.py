@@ -17,7 +17,10 @@ Workloads (--workload):
                 beside it.
   c4            batched form: AR(1) (rho 0.5) design 20,000 x 200,000 float32 (16 GB),
                 64 problems = 32 responses x 2 cross-validation row subsets, 50 lambda
-                values each; plain single-problem paths on a sample of the problems are
+                values each; check scans on BF16 matrix cores with x and r in two pieces
+                (--batch-precision bf16x2, the default; bf16x3 three pieces, fp64 FP64
+                matrix cores; the other two are timed once beside it, coefficients bit
+                for bit); plain single-problem paths on a sample of the problems are
                 timed beside it.
   c5            learned-screening form: block AR(1) (rho 0.7, blocks of 100) design
                 5,000 x 1,000,000 float32 (20 GB), 300 nonzeros in 30 blocks, SNR 3, 100
@@ -300,6 +303,17 @@ def run_precision(args, rec, ctx, bl, Xd, Xt, yd, y):
     return out
 
 
+BATCH_FORMS = {
+    # name: (precision constant, dtype text, kernel text, counter summary under profiles/)
+    "fp64": ("PREC_FP64", "f32 X, f64 MFMA check scans, f64 CD", "k_bscan (X'R, 64 right-hand sides, FP64 MFMA)",
+             "k_bscan_c4_ar1_20000x200000_f32_64rhs.md"),
+    "bf16x3": ("PREC_BF16X3", "f32 X, bf16 MFMA check scans (x, r in 3 pieces), f64 decisions in the band, f64 CD",
+               "k_bscan_bf16<3> (X'R on BF16 MFMA, 3+3 pieces)", "k_bscan_bf16x3_c4_ar1_20000x200000_f32_64rhs.md"),
+    "bf16x2": ("PREC_BF16X2", "f32 X, bf16 MFMA check scans (x, r in 2 pieces), f64 decisions in the band, f64 CD",
+               "k_bscan_bf16<2> (X'R on BF16 MFMA, 2+2 pieces)", "k_bscan_bf16x2_c4_ar1_20000x200000_f32_64rhs.md"),
+}
+
+
 def run_batch(args, rec, ctx, bl, Xd, Xt, prob):
     import numpy as np
     import torch
@@ -309,11 +323,24 @@ def run_batch(args, rec, ctx, bl, Xd, Xt, prob):
     Md = torch.from_numpy(prob.masks).to(dev)
     NB = Y.shape[0]
     kw = dict(nlambda=rec.nlambda, lambda_min_ratio=rec.lambda_min_ratio, rule=bl.SCREEN_SSR_BEDPP, tol=args.tol)
-    results, elapsed = timed(lambda: bl.fit_path_batch(ctx, Xd, Yd, Md, **kw), args.steps, args.warmup, ctx,
-                             "batch")
+    form = args.batch_precision
+    prec, dtype, kname, summary = BATCH_FORMS[form]
+    results, elapsed = timed(lambda: bl.fit_path_batch(ctx, Xd, Yd, Md, precision=getattr(bl, prec), **kw),
+                             args.steps, args.warmup, ctx, f"batch {form}")
     kernels = kernel_table(ctx, bl, elapsed)
     ctx.profile(False)
     res = results[-1]
+    # the other check-scan forms, one step each after a warm-up: coefficients bit for bit
+    others = {}
+    for o in BATCH_FORMS:
+        if o == form or args.no_other_forms:
+            continue
+        po = getattr(bl, BATCH_FORMS[o][0])
+        ro, el = timed(lambda: bl.fit_path_batch(ctx, Xd, Yd, Md, precision=po, **kw), 1, 1, ctx, f"batch {o}")
+        ko = kernel_table(ctx, bl, el)
+        ctx.profile(False)
+        others[o] = {"problem_paths_per_s": NB / el, "check_scan_avg_ms": ko["bscan"]["avg_ms"],
+                     "beta_bit_identical": bool(torch.equal(ro[-1].beta, res.beta))}
     # plain single-problem paths (row mask per problem) on a sample of the problems
     sample = [0, NB // 2 + 1, NB - 1][: max(1, args.plain_sample)]
     t_plain, dmax = [], 0.0
@@ -325,23 +352,28 @@ def run_batch(args, rec, ctx, bl, Xd, Xt, prob):
     bs = kernels["bscan"]
     paths_per_s = NB * args.steps / elapsed
     plain_pps = len(t_plain) / sum(t_plain)
+    if form == "fp64":
+        roof = {"bound": "mfma", "achieved": bs["TFLOPs"], "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": bs["TFLOPs"] / FP64_MFMA_PEAK_TFLOPS, "traffic": profiled_traffic(summary), "kernel": kname,
+                "avg_launch_ms": bs["avg_ms"], "TFLOP_per_launch": bs["TFLOP_per_launch"], "GBs": bs["GBs"]}
+    else:
+        # the BF16 forms read X once per launch and take 3 (2 pieces) or 6 (3 pieces) BF16 products per FP64
+        # product: far below the BF16 matrix-core peak, so HBM bounds them
+        roof = hbm_roofline(bs, kname, summary)
     out = {
         "value": paths_per_s,
         "ms_per_step": elapsed * 1e3 / args.steps,
-        "dtype": "f32 X, f64 MFMA scans, f64 CD",
+        "dtype": dtype,
         "config": {"workload": f"{rec.name}: AR(1) rho {rec.rho} X {rec.n}x{rec.p} float32, {NB} problems "
                                f"({rec.nresp} responses x {rec.nsub} CV row subsets, rows "
                                f"{int(prob.masks.sum(1).min())}..{int(prob.masks.sum(1).max())}), "
                                f"{rec.nlambda} lambda to {rec.lambda_min_ratio} lambda_max each, SSR-BEDPP, "
-                               f"CD tol {args.tol:g}; value counts problem paths",
-                   "n": rec.n, "p": rec.p, "nlambda": rec.nlambda, "nprob": NB},
-        "roofline": {"bound": "mfma", "achieved": bs["TFLOPs"], "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": bs["TFLOPs"] / FP64_MFMA_PEAK_TFLOPS,
-                     "traffic": profiled_traffic("k_bscan_c4_ar1_20000x200000_f32_64rhs.md"),
-                     "kernel": "k_bscan (X'R, 64 right-hand sides, FP64 MFMA)", "avg_launch_ms": bs["avg_ms"],
-                     "TFLOP_per_launch": bs["TFLOP_per_launch"], "GBs": bs["GBs"]},
+                               f"CD tol {args.tol:g}, check scans {form}; value counts problem paths",
+                   "n": rec.n, "p": rec.p, "nlambda": rec.nlambda, "nprob": NB, "check_scans": form},
+        "roofline": roof,
         "kernels": kernels,
-        "forms": {"plain_gpu_paths_per_s": plain_pps, "plain_sample": sample, "scan_cols_autotuned": res.scan_cols,
+        "forms": {"check_scans": form, "other_check_scans": others,
+                  "plain_gpu_paths_per_s": plain_pps, "plain_sample": sample, "scan_cols_autotuned": res.scan_cols,
                   "speedup_vs_plain_gpu": paths_per_s / plain_pps,
                   "max_abs_dbeta_vs_plain_path": dmax},
         "path": {"sweeps": int(res.sweeps.sum()), "violations": int(res.n_viol.sum()),
@@ -512,7 +544,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision-form", default="i8x4", choices=tuple(PRECISION_FORMS),
                     help="matrix-core form of the c3 check scans (the other form is timed once beside it)")
-    ap.add_argument("--no-other-forms", action="store_true", help="c3: skip the other precision form's path")
+    ap.add_argument("--no-other-forms", action="store_true",
+                    help="c3, c4: skip the other precision forms' paths")
+    ap.add_argument("--batch-precision", default="bf16x2", choices=tuple(BATCH_FORMS),
+                    help="c4: arithmetic of the batched form's check scans (the others are timed once beside it)")
     ap.add_argument("--copy-calib", type=float, default=0.0,
                     help="only copy a buffer of this many GB once (device to device) and exit: the reference "
                          "kernel for scaling FETCH_SIZE / WRITE_SIZE counters")

@@ -212,12 +212,16 @@ bl_status bl_kkt_check_noalloc(bl_ctx ctx, const bl_matrix* X, const double* cen
 /* Arithmetic of the check scans. */
 typedef enum {
     BL_PREC_FP64 = 0,      /* FP64 vector scan (any X type)                                          */
-    BL_PREC_BF16X3 = 1,    /* int8 X only: BF16 matrix cores against three BF16 pieces of the residual,
+    BL_PREC_BF16X3 = 1,    /* int8 X: BF16 matrix cores against three BF16 pieces of the residual,
                               FP32 chunks promoted to FP64; decisions within the error bound are
-                              re-taken on the FP64 scan, so they equal the FP64 decisions            */
-    BL_PREC_I8X4 = 2       /* int8 X only: int8 dot products against four int8 pieces of the residual
+                              re-taken on the FP64 scan, so they equal the FP64 decisions.
+                              Batched form, f32 X: x and r each in three BF16 pieces, six products */
+    BL_PREC_I8X4 = 2,      /* int8 X only: int8 dot products against four int8 pieces of the residual
                               with power-of-two scales, exact integer sums; decisions within the
                               error bound are re-taken on the FP64 scan, as for BL_PREC_BF16X3       */
+    BL_PREC_BF16X2 = 3     /* batched form, f32 X only: x and r each in two BF16 pieces, three products
+                              (bound about 5e-5 against 7e-6 for BF16X3: a wider band of FP64
+                              re-scans for half the matrix-core work); decisions as the FP64 scan's  */
 } bl_precision;
 
 /*
@@ -374,8 +378,13 @@ bl_status bl_fit_path_host(bl_ctx ctx, const bl_matrix* X, const double* y, cons
  * lockstep; every pass over X (column statistics, lambda_max and BEDPP products,
  * post-convergence scans) serves all problems at once on FP64 matrix cores.  The screening
  * kernels of a lambda step are captured once per call in a HIP graph and replayed.
- * Options as bl_fit_path (precision FP64, no learned rule, no resume); X->row_mask must be NULL; X is
- * f32 or f64.  opts->lambda NULL gives each problem its own grid from its own lambda_max; a host grid
+ * Options as bl_fit_path (no learned rule, resume, elastic net or penalty factors); X->row_mask must
+ * be NULL; X is f32 or f64.  opts->precision: BL_PREC_FP64 (FP64 matrix cores), or for f32 X
+ * BL_PREC_BF16X3 / BL_PREC_BF16X2, the check scans on BF16 matrix cores with x and r split into
+ * three / two BF16 pieces; every (column, problem) whose z lies within the scan's error bound of a
+ * threshold the path decides on (this check, the next strong rule) is re-scanned in FP64, and every
+ * solve starts from FP64 gradients of its working set, so coefficients and counts are bit-identical to
+ * the FP64 form's.  opts->lambda NULL gives each problem its own grid from its own lambda_max; a host grid
  * (K decreasing values) is shared by every problem, as cross-validation needs (Section 3.1.2), and is
  * solved from its first point (beta = 0 where that point is at or above the problem's lambda_max).
  */
@@ -508,11 +517,14 @@ bl_status bl_mlp_train(bl_ctx ctx, const float* feat, const float* label, int64_
  *   colstats  p x n_total x sizeof(element)
  *   gram      Gram entries of new pool members and the gather of the working set's Gram
  *   rupdate   residual update after a solve: m x n_total x sizeof(element)
- *   recheck   precision form: residual pieces, error band and FP64 re-scans of flagged and set columns
- *   setup     precision form: the two FP64 set-up scans (lambda_max and BEDPP products); the plain
- *             path counts them under scan (same kernel)
- *   bscan     batched form: the shared X'R contraction, columns x n_total x sizeof(element) + n_total x nprob x 8
- *             bytes and 2 x columns x n_total x nprob flops per launch
+ *   recheck   precision form: residual pieces, error band and FP64 re-scans of flagged and set columns;
+ *             batched form: the FP64 scan of the working sets' union before each solve and (BF16 scans)
+ *             the band and its FP64 re-scan after it, units = columns re-scanned
+ *   setup     precision and batched forms: the two FP64 set-up scans (lambda_max and BEDPP products); the
+ *             plain path counts them under scan (same kernel)
+ *   bscan     batched form: the check scans X_cols'R, columns x n_total x sizeof(element) + the right-hand
+ *             sides once (n_total x nprob x 8 bytes; BF16 forms: their 2 or 3 BF16 pieces) bytes and
+ *             2 x columns x n_total x nprob flops (the FP64 contraction's) per launch
  * bl_profile(ctx, 1) enables and resets the counters, bl_profile(ctx, 0) disables.
  */
 typedef struct {

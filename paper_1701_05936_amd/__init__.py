@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libbl.so")
 BL_OK, BL_ERR_INVALID, BL_ERR_NOMEM, BL_ERR_DEVICE, BL_ERR_NOT_CONVERGED, BL_ERR_UNSUPPORTED = range(6)
 X_F64, X_F32, X_I8 = 0, 1, 2
 SCREEN_NONE, SCREEN_SSR, SCREEN_BEDPP, SCREEN_SSR_BEDPP, SCREEN_LEARNED, SCREEN_ACTIVE = 0, 1, 2, 3, 4, 5
-PREC_FP64, PREC_BF16X3, PREC_I8X4 = 0, 1, 2
+PREC_FP64, PREC_BF16X3, PREC_I8X4, PREC_BF16X2 = 0, 1, 2, 3
 FAMILY_GAUSSIAN, FAMILY_BINOMIAL = 0, 1
 
 _STATUS_NAMES = {0: "BL_OK", 1: "BL_ERR_INVALID", 2: "BL_ERR_NOMEM", 3: "BL_ERR_DEVICE",

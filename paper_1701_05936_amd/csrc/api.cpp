@@ -909,8 +909,10 @@ bl_status bl_scan(bl_ctx ctx, const bl_matrix* X, const double* center, const do
     if (!center || !scale || !r || !z) return fail(ctx, BL_ERR_INVALID, "array arguments must be non-NULL");
     if (len < 0 || len > m.p) return fail(ctx, BL_ERR_INVALID, "len out of range");
     if (len > 0 && !cols) return fail(ctx, BL_ERR_INVALID, "cols is NULL");
-    if (precision != BL_PREC_FP64 && precision != BL_PREC_BF16X3 && precision != BL_PREC_I8X4)
+    if (precision != BL_PREC_FP64 && precision != BL_PREC_BF16X3 && precision != BL_PREC_I8X4 &&
+        precision != BL_PREC_BF16X2)
         return fail(ctx, BL_ERR_INVALID, "unknown precision");
+    if (precision == BL_PREC_BF16X2) return fail(ctx, BL_ERR_UNSUPPORTED, "BF16X2 scans are the batched form's");
     if (precision != BL_PREC_FP64 && !lowp_supported(m))
         return fail(ctx, BL_ERR_UNSUPPORTED, "matrix-core scans need int8 X with 16-byte aligned columns");
     int64_t n;
@@ -1295,8 +1297,11 @@ bl_status fit_path_impl(bl_ctx ctx, const XAccess& xa, const double* y, const bl
         return fail(ctx, BL_ERR_UNSUPPORTED, "resuming needs no z history: not with the learned rule or training records");
     const float tau_logit = learned && opts->mlp_tau > 0.0 ? (float)std::log(opts->mlp_tau / (1.0 - opts->mlp_tau))
                                                            : -INFINITY;
-    if (opts->precision != BL_PREC_FP64 && opts->precision != BL_PREC_BF16X3 && opts->precision != BL_PREC_I8X4)
+    if (opts->precision != BL_PREC_FP64 && opts->precision != BL_PREC_BF16X3 && opts->precision != BL_PREC_I8X4 &&
+        opts->precision != BL_PREC_BF16X2)
         return fail(ctx, BL_ERR_INVALID, "unknown precision");
+    if (opts->precision == BL_PREC_BF16X2)
+        return fail(ctx, BL_ERR_UNSUPPORTED, "BF16X2 scans are the batched form's");
     const bool lowp = opts->precision != BL_PREC_FP64;
     const bool i8 = opts->precision == BL_PREC_I8X4;
     if (lowp && !lowp_supported(m))

@@ -133,9 +133,10 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
     if (!(opts->tol > 0.0) || opts->max_sweeps < 1 || opts->max_rounds < 1)
         return fail(ctx, BL_ERR_INVALID, "tol > 0, max_sweeps >= 1 and max_rounds >= 1 are required");
     // check scans: FP64 matrix cores, or (f32 X) BF16 matrix cores with FP64 re-scans of the decisions in the band
-    const bool bf = opts->precision == BL_PREC_BF16X3;
+    const bool bf = opts->precision == BL_PREC_BF16X3 || opts->precision == BL_PREC_BF16X2;
+    const int pieces = opts->precision == BL_PREC_BF16X2 ? 2 : 3;
     if (opts->precision != BL_PREC_FP64 && !(bf && m.xtype == BL_X_F32))
-        return fail(ctx, BL_ERR_UNSUPPORTED, "batched form: FP64 scans, or BF16X3 scans of f32 X");
+        return fail(ctx, BL_ERR_UNSUPPORTED, "batched form: FP64 scans, or BF16X3 / BF16X2 scans of f32 X");
     // the active-set rule keeps only the previous active set: the strong rule with an infinite threshold
     const bool active_only = opts->rule == BL_SCREEN_ACTIVE;
     const bool bedpp = opts->rule == BL_SCREEN_BEDPP || opts->rule == BL_SCREEN_SSR_BEDPP || active_only;
@@ -197,10 +198,10 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
     int32_t *lF = nullptr, *lU = nullptr;
     int64_t* lenF = lens + BNP + 2;
     int64_t* lenU = lens + BNP + 3;
-    const double bf_rel = bf ? bscan_bf16_rel(nt) : 0.0;
+    const double bf_rel = bf ? bscan_bf16_rel(nt, pieces) : 0.0;
     ENSURE(BB_LU, p * 4, lU);
     if (bf) {
-        ENSURE(BB_RP, (size_t)bscan_bf16_pieces_bytes(nt), Rp);
+        ENSURE(BB_RP, (size_t)bscan_bf16_pieces_bytes(nt, pieces), Rp);
         ENSURE(BB_FLAG, p, flag);
         ENSURE(BB_LF, p * 4, lF);
     }
@@ -250,7 +251,7 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
     HIPCHK(launch_b_argmax(a, keep, p, NB, bs, st));
     if ((s = read_bs())) return s;
     prof_add(ctx, 0, BL_PROF_COLSTATS, 2.0 * p * nt * es);
-    prof_add(ctx, 2, BL_PROF_BSCAN, (double)p * nt * es + (double)nt * NB * 8.0, 2.0 * p * nt * NB);
+    prof_add(ctx, 2, BL_PROF_SETUP, (double)p * nt * es + (double)nt * NB * 8.0, 2.0 * p * nt * NB, (double)p);
     std::vector<double> lmax(NB);
     for (int b = 0; b < NB; ++b) {
         const BatchScalars& h = hp->bs[b];
@@ -269,7 +270,7 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
         prof_mark(ctx, 3);
         HIPCHK(launch_b_sum_r(R, nt, NB, bs, st));    // back to the residual's sum and ||y~||^2
         HIPCHK(hipStreamSynchronize(st));
-        prof_add(ctx, 2, BL_PROF_BSCAN, (double)p * nt * es + (double)nt * NB * 8.0, 2.0 * p * nt * NB);
+        prof_add(ctx, 2, BL_PROF_SETUP, (double)p * nt * es + (double)nt * NB * 8.0, 2.0 * p * nt * NB, (double)p);
     }
     // lambda grids (own lambda_max per problem) and strong-rule thresholds, resident on the device
     std::vector<double> lam((size_t)NB * K), lg((size_t)(K + 1) * BNP, 0.0), tg((size_t)K * BNP, 0.0);
@@ -409,12 +410,13 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
                 HIPCHK(launch_bscan(m, 2, lT, lenT, 0, R, NB, bs, c, sd, keep, zcur, st, waves));
                 prof_mark(ctx, 3);
             } else {
-                HIPCHK(launch_b_r_pieces(R, nt, NB, Rp, st));
+                HIPCHK(launch_b_r_pieces(R, nt, NB, pieces, Rp, st));
                 prof_mark(ctx, 2);
-                HIPCHK(launch_bscan_bf16(m, lT, lenT, 0, Rp, NB, bs, c, sd, keep, zcur, st));
+                HIPCHK(launch_bscan_bf16(m, lT, lenT, 0, pieces, Rp, NB, bs, c, sd, keep, zcur, st));
                 prof_mark(ctx, 3);
                 // decisions within the bound of a threshold (this check, the next strong rule) are re-taken on
                 // the FP64 scan of those columns
+                prof_mark(ctx, 0);
                 HIPCHK(launch_fill_u8(flag, 0, p, st));
                 HIPCHK(launch_b_band(lT, lenT, p, NB, zcur, c, sd, keep, bs, lam_k,
                                      (ssr && k + 1 < K) ? thrg + (size_t)(k + 1) * BNP : nullptr, bf_rel, flag, st));
@@ -424,6 +426,7 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
                 double* part;
                 ENSURE(BB_PART, bscan_split_part_bytes(nt, hp->lenF), part);
                 HIPCHK(launch_bscan_split(m, lF, hp->lenF, R, NB, bs, c, sd, keep, part, zcur, st));
+                prof_mark(ctx, 1);
             }
             if (ssr) HIPCHK(launch_b_viol(lT, lenT, p, NB, zcur, safe, strong, lam_k, wv, bs, st));
             HIPCHK(hipMemcpyAsync(&hp->lenT, lenT, 8, hipMemcpyDeviceToHost, st));
@@ -436,10 +439,11 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
                     cd_updates += (double)hp->bs[b].sweeps * hp->lens[b];
                 }
             prof_add(ctx, 6, BL_PROF_CD, cd_bytes, 0.0, cd_updates);
-            prof_add(ctx, 2, BL_PROF_BSCAN, (double)hp->lenT * nt * es + (double)nt * NB * (bf ? 6.0 : 8.0),
+            prof_add(ctx, 2, BL_PROF_BSCAN, (double)hp->lenT * nt * es + (double)nt * NB * (bf ? 2.0 * pieces : 8.0),
                      2.0 * hp->lenT * nt * NB, (double)hp->lenT);
-            // the FP64 scan of the working sets' union (BF16 form: the band's re-scans are not in this figure)
+            // the FP64 scans of the working sets' union and (BF16 form) of the columns in the band
             prof_add(ctx, 8, BL_PROF_RECHECK, (double)hp->lenU * nt * es, 0.0, (double)hp->lenU);
+            if (bf) prof_add(ctx, 0, BL_PROF_RECHECK, (double)hp->lenF * nt * es, 0.0, (double)hp->lenF);
             bool any = false;
             for (int b = 0; b < NB; ++b) {
                 if (!act[b]) continue;

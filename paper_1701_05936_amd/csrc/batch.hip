@@ -16,6 +16,7 @@
 #include <stdint.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "chain.h"
 #include "internal.h"
@@ -197,27 +198,31 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVE
 }
 
 // ---- the shared contraction on BF16 matrix cores (f32 X) ----------------------------------------------
-// The check scans of the batched form as Z = X_cols' R with both operands split into three BF16 pieces:
-//   x = x1 + x2 + x3 (f32 x: x1 = bf16(x), x2 = bf16(x - x1), x3 = bf16(x - x1 - x2), exact for normal x),
-//   r = r1 + r2 + r3 (FP64 r, remainder below (2^-8 + 2^-24)^3 |r|),
-// and the six products of order at most 4 taken on v_mfma_f32_16x16x32_bf16 (x1r1; x1r2 + x2r1;
-// x1r3 + x2r2 + x3r1: the dropped x2r3, x3r2, x3r3 are below 2^-23 |x| |r|).  Each of the three groups sums
-// in its own FP32 accumulator for 64 rows (two 32-row steps), then goes to FP64.  The error per (column,
-// problem) is bounded by bscan_bf16_rel() sqrt(n_b (s^2 + c^2)) ||r_b||_2 / (n_b s) (plus the FP64 scan's own
-// rounding, so that decisions outside the band equal the FP64 scan's); decisions within the band are
-// re-taken on the FP64 scan.
+// The check scans of the batched form as Z = X_cols' R with both operands split into PC = 2 or 3 BF16
+// pieces (round to nearest at every step):
+//   x = x_1 + .. + x_PC + dx,  x_1 = bf16(x), x_k = bf16(x - x_1 - .. - x_k-1)  (the differences are exact in FP32),
+//   r = r_1 + .. + r_PC + dr,  r_k = bf16((float)(r - r_1 - .. - r_k-1))      (the differences are exact in FP64),
+// |dx| <= e^PC |x| and |dr| <= (e + 2u)^PC |r| with e = 2^-8, u = 2^-24.  The products x_a r_b with
+// a + b <= PC + 1 are taken on v_mfma_f32_16x16x32_bf16 (PC = 3: six, PC = 2: three); the rest are dropped.
+// x_1 r_1 sums in an FP32 accumulator for one 64-row chunk (two 32-row steps), then goes to FP64; the smaller
+// products (at most 2^-7 (1 + 2^-6) |x| |r| together) share a second FP32 accumulator that goes to FP64
+// every BF_PROMO chunks.  bscan_bf16_rel() bounds the difference from the FP64 scan; decisions within that
+// band are re-taken on the FP64 scan of those columns.
 // Tile: a wavefront owns 16 columns against the 64 problems (four 16-problem tiles); lane (m, g) feeds rows
 // 8g .. 8g+7 of a 32-row step of column m (A) and of problem 16 nt + m (B).  The residual pieces of a
-// 64-row chunk sit in LDS, [piece][problem][row] with a padded row stride, double buffered.
+// 64-row chunk sit in LDS, [piece][problem][row] with a padded row stride, double buffered; the lane's X
+// values of the next two chunks are in flight in three register buffers taken in turn (the chunk loop is
+// unrolled three times so that no buffer is copied).
 constexpr int BF_K = 64;          // rows per chunk (two 32-row matrix-core steps)
 constexpr int BF_RS = BF_K + 8;   // LDS stride of a (piece, problem) row block, bf16 elements (144 bytes)
+constexpr int BF_PROMO = 9;       // chunks between promotions of the second accumulator (a multiple of 3)
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x8 __attribute__((ext_vector_type(8)));
 typedef int v4i32 __attribute__((ext_vector_type(4)));
 
-// residual pieces of every problem, problem-major per piece: Rp[(c * BNP + b) * n_pad + i]
-__global__ void k_b_r_pieces(const double* __restrict__ R, int64_t n_total, int64_t n_pad, int nprob,
+// residual pieces of every problem, problem-major per piece: Rp[(c * BNP + b) * n_pad + i], c < PC
+__global__ void k_b_r_pieces(const double* __restrict__ R, int64_t n_total, int64_t n_pad, int nprob, int pc,
                              __bf16* __restrict__ Rp) {
     const int64_t total = n_pad * BNP;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -225,8 +230,7 @@ __global__ void k_b_r_pieces(const double* __restrict__ R, int64_t n_total, int6
         const int64_t i = idx % n_pad;
         const int b = (int)(idx / n_pad);
         double rem = (i < n_total && b < nprob) ? R[i * BNP + b] : 0.0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < pc; ++c) {
             const __bf16 v = (__bf16)(float)rem;
             Rp[((int64_t)c * BNP + b) * n_pad + i] = v;
             rem -= (double)(float)v;
@@ -234,16 +238,19 @@ __global__ void k_b_r_pieces(const double* __restrict__ R, int64_t n_total, int6
     }
 }
 
-template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_bscan_bf16(const float* __restrict__ X, int64_t ldx, int64_t n_total,
+template <int WAVES, int PC>
+__global__ __launch_bounds__(64 * WAVES, 8 / WAVES) void k_bscan_bf16(const float* __restrict__ X, int64_t ldx, int64_t n_total,
                                                            int64_t n_pad, const __bf16* __restrict__ Rp,
                                                            const int32_t* __restrict__ cols,
                                                            const int64_t* __restrict__ len_dev, int64_t len_host,
                                                            int nprob, int64_t p, const BatchScalars* __restrict__ bs,
                                                            const double* __restrict__ c, const double* __restrict__ s,
                                                            const uint8_t* __restrict__ keep, double* __restrict__ out) {
+    static_assert(PC == 2 || PC == 3, "two or three pieces");
+    static_assert(BF_PROMO % 3 == 0, "the main loop promotes after whole groups of three chunks");
     constexpr int NT = 64 * WAVES;
-    __shared__ __bf16 Rl[2][3 * BNP * BF_RS];
+    constexpr int PLANE = PC * BNP * BF_RS;
+    __shared__ __bf16 Rl[2 * PLANE];
     const int64_t len = len_dev ? *len_dev : len_host;
     const int64_t f0 = (int64_t)blockIdx.x * 16 * WAVES;
     if (f0 >= len) return;
@@ -253,121 +260,168 @@ __global__ __launch_bounds__(64 * WAVES) void k_bscan_bf16(const float* __restri
     const bool ok = t < len;
     const int64_t j = ok ? (cols ? (int64_t)cols[t] : t) : 0;   // lanes past the list read column 0, unused
     const float* xc = X + j * ldx;
-    // staging of one chunk's pieces: 3 x 64 problems x 64 rows = 1536 16-byte blocks
-    constexpr int SB = 3 * BNP * (BF_K / 8);
+    // staging of one chunk's pieces: PC x 64 problems x 64 rows in 16-byte blocks
+    constexpr int SB = PC * BNP * (BF_K / 8);
     constexpr int SPT = (SB + NT - 1) / NT;
     v4i32 sreg[SPT];
-    auto stage_load = [&](int64_t i0) {
+    auto stage_load = [&](int64_t ck) {
 #pragma unroll
         for (int q = 0; q < SPT; ++q) {
             const int blk = tid + q * NT;
             if (blk < SB) {
                 const int cb = blk / (BF_K / 8), r8 = blk % (BF_K / 8);
-                sreg[q] = *reinterpret_cast<const v4i32*>(Rp + (int64_t)cb * n_pad + i0 + 8 * r8);
+                sreg[q] = *reinterpret_cast<const v4i32*>(Rp + (int64_t)cb * n_pad + ck * BF_K + 8 * r8);
             }
         }
     };
-    auto stage_store = [&](int buf) {
+    auto stage_store = [&](__bf16* dst) {
 #pragma unroll
         for (int q = 0; q < SPT; ++q) {
             const int blk = tid + q * NT;
             if (blk < SB) {
                 const int cb = blk / (BF_K / 8), r8 = blk % (BF_K / 8);
-                *reinterpret_cast<v4i32*>(&Rl[buf][cb * BF_RS + 8 * r8]) = sreg[q];
+                *reinterpret_cast<v4i32*>(dst + cb * BF_RS + 8 * r8) = sreg[q];
             }
         }
     };
-    // the lane's 16 values of a chunk: rows i0 + 32 ks + 8 g .. +7 for ks = 0, 1 (zero past n_total); the next
-    // two chunks' loads are in flight while a chunk is on the matrix cores
-    float xr[16], xn[16], xm[16];
-    auto load_x = [&](float (&dst)[16], int64_t i0) {
-        if (i0 + BF_K <= n_total) {
+    // the lane's 16 values of chunk ck: rows 64 ck + 32 ks + 8 g .. +7 for ks = 0, 1; load_fast for chunks
+    // inside n_total, load_x zero past it
+    auto load_fast = [&](float (&dst)[16], int64_t ck) {
 #pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                const float4* src = reinterpret_cast<const float4*>(xc + i0 + 32 * ks + 8 * g);
-                const float4 a = src[0], b = src[1];
-                dst[8 * ks + 0] = a.x; dst[8 * ks + 1] = a.y; dst[8 * ks + 2] = a.z; dst[8 * ks + 3] = a.w;
-                dst[8 * ks + 4] = b.x; dst[8 * ks + 5] = b.y; dst[8 * ks + 6] = b.z; dst[8 * ks + 7] = b.w;
-            }
+        for (int ks = 0; ks < 2; ++ks) {
+            const float4* src = reinterpret_cast<const float4*>(xc + ck * BF_K + 32 * ks + 8 * g);
+            const float4 a = src[0], b = src[1];
+            dst[8 * ks + 0] = a.x; dst[8 * ks + 1] = a.y; dst[8 * ks + 2] = a.z; dst[8 * ks + 3] = a.w;
+            dst[8 * ks + 4] = b.x; dst[8 * ks + 5] = b.y; dst[8 * ks + 6] = b.z; dst[8 * ks + 7] = b.w;
+        }
+    };
+    auto load_x = [&](float (&dst)[16], int64_t ck) {
+        if ((ck + 1) * BF_K <= n_total) {
+            load_fast(dst, ck);
         } else {
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
-                    const int64_t i = i0 + 32 * ks + 8 * g + q;
+                    const int64_t i = ck * BF_K + 32 * ks + 8 * g + q;
                     dst[8 * ks + q] = i < n_total ? xc[i] : 0.f;
                 }
         }
     };
     double acc64[4][4];
+    f32x4 a2[4];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+    for (int nt = 0; nt < 4; ++nt) {
+        a2[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc64[nt][q] = 0.0;
-    int buf = 0;
-    load_x(xr, 0);
-    if (BF_K < n_pad) load_x(xn, BF_K);
-    stage_load(0);
-    stage_store(0);
-    __syncthreads();
-    for (int64_t i0 = 0; i0 < n_pad; i0 += BF_K) {
-        const bool more = i0 + BF_K < n_pad;
-        if (i0 + 2 * BF_K < n_pad) load_x(xm, i0 + 2 * BF_K);
-        if (more) stage_load(i0 + BF_K);
-        const __bf16* Rb = Rl[buf];
-        f32x4 a1[4], a2[4], a3[4];
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            a1[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
-            a2[nt] = a1[nt];
-            a3[nt] = a1[nt];
-        }
+    }
+    int ch = 0;   // chunks done; the chunk being computed reads LDS buffer ch & 1
+    // one chunk's matrix-core steps on the lane's values xr; x_1 r_1 goes to FP64 at the end
+    auto compute = [&](const float (&xr)[16]) {
+        const __bf16* Rb = Rl + (ch & 1) * PLANE;
+        f32x4 a1[4];
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
             f32x8 xv;
 #pragma unroll
             for (int q = 0; q < 8; ++q) xv[q] = xr[8 * ks + q];
-            const bf16x8 x1 = __builtin_convertvector(xv, bf16x8);
-            const f32x8 d1 = xv - __builtin_convertvector(x1, f32x8);
-            const bf16x8 x2 = __builtin_convertvector(d1, bf16x8);
-            const f32x8 d2 = d1 - __builtin_convertvector(x2, f32x8);
-            const bf16x8 x3 = __builtin_convertvector(d2, bf16x8);
+            bf16x8 xp[PC];
+            xp[0] = __builtin_convertvector(xv, bf16x8);
+            f32x8 d = xv - __builtin_convertvector(xp[0], f32x8);
+            xp[1] = __builtin_convertvector(d, bf16x8);
+            if constexpr (PC == 3) {
+                d = d - __builtin_convertvector(xp[1], f32x8);
+                xp[2] = __builtin_convertvector(d, bf16x8);
+            }
             const int roff = 32 * ks + 8 * g;
-            // all twelve residual fragments of the step first (one wait), then the 24 matrix-core steps ordered
-            // so that steps on the same accumulator are at least four apart
-            bf16x8 rb[3][4];
+            bf16x8 rb[PC][4];
 #pragma unroll
-            for (int pc = 0; pc < 3; ++pc)
+            for (int pc = 0; pc < PC; ++pc)
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt)
                     rb[pc][nt] = *reinterpret_cast<const bf16x8*>(Rb + (pc * BNP + 16 * nt + m) * BF_RS + roff);
+            const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) a1[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, rb[0][nt], a1[nt], 0, 0, 0);
+            for (int nt = 0; nt < 4; ++nt)
+                a1[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xp[0], rb[0][nt], ks == 0 ? zero : a1[nt], 0, 0, 0);
+            // the smaller products, in decreasing order of magnitude: x1 r2, x2 r1 (, x1 r3, x2 r2, x3 r1)
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) a2[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, rb[1][nt], a2[nt], 0, 0, 0);
+            for (int nt = 0; nt < 4; ++nt) a2[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xp[0], rb[1][nt], a2[nt], 0, 0, 0);
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) a3[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, rb[2][nt], a3[nt], 0, 0, 0);
+            for (int nt = 0; nt < 4; ++nt) a2[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xp[1], rb[0][nt], a2[nt], 0, 0, 0);
+            if constexpr (PC == 3) {
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) a2[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x2, rb[0][nt], a2[nt], 0, 0, 0);
+                for (int nt = 0; nt < 4; ++nt) a2[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xp[0], rb[2][nt], a2[nt], 0, 0, 0);
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) a3[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x2, rb[1][nt], a3[nt], 0, 0, 0);
+                for (int nt = 0; nt < 4; ++nt) a2[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xp[1], rb[1][nt], a2[nt], 0, 0, 0);
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) a3[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x3, rb[0][nt], a3[nt], 0, 0, 0);
+                for (int nt = 0; nt < 4; ++nt) a2[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xp[2], rb[0][nt], a2[nt], 0, 0, 0);
+            }
         }
-        // the chunk's three FP32 sums go to FP64 (smallest first)
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc64[nt][q] += ((double)a3[nt][q] + (double)a2[nt][q]) + (double)a1[nt][q];
-        if (more) stage_store(buf ^ 1);   // the other buffer was last read before the previous barrier
+            for (int q = 0; q < 4; ++q) acc64[nt][q] += (double)a1[nt][q];
+    };
+    auto promote2 = [&]() {
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc64[nt][q] += (double)a2[nt][q];
+            a2[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    // next chunk's pieces into the other LDS buffer (last read before the previous barrier), then the barrier
+    auto next = [&]() {
+        stage_store(Rl + ((ch & 1) ^ 1) * PLANE);
         __syncthreads();
-        buf ^= 1;
+        ++ch;
+    };
+    const int64_t C = n_pad / BF_K, F = n_total / BF_K;   // chunks; chunks wholly inside n_total
+    // main loop: groups of three chunks, one per register buffer, whose loads (the pieces of the next chunk,
+    // then X two chunks ahead) are all unguarded; the pieces are issued first so that waiting for them leaves
+    // the X loads in flight
+    const int64_t Cmain = F >= 2 ? 3 * ((F - 2) / 3) : 0;
+    float xb[3][16];
+    load_x(xb[0], 0);
+    if (C > 1) load_x(xb[1], 1);
+    stage_load(0);
+    stage_store(Rl);
+    __syncthreads();
+    for (int64_t ck = 0; ck < Cmain; ck += 3) {
+        stage_load(ck + 1);
+        load_fast(xb[2], ck + 2);
+        compute(xb[0]);
+        next();
+        stage_load(ck + 2);
+        load_fast(xb[0], ck + 3);
+        compute(xb[1]);
+        next();
+        stage_load(ck + 3);
+        load_fast(xb[1], ck + 4);
+        compute(xb[2]);
+        next();
+        if (ch % BF_PROMO == 0) promote2();
+    }
+    promote2();
+    // the last chunks (at most five): guarded loads, one chunk ahead of the pieces and two of X
+    for (int64_t ck = Cmain; ck < C; ++ck) {
+        const bool more = ck + 1 < C;
+        if (more) stage_load(ck + 1);
+        float xn[16] = {};
+        if (ck + 2 < C) load_x(xn, ck + 2);
+        compute(xb[0]);
+        if (more) stage_store(Rl + ((ch & 1) ^ 1) * PLANE);
+        __syncthreads();
+        ++ch;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            xr[q] = xn[q];
-            xn[q] = xm[q];
+            xb[0][q] = xb[1][q];
+            xb[1][q] = xn[q];
         }
     }
+    promote2();
     // lane (m, g), register q of problem tile nt: column 16 w + 4 g + q of the workgroup, problem 16 nt + m
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -1189,36 +1243,61 @@ hipError_t launch_bscan(const Mat& mt, int mode, const int32_t* cols, const int6
     return bscan_waves<float>(variant, mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
 }
 
-// Relative factor of the BF16 scan's bound on |z~ - z_fp64| (times sqrt(n_b (s^2 + c^2)) ||r_b||_2 / (n_b s)):
-// residual pieces' remainder (2^-8 + 2^-24)^3, the dropped products 2 * 2^-24 (1 + 2^-7) + 2^-32, the X split
-// 2^-24 (exact for normal f32 values; kept for subnormal ones), FP32 sums of 64 rows (group x1r1: 65 u; the
-// groups 2^-7 and 2^-15 smaller: 130 u 2^-7 + 195 u 2^-15), the FP64 sums of the chunks and groups, and
-// the FP64 scan's own rounding over n rows (2 n 2^-53).
-double bscan_bf16_rel(int64_t n_total) {
-    const double u = std::ldexp(1.0, -24), u64 = std::ldexp(1.0, -53);
-    const double ur = std::pow(std::ldexp(1.0, -8) + u, 3.0);
-    const double dropped = 2.0 * u * (1.0 + std::ldexp(1.0, -7)) + std::ldexp(1.0, -32);
-    const double gc = 65.0 * u + 130.0 * u * std::ldexp(1.0, -7) + 195.0 * u * std::ldexp(1.0, -15);
-    const double g64 = (double)(n_total / BF_K + 8) * u64 + 2.0 * (double)n_total * u64;
-    return (ur + dropped + u + gc) * (1.0 + 1e-6) + g64;
+// Relative factor of the BF16 scan's bound on |z~ - z_fp64| (times sqrt(n_b (s^2 + c^2)) ||r_b||_2 / (n_b s),
+// which bounds sum_i |x_ij| |r_ib| / (n_b s_j) by Cauchy-Schwarz), for pc pieces of x and r.  With e = 2^-8,
+// er = e + 2u (u = 2^-24) and |x_a| <= e^(a-1) (1 + e) |x|, |r_b| <= er^(b-1) (1 + er) |r|:
+//   the dropped products (a + b > pc + 1), the remainders dx (e^pc |x|, kept although x is exact for pc = 3 and
+//   normal f32 values) and dr (er^pc |r|);
+//   the FP32 sums, bounded as sequential FP32 additions of every product (a matrix-core step adds 32 exact
+//   products of BF16 pieces to its accumulator): gamma_64 on x_1 r_1 (one chunk) and gamma_N2 on the other
+//   products (N2 = 64 BF_PROMO (products - 1) terms between promotions);
+//   the FP64 sums of the promoted values (one per chunk, one per BF_PROMO chunks, at most 2 n / 64 + 8 terms)
+//   and the FP64 scan's own rounding over n rows (2 n 2^-53), so that decisions outside the band are the FP64
+//   scan's.
+double bscan_bf16_rel(int64_t n_total, int pc) {
+    const double u = std::ldexp(1.0, -24), u64 = std::ldexp(1.0, -53), e = std::ldexp(1.0, -8), er = e + 2.0 * u;
+    auto gam = [&](double k) { return k * u / (1.0 - k * u); };
+    double dropped = 0.0, kept_small = 0.0;
+    int nprod = 0;
+    for (int a = 1; a <= pc; ++a)
+        for (int b = 1; b <= pc; ++b) {
+            const double mag = std::pow(e, a - 1) * (1.0 + e) * std::pow(er, b - 1) * (1.0 + er);
+            if (a + b > pc + 1) {
+                dropped += mag;
+            } else {
+                ++nprod;
+                if (a + b > 2) kept_small += mag;
+            }
+        }
+    const double rem = std::pow(e, pc) * (1.0 + std::pow(er, pc)) + std::pow(er, pc) * (1.0 + std::pow(e, pc));
+    const double first = gam(64.0) * (1.0 + e) * (1.0 + er);
+    const double rest = gam(64.0 * BF_PROMO * (nprod - 1)) * kept_small;
+    const double g64 = (2.0 * (double)(n_total / BF_K) + 8.0) * u64 * (1.0 + first + kept_small) + 2.0 * (double)n_total * u64;
+    return (dropped + rem + first + rest) * (1.0 + 1e-6) + g64;
 }
 
-int64_t bscan_bf16_pieces_bytes(int64_t n_total) { return (int64_t)3 * BNP * batch_pad(n_total) * 2; }
+int64_t bscan_bf16_pieces_bytes(int64_t n_total, int pc) { return (int64_t)pc * BNP * batch_pad(n_total) * 2; }
 
-hipError_t launch_b_r_pieces(const double* R, int64_t n_total, int nprob, __bf16* Rp, hipStream_t st) {
+hipError_t launch_b_r_pieces(const double* R, int64_t n_total, int nprob, int pc, __bf16* Rp, hipStream_t st) {
     const int64_t n_pad = batch_pad(n_total);
-    k_b_r_pieces<<<grid_for(n_pad * BNP, 256, 4096), 256, 0, st>>>(R, n_total, n_pad, nprob, Rp);
+    k_b_r_pieces<<<grid_for(n_pad * BNP, 256, 4096), 256, 0, st>>>(R, n_total, n_pad, nprob, pc, Rp);
     return hipGetLastError();
 }
 
-hipError_t launch_bscan_bf16(const Mat& mt, const int32_t* cols, const int64_t* len_dev, int64_t len_host,
+hipError_t launch_bscan_bf16(const Mat& mt, const int32_t* cols, const int64_t* len_dev, int64_t len_host, int pc,
                              const __bf16* Rp, int nprob, const BatchScalars* bs, const double* c, const double* s,
                              const uint8_t* keep, double* out, hipStream_t st) {
-    constexpr int W = 8;
+    constexpr int W = 8;   // 128 columns per workgroup share each staged chunk of residual pieces
     const int64_t work = len_dev ? mt.p : len_host;
     const int g = grid_for(work, 16 * W, 1 << 20);
-    k_bscan_bf16<W><<<g, 64 * W, 0, st>>>((const float*)mt.X, mt.ldx, mt.n_total, batch_pad(mt.n_total), Rp, cols,
-                                          len_dev, len_host, nprob, mt.p, bs, c, s, keep, out);
+    const float* X = (const float*)mt.X;
+    const int64_t n_pad = batch_pad(mt.n_total);
+    if (pc == 2)
+        k_bscan_bf16<W, 2><<<g, 64 * W, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, Rp, cols, len_dev, len_host, nprob, mt.p,
+                                                bs, c, s, keep, out);
+    else
+        k_bscan_bf16<W, 3><<<g, 64 * W, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, Rp, cols, len_dev, len_host, nprob, mt.p,
+                                                bs, c, s, keep, out);
     return hipGetLastError();
 }
 

@@ -252,11 +252,12 @@ size_t bscan_split_part_bytes(int64_t n_total, int64_t len);
 hipError_t launch_bscan_split(const Mat& mt, const int32_t* cols, int64_t len, const double* B, int nprob,
                               const BatchScalars* bs, const double* c, const double* s, const uint8_t* keep,
                               double* part, double* out, hipStream_t st);
-// BF16 form of the batched check scan (f32 X): residual pieces, the scan, its bound and the band flags
-double bscan_bf16_rel(int64_t n_total);
-int64_t bscan_bf16_pieces_bytes(int64_t n_total);
-hipError_t launch_b_r_pieces(const double* R, int64_t n_total, int nprob, __bf16* Rp, hipStream_t st);
-hipError_t launch_bscan_bf16(const Mat& mt, const int32_t* cols, const int64_t* len_dev, int64_t len_host,
+// BF16 form of the batched check scan (f32 X, pc = 2 or 3 pieces of x and r): residual pieces, the scan, its
+// bound and the band flags
+double bscan_bf16_rel(int64_t n_total, int pc);
+int64_t bscan_bf16_pieces_bytes(int64_t n_total, int pc);
+hipError_t launch_b_r_pieces(const double* R, int64_t n_total, int nprob, int pc, __bf16* Rp, hipStream_t st);
+hipError_t launch_bscan_bf16(const Mat& mt, const int32_t* cols, const int64_t* len_dev, int64_t len_host, int pc,
                              const __bf16* Rp, int nprob, const BatchScalars* bs, const double* c, const double* s,
                              const uint8_t* keep, double* out, hipStream_t st);
 hipError_t launch_b_band(const int32_t* cols, const int64_t* len_dev, int64_t p, int nprob, const double* z,

@@ -127,21 +127,23 @@ def test_batch_rejects_invalid_inputs(gpu_ctx):
     assert e.value.status == bl.BL_ERR_INVALID
 
 
+@pytest.mark.parametrize("prec", [bl.PREC_BF16X3, bl.PREC_BF16X2])
 @pytest.mark.parametrize("n,p,nresp,nsub,K", [(1500, 4000, 8, 2, 20), (1037, 2222, 32, 2, 15)])
-def test_batch_bf16_scans_equal_fp64_scans(gpu_ctx, n, p, nresp, nsub, K):
-    """The BF16 matrix-core check scans (f32 X) re-take every decision within their error bound on the FP64
-    scan and start each solve from FP64 gradients: the same coefficients as the FP64 scans, bit for bit."""
+def test_batch_bf16_scans_equal_fp64_scans(gpu_ctx, n, p, nresp, nsub, K, prec):
+    """The BF16 matrix-core check scans (f32 X, three or two pieces of x and r) re-take every decision within
+    their error bound on the FP64 scan and start each solve from FP64 gradients: the same coefficients as the
+    FP64 scans, bit for bit."""
     rec, X32, Y, masks = cv_problem(n, p, nresp, nsub, seed_shift=7)
     ratio = rec.lambda_min_ratio
     Xd, Yd, Md = to_dev(X32), to_dev(Y), to_dev(masks)
     kw = dict(nlambda=K, lambda_min_ratio=ratio, tol=1e-10)
     r64 = bl.fit_path_batch(gpu_ctx, Xd, Yd, Md, **kw)
-    rbf = bl.fit_path_batch(gpu_ctx, Xd, Yd, Md, precision=bl.PREC_BF16X3, **kw)
+    rbf = bl.fit_path_batch(gpu_ctx, Xd, Yd, Md, precision=prec, **kw)
     assert rbf.k_done == K
     assert torch.equal(rbf.beta, r64.beta)
     np.testing.assert_array_equal(rbf.obj, r64.obj)
     np.testing.assert_array_equal(rbf.n_strong, r64.n_strong)
     check_against_oracle(rbf, X32.astype(np.float64), Y, masks, K, ratio, [0, Y.shape[0] - 1])
     with pytest.raises(bl.BLError) as e:
-        bl.fit_path_batch(gpu_ctx, to_dev(X32.astype(np.float64)), Yd, Md, precision=bl.PREC_BF16X3, **kw)
+        bl.fit_path_batch(gpu_ctx, to_dev(X32.astype(np.float64)), Yd, Md, precision=prec, **kw)
     assert e.value.status == bl.BL_ERR_UNSUPPORTED
