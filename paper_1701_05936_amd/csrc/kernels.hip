@@ -240,29 +240,111 @@ __global__ __launch_bounds__(256) void k_colstats(const XT* __restrict__ X, int6
             // (n s2 - s1^2) / n^2, numerator exact in 64-bit integers
             var = (double)(n_rows * s2 - s1 * s1) * inv_n * inv_n;
         } else {
-            double a0 = 0.0, a1 = 0.0;
-            int64_t i = lane;
-            for (; i + WAVE < n_total; i += 2 * WAVE) {
-                double v0 = (!MASK || mask[i]) ? (double)x[i] : 0.0;
-                double v1 = (!MASK || mask[i + WAVE]) ? (double)x[i + WAVE] : 0.0;
-                a0 += v0;
-                a1 += v1;
+            // E consecutive rows per lane and wave-wide word of E * 64 rows: lane l takes rows E l .. E l + E - 1
+            // of every word, one accumulator per position in the word.  With 16-byte aligned columns (vec) the
+            // whole words are read as 16-byte loads, four words in flight; otherwise element by element in the
+            // same order, so both give the same sums.  Rows of the last, partial word are read one by one.
+            constexpr int E = 16 / (int)sizeof(XT);
+            constexpr int64_t WR = (int64_t)E * WAVE;
+            const int64_t nw = n_total / WR;   // whole words
+            const int64_t l0 = (int64_t)E * lane;
+            auto word = [&](int64_t k, double (&v)[E], bool (&ok)[E]) {
+                const int64_t r = k * WR + l0;
+                if (vec) {
+                    if constexpr (E == 2) {
+                        const double2 w = *reinterpret_cast<const double2*>(x + r);
+                        v[0] = (double)w.x;
+                        v[1] = (double)w.y;
+                    } else {
+                        const float4 w = *reinterpret_cast<const float4*>(x + r);
+                        v[0] = (double)w.x;
+                        v[1] = (double)w.y;
+                        v[2] = (double)w.z;
+                        v[3] = (double)w.w;
+                    }
+                    uint32_t mb = 0xFFFFFFFFu;
+                    if constexpr (MASK) {
+                        if constexpr (E == 2) mb = *reinterpret_cast<const uint16_t*>(mask + r);
+                        else mb = *reinterpret_cast<const uint32_t*>(mask + r);
+                    }
+#pragma unroll
+                    for (int e = 0; e < E; ++e) ok[e] = ((mb >> (8 * e)) & 0xFFu) != 0;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        ok[e] = !MASK || mask[r + e];
+                        v[e] = ok[e] ? (double)x[r + e] : 0.0;
+                    }
+                }
+            };
+            auto tail = [&](double (&v)[E], bool (&ok)[E]) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int64_t r = nw * WR + l0 + e;
+                    ok[e] = r < n_total && (!MASK || mask[r]);
+                    v[e] = ok[e] ? (double)x[r] : 0.0;
+                }
+            };
+            // pass 1: sums; pass 2: squared deviations from the mean (rows outside the fit add nothing)
+            double acc[E], q[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[e] = q[e] = 0.0;
+            {
+                int64_t k = 0;
+                for (; k + 4 <= nw; k += 4) {
+                    double v[4][E];
+                    bool ok[4][E];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) word(k + u, v[u], ok[u]);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int e = 0; e < E; ++e) acc[e] += ok[u][e] ? v[u][e] : 0.0;
+                }
+                for (; k <= nw; ++k) {
+                    double v[E];
+                    bool ok[E];
+                    if (k < nw) word(k, v, ok);
+                    else tail(v, ok);
+#pragma unroll
+                    for (int e = 0; e < E; ++e) acc[e] += ok[e] ? v[e] : 0.0;
+                }
             }
-            if (i < n_total && (!MASK || mask[i])) a0 += (double)x[i];
-            mean = wave_sum(a0 + a1) * inv_n;
-            double q0 = 0.0, q1 = 0.0;
-            i = lane;
-            for (; i + WAVE < n_total; i += 2 * WAVE) {
-                double d0 = (!MASK || mask[i]) ? (double)x[i] - mean : 0.0;
-                double d1 = (!MASK || mask[i + WAVE]) ? (double)x[i + WAVE] - mean : 0.0;
-                q0 = fma(d0, d0, q0);
-                q1 = fma(d1, d1, q1);
+            double tot = acc[0];
+#pragma unroll
+            for (int e = 1; e < E; ++e) tot += acc[e];
+            mean = wave_sum(tot) * inv_n;
+            {
+                int64_t k = 0;
+                for (; k + 4 <= nw; k += 4) {
+                    double v[4][E];
+                    bool ok[4][E];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) word(k + u, v[u], ok[u]);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int e = 0; e < E; ++e) {
+                            const double d = ok[u][e] ? v[u][e] - mean : 0.0;
+                            q[e] = fma(d, d, q[e]);
+                        }
+                }
+                for (; k <= nw; ++k) {
+                    double v[E];
+                    bool ok[E];
+                    if (k < nw) word(k, v, ok);
+                    else tail(v, ok);
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        const double d = ok[e] ? v[e] - mean : 0.0;
+                        q[e] = fma(d, d, q[e]);
+                    }
+                }
             }
-            if (i < n_total && (!MASK || mask[i])) {
-                double d = (double)x[i] - mean;
-                q0 = fma(d, d, q0);
-            }
-            var = wave_sum(q0 + q1) * inv_n;
+            double qt = q[0];
+#pragma unroll
+            for (int e = 1; e < E; ++e) qt += q[e];
+            var = wave_sum(qt) * inv_n;
         }
         if (lane == 0) {
             double sd = sqrt(var > 0.0 ? var : 0.0);
@@ -818,8 +900,12 @@ hipError_t launch_colstats(const Mat& m, double* c, double* s, uint8_t* keep, in
     const bool mk = m.mask != nullptr;
     // int8 codes read as 16-byte words: columns (and the row mask) 16-byte aligned, and few enough rows that a
     // lane's int32 sum of squares cannot overflow
-    const bool vec = m.xtype == 2 && (uintptr_t)m.X % 16 == 0 && m.ldx % 16 == 0 && (uintptr_t)m.mask % 16 == 0 &&
-                     m.n_total <= (int64_t(1) << 22);
+    // FP64 / FP32 X: whole 16-byte words when every column starts 16-byte aligned (the sums are the same either way)
+    const int64_t esz = m.xtype == 0 ? 8 : (m.xtype == 1 ? 4 : 1);
+    const bool vec = m.xtype == 2 ? ((uintptr_t)m.X % 16 == 0 && m.ldx % 16 == 0 && (uintptr_t)m.mask % 16 == 0 &&
+                                     m.n_total <= (int64_t(1) << 22))
+                                  : ((uintptr_t)m.X % 16 == 0 && (m.ldx * esz) % 16 == 0 &&
+                                     (uintptr_t)m.mask % (16 / esz) == 0);
     switch (m.xtype) {
         case 0:
             if (mk) k_colstats<double, true><<<g, 256, 0, st>>>((const double*)m.X, m.ldx, m.n_total, m.p, m.mask, n_rows, c, s, keep, vec);

@@ -15,6 +15,7 @@ import torch
 import datagen
 import oracle
 import paper_1701_05936_amd as bl
+from conftest import progress
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -22,7 +23,7 @@ CHUNK = 25_000
 
 
 def log(msg):
-    print(msg, flush=True)
+    progress(f"[fullsize] {msg}")
 
 
 def chunked(Xt, fn):
@@ -31,6 +32,8 @@ def chunked(Xt, fn):
     out = []
     for j0 in range(0, p, CHUNK):
         out.append(fn(np.ascontiguousarray(Xt[j0:j0 + CHUNK], dtype=np.float64), j0))
+        if (j0 // CHUNK) % 10 == 9:
+            log(f"  columns {j0 + CHUNK} of {p}")
     return out
 
 
@@ -216,6 +219,7 @@ def c5_full(gpu_ctx):
                         rule=bl.SCREEN_SSR_BEDPP, tol=1e-8, rec_feat=feat[n_rec:], rec_label=lab[n_rec:],
                         want_beta=False)
         n_rec += r.n_recorded
+        log(f"c5 training path {t + 1} of {tr.nresp}: {r.n_recorded} records")
     P = torch.from_numpy(bl.mlp_init(1)).to(DEV)
     info = bl.mlp_train(gpu_ctx, feat[:n_rec].contiguous(), lab[:n_rec].contiguous(), P, epochs=10, batch=8192,
                         lr=2e-3, seed=5, target_recall=0.995)
