@@ -97,11 +97,20 @@ bl_status bl_device_info(bl_ctx ctx, int* n_cu, char* name, int name_len);
  *               single-workgroup solve (up to 7,168 features) or else the residual-form solve.
  *               A value above the resident count is rejected (BL_ERR_INVALID); -1 keeps the current.
  *   resident    out: workgroups of the multi-workgroup solve that fit on the device at once.
+ *   cycle_min   working sets of bl_fit_path (squared loss) with at least this many features are solved
+ *               by active-set cycling (Section 3.1.1: the descent iterates over the nonzero
+ *               coefficients): sweeps over A = {j in E : beta_j != 0} until none changes a coefficient
+ *               by tol, then one sweep over E, repeated until a sweep over E changes none by tol (the
+ *               plain solve's stopping rule; the reported sweeps count both kinds).  Smaller sets
+ *               sweep E throughout.  Default -1 (off): on the genotype designs measured, cycling took
+ *               more coordinate updates in all than sweeping E (13.2 against 9.1 million on a
+ *               5,000 x 500,000 path).  0 keeps the current value; -1 turns cycling off.
  */
 typedef struct {
     int64_t cov_max;
     int32_t cd_helpers;
     int32_t resident;
+    int64_t cycle_min;
 } bl_limits;
 
 bl_status bl_get_limits(bl_ctx ctx, bl_limits* out);

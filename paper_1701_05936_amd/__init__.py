@@ -90,7 +90,8 @@ class _HostStream(ctypes.Structure):
 
 
 class _Limits(ctypes.Structure):
-    _fields_ = [("cov_max", ctypes.c_int64), ("cd_helpers", ctypes.c_int32), ("resident", ctypes.c_int32)]
+    _fields_ = [("cov_max", ctypes.c_int64), ("cd_helpers", ctypes.c_int32), ("resident", ctypes.c_int32),
+                ("cycle_min", ctypes.c_int64)]
 
 
 class _PathResult(ctypes.Structure):
@@ -254,14 +255,16 @@ class Context:
                 "units": kp.units}
 
     def limits(self) -> dict:
-        """Coordinate-descent size limits: cov_max, cd_helpers and the resident workgroup count."""
+        """Coordinate-descent limits: cov_max, cd_helpers, the resident workgroup count and cycle_min."""
         lm = _Limits()
         self._check(load_library().bl_get_limits(self._h, ctypes.byref(lm)))
-        return {"cov_max": lm.cov_max, "cd_helpers": lm.cd_helpers, "resident": lm.resident}
+        return {"cov_max": lm.cov_max, "cd_helpers": lm.cd_helpers, "resident": lm.resident,
+                "cycle_min": lm.cycle_min}
 
-    def set_limits(self, cov_max: int = 0, cd_helpers: int = -1):
-        """Lower (or restore) the limits; 0 / -1 keep the current value."""
-        lm = _Limits(int(cov_max), int(cd_helpers), 0)
+    def set_limits(self, cov_max: int = 0, cd_helpers: int = -1, cycle_min: int = 0):
+        """Lower (or restore) the limits; 0 / -1 keep the current value (cycle_min: 0 keeps, -1 turns
+        active-set cycling off)."""
+        lm = _Limits(int(cov_max), int(cd_helpers), 0, int(cycle_min))
         self._check(load_library().bl_set_limits(self._h, ctypes.byref(lm)))
 
     def device_info(self):

@@ -559,6 +559,103 @@ bl_status solve_set(bl_ctx ctx, const XAccess& xa, const int32_t* set, const int
     return BL_OK;
 }
 
+// Active-set cycling (the descent iterates over the nonzero coefficients of the working set, Section 3.1.1):
+// solve on A = {j in E : beta_j != 0} (E's order) until a sweep over A changes no coefficient by tol or more,
+// then sweep E once from its gradient at the current residual; stop when that sweep changes no coefficient by
+// tol or more (the plain solve's stopping rule), else take the new A and repeat.  Working sets below
+// ctx->cycle_min are solved by one plain solve.  Each part is a solve_set; their sweeps add up (an A-sweep
+// counts as a sweep) and their totals go to sc->round.  *cycled tells the caller that the CD, Gram and
+// residual-update timings were recorded here, part by part.
+bl_status solve_ws(bl_ctx ctx, const XAccess& xa, const int32_t* set, const int64_t* len_dev, int64_t m,
+                   const double* z, double* beta, double* r, const double* c, const double* s, const uint8_t* keep,
+                   double n_rows, double lam, double tol, int max_sweeps, double alpha, const double* w, void* scr,
+                   bool* cycled) {
+    *cycled = false;
+    if (m < ctx->cycle_min || max_sweeps < 2)
+        return solve_set(ctx, xa, set, len_dev, m, z, beta, r, c, s, n_rows, lam, tol, max_sweeps, alpha, w);
+    *cycled = true;
+    const Mat& mt = xa.m;
+    const int64_t p = mt.p;
+    hipStream_t st = ctx->stream;
+    const double col_bytes = (double)mt.n_total * elem_bytes(mt.xtype);
+    uint8_t* fl;
+    int32_t* lA;
+    int64_t* lenA;
+    double* zc;
+    ENSURE(B_CYCF, (size_t)p, fl);
+    ENSURE(B_CYCL, (size_t)p * 4, lA);
+    ENSURE(B_CYCN, 8, lenA);
+    ENSURE(B_ZCYC, (size_t)p * 8, zc);
+    // the round's figures of one part, and its timings
+    auto part_done = [&](int64_t mp, RoundInfo* ri) -> bl_status {
+        HIPCHK(hipMemcpyAsync(&ctx->sc_host->round, &ctx->sc->round, sizeof(RoundInfo), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        *ri = ctx->sc_host->round;
+        if (ctx->last_residual) {
+            prof_add(ctx, 0, BL_PROF_CD, (double)ri->sweeps * mp * col_bytes, 0.0, (double)ri->sweeps * mp);
+        } else {
+            prof_add(ctx, 0, BL_PROF_CD, (double)ri->sweeps * (double)mp * (double)mp * 8.0, 0.0,
+                     (double)ri->sweeps * mp);
+            prof_add(ctx, 4, BL_PROF_GRAM, ctx->pend_gram_bytes);
+            prof_add(ctx, 6, BL_PROF_RUPDATE, ctx->pend_ru_bytes);
+        }
+        return BL_OK;
+    };
+    // gradient of the listed columns at the current residual into zc
+    auto grad = [&](const int32_t* cols, const int64_t* len) -> bl_status {
+        ScanArgs ga{};
+        ga.cols = cols;
+        ga.len_dev = len;
+        ga.r = r;
+        ga.sc = ctx->sc;
+        ga.c = c;
+        ga.s = s;
+        ga.keep = keep;
+        ga.z = zc;
+        return x_scan(ctx, xa, ga);
+    };
+    int sweeps = 0, status = 1;
+    bl_status st_;
+    RoundInfo ri{};
+    const double* zA = z;   // the caller's gradient holds at the current residual for the first part
+    for (int cyc = 0;; ++cyc) {
+        HIPCHK(launch_fill_u8(fl, 0, p, st));
+        HIPCHK(launch_mark_nonzero(set, len_dev, m, beta, fl, st));
+        HIPCHK(launch_compact(fl, p, lA, lenA, scr, st));
+        HIPCHK(hipMemcpyAsync(&ctx->sc_host->stage, lenA, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const int64_t mA = ctx->sc_host->stage;
+        const int budget = max_sweeps - sweeps - 1;   // one sweep is kept for E
+        if (mA > 0 && mA < m && budget >= 1) {
+            if (cyc > 0) {
+                if ((st_ = grad(lA, lenA))) return st_;
+                zA = zc;
+            }
+            if ((st_ = solve_set(ctx, xa, lA, lenA, mA, zA, beta, r, c, s, n_rows, lam, tol, budget, alpha, w)))
+                return st_;
+            if ((st_ = part_done(mA, &ri))) return st_;
+            sweeps += ri.sweeps;
+            if (ri.status == 2) {
+                status = 2;
+                break;
+            }
+        }
+        // one sweep over E
+        if ((st_ = grad(set, len_dev))) return st_;
+        if ((st_ = solve_set(ctx, xa, set, len_dev, m, zc, beta, r, c, s, n_rows, lam, tol, 1, alpha, w))) return st_;
+        if ((st_ = part_done(m, &ri))) return st_;
+        sweeps += ri.sweeps;
+        if (ri.status != 1) {
+            status = ri.status;   // 0: the sweep over E changed nothing by tol; 2: device error
+            break;
+        }
+        if (sweeps >= max_sweeps) break;
+        zA = nullptr;
+    }
+    HIPCHK(launch_set_round(ctx->sc, sweeps, status, (int32_t)m, st));
+    return BL_OK;
+}
+
 double bedpp_rhs(double lmax, double lam, double v) {
     double slack = v - lmax * lmax;
     if (slack < 0.0) slack = 0.0;
@@ -603,6 +700,7 @@ bl_status bl_get_limits(bl_ctx ctx, bl_limits* out) {
     out->cov_max = ctx->cov_max;
     out->cd_helpers = ctx->cd_helpers;
     out->resident = ctx->cd_resident;
+    out->cycle_min = ctx->cycle_min == INT64_MAX ? -1 : ctx->cycle_min;
     return BL_OK;
 }
 
@@ -613,8 +711,11 @@ bl_status bl_set_limits(bl_ctx ctx, const bl_limits* in) {
     if (in->cd_helpers < -1 || in->cd_helpers > 255 || in->cd_helpers > ctx->cd_resident - 1)
         return fail(ctx, BL_ERR_INVALID, "cd_helpers must be -1 or in 0..%d (resident workgroups - 1, at most 255)",
                     std::min(255, std::max(0, ctx->cd_resident - 1)));
+    if (in->cycle_min < -1) return fail(ctx, BL_ERR_INVALID, "cycle_min must be -1, 0 or positive");
     if (in->cov_max > 0) ctx->cov_max = in->cov_max;
     if (in->cd_helpers >= 0) ctx->cd_helpers = in->cd_helpers;
+    if (in->cycle_min > 0) ctx->cycle_min = in->cycle_min;
+    if (in->cycle_min == -1) ctx->cycle_min = INT64_MAX;
     return BL_OK;
 }
 
@@ -1562,8 +1663,9 @@ bl_status fit_path_impl(bl_ctx ctx, const XAccess& xa, const double* y, const bl
                 HIPCHK(launch_scan(m, ea, st));
                 recheck_total += m_len;
             }
-            if ((s = solve_set(ctx, xa, lE, lens + 0, m_len, zsrc, beta, r, c, sc_, (double)n, lk, opts->tol,
-                               opts->max_sweeps, alpha, pf)))
+            bool cycled = false;
+            if ((s = solve_ws(ctx, xa, lE, lens + 0, m_len, zsrc, beta, r, c, sc_, keep, (double)n, lk, opts->tol,
+                              opts->max_sweeps, alpha, pf, scr, &cycled)))
                 return s;
             HIPCHK(hipMemsetAsync(&ctx->sc->round.n_viol, 0, sizeof(uint32_t), st));
             if (!lowp) {
@@ -1625,7 +1727,9 @@ bl_status fit_path_impl(bl_ctx ctx, const XAccess& xa, const double* y, const bl
             HIPCHK(hipMemcpyAsync(&ctx->sc_host->round, &ctx->sc->round, sizeof(RoundInfo), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             const RoundInfo ri = ctx->sc_host->round;
-            if (ctx->last_residual) {
+            if (cycled) {
+                // recorded part by part in solve_ws
+            } else if (ctx->last_residual) {
                 prof_add(ctx, 0, BL_PROF_CD, (double)ri.sweeps * ri.cd_len * col_bytes, 0.0,
                          (double)ri.sweeps * ri.cd_len);
             } else {

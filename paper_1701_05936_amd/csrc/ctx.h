@@ -39,6 +39,7 @@ struct bl_ctx_s {
     int64_t cov_max = 0;                // largest working set of the covariance solve
     int cd_helpers = 0;                 // most helper workgroups of the multi-workgroup solve
     int cd_resident = 0;                // workgroups of that solve resident on the device at once
+    int64_t cycle_min = INT64_MAX;      // working sets from this size on are solved by active-set cycling (off)
     bool last_residual = false;         // the last solve_set ran the residual-form solve
     // X in host memory: two device panel buffers streamed on `aux`, and the device cache of the columns
     // of the Gram pool's features
@@ -82,6 +83,8 @@ enum BufId {
     L_ETA, L_G, L_R0C,
     // batched BF16 scans
     BB_RP, BB_FLAG, BB_LF, BB_LU, BB_PART,
+    // active-set cycling
+    B_CYCF, B_CYCL, B_CYCN, B_ZCYC,
     B_COUNT
 };
 

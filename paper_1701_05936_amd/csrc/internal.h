@@ -110,6 +110,11 @@ hipError_t launch_enet_lmax_terms(const double* a, const double* w, double alpha
 
 // ordered compaction of a uint8 mask: out[0..len) = ascending j with mask[j] != 0; *len_dev = len
 size_t compact_scratch_bytes(int64_t p);
+// flag[set[e]] = 1 where beta[set[e]] != 0, e < *len_dev <= m_max (flag cleared by the caller)
+hipError_t launch_mark_nonzero(const int32_t* set, const int64_t* len_dev, int64_t m_max, const double* beta,
+                               uint8_t* flag, hipStream_t st);
+// sc->round.{sweeps, status, cd_len} = the given totals
+hipError_t launch_set_round(DevScalars* sc, int32_t sweeps, int32_t status, int32_t cd_len, hipStream_t st);
 hipError_t launch_compact(const uint8_t* mask, int64_t p, int32_t* out, int64_t* len_dev, void* scratch,
                           hipStream_t st);
 

@@ -845,6 +845,23 @@ __global__ __launch_bounds__(1024) void k_record(const int32_t* __restrict__ set
     }
 }
 
+// flag[set[e]] = 1 where beta[set[e]] != 0 (e < *len_dev); flag is cleared beforehand
+__global__ void k_mark_nonzero(const int32_t* __restrict__ set, const int64_t* __restrict__ len_dev,
+                               const double* __restrict__ beta, uint8_t* __restrict__ flag) {
+    const int64_t m = *len_dev;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t j = set[e];
+        if (beta[j] != 0.0) flag[j] = 1;
+    }
+}
+
+// the totals of a solve made of several: sweeps, status and the set size, where the check round reads them
+__global__ void k_set_round(DevScalars* __restrict__ sc, int32_t sweeps, int32_t status, int32_t cd_len) {
+    sc->round.sweeps = sweeps;
+    sc->round.status = status;
+    sc->round.cd_len = cd_len;
+}
+
 __global__ void k_fill_u8(uint8_t* p, uint8_t v, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -1051,6 +1068,17 @@ hipError_t launch_record(const int32_t* set, const int64_t* len_dev, const int64
                          const double* beta, const double* c, const double* s, const DevScalars* sc, double lam,
                          LamStats* out, hipStream_t st, double alpha, const double* w) {
     k_record<<<1, 1024, 0, st>>>(set, len_dev, len_safe, len_scan, beta, c, s, sc, lam, out, alpha, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_nonzero(const int32_t* set, const int64_t* len_dev, int64_t m_max, const double* beta,
+                               uint8_t* flag, hipStream_t st) {
+    k_mark_nonzero<<<grid_for(m_max > 0 ? m_max : 1, 256, 1024), 256, 0, st>>>(set, len_dev, beta, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_round(DevScalars* sc, int32_t sweeps, int32_t status, int32_t cd_len, hipStream_t st) {
+    k_set_round<<<1, 1, 0, st>>>(sc, sweeps, status, cd_len);
     return hipGetLastError();
 }
 
