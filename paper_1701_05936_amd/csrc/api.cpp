@@ -407,7 +407,7 @@ bl_status solve_set(bl_ctx ctx, const XAccess& xa, const int32_t* set, const int
     // covariance form up to cov_max features; the multi-workgroup solve only with every workgroup resident
     // and one threshold for every coordinate, else the single-workgroup solve (its gradient lives in LDS:
     // GCD_MAX features) or the residual form
-    int H = gcd_multi_helpers(m);
+    int H = gcd_multi_helpers(m, ctx->cd_helpers);
     const bool multi_ok = H <= ctx->cd_helpers && w == nullptr;
     const bool cov = m <= ctx->cov_max && (multi_ok || m <= GCD_MAX);
     if (!multi_ok) H = 0;

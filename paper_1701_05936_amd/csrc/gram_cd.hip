@@ -20,6 +20,8 @@
 // into the gradient of every other coordinate.  After the solve the residual
 // is brought up to date in one pass, r -= X~_E (beta_E - beta_E(start)).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include "chain.h"
@@ -655,6 +657,8 @@ __device__ __forceinline__ bool lead_gram_store(int* ctr, const double2 (&v)[GSE
     return true;
 }
 
+// OWN: blocks each helper owns at most (1 when there are helpers for every block, else 2)
+template <int OWN>
 __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
     // the wave index is uniform across the wave: taken through a scalar register, the per-wave branches
     // below compile to scalar jumps instead of execution-masked code that every wave walks through
@@ -787,6 +791,8 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
             // ---- preparing the block of sequence q ----
             const int l32 = lane & (MB - 1), half = lane >> 5;
             int bq = 0;
+            // the applied count of the next block's owner is read one block ahead (a lower bound: the counts
+            // only grow); the blocking read below runs only when that value is not yet enough
             for (int64_t q = 0;; ++q) {
                 if (lc_get(ctr, LC_STOP) != INT_MAX) break;
                 const int nl = blk_len(m, bq);
@@ -863,16 +869,16 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
     }
 
     // ---------------- helper ----------------
-    auto Gh = reinterpret_cast<double(*)[HOWN][MB * MB]>(arena);                         // [HBATCH][HOWN][MB*MB]
-    auto dlt = reinterpret_cast<double(*)[MB]>(arena + HBATCH * HOWN * MB * MB);           // [HBATCH][MB]
-    auto gh = reinterpret_cast<double(*)[MB]>(arena + HBATCH * HOWN * MB * MB + HBATCH * MB);  // [HOWN][MB]
-    auto hp = reinterpret_cast<double(*)[HOWN][MB]>(arena + HBATCH * HOWN * MB * MB + HBATCH * MB + HOWN * MB);
+    auto Gh = reinterpret_cast<double(*)[OWN][MB * MB]>(arena);                         // [HBATCH][OWN][MB*MB]
+    auto dlt = reinterpret_cast<double(*)[MB]>(arena + HBATCH * OWN * MB * MB);           // [HBATCH][MB]
+    auto gh = reinterpret_cast<double(*)[MB]>(arena + HBATCH * OWN * MB * MB + HBATCH * MB);  // [OWN][MB]
+    auto hp = reinterpret_cast<double(*)[OWN][MB]>(arena + HBATCH * OWN * MB * MB + HBATCH * MB + OWN * MB);
     int64_t& pub_sh = *reinterpret_cast<int64_t*>(arena + HELP_LDS - 8);
     int& quit_sh = *reinterpret_cast<int*>(arena + HELP_LDS - 7);
     const int h = blockIdx.x - 1;
-    int own[HOWN];
+    int own[OWN];
     int nown = 0;
-    for (int c = h; c < nb && nown < HOWN; c += H) own[nown++] = c;
+    for (int c = h; c < nb && nown < OWN; c += H) own[nown++] = c;
     const __amdgpu_buffer_rsrc_t grs = gram_rsrc(a.G, m);
     int64_t s0 = 0;  // next sequence to apply
     int hb = 0;      // s0 mod nb
@@ -906,9 +912,9 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
         // issued before the first one is waited for
         {
             constexpr int PER = MB * MB / MT;
-            double gv[HBATCH][HOWN][PER];
+            double gv[HBATCH][OWN][PER];
             double dv[HBATCH];
-            double hv[HOWN];
+            double hv[OWN];
 #pragma unroll
             for (int k = 0; k < HBATCH; ++k) {
                 int bq = hb + k;
@@ -918,7 +924,7 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
                 const bool kin = k < nbat;
                 dv[k] = (kin && tid < blk_len(m, bq)) ? ld_coh(a.delta + (int64_t)sl * MB + tid) : 0.0;
 #pragma unroll
-                for (int o = 0; o < HOWN; ++o) {
+                for (int o = 0; o < OWN; ++o) {
                     int dist = own[o] - bq;
                     if (dist < 0) dist += nb;
                     const bool use = kin && o < nown && dist > SLACK;
@@ -932,22 +938,22 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
                 }
             }
 #pragma unroll
-            for (int o = 0; o < HOWN; ++o)
+            for (int o = 0; o < OWN; ++o)
                 hv[o] = (o < nown && tid < blk_len(m, own[o])) ? ld_coh(a.g + (int64_t)own[o] * MB + tid) : 0.0;
 #pragma unroll
             for (int k = 0; k < HBATCH; ++k) {
                 if (tid < MB) dlt[k][tid] = dv[k];
 #pragma unroll
-                for (int o = 0; o < HOWN; ++o)
+                for (int o = 0; o < OWN; ++o)
 #pragma unroll
                     for (int q2 = 0; q2 < PER; ++q2) Gh[k][o][tid + q2 * MT] = gv[k][o][q2];
             }
 #pragma unroll
-            for (int o = 0; o < HOWN; ++o)
+            for (int o = 0; o < OWN; ++o)
                 if (tid < MB) gh[o][tid] = hv[o];
         }
         __syncthreads();
-        bool touched[HOWN] = {};
+        bool touched[OWN] = {};
         for (int k = 0; k < nbat; ++k) {
             int bq = hb + k;
             if (bq >= nb) bq -= nb;
@@ -1102,9 +1108,10 @@ hipError_t launch_gcd(const GcdArgs& a, hipStream_t st) {
 
 int64_t gram_cd_max() { return (int64_t)255 * HOWN * MB; }  // one workgroup per compute unit at most
 
-int gcd_multi_helpers(int64_t m) {
+int gcd_multi_helpers(int64_t m, int cap) {
     const int nb = (int)((m + MB - 1) / MB);
     if (nb < 2 * (SLACK + 2)) return 0;  // small sets: the single-workgroup solve
+    if (nb <= cap) return nb;            // a helper per block: each change reaches every block sooner
     return (nb + HOWN - 1) / HOWN;
 }
 
@@ -1180,18 +1187,21 @@ hipError_t launch_enet_unscale(const int32_t* set, int64_t m, const double* w, d
 }
 
 int gcd_multi_resident() {
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gcd_multi, MT, 0) != hipSuccess) {
+    int per_cu1 = 0, per_cu2 = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu1, k_gcd_multi<1>, MT, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, k_gcd_multi<HOWN>, MT, 0) != hipSuccess) {
         (void)hipGetLastError();
         return 0;
     }
-    return per_cu * device_cu_count();
+    return std::min(per_cu1, per_cu2) * device_cu_count();
 }
 
 size_t gcd_multi_sync_words(int H) { return (size_t)(SYNC_APPLIED + 16 * (H + 1)); }
 
 hipError_t launch_gcd_multi(const GcdMultiArgs& a, hipStream_t st) {
-    k_gcd_multi<<<1 + a.H, MT, 0, st>>>(a);
+    const int nb = (int)((a.m + MB - 1) / MB);
+    if (a.H >= nb) k_gcd_multi<1><<<1 + a.H, MT, 0, st>>>(a);
+    else k_gcd_multi<HOWN><<<1 + a.H, MT, 0, st>>>(a);
     return hipGetLastError();
 }
 

@@ -186,7 +186,9 @@ struct GcdMultiArgs {
     int max_sweeps;
     DevScalars* sc;
 };
-int gcd_multi_helpers(int64_t m);  // 0: use the single-workgroup solve
+// helper workgroups of the multi-workgroup solve of m features: one per block of 32 when at most cap, else one
+// per two blocks; 0: use the single-workgroup solve
+int gcd_multi_helpers(int64_t m, int cap);
 int gcd_multi_resident();          // workgroups of the multi-workgroup solve resident on the device at once
 // Elastic net in the covariance solve: with q_e = sqrt(1 + lam (1 - alpha) w_e) the working set's problem in
 // gamma_e = q_e beta_e is a lasso with unit-diagonal Gram G~ = Q^-1 (G + lam (1 - alpha) W) Q^-1, gradient
