@@ -791,8 +791,6 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
             // ---- preparing the block of sequence q ----
             const int l32 = lane & (MB - 1), half = lane >> 5;
             int bq = 0;
-            // the applied count of the next block's owner is read one block ahead (a lower bound: the counts
-            // only grow); the blocking read below runs only when that value is not yet enough
             for (int64_t q = 0;; ++q) {
                 if (lc_get(ctr, LC_STOP) != INT_MAX) break;
                 const int nl = blk_len(m, bq);
