@@ -237,8 +237,9 @@ __global__ __launch_bounds__(64 * GM_W) void k_gram_update(const XT* __restrict_
 // exact, as are the FP64 kernel's sums (every partial sum is an integer below 2^53), so both kernels produce
 // the same Gram entries bit for bit.  Lane (m, kq) loads 16 consecutive codes of its column (rows 16 kq .. of a
 // 64-row step) and hands the word to the matrix cores as it is.  Columns, ldx and the row mask are 16-byte
-// aligned; the word holding the last row is read whole (it lies within the column's padded length), and its
-// rows past n_total, like the rows outside the fit, are cleared in the B operand.  The output layout of this
+// aligned; the word holding the last row is read whole (it lies within the column's padded length; a row mask
+// is taken here only when n_total is a multiple of 16, so its words end at row n_total), and its rows past
+// n_total, like the rows outside the fit, are cleared in the B operand.  The output layout of this
 // instruction is row 4 kq + q (the FP64 one above is kq + 4 q).
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 constexpr int GI_R = 64;   // rows per int8 step
@@ -1046,8 +1047,11 @@ static hipError_t gram_typed(const Mat& m, const int32_t* pool_list, int64_t P, 
                              hipStream_t st) {
     dim3 grid((unsigned)((P + GM_K - 1) / GM_K), (unsigned)((N + GM_N - 1) / GM_N));
     if constexpr (sizeof(XT) == 1) {
-        // int8 matrix cores when every column (and the row mask) is 16-byte aligned
-        const bool al = (uintptr_t)m.X % 16 == 0 && m.ldx % 16 == 0 && (uintptr_t)m.mask % 16 == 0;
+        // int8 matrix cores when every column (and the row mask) is 16-byte aligned; with a row mask also only
+        // when n_total is a multiple of 16, so that the mask's last 16-byte word lies within its n_total bytes
+        // (otherwise the FP64 kernel below, whose integer sums are the same bits)
+        const bool al = (uintptr_t)m.X % 16 == 0 && m.ldx % 16 == 0 && (uintptr_t)m.mask % 16 == 0 &&
+                        (m.mask == nullptr || m.n_total % 16 == 0);
         if (al && m.n_total > 0) {
             if (m.mask)
                 k_gram_update_i8<true><<<grid, 64 * GM_W, 0, st>>>((const int8_t*)m.X, m.ldx, m.n_total, m.mask,
