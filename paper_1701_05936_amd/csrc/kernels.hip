@@ -285,66 +285,69 @@ __global__ __launch_bounds__(256) void k_colstats(const XT* __restrict__ X, int6
                     v[e] = ok[e] ? (double)x[r] : 0.0;
                 }
             };
-            // pass 1: sums; pass 2: squared deviations from the mean (rows outside the fit add nothing)
-            double acc[E], q[E];
-#pragma unroll
-            for (int e = 0; e < E; ++e) acc[e] = q[e] = 0.0;
+            // One pass: each lane keeps the count, mean and sum of squared deviations of its rows, taking four
+            // words at a time (their own mean and squared deviations, then the pairwise update of Chan, Golub
+            // and LeVeque: M2 = M2a + M2b + d^2 na nb / (na + nb)); the lanes are then combined the same way.
+            // X is read once; rows outside the fit add nothing.
+            double ln = 0.0, lm = 0.0, lq = 0.0;
+            auto merge = [](double& na, double& ma, double& qa, double nb, double mb, double qb) {
+                const double nn = na + nb;
+                if (nb > 0.0) {
+                    const double d = mb - ma, f = nb / nn;
+                    ma = fma(d, f, ma);
+                    qa = qa + qb + d * d * na * f;
+                    na = nn;
+                }
+            };
+            auto chunk = [&](const double* v, const bool* ok, int cnt_max) {
+                double cnt = 0.0, sm = 0.0;
+                for (int i = 0; i < cnt_max; ++i) {
+                    cnt += ok[i] ? 1.0 : 0.0;
+                    sm += ok[i] ? v[i] : 0.0;
+                }
+                const double cm = cnt > 0.0 ? sm / cnt : 0.0;
+                double cq = 0.0;
+                for (int i = 0; i < cnt_max; ++i) {
+                    const double d = ok[i] ? v[i] - cm : 0.0;
+                    cq = fma(d, d, cq);
+                }
+                merge(ln, lm, lq, cnt, cm, cq);
+            };
             {
                 int64_t k = 0;
                 for (; k + 4 <= nw; k += 4) {
-                    double v[4][E];
-                    bool ok[4][E];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) word(k + u, v[u], ok[u]);
+                    double v[4 * E];
+                    bool ok[4 * E];
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int e = 0; e < E; ++e) acc[e] += ok[u][e] ? v[u][e] : 0.0;
+                        word(k + u, *reinterpret_cast<double(*)[E]>(v + u * E), *reinterpret_cast<bool(*)[E]>(ok + u * E));
+                    chunk(v, ok, 4 * E);
                 }
                 for (; k <= nw; ++k) {
                     double v[E];
                     bool ok[E];
                     if (k < nw) word(k, v, ok);
                     else tail(v, ok);
-#pragma unroll
-                    for (int e = 0; e < E; ++e) acc[e] += ok[e] ? v[e] : 0.0;
+                    chunk(v, ok, E);
                 }
             }
-            double tot = acc[0];
+            // lanes combined pairwise, lane l with lane l ^ 2^i (every lane ends with the same figures)
 #pragma unroll
-            for (int e = 1; e < E; ++e) tot += acc[e];
-            mean = wave_sum(tot) * inv_n;
-            {
-                int64_t k = 0;
-                for (; k + 4 <= nw; k += 4) {
-                    double v[4][E];
-                    bool ok[4][E];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) word(k + u, v[u], ok[u]);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int e = 0; e < E; ++e) {
-                            const double d = ok[u][e] ? v[u][e] - mean : 0.0;
-                            q[e] = fma(d, d, q[e]);
-                        }
-                }
-                for (; k <= nw; ++k) {
-                    double v[E];
-                    bool ok[E];
-                    if (k < nw) word(k, v, ok);
-                    else tail(v, ok);
-#pragma unroll
-                    for (int e = 0; e < E; ++e) {
-                        const double d = ok[e] ? v[e] - mean : 0.0;
-                        q[e] = fma(d, d, q[e]);
-                    }
+            for (int sh = 1; sh < WAVE; sh <<= 1) {
+                const double on = __shfl_xor(ln, sh), om = __shfl_xor(lm, sh), oq = __shfl_xor(lq, sh);
+                // the lower lane of each pair is taken as "a", so both lanes form the same sums
+                if (lane & sh) {
+                    double n2 = on, m2 = om, q2 = oq;
+                    merge(n2, m2, q2, ln, lm, lq);
+                    ln = n2;
+                    lm = m2;
+                    lq = q2;
+                } else {
+                    merge(ln, lm, lq, on, om, oq);
                 }
             }
-            double qt = q[0];
-#pragma unroll
-            for (int e = 1; e < E; ++e) qt += q[e];
-            var = wave_sum(qt) * inv_n;
+            mean = lm;
+            var = lq * inv_n;
         }
         if (lane == 0) {
             double sd = sqrt(var > 0.0 ? var : 0.0);
