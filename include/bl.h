@@ -423,7 +423,10 @@ typedef struct {
     double time_ms;            /* out                                                                  */
     int32_t scan_cols;         /* out: columns per workgroup of the shared scan, picked by timing the
                                   candidates (64, 128, 256, with or without register prefetch) on this
-                                  shape once per context                                               */
+                                  shape once per context; with the environment variable
+                                  BL_AUTOTUNE_CACHE naming a file, the pick is read from it (one line
+                                  "bscan <arch> <xtype> <n_total> <p> <variant>" per shape) and a new
+                                  shape's pick appended, so later processes skip the timing            */
 } bl_batch_result;
 
 bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_batch* batch, const bl_path_opts* opts,

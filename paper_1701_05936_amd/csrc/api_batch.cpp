@@ -5,7 +5,10 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "ctx.h"
@@ -47,8 +50,57 @@ bl_status bpool_reserve(bl_ctx ctx, int nprob, int64_t need, const std::vector<i
 // Pick the variant of the shared scan for this shape (workgroup width, register prefetch): time each
 // candidate on up to 32,768 columns (raw products against the row masks) and keep the fastest.  Every candidate computes each
 // column's products in the same order, so the choice never changes results.
+// The tuning cache file named by the environment variable BL_AUTOTUNE_CACHE (when set): one line per shape,
+// "bscan <arch> <xtype> <n_total> <p> <variant>"; a shape found there is not timed again, a new one is appended.
+static std::string tune_key(bl_ctx ctx, const Mat& m) {
+    hipDeviceProp_t prop{};
+    std::string arch = hipGetDeviceProperties(&prop, ctx->device) == hipSuccess ? prop.gcnArchName : "unknown";
+    for (char& ch : arch)
+        if (ch == ' ') ch = '_';
+    char buf[160];
+    std::snprintf(buf, sizeof(buf), "bscan %s %d %lld %lld", arch.c_str(), m.xtype, (long long)m.n_total,
+                  (long long)m.p);
+    return buf;
+}
+
+static int tune_cache_lookup(const std::string& key) {
+    const char* path = std::getenv("BL_AUTOTUNE_CACHE");
+    if (!path || !*path) return -1;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return -1;
+    char line[256];
+    int found = -1;
+    while (std::fgets(line, sizeof(line), f)) {
+        const size_t kl = key.size();
+        if (std::strncmp(line, key.c_str(), kl) == 0 && line[kl] == ' ') {
+            const int v = std::atoi(line + kl + 1);
+            if (v >= 0 && v < BSCAN_VARIANTS) found = v;   // the last entry for the shape wins
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+static void tune_cache_store(const std::string& key, int v) {
+    const char* path = std::getenv("BL_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;   // the cache is an optimization: an unwritable file only costs the timing next time
+    std::fprintf(f, "%s %d\n", key.c_str(), v);
+    std::fclose(f);
+}
+
 bl_status tune_bscan(bl_ctx ctx, const Mat& m, const double* B, int nprob, BatchScalars* bs, double* out) {
     if (ctx->bscan_n == m.n_total && ctx->bscan_p == m.p && ctx->bscan_x == m.xtype) return BL_OK;
+    const std::string key = tune_key(ctx, m);
+    const int cached = tune_cache_lookup(key);
+    if (cached >= 0) {
+        ctx->bscan_n = m.n_total;
+        ctx->bscan_p = m.p;
+        ctx->bscan_x = m.xtype;
+        ctx->bscan_waves = cached;
+        return BL_OK;
+    }
     hipStream_t st = ctx->stream;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
@@ -85,6 +137,7 @@ bl_status tune_bscan(bl_ctx ctx, const Mat& m, const double* B, int nprob, Batch
     ctx->bscan_p = m.p;
     ctx->bscan_x = m.xtype;
     ctx->bscan_waves = pick;
+    tune_cache_store(key, pick);
     return BL_OK;
 }
 

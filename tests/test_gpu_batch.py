@@ -147,3 +147,22 @@ def test_batch_bf16_scans_equal_fp64_scans(gpu_ctx, n, p, nresp, nsub, K, prec):
     with pytest.raises(bl.BLError) as e:
         bl.fit_path_batch(gpu_ctx, to_dev(X32.astype(np.float64)), Yd, Md, precision=prec, **kw)
     assert e.value.status == bl.BL_ERR_UNSUPPORTED
+
+
+def test_autotune_cache_file(tmp_path, monkeypatch):
+    """BL_AUTOTUNE_CACHE: the first context times the scan variants on this shape and appends its pick; a new
+    context reads it back (no second line) and the two runs give the same coefficients."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("BL_AUTOTUNE_CACHE", str(path))
+    rec, X32, Y, masks = cv_problem(700, 1300, 4, 2, seed_shift=9)
+    Xd, Yd, Md = to_dev(X32), to_dev(Y), to_dev(masks)
+    kw = dict(nlambda=8, lambda_min_ratio=rec.lambda_min_ratio, tol=1e-10)
+    with bl.Context(0) as c1:
+        r1 = bl.fit_path_batch(c1, Xd, Yd, Md, **kw)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("bscan ") and lines[0].split()[3:5] == ["700", "1300"]
+    with bl.Context(0) as c2:
+        r2 = bl.fit_path_batch(c2, Xd, Yd, Md, **kw)
+    assert path.read_text().splitlines() == lines
+    assert r2.scan_cols == r1.scan_cols
+    assert torch.equal(r1.beta, r2.beta)

@@ -115,19 +115,32 @@ def c4_full(gpu_ctx):
     prob = datagen.make(rec)
     Y = np.repeat(prob.y, rec.nsub, axis=0)
     Xd = torch.from_numpy(prob.Xt).to(DEV)
-    res = bl.fit_path_batch(gpu_ctx, Xd, torch.from_numpy(Y).to(DEV), torch.from_numpy(prob.masks).to(DEV),
-                            nlambda=rec.nlambda, lambda_min_ratio=rec.lambda_min_ratio, rule=bl.SCREEN_SSR_BEDPP,
-                            tol=1e-10)
+    Yd, Md = torch.from_numpy(Y).to(DEV), torch.from_numpy(prob.masks).to(DEV)
+    kw = dict(nlambda=rec.nlambda, lambda_min_ratio=rec.lambda_min_ratio, rule=bl.SCREEN_SSR_BEDPP, tol=1e-10)
+    res = bl.fit_path_batch(gpu_ctx, Xd, Yd, Md, **kw)
     log(f"GPU batch: {res.time_ms:.0f} ms for {Y.shape[0]} problems")
+    # the BF16 check-scan forms, the configuration bench.py times (two pieces) and three pieces
+    same = {}
+    for name, prec in (("bf16x2", bl.PREC_BF16X2), ("bf16x3", bl.PREC_BF16X3)):
+        rb = bl.fit_path_batch(gpu_ctx, Xd, Yd, Md, precision=prec, **kw)
+        same[name] = bool(torch.equal(rb.beta, res.beta)) and rb.k_done == res.k_done
+        log(f"GPU batch, {name} check scans: {rb.time_ms:.0f} ms, coefficients bit-identical: {same[name]}")
+        del rb
     beta = res.beta.cpu().numpy()
     del Xd
     torch.cuda.empty_cache()
-    return rec, prob, Y, res, beta
+    return rec, prob, Y, res, beta, same
+
+
+def test_c4_full_bf16_check_scans_equal_fp64(c4_full):
+    """At the benchmarked shape the BF16 matrix-core check scans (two and three pieces) take every decision
+    the FP64 scans take: all 64 problems' coefficients are the same bits."""
+    assert c4_full[5] == {"bf16x2": True, "bf16x3": True}
 
 
 @pytest.mark.parametrize("b,k", [(0, 49), (37, 25)])
 def test_c4_full_kkt_certificate(c4_full, b, k):
-    rec, prob, Y, res, beta, = c4_full
+    rec, prob, Y, res, beta, _ = c4_full
     Xt, mask = prob.Xt, prob.masks[b]
     # the problem's own standardization by the oracle, chunk by chunk
     st = chunked(Xt, lambda blk, j0: oracle.standardize(blk, mask)[:3])
