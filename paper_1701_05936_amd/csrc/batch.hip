@@ -214,7 +214,8 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVE
 // values of the next two chunks are in flight in three register buffers taken in turn (the chunk loop is
 // unrolled three times so that no buffer is copied).
 constexpr int BF_K = 64;          // rows per chunk (two 32-row matrix-core steps)
-constexpr int BF_RS = BF_K + 8;   // LDS stride of a (piece, problem) row block, bf16 elements (144 bytes)
+constexpr int BF_RS = BF_K + 16;  // LDS stride of a (piece, problem) row block, bf16 elements (160 bytes: the
+                                  // matrix-core operand reads and the staging writes measured free of bank conflicts)
 constexpr int BF_PROMO = 9;       // chunks between promotions of the second accumulator (a multiple of 3)
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
