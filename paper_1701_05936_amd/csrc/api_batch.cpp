@@ -247,6 +247,7 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
     int64_t* kdev;   // lambda step counter read by the replayed screening graph
     ENSURE(BB_KDEV, 8, kdev);
     __bf16* Rp = nullptr;
+    double* bfpart = nullptr;
     uint8_t* flag = nullptr;
     int32_t *lF = nullptr, *lU = nullptr;
     int64_t* lenF = lens + BNP + 2;
@@ -255,6 +256,7 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
     ENSURE(BB_LU, p * 4, lU);
     if (bf) {
         ENSURE(BB_RP, (size_t)bscan_bf16_pieces_bytes(nt, pieces), Rp);
+        ENSURE(BB_BFPART, bscan_bf16_part_bytes(pieces), bfpart);
         ENSURE(BB_FLAG, p, flag);
         ENSURE(BB_LF, p * 4, lF);
     }
@@ -465,7 +467,7 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
             } else {
                 HIPCHK(launch_b_r_pieces(R, nt, NB, pieces, Rp, st));
                 prof_mark(ctx, 2);
-                HIPCHK(launch_bscan_bf16(m, lT, lenT, 0, pieces, Rp, NB, bs, c, sd, keep, zcur, st));
+                HIPCHK(launch_bscan_bf16(m, lT, lenT, 0, pieces, Rp, NB, bs, c, sd, keep, bfpart, zcur, st));
                 prof_mark(ctx, 3);
                 // decisions within the bound of a threshold (this check, the next strong rule) are re-taken on
                 // the FP64 scan of those columns

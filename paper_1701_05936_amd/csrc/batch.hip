@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -239,6 +240,38 @@ __global__ void k_b_r_pieces(const double* __restrict__ R, int64_t n_total, int6
     }
 }
 
+// Work split: a column list of len columns is T = ceil(len / (16 WAVES)) tiles of 16 WAVES columns, each C
+// chunks of 64 rows.  The G workgroups of a launch (as many as the device holds at once) first run
+// Tf = floor(T / G) whole tiles each, tile i + k G for workgroup i, all of them moving through the rows in step
+// so that the residual pieces of a chunk are read from L2 by every workgroup at about the same time.  The
+// T - Tf G tiles left over are cut by rows: their (tile, chunk) units, tile-major, go out in equal contiguous
+// ranges of at least BF_QMIN chunks, one per workgroup, so every workgroup finishes at about the same time
+// however T falls against G.  A tile
+// run whole by one workgroup is written out directly; the rows of a cut tile that one workgroup ran are
+// stored as raw FP64 sums in part, slot 0 for the first leftover tile the workgroup touches and slot 1 for
+// the second, and k_bscan_bf16_join adds the slots of each cut tile in row order.
+constexpr int BF_QMIN = 8;   // fewest chunks in a range of leftover units (bounds the rows a cut tile is cut into)
+struct BfSplit {
+    int64_t T, C, Tf, Trem, q;   // tiles, chunks per tile, whole tiles per workgroup, leftover tiles, units per range
+};
+template <int WAVES>
+__device__ __forceinline__ BfSplit bf_split(int64_t len, int64_t n_pad, int64_t G) {
+    BfSplit s;
+    s.T = (len + 16 * WAVES - 1) / (16 * WAVES);
+    s.C = n_pad / BF_K;
+    s.Tf = s.T / G;
+    s.Trem = s.T - s.Tf * G;
+    s.q = max((s.Trem * s.C + G - 1) / G, (int64_t)BF_QMIN);
+    return s;
+}
+// z_j of problem b from its raw sum x_j' r_b (the implicit standardization of the column)
+__device__ __forceinline__ void bf_store(double acc, int b, int64_t jq, int64_t p, const BatchScalars* bs,
+                                         const double* c, const double* s, const uint8_t* keep, double* out) {
+    const int64_t bj = (int64_t)b * p + jq;
+    const bool kept = keep == nullptr || keep[bj] != 0;
+    out[bj] = kept ? (acc - c[bj] * bs[b].sum_r) / ((double)bs[b].n_rows * s[bj]) : 0.0;
+}
+
 template <int WAVES, int PC>
 __global__ __launch_bounds__(64 * WAVES, 8 / WAVES) void k_bscan_bf16(const float* __restrict__ X, int64_t ldx, int64_t n_total,
                                                            int64_t n_pad, const __bf16* __restrict__ Rp,
@@ -246,21 +279,23 @@ __global__ __launch_bounds__(64 * WAVES, 8 / WAVES) void k_bscan_bf16(const floa
                                                            const int64_t* __restrict__ len_dev, int64_t len_host,
                                                            int nprob, int64_t p, const BatchScalars* __restrict__ bs,
                                                            const double* __restrict__ c, const double* __restrict__ s,
-                                                           const uint8_t* __restrict__ keep, double* __restrict__ out) {
+                                                           const uint8_t* __restrict__ keep, double* __restrict__ part,
+                                                           double* __restrict__ out) {
     static_assert(PC == 2 || PC == 3, "two or three pieces");
     static_assert(BF_PROMO % 3 == 0, "the main loop promotes after whole groups of three chunks");
-    constexpr int NT = 64 * WAVES;
+    constexpr int NT = 64 * WAVES, TW = 16 * WAVES;
     constexpr int PLANE = PC * BNP * BF_RS;
     __shared__ __bf16 Rl[2 * PLANE];
     const int64_t len = len_dev ? *len_dev : len_host;
-    const int64_t f0 = (int64_t)blockIdx.x * 16 * WAVES;
-    if (f0 >= len) return;
+    const int64_t G = gridDim.x, wg = blockIdx.x;
+    const BfSplit sp = bf_split<WAVES>(len, n_pad, G);
+    const int64_t C = sp.C, F = n_total / BF_K;   // chunks; chunks wholly inside n_total
+    // this workgroup's range of leftover units
+    const int64_t u0 = wg * sp.q, u1 = min(u0 + sp.q, sp.Trem * C);
+    if (sp.Tf == 0 && u0 >= u1) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid / 64;
     const int m = lane & 15, g = lane >> 4;
-    const int64_t t = f0 + 16 * w + m;
-    const bool ok = t < len;
-    const int64_t j = ok ? (cols ? (int64_t)cols[t] : t) : 0;   // lanes past the list read column 0, unused
-    const float* xc = X + j * ldx;
+    const float* xc = X;   // the lane's column of the tile being run
     // staging of one chunk's pieces: PC x 64 problems x 64 rows in 16-byte blocks
     constexpr int SB = PC * BNP * (BF_K / 8);
     constexpr int SPT = (SB + NT - 1) / NT;
@@ -379,65 +414,124 @@ __global__ __launch_bounds__(64 * WAVES, 8 / WAVES) void k_bscan_bf16(const floa
         __syncthreads();
         ++ch;
     };
-    const int64_t C = n_pad / BF_K, F = n_total / BF_K;   // chunks; chunks wholly inside n_total
-    // main loop: groups of three chunks, one per register buffer, whose loads (the pieces of the next chunk,
-    // then X two chunks ahead) are all unguarded; the pieces are issued first so that waiting for them leaves
-    // the X loads in flight
-    const int64_t Cmain = F >= 2 ? 3 * ((F - 2) / 3) : 0;
     float xb[3][16];
-    load_x(xb[0], 0);
-    if (C > 1) load_x(xb[1], 1);
-    stage_load(0);
-    stage_store(Rl);
-    __syncthreads();
-    for (int64_t ck = 0; ck < Cmain; ck += 3) {
-        stage_load(ck + 1);
-        load_fast(xb[2], ck + 2);
-        compute(xb[0]);
-        next();
-        stage_load(ck + 2);
-        load_fast(xb[0], ck + 3);
-        compute(xb[1]);
-        next();
-        stage_load(ck + 3);
-        load_fast(xb[1], ck + 4);
-        compute(xb[2]);
-        next();
-        if (ch % BF_PROMO == 0) promote2();
-    }
-    promote2();
-    // the last chunks (at most five): guarded loads, one chunk ahead of the pieces and two of X
-    for (int64_t ck = Cmain; ck < C; ++ck) {
-        const bool more = ck + 1 < C;
-        if (more) stage_load(ck + 1);
-        float xn[16] = {};
-        if (ck + 2 < C) load_x(xn, ck + 2);
-        compute(xb[0]);
-        if (more) stage_store(Rl + ((ch & 1) ^ 1) * PLANE);
+    // the workgroup's jobs: its Tf whole tiles, then the one or two tiles its range of leftover units touches;
+    // a job runs chunks c0 .. c1 - 1 of tile tt into acc64 (zero on entry) and writes the sums out (the whole
+    // tile) or stores them in part slot `slot` (some of its rows)
+    const int64_t head = u0 / C;
+    const int64_t njobs = sp.Tf + (u0 < u1 ? (u1 - 1) / C - head + 1 : 0);
+    for (int64_t job = 0; job < njobs; ++job) {
+        int64_t tt = wg + job * G, c0 = 0, c1 = C;
+        int slot = 0;
+        if (job >= sp.Tf) {
+            const int64_t tr = head + (job - sp.Tf);
+            tt = sp.Tf * G + tr;
+            c0 = max(u0 - tr * C, (int64_t)0);
+            c1 = min(u1 - tr * C, C);
+            slot = tr == head ? 0 : 1;
+        }
+        const int64_t t = tt * TW + 16 * w + m;
+        const int64_t j = t < len ? (cols ? (int64_t)cols[t] : t) : 0;   // lanes past the list read column 0, unused
+        xc = X + j * ldx;
+        // main loop: groups of three chunks, one per register buffer, whose loads (the pieces of the next
+        // chunk, then X two chunks ahead) are all unguarded; the pieces are issued first so that waiting for
+        // them leaves the X loads in flight
+        const int64_t E = min(F, c1);
+        const int64_t Cmain = E - c0 >= 2 ? 3 * ((E - c0 - 2) / 3) : 0;
+        load_x(xb[0], c0);
+        if (c0 + 1 < c1) load_x(xb[1], c0 + 1);
+        // this LDS buffer was last read by the chunk before the previous one, which the last barrier ended
+        stage_load(c0);
+        stage_store(Rl + (ch & 1) * PLANE);
         __syncthreads();
-        ++ch;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            xb[0][q] = xb[1][q];
-            xb[1][q] = xn[q];
+        int grp = 0;
+        for (int64_t ck = c0; ck < c0 + Cmain; ck += 3) {
+            stage_load(ck + 1);
+            load_fast(xb[2], ck + 2);
+            compute(xb[0]);
+            next();
+            stage_load(ck + 2);
+            load_fast(xb[0], ck + 3);
+            compute(xb[1]);
+            next();
+            stage_load(ck + 3);
+            load_fast(xb[1], ck + 4);
+            compute(xb[2]);
+            next();
+            if (++grp == BF_PROMO / 3) {
+                grp = 0;
+                promote2();
+            }
         }
-    }
-    promote2();
-    // lane (m, g), register q of problem tile nt: column 16 w + 4 g + q of the workgroup, problem 16 nt + m
+        promote2();
+        // the last chunks (at most five): guarded loads, one chunk ahead of the pieces and two of X
+        for (int64_t ck = c0 + Cmain; ck < c1; ++ck) {
+            const bool more = ck + 1 < c1;
+            if (more) stage_load(ck + 1);
+            float xn[16] = {};
+            if (ck + 2 < c1) load_x(xn, ck + 2);
+            compute(xb[0]);
+            if (more) stage_store(Rl + ((ch & 1) ^ 1) * PLANE);
+            __syncthreads();
+            ++ch;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t tq = f0 + 16 * w + 4 * g + q;
-        if (tq >= len) continue;
-        const int64_t jq = cols ? (int64_t)cols[tq] : tq;
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const int b = 16 * nt + m;
-            if (b >= nprob) continue;
-            const int64_t bj = (int64_t)b * p + jq;
-            const bool kept = keep == nullptr || keep[bj] != 0;
-            out[bj] = kept ? (acc64[nt][q] - c[bj] * bs[b].sum_r) / ((double)bs[b].n_rows * s[bj]) : 0.0;
+            for (int q = 0; q < 16; ++q) {
+                xb[0][q] = xb[1][q];
+                xb[1][q] = xn[q];
+            }
         }
+        promote2();
+        // lane (m, g), register q of problem tile nt: column 16 w + 4 g + q of the tile, problem 16 nt + m
+        const bool whole = c0 == 0 && c1 == C;
+        double* pp = part + (wg * 2 + slot) * (int64_t)TW * BNP;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int ci = 16 * w + 4 * g + q;
+            const int64_t tq = tt * TW + ci;
+            if (tq >= len) continue;
+            const int64_t jq = cols ? (int64_t)cols[tq] : tq;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int b = 16 * nt + m;
+                if (b >= nprob) continue;
+                if (whole) bf_store(acc64[nt][q], b, jq, p, bs, c, s, keep, out);
+                else pp[(int64_t)b * TW + ci] = acc64[nt][q];
+            }
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc64[nt][q] = 0.0;
     }
+}
+
+// The cut leftover tiles of a k_bscan_bf16 launch with G workgroups: one thread per (leftover tile, problem,
+// column) adds the tile's stored rows in row order, if the tile was cut (a leftover tile one workgroup ran
+// whole is written already).
+template <int WAVES>
+__global__ __launch_bounds__(256) void k_bscan_bf16_join(const int64_t* __restrict__ len_dev, int64_t len_host,
+                                                         int64_t n_pad, int64_t G, const int32_t* __restrict__ cols,
+                                                         int nprob, int64_t p, const BatchScalars* __restrict__ bs,
+                                                         const double* __restrict__ c, const double* __restrict__ s,
+                                                         const uint8_t* __restrict__ keep,
+                                                         const double* __restrict__ part, double* __restrict__ out) {
+    constexpr int TW = 16 * WAVES;
+    const int64_t len = len_dev ? *len_dev : len_host;
+    const BfSplit sp = bf_split<WAVES>(len, n_pad, G);
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tr = e / (TW * BNP);
+    const int b = (int)(e / TW % BNP), ci = (int)(e % TW);
+    if (tr >= sp.Trem || b >= nprob) return;
+    const int64_t tq = (sp.Tf * G + tr) * TW + ci;
+    const int64_t i0 = tr * sp.C / sp.q, i1 = ((tr + 1) * sp.C - 1) / sp.q;
+    if (tq >= len || i0 == i1) return;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int64_t i = i0; i <= i1; ++i) {
+        const int slot = i * sp.q / sp.C == tr ? 0 : 1;
+        acc += part[((i * 2 + slot) * BNP + b) * TW + ci];
+    }
+    bf_store(acc, b, cols ? (int64_t)cols[tq] : tq, p, bs, c, s, keep, out);
 }
 
 // Flag the columns whose matrix-core z, for some problem, lies within its error bound of a threshold the path
@@ -1285,20 +1379,47 @@ hipError_t launch_b_r_pieces(const double* R, int64_t n_total, int nprob, int pc
     return hipGetLastError();
 }
 
+// workgroups of k_bscan_bf16 the device holds at once (its launches take exactly that many)
+constexpr int BF_W = 8;   // 128 columns per workgroup share each staged chunk of residual pieces
+int bscan_bf16_slots(int pc) {
+    static int cached[2] = {0, 0};
+    int& n = cached[pc == 3 ? 1 : 0];
+    if (!n) {
+        int per_cu = 0;
+        const hipError_t e = pc == 3
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bscan_bf16<BF_W, 3>, 64 * BF_W, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bscan_bf16<BF_W, 2>, 64 * BF_W, 0);
+        if (e != hipSuccess || per_cu < 1) {
+            (void)hipGetLastError();
+            per_cu = 1;
+        }
+        n = per_cu * device_cu_count();
+    }
+    return n;
+}
+
+size_t bscan_bf16_part_bytes(int pc) { return (size_t)bscan_bf16_slots(pc) * 2 * 16 * BF_W * BNP * sizeof(double); }
+
 hipError_t launch_bscan_bf16(const Mat& mt, const int32_t* cols, const int64_t* len_dev, int64_t len_host, int pc,
                              const __bf16* Rp, int nprob, const BatchScalars* bs, const double* c, const double* s,
-                             const uint8_t* keep, double* out, hipStream_t st) {
-    constexpr int W = 8;   // 128 columns per workgroup share each staged chunk of residual pieces
-    const int64_t work = len_dev ? mt.p : len_host;
-    const int g = grid_for(work, 16 * W, 1 << 20);
+                             const uint8_t* keep, double* part, double* out, hipStream_t st) {
+    const int g = bscan_bf16_slots(pc);
     const float* X = (const float*)mt.X;
     const int64_t n_pad = batch_pad(mt.n_total);
+    if (n_pad <= 0) return hipErrorInvalidValue;
     if (pc == 2)
-        k_bscan_bf16<W, 2><<<g, 64 * W, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, Rp, cols, len_dev, len_host, nprob, mt.p,
-                                                bs, c, s, keep, out);
+        k_bscan_bf16<BF_W, 2><<<g, 64 * BF_W, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, Rp, cols, len_dev, len_host, nprob,
+                                                      mt.p, bs, c, s, keep, part, out);
     else
-        k_bscan_bf16<W, 3><<<g, 64 * W, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, Rp, cols, len_dev, len_host, nprob, mt.p,
-                                                bs, c, s, keep, out);
+        k_bscan_bf16<BF_W, 3><<<g, 64 * BF_W, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, Rp, cols, len_dev, len_host, nprob,
+                                                      mt.p, bs, c, s, keep, part, out);
+    // at most g - 1 leftover tiles (fewer when the list length is on the host)
+    int64_t tiles = g - 1;
+    if (!len_dev) tiles = std::min(tiles, (len_host + 16 * BF_W - 1) / (16 * BF_W));
+    if (tiles > 0)
+        k_bscan_bf16_join<BF_W><<<(int)(tiles * 16 * BF_W * BNP / 256), 256, 0, st>>>(len_dev, len_host, n_pad, g, cols,
+                                                                                     nprob, mt.p, bs, c, s, keep, part,
+                                                                                     out);
     return hipGetLastError();
 }
 

@@ -264,9 +264,14 @@ hipError_t launch_bscan_split(const Mat& mt, const int32_t* cols, int64_t len, c
 double bscan_bf16_rel(int64_t n_total, int pc);
 int64_t bscan_bf16_pieces_bytes(int64_t n_total, int pc);
 hipError_t launch_b_r_pieces(const double* R, int64_t n_total, int nprob, int pc, __bf16* Rp, hipStream_t st);
+// the scan takes as many workgroups as the device holds at once and splits the column list between them
+// evenly, cutting tiles by rows where needed (part: scratch of bscan_bf16_part_bytes(pc) bytes for the rows of
+// the cut tiles)
+int bscan_bf16_slots(int pc);
+size_t bscan_bf16_part_bytes(int pc);
 hipError_t launch_bscan_bf16(const Mat& mt, const int32_t* cols, const int64_t* len_dev, int64_t len_host, int pc,
                              const __bf16* Rp, int nprob, const BatchScalars* bs, const double* c, const double* s,
-                             const uint8_t* keep, double* out, hipStream_t st);
+                             const uint8_t* keep, double* part, double* out, hipStream_t st);
 hipError_t launch_b_band(const int32_t* cols, const int64_t* len_dev, int64_t p, int nprob, const double* z,
                          const double* c, const double* s, const uint8_t* keep, const BatchScalars* bs,
                          const double* lam, const double* thr, double rel, uint8_t* flag, hipStream_t st);

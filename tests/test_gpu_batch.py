@@ -128,13 +128,17 @@ def test_batch_rejects_invalid_inputs(gpu_ctx):
 
 
 @pytest.mark.parametrize("prec", [bl.PREC_BF16X3, bl.PREC_BF16X2])
-@pytest.mark.parametrize("n,p,nresp,nsub,K", [(1500, 4000, 8, 2, 20), (1037, 2222, 32, 2, 15)])
-def test_batch_bf16_scans_equal_fp64_scans(gpu_ctx, n, p, nresp, nsub, K, prec):
+@pytest.mark.parametrize("n,p,nresp,nsub,K,ratio", [(1500, 4000, 8, 2, 20, None), (1037, 2222, 32, 2, 15, None),
+                                                    (701, 40000, 8, 2, 6, 0.3)])
+def test_batch_bf16_scans_equal_fp64_scans(gpu_ctx, n, p, nresp, nsub, K, ratio, prec):
     """The BF16 matrix-core check scans (f32 X, three or two pieces of x and r) re-take every decision within
     their error bound on the FP64 scan and start each solve from FP64 gradients: the same coefficients as the
-    FP64 scans, bit for bit."""
+    FP64 scans, bit for bit.  The scan splits its column list evenly over the workgroups the device holds at
+    once: lists shorter than one 128-column tile per workgroup are cut by rows throughout (the first two
+    shapes); 40,000 columns (every column survives BEDPP from the third step on) give every workgroup a whole
+    tile and cut the tiles left over by rows."""
     rec, X32, Y, masks = cv_problem(n, p, nresp, nsub, seed_shift=7)
-    ratio = rec.lambda_min_ratio
+    ratio = ratio or rec.lambda_min_ratio
     Xd, Yd, Md = to_dev(X32), to_dev(Y), to_dev(masks)
     kw = dict(nlambda=K, lambda_min_ratio=ratio, tol=1e-10)
     r64 = bl.fit_path_batch(gpu_ctx, Xd, Yd, Md, **kw)
