@@ -18,6 +18,11 @@ using namespace blapi;
 
 namespace {
 
+// distinct row masks up to which the column statistics take one pass of X per mask rather than the two mask
+// scans on the matrix cores (a pass of the statistics kernel is HBM-bound; the two scans take about six of
+// its passes with 64 problems)
+constexpr int BATCH_STATS_PASSES = 4;
+
 bl_status bpool_reserve(bl_ctx ctx, int nprob, int64_t need, const std::vector<int64_t>& sizes) {
     if (need <= ctx->bpool_cap && nprob <= ctx->bpool_np) return BL_OK;
     int64_t cap = need <= ctx->bpool_cap ? ctx->bpool_cap : std::max<int64_t>({need, ctx->bpool_cap * 2, 256});
@@ -294,18 +299,65 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
     if ((s = tune_bscan(ctx, m, Mb, NB, bs, S1))) return s;
     const int waves = ctx->bscan_waves;   // the variant picked for this shape
     res->scan_cols = bscan_variant_cols(waves);
+    // Centers and scales depend on a problem's rows alone, so problems with the same mask (the responses of
+    // one cross-validation fold) share them.  With few distinct masks each takes one pass of the column
+    // statistics kernel and the other problems copy its results; otherwise the two mask scans X'M and
+    // (X o X)'M run on the matrix cores for every problem at once.
+    std::vector<int> rep(NB);
+    std::vector<int64_t> rows(NB, nt);
+    int U = 0;
+    {
+        std::vector<uint8_t> hm(bt->masks ? (size_t)NB * nt : 0);
+        if (bt->masks) {
+            HIPCHK(hipMemcpyAsync(hm.data(), masks, hm.size(), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
+        for (int b = 0; b < NB; ++b) {
+            rep[b] = b;
+            for (int u = 0; u < b && bt->masks; ++u)
+                if (rep[u] == u && std::memcmp(&hm[(size_t)u * nt], &hm[(size_t)b * nt], (size_t)nt) == 0) {
+                    rep[b] = u;
+                    break;
+                }
+            if (!bt->masks && b > 0) rep[b] = 0;
+            if (rep[b] != b) continue;
+            ++U;
+            if (bt->masks)
+                rows[b] = nt - std::count(hm.begin() + (size_t)b * nt, hm.begin() + (size_t)(b + 1) * nt, (uint8_t)0);
+        }
+    }
+    const bool by_mask = U <= BATCH_STATS_PASSES;
     prof_mark(ctx, 0);
-    HIPCHK(launch_bscan(m, 0, nullptr, nullptr, p, Mb, NB, bs, nullptr, nullptr, nullptr, S1, st, waves));
-    HIPCHK(launch_bscan(m, 1, nullptr, nullptr, p, Mb, NB, bs, nullptr, nullptr, nullptr, S2, st, waves));
+    if (by_mask) {
+        for (int b = 0; b < NB; ++b) {
+            if (rep[b] != b) continue;
+            Mat mb = m;
+            mb.mask = bt->masks ? masks + (size_t)b * nt : nullptr;
+            HIPCHK(launch_colstats(mb, c + (size_t)b * p, sd + (size_t)b * p, keep + (size_t)b * p, rows[b], st));
+        }
+    } else {
+        HIPCHK(launch_bscan(m, 0, nullptr, nullptr, p, Mb, NB, bs, nullptr, nullptr, nullptr, S1, st, waves));
+        HIPCHK(launch_bscan(m, 1, nullptr, nullptr, p, Mb, NB, bs, nullptr, nullptr, nullptr, S2, st, waves));
+    }
     prof_mark(ctx, 1);
-    HIPCHK(launch_b_stats(S1, S2, p, NB, bs, c, sd, keep, st));
+    if (by_mask) {
+        for (int b = 0; b < NB; ++b) {
+            if (rep[b] == b) continue;
+            const size_t o = (size_t)b * p, ou = (size_t)rep[b] * p;
+            HIPCHK(hipMemcpyAsync(c + o, c + ou, (size_t)p * 8, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(sd + o, sd + ou, (size_t)p * 8, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(keep + o, keep + ou, (size_t)p, hipMemcpyDeviceToDevice, st));
+        }
+    } else {
+        HIPCHK(launch_b_stats(S1, S2, p, NB, bs, c, sd, keep, st));
+    }
     HIPCHK(launch_b_sum_r(R, nt, NB, bs, st));
     prof_mark(ctx, 2);
     HIPCHK(launch_bscan(m, 2, nullptr, nullptr, p, Yt, NB, bs, c, sd, keep, a, st, waves));
     prof_mark(ctx, 3);
     HIPCHK(launch_b_argmax(a, keep, p, NB, bs, st));
     if ((s = read_bs())) return s;
-    prof_add(ctx, 0, BL_PROF_COLSTATS, 2.0 * p * nt * es);
+    prof_add(ctx, 0, BL_PROF_COLSTATS, (by_mask ? (double)U : 2.0) * p * nt * es);
     prof_add(ctx, 2, BL_PROF_SETUP, (double)p * nt * es + (double)nt * NB * 8.0, 2.0 * p * nt * NB, (double)p);
     std::vector<double> lmax(NB);
     for (int b = 0; b < NB; ++b) {

@@ -736,10 +736,12 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
                     go[(int)(q & (OR - 1)) * MB + lane] = gl;
                     bo[(int)(q & (OR - 1)) * MB + lane] = bv;
                 }
-                maxd = fmax(maxd, wmax);
+                maxd = fmax(maxd, wmax);   // this lane's largest change in the sweep so far
                 bool stop = false;
                 if (b == nb - 1) {
                     ++sweeps;
+#pragma unroll
+                    for (int o = WAVE / 2; o > 0; o >>= 1) maxd = fmax(maxd, __shfl_xor(maxd, o, WAVE));
                     if (maxd < a.tol) stop = true;
                     else if (sweeps >= a.max_sweeps) {
                         status = 1;

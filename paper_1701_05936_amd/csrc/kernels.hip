@@ -922,8 +922,9 @@ hipError_t launch_colstats(const Mat& m, double* c, double* s, uint8_t* keep, in
     // lane's int32 sum of squares cannot overflow
     // FP64 / FP32 X: whole 16-byte words when every column starts 16-byte aligned (the sums are the same either way)
     const int64_t esz = m.xtype == 0 ? 8 : (m.xtype == 1 ? 4 : 1);
+    // (with a mask the last word of it read must lie inside its n_total bytes)
     const bool vec = m.xtype == 2 ? ((uintptr_t)m.X % 16 == 0 && m.ldx % 16 == 0 && (uintptr_t)m.mask % 16 == 0 &&
-                                     m.n_total <= (int64_t(1) << 22))
+                                     (!mk || m.n_total % 16 == 0) && m.n_total <= (int64_t(1) << 22))
                                   : ((uintptr_t)m.X % 16 == 0 && (m.ldx * esz) % 16 == 0 &&
                                      (uintptr_t)m.mask % (16 / esz) == 0);
     switch (m.xtype) {

@@ -73,6 +73,17 @@ def test_batch_all_rules_f64_all_rows(gpu_ctx, rule):
     assert (res.sweeps[:, 0] == 0).all() and (res.n_active[:, 0] == 0).all()
 
 
+def test_batch_shared_masks_match_oracle(gpu_ctx):
+    """Problems with the same row mask (several responses on one cross-validation fold) share its column
+    statistics, one pass of X per distinct mask: three masks over twelve problems, each against the oracle."""
+    rec, X32, Y, masks = cv_problem(800, 1700, 6, 2, seed_shift=11)
+    masks = masks[np.arange(12) % 3]
+    K, ratio = 12, rec.lambda_min_ratio
+    res = bl.fit_path_batch(gpu_ctx, to_dev(X32), to_dev(Y), to_dev(masks), nlambda=K, lambda_min_ratio=ratio,
+                            tol=1e-10)
+    check_against_oracle(res, X32.astype(np.float64), Y, masks, K, ratio, range(12))
+
+
 def test_batch_equals_single_problem_batches(gpu_ctx):
     """A problem's path does not depend on which other problems share the batch."""
     rec, X32, Y, masks = cv_problem(900, 1500, 4, 2, seed_shift=7)
