@@ -492,7 +492,7 @@ __global__ __launch_bounds__(GCD_THREADS) void k_gcd(GcdArgs a) {
 // Every wait is bounded: on time-out the waiter raises an error flag that all
 // others see, and the host reports a device error.
 constexpr int MB = 32;      // coordinates per block
-constexpr int SLACK = 5;    // most recent blocks whose changes the leader applies itself
+constexpr int SLACK = 4;    // most recent blocks whose changes the leader applies itself
 constexpr int MT = 256;     // threads per workgroup
 constexpr int HBATCH = 4;   // sequences a helper applies per round trip at most
 constexpr int HOWN = 2;     // blocks a helper owns at most
@@ -569,8 +569,11 @@ __device__ __forceinline__ uint32_t gram_off(int64_t m, int cb, int cl, int rb, 
 }
 
 // The leader loads Gram sets with 16-byte loads: lane l covers rows 2 (l % 16) and 2 (l % 16) + 1 of
-// columns l / 16 + 4k, k < GPER.  32 loads per lane stay under the 63 memory operations a wave can keep
-// in flight, so issuing a set never waits for the first of its own loads to return.
+// columns l / 16 + 4k, k < GPER.  A set is (SLACK + 1) GPER = 40 loads per lane: under the 63 memory
+// operations a wave can keep in flight, so issuing a set never waits for the first of its own loads to
+// return (the next set's loads wait for the oldest ones of the set before).  The set size is what paces the
+// loader: with SLACK = 5 (48 loads) the chain waited for it, and loading the next set block by block between
+// the stores of the current one was slower still.
 constexpr int GPER = MB * MB / (2 * WAVE);   // 16-byte loads per lane for one Gram block
 constexpr int GSET = (SLACK + 1) * GPER;      // for one set of SLACK + 1 blocks
 constexpr uint32_t GOFF_NONE2 = 0xFFFFFFF0u;  // out of range for a 16-byte load
@@ -726,7 +729,7 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
                 auto col = [&](int t) { return gc[t]; };
                 auto coln = [&](int t) { return gn[t]; };
                 double* dq = dh + (int)(q & (DR - 1)) * MB;   // this block's change slot
-                if (!chain_fast_next<MB>(gl, bv, col, coln, lam, bl, dl, wmax, dq, un)) {
+                if (!chain_fast_next<MB>(gl, bv, col, coln, lam, bl, dl, wmax, un)) {
                     chain_exact<MB>(gl, bv, col, lam, bl, dl, wmax);
                     if (lane < MB) dq[lane] = lane < bl ? dl : 0.0;
                     un = chain_next_update<MB>(coln, dq);
