@@ -710,21 +710,25 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
                 for (int t = 0; t < MB; ++t) gc[t] = Gm[t * MB + l32];
             }
             while (ok) {
-                // the prepared block, and free result slots (their publication is done)
-                ok = lead_wait(ctr, [&] { return lc_get(ctr, LC_PREP) > q && lc_get(ctr, LC_PUB) > q - OR; },
-                               limit, false);
+                // the prepared block, free result slots (their publication is done) and the next block's
+                // entries against this one (its Gram set is loaded whether or not the chain stops after this
+                // block), the three counters read together: the other waves run ahead, so one read usually
+                // finds all of them ready
+                ok = lead_wait(ctr, [&] {
+                    const int pr = lc_get(ctr, LC_PREP), pu = lc_get(ctr, LC_PUB), gr = lc_get(ctr, LC_GRAM);
+                    return (pr > q) & (pu > q - OR) & (gr > q + 1);
+                }, limit, false);
                 if (!ok) break;
                 const int cur = (int)(q & 1), bl = blk_len(m, b);
-                double gl = lane < bl ? gp[cur * MB + l32] : 0.0;
-                const double bv0 = lane < bl ? bp[cur * MB + l32] : 0.0;
-                if (q >= 1 && lane < bl) gl -= un;   // the previous block's changes
-                // the next block's entries against this one (its Gram set is loaded whether or not the
-                // chain stops after this block)
-                ok = lead_wait(ctr, [&] { return lc_get(ctr, LC_GRAM) > q + 1; }, limit, false);
-                if (!ok) break;
+                // every lane reads (the slots hold MB values), so that no branch holds up the reads after these
+                const double gpl = gp[cur * MB + l32], bpl = bp[cur * MB + l32];
                 const double* Gn1 = Gm + (int)((q + 1) % GR) * (SLACK + 1) * MB * MB;
 #pragma unroll
                 for (int t = 0; t < MB; ++t) gn[t] = Gn1[MB * MB + t * MB + l32];
+                __builtin_amdgcn_sched_barrier(0);   // all of these reads issue before the first use of one
+                // the previous block's changes
+                double gl = lane < bl ? (q >= 1 ? gpl - un : gpl) : 0.0;
+                const double bv0 = lane < bl ? bpl : 0.0;
                 double bv = bv0, dl = 0.0, wmax = 0.0;
                 auto col = [&](int t) { return gc[t]; };
                 auto coln = [&](int t) { return gn[t]; };
@@ -795,24 +799,37 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
             }
         } else if (wv == 2) {
             // ---- preparing the block of sequence q ----
+            // Pipelined by one block so that the global-memory round trips overlap the work in LDS: the owner's
+            // count for the next block is read before this block's sums, and the next block's gradient and
+            // coefficients are read (once that count and the publication allow) after this block is handed on,
+            // to arrive while the next block's sums are formed.
             const int l32 = lane & (MB - 1), half = lane >> 5;
-            int bq = 0;
-            for (int64_t q = 0;; ++q) {
-                if (lc_get(ctr, LC_STOP) != INT_MAX) break;
-                const int nl = blk_len(m, bq);
-                const int64_t need = q - SLACK;
+            // block bb at sequence qq: its owner must have applied every change below qq - SLACK (fl: a value
+            // of the owner's count read earlier, polled again only if it is not yet enough), and its
+            // coefficients, last set at sequence qq - nb, must be published; then its reads go out
+            auto fetch = [&](int64_t qq, int bb, uint32_t fl, double& gq, double& bq_) -> bool {
+                const int64_t need = qq - SLACK;
                 bool ok = true;
-                if (need > 0) {
-                    const int owner = bq % H;
+                if (need > 0 && (int64_t)fl < need) {
+                    const int owner = bb % H;
                     ok = lead_wait(ctr, [&] { return (int64_t)ld_flag(sync + SYNC_APPLIED + 16 * owner) >= need; },
                                    limit, true);
                 }
-                // the block's coefficients were last set at sequence q - nb: wait for their publication
-                if (ok && q >= nb) ok = lead_wait(ctr, [&] { return lc_get(ctr, LC_PUB) > q - nb; }, limit, true);
-                if (!ok) break;
-                const int64_t e0 = (int64_t)bq * MB;
-                const double gn = l32 < nl ? ld_coh(a.g + e0 + l32) : 0.0;
-                const double bn = l32 < nl ? ld_coh(a.b + e0 + l32) : 0.0;
+                if (ok && qq >= nb) ok = lead_wait(ctr, [&] { return lc_get(ctr, LC_PUB) > qq - nb; }, limit, true);
+                if (!ok) return false;
+                const int nl = blk_len(m, bb);
+                const int64_t e0 = (int64_t)bb * MB;
+                gq = l32 < nl ? ld_coh(a.g + e0 + l32) : 0.0;
+                bq_ = l32 < nl ? ld_coh(a.b + e0 + l32) : 0.0;
+                return true;
+            };
+            int bq = 0;
+            double gcur = 0.0, bcur = 0.0;
+            bool ok = lc_get(ctr, LC_STOP) == INT_MAX && fetch(0, 0, 0u, gcur, bcur);
+            for (int64_t q = 0; ok; ++q) {
+                if (lc_get(ctr, LC_STOP) != INT_MAX) break;
+                const int bn1 = bq + 1 == nb ? 0 : bq + 1;
+                const uint32_t fl1 = ld_flag(sync + SYNC_APPLIED + 16 * (bn1 % H));   // used after the sums
                 // the changes up to q - 2, the Gram set of q, and a free slot (the chain of q - 2 is done)
                 ok = lead_wait(ctr, [&] { return lc_get(ctr, LC_CHAIN) >= q - 1 && lc_get(ctr, LC_GRAM) > q; },
                                limit, true);
@@ -837,12 +854,15 @@ __global__ __launch_bounds__(MT) void k_gcd_multi(GcdMultiArgs a) {
                 }
                 u += __shfl_xor(u, 32, WAVE);
                 if (lane < MB) {
-                    gp[(int)(q & 1) * MB + lane] = gn - u;
-                    bp[(int)(q & 1) * MB + lane] = bn;
+                    gp[(int)(q & 1) * MB + lane] = gcur - u;
+                    bp[(int)(q & 1) * MB + lane] = bcur;
                 }
                 lc_set(ctr, LC_PREP, (int)(q + 1));
-                bq = bq + 1 == nb ? 0 : bq + 1;
+                ok = fetch(q + 1, bn1, fl1, gcur, bcur);
+                bq = bn1;
             }
+            // the reads still in flight complete before the wave ends
+            wait_mem();
         } else {
             // ---- Gram sets, two in flight: set j + 1 is loading while set j is stored ----
             double2 va[GSET], vb[GSET];
