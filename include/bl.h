@@ -475,7 +475,7 @@ bl_status bl_cv_fit(bl_ctx ctx, const bl_matrix* X, const bl_cv* cv, const bl_pa
 
 /*
  * Screening network of the learned form (the paper has none; it stands beside the strong rule,
- * which stays the fallback, and the exact check, which stays the judge).
+ * which stays the fallback, and the exact check, which keeps the last word).
  *   input f (4 floats, as recorded above) -> h1 = relu(W1 f + b1) (64) -> h2 = relu(W2 h1 + b2) (64)
  *   -> logit o = w3 . h2 + b3 -> score sigmoid(o).
  * Parameters: FP32 vector of BL_MLP_NPARAMS = 4545 in the order W1[64][4], b1[64], W2[64][64], b2[64],
