@@ -95,7 +95,8 @@ static void tune_cache_store(const std::string& key, int v) {
     std::fclose(f);
 }
 
-bl_status tune_bscan(bl_ctx ctx, const Mat& m, const double* B, int nprob, BatchScalars* bs, double* out) {
+bl_status tune_bscan(bl_ctx ctx, const Mat& m, const double* B, int nprob, BatchScalars* bs, double* part,
+                     double* out) {
     if (ctx->bscan_n == m.n_total && ctx->bscan_p == m.p && ctx->bscan_x == m.xtype) return BL_OK;
     const std::string key = tune_key(ctx, m);
     const int cached = tune_cache_lookup(key);
@@ -118,10 +119,10 @@ bl_status tune_bscan(bl_ctx ctx, const Mat& m, const double* B, int nprob, Batch
     int pick = 1;
     bl_status s = BL_OK;
     for (int w = 0; w < BSCAN_VARIANTS; ++w) {
-        hipError_t e = launch_bscan(m, 0, nullptr, nullptr, cols, B, nprob, bs, nullptr, nullptr, nullptr, out, st, w);
+        hipError_t e = launch_bscan(m, 0, nullptr, nullptr, cols, B, nprob, bs, nullptr, nullptr, nullptr, part, out, st, w);
         if (e == hipSuccess) e = hipEventRecord(e0, st);
         for (int r = 0; r < 2 && e == hipSuccess; ++r)
-            e = launch_bscan(m, 0, nullptr, nullptr, cols, B, nprob, bs, nullptr, nullptr, nullptr, out, st, w);
+            e = launch_bscan(m, 0, nullptr, nullptr, cols, B, nprob, bs, nullptr, nullptr, nullptr, part, out, st, w);
         if (e == hipSuccess) e = hipEventRecord(e1, st);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.f;
@@ -249,6 +250,8 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
     ENSURE(BB_B1, P8, b1);
     ENSURE(BB_STATS, (size_t)NB * K * sizeof(LamStats), stats);
     ENSURE(BB_CMP, std::max(b_compact_scratch_bytes(p), compact_scratch_bytes(p)), cmp);
+    double* bspart;   // rows of the shared scans' cut tiles
+    ENSURE(BB_BSPART, bscan_part_bytes(), bspart);
     int64_t* kdev;   // lambda step counter read by the replayed screening graph
     ENSURE(BB_KDEV, 8, kdev);
     __bf16* Rp = nullptr;
@@ -296,7 +299,7 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
     if (!bt->masks) HIPCHK(launch_fill_u8(masks, 1, (int64_t)NB * nt, st));
     HIPCHK(launch_b_masks(masks, nt, NB, Mb, st));
     HIPCHK(launch_b_center_y(masks, bt->Y, nt, NB, Yt, R, bs, st));
-    if ((s = tune_bscan(ctx, m, Mb, NB, bs, S1))) return s;
+    if ((s = tune_bscan(ctx, m, Mb, NB, bs, bspart, S1))) return s;
     const int waves = ctx->bscan_waves;   // the variant picked for this shape
     res->scan_cols = bscan_variant_cols(waves);
     // Centers and scales depend on a problem's rows alone, so problems with the same mask (the responses of
@@ -336,8 +339,8 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
             HIPCHK(launch_colstats(mb, c + (size_t)b * p, sd + (size_t)b * p, keep + (size_t)b * p, rows[b], st));
         }
     } else {
-        HIPCHK(launch_bscan(m, 0, nullptr, nullptr, p, Mb, NB, bs, nullptr, nullptr, nullptr, S1, st, waves));
-        HIPCHK(launch_bscan(m, 1, nullptr, nullptr, p, Mb, NB, bs, nullptr, nullptr, nullptr, S2, st, waves));
+        HIPCHK(launch_bscan(m, 0, nullptr, nullptr, p, Mb, NB, bs, nullptr, nullptr, nullptr, bspart, S1, st, waves));
+        HIPCHK(launch_bscan(m, 1, nullptr, nullptr, p, Mb, NB, bs, nullptr, nullptr, nullptr, bspart, S2, st, waves));
     }
     prof_mark(ctx, 1);
     if (by_mask) {
@@ -353,7 +356,7 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
     }
     HIPCHK(launch_b_sum_r(R, nt, NB, bs, st));
     prof_mark(ctx, 2);
-    HIPCHK(launch_bscan(m, 2, nullptr, nullptr, p, Yt, NB, bs, c, sd, keep, a, st, waves));
+    HIPCHK(launch_bscan(m, 2, nullptr, nullptr, p, Yt, NB, bs, c, sd, keep, bspart, a, st, waves));
     prof_mark(ctx, 3);
     HIPCHK(launch_b_argmax(a, keep, p, NB, bs, st));
     if ((s = read_bs())) return s;
@@ -373,7 +376,7 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
         HIPCHK(launch_b_std_column(m, masks, NB, bs, c, sd, Bm, st));
         HIPCHK(launch_b_sum_r(Bm, nt, NB, bs, st));   // the mode-2 scan subtracts c_j * (sum of the right-hand side)
         prof_mark(ctx, 2);
-        HIPCHK(launch_bscan(m, 2, nullptr, nullptr, p, Bm, NB, bs, c, sd, keep, bb, st, waves));
+        HIPCHK(launch_bscan(m, 2, nullptr, nullptr, p, Bm, NB, bs, c, sd, keep, bspart, bb, st, waves));
         prof_mark(ctx, 3);
         HIPCHK(launch_b_sum_r(R, nt, NB, bs, st));    // back to the residual's sum and ||y~||^2
         HIPCHK(hipStreamSynchronize(st));
@@ -514,7 +517,7 @@ extern "C" bl_status bl_fit_path_batch(bl_ctx ctx, const bl_matrix* X, const bl_
             // post-convergence scan of every problem over the union list, then each problem's check
             if (!bf) {
                 prof_mark(ctx, 2);
-                HIPCHK(launch_bscan(m, 2, lT, lenT, 0, R, NB, bs, c, sd, keep, zcur, st, waves));
+                HIPCHK(launch_bscan(m, 2, lT, lenT, 0, R, NB, bs, c, sd, keep, bspart, zcur, st, waves));
                 prof_mark(ctx, 3);
             } else {
                 HIPCHK(launch_b_r_pieces(R, nt, NB, pieces, Rp, st));

@@ -66,9 +66,91 @@ int grid_for(int64_t work, int per_block, int max_blocks) {
 constexpr int BS_K = 64;
 constexpr int BS_LD = BNP + 2;   // LDS row stride of the staged B rows (doubles)
 
+// Work split of a column list over the G workgroups of a launch (as many as the device holds at once), for
+// the one-pass scans (k_bscan modes 0-2 and k_bscan_bf16): the list is T = ceil(len / TW) tiles of TW columns,
+// each C chunks of 64 rows.  Every workgroup first runs Tf = floor(T / G) whole tiles, tile i + k G for
+// workgroup i, all of them moving through the rows in step so that each chunk of the right-hand sides is read
+// from L2 by every workgroup at about the same time.  The T - Tf G tiles left over are cut by rows: their
+// (tile, chunk) units, tile-major, go out in equal contiguous ranges of at least BF_QMIN chunks, one per
+// workgroup, so that every workgroup finishes at about the same time however T falls against G.  A tile run
+// whole by one workgroup is written out directly; the rows of a cut tile that one workgroup ran are stored as
+// raw FP64 sums in its part slot (slot 0 for the first leftover tile the workgroup touches, slot 1 for the
+// second, layout [slot][problem][column of the tile]), and a join kernel adds the slots of each cut tile in
+// row order.
+constexpr int SPLIT_CHUNK = 64;  // rows per chunk of the split (the batch of both scans)
+constexpr int BF_QMIN = 8;       // fewest chunks in a range of leftover units (bounds the rows a tile is cut into)
+struct BfSplit {
+    int64_t T, C, Tf, Trem, q;   // tiles, chunks per tile, whole tiles per workgroup, leftover tiles, units per range
+};
+template <int TW>
+__device__ __forceinline__ BfSplit tile_split(int64_t len, int64_t n_pad, int64_t G) {
+    BfSplit s;
+    s.T = (len + TW - 1) / TW;
+    s.C = n_pad / SPLIT_CHUNK;
+    s.Tf = s.T / G;
+    s.Trem = s.T - s.Tf * G;
+    s.q = max((s.Trem * s.C + G - 1) / G, (int64_t)BF_QMIN);
+    return s;
+}
+// the workgroup's jobs: its Tf whole tiles, then the one or two leftover tiles its range of units touches; job
+// k runs rows [r0, r1) of tile tt and stores them in part slot `slot` unless `whole`
+struct TileJob {
+    int64_t tt, r0, r1;
+    int slot;
+    bool whole;
+};
+struct TileJobs {
+    BfSplit sp;
+    int64_t G, wg, u0, u1, head, n;
+};
+template <int TW>
+__device__ __forceinline__ TileJobs tile_jobs(int64_t len, int64_t n_pad, int64_t G, int64_t wg) {
+    TileJobs J;
+    J.sp = tile_split<TW>(len, n_pad, G);
+    J.G = G;
+    J.wg = wg;
+    J.u0 = wg * J.sp.q;
+    J.u1 = min(J.u0 + J.sp.q, J.sp.Trem * J.sp.C);
+    J.head = J.sp.C > 0 ? J.u0 / J.sp.C : 0;
+    J.n = J.sp.Tf + (J.u0 < J.u1 ? (J.u1 - 1) / J.sp.C - J.head + 1 : 0);
+    return J;
+}
+__device__ __forceinline__ TileJob tile_job(const TileJobs& J, int64_t k) {
+    TileJob t;
+    const int64_t C = J.sp.C;
+    if (k < J.sp.Tf) {
+        t.tt = J.wg + k * J.G;
+        t.r0 = 0;
+        t.r1 = C * SPLIT_CHUNK;
+        t.slot = 0;
+        t.whole = true;
+    } else {
+        const int64_t tr = J.head + (k - J.sp.Tf);
+        const int64_t c0 = max(J.u0 - tr * C, (int64_t)0), c1 = min(J.u1 - tr * C, C);
+        t.tt = J.sp.Tf * J.G + tr;
+        t.r0 = c0 * SPLIT_CHUNK;
+        t.r1 = c1 * SPLIT_CHUNK;
+        t.slot = tr == J.head ? 0 : 1;
+        t.whole = c0 == 0 && c1 == C;
+    }
+    return t;
+}
+// the leftover tile tr of a launch with G workgroups is cut if more than one workgroup ran rows of it; if so,
+// its stored rows lie in slots of workgroups i0 .. i1
+__device__ __forceinline__ bool tile_cut(const BfSplit& sp, int64_t tr, int64_t& i0, int64_t& i1) {
+    i0 = tr * sp.C / sp.q;
+    i1 = ((tr + 1) * sp.C - 1) / sp.q;
+    return i0 != i1;
+}
+__device__ __forceinline__ int tile_slot(const BfSplit& sp, int64_t i, int64_t tr) {
+    return i * sp.q / sp.C == tr ? 0 : 1;
+}
+
 // mode 0: raw dot products; mode 1: squared X (masked second moments); mode 2: standardized correlations;
-// mode 3: raw dot products of the rows [rc * blockIdx.y, rc * (blockIdx.y + 1)) only, written to
-// out[(blockIdx.y * len + t) * BNP + b] (split over rows for short column lists; k_bscan_reduce adds them)
+// modes 0-2 split the list over the launch's workgroups (tile_jobs; part: the rows of cut tiles, added by
+// k_bscan_join); mode 3: raw dot products of the rows [rc * blockIdx.y, rc * (blockIdx.y + 1)) of tile
+// blockIdx.x only, written to out[(blockIdx.y * len + t) * BNP + b] (split over rows for short column lists;
+// k_bscan_reduce adds them)
 template <typename XT, int MODE, int WAVES, bool PF>
 __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVES >= 4 ? 2 : 1))) void k_bscan(const XT* __restrict__ X, int64_t ldx, int64_t n_total,
                                                       int64_t n_pad, const int32_t* __restrict__ cols,
@@ -76,32 +158,22 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVE
                                                       const double* __restrict__ B, int nprob, int64_t p,
                                                       BatchScalars* __restrict__ bs, const double* __restrict__ c,
                                                       const double* __restrict__ s, const uint8_t* __restrict__ keep,
-                                                      double* __restrict__ out, int64_t rc) {
+                                                      double* __restrict__ part, double* __restrict__ out, int64_t rc) {
     constexpr int NT = 64 * WAVES, TF = 32 * WAVES;
+    static_assert(BS_K == SPLIT_CHUNK, "the split's chunks are the scan's row batches");
     __shared__ double Bl[2][BS_K * BS_LD];
     const int64_t len = len_dev ? *len_dev : len_host;
-    const int64_t f0 = (int64_t)blockIdx.x * TF;
-    if (f0 >= len) return;
-    const int64_t row0 = MODE == 3 ? rc * (int64_t)blockIdx.y : 0;
-    const int64_t row1 = MODE == 3 ? (row0 + rc < n_pad ? row0 + rc : n_pad) : n_pad;
+    TileJobs J{};
+    int64_t njobs;
+    if constexpr (MODE == 3) {
+        njobs = (int64_t)blockIdx.x * TF < len ? 1 : 0;
+    } else {
+        J = tile_jobs<TF>(len, n_pad, gridDim.x, blockIdx.x);
+        njobs = J.n;
+    }
+    if (njobs == 0) return;
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
     const int m = lane & 15, kq = lane >> 4;
-    // the two columns this lane feeds (tiles ft = 0, 1)
-    const XT* xc[2];
-    bool ok[2];
-#pragma unroll
-    for (int ft = 0; ft < 2; ++ft) {
-        const int64_t t = f0 + 32 * w + 16 * ft + m;
-        ok[ft] = t < len;
-        const int64_t j = ok[ft] ? (cols ? (int64_t)cols[t] : t) : 0;
-        xc[ft] = X + j * ldx;
-    }
-    f64x4 acc[2][4];
-#pragma unroll
-    for (int ft = 0; ft < 2; ++ft)
-#pragma unroll
-        for (int pt = 0; pt < 4; ++pt) acc[ft][pt] = (f64x4){0.0, 0.0, 0.0, 0.0};
-
     // a batch of B (64 rows x 64 problems) is staged in two halves: its loads are issued before the current
     // batch goes to the matrix cores and its LDS stores after, so the wave does not wait on them in between
     constexpr int SPT = BS_K * BNP / NT;   // B values per thread
@@ -114,87 +186,156 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(WAVE
 #pragma unroll
         for (int q = 0; q < SPT; ++q) Bl[buf][((tid + q * NT) / BNP) * BS_LD + (tid + q * NT) % BNP] = sreg[q];
     };
-    // raw X values of the lane's rows of one batch (zero past n_total or for an idle column), converted to
-    // FP64 as the matrix cores take them; with PF the next batch's values load into xn meanwhile
-    XT xr[2][16], xn[2][16];
-    auto load = [&](XT (&dst)[2][16], int64_t i0) {
+    for (int64_t job = 0; job < njobs; ++job) {
+        int64_t tt, row0, row1;
+        int slot = 0;
+        bool whole;
+        if constexpr (MODE == 3) {
+            tt = blockIdx.x;
+            row0 = rc * (int64_t)blockIdx.y;
+            row1 = row0 + rc < n_pad ? row0 + rc : n_pad;
+            whole = false;
+        } else {
+            const TileJob tj = tile_job(J, job);
+            tt = tj.tt;
+            row0 = tj.r0;
+            row1 = tj.r1;
+            slot = tj.slot;
+            whole = tj.whole;
+        }
+        const int64_t f0 = tt * TF;
+        // the two columns this lane feeds (tiles ft = 0, 1)
+        const XT* xc[2];
+        bool ok[2];
 #pragma unroll
         for (int ft = 0; ft < 2; ++ft) {
-            const int64_t r0 = i0 + 16 * kq;
-            if (ok[ft] && r0 + 16 <= n_total) {
-#pragma unroll
-                for (int q = 0; q < 16; ++q) dst[ft][q] = xc[ft][r0 + q];
-            } else {
-#pragma unroll
-                for (int q = 0; q < 16; ++q) dst[ft][q] = (ok[ft] && r0 + q < n_total) ? xc[ft][r0 + q] : (XT)0;
-            }
+            const int64_t t = f0 + 32 * w + 16 * ft + m;
+            ok[ft] = t < len;
+            const int64_t j = ok[ft] ? (cols ? (int64_t)cols[t] : t) : 0;
+            xc[ft] = X + j * ldx;
         }
-    };
-    int buf = 0;
-    if (PF) load(xr, row0);
-    stage_load(row0);
-    stage_store(0);
-    __syncthreads();
-    for (int64_t i0 = row0; i0 < row1; i0 += BS_K) {
-        if (!PF) load(xr, i0);
-        const bool more = i0 + BS_K < row1;
-        if (more) {
-            if (PF) load(xn, i0 + BS_K);
-            stage_load(i0 + BS_K);
-        }
-        const double* Bb = Bl[buf];
+        f64x4 acc[2][4];
 #pragma unroll
-        for (int st = 0; st < 16; ++st) {
-            const int row = 16 * kq + st;
-            double xa[2];
+        for (int ft = 0; ft < 2; ++ft)
+#pragma unroll
+            for (int pt = 0; pt < 4; ++pt) acc[ft][pt] = (f64x4){0.0, 0.0, 0.0, 0.0};
+        // raw X values of the lane's rows of one batch (zero past n_total or for an idle column), converted to
+        // FP64 as the matrix cores take them; with PF the next batch's values load into xn meanwhile
+        XT xr[2][16], xn[2][16];
+        auto load = [&](XT (&dst)[2][16], int64_t i0) {
 #pragma unroll
             for (int ft = 0; ft < 2; ++ft) {
-                const double v = (double)xr[ft][st];
-                xa[ft] = MODE == 1 ? v * v : v;
-            }
+                const int64_t r0 = i0 + 16 * kq;
+                if (ok[ft] && r0 + 16 <= n_total) {
 #pragma unroll
-            for (int pt = 0; pt < 4; ++pt) {
-                const double bv = Bb[row * BS_LD + 16 * pt + m];
+                    for (int q = 0; q < 16; ++q) dst[ft][q] = xc[ft][r0 + q];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) dst[ft][q] = (ok[ft] && r0 + q < n_total) ? xc[ft][r0 + q] : (XT)0;
+                }
+            }
+        };
+        // buffer 0 was last read before the barrier that ended the previous job
+        int buf = 0;
+        if (PF) load(xr, row0);
+        stage_load(row0);
+        stage_store(0);
+        __syncthreads();
+        for (int64_t i0 = row0; i0 < row1; i0 += BS_K) {
+            if (!PF) load(xr, i0);
+            const bool more = i0 + BS_K < row1;
+            if (more) {
+                if (PF) load(xn, i0 + BS_K);
+                stage_load(i0 + BS_K);
+            }
+            const double* Bb = Bl[buf];
+#pragma unroll
+            for (int st = 0; st < 16; ++st) {
+                const int row = 16 * kq + st;
+                double xa[2];
+#pragma unroll
+                for (int ft = 0; ft < 2; ++ft) {
+                    const double v = (double)xr[ft][st];
+                    xa[ft] = MODE == 1 ? v * v : v;
+                }
+#pragma unroll
+                for (int pt = 0; pt < 4; ++pt) {
+                    const double bv = Bb[row * BS_LD + 16 * pt + m];
+#pragma unroll
+                    for (int ft = 0; ft < 2; ++ft)
+                        acc[ft][pt] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ft], bv, acc[ft][pt], 0, 0, 0);
+                }
+            }
+            if (more) stage_store(buf ^ 1);   // the other buffer was last read before the previous barrier
+            __syncthreads();
+            buf ^= 1;
+            if (PF) {
 #pragma unroll
                 for (int ft = 0; ft < 2; ++ft)
-                    acc[ft][pt] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[ft], bv, acc[ft][pt], 0, 0, 0);
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) xr[ft][q] = xn[ft][q];
             }
         }
-        if (more) stage_store(buf ^ 1);   // the other buffer was last read before the previous barrier
-        __syncthreads();
-        buf ^= 1;
-        if (PF) {
+        // lane (m, kq), register q of tile (ft, pt) holds column 32w + 16ft + kq + 4q against problem 16pt + m
+        double* pp = part + (J.wg * 2 + slot) * (int64_t)BNP * TF;
 #pragma unroll
-            for (int ft = 0; ft < 2; ++ft)
+        for (int ft = 0; ft < 2; ++ft) {
 #pragma unroll
-                for (int q = 0; q < 16; ++q) xr[ft][q] = xn[ft][q];
+            for (int q = 0; q < 4; ++q) {
+                const int ci = 32 * w + 16 * ft + kq + 4 * q;
+                const int64_t t = f0 + ci;
+                if (t >= len) continue;
+                const int64_t j = cols ? (int64_t)cols[t] : t;
+#pragma unroll
+                for (int pt = 0; pt < 4; ++pt) {
+                    const int b = 16 * pt + m;
+                    if (b >= nprob) continue;
+                    const double v = acc[ft][pt][q];
+                    if (MODE == 3) {
+                        out[((int64_t)blockIdx.y * len + t) * BNP + b] = v;
+                    } else if (!whole) {
+                        pp[(int64_t)b * TF + ci] = v;
+                    } else if (MODE == 2) {
+                        const int64_t bj = (int64_t)b * p + j;
+                        const bool kept = keep == nullptr || keep[bj] != 0;
+                        out[bj] = kept ? (v - c[bj] * bs[b].sum_r) / ((double)bs[b].n_rows * s[bj]) : 0.0;
+                    } else {
+                        out[(int64_t)b * p + j] = v;
+                    }
+                }
+            }
         }
     }
-    // lane (m, kq), register q of tile (ft, pt) holds column 32w + 16ft + kq + 4q against problem 16pt + m
-#pragma unroll
-    for (int ft = 0; ft < 2; ++ft) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t t = f0 + 32 * w + 16 * ft + kq + 4 * q;
-            if (t >= len) continue;
-            const int64_t j = cols ? (int64_t)cols[t] : t;
-#pragma unroll
-            for (int pt = 0; pt < 4; ++pt) {
-                const int b = 16 * pt + m;
-                if (b >= nprob) continue;
-                const double v = acc[ft][pt][q];
-                double o = v;
-                if (MODE == 2) {
-                    const int64_t bj = (int64_t)b * p + j;
-                    const bool kept = keep == nullptr || keep[bj] != 0;
-                    o = kept ? (v - c[bj] * bs[b].sum_r) / ((double)bs[b].n_rows * s[bj]) : 0.0;
-                }
-                if (MODE == 3)
-                    out[((int64_t)blockIdx.y * len + t) * BNP + b] = v;
-                else
-                    out[(int64_t)b * p + j] = o;
-            }
-        }
+}
+
+// The cut leftover tiles of a k_bscan launch (modes 0-2) with G workgroups: one thread per (leftover tile,
+// problem, column) adds the tile's stored rows in row order, then writes the mode's result.
+template <int TF, int MODE>
+__global__ __launch_bounds__(256) void k_bscan_join(const int64_t* __restrict__ len_dev, int64_t len_host,
+                                                    int64_t n_pad, int64_t G, const int32_t* __restrict__ cols,
+                                                    int nprob, int64_t p, const BatchScalars* __restrict__ bs,
+                                                    const double* __restrict__ c, const double* __restrict__ s,
+                                                    const uint8_t* __restrict__ keep, const double* __restrict__ part,
+                                                    double* __restrict__ out) {
+    const int64_t len = len_dev ? *len_dev : len_host;
+    const BfSplit sp = tile_split<TF>(len, n_pad, G);
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tr = e / (TF * BNP);
+    const int b = (int)(e / TF % BNP), ci = (int)(e % TF);
+    if (tr >= sp.Trem || b >= nprob) return;
+    const int64_t t = (sp.Tf * G + tr) * TF + ci;
+    int64_t i0, i1;
+    if (t >= len || !tile_cut(sp, tr, i0, i1)) return;
+    double v = 0.0;
+#pragma unroll 8
+    for (int64_t i = i0; i <= i1; ++i) v += part[((i * 2 + tile_slot(sp, i, tr)) * BNP + b) * TF + ci];
+    const int64_t j = cols ? (int64_t)cols[t] : t;
+    const int64_t bj = (int64_t)b * p + j;
+    if (MODE == 2) {
+        const bool kept = keep == nullptr || keep[bj] != 0;
+        out[bj] = kept ? (v - c[bj] * bs[b].sum_r) / ((double)bs[b].n_rows * s[bj]) : 0.0;
+    } else {
+        out[bj] = v;
     }
 }
 
@@ -240,30 +381,6 @@ __global__ void k_b_r_pieces(const double* __restrict__ R, int64_t n_total, int6
     }
 }
 
-// Work split: a column list of len columns is T = ceil(len / (16 WAVES)) tiles of 16 WAVES columns, each C
-// chunks of 64 rows.  The G workgroups of a launch (as many as the device holds at once) first run
-// Tf = floor(T / G) whole tiles each, tile i + k G for workgroup i, all of them moving through the rows in step
-// so that the residual pieces of a chunk are read from L2 by every workgroup at about the same time.  The
-// T - Tf G tiles left over are cut by rows: their (tile, chunk) units, tile-major, go out in equal contiguous
-// ranges of at least BF_QMIN chunks, one per workgroup, so every workgroup finishes at about the same time
-// however T falls against G.  A tile
-// run whole by one workgroup is written out directly; the rows of a cut tile that one workgroup ran are
-// stored as raw FP64 sums in part, slot 0 for the first leftover tile the workgroup touches and slot 1 for
-// the second, and k_bscan_bf16_join adds the slots of each cut tile in row order.
-constexpr int BF_QMIN = 8;   // fewest chunks in a range of leftover units (bounds the rows a cut tile is cut into)
-struct BfSplit {
-    int64_t T, C, Tf, Trem, q;   // tiles, chunks per tile, whole tiles per workgroup, leftover tiles, units per range
-};
-template <int WAVES>
-__device__ __forceinline__ BfSplit bf_split(int64_t len, int64_t n_pad, int64_t G) {
-    BfSplit s;
-    s.T = (len + 16 * WAVES - 1) / (16 * WAVES);
-    s.C = n_pad / BF_K;
-    s.Tf = s.T / G;
-    s.Trem = s.T - s.Tf * G;
-    s.q = max((s.Trem * s.C + G - 1) / G, (int64_t)BF_QMIN);
-    return s;
-}
 // z_j of problem b from its raw sum x_j' r_b (the implicit standardization of the column)
 __device__ __forceinline__ void bf_store(double acc, int b, int64_t jq, int64_t p, const BatchScalars* bs,
                                          const double* c, const double* s, const uint8_t* keep, double* out) {
@@ -288,7 +405,7 @@ __global__ __launch_bounds__(64 * WAVES, 8 / WAVES) void k_bscan_bf16(const floa
     __shared__ __bf16 Rl[2 * PLANE];
     const int64_t len = len_dev ? *len_dev : len_host;
     const int64_t G = gridDim.x, wg = blockIdx.x;
-    const BfSplit sp = bf_split<WAVES>(len, n_pad, G);
+    const BfSplit sp = tile_split<16 * WAVES>(len, n_pad, G);
     const int64_t C = sp.C, F = n_total / BF_K;   // chunks; chunks wholly inside n_total
     // this workgroup's range of leftover units
     const int64_t u0 = wg * sp.q, u1 = min(u0 + sp.q, sp.Trem * C);
@@ -517,7 +634,7 @@ __global__ __launch_bounds__(256) void k_bscan_bf16_join(const int64_t* __restri
                                                          const double* __restrict__ part, double* __restrict__ out) {
     constexpr int TW = 16 * WAVES;
     const int64_t len = len_dev ? *len_dev : len_host;
-    const BfSplit sp = bf_split<WAVES>(len, n_pad, G);
+    const BfSplit sp = tile_split<16 * WAVES>(len, n_pad, G);
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t tr = e / (TW * BNP);
     const int b = (int)(e / TW % BNP), ci = (int)(e % TW);
@@ -1240,26 +1357,53 @@ __global__ __launch_bounds__(1024) void k_b_record(const int32_t* __restrict__ s
 // ---- launchers -------------------------------------------------------------------------------------------------
 int64_t batch_pad(int64_t n_total) { return (n_total + BS_K - 1) / BS_K * BS_K; }
 
+// workgroups of k_bscan<XT, MODE, WAVES, PF> the device holds at once, at most two per CU (the size of the
+// part scratch, bscan_part_bytes, assumes that bound; the 67.5 KB of LDS a workgroup takes allows no more)
+template <typename XT, int MODE, int WAVES, bool PF>
+static int bscan_slots() {
+    static int cached = 0;
+    if (!cached) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_bscan<XT, MODE, WAVES, PF>, 64 * WAVES, 0) !=
+                hipSuccess ||
+            per_cu < 1) {
+            (void)hipGetLastError();
+            per_cu = 1;
+        }
+        cached = (per_cu < 2 ? per_cu : 2) * device_cu_count();
+    }
+    return cached;
+}
+
+size_t bscan_part_bytes() { return (size_t)2 * device_cu_count() * 2 * (32 * 8) * BNP * sizeof(double); }
+
+template <typename XT, int MODE, int WAVES, bool PF>
+static hipError_t bscan_mode(const Mat& mt, const int32_t* cols, const int64_t* len_dev, int64_t len_host,
+                             const double* B, int nprob, BatchScalars* bs, const double* c, const double* s,
+                             const uint8_t* keep, double* part, double* out, hipStream_t st) {
+    constexpr int TF = 32 * WAVES;
+    const int64_t n_pad = batch_pad(mt.n_total);
+    const int g = bscan_slots<XT, MODE, WAVES, PF>();
+    k_bscan<XT, MODE, WAVES, PF><<<g, 64 * WAVES, 0, st>>>((const XT*)mt.X, mt.ldx, mt.n_total, n_pad, cols, len_dev,
+                                                           len_host, B, nprob, mt.p, bs, c, s, keep, part, out, n_pad);
+    // at most g - 1 leftover tiles (fewer when the list length is on the host)
+    int64_t tiles = g - 1;
+    if (!len_dev) tiles = std::min(tiles, (len_host + TF - 1) / TF);
+    if (tiles > 0)
+        k_bscan_join<TF, MODE><<<(int)(tiles * TF * BNP / 256), 256, 0, st>>>(len_dev, len_host, n_pad, g, cols, nprob,
+                                                                            mt.p, bs, c, s, keep, part, out);
+    return hipGetLastError();
+}
+
 template <typename XT, int WAVES, bool PF>
 static hipError_t bscan_typed(const Mat& mt, int mode, const int32_t* cols, const int64_t* len_dev, int64_t len_host,
                               const double* B, int nprob, BatchScalars* bs, const double* c, const double* s,
-                              const uint8_t* keep, double* out, hipStream_t st) {
-    constexpr int TF = 32 * WAVES;
-    const int64_t n_pad = batch_pad(mt.n_total);
-    const int64_t work = len_dev ? mt.p : len_host;
-    const int g = (int)((work + TF - 1) / TF);
-    const XT* X = (const XT*)mt.X;
-    if (g <= 0) return hipSuccess;
-    if (mode == 0)
-        k_bscan<XT, 0, WAVES, PF><<<g, 64 * WAVES, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, cols, len_dev, len_host, B, nprob,
-                                                       mt.p, bs, c, s, keep, out, n_pad);
-    else if (mode == 1)
-        k_bscan<XT, 1, WAVES, PF><<<g, 64 * WAVES, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, cols, len_dev, len_host, B, nprob,
-                                                       mt.p, bs, c, s, keep, out, n_pad);
-    else
-        k_bscan<XT, 2, WAVES, PF><<<g, 64 * WAVES, 0, st>>>(X, mt.ldx, mt.n_total, n_pad, cols, len_dev, len_host, B, nprob,
-                                                       mt.p, bs, c, s, keep, out, n_pad);
-    return hipGetLastError();
+                              const uint8_t* keep, double* part, double* out, hipStream_t st) {
+    if (!len_dev && len_host <= 0) return hipSuccess;
+    if (batch_pad(mt.n_total) <= 0) return hipErrorInvalidValue;
+    if (mode == 0) return bscan_mode<XT, 0, WAVES, PF>(mt, cols, len_dev, len_host, B, nprob, bs, c, s, keep, part, out, st);
+    if (mode == 1) return bscan_mode<XT, 1, WAVES, PF>(mt, cols, len_dev, len_host, B, nprob, bs, c, s, keep, part, out, st);
+    return bscan_mode<XT, 2, WAVES, PF>(mt, cols, len_dev, len_host, B, nprob, bs, c, s, keep, part, out, st);
 }
 
 // sum of the row-range partials in range order, then the standardized correlation of each (column, problem)
@@ -1291,7 +1435,7 @@ static hipError_t bscan_split_typed(const Mat& mt, const int32_t* cols, int64_t 
     const int nch = (int)((n_pad + SPLIT_ROWS - 1) / SPLIT_ROWS);
     dim3 grid((unsigned)((len + TF - 1) / TF), (unsigned)nch);
     k_bscan<XT, 3, W, false><<<grid, 64 * W, 0, st>>>((const XT*)mt.X, mt.ldx, mt.n_total, n_pad, cols, nullptr, len, B,
-                                                      nprob, mt.p, nullptr, nullptr, nullptr, nullptr, part,
+                                                      nprob, mt.p, nullptr, nullptr, nullptr, nullptr, nullptr, part,
                                                       SPLIT_ROWS);
     k_bscan_reduce<<<grid_for(len * BNP, 256, 4096), 256, 0, st>>>(part, nch, len, cols, mt.p, nprob, bs, c, s, keep,
                                                                     out);
@@ -1301,16 +1445,16 @@ static hipError_t bscan_split_typed(const Mat& mt, const int32_t* cols, int64_t 
 template <typename XT>
 static hipError_t bscan_waves(int variant, const Mat& mt, int mode, const int32_t* cols, const int64_t* len_dev,
                               int64_t len_host, const double* B, int nprob, BatchScalars* bs, const double* c,
-                              const double* s, const uint8_t* keep, double* out, hipStream_t st) {
+                              const double* s, const uint8_t* keep, double* part, double* out, hipStream_t st) {
 #define BSCAN_CASE(V, W, P) \
-    case V: return bscan_typed<XT, W, P>(mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
+    case V: return bscan_typed<XT, W, P>(mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, part, out, st);
     switch (variant) {
         BSCAN_CASE(0, 2, false)
         BSCAN_CASE(2, 8, false)
         BSCAN_CASE(3, 2, true)
         BSCAN_CASE(4, 4, true)
         BSCAN_CASE(5, 8, true)
-        default: return bscan_typed<XT, 4, false>(mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
+        default: return bscan_typed<XT, 4, false>(mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, part, out, st);
     }
 #undef BSCAN_CASE
 }
@@ -1332,10 +1476,10 @@ hipError_t launch_bscan_split(const Mat& mt, const int32_t* cols, int64_t len, c
 
 hipError_t launch_bscan(const Mat& mt, int mode, const int32_t* cols, const int64_t* len_dev, int64_t len_host,
                         const double* B, int nprob, BatchScalars* bs, const double* c, const double* s,
-                        const uint8_t* keep, double* out, hipStream_t st, int variant) {
+                        const uint8_t* keep, double* part, double* out, hipStream_t st, int variant) {
     if (mt.xtype == 0)
-        return bscan_waves<double>(variant, mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
-    return bscan_waves<float>(variant, mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, out, st);
+        return bscan_waves<double>(variant, mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, part, out, st);
+    return bscan_waves<float>(variant, mt, mode, cols, len_dev, len_host, B, nprob, bs, c, s, keep, part, out, st);
 }
 
 // Relative factor of the BF16 scan's bound on |z~ - z_fp64| (times sqrt(n_b (s^2 + c^2)) ||r_b||_2 / (n_b s),

@@ -82,7 +82,7 @@ enum BufId {
     // logistic regression
     L_ETA, L_G, L_R0C,
     // batched BF16 scans
-    BB_RP, BB_FLAG, BB_LF, BB_LU, BB_PART, BB_BFPART,
+    BB_RP, BB_FLAG, BB_LF, BB_LU, BB_PART, BB_BFPART, BB_BSPART,
     // active-set cycling
     B_CYCF, B_CYCL, B_CYCN, B_ZCYC,
     B_COUNT

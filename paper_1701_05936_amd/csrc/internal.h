@@ -275,9 +275,13 @@ hipError_t launch_bscan_bf16(const Mat& mt, const int32_t* cols, const int64_t* 
 hipError_t launch_b_band(const int32_t* cols, const int64_t* len_dev, int64_t p, int nprob, const double* z,
                          const double* c, const double* s, const uint8_t* keep, const BatchScalars* bs,
                          const double* lam, const double* thr, double rel, uint8_t* flag, hipStream_t st);
+// modes 0-2 take as many workgroups as the device holds at once and split the column list evenly between
+// them, cutting tiles by rows where needed (part: scratch of bscan_part_bytes() bytes for the rows of the cut
+// tiles)
+size_t bscan_part_bytes();
 hipError_t launch_bscan(const Mat& mt, int mode, const int32_t* cols, const int64_t* len_dev, int64_t len_host,
                         const double* B, int nprob, BatchScalars* bs, const double* c, const double* s,
-                        const uint8_t* keep, double* out, hipStream_t st, int variant = 1);
+                        const uint8_t* keep, double* part, double* out, hipStream_t st, int variant = 1);
 hipError_t launch_b_masks(const uint8_t* masks, int64_t n_total, int nprob, double* Mb, hipStream_t st);
 hipError_t launch_b_center_y(const uint8_t* masks, const double* Y, int64_t n_total, int nprob, double* Yt, double* R,
                              BatchScalars* bs, hipStream_t st);
