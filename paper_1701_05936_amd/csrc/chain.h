@@ -10,7 +10,9 @@
 // assumptions are checked after the block (conservatively for the zero coefficients); if one may fail
 // the block is not changed and the caller runs chain_exact, the plain sequential chain, from the same
 // state.  Both produce the coordinate-descent iterate: skipped steps are exact no-ops, and a kept-sign
-// step differs from the written-out soft threshold only in rounding.
+// step differs from the written-out soft threshold only in rounding.  chain_fast_next, the form of the
+// multi-workgroup solve, checks the zero coefficients exactly (on their gradients at their own steps) and
+// also forms the next block's first update in its step loop.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -100,7 +102,8 @@ __device__ __forceinline__ bool chain_fast(double& gl, double& bv, Col col, doub
 }
 
 // sum_t gn(t) dsh[t] over a block's changes dsh (NB doubles of LDS read as broadcasts), even and odd t
-// summed separately, then added: the update chain_fast_next folds into its post-pass
+// summed separately, then added: the next block's first update in the order chain_fast_next sums it in its
+// step loop, for blocks that chain_exact ran
 template <int NB, typename ColN>
 __device__ __forceinline__ double chain_next_update(ColN gn, const double* dsh) {
     double u0 = 0.0, u1 = 0.0;
