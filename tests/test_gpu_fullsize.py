@@ -1,4 +1,5 @@
-"""Full-size parity in the launch configurations bench.py times (CD tolerance 1e-10 here, 1e-8 there): the
+"""Full-size parity in the launch configurations bench.py times (CD tolerance 1e-10 here, 1e-8 there, except
+the learned form's path, certified at bench.py's 1e-8): the
 plain path on the 5,000 x 500,000 genotype design (FP64, 20 GB), the precision form on the 10,000 x
 2,000,000 genotype design (int8, 20 GB), the batched form on the 20,000 x 200,000 AR(1) design (64
 problems) and the learned form on the 5,000 x 1,000,000 block-AR(1) design (float32, 20 GB).
@@ -213,7 +214,8 @@ def test_c3_full_kkt_certificate(c3_full, k):
 @pytest.fixture(scope="module")
 def c5_full(gpu_ctx):
     """The learned form on the full c5 design over its whole 100-lambda grid, with a network trained on 10
-    recorded strong-rule paths (first 60 lambda values) of a 10,000-column design of the same recipe."""
+    recorded strong-rule paths (first 60 lambda values) of a 10,000-column design of the same recipe.  The
+    path runs at the CD tolerance bench.py times it at (1e-8): the certificate is of the timed configuration."""
     rec = datagen.RECIPES["c5"]
     depth = 60
     full = rec.nlambda
@@ -245,7 +247,7 @@ def c5_full(gpu_ctx):
     yd = torch.from_numpy(y).to(DEV)
     lmax = bl.fit_path(gpu_ctx, Xd, yd, nlambda=1, want_beta=False).lambda_max
     res = bl.fit_path(gpu_ctx, Xd, yd, nlambda=full, lambda_min_ratio=rec.lambda_min_ratio,
-                      rule=bl.SCREEN_LEARNED, mlp=P, mlp_tau=info["tau"], tol=1e-10)
+                      rule=bl.SCREEN_LEARNED, mlp=P, mlp_tau=info["tau"], tol=1e-8)
     log(f"learned path: {res.time_ms:.0f} ms, {res.n_active[-1]} active at the end, "
         f"{int(res.n_viol.sum())} violations repaired, working sets {int(res.n_strong.sum())}")
     del Xd
